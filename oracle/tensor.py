@@ -1,0 +1,77 @@
+"""mu-mode product and Tucker operator (oracle), Section 2 of the paper.
+
+vec(V) stacks by columns (Lemma 1): the first index i_1 runs fastest.  A vector of
+length N = n_1...n_d is therefore viewed as the C-ordered NumPy array of shape
+(n_d, ..., n_1); mode mu is axis d - mu of that array.
+
+The mu-mode product V x_mu L has entries
+    w_{i_1..i_d} = sum_j v_{i_1..i_{mu-1} j i_{mu+1}..i_d} L[i_mu, j],
+computed here by one library contraction (numpy.tensordot) per mode -- the step
+the paper describes as a single matrix-matrix product.
+"""
+from __future__ import annotations
+
+from typing import Sequence
+
+import numpy as np
+
+
+def as_tensor(v: np.ndarray, n: Sequence[int]) -> np.ndarray:
+    return np.asarray(v).reshape(tuple(reversed(list(n))))
+
+
+def mode_product(V: np.ndarray, L: np.ndarray, mu: int) -> np.ndarray:
+    """V x_mu L for V of shape (n_d, ..., n_1) and 1-based mode mu."""
+    ax = V.ndim - mu
+    W = np.tensordot(L, V, axes=([1], [ax]))      # new axis 0 is i_mu
+    return np.ascontiguousarray(np.moveaxis(W, 0, ax))
+
+
+def tucker(v: np.ndarray, n: Sequence[int], Ls: Sequence[np.ndarray]) -> np.ndarray:
+    """vec(V x_1 L_1 x_2 ... x_d L_d) for v = vec(V); Ls[mu-1] = L_mu."""
+    V = as_tensor(v, n)
+    for mu, L in enumerate(Ls, start=1):
+        V = mode_product(V, L, mu)
+    return V.reshape(-1)
+
+
+def mode_product_loops(v: np.ndarray, n: Sequence[int], L: np.ndarray, mu: int) -> np.ndarray:
+    """Same as mode_product, written as explicit loops over the mu-fibres (tiny sizes only)."""
+    n = list(n)
+    nlo = int(np.prod(n[: mu - 1])) if mu > 1 else 1
+    nmu = n[mu - 1]
+    nhi = int(np.prod(n[mu:])) if mu < len(n) else 1
+    out = np.zeros(len(v), dtype=np.result_type(v, L))
+    for b in range(nhi):
+        for a in range(nlo):
+            for i in range(nmu):
+                acc = 0.0
+                for j in range(nmu):
+                    acc += L[i, j] * v[a + nlo * (j + nmu * b)]
+                out[a + nlo * (i + nmu * b)] = acc
+    return out
+
+
+def kron_sum_dense(A: Sequence[np.ndarray]) -> np.ndarray:
+    """K = A_d (+) ... (+) A_1 = sum_mu I x .. x A_mu x .. x I assembled densely (pins only)."""
+    n = [a.shape[0] for a in A]
+    N = int(np.prod(n))
+    dt = np.result_type(*A)
+    K = np.zeros((N, N), dtype=dt)
+    for mu in range(len(A)):
+        M = np.ones((1, 1), dtype=dt)
+        for nu in range(len(A)):             # build I_d x ... x I_1 from the slow end
+            factor = A[nu] if nu == mu else np.eye(n[nu])
+            M = np.kron(factor, M)
+        K = K + M
+    return K
+
+
+def kron_sum_apply(A: Sequence[np.ndarray], v: np.ndarray) -> np.ndarray:
+    """K v without forming K: sum over mu of V x_mu A_mu."""
+    n = [a.shape[0] for a in A]
+    V = as_tensor(v, n)
+    out = np.zeros_like(V, dtype=np.result_type(V, *A))
+    for mu, a in enumerate(A, start=1):
+        out = out + mode_product(V, a, mu)
+    return out.reshape(-1)

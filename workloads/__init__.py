@@ -1,0 +1,159 @@
+"""Seeded synthetic inputs shared by the CPU oracle, the tests and the benchmark.
+
+This module builds *inputs only*: the small matrices A_mu of a Kronecker sum
+K = A_d (+) ... (+) A_1 and the vectors the phi-functions act on.  It holds none of
+the method's arithmetic (no quadrature, no exponentials, no mu-mode products), so
+that the oracle and the GPU path can both draw the same data without sharing code.
+
+Layout convention (Lemma 1 of the paper, Section 2): a vector v of length
+N = n_1 * ... * n_d is vec(V) of the order-d tensor V, stacked by columns, i.e. the
+index i_1 runs fastest.  As a NumPy array that is the C-ordered shape
+(n_d, ..., n_1).  Matrices are dense float64 (or complex128), row-major, A[i, j]
+being the coefficient of u_j in row i.
+
+The operators follow the discretisations the paper uses (Section 1 and Section 4):
+second-order finite differences with homogeneous Dirichlet boundary conditions on a
+uniform grid of [0, 1] with h = 1/(n+1), central differences for advection, and
+(for batched workloads) Chebyshev spectral second-derivative matrices.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+__all__ = [
+    "fd2_dirichlet", "central_adv_dirichlet", "adr_1d", "cheb_d2_dirichlet",
+    "randn_vec", "uniform_vec", "Workload", "config_fd2_2d", "config_allen_cahn_3d",
+    "config_adr_3d", "validation_table1",
+]
+
+
+def fd2_dirichlet(n: int, length: float = 1.0) -> np.ndarray:
+    """tridiag(1, -2, 1)/h^2 on n interior points of [0, length], h = length/(n+1)."""
+    h = length / (n + 1)
+    A = np.zeros((n, n))
+    idx = np.arange(n)
+    A[idx, idx] = -2.0
+    A[idx[:-1], idx[:-1] + 1] = 1.0
+    A[idx[1:], idx[1:] - 1] = 1.0
+    return A / (h * h)
+
+
+def central_adv_dirichlet(n: int, beta: float, length: float = 1.0) -> np.ndarray:
+    """beta * (u_{i+1} - u_{i-1}) / (2h), homogeneous Dirichlet, h = length/(n+1)."""
+    h = length / (n + 1)
+    A = np.zeros((n, n))
+    idx = np.arange(n)
+    A[idx[:-1], idx[:-1] + 1] = 1.0
+    A[idx[1:], idx[1:] - 1] = -1.0
+    return (beta / (2.0 * h)) * A
+
+
+def adr_1d(n: int, eps: float, beta: float, react: float) -> np.ndarray:
+    """eps * FD2 + central advection with speed beta + react * I (one direction)."""
+    return eps * fd2_dirichlet(n) + central_adv_dirichlet(n, beta) + react * np.eye(n)
+
+
+def cheb_d2_dirichlet(n: int) -> np.ndarray:
+    """Chebyshev second-derivative matrix on the n interior Chebyshev-Lobatto points
+    of [-1, 1] (Dirichlet: first and last rows/columns of the (n+2)-point matrix removed).
+    Dense, nonsymmetric; spectral radius grows like n^4."""
+    m = n + 1
+    x = np.cos(np.pi * np.arange(m + 1) / m)
+    c = np.ones(m + 1)
+    c[0] = c[-1] = 2.0
+    c *= (-1.0) ** np.arange(m + 1)
+    X = np.tile(x, (m + 1, 1)).T
+    dX = X - X.T
+    D = np.outer(c, 1.0 / c) / (dX + np.eye(m + 1))
+    D -= np.diag(D.sum(axis=1))
+    D2 = D @ D
+    return np.ascontiguousarray(D2[1:-1, 1:-1])
+
+
+def randn_vec(n: Sequence[int], seed: int) -> np.ndarray:
+    """v ~ N(0, 1) in vec order (i_1 fastest), float64."""
+    N = int(np.prod(n))
+    return np.random.default_rng(seed).standard_normal(N)
+
+
+def uniform_vec(n: Sequence[int], seed: int, lo: float, hi: float) -> np.ndarray:
+    N = int(np.prod(n))
+    return np.random.default_rng(seed).uniform(lo, hi, N)
+
+
+def grid_1d(n: int) -> np.ndarray:
+    """Interior grid points of [0, 1] with h = 1/(n+1)."""
+    return np.arange(1, n + 1) / (n + 1)
+
+
+@dataclass
+class Workload:
+    """One phi-action problem: operators, step, vectors and requested outputs."""
+    name: str
+    n: List[int]                       # n[0] = n_1 (fastest index)
+    A: List[np.ndarray]                # A[mu-1] = A_mu
+    tau: float
+    p: int                             # highest phi index
+    n_scales: int                      # number of time scales requested
+    task: str                          # "same_vector" or "lincomb"
+    tol: float                         # relative tolerance (norms taken as 1)
+    v: Optional[np.ndarray] = None     # same-vector input
+    vs: Optional[List[Optional[np.ndarray]]] = None   # lincomb inputs v_0..v_p
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def N(self) -> int:
+        return int(np.prod(self.n))
+
+    @property
+    def d(self) -> int:
+        return len(self.n)
+
+
+def config_fd2_2d(n: int = 32, tau: float = 1e-3, seed: int = 0, p: int = 3) -> Workload:
+    """2D FD Laplacian, Dirichlet, n x n, phi_0..phi_p on one N(0,1) vector."""
+    A = fd2_dirichlet(n)
+    return Workload(name=f"fd2_2d_{n}x{n}", n=[n, n], A=[A, A.copy()], tau=tau, p=p,
+                    n_scales=1, task="same_vector", tol=2.0 ** -53,
+                    v=randn_vec([n, n], seed))
+
+
+def config_allen_cahn_3d(n: int = 64, tau: float = 1e-3, seed: int = 1,
+                         eps: float = 0.01, p: int = 4) -> Workload:
+    """3D Allen-Cahn u' = eps*Lap(u) + u - u^3 with FD Dirichlet Laplacian.  The linear
+    part K is eps*Lap (the +u term is kept in g); one linear combination
+    exp(tau K) v_0 + sum_l phi_l(tau K) v_l with v_0 = u_0, v_l = tau*g(u_0)."""
+    A = eps * fd2_dirichlet(n)
+    u0 = uniform_vec([n, n, n], seed, -0.9, 0.9)
+    g = u0 - u0 ** 3
+    vs = [u0] + [tau * g for _ in range(p)]
+    return Workload(name=f"allen_cahn_3d_{n}^3", n=[n, n, n], A=[A, A.copy(), A.copy()],
+                    tau=tau, p=p, n_scales=2, task="lincomb", tol=2.0 ** -53, vs=vs,
+                    meta={"eps": eps})
+
+
+def config_adr_3d(n: int = 256, tau: float = 1e-3, seed: int = 2, p: int = 4,
+                  betas=(1.0, 0.5, 0.25), eps: float = 0.5, react: float = -1.0) -> Workload:
+    """3D advection-diffusion-reaction: A_mu = eps*FD2 + beta_mu*central_adv + react*I."""
+    A = [adr_1d(n, eps, b, react) for b in betas]
+    return Workload(name=f"adr_3d_{n}^3", n=[n, n, n], A=A, tau=tau, p=p, n_scales=1,
+                    task="same_vector", tol=2.0 ** -53, v=randn_vec([n, n, n], seed),
+                    meta={"betas": list(betas), "eps": eps, "react": react})
+
+
+def validation_table1(d: int, n: int):
+    """The code-validation operators of Section 4.1: A_mu = FD2 of (1+i)/100 * Lap on
+    [0,1]^d (Dirichlet) and v = samples of 4096(1+i) prod_mu x_mu(1-x_mu).
+    Returns (A list of complex matrices, v complex vector in vec order)."""
+    A = (1.0 + 1.0j) / 100.0 * fd2_dirichlet(n)
+    x = grid_1d(n)
+    f = x * (1.0 - x)
+    v = np.array([1.0 + 0.0j])
+    for _ in range(d):
+        v = np.kron(f, v)          # i_1 fastest: new (slower) index on the left
+    v = 4096.0 * (1.0 + 1.0j) * v
+    return [A.copy() for _ in range(d)], v
