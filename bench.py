@@ -1,0 +1,169 @@
+"""Benchmark: phi_0..phi_4 actions of a 3D advection-diffusion-reaction Kronecker sum.
+
+Workload: n = 256^3 (N = 16,777,216 dofs), A_mu = 0.5 * FD2 Laplacian + central
+advection (beta_mu = 1, 0.5, 0.25) - I, Dirichlet, h = 1/257, tau = 1e-3,
+v ~ N(0, 1) (seed 2), phi-functions on the same vector, p = 4, one scale,
+tolerance 2^-53 ||v||_2, FP64 throughout.
+
+One step is one pass of the whole path: host planning of (s, q), the device Pade
+exponentials of the small matrices and their squarings, and the phi-action call
+(phiks_plan + phiks_apply + phiks_plan_destroy).  Inputs are resident in HBM before
+the timed region.  The value is dofs/s = N * steps / time.
+
+Also reported (same JSON line): the roofline of the dominant kernel (the FP64 MFMA
+mu-mode product), measured live with HIP events around every mu-mode launch of the
+timed region, and the CPU oracle timed on this host for one full call.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("φ-action dofs/s and μ-mode GFLOP/s (% MFMA peak), FP64 vs FP32-MFMA; "
+          "p99 lat")
+FP64_PEAK_TFLOPS = 78.6   # MI355X dense FP64 (matrix and vector)
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(w, plan_info):
+    """Time the oracle (as it stands) for one full call of the same workload:
+    its own planner plus the phi-actions with the resulting (s, q)."""
+    from oracle import bound, phiks as ophiks
+    t0 = time.perf_counter()
+    xi = bound.kron_sum_rectangle([w.tau * a for a in w.A])
+    s, q, _ = bound.plan(xi, w.p, w.n_scales, w.tol, w.task)
+    t1 = time.perf_counter()
+    ophiks.phi_same_vector(w.A, w.tau, w.v, w.p, w.n_scales, s, q)
+    t2 = time.perf_counter()
+    try:
+        import threadpoolctl
+        threads = max([x.get("num_threads", 1) for x in threadpoolctl.threadpool_info()] or [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    return {"value": w.N / (t2 - t0), "unit": "dofs/s", "cores": int(threads),
+            "kind": "oracle",
+            "sample": (f"one full call at 256^3 (planner {t1 - t0:.1f} s + phi-actions "
+                       f"{t2 - t1:.1f} s, plan s={s} q={q})"),
+            "seconds": t2 - t0}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: the phi-action path here is single-GPU "
+              "(multi-GPU slab sharding is a design note, not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2210_07667_amd as ph
+    import workloads
+
+    dev = torch.device("cuda", 0)
+    w = workloads.config_adr_3d(n=args.n)
+    log(f"[bench] workload {w.name} N={w.N} tau={w.tau} p={w.p}")
+    v = torch.from_numpy(w.v).to(dev)
+    stream = torch.cuda.current_stream(dev)
+    st = stream.cuda_stream
+
+    plan = ph.phiks_plan(w.A, w.tau, w.p, w.n_scales, w.tol, w.task, stream=st)
+    info = plan.info()
+    ws = torch.empty(plan.workspace_size() // 8 + 1, dtype=torch.float64, device=dev)
+    out = torch.empty((w.n_scales, w.p + 1, w.N), dtype=torch.float64, device=dev)
+    plan.close()
+    log(f"[bench] plan {info}, workspace {ws.numel() * 8 / 2**30:.2f} GiB")
+
+    def step():
+        pl = ph.phiks_plan(w.A, w.tau, w.p, w.n_scales, w.tol, w.task, stream=st)
+        ph.phiks_apply(pl, v.data_ptr(), out.data_ptr(), ws.data_ptr(), ws.numel() * 8, st)
+        pl.close()
+
+    for i in range(args.warmup):
+        step()
+        log(f"[bench] warmup {i + 1}/{args.warmup}")
+    torch.cuda.synchronize()
+
+    ph.phiks_kernel_timing_read()          # clear
+    ph.phiks_kernel_timing(True)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for i in range(args.steps):
+        step()
+        log(f"[bench] step {i + 1}/{args.steps}")
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ph.phiks_kernel_timing(False)
+    k_ms, k_launch, k_flops = ph.phiks_kernel_timing_read()
+    ms_total = ev0.elapsed_time(ev1)
+    ms_step = max(ms_total, wall * 1e3) / args.steps
+
+    # phi-action call alone with the plan built once (reported beside the step)
+    pl = ph.phiks_plan(w.A, w.tau, w.p, w.n_scales, w.tol, w.task, stream=st)
+    torch.cuda.synchronize()
+    a0 = torch.cuda.Event(enable_timing=True)
+    a1 = torch.cuda.Event(enable_timing=True)
+    a0.record(stream)
+    reps = max(3, args.steps // 2)
+    for _ in range(reps):
+        ph.phiks_apply(pl, v.data_ptr(), out.data_ptr(), ws.data_ptr(), ws.numel() * 8, st)
+    a1.record(stream)
+    torch.cuda.synchronize()
+    apply_ms = a0.elapsed_time(a1) / reps
+    pl.close()
+
+    achieved = (k_flops / (k_ms * 1e-3)) / 1e12 if k_ms > 0 else 0.0
+    n_mu = w.n[0]
+    line = {
+        "metric": METRIC,
+        "value": w.N / (ms_step * 1e-3),
+        "unit": "dofs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"adr3d_{n_mu}^3_phi0-4_same_vector_tau1e-3_fp64",
+                   "N": w.N, "p": w.p, "n_scales": w.n_scales, "tol": "2^-53*||v||",
+                   "plan": info},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
+                     "traffic": None,
+                     "kernel": "gemm_f64_kernel (mu-mode product)",
+                     "launches": k_launch, "avg_launch_ms": k_ms / max(k_launch, 1),
+                     "flops_per_launch": k_flops / max(k_launch, 1)},
+        "apply_only_ms": apply_ms,
+        "apply_only_dofs_per_s": w.N / (apply_ms * 1e-3),
+        "mu_mode_gflops_per_s": achieved * 1e3,
+    }
+    if not args.no_cpu_baseline:
+        log("[bench] timing the CPU oracle (one full call)")
+        line["cpu_baseline"] = cpu_baseline(w, info)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

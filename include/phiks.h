@@ -1,0 +1,203 @@
+/*
+ * phiks.h -- C ABI of the MI355X (gfx950) library for actions of phi-functions of
+ * Kronecker sums.
+ *
+ * The operation (Caliari, Cassini, Zivcovich, "A mu-mode approach for exponential
+ * integrators: actions of phi-functions of Kronecker sums", arXiv 2210.07667):
+ *
+ *   K = A_d (+) ... (+) A_1 = sum_mu I_d x .. x I_{mu+1} x A_mu x I_{mu-1} x .. x I_1
+ *   (eq. kronsum, Section 1), A_mu dense n_mu x n_mu, and
+ *   phi_l(X) = int_0^1 theta^(l-1)/(l-1)! exp((1-theta) X) dtheta, phi_0 = exp
+ *   (eq. phifunctions).
+ *
+ * Two tasks (Section 3):
+ *   same vector   (eq. diffphi, eq. scaldiffphi): phi_l(2^-j tau K) v, l = 0..p,
+ *                 j = 0..n_scales-1;
+ *   combination   (eq. lincomb, eq. scallincomb): exp(c_j tau K) v_0 +
+ *                 sum_{l=1}^p c_j^l phi_l(c_j tau K) v_l, c_j = 2^-j.
+ * K is never formed: every exponential of K is a Tucker operator (chain of mu-mode
+ * products, Section 2, eq. tucker) with small exponentials of the B_mu = tau A_mu,
+ * inside a Gauss-Lobatto quadrature of the phi integral plus a scaling-and-squaring
+ * recurrence (eqs. integrandsimul/simul, integrandcomb/comb).  The scaling s and the
+ * number q of quadrature points are chosen from a remainder bound (Section 3.3).
+ *
+ * Vector layout (Lemma 1, Section 2): a vector of length N = n_1 * ... * n_d is
+ * vec(V), stacked by columns: index i_1 runs fastest.  As a row-major array that is
+ * the shape (n_d, ..., n_1).  All vectors are float64 in device memory.
+ *
+ * Conventions for every entry point:
+ *   - return PHIKS_OK (0) or a negative status; nothing throws across the ABI;
+ *   - every argument is validated before any device work is enqueued;
+ *   - device work is enqueued on the given HIP stream (NULL = the null stream) and
+ *     is stream-ordered; no entry point synchronises the stream except where noted;
+ *   - inputs and outputs are caller-owned device buffers; outputs must not alias
+ *     inputs; the library never frees them.
+ */
+#ifndef PHIKS_H
+#define PHIKS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct phiks_plan_s* phiks_plan_t;
+
+enum {
+  PHIKS_OK = 0,
+  PHIKS_EINVAL = -1,      /* invalid argument (shape, count, pointer, task, ...) */
+  PHIKS_ENOPLAN = -2,     /* no (s, q) with s <= s_max meets the tolerance */
+  PHIKS_ENOMEM = -3,      /* device or host allocation failed */
+  PHIKS_EDEVICE = -4,     /* a HIP call failed; phiks_last_error() has the text */
+  PHIKS_EWORKSPACE = -5,  /* workspace pointer NULL or ws_bytes too small */
+  PHIKS_ENONFINITE = -6   /* non-finite matrix entry, tau or tolerance */
+};
+
+enum { PHIKS_SAME_VECTOR = 0, PHIKS_LINCOMB = 1 };
+enum { PHIKS_FP64 = 0 };
+
+#define PHIKS_MAX_D 8      /* largest number of modes d */
+#define PHIKS_MAX_P 8      /* largest phi index p */
+#define PHIKS_MAX_N 1024   /* largest mode size n_mu */
+
+/*
+ * phiks_plan -- choose (s, q) and build the small exponentials.
+ *
+ * Section 3.3: for s = max(0, n_scales-1), max(0, n_scales-1)+1, ... take the
+ * smallest q in [3, 12] whose quadrature remainder bound (estimate CPestimate over
+ * the rectangle Xi = Xi_1 + ... + Xi_d containing the numerical range of tau K,
+ * Xi_mu the Bendixson rectangle of tau A_mu) satisfies
+ *   same vector:  b_{q,l}(s) ||v||_2 <= tol 2^(l s),                       l = 1..p
+ *   combination:  sum_{k<=l} b_{q,l-k+1}(s) ||v_{p+1-k}||_2 / 2^((l-k+1)s) <= tol
+ * and stop before the first s whose Tucker count (eq. Tpsv: q + s p + n_scales;
+ * eq. Tlcp: q p + s p + n_scales) is strictly larger than the previous one.
+ * Then, on the device, the Pade [m/m] scaling-and-squaring exponentials
+ * exp((1 - theta_i) tau A_mu / 2^s) for every Gauss-Lobatto node theta_i < 1 and
+ * exp(tau A_mu / 2^j) for j = s..0 (by squaring, Section 3.1) are computed.
+ *
+ *   d         number of modes, 1 <= d <= PHIKS_MAX_D
+ *   n         host array of d sizes; n[0] = n_1 is the fastest index;
+ *             1 <= n[mu] <= PHIKS_MAX_N
+ *   A         host array of d host pointers; A[mu] is A_{mu+1}, row-major
+ *             n[mu] x n[mu] float64 (A[i*n + j] multiplies u_j in row i); copied
+ *   tau       time step, finite and > 0
+ *   p         highest phi index, 0 <= p <= PHIKS_MAX_P (p = 0: exponential only)
+ *   n_scales  number of scales 2^-j, j = 0..n_scales-1, 1 <= n_scales <= 16
+ *   tol       absolute tolerance delta > 0 (relative when vnorms == NULL)
+ *   task      PHIKS_SAME_VECTOR or PHIKS_LINCOMB
+ *   vnorms    host array of 2-norms (same vector: 1 value ||v||; combination: p+1
+ *             values ||v_0||..||v_p||), or NULL for all norms = 1
+ *   precision PHIKS_FP64
+ *   hip_stream stream for the device work (hipStream_t), may be NULL
+ *   out       receives the plan; owned by the caller, release with
+ *             phiks_plan_destroy.  Its device buffers live on the current device.
+ *
+ * Errors: EINVAL, ENONFINITE, ENOPLAN (before any device work), ENOMEM, EDEVICE.
+ * The plan's matrices are ready in stream order; the call does not synchronise.
+ */
+int phiks_plan(int d, const int64_t* n, const double* const* A, double tau, int p,
+               int n_scales, double tol, int task, const double* vnorms, int precision,
+               void* hip_stream, phiks_plan_t* out);
+
+/*
+ * phiks_apply -- same vector (eqs. integrandsimul and simul, multi-scale outputs
+ * of eq. scaldiffphi).  Requires a plan made with PHIKS_SAME_VECTOR.
+ *
+ *   v     device, N float64
+ *   out   device, n_scales * (p+1) * N float64;
+ *         out[(j*(p+1) + l)*N + k] = (phi_l(2^-j tau K) v)[k], l = 0 is exp
+ *   ws    device workspace of at least phiks_workspace_size() bytes
+ * Errors: EINVAL (wrong task, NULL pointers), EWORKSPACE, EDEVICE.
+ */
+int phiks_apply(phiks_plan_t plan, const double* v, double* out, void* ws,
+                size_t ws_bytes, void* hip_stream);
+
+/*
+ * phiks_combine -- linear combination (eqs. integrandcomb and comb, eq. scallincomb).
+ * Requires a plan made with PHIKS_LINCOMB.
+ *
+ *   v     host array of p+1 device pointers v_0..v_p (N float64 each); any entry
+ *         may be NULL for a zero vector (v_0 == NULL skips the exponential term)
+ *   out   device, n_scales * N float64;
+ *         out[j*N + k] = (exp(c_j tau K) v_0 + sum_l c_j^l phi_l(c_j tau K) v_l)[k]
+ *   ws    device workspace of at least phiks_workspace_size() bytes
+ * Errors: EINVAL, EWORKSPACE, EDEVICE.
+ */
+int phiks_combine(phiks_plan_t plan, const double* const* v, double* out, void* ws,
+                  size_t ws_bytes, void* hip_stream);
+
+/*
+ * phiks_tucker -- the Tucker operator of Section 2 (eq. tucker, Lemma 1):
+ *   out = vec(V x_1 L_1 x_2 ... x_d L_d) = (L_d x ... x L_1) v
+ * with no plan: d mu-mode products on the device.
+ *
+ *   d, n      as for phiks_plan
+ *   L         host array of d device pointers; L[mu] row-major n[mu] x n[mu] float64
+ *   v, out    device, N float64 each (out must not alias v)
+ *   ws        device workspace of at least 2 * N * sizeof(double) bytes (d >= 2)
+ * Errors: EINVAL, EWORKSPACE, EDEVICE.
+ */
+int phiks_tucker(int d, const int64_t* n, const double* const* L, const double* v,
+                 double* out, void* ws, size_t ws_bytes, void* hip_stream);
+
+/* Workspace bytes needed by phiks_apply / phiks_combine for this plan. */
+int phiks_workspace_size(phiks_plan_t plan, size_t* bytes);
+
+/*
+ * Plan summary: scaling s, quadrature points q, the paper's Tucker count
+ * (eq. Tpsv / eq. Tlcp) and the count actually executed (the node theta_q = 1 and,
+ * for combinations with v_0 == NULL, the exponential terms need none).
+ */
+int phiks_plan_info(phiks_plan_t plan, int* s, int* q, int* tucker_paper,
+                    int* tucker_exec);
+
+/* Release a plan and its device memory (synchronises the plan's device). NULL is a no-op. */
+void phiks_plan_destroy(phiks_plan_t plan);
+
+/*
+ * Kernel timing for measurement: while enabled, every mu-mode product kernel launch
+ * is bracketed by HIP events recorded on the launch stream.  phiks_kernel_timing_read
+ * waits for the recorded launches, returns the summed kernel time (ms), the number
+ * of launches and their algorithmic flops (2 * rows * cols * contraction length per
+ * product), and clears the record.
+ */
+int phiks_kernel_timing(int enable);
+int phiks_kernel_timing_read(double* total_ms, int64_t* launches, double* flops);
+
+/* Static text for a status code. */
+const char* phiks_status_string(int status);
+
+/* Text of the last failure on the calling thread ("" if none). */
+const char* phiks_last_error(void);
+
+/*
+ * Host-only helpers (no device work; usable without a GPU).  They expose the
+ * planning steps of Section 3.3 for inspection and testing.
+ */
+
+/* The (s, q, T#) that phiks_plan would choose; arguments as for phiks_plan. */
+int phiks_plan_params(int d, const int64_t* n, const double* const* A, double tau,
+                      int p, int n_scales, double tol, int task, const double* vnorms,
+                      int* s, int* q, int* tucker_paper);
+
+/* Gauss-Lobatto-Legendre rule on [0,1] with q points, 2 <= q <= 12:
+ * theta[0] = 0 < ... < theta[q-1] = 1 and weights w (host arrays of q doubles). */
+int phiks_gll(int q, double* theta, double* w);
+
+/* Bendixson rectangle of the n x n row-major host matrix B: re_lo, re_hi, im_lo,
+ * im_hi (xi[0..3]) of [lambda(H)] x i[lambda(S)], H = (B+B^T)/2, S = (B-B^T)/(2i). */
+int phiks_rectangle(int64_t n, const double* B, double* xi);
+
+/* Remainder bound of estimate (CPestimate) at one point w = w_re + i w_im of the
+ * numerical range: |R_q(f_l(., w))| for l = 1..p written to err[0..p-1], computed
+ * as the contour integral over an ellipse with foci 0 and 1 of the kernel k_q
+ * (Section 3.3), without the factor (1 + sqrt 2). */
+int phiks_remainder(int q, int p, double w_re, double w_im, double* err);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PHIKS_H */

@@ -1,0 +1,314 @@
+"""Python binding of libphiks (the C ABI declared in include/phiks.h).
+
+Argument marshalling only: every step of the computation runs inside libphiks
+(host planner in C++, all vector work in HIP kernels on gfx950).  Device buffers are
+passed as raw device addresses (e.g. ``tensor.data_ptr()`` of a torch tensor on the
+GPU) and streams as raw ``hipStream_t`` handles (``torch.cuda.current_stream()
+.cuda_stream``).  The library must have been built (``python -m
+paper_2210_07667_amd.build``); importing this module fails loudly otherwise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libphiks.so")
+
+PHIKS_OK = 0
+PHIKS_EINVAL = -1
+PHIKS_ENOPLAN = -2
+PHIKS_ENOMEM = -3
+PHIKS_EDEVICE = -4
+PHIKS_EWORKSPACE = -5
+PHIKS_ENONFINITE = -6
+PHIKS_SAME_VECTOR = 0
+PHIKS_LINCOMB = 1
+PHIKS_FP64 = 0
+
+# every exported entry point of include/phiks.h
+SYMBOLS = ("phiks_plan", "phiks_apply", "phiks_combine", "phiks_workspace_size",
+           "phiks_plan_info", "phiks_plan_destroy", "phiks_status_string",
+           "phiks_last_error", "phiks_plan_params", "phiks_gll", "phiks_rectangle",
+           "phiks_remainder", "phiks_tucker", "phiks_kernel_timing",
+           "phiks_kernel_timing_read")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with "
+                      "`python paper_2210_07667_amd/build.py` (no CPU fallback exists)")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+_i64p = ctypes.POINTER(ctypes.c_int64)
+_dp = ctypes.POINTER(ctypes.c_double)
+_dpp = ctypes.POINTER(_dp)
+_vp = ctypes.c_void_p
+
+_lib.phiks_plan.restype = ctypes.c_int
+_lib.phiks_plan.argtypes = [ctypes.c_int, _i64p, _dpp, ctypes.c_double, ctypes.c_int,
+                            ctypes.c_int, ctypes.c_double, ctypes.c_int, _dp, ctypes.c_int,
+                            _vp, ctypes.POINTER(_vp)]
+_lib.phiks_apply.restype = ctypes.c_int
+_lib.phiks_apply.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]
+_lib.phiks_combine.restype = ctypes.c_int
+_lib.phiks_combine.argtypes = [_vp, ctypes.POINTER(_vp), _vp, _vp, ctypes.c_size_t, _vp]
+_lib.phiks_workspace_size.restype = ctypes.c_int
+_lib.phiks_workspace_size.argtypes = [_vp, ctypes.POINTER(ctypes.c_size_t)]
+_lib.phiks_plan_info.restype = ctypes.c_int
+_lib.phiks_plan_info.argtypes = [_vp] + [ctypes.POINTER(ctypes.c_int)] * 4
+_lib.phiks_plan_destroy.restype = None
+_lib.phiks_plan_destroy.argtypes = [_vp]
+_lib.phiks_status_string.restype = ctypes.c_char_p
+_lib.phiks_status_string.argtypes = [ctypes.c_int]
+_lib.phiks_last_error.restype = ctypes.c_char_p
+_lib.phiks_last_error.argtypes = []
+_lib.phiks_plan_params.restype = ctypes.c_int
+_lib.phiks_plan_params.argtypes = [ctypes.c_int, _i64p, _dpp, ctypes.c_double, ctypes.c_int,
+                                   ctypes.c_int, ctypes.c_double, ctypes.c_int, _dp]
+_lib.phiks_plan_params.argtypes += [ctypes.POINTER(ctypes.c_int)] * 3
+_lib.phiks_tucker.restype = ctypes.c_int
+_lib.phiks_tucker.argtypes = [ctypes.c_int, _i64p, ctypes.POINTER(_vp), _vp, _vp, _vp,
+                              ctypes.c_size_t, _vp]
+_lib.phiks_kernel_timing.restype = ctypes.c_int
+_lib.phiks_kernel_timing.argtypes = [ctypes.c_int]
+_lib.phiks_kernel_timing_read.restype = ctypes.c_int
+_lib.phiks_kernel_timing_read.argtypes = [_dp, _i64p, _dp]
+_lib.phiks_gll.restype = ctypes.c_int
+_lib.phiks_gll.argtypes = [ctypes.c_int, _dp, _dp]
+_lib.phiks_rectangle.restype = ctypes.c_int
+_lib.phiks_rectangle.argtypes = [ctypes.c_int64, _dp, _dp]
+_lib.phiks_remainder.restype = ctypes.c_int
+_lib.phiks_remainder.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                 _dp]
+
+
+class PhiksError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        msg = _lib.phiks_status_string(status).decode()
+        detail = _lib.phiks_last_error().decode()
+        super().__init__(f"{where}: {msg} ({status}){': ' + detail if detail else ''}")
+        self.status = status
+
+
+def _check(status: int, where: str) -> None:
+    if status != PHIKS_OK:
+        raise PhiksError(status, where)
+
+
+def status_string(status: int) -> str:
+    return _lib.phiks_status_string(status).decode()
+
+
+def _host_mats(A: Sequence[np.ndarray]):
+    mats = [np.ascontiguousarray(np.asarray(a, dtype=np.float64)) for a in A]
+    for m in mats:
+        if m.ndim != 2 or m.shape[0] != m.shape[1]:
+            raise ValueError("each A_mu must be a square matrix")
+    n = (ctypes.c_int64 * len(mats))(*[m.shape[0] for m in mats])
+    ptrs = (_dp * len(mats))(*[m.ctypes.data_as(_dp) for m in mats])
+    return mats, n, ptrs
+
+
+def _task_code(task) -> int:
+    if task in ("same_vector", PHIKS_SAME_VECTOR):
+        return PHIKS_SAME_VECTOR
+    if task in ("lincomb", PHIKS_LINCOMB):
+        return PHIKS_LINCOMB
+    raise ValueError(f"unknown task {task!r}")
+
+
+def _norms(vnorms):
+    if vnorms is None:
+        return None, None
+    arr = (ctypes.c_double * len(vnorms))(*[float(x) for x in vnorms])
+    return arr, ctypes.cast(arr, _dp)
+
+
+class Plan:
+    """Owns a phiks_plan_t (released by close() or garbage collection)."""
+
+    def __init__(self, handle: int, d: int, n, p: int, n_scales: int, task: int):
+        self._h = ctypes.c_void_p(handle)
+        self.d, self.n, self.p, self.n_scales, self.task = d, list(n), p, n_scales, task
+        self.N = int(np.prod(self.n))
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self):
+        s, q, tp, te = (ctypes.c_int() for _ in range(4))
+        _check(_lib.phiks_plan_info(self._h, ctypes.byref(s), ctypes.byref(q),
+                                    ctypes.byref(tp), ctypes.byref(te)), "phiks_plan_info")
+        return {"s": s.value, "q": q.value, "tucker_paper": tp.value, "tucker_exec": te.value}
+
+    def workspace_size(self) -> int:
+        b = ctypes.c_size_t()
+        _check(_lib.phiks_workspace_size(self._h, ctypes.byref(b)), "phiks_workspace_size")
+        return b.value
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            _lib.phiks_plan_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def phiks_plan(A: Sequence[np.ndarray], tau: float, p: int, n_scales: int, tol: float,
+               task="same_vector", vnorms: Optional[Sequence[float]] = None,
+               precision: int = PHIKS_FP64, stream: int = 0) -> Plan:
+    mats, n, ptrs = _host_mats(A)
+    keep, vn = _norms(vnorms)
+    out = ctypes.c_void_p()
+    tc = _task_code(task)
+    _check(_lib.phiks_plan(len(mats), n, ptrs, float(tau), int(p), int(n_scales), float(tol),
+                           tc, vn, int(precision), ctypes.c_void_p(stream), ctypes.byref(out)),
+           "phiks_plan")
+    return Plan(out.value, len(mats), list(n), p, n_scales, tc)
+
+
+def phiks_apply(plan: Plan, v_ptr: int, out_ptr: int, ws_ptr: int, ws_bytes: int,
+                stream: int = 0) -> None:
+    _check(_lib.phiks_apply(plan.handle, _vp(v_ptr), _vp(out_ptr), _vp(ws_ptr),
+                            ctypes.c_size_t(ws_bytes), _vp(stream)), "phiks_apply")
+
+
+def phiks_combine(plan: Plan, v_ptrs: Sequence[Optional[int]], out_ptr: int, ws_ptr: int,
+                  ws_bytes: int, stream: int = 0) -> None:
+    arr = (_vp * len(v_ptrs))(*[None if x is None else _vp(x) for x in v_ptrs])
+    _check(_lib.phiks_combine(plan.handle, arr, _vp(out_ptr), _vp(ws_ptr),
+                              ctypes.c_size_t(ws_bytes), _vp(stream)), "phiks_combine")
+
+
+def phiks_tucker(n: Sequence[int], L_ptrs: Sequence[int], v_ptr: int, out_ptr: int,
+                 ws_ptr: int, ws_bytes: int, stream: int = 0) -> None:
+    nn = (ctypes.c_int64 * len(n))(*[int(x) for x in n])
+    lp = (_vp * len(L_ptrs))(*[_vp(x) for x in L_ptrs])
+    _check(_lib.phiks_tucker(len(n), nn, lp, _vp(v_ptr), _vp(out_ptr), _vp(ws_ptr),
+                             ctypes.c_size_t(ws_bytes), _vp(stream)), "phiks_tucker")
+
+
+def phiks_plan_params(A: Sequence[np.ndarray], tau: float, p: int, n_scales: int, tol: float,
+                      task="same_vector", vnorms: Optional[Sequence[float]] = None):
+    """(s, q, T#) the planner chooses (host only, no GPU needed)."""
+    mats, n, ptrs = _host_mats(A)
+    keep, vn = _norms(vnorms)
+    s, q, t = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    _check(_lib.phiks_plan_params(len(mats), n, ptrs, float(tau), int(p), int(n_scales),
+                                  float(tol), _task_code(task), vn, ctypes.byref(s),
+                                  ctypes.byref(q), ctypes.byref(t)), "phiks_plan_params")
+    return s.value, q.value, t.value
+
+
+def phiks_plan_params_raw(d, n, A_ptrs, tau, p, n_scales, tol, task, vnorms_ptr):
+    """Direct pass-through (for argument-validation tests)."""
+    s, q, t = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    return _lib.phiks_plan_params(d, n, A_ptrs, tau, p, n_scales, tol, task, vnorms_ptr,
+                                  ctypes.byref(s), ctypes.byref(q), ctypes.byref(t))
+
+
+def phiks_kernel_timing(enable: bool) -> None:
+    _check(_lib.phiks_kernel_timing(1 if enable else 0), "phiks_kernel_timing")
+
+
+def phiks_kernel_timing_read():
+    """(total kernel ms, launches, algorithmic flops) of the mu-mode kernels timed
+    since the last read."""
+    ms, n, fl = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
+    _check(_lib.phiks_kernel_timing_read(ctypes.byref(ms), ctypes.byref(n), ctypes.byref(fl)),
+           "phiks_kernel_timing_read")
+    return ms.value, n.value, fl.value
+
+
+def phiks_gll(q: int):
+    th = (ctypes.c_double * q)()
+    w = (ctypes.c_double * q)()
+    _check(_lib.phiks_gll(q, th, w), "phiks_gll")
+    return list(th), list(w)
+
+
+def phiks_rectangle(B: np.ndarray):
+    B = np.ascontiguousarray(np.asarray(B, dtype=np.float64))
+    xi = (ctypes.c_double * 4)()
+    _check(_lib.phiks_rectangle(B.shape[0], B.ctypes.data_as(_dp), xi), "phiks_rectangle")
+    return tuple(xi)
+
+
+def phiks_remainder(q: int, p: int, w: complex):
+    err = (ctypes.c_double * p)()
+    _check(_lib.phiks_remainder(q, p, float(w.real), float(w.imag), err), "phiks_remainder")
+    return list(err)
+
+
+# ------------------------------------------------------------- torch helpers
+def _torch():
+    import torch
+    return torch
+
+
+def apply_torch(plan: Plan, v, out=None, ws=None, stream=None):
+    """Same-vector task on torch float64 CUDA tensors; returns out of shape
+    (n_scales, p+1, N)."""
+    torch = _torch()
+    if plan.task != PHIKS_SAME_VECTOR:
+        raise ValueError("plan was made for a linear combination")
+    if v.dtype != torch.float64 or not v.is_cuda or not v.is_contiguous() or v.numel() != plan.N:
+        raise ValueError("v must be a contiguous float64 GPU tensor of N entries")
+    if out is None:
+        out = torch.empty((plan.n_scales, plan.p + 1, plan.N), dtype=torch.float64,
+                          device=v.device)
+    nbytes = plan.workspace_size()
+    if ws is None:
+        ws = torch.empty(max(nbytes // 8, 1), dtype=torch.float64, device=v.device)
+    st = torch.cuda.current_stream(v.device).cuda_stream if stream is None else stream
+    phiks_apply(plan, v.data_ptr(), out.data_ptr(), ws.data_ptr(), ws.numel() * 8, st)
+    return out
+
+
+def tucker_torch(n: Sequence[int], Ls, v, out=None, stream=None):
+    """Tucker operator on torch float64 GPU tensors (Ls: list of n_mu x n_mu)."""
+    torch = _torch()
+    N = int(np.prod(n))
+    if out is None:
+        out = torch.empty(N, dtype=torch.float64, device=v.device)
+    ws = torch.empty(max(2 * N, 1), dtype=torch.float64, device=v.device)
+    st = torch.cuda.current_stream(v.device).cuda_stream if stream is None else stream
+    phiks_tucker(n, [L.data_ptr() for L in Ls], v.data_ptr(), out.data_ptr(), ws.data_ptr(),
+                 ws.numel() * 8, st)
+    return out
+
+
+def combine_torch(plan: Plan, vs, out=None, ws=None, stream=None):
+    """Linear-combination task; vs = [v_0, ..., v_p] (None for zero vectors);
+    returns out of shape (n_scales, N)."""
+    torch = _torch()
+    if plan.task != PHIKS_LINCOMB:
+        raise ValueError("plan was made for the same-vector task")
+    if len(vs) != plan.p + 1:
+        raise ValueError("need p+1 vectors")
+    dev = None
+    for x in vs:
+        if x is None:
+            continue
+        if x.dtype != torch.float64 or not x.is_cuda or not x.is_contiguous() or x.numel() != plan.N:
+            raise ValueError("vectors must be contiguous float64 GPU tensors of N entries")
+        dev = x.device
+    if dev is None:
+        dev = torch.device("cuda", torch.cuda.current_device())
+    if out is None:
+        out = torch.empty((plan.n_scales, plan.N), dtype=torch.float64, device=dev)
+    nbytes = plan.workspace_size()
+    if ws is None:
+        ws = torch.empty(max(nbytes // 8, 1), dtype=torch.float64, device=dev)
+    st = torch.cuda.current_stream(dev).cuda_stream if stream is None else stream
+    phiks_combine(plan, [None if x is None else x.data_ptr() for x in vs], out.data_ptr(),
+                  ws.data_ptr(), ws.numel() * 8, st)
+    return out

@@ -1,0 +1,216 @@
+// FP64 MFMA GEMM for gfx950, specialised for mu-mode products (Section 2 of the
+// paper: each mu-mode product is one matrix-matrix product).
+//
+// A tensor V of shape n_1 x ... x n_d stored with i_1 fastest is, for mode mu, a
+// batch of n_> = n_{mu+1}...n_d slabs X_b of shape n_mu x n_<  (n_< = n_1...n_{mu-1},
+// contiguous along n_<).  The mu-mode product W = V x_mu L is
+//   mode 1:        W[m][i] = sum_j X[m][j] L[i][j]           (rows m < n_>)
+//   mode mu > 1:   W_b[i][a] = sum_j L[i][j] X_b[j][a]         (a < n_<, batch b)
+// i.e. C = A B with A always contiguous along the contraction index k and B either
+// contiguous along n (mode > 1) or along k (mode 1, B = L^T).  No permutation of the
+// tensor is ever made; the tiles of X are staged through LDS in the layout the MFMA
+// fragments read.
+//
+// MFMA: v_mfma_f64_16x16x4_f64.  Per lane l (64-wide wave):
+//   A operand  A[m0 + (l & 15)][k0 + (l >> 4)]
+//   B operand  B[k0 + (l >> 4)][n0 + (l & 15)]
+//   C result   c[r] = C[m0 + 4 (l >> 4) + r][n0 + (l & 15)],  r = 0..3
+//
+// Launch: 1-D grid over (m tiles, n tiles, batch) with the m-tile fastest, so that
+// the work-groups sharing one B tile are consecutive; the work-group ids are then
+// remapped so that consecutive logical tiles land on the same XCD (the hardware
+// deals work-groups round-robin over the 8 XCDs, each with its own L2).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace phiks {
+
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+struct GemmArgs {
+  int M, N, K;
+  const double* A;
+  int64_t lda;   // A(m, k) = A[m * lda + k]
+  const double* B;
+  int64_t ldb;   // B(k, n) = B[k * ldb + n] (n-contiguous) or B[n * ldb + k] (k-contiguous)
+  double* C;
+  int64_t ldc;   // C(m, n) = C[m * ldc + n]
+  int nb0, nb1;  // batch z = z1 * nb0 + z0
+  int64_t sA0, sA1, sB0, sB1, sC0, sC1;
+  int tiles_m, tiles_n;
+  int64_t total_tiles;
+  // pointer-array batch (used when pA != nullptr): operands of batch z are
+  // pA[z], pB[z], pC[z]; the strides above are then ignored
+  const double* const* pA;
+  const double* const* pB;
+  double* const* pC;
+};
+
+// C = alpha * acc (+ beta * C).  beta == 0 never reads C.
+struct EpiStore {
+  double alpha, beta;
+  __device__ __forceinline__ void operator()(double* C, int64_t e, double acc) const {
+    C[e] = (beta == 0.0) ? alpha * acc : alpha * acc + beta * C[e];
+  }
+};
+
+// Output tensors l = 0..p-1 of N entries each, contiguous from the C base pointer:
+// out_l = a[l] * acc + sum_{k <= l} c[l][k] * Y_k   (Y_k = Y + k * N, same offset).
+// This is the squaring step of eq. simul / eq. comb fused into the last mu-mode product.
+struct EpiLinComb {
+  const double* Y;
+  int64_t N;
+  int p;
+  double a[8];
+  double c[8][8];
+  __device__ __forceinline__ void operator()(double* C, int64_t e, double acc) const {
+    const int64_t l = e / N;
+    const int64_t off = e - l * N;
+    double r = a[l] * acc;
+    for (int k = 0; k <= (int)l; ++k) r += c[l][k] * Y[k * N + off];
+    C[e] = r;
+  }
+};
+
+__device__ __forceinline__ int64_t xcd_remap(int64_t g, int64_t G) {
+  const int64_t xcd = g & 7;
+  const int64_t slot = g >> 3;
+  const int64_t per = G >> 3;
+  const int64_t rem = G & 7;
+  return (xcd < rem) ? xcd * (per + 1) + slot : rem * (per + 1) + (xcd - rem) * per + slot;
+}
+
+template <int BM, int BN, int WM, int WN, bool B_KCONTIG, class Epi>
+__global__ void __launch_bounds__(256) gemm_f64_kernel(GemmArgs g, Epi epi) {
+  constexpr int BK = 16;
+  constexpr int PA = BM + ((BM % 32 == 16) ? 0 : (48 - BM % 32) % 32);  // row stride = 16 mod 32
+  constexpr int PB = BN + ((BN % 32 == 16) ? 0 : (48 - BN % 32) % 32);
+  constexpr int WGM = BM / WM;
+  constexpr int WGN = BN / WN;
+  static_assert(WGM * WGN == 4, "4 waves per work-group");
+  constexpr int FM = WM / 16;
+  constexpr int FN = WN / 16;
+  constexpr int LA = BM * BK / 256;  // A elements per thread per chunk
+  constexpr int LB = BN * BK / 256;
+
+  __shared__ double As[2][BK][PA];
+  __shared__ double Bs[2][BK][PB];
+
+  const int64_t t = xcd_remap(blockIdx.x, g.total_tiles);
+  const int tm = (int)(t % g.tiles_m);
+  const int64_t rest = t / g.tiles_m;
+  const int tn = (int)(rest % g.tiles_n);
+  const int64_t z = rest / g.tiles_n;
+  const int64_t z0 = z % g.nb0;
+  const int64_t z1 = z / g.nb0;
+
+  const double* __restrict__ A;
+  const double* __restrict__ B;
+  double* Cb;
+  int64_t cbase;
+  if (g.pA != nullptr) {
+    A = g.pA[z];
+    B = g.pB[z];
+    Cb = g.pC[z];
+    cbase = 0;
+  } else {
+    A = g.A + z0 * g.sA0 + z1 * g.sA1;
+    B = g.B + z0 * g.sB0 + z1 * g.sB1;
+    Cb = g.C;
+    cbase = z0 * g.sC0 + z1 * g.sC1;
+  }
+
+  const int m0 = tm * BM;
+  const int n0 = tn * BN;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = (wave / WGN) * WM;
+  const int wn = (wave % WGN) * WN;
+
+  double ra[LA], rb[LB];
+  auto load_chunk = [&](int k0) {
+#pragma unroll
+    for (int i = 0; i < LA; ++i) {
+      const int e = tid + i * 256;
+      const int m = e / BK, k = e % BK;
+      const int gm = m0 + m, gk = k0 + k;
+      ra[i] = (gm < g.M && gk < g.K) ? A[(int64_t)gm * g.lda + gk] : 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < LB; ++i) {
+      const int e = tid + i * 256;
+      if constexpr (B_KCONTIG) {
+        const int n = e / BK, k = e % BK;
+        const int gn = n0 + n, gk = k0 + k;
+        rb[i] = (gn < g.N && gk < g.K) ? B[(int64_t)gn * g.ldb + gk] : 0.0;
+      } else {
+        const int k = e / BN, n = e % BN;
+        const int gn = n0 + n, gk = k0 + k;
+        rb[i] = (gn < g.N && gk < g.K) ? B[(int64_t)gk * g.ldb + gn] : 0.0;
+      }
+    }
+  };
+  auto store_chunk = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < LA; ++i) {
+      const int e = tid + i * 256;
+      As[buf][e % BK][e / BK] = ra[i];
+    }
+#pragma unroll
+    for (int i = 0; i < LB; ++i) {
+      const int e = tid + i * 256;
+      if constexpr (B_KCONTIG) Bs[buf][e % BK][e / BK] = rb[i];
+      else Bs[buf][e / BN][e % BN] = rb[i];
+    }
+  };
+
+  dbl4 acc[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
+
+  const int nchunks = (g.K + BK - 1) / BK;
+  load_chunk(0);
+  store_chunk(0);
+  __syncthreads();
+  const int lr = lane & 15;
+  const int lk = lane >> 4;
+  for (int c = 0; c < nchunks; ++c) {
+    const int buf = c & 1;
+    if (c + 1 < nchunks) load_chunk((c + 1) * BK);
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 4) {
+      double fa[FM], fb[FN];
+#pragma unroll
+      for (int i = 0; i < FM; ++i) fa[i] = As[buf][kk + lk][wm + i * 16 + lr];
+#pragma unroll
+      for (int j = 0; j < FN; ++j) fb[j] = Bs[buf][kk + lk][wn + j * 16 + lr];
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[i], fb[j], acc[i][j], 0, 0, 0);
+    }
+    if (c + 1 < nchunks) store_chunk(buf ^ 1);
+    __syncthreads();
+  }
+
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+      const int n = n0 + wn + j * 16 + lr;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + wm + i * 16 + 4 * lk + r;
+        if (m < g.M && n < g.N) epi(Cb, cbase + (int64_t)m * g.ldc + n, acc[i][j][r]);
+      }
+    }
+}
+
+}  // namespace phiks

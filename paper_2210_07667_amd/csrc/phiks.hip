@@ -1,0 +1,946 @@
+// Runtime and C ABI of the phiks library for MI355X (gfx950).
+//
+// phiks_plan:    host planning (planner.cpp), then the small exponentials on the
+//                device: Pade [m/m] with scaling and squaring for every node matrix
+//                exp((1-theta_i) tau A_mu / 2^s), and exp(tau A_mu / 2^j) for j = s..0
+//                by squaring (Section 3.1).
+// phiks_apply:   same vector, eqs. integrandsimul / simul.
+// phiks_combine: linear combination, eqs. integrandcomb / comb.
+// Every exponential of K is a Tucker operator (eq. Tuckerprod): d mu-mode products,
+// each one FP64 MFMA GEMM launch (gemm_f64.hpp) with no tensor permutation; the
+// weighted sums and the squaring recurrences are fused into the epilogue of the
+// last mu-mode product or done by one memory-bound pass (kernels.hpp).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "gemm_f64.hpp"
+#include "kernels.hpp"
+#include "phiks.h"
+#include "planner.hpp"
+
+using namespace phiks;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+void set_error(const std::string& s) { g_last_error = s; }
+
+#define HIP_OK(expr)                                                                  \
+  do {                                                                                \
+    hipError_t e_ = (expr);                                                           \
+    if (e_ != hipSuccess) {                                                           \
+      set_error(std::string(#expr) + ": " + hipGetErrorString(e_));                   \
+      return PHIKS_EDEVICE;                                                           \
+    }                                                                                 \
+  } while (0)
+
+#define CHECK_LAUNCH()                                                                \
+  do {                                                                                \
+    hipError_t e_ = hipGetLastError();                                                \
+    if (e_ != hipSuccess) {                                                           \
+      set_error(std::string("kernel launch: ") + hipGetErrorString(e_));              \
+      return PHIKS_EDEVICE;                                                           \
+    }                                                                                 \
+  } while (0)
+
+#define RET_IF(st)                                                                    \
+  do {                                                                                \
+    int r_ = (st);                                                                    \
+    if (r_ != PHIKS_OK) return r_;                                                    \
+  } while (0)
+
+// --------------------------------------------------- kernel timing (optional)
+// When enabled, every mu-mode GEMM launch is bracketed by two HIP events recorded
+// on its own stream, with its algorithmic flop count 2 M N K (per batch entry).
+struct TimedLaunch {
+  hipEvent_t a, b;
+  double flops;
+};
+std::mutex g_timing_mu;
+bool g_timing = false;
+std::vector<TimedLaunch> g_timed;
+std::vector<hipEvent_t> g_event_pool;
+
+hipEvent_t pooled_event() {
+  if (!g_event_pool.empty()) {
+    hipEvent_t e = g_event_pool.back();
+    g_event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// ------------------------------------------------------------- GEMM launching
+enum class Tile { T128x64, T64x128, T64x64, T32x32 };
+
+Tile pick_tile(int M, int N) {
+  if (M >= 128 && N >= 64) return Tile::T128x64;
+  if (M >= 64 && N >= 128) return Tile::T64x128;
+  if (M >= 64 && N >= 64) return Tile::T64x64;
+  return Tile::T32x32;
+}
+
+template <int BM, int BN, int WM, int WN, bool KC, class Epi>
+int launch_cfg(GemmArgs g, const Epi& epi, hipStream_t st) {
+  g.tiles_m = (g.M + BM - 1) / BM;
+  g.tiles_n = (g.N + BN - 1) / BN;
+  g.total_tiles = (int64_t)g.tiles_m * g.tiles_n * g.nb0 * g.nb1;
+  if (g.total_tiles <= 0) return PHIKS_OK;
+  if (g.total_tiles > 0x7fffffffLL) {
+    set_error("GEMM grid too large");
+    return PHIKS_EINVAL;
+  }
+  hipEvent_t ea = nullptr, eb = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_timing_mu);
+    if (g_timing) {
+      ea = pooled_event();
+      eb = pooled_event();
+      if (ea && eb) HIP_OK(hipEventRecord(ea, st));
+    }
+  }
+  hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, WM, WN, KC, Epi>), dim3((unsigned)g.total_tiles),
+                     dim3(256), 0, st, g, epi);
+  CHECK_LAUNCH();
+  if (ea && eb) {
+    HIP_OK(hipEventRecord(eb, st));
+    std::lock_guard<std::mutex> lk(g_timing_mu);
+    g_timed.push_back({ea, eb, 2.0 * g.M * (double)g.N * g.K * g.nb0 * (double)g.nb1});
+  }
+  return PHIKS_OK;
+}
+
+template <bool KC, class Epi>
+int launch_gemm(const GemmArgs& g, const Epi& epi, hipStream_t st) {
+  switch (pick_tile(g.M, g.N)) {
+    case Tile::T128x64: return launch_cfg<128, 64, 64, 32, KC>(g, epi, st);
+    case Tile::T64x128: return launch_cfg<64, 128, 32, 64, KC>(g, epi, st);
+    case Tile::T64x64: return launch_cfg<64, 64, 32, 32, KC>(g, epi, st);
+    default: return launch_cfg<32, 32, 16, 16, KC>(g, epi, st);
+  }
+}
+
+GemmArgs empty_args() {
+  GemmArgs g;
+  std::memset(&g, 0, sizeof(g));
+  g.nb0 = g.nb1 = 1;
+  return g;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------- the plan
+struct phiks_plan_s {
+  int d = 0;
+  int64_t n[PHIKS_MAX_D] = {0};
+  int64_t N = 0;
+  double tau = 0.0;
+  int p = 0, ns = 1, task = 0, precision = 0;
+  int s = 0, q = 0, t_paper = 0, t_exec = 0;
+  double theta[kQMax] = {0}, w[kQMax] = {0};
+  int device = 0;
+  void* dmem = nullptr;                 // all plan-lifetime device matrices
+  double* Lnode[PHIKS_MAX_D] = {nullptr};  // (q-1) node matrices per mode, stride n^2
+  double* E[PHIKS_MAX_D] = {nullptr};      // (s+1) matrices per mode: exp(B/2^j), stride n^2
+  std::vector<std::vector<char>> host_keep;  // host sources of async copies
+};
+
+namespace {
+
+int64_t sq(int64_t x) { return x * x; }
+
+// ---------------------------------------------------------- Tucker operator
+// Applies, to nbatch tensors in_b = in + b*in_stride, the Tucker operator with the
+// matrices L[mu] + b*l_stride[mu] (Section 2, eq. tucker), writing the last mode
+// through the epilogue into out (batch b at out + b*N).  ta/tb: nbatch*N scratch.
+// The result of mode mu (< d) goes to ta for odd mu and tb for even mu; out must be
+// the buffer not read by the last mode.
+template <class Epi>
+int tucker(const phiks_plan_s& P, const double* in, int64_t in_stride,
+           double* const* L, const int64_t* l_stride, int nbatch, double* out,
+           double* ta, double* tb, const Epi& epi, hipStream_t st) {
+  const int d = P.d;
+  const int64_t N = P.N;
+  const double* cur = in;
+  int64_t cur_stride = in_stride;
+  for (int mu = 1; mu <= d; ++mu) {
+    const int64_t nm = P.n[mu - 1];
+    int64_t nlo = 1, nhi = 1;
+    for (int k = 0; k < mu - 1; ++k) nlo *= P.n[k];
+    for (int k = mu; k < d; ++k) nhi *= P.n[k];
+    const bool last = (mu == d);
+    double* dst = last ? out : ((mu % 2 == 1) ? ta : tb);
+    GemmArgs g = empty_args();
+    g.nb1 = nbatch;
+    if (mu == 1) {
+      // W[m][i] = sum_j X[m][j] L[i][j], rows m < n_>
+      g.M = (int)nhi;
+      g.N = (int)nm;
+      g.K = (int)nm;
+      g.A = cur;
+      g.lda = nm;
+      g.B = L[0];
+      g.ldb = nm;
+      g.C = dst;
+      g.ldc = nm;
+      g.sA1 = cur_stride;
+      g.sB1 = l_stride[0];
+      g.sC1 = N;
+      if (last) RET_IF((launch_gemm<true>(g, epi, st)));
+      else RET_IF((launch_gemm<true>(g, EpiStore{1.0, 0.0}, st)));
+    } else {
+      // W_b[i][a] = sum_j L[i][j] X_b[j][a], batch b < n_>
+      g.M = (int)nm;
+      g.N = (int)nlo;
+      g.K = (int)nm;
+      g.A = L[mu - 1];
+      g.lda = nm;
+      g.B = cur;
+      g.ldb = nlo;
+      g.C = dst;
+      g.ldc = nlo;
+      g.nb0 = (int)nhi;
+      g.sA0 = 0;
+      g.sB0 = nm * nlo;
+      g.sC0 = nm * nlo;
+      g.sA1 = l_stride[mu - 1];
+      g.sB1 = cur_stride;
+      g.sC1 = N;
+      if (last) RET_IF((launch_gemm<false>(g, epi, st)));
+      else RET_IF((launch_gemm<false>(g, EpiStore{1.0, 0.0}, st)));
+    }
+    cur = dst;
+    cur_stride = N;
+  }
+  return PHIKS_OK;
+}
+
+// the buffer (ta or tb) that the last mode does not read
+double* tucker_free_buffer(int d, double* ta, double* tb) {
+  if (d == 1) return ta;
+  return ((d - 1) % 2 == 1) ? tb : ta;
+}
+
+int launch_combine(const CombineArgs& a, hipStream_t st) {
+  if (a.N <= 0 || a.nout <= 0) return PHIKS_OK;
+  int64_t blocks = (a.N + 255) / 256;
+  blocks = std::min<int64_t>(blocks, 8192);
+  hipLaunchKernelGGL(combine_kernel, dim3((unsigned)blocks), dim3(256), 0, st, a);
+  CHECK_LAUNCH();
+  return PHIKS_OK;
+}
+
+double factorial(int k) {
+  double f = 1.0;
+  for (int i = 2; i <= k; ++i) f *= i;
+  return f;
+}
+
+// ----------------------------------------------------------- Pade parameters
+// Backward-error thresholds theta_m for the [m/m] Pade approximant in double
+// precision and the degree selection of Higham, "The scaling and squaring method
+// for the matrix exponential revisited" (SIAM J. Matrix Anal. Appl. 2005), which is
+// the method the paper's expm follows.
+const int kPadeM[5] = {3, 5, 7, 9, 13};
+const double kPadeTheta[5] = {1.495585217958292e-2, 2.539398330063230e-1,
+                              9.504178996162932e-1, 2.097847961257068e0,
+                              5.371920351148152e0};
+
+// b_j = (2m - j)! m! / ((2m)! j! (m - j)!)
+void pade_coefs(int m, double* b) {
+  for (int j = 0; j <= m; ++j) {
+    long double v = 1.0L;
+    // (2m-j)!/(2m)! * m!/(m-j)! / j!
+    for (int k = 2 * m - j + 1; k <= 2 * m; ++k) v /= k;
+    for (int k = m - j + 1; k <= m; ++k) v *= k;
+    for (int k = 2; k <= j; ++k) v /= k;
+    b[j] = (double)v;
+  }
+}
+
+struct ExpmRequest {
+  int mu;          // mode
+  double c;        // exp(c B_mu) is requested
+  double* dst;     // n^2 destination
+};
+
+// Computes exp(c_r B_{mu_r}) for every request on the device.
+int batched_expm(phiks_plan_s& P, const std::vector<std::vector<double>>& Bshift,
+                 const double* sigma, const double* norm1,
+                 const std::vector<ExpmRequest>& reqs, hipStream_t st) {
+  const int d = P.d;
+  if (reqs.empty()) return PHIKS_OK;
+  // degree and scaling per request
+  struct Sel { int m; int t; double gamma; };
+  std::vector<Sel> sel(reqs.size());
+  int max_nk[PHIKS_MAX_D] = {0};
+  for (size_t r = 0; r < reqs.size(); ++r) {
+    const double x = std::fabs(reqs[r].c) * norm1[reqs[r].mu];
+    Sel s{13, 0, reqs[r].c};
+    bool done = false;
+    for (int k = 0; k < 4 && !done; ++k)
+      if (x <= kPadeTheta[k]) { s.m = kPadeM[k]; done = true; }
+    if (!done) {
+      s.m = 13;
+      s.t = (x > kPadeTheta[4]) ? (int)std::ceil(std::log2(x / kPadeTheta[4])) : 0;
+      if (s.t < 0) s.t = 0;
+      s.gamma = reqs[r].c / std::ldexp(1.0, s.t);
+    }
+    sel[r] = s;
+    max_nk[reqs[r].mu] = std::max(max_nk[reqs[r].mu], (s.m - 1) / 2);
+  }
+  // scratch: per mode Bs + 6 powers; per request SU, V, U, Q, X, T
+  size_t total = 0;
+  std::vector<size_t> mode_off(d), req_off(reqs.size());
+  for (int mu = 0; mu < d; ++mu) { mode_off[mu] = total; total += 7 * sq(P.n[mu]); }
+  for (size_t r = 0; r < reqs.size(); ++r) { req_off[r] = total; total += 6 * sq(P.n[reqs[r].mu]); }
+  double* scratch = nullptr;
+  HIP_OK(hipMallocAsync((void**)&scratch, total * sizeof(double), st));
+  auto bs_ptr = [&](int mu) { return scratch + mode_off[mu]; };
+  auto pw_ptr = [&](int mu, int k) { return scratch + mode_off[mu] + (size_t)k * sq(P.n[mu]); };
+  for (int mu = 0; mu < d; ++mu) {
+    P.host_keep.emplace_back(sizeof(double) * Bshift[mu].size());
+    std::memcpy(P.host_keep.back().data(), Bshift[mu].data(), P.host_keep.back().size());
+    HIP_OK(hipMemcpyAsync(bs_ptr(mu), P.host_keep.back().data(), P.host_keep.back().size(),
+                          hipMemcpyHostToDevice, st));
+  }
+  // even powers Bs^2 .. Bs^(2 nk) per mode: P2 = Bs Bs, P(2k) = P(2k-2) P2
+  int kmax = 0;
+  for (int mu = 0; mu < d; ++mu) kmax = std::max(kmax, max_nk[mu]);
+  std::vector<const double*> hA, hB;
+  std::vector<double*> hC;
+  auto run_ptr_gemm = [&](std::vector<const double*>& a, std::vector<const double*>& b,
+                          std::vector<double*>& c, int n) -> int {
+    if (a.empty()) return PHIKS_OK;
+    const size_t nb = a.size();
+    P.host_keep.emplace_back(3 * nb * sizeof(void*));
+    void** hp = (void**)P.host_keep.back().data();
+    for (size_t i = 0; i < nb; ++i) {
+      hp[i] = (void*)a[i];
+      hp[nb + i] = (void*)b[i];
+      hp[2 * nb + i] = (void*)c[i];
+    }
+    void** dp = nullptr;
+    HIP_OK(hipMallocAsync((void**)&dp, 3 * nb * sizeof(void*), st));
+    HIP_OK(hipMemcpyAsync(dp, hp, 3 * nb * sizeof(void*), hipMemcpyHostToDevice, st));
+    GemmArgs g = empty_args();
+    g.M = g.N = g.K = n;
+    g.lda = g.ldb = g.ldc = n;
+    g.nb1 = (int)nb;
+    g.pA = (const double* const*)dp;
+    g.pB = (const double* const*)(dp + nb);
+    g.pC = (double* const*)(dp + 2 * nb);
+    int rc = launch_gemm<false>(g, EpiStore{1.0, 0.0}, st);
+    HIP_OK(hipFreeAsync(dp, st));
+    return rc;
+  };
+  // group modes by size for the pointer-array GEMMs
+  std::vector<int64_t> sizes;
+  for (int mu = 0; mu < d; ++mu)
+    if (std::find(sizes.begin(), sizes.end(), P.n[mu]) == sizes.end()) sizes.push_back(P.n[mu]);
+  for (int k = 1; k <= kmax; ++k) {
+    for (int64_t nsz : sizes) {
+      std::vector<const double*> a, b;
+      std::vector<double*> c;
+      for (int mu = 0; mu < d; ++mu) {
+        if (P.n[mu] != nsz || max_nk[mu] < k) continue;
+        if (k == 1) { a.push_back(bs_ptr(mu)); b.push_back(bs_ptr(mu)); }
+        else { a.push_back(pw_ptr(mu, k - 1)); b.push_back(pw_ptr(mu, 1)); }
+        c.push_back(pw_ptr(mu, k));
+      }
+      RET_IF(run_ptr_gemm(a, b, c, (int)nsz));
+    }
+  }
+  // jobs
+  std::vector<ExpmJob> jobs(reqs.size());
+  for (size_t r = 0; r < reqs.size(); ++r) {
+    const int mu = reqs[r].mu;
+    const int64_t nn = sq(P.n[mu]);
+    ExpmJob& J = jobs[r];
+    std::memset(&J, 0, sizeof(J));
+    const Sel& s = sel[r];
+    double b[14];
+    pade_coefs(s.m, b);
+    J.nk = (s.m - 1) / 2;
+    J.n = (int)P.n[mu];
+    for (int k = 1; k <= J.nk; ++k) J.pw[k] = pw_ptr(mu, k);
+    double g2k = 1.0;  // gamma^(2k)
+    for (int k = 0; k <= J.nk; ++k) {
+      J.cv[k] = b[2 * k] * g2k;
+      J.cu[k] = b[2 * k + 1] * g2k * s.gamma;
+      g2k *= s.gamma * s.gamma;
+    }
+    double* base = scratch + req_off[r];
+    J.SU = base;
+    J.V = base + nn;
+    J.U = base + 2 * nn;
+    J.Q = base + 3 * nn;
+    J.X = base + 4 * nn;
+  }
+  P.host_keep.emplace_back(jobs.size() * sizeof(ExpmJob));
+  std::memcpy(P.host_keep.back().data(), jobs.data(), P.host_keep.back().size());
+  ExpmJob* djobs = nullptr;
+  HIP_OK(hipMallocAsync((void**)&djobs, jobs.size() * sizeof(ExpmJob), st));
+  HIP_OK(hipMemcpyAsync(djobs, P.host_keep.back().data(), jobs.size() * sizeof(ExpmJob),
+                        hipMemcpyHostToDevice, st));
+  int64_t nmax = 0;
+  for (int mu = 0; mu < d; ++mu) nmax = std::max(nmax, P.n[mu]);
+  const unsigned eblocks = (unsigned)std::min<int64_t>((sq(nmax) + 255) / 256, 1024);
+  hipLaunchKernelGGL(expm_form_kernel, dim3(eblocks, (unsigned)jobs.size()), dim3(256), 0, st,
+                     djobs);
+  CHECK_LAUNCH();
+  // U = Bs * SU
+  for (int64_t nsz : sizes) {
+    std::vector<const double*> a, b;
+    std::vector<double*> c;
+    for (size_t r = 0; r < reqs.size(); ++r) {
+      if (P.n[reqs[r].mu] != nsz) continue;
+      a.push_back(bs_ptr(reqs[r].mu));
+      b.push_back(jobs[r].SU);
+      c.push_back(jobs[r].U);
+    }
+    RET_IF(run_ptr_gemm(a, b, c, (int)nsz));
+  }
+  hipLaunchKernelGGL(expm_qx_kernel, dim3(eblocks, (unsigned)jobs.size()), dim3(256), 0, st,
+                     djobs);
+  CHECK_LAUNCH();
+  hipLaunchKernelGGL(lu_solve_kernel, dim3((unsigned)jobs.size()), dim3(kSolveThreads), 0, st,
+                     djobs);
+  CHECK_LAUNCH();
+  // squarings: X <- X^2 (ping-pong through the T buffer)
+  std::vector<double*> curp(reqs.size()), othp(reqs.size());
+  int tmax = 0;
+  for (size_t r = 0; r < reqs.size(); ++r) {
+    curp[r] = jobs[r].X;
+    othp[r] = scratch + req_off[r] + 5 * sq(P.n[reqs[r].mu]);
+    tmax = std::max(tmax, sel[r].t);
+  }
+  for (int t = 0; t < tmax; ++t) {
+    for (int64_t nsz : sizes) {
+      std::vector<const double*> a, b;
+      std::vector<double*> c;
+      std::vector<size_t> idx;
+      for (size_t r = 0; r < reqs.size(); ++r) {
+        if (P.n[reqs[r].mu] != nsz || sel[r].t <= t) continue;
+        a.push_back(curp[r]);
+        b.push_back(curp[r]);
+        c.push_back(othp[r]);
+        idx.push_back(r);
+      }
+      RET_IF(run_ptr_gemm(a, b, c, (int)nsz));
+      for (size_t r : idx) std::swap(curp[r], othp[r]);
+    }
+  }
+  // dst = e^{c sigma} X
+  std::vector<ScaleJob> sj(reqs.size());
+  for (size_t r = 0; r < reqs.size(); ++r) {
+    sj[r].src = curp[r];
+    sj[r].dst = reqs[r].dst;
+    sj[r].scale = std::exp(reqs[r].c * sigma[reqs[r].mu]);
+    sj[r].n = (int)P.n[reqs[r].mu];
+  }
+  P.host_keep.emplace_back(sj.size() * sizeof(ScaleJob));
+  std::memcpy(P.host_keep.back().data(), sj.data(), P.host_keep.back().size());
+  ScaleJob* dsj = nullptr;
+  HIP_OK(hipMallocAsync((void**)&dsj, sj.size() * sizeof(ScaleJob), st));
+  HIP_OK(hipMemcpyAsync(dsj, P.host_keep.back().data(), sj.size() * sizeof(ScaleJob),
+                        hipMemcpyHostToDevice, st));
+  hipLaunchKernelGGL(scale_copy_kernel, dim3(eblocks, (unsigned)sj.size()), dim3(256), 0, st,
+                     dsj);
+  CHECK_LAUNCH();
+  HIP_OK(hipFreeAsync(dsj, st));
+  HIP_OK(hipFreeAsync(djobs, st));
+  HIP_OK(hipFreeAsync(scratch, st));
+  return PHIKS_OK;
+}
+
+int validate_problem(int d, const int64_t* n, const double* const* A, double tau, int p,
+                     int n_scales, double tol, int task, const double* vnorms) {
+  if (d < 1 || d > PHIKS_MAX_D || !n || !A) return PHIKS_EINVAL;
+  if (p < 0 || p > PHIKS_MAX_P || n_scales < 1 || n_scales > 16) return PHIKS_EINVAL;
+  if (task != PHIKS_SAME_VECTOR && task != PHIKS_LINCOMB) return PHIKS_EINVAL;
+  if (!std::isfinite(tau) || !std::isfinite(tol)) return PHIKS_ENONFINITE;
+  if (!(tau > 0.0) || !(tol > 0.0)) return PHIKS_EINVAL;
+  int64_t N = 1;
+  for (int mu = 0; mu < d; ++mu) {
+    if (n[mu] < 1 || n[mu] > PHIKS_MAX_N || !A[mu]) return PHIKS_EINVAL;
+    N *= n[mu];
+    if (N > (int64_t)1 << 40) return PHIKS_EINVAL;
+    for (int64_t e = 0; e < n[mu] * n[mu]; ++e)
+      if (!std::isfinite(A[mu][e])) return PHIKS_ENONFINITE;
+  }
+  if (vnorms) {
+    const int nv = (task == PHIKS_SAME_VECTOR) ? 1 : p + 1;
+    for (int k = 0; k < nv; ++k)
+      if (!std::isfinite(vnorms[k]) || vnorms[k] < 0.0) return PHIKS_EINVAL;
+  }
+  return PHIKS_OK;
+}
+
+// host planning shared by phiks_plan and phiks_plan_params
+int host_plan(int d, const int64_t* n, const double* const* A, double tau, int p,
+              int n_scales, double tol, int task, const double* vnorms, PlanChoice& pc) {
+  Rect xi{0.0, 0.0, 0.0, 0.0};
+  for (int mu = 0; mu < d; ++mu) {
+    Rect r = bendixson_rectangle(n[mu], A[mu]);
+    xi.re_lo += tau * r.re_lo;
+    xi.re_hi += tau * r.re_hi;
+    xi.im_lo += tau * r.im_lo;
+    xi.im_hi += tau * r.im_hi;
+  }
+  pc = choose_sq(xi, p, n_scales, tol, task, vnorms);
+  if (!pc.ok) {
+    set_error("no (s, q) with s <= 64 and q <= 12 meets the tolerance");
+    return PHIKS_ENOPLAN;
+  }
+  return PHIKS_OK;
+}
+
+size_t workspace_doubles(const phiks_plan_s& P) {
+  const int64_t N = P.N;
+  if (P.task == PHIKS_SAME_VECTOR) {
+    const int64_t t = std::max<int64_t>({(int64_t)P.q - 1, (int64_t)P.p, 1});
+    return (size_t)(2 * t + 2 * P.p) * N;
+  }
+  const int64_t pp = std::max(P.p, 1);
+  return (size_t)(5 * pp) * N;
+}
+
+}  // namespace
+
+// =================================================================== C ABI
+extern "C" {
+
+const char* phiks_status_string(int status) {
+  switch (status) {
+    case PHIKS_OK: return "ok";
+    case PHIKS_EINVAL: return "invalid argument";
+    case PHIKS_ENOPLAN: return "no (s, q) meets the tolerance";
+    case PHIKS_ENOMEM: return "out of memory";
+    case PHIKS_EDEVICE: return "device error";
+    case PHIKS_EWORKSPACE: return "workspace missing or too small";
+    case PHIKS_ENONFINITE: return "non-finite input";
+    default: return "unknown status";
+  }
+}
+
+const char* phiks_last_error(void) { return g_last_error.c_str(); }
+
+int phiks_gll(int q, double* theta, double* w) {
+  if (q < 2 || q > kQMax || !theta || !w) return PHIKS_EINVAL;
+  gll_rule(q, theta, w);
+  return PHIKS_OK;
+}
+
+int phiks_rectangle(int64_t n, const double* B, double* xi) {
+  if (n < 1 || n > PHIKS_MAX_N || !B || !xi) return PHIKS_EINVAL;
+  for (int64_t e = 0; e < n * n; ++e)
+    if (!std::isfinite(B[e])) return PHIKS_ENONFINITE;
+  Rect r = bendixson_rectangle(n, B);
+  xi[0] = r.re_lo;
+  xi[1] = r.re_hi;
+  xi[2] = r.im_lo;
+  xi[3] = r.im_hi;
+  return PHIKS_OK;
+}
+
+int phiks_remainder(int q, int p, double w_re, double w_im, double* err) {
+  if (q < 2 || q > kQMax || p < 1 || p > PHIKS_MAX_P || !err) return PHIKS_EINVAL;
+  if (!std::isfinite(w_re) || !std::isfinite(w_im)) return PHIKS_ENONFINITE;
+  remainder(q, p, w_re, w_im, err);
+  return PHIKS_OK;
+}
+
+int phiks_plan_params(int d, const int64_t* n, const double* const* A, double tau, int p,
+                      int n_scales, double tol, int task, const double* vnorms, int* s,
+                      int* q, int* tucker_paper) {
+  int rc = validate_problem(d, n, A, tau, p, n_scales, tol, task, vnorms);
+  if (rc != PHIKS_OK) return rc;
+  PlanChoice pc;
+  rc = host_plan(d, n, A, tau, p, n_scales, tol, task, vnorms, pc);
+  if (rc != PHIKS_OK) return rc;
+  if (s) *s = pc.s;
+  if (q) *q = pc.q;
+  if (tucker_paper) *tucker_paper = pc.tucker_paper;
+  return PHIKS_OK;
+}
+
+int phiks_plan(int d, const int64_t* n, const double* const* A, double tau, int p,
+               int n_scales, double tol, int task, const double* vnorms, int precision,
+               void* hip_stream, phiks_plan_t* out) {
+  if (!out) return PHIKS_EINVAL;
+  *out = nullptr;
+  int rc = validate_problem(d, n, A, tau, p, n_scales, tol, task, vnorms);
+  if (rc != PHIKS_OK) return rc;
+  if (precision != PHIKS_FP64) return PHIKS_EINVAL;
+  PlanChoice pc;
+  rc = host_plan(d, n, A, tau, p, n_scales, tol, task, vnorms, pc);
+  if (rc != PHIKS_OK) return rc;
+
+  phiks_plan_s* P = new (std::nothrow) phiks_plan_s;
+  if (!P) return PHIKS_ENOMEM;
+  P->d = d;
+  P->N = 1;
+  for (int mu = 0; mu < d; ++mu) { P->n[mu] = n[mu]; P->N *= n[mu]; }
+  P->tau = tau;
+  P->p = p;
+  P->ns = n_scales;
+  P->task = task;
+  P->precision = precision;
+  P->s = pc.s;
+  P->q = pc.q;
+  P->t_paper = pc.tucker_paper;
+  if (p > 0) gll_rule(pc.q, P->theta, P->w);
+  const int nodes = (p > 0) ? pc.q - 1 : 0;  // nodes with theta < 1 need a Tucker
+  if (task == PHIKS_SAME_VECTOR) P->t_exec = nodes + pc.s * p + n_scales;
+  else P->t_exec = nodes * p + pc.s * p + n_scales;
+  hipStream_t st = (hipStream_t)hip_stream;
+  auto fail = [&](int code) {
+    phiks_plan_destroy(P);
+    return code;
+  };
+  if (hipGetDevice(&P->device) != hipSuccess) { set_error("hipGetDevice failed"); return fail(PHIKS_EDEVICE); }
+
+  // plan-lifetime device memory: node matrices and exp(B/2^j), j = 0..s
+  size_t total = 0;
+  size_t offL[PHIKS_MAX_D], offE[PHIKS_MAX_D];
+  for (int mu = 0; mu < d; ++mu) {
+    offL[mu] = total;
+    total += (size_t)nodes * sq(n[mu]);
+    offE[mu] = total;
+    total += (size_t)(pc.s + 1) * sq(n[mu]);
+  }
+  if (hipMalloc(&P->dmem, std::max<size_t>(total, 1) * sizeof(double)) != hipSuccess) {
+    set_error("hipMalloc of plan matrices failed");
+    return fail(PHIKS_ENOMEM);
+  }
+  double* base = (double*)P->dmem;
+  for (int mu = 0; mu < d; ++mu) {
+    P->Lnode[mu] = base + offL[mu];
+    P->E[mu] = base + offE[mu];
+  }
+  // shifted operators B_mu - sigma_mu I, sigma_mu = tr(B_mu)/n_mu (the shift remark
+  // of Section 3.1), and their 1-norms for the Pade degree choice
+  std::vector<std::vector<double>> Bs(d);
+  double sigma[PHIKS_MAX_D], norm1[PHIKS_MAX_D];
+  for (int mu = 0; mu < d; ++mu) {
+    const int64_t m = n[mu];
+    Bs[mu].resize(m * m);
+    double tr = 0.0;
+    for (int64_t i = 0; i < m; ++i) tr += A[mu][i * m + i];
+    sigma[mu] = tau * tr / m;
+    for (int64_t e = 0; e < m * m; ++e) Bs[mu][e] = tau * A[mu][e];
+    for (int64_t i = 0; i < m; ++i) Bs[mu][i * m + i] -= sigma[mu];
+    double nrm = 0.0;
+    for (int64_t j = 0; j < m; ++j) {
+      double col = 0.0;
+      for (int64_t i = 0; i < m; ++i) col += std::fabs(Bs[mu][i * m + j]);
+      nrm = std::max(nrm, col);
+    }
+    norm1[mu] = nrm;
+  }
+  // requests: node matrices exp((1-theta_i) B / 2^s) for theta_i < 1 (theta_0 = 0
+  // gives exp(B/2^s) itself), or exp(B/2^s) alone when there is no quadrature
+  std::vector<ExpmRequest> reqs;
+  const double inv2s = std::ldexp(1.0, -pc.s);
+  for (int mu = 0; mu < d; ++mu) {
+    if (nodes > 0) {
+      for (int i = 0; i < nodes; ++i)
+        reqs.push_back({mu, (1.0 - P->theta[i]) * inv2s, P->Lnode[mu] + (size_t)i * sq(n[mu])});
+    } else {
+      reqs.push_back({mu, inv2s, P->E[mu] + (size_t)pc.s * sq(n[mu])});
+    }
+  }
+  rc = batched_expm(*P, Bs, sigma, norm1, reqs, st);
+  if (rc != PHIKS_OK) return fail(rc);
+  if (nodes > 0) {
+    for (int mu = 0; mu < d; ++mu) {
+      if (hipMemcpyAsync(P->E[mu] + (size_t)pc.s * sq(n[mu]), P->Lnode[mu],
+                         sq(n[mu]) * sizeof(double), hipMemcpyDeviceToDevice, st) != hipSuccess) {
+        set_error("hipMemcpyAsync failed");
+        return fail(PHIKS_EDEVICE);
+      }
+    }
+  }
+  // exp(B/2^(j-1)) = exp(B/2^j)^2, j = s..1 (Section 3.1)
+  for (int j = pc.s; j >= 1; --j) {
+    for (int mu = 0; mu < d; ++mu) {
+      GemmArgs g = empty_args();
+      const int64_t m = n[mu];
+      g.M = g.N = g.K = (int)m;
+      g.lda = g.ldb = g.ldc = m;
+      g.A = P->E[mu] + (size_t)j * sq(m);
+      g.B = g.A;
+      g.C = P->E[mu] + (size_t)(j - 1) * sq(m);
+      rc = launch_gemm<false>(g, EpiStore{1.0, 0.0}, st);
+      if (rc != PHIKS_OK) return fail(rc);
+    }
+  }
+  *out = P;
+  return PHIKS_OK;
+}
+
+void phiks_plan_destroy(phiks_plan_t plan) {
+  if (!plan) return;
+  if (plan->dmem) {
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(plan->device);
+    (void)hipDeviceSynchronize();
+    (void)hipFree(plan->dmem);
+    (void)hipSetDevice(cur);
+  }
+  delete plan;
+}
+
+int phiks_plan_info(phiks_plan_t plan, int* s, int* q, int* tucker_paper, int* tucker_exec) {
+  if (!plan) return PHIKS_EINVAL;
+  if (s) *s = plan->s;
+  if (q) *q = plan->q;
+  if (tucker_paper) *tucker_paper = plan->t_paper;
+  if (tucker_exec) *tucker_exec = plan->t_exec;
+  return PHIKS_OK;
+}
+
+int phiks_kernel_timing(int enable) {
+  std::lock_guard<std::mutex> lk(g_timing_mu);
+  g_timing = (enable != 0);
+  return PHIKS_OK;
+}
+
+int phiks_kernel_timing_read(double* total_ms, int64_t* launches, double* flops) {
+  if (!total_ms || !launches || !flops) return PHIKS_EINVAL;
+  std::lock_guard<std::mutex> lk(g_timing_mu);
+  double ms = 0.0, fl = 0.0;
+  for (auto& t : g_timed) {
+    HIP_OK(hipEventSynchronize(t.b));
+    float x = 0.0f;
+    HIP_OK(hipEventElapsedTime(&x, t.a, t.b));
+    ms += x;
+    fl += t.flops;
+    g_event_pool.push_back(t.a);
+    g_event_pool.push_back(t.b);
+  }
+  *total_ms = ms;
+  *launches = (int64_t)g_timed.size();
+  *flops = fl;
+  g_timed.clear();
+  return PHIKS_OK;
+}
+
+int phiks_tucker(int d, const int64_t* n, const double* const* L, const double* v,
+                 double* out, void* ws, size_t ws_bytes, void* hip_stream) {
+  if (d < 1 || d > PHIKS_MAX_D || !n || !L || !v || !out) return PHIKS_EINVAL;
+  phiks_plan_s P;
+  P.d = d;
+  P.N = 1;
+  for (int mu = 0; mu < d; ++mu) {
+    if (n[mu] < 1 || n[mu] > PHIKS_MAX_N || !L[mu]) return PHIKS_EINVAL;
+    P.n[mu] = n[mu];
+    P.N *= n[mu];
+  }
+  const size_t need = (d >= 2) ? 2 * (size_t)P.N * sizeof(double) : 0;
+  if (need > 0 && (!ws || ws_bytes < need)) return PHIKS_EWORKSPACE;
+  double* ta = (double*)ws;
+  double* tb = ta ? ta + P.N : nullptr;
+  double* Ls[PHIKS_MAX_D];
+  int64_t zero_stride[PHIKS_MAX_D] = {0};
+  for (int mu = 0; mu < d; ++mu) Ls[mu] = const_cast<double*>(L[mu]);
+  return tucker(P, v, 0, Ls, zero_stride, 1, out, ta, tb, EpiStore{1.0, 0.0},
+                (hipStream_t)hip_stream);
+}
+
+int phiks_workspace_size(phiks_plan_t plan, size_t* bytes) {
+  if (!plan || !bytes) return PHIKS_EINVAL;
+  *bytes = workspace_doubles(*plan) * sizeof(double);
+  return PHIKS_OK;
+}
+
+int phiks_apply(phiks_plan_t plan, const double* v, double* out, void* ws, size_t ws_bytes,
+                void* hip_stream) {
+  if (!plan || !v || !out) return PHIKS_EINVAL;
+  if (plan->task != PHIKS_SAME_VECTOR) return PHIKS_EINVAL;
+  const phiks_plan_s& P = *plan;
+  const size_t need = workspace_doubles(P) * sizeof(double);
+  if (!ws || ws_bytes < need) return PHIKS_EWORKSPACE;
+  hipStream_t st = (hipStream_t)hip_stream;
+  const int64_t N = P.N;
+  const int p = P.p, ns = P.ns, s = P.s, q = P.q, d = P.d;
+  const int64_t tcount = std::max<int64_t>({(int64_t)q - 1, (int64_t)p, 1});
+  double* ta = (double*)ws;
+  double* tb = ta + tcount * N;
+  double* pa = tb + tcount * N;
+  double* pb = pa + (int64_t)p * N;
+  auto slot = [&](int level, int ell) { return out + ((int64_t)level * (p + 1) + ell) * N; };
+  double* Lsh[PHIKS_MAX_D];
+  int64_t zero_stride[PHIKS_MAX_D] = {0};
+  int64_t node_stride[PHIKS_MAX_D];
+  for (int mu = 0; mu < d; ++mu) node_stride[mu] = sq(P.n[mu]);
+
+  if (p > 0) {
+    // eq. integrandsimul: one Tucker per node theta_i < 1, all nodes in one batch
+    const int nodes = q - 1;
+    double* wbuf = tucker_free_buffer(d, ta, tb);
+    RET_IF(tucker(P, v, 0, P.Lnode, node_stride, nodes, wbuf, ta, tb, EpiStore{1.0, 0.0}, st));
+    double* cur = (s < ns) ? slot(s, 1) : pa;
+    CombineArgs ca;
+    std::memset(&ca, 0, sizeof(ca));
+    ca.nin = nodes + 1;
+    for (int i = 0; i < nodes; ++i) ca.in[i] = wbuf + (int64_t)i * N;
+    ca.in[nodes] = v;  // theta_q = 1: exp(0) v = v
+    ca.out = cur;
+    ca.out_stride = N;
+    ca.nout = p;
+    ca.beta = 0.0;
+    ca.N = N;
+    for (int ell = 1; ell <= p; ++ell)
+      for (int i = 0; i < q; ++i)
+        ca.coef[ell - 1][i] = P.w[i] * std::pow(P.theta[i], ell - 1) / factorial(ell - 1);
+    RET_IF(launch_combine(ca, st));
+    // eq. simul: j = s..1, fused into the last mu-mode product of Tucker(P_l; E_j)
+    for (int j = s; j >= 1; --j) {
+      double* dst = (j - 1 < ns) ? slot(j - 1, 1) : ((cur == pa) ? pb : pa);
+      EpiLinComb epi;
+      std::memset(&epi, 0, sizeof(epi));
+      epi.Y = cur;
+      epi.N = N;
+      epi.p = p;
+      for (int ell = 1; ell <= p; ++ell) {
+        const double sc = std::ldexp(1.0, -ell);
+        epi.a[ell - 1] = sc;
+        for (int k = 1; k <= ell; ++k) epi.c[ell - 1][k - 1] = sc / factorial(ell - k);
+      }
+      for (int mu = 0; mu < d; ++mu) Lsh[mu] = P.E[mu] + (size_t)j * sq(P.n[mu]);
+      RET_IF(tucker(P, cur, N, Lsh, zero_stride, p, dst, ta, tb, epi, st));
+      cur = dst;
+    }
+  }
+  // exponential outputs exp(2^-j tau K) v (eq. tucker with exp(B/2^j))
+  for (int lev = 0; lev < ns; ++lev) {
+    for (int mu = 0; mu < d; ++mu) Lsh[mu] = P.E[mu] + (size_t)lev * sq(P.n[mu]);
+    RET_IF(tucker(P, v, 0, Lsh, zero_stride, 1, slot(lev, 0), ta, tb, EpiStore{1.0, 0.0}, st));
+  }
+  return PHIKS_OK;
+}
+
+int phiks_combine(phiks_plan_t plan, const double* const* v, double* out, void* ws,
+                  size_t ws_bytes, void* hip_stream) {
+  if (!plan || !v || !out) return PHIKS_EINVAL;
+  if (plan->task != PHIKS_LINCOMB) return PHIKS_EINVAL;
+  const phiks_plan_s& P = *plan;
+  const size_t need = workspace_doubles(P) * sizeof(double);
+  if (!ws || ws_bytes < need) return PHIKS_EWORKSPACE;
+  hipStream_t st = (hipStream_t)hip_stream;
+  const int64_t N = P.N;
+  const int p = P.p, ns = P.ns, s = P.s, q = P.q, d = P.d;
+  const int64_t pp = std::max(p, 1);
+  double* U = (double*)ws;
+  double* ta = U + pp * N;
+  double* tb = ta + pp * N;
+  double* qa = tb + pp * N;
+  double* qb = qa + pp * N;
+  double* Lsh[PHIKS_MAX_D];
+  int64_t zero_stride[PHIKS_MAX_D] = {0};
+  bool any = false;
+  for (int k = 1; k <= p; ++k) any = any || (v[k] != nullptr);
+
+  // node inputs U_il = sum_{k<=l} theta^(l-k)/(l-k)! v_{p+1-k} / 2^((l-k+1)s)
+  auto node_inputs = [&](double th, double scale, double* dst, double beta) -> int {
+    CombineArgs ca;
+    std::memset(&ca, 0, sizeof(ca));
+    ca.out = dst;
+    ca.out_stride = N;
+    ca.nout = p;
+    ca.beta = beta;
+    ca.N = N;
+    int t = 0;
+    for (int vi = 1; vi <= p; ++vi) {  // vi = p + 1 - k
+      if (!v[vi]) continue;
+      ca.in[t] = v[vi];
+      const int k = p + 1 - vi;
+      for (int ell = 1; ell <= p; ++ell) {
+        double c = 0.0;
+        if (k <= ell)
+          c = scale * std::pow(th, ell - k) / factorial(ell - k) * std::ldexp(1.0, -(ell - k + 1) * s);
+        ca.coef[ell - 1][t] = c;
+      }
+      ++t;
+    }
+    ca.nin = t;
+    return launch_combine(ca, st);
+  };
+
+  auto emit = [&](int lev, const double* Q) -> int {
+    double* o = out + (int64_t)lev * N;
+    for (int mu = 0; mu < d; ++mu) Lsh[mu] = P.E[mu] + (size_t)lev * sq(P.n[mu]);
+    if (v[0]) {
+      if (Q) {
+        EpiLinComb epi;
+        std::memset(&epi, 0, sizeof(epi));
+        epi.Y = Q + (int64_t)(p - 1) * N;
+        epi.N = N;
+        epi.p = 1;
+        epi.a[0] = 1.0;
+        epi.c[0][0] = 1.0;
+        return tucker(P, v[0], 0, Lsh, zero_stride, 1, o, ta, tb, epi, st);
+      }
+      return tucker(P, v[0], 0, Lsh, zero_stride, 1, o, ta, tb, EpiStore{1.0, 0.0}, st);
+    }
+    if (Q) {
+      HIP_OK(hipMemcpyAsync(o, Q + (int64_t)(p - 1) * N, N * sizeof(double),
+                            hipMemcpyDeviceToDevice, st));
+      return PHIKS_OK;
+    }
+    HIP_OK(hipMemsetAsync(o, 0, N * sizeof(double), st));
+    return PHIKS_OK;
+  };
+
+  const double* Qcur = nullptr;
+  if (p > 0 && any) {
+    double* Q = qa;
+    // node theta_q = 1: no Tucker, Q_l = w_q U_ql
+    RET_IF(node_inputs(1.0, P.w[q - 1], Q, 0.0));
+    for (int i = 0; i < q - 1; ++i) {
+      RET_IF(node_inputs(P.theta[i], 1.0, U, 0.0));
+      for (int mu = 0; mu < d; ++mu) Lsh[mu] = P.Lnode[mu] + (size_t)i * sq(P.n[mu]);
+      RET_IF(tucker(P, U, N, Lsh, zero_stride, p, Q, ta, tb, EpiStore{P.w[i], 1.0}, st));
+    }
+    double* cur = Q;
+    if (s < ns) RET_IF(emit(s, cur));
+    // eq. comb: Q_l <- Tucker(Q_l; E_j) + sum_{k<=l} Q_k / ((l-k)! 2^((l-k) j))
+    for (int j = s; j >= 1; --j) {
+      double* dst = (cur == qa) ? qb : qa;
+      EpiLinComb epi;
+      std::memset(&epi, 0, sizeof(epi));
+      epi.Y = cur;
+      epi.N = N;
+      epi.p = p;
+      for (int ell = 1; ell <= p; ++ell) {
+        epi.a[ell - 1] = 1.0;
+        for (int k = 1; k <= ell; ++k)
+          epi.c[ell - 1][k - 1] = std::ldexp(1.0, -(ell - k) * j) / factorial(ell - k);
+      }
+      for (int mu = 0; mu < d; ++mu) Lsh[mu] = P.E[mu] + (size_t)j * sq(P.n[mu]);
+      RET_IF(tucker(P, cur, N, Lsh, zero_stride, p, dst, ta, tb, epi, st));
+      cur = dst;
+      if (j - 1 < ns) RET_IF(emit(j - 1, cur));
+    }
+    Qcur = cur;
+  } else {
+    for (int lev = 0; lev < ns; ++lev) RET_IF(emit(lev, nullptr));
+  }
+  (void)Qcur;
+  return PHIKS_OK;
+}
+
+}  // extern "C"

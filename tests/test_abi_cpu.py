@@ -1,0 +1,152 @@
+"""C ABI checks that need no GPU: the library loads, exports every entry point of
+include/phiks.h, validates arguments, and its host planning steps (Gauss-Lobatto
+rule, rectangle, remainder, (s, q) choice) agree with the oracle."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workloads
+from oracle import bound, gll
+
+ph = pytest.importorskip("paper_2210_07667_amd")
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_exports_every_declared_symbol():
+    hdr = open(os.path.join(ROOT, "include", "phiks.h")).read()
+    declared = set(re.findall(r"^\s*(?:int|void|const char\*)\s+(phiks_\w+)\s*\(", hdr, re.M))
+    assert declared, "no declarations parsed"
+    lib = ctypes.CDLL(ph.LIB_PATH)
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert declared == set(ph.SYMBOLS)
+
+
+def test_status_strings():
+    for code in range(-6, 1):
+        assert ph.status_string(code) != "unknown status"
+
+
+@pytest.mark.parametrize("q", range(2, 13))
+def test_gll_matches_oracle(q):
+    t1, w1 = ph.phiks_gll(q)
+    t2, w2 = gll.gll(q)
+    assert np.max(np.abs(np.subtract(t1, t2))) <= 2.3e-16
+    assert np.max(np.abs(np.subtract(w1, w2))) <= 2.3e-16
+
+
+def test_remainder_matches_exact_quadrature_error():
+    """Contour integral with the recurrence-evaluated kernel (library) against the
+    exact quadrature error computed in high precision (oracle)."""
+    rng = np.random.default_rng(0)
+    for _ in range(120):
+        q = int(rng.integers(3, 13))
+        mag = 10 ** rng.uniform(-2.5, 1.6)
+        ang = rng.uniform(0, 2 * np.pi)
+        w = complex(mag * np.cos(ang), mag * np.sin(ang))
+        a = ph.phiks_remainder(q, 5, w)
+        b = bound.quad_errors(q, w, 5)
+        for x, y in zip(a, b):
+            assert abs(x - y) <= 1e-8 * y + 1e-300, (q, w, x, y)
+
+
+@pytest.mark.parametrize("kind", ["adr", "dense", "cheb"])
+def test_rectangle_matches_oracle(kind):
+    rng = np.random.default_rng(3)
+    B = {"adr": workloads.adr_1d(40, 0.5, 1.0, -1.0),
+         "dense": rng.standard_normal((33, 33)),
+         "cheb": workloads.cheb_d2_dirichlet(24)}[kind]
+    a = np.array(ph.phiks_rectangle(B))
+    b = np.array(bound.rectangle(B))
+    assert np.allclose(a, b, rtol=1e-12, atol=1e-12 * np.abs(b).max())
+
+
+CONFIGS = [
+    lambda: workloads.config_fd2_2d(),
+    lambda: workloads.config_allen_cahn_3d(tau=1e-3),
+    lambda: workloads.config_allen_cahn_3d(tau=1e-2),
+    lambda: workloads.config_adr_3d(tau=1e-3),
+    lambda: workloads.config_adr_3d(tau=1e-4),
+]
+
+
+@pytest.mark.parametrize("make", CONFIGS)
+def test_plan_matches_oracle_planner(make):
+    w = make()
+    got = ph.phiks_plan_params(w.A, w.tau, w.p, w.n_scales, w.tol, w.task)
+    xi = bound.kron_sum_rectangle([w.tau * a for a in w.A])
+    assert got == tuple(bound.plan(xi, w.p, w.n_scales, w.tol, w.task))
+
+
+def test_plan_matches_oracle_on_small_sweep():
+    rng = np.random.default_rng(4)
+    for trial in range(6):
+        d = int(rng.integers(1, 4))
+        n = [int(rng.integers(2, 9)) for _ in range(d)]
+        A = [workloads.adr_1d(k, 0.5, float(rng.uniform(-2, 2)), -1.0) for k in n]
+        tau = float(10 ** rng.uniform(-3, -1))
+        p = int(rng.integers(1, 6))
+        ns = int(rng.integers(1, 4))
+        task = "same_vector" if trial % 2 == 0 else "lincomb"
+        vn = None
+        if trial % 3 == 2:
+            vn = [float(x) for x in rng.uniform(0.1, 10, 1 if task == "same_vector" else p + 1)]
+        got = ph.phiks_plan_params(A, tau, p, ns, 2.0 ** -53, task, vn)
+        xi = bound.kron_sum_rectangle([tau * a for a in A])
+        ref = bound.plan(xi, p, ns, 2.0 ** -53, task, vn)
+        assert got == tuple(ref), (trial, d, n, tau, p, ns, task)
+
+
+def test_invalid_arguments_are_rejected():
+    A = [workloads.fd2_dirichlet(4)]
+    with pytest.raises(ph.PhiksError) as e:
+        ph.phiks_plan_params(A, -1.0, 2, 1, 1e-10)
+    assert e.value.status == ph.PHIKS_EINVAL
+    with pytest.raises(ph.PhiksError) as e:
+        ph.phiks_plan_params(A, float("nan"), 2, 1, 1e-10)
+    assert e.value.status == ph.PHIKS_ENONFINITE
+    with pytest.raises(ph.PhiksError) as e:
+        ph.phiks_plan_params(A, 1e-3, 2, 1, 0.0)
+    assert e.value.status == ph.PHIKS_EINVAL
+    with pytest.raises(ph.PhiksError) as e:
+        ph.phiks_plan_params(A, 1e-3, 99, 1, 1e-10)
+    assert e.value.status == ph.PHIKS_EINVAL
+    with pytest.raises(ph.PhiksError) as e:
+        ph.phiks_plan_params(A, 1e-3, 2, 0, 1e-10)
+    assert e.value.status == ph.PHIKS_EINVAL
+    bad = workloads.fd2_dirichlet(4)
+    bad[1, 2] = np.inf
+    with pytest.raises(ph.PhiksError) as e:
+        ph.phiks_plan_params([bad], 1e-3, 2, 1, 1e-10)
+    assert e.value.status == ph.PHIKS_ENONFINITE
+    with pytest.raises(ph.PhiksError) as e:
+        ph.phiks_plan_params([np.zeros((2000, 2000))], 1e-3, 2, 1, 1e-10)
+    assert e.value.status == ph.PHIKS_EINVAL
+    with pytest.raises(ph.PhiksError) as e:
+        ph.phiks_plan_params(A, 1e-3, 2, 1, 1e-10, "lincomb", [1.0, -2.0, 1.0])
+    assert e.value.status == ph.PHIKS_EINVAL
+    assert ph.phiks_plan_params_raw(0, None, None, 1e-3, 1, 1, 1e-10, 0, None) == ph.PHIKS_EINVAL
+
+
+def test_unreachable_tolerance_gives_enoplan():
+    """A tolerance far below what q <= 12 can reach at any s <= 64."""
+    A = [workloads.fd2_dirichlet(8)]
+    with pytest.raises(ph.PhiksError) as e:
+        ph.phiks_plan_params(A, 1e-2, 3, 1, 1e-300)
+    assert e.value.status == ph.PHIKS_ENOPLAN
+
+
+def test_host_only_calls_on_null_plan():
+    lib = ctypes.CDLL(ph.LIB_PATH)
+    lib.phiks_plan_info.argtypes = [ctypes.c_void_p] + [ctypes.c_void_p] * 4
+    assert lib.phiks_plan_info(None, None, None, None, None) == ph.PHIKS_EINVAL
+    lib.phiks_workspace_size.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+    assert lib.phiks_workspace_size(None, None) == ph.PHIKS_EINVAL
+    lib.phiks_apply.argtypes = [ctypes.c_void_p] * 4 + [ctypes.c_size_t, ctypes.c_void_p]
+    assert lib.phiks_apply(None, None, None, None, 0, None) == ph.PHIKS_EINVAL
+    lib.phiks_plan_destroy.argtypes = [ctypes.c_void_p]
+    lib.phiks_plan_destroy(None)

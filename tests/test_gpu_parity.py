@@ -1,0 +1,212 @@
+"""GPU parity: libphiks (HIP, gfx950) against the FP64 CPU oracle.
+
+All calls go through the C ABI (ctypes binding).  Parity is measured with the same
+plan (s, q): the library's planner and the oracle's planner are checked to choose
+the same (s, q) on the CPU, and here the oracle is run with the plan the library
+reports.  Bar: relative infinity-norm difference <= 1e-12 (FP64 path); the error
+of one mu-mode product is ~ n eps, and the squaring recurrence multiplies it by at
+most ~2^s (s <= 8 here), so 1e-12 leaves a margin above rounding.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads
+from oracle import bound, phiks as ophiks, tensor
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+ph = pytest.importorskip("paper_2210_07667_amd")
+TOL = 1e-12
+
+
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda", 0)
+
+
+def relerr(got, ref):
+    got, ref = np.asarray(got), np.asarray(ref)
+    return float(np.abs(got - ref).max() / max(np.abs(ref).max(), 1e-300))
+
+
+def to_dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64)).to(dev())
+
+
+# ----------------------------------------------------------- Tucker operator
+TUCKER_SHAPES = [[1], [7], [33], [300], [5, 3], [64, 64], [17, 130], [129, 65], [3, 4, 5],
+                 [40, 33, 20], [64, 64, 64], [2, 3, 2, 3], [9, 10, 11, 8], [256, 3, 2],
+                 [2, 257, 3], [5, 5, 5, 5, 5]]
+
+
+@pytest.mark.parametrize("n", TUCKER_SHAPES, ids=lambda n: "x".join(map(str, n)))
+def test_tucker_vs_oracle(n):
+    print(f"[tucker] n={n}", flush=True)
+    rng = np.random.default_rng(sum(n))
+    Ls = [rng.standard_normal((k, k)) / math.sqrt(k) for k in n]
+    v = rng.standard_normal(int(np.prod(n)))
+    out = ph.tucker_torch(n, [to_dev(L) for L in Ls], to_dev(v))
+    torch.cuda.synchronize()
+    ref = tensor.tucker(v, n, Ls)
+    assert relerr(out.cpu().numpy(), ref) < 1e-13
+
+
+# ------------------------------------------------------------- phi actions
+def run_apply(A, tau, v, p, ns, tol=2.0 ** -53):
+    plan = ph.phiks_plan(A, tau, p, ns, tol, "same_vector")
+    out = ph.apply_torch(plan, to_dev(v))
+    torch.cuda.synchronize()
+    info = plan.info()
+    plan.close()
+    return out.cpu().numpy(), info
+
+
+def run_combine(A, tau, vs, p, ns, tol=2.0 ** -53):
+    plan = ph.phiks_plan(A, tau, p, ns, tol, "lincomb")
+    out = ph.combine_torch(plan, [None if x is None else to_dev(x) for x in vs])
+    torch.cuda.synchronize()
+    info = plan.info()
+    plan.close()
+    return out.cpu().numpy(), info
+
+
+SV_CASES = [
+    ("adr", [6], 0.5, 3, 1),
+    ("adr", [5, 4, 3], 2e-2, 4, 2),
+    ("adr", [33, 17], 5e-3, 5, 3),
+    ("adr", [3, 3, 2, 2], 0.05, 2, 1),
+    ("adr", [40, 30, 20], 1e-3, 4, 2),
+    ("fd2", [65, 70], 2e-3, 4, 1),
+    ("cheb", [24, 20], 1e-3, 3, 1),
+]
+
+
+def ops(kind, n):
+    if kind == "fd2":
+        return [workloads.fd2_dirichlet(k) for k in n]
+    if kind == "cheb":
+        return [workloads.cheb_d2_dirichlet(k) for k in n]
+    betas = [1.0, 0.5, 0.25, 0.125]
+    return [workloads.adr_1d(k, 0.5, betas[i], -1.0) for i, k in enumerate(n)]
+
+
+@pytest.mark.parametrize("kind,n,tau,p,ns", SV_CASES)
+def test_apply_vs_oracle(kind, n, tau, p, ns):
+    print(f"[apply] {kind} n={n} tau={tau} p={p} ns={ns}", flush=True)
+    A = ops(kind, n)
+    v = workloads.randn_vec(n, 21)
+    got, info = run_apply(A, tau, v, p, ns)
+    ref = ophiks.phi_same_vector(A, tau, v, p, ns, info["s"], info["q"])
+    for j in range(ns):
+        for ell in range(p + 1):
+            assert relerr(got[j, ell], ref[j, ell]) < TOL, (j, ell, info)
+
+
+def test_apply_fd2_32x32_workload():
+    """2D FD Laplacian 32x32, tau = 1e-3, phi_0..phi_3, tolerance 2^-53 ||v||."""
+    w = workloads.config_fd2_2d()
+    got, info = run_apply(w.A, w.tau, w.v, w.p, w.n_scales, w.tol)
+    ref = ophiks.phi_same_vector(w.A, w.tau, w.v, w.p, w.n_scales, info["s"], info["q"])
+    for ell in range(w.p + 1):
+        assert relerr(got[0, ell], ref[0, ell]) < TOL
+
+
+def test_apply_exponential_only():
+    A = ops("adr", [20, 9, 7])
+    v = workloads.randn_vec([20, 9, 7], 22)
+    got, info = run_apply(A, 0.02, v, 0, 3)
+    ref = ophiks.phi_same_vector(A, 0.02, v, 0, 3, info["s"], info["q"])
+    assert info["s"] == 2 and info["q"] == 0
+    for j in range(3):
+        assert relerr(got[j, 0], ref[j, 0]) < TOL
+
+
+LC_CASES = [
+    ([6], 0.3, 3, 1),
+    ([5, 4, 3], 2e-2, 4, 3),
+    ([31, 18], 5e-3, 2, 2),
+    ([12, 11, 10], 1e-2, 5, 2),
+]
+
+
+@pytest.mark.parametrize("n,tau,p,ns", LC_CASES)
+def test_combine_vs_oracle(n, tau, p, ns):
+    print(f"[combine] n={n} tau={tau} p={p} ns={ns}", flush=True)
+    A = ops("adr", n)
+    rng = np.random.default_rng(23)
+    N = int(np.prod(n))
+    vs = [rng.standard_normal(N) for _ in range(p + 1)]
+    got, info = run_combine(A, tau, vs, p, ns)
+    ref = ophiks.phi_lincomb(A, tau, vs, p, ns, info["s"], info["q"])
+    for j in range(ns):
+        assert relerr(got[j], ref[j]) < TOL, (j, info)
+
+
+def test_combine_with_missing_vectors():
+    A = ops("adr", [9, 8, 7])
+    rng = np.random.default_rng(24)
+    vs = [None, rng.standard_normal(504), None, rng.standard_normal(504)]
+    got, info = run_combine(A, 0.03, vs, 3, 2)
+    ref = ophiks.phi_lincomb(A, 0.03, vs, 3, 2, info["s"], info["q"])
+    for j in range(2):
+        assert relerr(got[j], ref[j]) < TOL
+
+
+def test_combine_allen_cahn_64_workload():
+    """3D Allen-Cahn 64^3 combination exp(tau K)u0 + sum_l phi_l(tau K) tau g(u0), p = 4,
+    two scales, tau = 1e-3 and 1e-2."""
+    for tau in (1e-3, 1e-2):
+        w = workloads.config_allen_cahn_3d(tau=tau)
+        print(f"[combine] allen-cahn 64^3 tau={tau}", flush=True)
+        got, info = run_combine(w.A, w.tau, w.vs, w.p, w.n_scales, w.tol)
+        ref = ophiks.phi_lincomb(w.A, w.tau, w.vs, w.p, w.n_scales, info["s"], info["q"])
+        for j in range(w.n_scales):
+            assert relerr(got[j], ref[j]) < TOL, (tau, j, info)
+
+
+def test_plan_matches_library_planner_and_counts():
+    w = workloads.config_adr_3d(n=64)
+    s, q, t = ph.phiks_plan_params(w.A, w.tau, w.p, w.n_scales, w.tol, w.task)
+    plan = ph.phiks_plan(w.A, w.tau, w.p, w.n_scales, w.tol, w.task)
+    info = plan.info()
+    plan.close()
+    assert (info["s"], info["q"], info["tucker_paper"]) == (s, q, t)
+    assert info["tucker_exec"] == (q - 1) + s * w.p + w.n_scales
+
+
+def test_workspace_too_small_is_rejected():
+    A = ops("adr", [8, 8])
+    plan = ph.phiks_plan(A, 1e-2, 2, 1, 1e-12)
+    v = to_dev(np.ones(64))
+    out = torch.empty(3 * 64, dtype=torch.float64, device=dev())
+    ws = torch.empty(8, dtype=torch.float64, device=dev())
+    with pytest.raises(ph.PhiksError) as e:
+        ph.phiks_apply(plan, v.data_ptr(), out.data_ptr(), ws.data_ptr(), 64)
+    assert e.value.status == ph.PHIKS_EWORKSPACE
+    with pytest.raises(ph.PhiksError) as e:
+        ph.phiks_combine(plan, [v.data_ptr()] * 3, out.data_ptr(), ws.data_ptr(), 1 << 20)
+    assert e.value.status == ph.PHIKS_EINVAL    # plan made for the same-vector task
+    plan.close()
+
+
+# ------------------------------------------------------- full-size 256^3 case
+def test_adr_256_full_size_against_oracle():
+    """3D ADR 256^3, phi_0..phi_4 on one vector, tau = 1e-3, tolerance 2^-53 ||v||:
+    the whole output against the oracle run with the same (s, q), plus the
+    recurrence phi_l = tau K phi_{l+1} + I/l! as an independent property."""
+    w = workloads.config_adr_3d()
+    print("[apply] adr 256^3 full size", flush=True)
+    got, info = run_apply(w.A, w.tau, w.v, w.p, w.n_scales, w.tol)
+    print(f"[apply] plan {info}; running oracle", flush=True)
+    ref = ophiks.phi_same_vector(w.A, w.tau, w.v, w.p, w.n_scales, info["s"], info["q"])
+    for ell in range(w.p + 1):
+        assert relerr(got[0, ell], ref[0, ell]) < TOL, ell
+    B = [w.tau * a for a in w.A]
+    for ell in range(w.p):
+        lhs = got[0, ell]
+        rhs = tensor.kron_sum_apply(B, got[0, ell + 1]) + w.v / math.factorial(ell)
+        assert relerr(lhs, rhs) < 1e-9, ell
