@@ -11,8 +11,9 @@ exponentials of the small matrices and their squarings, and the phi-action call
 the timed region.  The value is dofs/s = N * steps / time.
 
 Also reported (same JSON line): the roofline of the dominant kernel (the FP64 MFMA
-mu-mode product), measured live with HIP events around every mu-mode launch of the
-timed region, and the CPU oracle timed on this host for one full call.
+mu-mode product), measured live with HIP events recorded by the library around every
+mu-mode launch of the timed region, and the CPU oracle timed on this host for one full
+call.  Device memory comes from the library itself (no other GPU framework is loaded).
 """
 from __future__ import annotations
 
@@ -71,64 +72,56 @@ def main():
               "(multi-GPU slab sharding is a design note, not built)", file=sys.stderr)
         sys.exit(2)
 
-    import torch
     import paper_2210_07667_amd as ph
     import workloads
 
-    dev = torch.device("cuda", 0)
+    if ph.device_count() < 1:
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
     w = workloads.config_adr_3d(n=args.n)
     log(f"[bench] workload {w.name} N={w.N} tau={w.tau} p={w.p}")
-    v = torch.from_numpy(w.v).to(dev)
-    stream = torch.cuda.current_stream(dev)
-    st = stream.cuda_stream
+    v = ph.DeviceArray.from_numpy(w.v)
+    st = 0  # null stream
 
     plan = ph.phiks_plan(w.A, w.tau, w.p, w.n_scales, w.tol, w.task, stream=st)
     info = plan.info()
-    ws = torch.empty(plan.workspace_size() // 8 + 1, dtype=torch.float64, device=dev)
-    out = torch.empty((w.n_scales, w.p + 1, w.N), dtype=torch.float64, device=dev)
+    ws = ph.DeviceArray(plan.workspace_size() // 8 + 1)
+    out = ph.DeviceArray(w.n_scales * (w.p + 1) * w.N)
     plan.close()
-    log(f"[bench] plan {info}, workspace {ws.numel() * 8 / 2**30:.2f} GiB")
+    log(f"[bench] plan {info}, workspace {ws.nbytes / 2**30:.2f} GiB")
 
     def step():
         pl = ph.phiks_plan(w.A, w.tau, w.p, w.n_scales, w.tol, w.task, stream=st)
-        ph.phiks_apply(pl, v.data_ptr(), out.data_ptr(), ws.data_ptr(), ws.numel() * 8, st)
+        ph.phiks_apply(pl, v.ptr, out.ptr, ws.ptr, ws.nbytes, st)
         pl.close()
 
     for i in range(args.warmup):
         step()
         log(f"[bench] warmup {i + 1}/{args.warmup}")
-    torch.cuda.synchronize()
+    ph.synchronize()
 
     ph.phiks_kernel_timing_read()          # clear
     ph.phiks_kernel_timing(True)
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
+    ph.synchronize()
     t0 = time.perf_counter()
-    ev0.record(stream)
     for i in range(args.steps):
         step()
         log(f"[bench] step {i + 1}/{args.steps}")
-    ev1.record(stream)
-    torch.cuda.synchronize()
+    ph.synchronize()
     wall = time.perf_counter() - t0
     ph.phiks_kernel_timing(False)
     k_ms, k_launch, k_flops = ph.phiks_kernel_timing_read()
-    ms_total = ev0.elapsed_time(ev1)
-    ms_step = max(ms_total, wall * 1e3) / args.steps
+    ms_step = wall * 1e3 / args.steps
 
     # phi-action call alone with the plan built once (reported beside the step)
     pl = ph.phiks_plan(w.A, w.tau, w.p, w.n_scales, w.tol, w.task, stream=st)
-    torch.cuda.synchronize()
-    a0 = torch.cuda.Event(enable_timing=True)
-    a1 = torch.cuda.Event(enable_timing=True)
-    a0.record(stream)
+    ph.synchronize()
     reps = max(3, args.steps // 2)
+    a0 = time.perf_counter()
     for _ in range(reps):
-        ph.phiks_apply(pl, v.data_ptr(), out.data_ptr(), ws.data_ptr(), ws.numel() * 8, st)
-    a1.record(stream)
-    torch.cuda.synchronize()
-    apply_ms = a0.elapsed_time(a1) / reps
+        ph.phiks_apply(pl, v.ptr, out.ptr, ws.ptr, ws.nbytes, st)
+    ph.synchronize()
+    apply_ms = (time.perf_counter() - a0) * 1e3 / reps
     pl.close()
 
     achieved = (k_flops / (k_ms * 1e-3)) / 1e12 if k_ms > 0 else 0.0

@@ -166,6 +166,18 @@ void phiks_plan_destroy(phiks_plan_t plan);
 int phiks_kernel_timing(int enable);
 int phiks_kernel_timing_read(double* total_ms, int64_t* launches, double* flops);
 
+/*
+ * Device-memory plumbing for callers without their own allocator (the Python
+ * binding and the tests use these, so that one HIP runtime -- the one this library
+ * was built against -- serves the whole process).  Copies are synchronous.
+ */
+int phiks_device_count(int* count);            /* 0 when no GPU is visible */
+int phiks_device_alloc(size_t bytes, void** ptr);
+int phiks_device_free(void* ptr);
+int phiks_memcpy_htod(void* dst, const void* src, size_t bytes);
+int phiks_memcpy_dtoh(void* dst, const void* src, size_t bytes);
+int phiks_device_synchronize(void);
+
 /* Static text for a status code. */
 const char* phiks_status_string(int status);
 

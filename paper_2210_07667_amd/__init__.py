@@ -2,10 +2,13 @@
 
 Argument marshalling only: every step of the computation runs inside libphiks
 (host planner in C++, all vector work in HIP kernels on gfx950).  Device buffers are
-passed as raw device addresses (e.g. ``tensor.data_ptr()`` of a torch tensor on the
-GPU) and streams as raw ``hipStream_t`` handles (``torch.cuda.current_stream()
-.cuda_stream``).  The library must have been built (``python -m
-paper_2210_07667_amd.build``); importing this module fails loudly otherwise.
+raw device addresses; ``DeviceArray`` allocates them through the library itself, so
+that the process uses the one HIP runtime the library was built against (a second,
+differently versioned HIP runtime in the same process -- e.g. one bundled with
+another framework -- would be shadowed by soname and is not supported).  Streams are
+raw ``hipStream_t`` handles (0 = the null stream).  The library must have been built
+(``python paper_2210_07667_amd/build.py``); importing this module fails loudly
+otherwise -- there is no CPU fallback.
 """
 from __future__ import annotations
 
@@ -34,7 +37,9 @@ SYMBOLS = ("phiks_plan", "phiks_apply", "phiks_combine", "phiks_workspace_size",
            "phiks_plan_info", "phiks_plan_destroy", "phiks_status_string",
            "phiks_last_error", "phiks_plan_params", "phiks_gll", "phiks_rectangle",
            "phiks_remainder", "phiks_tucker", "phiks_kernel_timing",
-           "phiks_kernel_timing_read")
+           "phiks_kernel_timing_read", "phiks_device_count", "phiks_device_alloc",
+           "phiks_device_free", "phiks_memcpy_htod", "phiks_memcpy_dtoh",
+           "phiks_device_synchronize")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with "
@@ -248,67 +253,112 @@ def phiks_remainder(q: int, p: int, w: complex):
     return list(err)
 
 
-# ------------------------------------------------------------- torch helpers
-def _torch():
-    import torch
-    return torch
+# ----------------------------------------------------------- device arrays
+_lib.phiks_device_count.restype = ctypes.c_int
+_lib.phiks_device_count.argtypes = [ctypes.POINTER(ctypes.c_int)]
+_lib.phiks_device_alloc.restype = ctypes.c_int
+_lib.phiks_device_alloc.argtypes = [ctypes.c_size_t, ctypes.POINTER(_vp)]
+_lib.phiks_device_free.restype = ctypes.c_int
+_lib.phiks_device_free.argtypes = [_vp]
+_lib.phiks_memcpy_htod.restype = ctypes.c_int
+_lib.phiks_memcpy_htod.argtypes = [_vp, _vp, ctypes.c_size_t]
+_lib.phiks_memcpy_dtoh.restype = ctypes.c_int
+_lib.phiks_memcpy_dtoh.argtypes = [_vp, _vp, ctypes.c_size_t]
+_lib.phiks_device_synchronize.restype = ctypes.c_int
+_lib.phiks_device_synchronize.argtypes = []
 
 
-def apply_torch(plan: Plan, v, out=None, ws=None, stream=None):
-    """Same-vector task on torch float64 CUDA tensors; returns out of shape
-    (n_scales, p+1, N)."""
-    torch = _torch()
+def device_count() -> int:
+    n = ctypes.c_int()
+    _check(_lib.phiks_device_count(ctypes.byref(n)), "phiks_device_count")
+    return n.value
+
+
+def synchronize() -> None:
+    _check(_lib.phiks_device_synchronize(), "phiks_device_synchronize")
+
+
+class DeviceArray:
+    """float64 buffer in device memory (allocated through libphiks)."""
+
+    def __init__(self, n: int):
+        self.n = int(n)
+        p = ctypes.c_void_p()
+        _check(_lib.phiks_device_alloc(max(self.n, 1) * 8, ctypes.byref(p)), "phiks_device_alloc")
+        self._p = p
+
+    @property
+    def ptr(self) -> int:
+        return self._p.value
+
+    @property
+    def nbytes(self) -> int:
+        return self.n * 8
+
+    @classmethod
+    def from_numpy(cls, x) -> "DeviceArray":
+        x = np.ascontiguousarray(np.asarray(x, dtype=np.float64)).reshape(-1)
+        d = cls(x.size)
+        _check(_lib.phiks_memcpy_htod(d._p, x.ctypes.data_as(_vp), x.nbytes), "phiks_memcpy_htod")
+        return d
+
+    def to_numpy(self) -> np.ndarray:
+        x = np.empty(self.n, dtype=np.float64)
+        _check(_lib.phiks_memcpy_dtoh(x.ctypes.data_as(_vp), self._p, x.nbytes), "phiks_memcpy_dtoh")
+        return x
+
+    def free(self) -> None:
+        if self._p is not None and self._p.value:
+            _lib.phiks_device_free(self._p)
+        self._p = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def apply_arrays(plan: Plan, v: DeviceArray, out: Optional[DeviceArray] = None,
+                 ws: Optional[DeviceArray] = None, stream: int = 0) -> DeviceArray:
+    """Same-vector task; out holds n_scales * (p+1) * N values."""
     if plan.task != PHIKS_SAME_VECTOR:
         raise ValueError("plan was made for a linear combination")
-    if v.dtype != torch.float64 or not v.is_cuda or not v.is_contiguous() or v.numel() != plan.N:
-        raise ValueError("v must be a contiguous float64 GPU tensor of N entries")
+    if v.n != plan.N:
+        raise ValueError("v must hold N values")
     if out is None:
-        out = torch.empty((plan.n_scales, plan.p + 1, plan.N), dtype=torch.float64,
-                          device=v.device)
-    nbytes = plan.workspace_size()
+        out = DeviceArray(plan.n_scales * (plan.p + 1) * plan.N)
     if ws is None:
-        ws = torch.empty(max(nbytes // 8, 1), dtype=torch.float64, device=v.device)
-    st = torch.cuda.current_stream(v.device).cuda_stream if stream is None else stream
-    phiks_apply(plan, v.data_ptr(), out.data_ptr(), ws.data_ptr(), ws.numel() * 8, st)
+        ws = DeviceArray(plan.workspace_size() // 8 + 1)
+    phiks_apply(plan, v.ptr, out.ptr, ws.ptr, ws.nbytes, stream)
     return out
 
 
-def tucker_torch(n: Sequence[int], Ls, v, out=None, stream=None):
-    """Tucker operator on torch float64 GPU tensors (Ls: list of n_mu x n_mu)."""
-    torch = _torch()
-    N = int(np.prod(n))
-    if out is None:
-        out = torch.empty(N, dtype=torch.float64, device=v.device)
-    ws = torch.empty(max(2 * N, 1), dtype=torch.float64, device=v.device)
-    st = torch.cuda.current_stream(v.device).cuda_stream if stream is None else stream
-    phiks_tucker(n, [L.data_ptr() for L in Ls], v.data_ptr(), out.data_ptr(), ws.data_ptr(),
-                 ws.numel() * 8, st)
-    return out
-
-
-def combine_torch(plan: Plan, vs, out=None, ws=None, stream=None):
-    """Linear-combination task; vs = [v_0, ..., v_p] (None for zero vectors);
-    returns out of shape (n_scales, N)."""
-    torch = _torch()
+def combine_arrays(plan: Plan, vs, out: Optional[DeviceArray] = None,
+                   ws: Optional[DeviceArray] = None, stream: int = 0) -> DeviceArray:
+    """Linear-combination task; vs = [v_0, ..., v_p] (None for zero vectors)."""
     if plan.task != PHIKS_LINCOMB:
         raise ValueError("plan was made for the same-vector task")
     if len(vs) != plan.p + 1:
         raise ValueError("need p+1 vectors")
-    dev = None
     for x in vs:
-        if x is None:
-            continue
-        if x.dtype != torch.float64 or not x.is_cuda or not x.is_contiguous() or x.numel() != plan.N:
-            raise ValueError("vectors must be contiguous float64 GPU tensors of N entries")
-        dev = x.device
-    if dev is None:
-        dev = torch.device("cuda", torch.cuda.current_device())
+        if x is not None and x.n != plan.N:
+            raise ValueError("vectors must hold N values")
     if out is None:
-        out = torch.empty((plan.n_scales, plan.N), dtype=torch.float64, device=dev)
-    nbytes = plan.workspace_size()
+        out = DeviceArray(plan.n_scales * plan.N)
     if ws is None:
-        ws = torch.empty(max(nbytes // 8, 1), dtype=torch.float64, device=dev)
-    st = torch.cuda.current_stream(dev).cuda_stream if stream is None else stream
-    phiks_combine(plan, [None if x is None else x.data_ptr() for x in vs], out.data_ptr(),
-                  ws.data_ptr(), ws.numel() * 8, st)
+        ws = DeviceArray(plan.workspace_size() // 8 + 1)
+    phiks_combine(plan, [None if x is None else x.ptr for x in vs], out.ptr, ws.ptr, ws.nbytes,
+                  stream)
+    return out
+
+
+def tucker_arrays(n: Sequence[int], Ls: Sequence[DeviceArray], v: DeviceArray,
+                  out: Optional[DeviceArray] = None, stream: int = 0) -> DeviceArray:
+    N = int(np.prod(n))
+    if out is None:
+        out = DeviceArray(N)
+    ws = DeviceArray(2 * N)
+    phiks_tucker(n, [L.ptr for L in Ls], v.ptr, out.ptr, ws.ptr, ws.nbytes, stream)
+    ws.free()
     return out

@@ -14,7 +14,7 @@
 // MFMA: v_mfma_f64_16x16x4_f64.  Per lane l (64-wide wave):
 //   A operand  A[m0 + (l & 15)][k0 + (l >> 4)]
 //   B operand  B[k0 + (l >> 4)][n0 + (l & 15)]
-//   C result   c[r] = C[m0 + 4 (l >> 4) + r][n0 + (l & 15)],  r = 0..3
+//   C result   c[r] = C[m0 + (l >> 4) + 4 r][n0 + (l & 15)],  r = 0..3
 //
 // Launch: 1-D grid over (m tiles, n tiles, batch) with the m-tile fastest, so that
 // the work-groups sharing one B tile are consecutive; the work-group ids are then
@@ -207,7 +207,7 @@ __global__ void __launch_bounds__(256) gemm_f64_kernel(GemmArgs g, Epi epi) {
       const int n = n0 + wn + j * 16 + lr;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int m = m0 + wm + i * 16 + 4 * lk + r;
+        const int m = m0 + wm + i * 16 + lk + 4 * r;
         if (m < g.M && n < g.N) epi(Cb, cbase + (int64_t)m * g.ldc + n, acc[i][j][r]);
       }
     }

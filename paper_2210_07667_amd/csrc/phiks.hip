@@ -109,6 +109,7 @@ int launch_cfg(GemmArgs g, const Epi& epi, hipStream_t st) {
       if (ea && eb) HIP_OK(hipEventRecord(ea, st));
     }
   }
+  (void)hipGetLastError();  // clear a stale error left by an unrelated earlier call
   hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, WM, WN, KC, Epi>), dim3((unsigned)g.total_tiles),
                      dim3(256), 0, st, g, epi);
   CHECK_LAUNCH();
@@ -235,6 +236,7 @@ int launch_combine(const CombineArgs& a, hipStream_t st) {
   if (a.N <= 0 || a.nout <= 0) return PHIKS_OK;
   int64_t blocks = (a.N + 255) / 256;
   blocks = std::min<int64_t>(blocks, 8192);
+  (void)hipGetLastError();
   hipLaunchKernelGGL(combine_kernel, dim3((unsigned)blocks), dim3(256), 0, st, a);
   CHECK_LAUNCH();
   return PHIKS_OK;
@@ -396,6 +398,7 @@ int batched_expm(phiks_plan_s& P, const std::vector<std::vector<double>>& Bshift
   int64_t nmax = 0;
   for (int mu = 0; mu < d; ++mu) nmax = std::max(nmax, P.n[mu]);
   const unsigned eblocks = (unsigned)std::min<int64_t>((sq(nmax) + 255) / 256, 1024);
+  (void)hipGetLastError();
   hipLaunchKernelGGL(expm_form_kernel, dim3(eblocks, (unsigned)jobs.size()), dim3(256), 0, st,
                      djobs);
   CHECK_LAUNCH();
@@ -411,9 +414,11 @@ int batched_expm(phiks_plan_s& P, const std::vector<std::vector<double>>& Bshift
     }
     RET_IF(run_ptr_gemm(a, b, c, (int)nsz));
   }
+  (void)hipGetLastError();
   hipLaunchKernelGGL(expm_qx_kernel, dim3(eblocks, (unsigned)jobs.size()), dim3(256), 0, st,
                      djobs);
   CHECK_LAUNCH();
+  (void)hipGetLastError();
   hipLaunchKernelGGL(lu_solve_kernel, dim3((unsigned)jobs.size()), dim3(kSolveThreads), 0, st,
                      djobs);
   CHECK_LAUNCH();
@@ -455,6 +460,7 @@ int batched_expm(phiks_plan_s& P, const std::vector<std::vector<double>>& Bshift
   HIP_OK(hipMallocAsync((void**)&dsj, sj.size() * sizeof(ScaleJob), st));
   HIP_OK(hipMemcpyAsync(dsj, P.host_keep.back().data(), sj.size() * sizeof(ScaleJob),
                         hipMemcpyHostToDevice, st));
+  (void)hipGetLastError();
   hipLaunchKernelGGL(scale_copy_kernel, dim3(eblocks, (unsigned)sj.size()), dim3(256), 0, st,
                      dsj);
   CHECK_LAUNCH();
@@ -709,6 +715,52 @@ int phiks_plan_info(phiks_plan_t plan, int* s, int* q, int* tucker_paper, int* t
   if (q) *q = plan->q;
   if (tucker_paper) *tucker_paper = plan->t_paper;
   if (tucker_exec) *tucker_exec = plan->t_exec;
+  return PHIKS_OK;
+}
+
+int phiks_device_count(int* count) {
+  if (!count) return PHIKS_EINVAL;
+  *count = 0;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess) return PHIKS_OK;  // no device: count 0
+  *count = n;
+  return PHIKS_OK;
+}
+
+int phiks_device_alloc(size_t bytes, void** ptr) {
+  if (!ptr) return PHIKS_EINVAL;
+  *ptr = nullptr;
+  if (bytes == 0) bytes = 8;
+  if (hipMalloc(ptr, bytes) != hipSuccess) {
+    set_error("hipMalloc failed");
+    *ptr = nullptr;
+    return PHIKS_ENOMEM;
+  }
+  return PHIKS_OK;
+}
+
+int phiks_device_free(void* ptr) {
+  if (!ptr) return PHIKS_OK;
+  HIP_OK(hipFree(ptr));
+  return PHIKS_OK;
+}
+
+int phiks_memcpy_htod(void* dst, const void* src, size_t bytes) {
+  if (bytes == 0) return PHIKS_OK;
+  if (!dst || !src) return PHIKS_EINVAL;
+  HIP_OK(hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice));
+  return PHIKS_OK;
+}
+
+int phiks_memcpy_dtoh(void* dst, const void* src, size_t bytes) {
+  if (bytes == 0) return PHIKS_OK;
+  if (!dst || !src) return PHIKS_EINVAL;
+  HIP_OK(hipMemcpy(dst, src, bytes, hipMemcpyDeviceToHost));
+  return PHIKS_OK;
+}
+
+int phiks_device_synchronize(void) {
+  HIP_OK(hipDeviceSynchronize());
   return PHIKS_OK;
 }
 
