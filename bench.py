@@ -66,6 +66,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first copy N doubles device-to-device once (a plain copy of known "
+                         "size, to scale hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the phi-action path here is single-GPU "
@@ -83,6 +86,12 @@ def main():
     v = ph.DeviceArray.from_numpy(w.v)
     st = 0  # null stream
 
+    if args.copy_calibration:
+        tmp = ph.DeviceArray(w.N)
+        ph.copy_device(tmp, v, st)
+        ph.synchronize()
+        tmp.free()
+        log(f"[bench] calibration copy of {w.N * 8} bytes done")
     plan = ph.phiks_plan(w.A, w.tau, w.p, w.n_scales, w.tol, w.task, stream=st)
     info = plan.info()
     ws = ph.DeviceArray(plan.workspace_size() // 8 + 1)

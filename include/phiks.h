@@ -176,6 +176,7 @@ int phiks_device_alloc(size_t bytes, void** ptr);
 int phiks_device_free(void* ptr);
 int phiks_memcpy_htod(void* dst, const void* src, size_t bytes);
 int phiks_memcpy_dtoh(void* dst, const void* src, size_t bytes);
+int phiks_memcpy_dtod(void* dst, const void* src, size_t bytes, void* hip_stream); /* async */
 int phiks_device_synchronize(void);
 
 /* Static text for a status code. */

@@ -39,7 +39,7 @@ SYMBOLS = ("phiks_plan", "phiks_apply", "phiks_combine", "phiks_workspace_size",
            "phiks_remainder", "phiks_tucker", "phiks_kernel_timing",
            "phiks_kernel_timing_read", "phiks_device_count", "phiks_device_alloc",
            "phiks_device_free", "phiks_memcpy_htod", "phiks_memcpy_dtoh",
-           "phiks_device_synchronize")
+           "phiks_device_synchronize", "phiks_memcpy_dtod")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with "
@@ -264,6 +264,8 @@ _lib.phiks_memcpy_htod.restype = ctypes.c_int
 _lib.phiks_memcpy_htod.argtypes = [_vp, _vp, ctypes.c_size_t]
 _lib.phiks_memcpy_dtoh.restype = ctypes.c_int
 _lib.phiks_memcpy_dtoh.argtypes = [_vp, _vp, ctypes.c_size_t]
+_lib.phiks_memcpy_dtod.restype = ctypes.c_int
+_lib.phiks_memcpy_dtod.argtypes = [_vp, _vp, ctypes.c_size_t, _vp]
 _lib.phiks_device_synchronize.restype = ctypes.c_int
 _lib.phiks_device_synchronize.argtypes = []
 
@@ -272,6 +274,11 @@ def device_count() -> int:
     n = ctypes.c_int()
     _check(_lib.phiks_device_count(ctypes.byref(n)), "phiks_device_count")
     return n.value
+
+
+def copy_device(dst: "DeviceArray", src: "DeviceArray", stream: int = 0) -> None:
+    n = min(dst.n, src.n) * 8
+    _check(_lib.phiks_memcpy_dtod(_vp(dst.ptr), _vp(src.ptr), n, _vp(stream)), "phiks_memcpy_dtod")
 
 
 def synchronize() -> None:

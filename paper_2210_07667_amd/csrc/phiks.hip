@@ -759,6 +759,13 @@ int phiks_memcpy_dtoh(void* dst, const void* src, size_t bytes) {
   return PHIKS_OK;
 }
 
+int phiks_memcpy_dtod(void* dst, const void* src, size_t bytes, void* hip_stream) {
+  if (bytes == 0) return PHIKS_OK;
+  if (!dst || !src) return PHIKS_EINVAL;
+  HIP_OK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, (hipStream_t)hip_stream));
+  return PHIKS_OK;
+}
+
 int phiks_device_synchronize(void) {
   HIP_OK(hipDeviceSynchronize());
   return PHIKS_OK;
