@@ -8,7 +8,7 @@
 //   mode mu > 1:   W_b[i][a] = sum_j L[i][j] X_b[j][a]         (a < n_<, batch b)
 // i.e. C = A B with A always contiguous along the contraction index k and B either
 // contiguous along n (mode > 1) or along k (mode 1, B = L^T).  No permutation of the
-// tensor is ever made; the tiles of X are staged through LDS in the layout the MFMA
+// tensor is ever made; the tiles are staged through LDS in the layout the MFMA
 // fragments read.
 //
 // MFMA: v_mfma_f64_16x16x4_f64.  Per lane l (64-wide wave):
@@ -16,19 +16,28 @@
 //   B operand  B[k0 + (l >> 4)][n0 + (l & 15)]
 //   C result   c[r] = C[m0 + (l >> 4) + 4 r][n0 + (l & 15)],  r = 0..3
 //
-// Launch: 1-D grid over (m tiles, n tiles, batch) with the m-tile fastest, so that
-// the work-groups sharing one B tile are consecutive; the work-group ids are then
-// remapped so that consecutive logical tiles land on the same XCD (the hardware
-// deals work-groups round-robin over the 8 XCDs, each with its own L2).
+// LDS: tiles are stored k-major (row k holds the BM (or BN) entries of that k) with
+// an XOR swizzle of the column index so that both the transposing stores (lanes
+// spread over k) and the fragment reads (16 columns x 2 rows per half-wave) hit
+// distinct banks: column c of row k is stored at c ^ swz(k).
+//
+// Launch: 1-D grid; the batch index z1 varies fastest, then the m tile, the n tile
+// and the inner batch index z0.  Work-groups of consecutive ids therefore share the
+// same input tile (node batches of one vector) or the same epilogue operands (the p
+// tensors of a squaring step); ids are remapped so that consecutive logical tiles
+// land on one XCD (work-groups are dealt round-robin over the 8 XCDs, each with its
+// own L2).
 #pragma once
 
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 namespace phiks {
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
+typedef double dbl2 __attribute__((ext_vector_type(2)));
 
 struct GemmArgs {
   int M, N, K;
@@ -38,12 +47,12 @@ struct GemmArgs {
   int64_t ldb;   // B(k, n) = B[k * ldb + n] (n-contiguous) or B[n * ldb + k] (k-contiguous)
   double* C;
   int64_t ldc;   // C(m, n) = C[m * ldc + n]
-  int nb0, nb1;  // batch z = z1 * nb0 + z0
+  int nb0, nb1;  // batch z = (z0, z1)
   int64_t sA0, sA1, sB0, sB1, sC0, sC1;
   int tiles_m, tiles_n;
   int64_t total_tiles;
-  // pointer-array batch (used when pA != nullptr): operands of batch z are
-  // pA[z], pB[z], pC[z]; the strides above are then ignored
+  // pointer-array batch (used when pA != nullptr): operands of batch z1 are
+  // pA[z1], pB[z1], pC[z1] (nb0 must be 1); the strides above are then ignored
   const double* const* pA;
   const double* const* pB;
   double* const* pC;
@@ -52,12 +61,12 @@ struct GemmArgs {
 // C = alpha * acc (+ beta * C).  beta == 0 never reads C.
 struct EpiStore {
   double alpha, beta;
-  __device__ __forceinline__ void operator()(double* C, int64_t e, double acc) const {
+  __device__ __forceinline__ void operator()(double* C, int64_t e, int64_t, double acc) const {
     C[e] = (beta == 0.0) ? alpha * acc : alpha * acc + beta * C[e];
   }
 };
 
-// Output tensors l = 0..p-1 of N entries each, contiguous from the C base pointer:
+// Output tensor l = z1 (the batch index; tensors N apart from the C base pointer):
 // out_l = a[l] * acc + sum_{k <= l} c[l][k] * Y_k   (Y_k = Y + k * N, same offset).
 // This is the squaring step of eq. simul / eq. comb fused into the last mu-mode product.
 struct EpiLinComb {
@@ -66,8 +75,7 @@ struct EpiLinComb {
   int p;
   double a[8];
   double c[8][8];
-  __device__ __forceinline__ void operator()(double* C, int64_t e, double acc) const {
-    const int64_t l = e / N;
+  __device__ __forceinline__ void operator()(double* C, int64_t e, int64_t l, double acc) const {
     const int64_t off = e - l * N;
     double r = a[l] * acc;
     for (int k = 0; k <= (int)l; ++k) r += c[l][k] * Y[k * N + off];
@@ -83,38 +91,45 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t g, int64_t G) {
   return (xcd < rem) ? xcd * (per + 1) + slot : rem * (per + 1) + (xcd - rem) * per + slot;
 }
 
-template <int BM, int BN, int WM, int WN, bool B_KCONTIG, class Epi>
-__global__ void __launch_bounds__(256) gemm_f64_kernel(GemmArgs g, Epi epi) {
+// swizzle of a transposed (k-major) tile: bit 4 from k's parity, bits 2..4 from k/2
+__device__ __forceinline__ int swz_t(int k) { return ((k & 1) << 4) ^ (((k >> 1) & 7) << 2); }
+// swizzle of an n-contiguous tile: flips the 16-column half on odd k
+__device__ __forceinline__ int swz_n(int k) { return (k & 1) << 4; }
+
+// VEC: operands are loaded 2 doubles (16 bytes) at a time; requires even K, lda, ldb,
+// batch strides and 16-byte aligned base pointers (checked by the launcher).
+template <int BM, int BN, int WM, int WN, bool B_KCONTIG, bool VEC, class Epi>
+__global__ void __launch_bounds__(256, 2) gemm_f64_kernel(GemmArgs g, Epi epi) {
   constexpr int BK = 16;
-  constexpr int PA = BM + ((BM % 32 == 16) ? 0 : (48 - BM % 32) % 32);  // row stride = 16 mod 32
-  constexpr int PB = BN + ((BN % 32 == 16) ? 0 : (48 - BN % 32) % 32);
   constexpr int WGM = BM / WM;
   constexpr int WGN = BN / WN;
   static_assert(WGM * WGN == 4, "4 waves per work-group");
+  static_assert(BM % 32 == 0 && BN % 32 == 0, "tiles are multiples of 32");
   constexpr int FM = WM / 16;
   constexpr int FN = WN / 16;
-  constexpr int LA = BM * BK / 256;  // A elements per thread per chunk
-  constexpr int LB = BN * BK / 256;
+  constexpr int VW = VEC ? 2 : 1;                 // doubles per load
+  constexpr int LA = BM * BK / (256 * VW);        // A loads per thread per chunk
+  constexpr int LB = BN * BK / (256 * VW);
 
-  __shared__ double As[2][BK][PA];
-  __shared__ double Bs[2][BK][PB];
+  __shared__ __align__(16) double As[2][BK][BM];
+  __shared__ __align__(16) double Bs[2][BK][BN];
 
   const int64_t t = xcd_remap(blockIdx.x, g.total_tiles);
-  const int tm = (int)(t % g.tiles_m);
-  const int64_t rest = t / g.tiles_m;
+  const int64_t z1 = t % g.nb1;
+  int64_t rest = t / g.nb1;
+  const int tm = (int)(rest % g.tiles_m);
+  rest /= g.tiles_m;
   const int tn = (int)(rest % g.tiles_n);
-  const int64_t z = rest / g.tiles_n;
-  const int64_t z0 = z % g.nb0;
-  const int64_t z1 = z / g.nb0;
+  const int64_t z0 = rest / g.tiles_n;
 
   const double* __restrict__ A;
   const double* __restrict__ B;
   double* Cb;
   int64_t cbase;
   if (g.pA != nullptr) {
-    A = g.pA[z];
-    B = g.pB[z];
-    Cb = g.pC[z];
+    A = g.pA[z1];
+    B = g.pB[z1];
+    Cb = g.pC[z1];
     cbase = 0;
   } else {
     A = g.A + z0 * g.sA0 + z1 * g.sA1;
@@ -131,40 +146,63 @@ __global__ void __launch_bounds__(256) gemm_f64_kernel(GemmArgs g, Epi epi) {
   const int wm = (wave / WGN) * WM;
   const int wn = (wave % WGN) * WN;
 
-  double ra[LA], rb[LB];
+  // Loads: A and k-contiguous B read VW consecutive k of one row per load; an
+  // n-contiguous B reads VW consecutive n of one k.  Out-of-range elements read a
+  // clamped in-range address and are replaced by zero (no branches).
+  typedef typename std::conditional<VEC, dbl2, double>::type vec_t;
+  vec_t ra[LA], rb[LB];
   auto load_chunk = [&](int k0) {
 #pragma unroll
     for (int i = 0; i < LA; ++i) {
       const int e = tid + i * 256;
-      const int m = e / BK, k = e % BK;
+      const int m = e / (BK / VW), k = VW * (e % (BK / VW));
       const int gm = m0 + m, gk = k0 + k;
-      ra[i] = (gm < g.M && gk < g.K) ? A[(int64_t)gm * g.lda + gk] : 0.0;
+      const bool ok = (gm < g.M) && (gk < g.K);
+      const int64_t off = ok ? (int64_t)gm * g.lda + gk : 0;
+      const vec_t x = *reinterpret_cast<const vec_t*>(A + off);
+      ra[i] = ok ? x : vec_t(0.0);
     }
 #pragma unroll
     for (int i = 0; i < LB; ++i) {
       const int e = tid + i * 256;
-      if constexpr (B_KCONTIG) {
-        const int n = e / BK, k = e % BK;
-        const int gn = n0 + n, gk = k0 + k;
-        rb[i] = (gn < g.N && gk < g.K) ? B[(int64_t)gn * g.ldb + gk] : 0.0;
-      } else {
-        const int k = e / BN, n = e % BN;
-        const int gn = n0 + n, gk = k0 + k;
-        rb[i] = (gn < g.N && gk < g.K) ? B[(int64_t)gk * g.ldb + gn] : 0.0;
-      }
+      int n, k;
+      if constexpr (B_KCONTIG) { n = e / (BK / VW); k = VW * (e % (BK / VW)); }
+      else { k = e / (BN / VW); n = VW * (e % (BN / VW)); }
+      const int gn = n0 + n, gk = k0 + k;
+      const bool ok = (gn < g.N) && (gk < g.K);
+      const int64_t off = ok ? (B_KCONTIG ? (int64_t)gn * g.ldb + gk : (int64_t)gk * g.ldb + gn) : 0;
+      const vec_t x = *reinterpret_cast<const vec_t*>(B + off);
+      rb[i] = ok ? x : vec_t(0.0);
     }
   };
   auto store_chunk = [&](int buf) {
 #pragma unroll
     for (int i = 0; i < LA; ++i) {
       const int e = tid + i * 256;
-      As[buf][e % BK][e / BK] = ra[i];
+      const int m = e / (BK / VW), k = VW * (e % (BK / VW));
+      if constexpr (VEC) {
+        As[buf][k][m ^ swz_t(k)] = ra[i][0];
+        As[buf][k + 1][m ^ swz_t(k + 1)] = ra[i][1];
+      } else {
+        As[buf][k][m ^ swz_t(k)] = ra[i];
+      }
     }
 #pragma unroll
     for (int i = 0; i < LB; ++i) {
       const int e = tid + i * 256;
-      if constexpr (B_KCONTIG) Bs[buf][e % BK][e / BK] = rb[i];
-      else Bs[buf][e / BN][e % BN] = rb[i];
+      if constexpr (B_KCONTIG) {
+        const int n = e / (BK / VW), k = VW * (e % (BK / VW));
+        if constexpr (VEC) {
+          Bs[buf][k][n ^ swz_t(k)] = rb[i][0];
+          Bs[buf][k + 1][n ^ swz_t(k + 1)] = rb[i][1];
+        } else {
+          Bs[buf][k][n ^ swz_t(k)] = rb[i];
+        }
+      } else {
+        const int k = e / (BN / VW), n = VW * (e % (BN / VW));
+        if constexpr (VEC) *reinterpret_cast<dbl2*>(&Bs[buf][k][n ^ swz_n(k)]) = rb[i];
+        else Bs[buf][k][n ^ swz_n(k)] = rb[i];
+      }
     }
   };
 
@@ -185,11 +223,15 @@ __global__ void __launch_bounds__(256) gemm_f64_kernel(GemmArgs g, Epi epi) {
     if (c + 1 < nchunks) load_chunk((c + 1) * BK);
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
+      const int k = kk + lk;
       double fa[FM], fb[FN];
 #pragma unroll
-      for (int i = 0; i < FM; ++i) fa[i] = As[buf][kk + lk][wm + i * 16 + lr];
+      for (int i = 0; i < FM; ++i) fa[i] = As[buf][k][(wm + i * 16 + lr) ^ swz_t(k)];
 #pragma unroll
-      for (int j = 0; j < FN; ++j) fb[j] = Bs[buf][kk + lk][wn + j * 16 + lr];
+      for (int j = 0; j < FN; ++j) {
+        if constexpr (B_KCONTIG) fb[j] = Bs[buf][k][(wn + j * 16 + lr) ^ swz_t(k)];
+        else fb[j] = Bs[buf][k][(wn + j * 16 + lr) ^ swz_n(k)];
+      }
 #pragma unroll
       for (int i = 0; i < FM; ++i)
 #pragma unroll
@@ -208,7 +250,7 @@ __global__ void __launch_bounds__(256) gemm_f64_kernel(GemmArgs g, Epi epi) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int m = m0 + wm + i * 16 + lk + 4 * r;
-        if (m < g.M && n < g.N) epi(Cb, cbase + (int64_t)m * g.ldc + n, acc[i][j][r]);
+        if (m < g.M && n < g.N) epi(Cb, cbase + (int64_t)m * g.ldc + n, z1, acc[i][j][r]);
       }
     }
 }

@@ -83,14 +83,36 @@ hipEvent_t pooled_event() {
 // ------------------------------------------------------------- GEMM launching
 enum class Tile { T128x64, T64x128, T64x64, T32x32 };
 
-Tile pick_tile(int M, int N) {
-  if (M >= 128 && N >= 64) return Tile::T128x64;
-  if (M >= 64 && N >= 128) return Tile::T64x128;
-  if (M >= 64 && N >= 64) return Tile::T64x64;
+int64_t tiles_for(const GemmArgs& g, int bm, int bn) {
+  return (int64_t)((g.M + bm - 1) / bm) * ((g.N + bn - 1) / bn) * g.nb0 * g.nb1;
+}
+
+// Largest tile that still gives at least one work-group per compute unit; small
+// products (the exponentials of the small matrices) get small tiles and more groups.
+Tile pick_tile(const GemmArgs& g) {
+  constexpr int64_t kCUs = 256;
+  if (g.M >= 128 && g.N >= 64 && tiles_for(g, 128, 64) >= kCUs) return Tile::T128x64;
+  if (g.M >= 64 && g.N >= 128 && tiles_for(g, 64, 128) >= kCUs) return Tile::T64x128;
+  if (g.M >= 64 && g.N >= 64 && tiles_for(g, 64, 64) >= kCUs) return Tile::T64x64;
+  if (g.M >= 96 && g.N >= 48 && tiles_for(g, 32, 32) < kCUs) return Tile::T64x64;
   return Tile::T32x32;
 }
 
-template <int BM, int BN, int WM, int WN, bool KC, class Epi>
+bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
+
+// 16-byte loads need even contraction length, even leading dimensions and batch
+// strides, 16-byte aligned bases, and (for n-contiguous B) an even N.
+bool vec_ok(const GemmArgs& g, bool kcontig, const std::vector<const void*>& extra_ptrs) {
+  if (g.K % 2 || g.lda % 2 || g.ldb % 2) return false;
+  if (!kcontig && g.N % 2) return false;
+  if (g.sA0 % 2 || g.sA1 % 2 || g.sB0 % 2 || g.sB1 % 2) return false;
+  if (g.pA == nullptr && (!aligned16(g.A) || !aligned16(g.B))) return false;
+  for (const void* q : extra_ptrs)
+    if (!aligned16(q)) return false;
+  return true;
+}
+
+template <int BM, int BN, int WM, int WN, bool KC, bool VEC, class Epi>
 int launch_cfg(GemmArgs g, const Epi& epi, hipStream_t st) {
   g.tiles_m = (g.M + BM - 1) / BM;
   g.tiles_n = (g.N + BN - 1) / BN;
@@ -110,8 +132,8 @@ int launch_cfg(GemmArgs g, const Epi& epi, hipStream_t st) {
     }
   }
   (void)hipGetLastError();  // clear a stale error left by an unrelated earlier call
-  hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, WM, WN, KC, Epi>), dim3((unsigned)g.total_tiles),
-                     dim3(256), 0, st, g, epi);
+  hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, WM, WN, KC, VEC, Epi>),
+                     dim3((unsigned)g.total_tiles), dim3(256), 0, st, g, epi);
   CHECK_LAUNCH();
   if (ea && eb) {
     HIP_OK(hipEventRecord(eb, st));
@@ -121,14 +143,25 @@ int launch_cfg(GemmArgs g, const Epi& epi, hipStream_t st) {
   return PHIKS_OK;
 }
 
-template <bool KC, class Epi>
-int launch_gemm(const GemmArgs& g, const Epi& epi, hipStream_t st) {
-  switch (pick_tile(g.M, g.N)) {
-    case Tile::T128x64: return launch_cfg<128, 64, 64, 32, KC>(g, epi, st);
-    case Tile::T64x128: return launch_cfg<64, 128, 32, 64, KC>(g, epi, st);
-    case Tile::T64x64: return launch_cfg<64, 64, 32, 32, KC>(g, epi, st);
-    default: return launch_cfg<32, 32, 16, 16, KC>(g, epi, st);
+template <bool KC, bool VEC, class Epi>
+int launch_tile(const GemmArgs& g, const Epi& epi, hipStream_t st) {
+  switch (pick_tile(g)) {
+    case Tile::T128x64: return launch_cfg<128, 64, 64, 32, KC, VEC>(g, epi, st);
+    case Tile::T64x128: return launch_cfg<64, 128, 32, 64, KC, VEC>(g, epi, st);
+    case Tile::T64x64: return launch_cfg<64, 64, 32, 32, KC, VEC>(g, epi, st);
+    default: return launch_cfg<32, 32, 16, 16, KC, VEC>(g, epi, st);
   }
+}
+
+template <bool KC, class Epi>
+int launch_gemm(const GemmArgs& g, const Epi& epi, hipStream_t st,
+                const std::vector<const void*>& extra_ptrs = {}) {
+  if (g.pA != nullptr && g.nb0 != 1) {
+    set_error("pointer-array GEMM needs nb0 == 1");
+    return PHIKS_EINVAL;
+  }
+  if (vec_ok(g, KC, extra_ptrs)) return launch_tile<KC, true>(g, epi, st);
+  return launch_tile<KC, false>(g, epi, st);
 }
 
 GemmArgs empty_args() {
@@ -342,7 +375,12 @@ int batched_expm(phiks_plan_s& P, const std::vector<std::vector<double>>& Bshift
     g.pA = (const double* const*)dp;
     g.pB = (const double* const*)(dp + nb);
     g.pC = (double* const*)(dp + 2 * nb);
-    int rc = launch_gemm<false>(g, EpiStore{1.0, 0.0}, st);
+    std::vector<const void*> ptrs;
+    for (size_t i = 0; i < nb; ++i) {
+      ptrs.push_back(a[i]);
+      ptrs.push_back(b[i]);
+    }
+    int rc = launch_gemm<false>(g, EpiStore{1.0, 0.0}, st, ptrs);
     HIP_OK(hipFreeAsync(dp, st));
     return rc;
   };
