@@ -21,12 +21,13 @@
 // spread over k) and the fragment reads (16 columns x 2 rows per half-wave) hit
 // distinct banks: column c of row k is stored at c ^ swz(k).
 //
-// Launch: 1-D grid; the batch index z1 varies fastest, then the m tile, the n tile
-// and the inner batch index z0.  Work-groups of consecutive ids therefore share the
-// same input tile (node batches of one vector) or the same epilogue operands (the p
-// tensors of a squaring step); ids are remapped so that consecutive logical tiles
-// land on one XCD (work-groups are dealt round-robin over the 8 XCDs, each with its
-// own L2).
+// Launch: 1-D grid.  Mode 1 (k-contiguous B): the n tile (along L) varies fastest,
+// then the batch index z1, the m tile and z0, so that every work-group reading one
+// row block of the tensor (shared by the nodes of a batch too) runs back to back.
+// Modes > 1: z1 varies fastest (the p tensors of a squaring step share the epilogue
+// operands), then the m tile (along L), the n tile and z0.  Ids are remapped so that
+// consecutive logical tiles land on one XCD (work-groups are dealt round-robin over
+// the 8 XCDs, each with its own L2).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -114,13 +115,24 @@ __global__ void __launch_bounds__(256, 2) gemm_f64_kernel(GemmArgs g, Epi epi) {
   __shared__ __align__(16) double As[2][BK][BM];
   __shared__ __align__(16) double Bs[2][BK][BN];
 
-  const int64_t t = xcd_remap(blockIdx.x, g.total_tiles);
-  const int64_t z1 = t % g.nb1;
-  int64_t rest = t / g.nb1;
-  const int tm = (int)(rest % g.tiles_m);
-  rest /= g.tiles_m;
-  const int tn = (int)(rest % g.tiles_n);
-  const int64_t z0 = rest / g.tiles_n;
+  int64_t rest = xcd_remap(blockIdx.x, g.total_tiles);
+  int tm, tn;
+  int64_t z1, z0;
+  if constexpr (B_KCONTIG) {
+    tn = (int)(rest % g.tiles_n);
+    rest /= g.tiles_n;
+    z1 = rest % g.nb1;
+    rest /= g.nb1;
+    tm = (int)(rest % g.tiles_m);
+    z0 = rest / g.tiles_m;
+  } else {
+    z1 = rest % g.nb1;
+    rest /= g.nb1;
+    tm = (int)(rest % g.tiles_m);
+    rest /= g.tiles_m;
+    tn = (int)(rest % g.tiles_n);
+    z0 = rest / g.tiles_n;
+  }
 
   const double* __restrict__ A;
   const double* __restrict__ B;

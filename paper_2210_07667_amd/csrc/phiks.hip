@@ -265,8 +265,12 @@ double* tucker_free_buffer(int d, double* ta, double* tb) {
   return ((d - 1) % 2 == 1) ? tb : ta;
 }
 
-int launch_combine(const CombineArgs& a, hipStream_t st) {
-  if (a.N <= 0 || a.nout <= 0) return PHIKS_OK;
+int launch_combine(const CombineArgs& a_in, hipStream_t st) {
+  if (a_in.N <= 0 || a_in.nout <= 0) return PHIKS_OK;
+  CombineArgs a = a_in;
+  bool v = (a.N % 2 == 0) && (a.out_stride % 2 == 0) && ((uintptr_t)a.out % 16 == 0);
+  for (int t = 0; t < a.nin; ++t) v = v && ((uintptr_t)a.in[t] % 16 == 0);
+  a.vec = v ? 1 : 0;
   int64_t blocks = (a.N + 255) / 256;
   blocks = std::min<int64_t>(blocks, 8192);
   (void)hipGetLastError();

@@ -182,51 +182,46 @@ void householder_tridiag(std::vector<double>& M, int64_t n, bool skew,
   for (int64_t k = 0; k + 1 < n; ++k) b[k] = M[(k + 1) * n + k];
 }
 
-bool is_tridiagonal(const std::vector<double>& M, int64_t n) {
-  for (int64_t i = 0; i < n; ++i)
-    for (int64_t j = 0; j < n; ++j)
-      if ((j > i + 1 || i > j + 1) && M[i * n + j] != 0.0) return false;
-  return true;
-}
-
 }  // namespace
 
 Rect bendixson_rectangle(int64_t n, const double* B) {
-  std::vector<double> H(n * n), S(n * n);
-  for (int64_t i = 0; i < n; ++i)
-    for (int64_t j = 0; j < n; ++j) {
-      H[i * n + j] = 0.5 * (B[i * n + j] + B[j * n + i]);
-      S[i * n + j] = 0.5 * (B[i * n + j] - B[j * n + i]);
-    }
-  std::vector<double> a, b;
   Rect r{};
-  if (is_tridiagonal(H, n)) {
+  std::vector<double> a, b;
+  // banded fast path: a tridiagonal B has tridiagonal H = (B+B^T)/2 and S = (B-B^T)/2
+  bool tri = true;
+  for (int64_t i = 0; i < n && tri; ++i)
+    for (int64_t j = 0; j < n; ++j)
+      if ((j > i + 1 || i > j + 1) && B[i * n + j] != 0.0) { tri = false; break; }
+  if (tri) {
     a.resize(n);
     b.resize(n > 0 ? n - 1 : 0);
-    for (int64_t k = 0; k < n; ++k) a[k] = H[k * n + k];
-    for (int64_t k = 0; k + 1 < n; ++k) b[k] = H[(k + 1) * n + k];
+    for (int64_t k = 0; k < n; ++k) a[k] = B[k * n + k];
+    for (int64_t k = 0; k + 1 < n; ++k) b[k] = 0.5 * (B[(k + 1) * n + k] + B[k * n + k + 1]);
+    tridiag_extremes(a, b, r.re_lo, r.re_hi);
+    for (int64_t k = 0; k + 1 < n; ++k) b[k] = std::fabs(0.5 * (B[(k + 1) * n + k] - B[k * n + k + 1]));
+    for (auto& x : a) x = 0.0;
   } else {
+    std::vector<double> H(n * n), S(n * n);
+    for (int64_t i = 0; i < n; ++i)
+      for (int64_t j = 0; j < n; ++j) {
+        H[i * n + j] = 0.5 * (B[i * n + j] + B[j * n + i]);
+        S[i * n + j] = 0.5 * (B[i * n + j] - B[j * n + i]);
+      }
     householder_tridiag(H, n, false, a, b);
-  }
-  tridiag_extremes(a, b, r.re_lo, r.re_hi);
-  // S real skew: the Hermitian matrix S/i has eigenvalues +-omega; its tridiagonal
-  // form has zero diagonal and off-diagonal moduli |b_k|.
-  if (is_tridiagonal(S, n)) {
-    a.assign(n, 0.0);
-    b.resize(n > 0 ? n - 1 : 0);
-    for (int64_t k = 0; k + 1 < n; ++k) b[k] = S[(k + 1) * n + k];
-  } else {
+    tridiag_extremes(a, b, r.re_lo, r.re_hi);
+    // S real skew: the Hermitian matrix S/i has eigenvalues +-omega; its tridiagonal
+    // form has zero diagonal and off-diagonal moduli |b_k|
     householder_tridiag(S, n, true, a, b);
+    for (auto& x : b) x = std::fabs(x);
+    for (auto& x : a) x = 0.0;
   }
-  for (auto& x : b) x = std::fabs(x);
-  for (auto& x : a) x = 0.0;
   double lo, hi;
   tridiag_extremes(a, b, lo, hi);
   // the spectrum of S/i is symmetric: use the larger modulus on both sides
-  double om = std::max(std::fabs(lo), std::fabs(hi));
+  const double om = std::max(std::fabs(lo), std::fabs(hi));
   r.im_lo = -om;
   r.im_hi = om;
-  if (n == 1) { r.im_lo = r.im_hi = 0.0; }
+  if (n == 1) r.im_lo = r.im_hi = 0.0;
   return r;
 }
 
