@@ -37,6 +37,26 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def measured_traffic():
+    """HBM bytes per mu-mode launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
+    summary, or None when the kernel sources changed since those counters were taken."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", "mu_mode_gemm_adr3d_256_traffic.md")
+    try:
+        text = open(path).read()
+    except OSError:
+        return None
+    h = hashlib.sha256()
+    for f in ("gemm_f64.hpp", "phiks.hip"):
+        h.update(open(os.path.join(ROOT, "paper_2210_07667_amd", "csrc", f), "rb").read())
+    m1 = re.search(r"kernel_source_sha256: (\w+)", text)
+    m2 = re.search(r"traffic_bytes_per_launch: ([0-9.eE+-]+)", text)
+    if not m1 or not m2 or m1.group(1) != h.hexdigest():
+        return None
+    return float(m2.group(1))
+
+
 def cpu_baseline(w, plan_info):
     """Time the oracle (as it stands) for one full call of the same workload:
     its own planner plus the phi-actions with the resulting (s, q)."""
@@ -153,7 +173,7 @@ def main():
                    "plan": info},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
-                     "traffic": None,
+                     "traffic": measured_traffic(), "traffic_unit": "bytes per launch",
                      "kernel": "gemm_f64_kernel (mu-mode product)",
                      "launches": k_launch, "avg_launch_ms": k_ms / max(k_launch, 1),
                      "flops_per_launch": k_flops / max(k_launch, 1)},

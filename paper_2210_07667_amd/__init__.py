@@ -19,7 +19,8 @@ from typing import Optional, Sequence
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libphiks.so")
+# PHIKS_LIBRARY selects another build of the same library (e.g. a tuning variant)
+LIB_PATH = os.environ.get("PHIKS_LIBRARY") or os.path.join(_HERE, "libphiks.so")
 
 PHIKS_OK = 0
 PHIKS_EINVAL = -1

@@ -36,23 +36,27 @@ def _run(cmd):
     return out
 
 
-def build(verbose: bool = False) -> str:
-    os.makedirs(BUILD, exist_ok=True)
-    planner_o = os.path.join(BUILD, "planner.o")
-    phiks_o = os.path.join(BUILD, "phiks.o")
+def build(verbose: bool = False, out: str = LIB, build_dir: str = BUILD,
+          defines=()) -> str:
+    """Compile libphiks.so; `defines` are extra -D flags (tuning variants)."""
+    os.makedirs(build_dir, exist_ok=True)
+    planner_o = os.path.join(build_dir, "planner.o")
+    phiks_o = os.path.join(build_dir, "phiks.o")
+    dflags = [f"-D{d}" for d in defines]
     steps = [
         ["g++", "-O2", "-std=c++17", "-fPIC", "-Wall", f"-I{INCLUDE}", "-c",
          os.path.join(CSRC, "planner.cpp"), "-o", planner_o],
-        [HIPCC, *HIP_FLAGS, f"-I{INCLUDE}", "-c", os.path.join(CSRC, "phiks.hip"), "-o", phiks_o],
+        [HIPCC, *HIP_FLAGS, *dflags, f"-I{INCLUDE}", "-c", os.path.join(CSRC, "phiks.hip"),
+         "-o", phiks_o],
         [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", planner_o, phiks_o,
-         "-o", LIB + ".tmp"],
+         "-o", out + ".tmp"],
     ]
     for cmd in steps:
-        out = _run(cmd)
-        if verbose and out.strip():
-            print(out)
-    shutil.move(LIB + ".tmp", LIB)
-    return LIB
+        log = _run(cmd)
+        if verbose and log.strip():
+            print(log)
+    shutil.move(out + ".tmp", out)
+    return out
 
 
 if __name__ == "__main__":

@@ -99,8 +99,12 @@ __device__ __forceinline__ int swz_n(int k) { return (k & 1) << 4; }
 
 // VEC: operands are loaded 2 doubles (16 bytes) at a time; requires even K, lda, ldb,
 // batch strides and 16-byte aligned base pointers (checked by the launcher).
+#ifndef PHIKS_GEMM_MIN_WAVES
+#define PHIKS_GEMM_MIN_WAVES 3  // minimum waves per SIMD the register budget must allow
+#endif
+
 template <int BM, int BN, int WM, int WN, bool B_KCONTIG, bool VEC, class Epi>
-__global__ void __launch_bounds__(256, 2) gemm_f64_kernel(GemmArgs g, Epi epi) {
+__global__ void __launch_bounds__(256, PHIKS_GEMM_MIN_WAVES) gemm_f64_kernel(GemmArgs g, Epi epi) {
   constexpr int BK = 16;
   constexpr int WGM = BM / WM;
   constexpr int WGN = BN / WN;
@@ -254,17 +258,62 @@ __global__ void __launch_bounds__(256, 2) gemm_f64_kernel(GemmArgs g, Epi epi) {
     __syncthreads();
   }
 
+  if constexpr (std::is_same<Epi, EpiLinComb>::value) {
+    // Squaring recurrence on the whole register tile: out = a_l acc + sum_k c_lk Y_k.
+    // For each k all loads of the tile are issued before their fused multiply-adds.
+    const int l = (int)z1;
+    const double al = epi.a[l];
 #pragma unroll
-  for (int i = 0; i < FM; ++i)
+    for (int i = 0; i < FM; ++i)
 #pragma unroll
-    for (int j = 0; j < FN; ++j) {
-      const int n = n0 + wn + j * 16 + lr;
+      for (int j = 0; j < FN; ++j) acc[i][j] *= al;
+    for (int k = 0; k <= l; ++k) {
+      const double ck = epi.c[l][k];
+      const double* __restrict__ Yk = epi.Y + (int64_t)(k - l) * epi.N;
+      double y[FM][FN][4];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int m = m0 + wm + i * 16 + lk + 4 * r;
-        if (m < g.M && n < g.N) epi(Cb, cbase + (int64_t)m * g.ldc + n, z1, acc[i][j][r]);
-      }
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+          const int n = n0 + wn + j * 16 + lr;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int m = m0 + wm + i * 16 + lk + 4 * r;
+            const bool ok = m < g.M && n < g.N;
+            y[i][j][r] = ok ? Yk[cbase + (int64_t)m * g.ldc + n] : 0.0;
+          }
+        }
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) acc[i][j][r] += ck * y[i][j][r];
     }
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j) {
+        const int n = n0 + wn + j * 16 + lr;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int m = m0 + wm + i * 16 + lk + 4 * r;
+          if (m < g.M && n < g.N) Cb[cbase + (int64_t)m * g.ldc + n] = acc[i][j][r];
+        }
+      }
+  } else {
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j) {
+        const int n = n0 + wn + j * 16 + lr;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int m = m0 + wm + i * 16 + lk + 4 * r;
+          if (m < g.M && n < g.N) epi(Cb, cbase + (int64_t)m * g.ldc + n, z1, acc[i][j][r]);
+        }
+      }
+  }
 }
 
 }  // namespace phiks

@@ -81,7 +81,7 @@ hipEvent_t pooled_event() {
 }
 
 // ------------------------------------------------------------- GEMM launching
-enum class Tile { T128x64, T64x128, T64x64, T32x32 };
+enum class Tile { T128x128, T128x64, T64x128, T64x64, T32x32 };
 
 int64_t tiles_for(const GemmArgs& g, int bm, int bn) {
   return (int64_t)((g.M + bm - 1) / bm) * ((g.N + bn - 1) / bn) * g.nb0 * g.nb1;
@@ -89,8 +89,13 @@ int64_t tiles_for(const GemmArgs& g, int bm, int bn) {
 
 // Largest tile that still gives at least one work-group per compute unit; small
 // products (the exponentials of the small matrices) get small tiles and more groups.
+#ifndef PHIKS_BIG_TILE
+#define PHIKS_BIG_TILE 0  // 0: 128 x 64, 1: 128 x 128
+#endif
 Tile pick_tile(const GemmArgs& g) {
   constexpr int64_t kCUs = 256;
+  if (PHIKS_BIG_TILE == 1 && g.M >= 128 && g.N >= 128 && tiles_for(g, 128, 128) >= kCUs)
+    return Tile::T128x128;
   if (g.M >= 128 && g.N >= 64 && tiles_for(g, 128, 64) >= kCUs) return Tile::T128x64;
   if (g.M >= 64 && g.N >= 128 && tiles_for(g, 64, 128) >= kCUs) return Tile::T64x128;
   if (g.M >= 64 && g.N >= 64 && tiles_for(g, 64, 64) >= kCUs) return Tile::T64x64;
@@ -146,6 +151,9 @@ int launch_cfg(GemmArgs g, const Epi& epi, hipStream_t st) {
 template <bool KC, bool VEC, class Epi>
 int launch_tile(const GemmArgs& g, const Epi& epi, hipStream_t st) {
   switch (pick_tile(g)) {
+#if PHIKS_BIG_TILE == 1
+    case Tile::T128x128: return launch_cfg<128, 128, 64, 64, KC, VEC>(g, epi, st);
+#endif
     case Tile::T128x64: return launch_cfg<128, 64, 64, 32, KC, VEC>(g, epi, st);
     case Tile::T64x128: return launch_cfg<64, 128, 32, 64, KC, VEC>(g, epi, st);
     case Tile::T64x64: return launch_cfg<64, 64, 32, 32, KC, VEC>(g, epi, st);
