@@ -153,7 +153,13 @@ int phiks_workspace_size(phiks_plan_t plan, size_t* bytes);
 int phiks_plan_info(phiks_plan_t plan, int* s, int* q, int* tucker_paper,
                     int* tucker_exec);
 
-/* Release a plan and its device memory (synchronises the plan's device). NULL is a no-op. */
+/*
+ * Release a plan.  Stream-ordered: its device memory is freed (hipFreeAsync) and its
+ * host staging buffers are released after all work already enqueued on the stream the
+ * plan was made with; the call itself does not wait.  Work using the plan that was
+ * enqueued on other streams must be ordered before that point by the caller (e.g. an
+ * event), and the plan's stream must still exist.  NULL is a no-op.
+ */
 void phiks_plan_destroy(phiks_plan_t plan);
 
 /*

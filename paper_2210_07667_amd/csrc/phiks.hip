@@ -191,6 +191,7 @@ struct phiks_plan_s {
   int s = 0, q = 0, t_paper = 0, t_exec = 0;
   double theta[kQMax] = {0}, w[kQMax] = {0};
   int device = 0;
+  hipStream_t stream = nullptr;         // stream the plan was built on (and is released on)
   void* dmem = nullptr;                 // all plan-lifetime device matrices
   double* Lnode[PHIKS_MAX_D] = {nullptr};  // (q-1) node matrices per mode, stride n^2
   double* E[PHIKS_MAX_D] = {nullptr};      // (s+1) matrices per mode: exp(B/2^j), stride n^2
@@ -676,8 +677,10 @@ int phiks_plan(int d, const int64_t* n, const double* const* A, double tau, int 
     offE[mu] = total;
     total += (size_t)(pc.s + 1) * sq(n[mu]);
   }
-  if (hipMalloc(&P->dmem, std::max<size_t>(total, 1) * sizeof(double)) != hipSuccess) {
-    set_error("hipMalloc of plan matrices failed");
+  P->stream = st;
+  if (hipMallocAsync(&P->dmem, std::max<size_t>(total, 1) * sizeof(double), st) != hipSuccess) {
+    P->dmem = nullptr;
+    set_error("hipMallocAsync of plan matrices failed");
     return fail(PHIKS_ENOMEM);
   }
   double* base = (double*)P->dmem;
@@ -746,16 +749,23 @@ int phiks_plan(int d, const int64_t* n, const double* const* A, double tau, int 
   return PHIKS_OK;
 }
 
+namespace {
+void release_host_keep(void* p) { delete static_cast<std::vector<std::vector<char>>*>(p); }
+}  // namespace
+
 void phiks_plan_destroy(phiks_plan_t plan) {
   if (!plan) return;
-  if (plan->dmem) {
-    int cur = 0;
-    (void)hipGetDevice(&cur);
-    (void)hipSetDevice(plan->device);
-    (void)hipDeviceSynchronize();
-    (void)hipFree(plan->dmem);
-    (void)hipSetDevice(cur);
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  (void)hipSetDevice(plan->device);
+  if (plan->dmem) (void)hipFreeAsync(plan->dmem, plan->stream);
+  // host sources of the plan's asynchronous copies are released once the stream gets here
+  auto* keep = new std::vector<std::vector<char>>(std::move(plan->host_keep));
+  if (hipLaunchHostFunc(plan->stream, release_host_keep, keep) != hipSuccess) {
+    (void)hipStreamSynchronize(plan->stream);
+    release_host_keep(keep);
   }
+  (void)hipSetDevice(cur);
   delete plan;
 }
 
