@@ -31,6 +31,7 @@ sys.path.insert(0, ROOT)
 METRIC = ("φ-action dofs/s and μ-mode GFLOP/s (% MFMA peak), FP64 vs FP32-MFMA; "
           "p99 lat")
 FP64_PEAK_TFLOPS = 78.6   # MI355X dense FP64 (matrix and vector)
+FP32_PEAK_TFLOPS = 157.3  # MI355X dense FP32 (matrix)
 
 
 def log(msg):
@@ -153,6 +154,28 @@ def main():
     apply_ms = (time.perf_counter() - a0) * 1e3 / reps
     pl.close()
 
+    # the same call with the mu-mode products in FP32 MFMA (everything else FP64)
+    ref64 = out.to_numpy()
+    pl32 = ph.phiks_plan(w.A, w.tau, w.p, w.n_scales, w.tol, w.task, stream=st,
+                         precision=ph.PHIKS_FP32)
+    ph.phiks_apply(pl32, v.ptr, out.ptr, ws.ptr, ws.nbytes, st)
+    ph.synchronize()
+    ph.phiks_kernel_timing_read()
+    ph.phiks_kernel_timing(True)
+    b0 = time.perf_counter()
+    for _ in range(reps):
+        ph.phiks_apply(pl32, v.ptr, out.ptr, ws.ptr, ws.nbytes, st)
+    ph.synchronize()
+    apply32_ms = (time.perf_counter() - b0) * 1e3 / reps
+    ph.phiks_kernel_timing(False)
+    k32_ms, k32_launch, k32_flops = ph.phiks_kernel_timing_read()
+    pl32.close()
+    got32 = out.to_numpy()
+    N = w.N
+    err32 = max(float(np.abs(got32[l * N:(l + 1) * N] - ref64[l * N:(l + 1) * N]).max()
+                      / np.abs(ref64[l * N:(l + 1) * N]).max()) for l in range(w.p + 1))
+    ach32 = (k32_flops / (k32_ms * 1e-3)) / 1e12 if k32_ms > 0 else 0.0
+
     achieved = (k_flops / (k_ms * 1e-3)) / 1e12 if k_ms > 0 else 0.0
     n_mu = w.n[0]
     line = {
@@ -180,6 +203,10 @@ def main():
         "apply_only_ms": apply_ms,
         "apply_only_dofs_per_s": w.N / (apply_ms * 1e-3),
         "mu_mode_gflops_per_s": achieved * 1e3,
+        "fp32_mfma": {"apply_only_ms": apply32_ms, "apply_only_dofs_per_s": w.N / (apply32_ms * 1e-3),
+                      "mu_mode_tflops": ach32, "peak_tflops": FP32_PEAK_TFLOPS,
+                      "frac": ach32 / FP32_PEAK_TFLOPS,
+                      "max_rel_err_vs_fp64": err32},
     }
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle (one full call)")

@@ -56,7 +56,11 @@ enum {
 };
 
 enum { PHIKS_SAME_VECTOR = 0, PHIKS_LINCOMB = 1 };
-enum { PHIKS_FP64 = 0 };
+/* Arithmetic of the mu-mode products.  PHIKS_FP32: FP32 MFMA products of FP32 copies
+ * of the small exponentials, FP32 intermediates between the modes of a Tucker
+ * operator; the small exponentials themselves, the quadrature sums, the squaring
+ * recurrence and every output stay FP64. */
+enum { PHIKS_FP64 = 0, PHIKS_FP32 = 1 };
 
 #define PHIKS_MAX_D 8      /* largest number of modes d */
 #define PHIKS_MAX_P 8      /* largest phi index p */
@@ -89,7 +93,7 @@ enum { PHIKS_FP64 = 0 };
  *   task      PHIKS_SAME_VECTOR or PHIKS_LINCOMB
  *   vnorms    host array of 2-norms (same vector: 1 value ||v||; combination: p+1
  *             values ||v_0||..||v_p||), or NULL for all norms = 1
- *   precision PHIKS_FP64
+ *   precision PHIKS_FP64 or PHIKS_FP32 (see above)
  *   hip_stream stream for the device work (hipStream_t), may be NULL
  *   out       receives the plan; owned by the caller, release with
  *             phiks_plan_destroy.  Its device buffers live on the current device.

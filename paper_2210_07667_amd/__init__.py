@@ -32,6 +32,7 @@ PHIKS_ENONFINITE = -6
 PHIKS_SAME_VECTOR = 0
 PHIKS_LINCOMB = 1
 PHIKS_FP64 = 0
+PHIKS_FP32 = 1
 
 # every exported entry point of include/phiks.h
 SYMBOLS = ("phiks_plan", "phiks_apply", "phiks_combine", "phiks_workspace_size",

@@ -1,0 +1,268 @@
+// FP32 MFMA variant of the mu-mode product (see gemm_f64.hpp for the three views and
+// the tile order).  Operands are converted to FP32 on their way into LDS (the tensor
+// may arrive in FP64 -- the first mode of a Tucker operator reads the FP64 vectors of
+// the phi recurrence -- or in FP32, the intermediate modes), the products accumulate
+// in FP32 on v_mfma_f32_16x16x4_f32, and the last mode writes FP64 through the same
+// epilogues as the FP64 kernel (the squaring recurrence stays in FP64).
+//
+// MFMA v_mfma_f32_16x16x4_f32, per lane l:
+//   A operand  A[m0 + (l & 15)][k0 + (l >> 4)]
+//   B operand  B[k0 + (l >> 4)][n0 + (l & 15)]
+//   C result   c[r] = C[m0 + 4 (l >> 4) + r][n0 + (l & 15)]      (checked on the GPU)
+//
+// LDS: k-major tiles of floats, 32 k per chunk.  Column c of row k is stored at
+// c ^ swz(k) so that a wave's fragment read (16 columns x 4 rows) and its
+// transposing stores (8 rows x 8 groups of 4 k) both touch 64 distinct banks.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <type_traits>
+
+#include "gemm_f64.hpp"
+
+namespace phiks {
+
+typedef float flt4 __attribute__((ext_vector_type(4)));
+
+// C = alpha * acc (+ beta * C) for an output of element type T.
+template <class T>
+struct EpiStoreT {
+  double alpha, beta;
+  __device__ __forceinline__ void operator()(T* C, int64_t e, int64_t, double acc) const {
+    C[e] = (T)((beta == 0.0) ? alpha * acc : alpha * acc + beta * (double)C[e]);
+  }
+};
+
+template <int BM> __device__ __forceinline__ int swz32_t(int k) {
+  return ((16 * (k & 3)) ^ (8 * ((k >> 2) & 7))) & (BM - 1);
+}
+template <int BN> __device__ __forceinline__ int swz32_n(int k) { return (16 * (k & 3)) & (BN - 1); }
+
+template <class T> struct Vec4;
+template <> struct Vec4<float> {
+  __device__ __forceinline__ static flt4 load(const float* p) { return *reinterpret_cast<const flt4*>(p); }
+};
+template <> struct Vec4<double> {
+  __device__ __forceinline__ static flt4 load(const double* p) {
+    const dbl2 a = *reinterpret_cast<const dbl2*>(p);
+    const dbl2 b = *reinterpret_cast<const dbl2*>(p + 2);
+    return flt4{(float)a[0], (float)a[1], (float)b[0], (float)b[1]};
+  }
+};
+
+// TA: element type of A in memory; B is FP32 (a small matrix or an FP32 intermediate)
+// unless B_KCONTIG is false and it is the tensor (then it is an FP32 intermediate).
+// TC: element type of C.  VEC: 4 elements per load (K, lda, ldb, strides multiples of 4,
+// 16-byte aligned bases, and N a multiple of 4 for an n-contiguous B).
+template <int BM, int BN, int WM, int WN, bool B_KCONTIG, bool VEC, class TA, class TC, class Epi>
+__global__ void __launch_bounds__(256, 3) gemm_f32_kernel(GemmArgs g, Epi epi) {
+  constexpr int BK = 32;
+  constexpr int WGM = BM / WM;
+  constexpr int WGN = BN / WN;
+  static_assert(WGM * WGN == 4, "4 waves per work-group");
+  constexpr int FM = WM / 16;
+  constexpr int FN = WN / 16;
+  constexpr int VW = VEC ? 4 : 1;
+  constexpr int LA = BM * BK / (256 * VW);
+  constexpr int LB = BN * BK / (256 * VW);
+  typedef typename std::conditional<VEC, flt4, float>::type vec_t;
+
+  __shared__ __align__(16) float As[2][BK][BM];
+  __shared__ __align__(16) float Bs[2][BK][BN];
+
+  int64_t rest = xcd_remap(blockIdx.x, g.total_tiles);
+  int tm, tn;
+  int64_t z1, z0;
+  if constexpr (B_KCONTIG) {
+    tn = (int)(rest % g.tiles_n);
+    rest /= g.tiles_n;
+    z1 = rest % g.nb1;
+    rest /= g.nb1;
+    tm = (int)(rest % g.tiles_m);
+    z0 = rest / g.tiles_m;
+  } else {
+    z1 = rest % g.nb1;
+    rest /= g.nb1;
+    tm = (int)(rest % g.tiles_m);
+    rest /= g.tiles_m;
+    tn = (int)(rest % g.tiles_n);
+    z0 = rest / g.tiles_n;
+  }
+  const TA* __restrict__ A = reinterpret_cast<const TA*>(g.A) + z0 * g.sA0 + z1 * g.sA1;
+  const float* __restrict__ B = reinterpret_cast<const float*>(g.B) + z0 * g.sB0 + z1 * g.sB1;
+  TC* Cb = reinterpret_cast<TC*>(g.C);
+  const int64_t cbase = z0 * g.sC0 + z1 * g.sC1;
+
+  const int m0 = tm * BM;
+  const int n0 = tn * BN;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = (wave / WGN) * WM;
+  const int wn = (wave % WGN) * WN;
+
+  vec_t ra[LA], rb[LB];
+  auto load_chunk = [&](int k0) {
+#pragma unroll
+    for (int i = 0; i < LA; ++i) {
+      const int e = tid + i * 256;
+      const int m = e / (BK / VW), k = VW * (e % (BK / VW));
+      const int gm = m0 + m, gk = k0 + k;
+      const bool ok = (gm < g.M) && (gk < g.K);
+      const int64_t off = ok ? (int64_t)gm * g.lda + gk : 0;
+      if constexpr (VEC) {
+        const flt4 x = Vec4<TA>::load(A + off);
+        ra[i] = ok ? x : flt4{0.f, 0.f, 0.f, 0.f};
+      } else {
+        const float x = (float)A[off];
+        ra[i] = ok ? x : 0.f;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < LB; ++i) {
+      const int e = tid + i * 256;
+      int n, k;
+      if constexpr (B_KCONTIG) { n = e / (BK / VW); k = VW * (e % (BK / VW)); }
+      else { k = e / (BN / VW); n = VW * (e % (BN / VW)); }
+      const int gn = n0 + n, gk = k0 + k;
+      const bool ok = (gn < g.N) && (gk < g.K);
+      const int64_t off = ok ? (B_KCONTIG ? (int64_t)gn * g.ldb + gk : (int64_t)gk * g.ldb + gn) : 0;
+      if constexpr (VEC) {
+        const flt4 x = Vec4<float>::load(B + off);
+        rb[i] = ok ? x : flt4{0.f, 0.f, 0.f, 0.f};
+      } else {
+        const float x = B[off];
+        rb[i] = ok ? x : 0.f;
+      }
+    }
+  };
+  auto store_chunk = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < LA; ++i) {
+      const int e = tid + i * 256;
+      const int m = e / (BK / VW), k = VW * (e % (BK / VW));
+      if constexpr (VEC) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) As[buf][k + t][m ^ swz32_t<BM>(k + t)] = ra[i][t];
+      } else {
+        As[buf][k][m ^ swz32_t<BM>(k)] = ra[i];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < LB; ++i) {
+      const int e = tid + i * 256;
+      if constexpr (B_KCONTIG) {
+        const int n = e / (BK / VW), k = VW * (e % (BK / VW));
+        if constexpr (VEC) {
+#pragma unroll
+          for (int t = 0; t < 4; ++t) Bs[buf][k + t][n ^ swz32_t<BN>(k + t)] = rb[i][t];
+        } else {
+          Bs[buf][k][n ^ swz32_t<BN>(k)] = rb[i];
+        }
+      } else {
+        const int k = e / (BN / VW), n = VW * (e % (BN / VW));
+        if constexpr (VEC) *reinterpret_cast<flt4*>(&Bs[buf][k][n ^ swz32_n<BN>(k)]) = rb[i];
+        else Bs[buf][k][n ^ swz32_n<BN>(k)] = rb[i];
+      }
+    }
+  };
+
+  flt4 acc[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) acc[i][j] = flt4{0.f, 0.f, 0.f, 0.f};
+
+  const int nchunks = (g.K + BK - 1) / BK;
+  load_chunk(0);
+  store_chunk(0);
+  __syncthreads();
+  const int lr = lane & 15;
+  const int lk = lane >> 4;
+  for (int c = 0; c < nchunks; ++c) {
+    const int buf = c & 1;
+    if (c + 1 < nchunks) load_chunk((c + 1) * BK);
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 4) {
+      const int k = kk + lk;
+      float fa[FM], fb[FN];
+#pragma unroll
+      for (int i = 0; i < FM; ++i) fa[i] = As[buf][k][(wm + i * 16 + lr) ^ swz32_t<BM>(k)];
+#pragma unroll
+      for (int j = 0; j < FN; ++j) {
+        if constexpr (B_KCONTIG) fb[j] = Bs[buf][k][(wn + j * 16 + lr) ^ swz32_t<BN>(k)];
+        else fb[j] = Bs[buf][k][(wn + j * 16 + lr) ^ swz32_n<BN>(k)];
+      }
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[i], fb[j], acc[i][j], 0, 0, 0);
+    }
+    if (c + 1 < nchunks) store_chunk(buf ^ 1);
+    __syncthreads();
+  }
+
+  if constexpr (std::is_same<Epi, EpiLinComb>::value) {
+    static_assert(std::is_same<TC, double>::value, "the squaring epilogue writes FP64");
+    const int l = (int)z1;
+    const double al = epi.a[l];
+    double o[FM][FN][4];
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) o[i][j][r] = al * (double)acc[i][j][r];
+    for (int k = 0; k <= l; ++k) {
+      const double ck = epi.c[l][k];
+      const double* __restrict__ Yk = epi.Y + (int64_t)(k - l) * epi.N;
+      double y[FM][FN][4];
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+          const int n = n0 + wn + j * 16 + lr;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int m = m0 + wm + i * 16 + 4 * lk + r;
+            const bool ok = m < g.M && n < g.N;
+            y[i][j][r] = ok ? Yk[cbase + (int64_t)m * g.ldc + n] : 0.0;
+          }
+        }
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) o[i][j][r] += ck * y[i][j][r];
+    }
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j) {
+        const int n = n0 + wn + j * 16 + lr;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int m = m0 + wm + i * 16 + 4 * lk + r;
+          if (m < g.M && n < g.N) Cb[cbase + (int64_t)m * g.ldc + n] = o[i][j][r];
+        }
+      }
+  } else {
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j) {
+        const int n = n0 + wn + j * 16 + lr;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int m = m0 + wm + i * 16 + 4 * lk + r;
+          if (m < g.M && n < g.N) epi(Cb, cbase + (int64_t)m * g.ldc + n, z1, (double)acc[i][j][r]);
+        }
+      }
+  }
+}
+
+}  // namespace phiks

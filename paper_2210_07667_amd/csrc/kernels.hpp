@@ -63,6 +63,13 @@ __global__ void __launch_bounds__(256) combine_kernel(CombineArgs a) {
   }
 }
 
+// dst = (float)src, n entries.
+__global__ void __launch_bounds__(256) to_f32_kernel(const double* src, float* dst, int64_t n) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x)
+    dst[e] = (float)src[e];
+}
+
 // ------------------------------------------------------------ Pade exponential
 // Job j computes the [m/m] Pade approximant of X = gamma * Bs (Bs = B - sigma I):
 //   S_U = sum_k cu[k] Bs^(2k),  V = sum_k cv[k] Bs^(2k)   (Bs^0 = I)

@@ -20,6 +20,7 @@
 #include <string>
 #include <vector>
 
+#include "gemm_f32.hpp"
 #include "gemm_f64.hpp"
 #include "kernels.hpp"
 #include "phiks.h"
@@ -172,6 +173,62 @@ int launch_gemm(const GemmArgs& g, const Epi& epi, hipStream_t st,
   return launch_tile<KC, false>(g, epi, st);
 }
 
+// ------------------------------------------------- FP32 MFMA mu-mode launches
+bool vec4_ok(const GemmArgs& g, bool kcontig) {
+  if (g.K % 4 || g.lda % 4 || g.ldb % 4) return false;
+  if (!kcontig && g.N % 4) return false;
+  if (g.sA0 % 4 || g.sA1 % 4 || g.sB0 % 4 || g.sB1 % 4) return false;
+  return aligned16(g.A) && aligned16(g.B);
+}
+
+template <int BM, int BN, int WM, int WN, bool KC, bool VEC, class TA, class TC, class Epi>
+int launch_cfg32(GemmArgs g, const Epi& epi, hipStream_t st) {
+  g.tiles_m = (g.M + BM - 1) / BM;
+  g.tiles_n = (g.N + BN - 1) / BN;
+  g.total_tiles = (int64_t)g.tiles_m * g.tiles_n * g.nb0 * g.nb1;
+  if (g.total_tiles <= 0) return PHIKS_OK;
+  if (g.total_tiles > 0x7fffffffLL) {
+    set_error("GEMM grid too large");
+    return PHIKS_EINVAL;
+  }
+  hipEvent_t ea = nullptr, eb = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_timing_mu);
+    if (g_timing) {
+      ea = pooled_event();
+      eb = pooled_event();
+      if (ea && eb) HIP_OK(hipEventRecord(ea, st));
+    }
+  }
+  (void)hipGetLastError();
+  hipLaunchKernelGGL((gemm_f32_kernel<BM, BN, WM, WN, KC, VEC, TA, TC, Epi>),
+                     dim3((unsigned)g.total_tiles), dim3(256), 0, st, g, epi);
+  CHECK_LAUNCH();
+  if (ea && eb) {
+    HIP_OK(hipEventRecord(eb, st));
+    std::lock_guard<std::mutex> lk(g_timing_mu);
+    g_timed.push_back({ea, eb, 2.0 * g.M * (double)g.N * g.K * g.nb0 * (double)g.nb1});
+  }
+  return PHIKS_OK;
+}
+
+template <bool KC, bool VEC, class TA, class TC, class Epi>
+int launch_tile32(const GemmArgs& g, const Epi& epi, hipStream_t st) {
+  switch (pick_tile(g)) {
+    case Tile::T128x128:
+    case Tile::T128x64: return launch_cfg32<128, 64, 64, 32, KC, VEC, TA, TC>(g, epi, st);
+    case Tile::T64x128: return launch_cfg32<64, 128, 32, 64, KC, VEC, TA, TC>(g, epi, st);
+    case Tile::T64x64: return launch_cfg32<64, 64, 32, 32, KC, VEC, TA, TC>(g, epi, st);
+    default: return launch_cfg32<32, 32, 16, 16, KC, VEC, TA, TC>(g, epi, st);
+  }
+}
+
+template <bool KC, class TA, class TC, class Epi>
+int launch_gemm32(const GemmArgs& g, const Epi& epi, hipStream_t st) {
+  if (vec4_ok(g, KC)) return launch_tile32<KC, true, TA, TC>(g, epi, st);
+  return launch_tile32<KC, false, TA, TC>(g, epi, st);
+}
+
 GemmArgs empty_args() {
   GemmArgs g;
   std::memset(&g, 0, sizeof(g));
@@ -195,6 +252,8 @@ struct phiks_plan_s {
   void* dmem = nullptr;                 // all plan-lifetime device matrices
   double* Lnode[PHIKS_MAX_D] = {nullptr};  // (q-1) node matrices per mode, stride n^2
   double* E[PHIKS_MAX_D] = {nullptr};      // (s+1) matrices per mode: exp(B/2^j), stride n^2
+  float* Lnode32[PHIKS_MAX_D] = {nullptr};  // FP32 copies (precision PHIKS_FP32)
+  float* E32[PHIKS_MAX_D] = {nullptr};
   std::vector<std::vector<char>> host_keep;  // host sources of async copies
 };
 
@@ -266,6 +325,95 @@ int tucker(const phiks_plan_s& P, const double* in, int64_t in_stride,
     cur_stride = N;
   }
   return PHIKS_OK;
+}
+
+// FP32 MFMA Tucker operator: the chain input (FP64) is converted in the first mode,
+// intermediate modes are FP32 (ta/tb hold floats), the last mode writes FP64 through
+// the same epilogue as the FP64 chain.  L[mu] are FP32 copies of the matrices.
+template <class Epi>
+int tucker32(const phiks_plan_s& P, const double* in, int64_t in_stride,
+             float* const* L, const int64_t* l_stride, int nbatch, double* out,
+             double* ta, double* tb, const Epi& epi, hipStream_t st) {
+  const int d = P.d;
+  const int64_t N = P.N;
+  const void* cur = in;
+  int64_t cur_stride = in_stride;
+  for (int mu = 1; mu <= d; ++mu) {
+    const int64_t nm = P.n[mu - 1];
+    int64_t nlo = 1, nhi = 1;
+    for (int k = 0; k < mu - 1; ++k) nlo *= P.n[k];
+    for (int k = mu; k < d; ++k) nhi *= P.n[k];
+    const bool last = (mu == d);
+    void* dst = last ? (void*)out : (void*)((mu % 2 == 1) ? ta : tb);
+    GemmArgs g = empty_args();
+    g.nb1 = nbatch;
+    if (mu == 1) {
+      g.M = (int)nhi;
+      g.N = (int)nm;
+      g.K = (int)nm;
+      g.A = reinterpret_cast<const double*>(cur);
+      g.lda = nm;
+      g.B = reinterpret_cast<const double*>(L[0]);
+      g.ldb = nm;
+      g.C = reinterpret_cast<double*>(dst);
+      g.ldc = nm;
+      g.sA1 = cur_stride;
+      g.sB1 = l_stride[0];
+      g.sC1 = N;
+      if (last) RET_IF((launch_gemm32<true, double, double>(g, epi, st)));
+      else RET_IF((launch_gemm32<true, double, float>(g, EpiStoreT<float>{1.0, 0.0}, st)));
+    } else {
+      g.M = (int)nm;
+      g.N = (int)nlo;
+      g.K = (int)nm;
+      g.A = reinterpret_cast<const double*>(L[mu - 1]);
+      g.lda = nm;
+      g.B = reinterpret_cast<const double*>(cur);
+      g.ldb = nlo;
+      g.C = reinterpret_cast<double*>(dst);
+      g.ldc = nlo;
+      g.nb0 = (int)nhi;
+      g.sB0 = nm * nlo;
+      g.sC0 = nm * nlo;
+      g.sA1 = l_stride[mu - 1];
+      g.sB1 = cur_stride;
+      g.sC1 = N;
+      if (last) RET_IF((launch_gemm32<false, float, double>(g, epi, st)));
+      else RET_IF((launch_gemm32<false, float, float>(g, EpiStoreT<float>{1.0, 0.0}, st)));
+    }
+    cur = dst;
+    cur_stride = N;
+  }
+  return PHIKS_OK;
+}
+
+// Which small matrices a Tucker operator of the phi recurrence uses.
+enum class MatSel { AllNodes, Node, Level };
+
+// Tucker operator of the plan in its precision: matrices of every node theta_i < 1
+// batched (AllNodes), of one node (Node, idx), or exp(B/2^idx) (Level, idx).
+template <class Epi>
+int plan_tucker(const phiks_plan_s& P, MatSel sel, int idx, const double* in,
+                int64_t in_stride, int nbatch, double* out, double* ta, double* tb,
+                const Epi& epi, hipStream_t st) {
+  int64_t stride[PHIKS_MAX_D];
+  for (int mu = 0; mu < P.d; ++mu) stride[mu] = (sel == MatSel::AllNodes) ? P.n[mu] * P.n[mu] : 0;
+  if (P.precision == PHIKS_FP32) {
+    float* L[PHIKS_MAX_D];
+    for (int mu = 0; mu < P.d; ++mu) {
+      const int64_t nn = P.n[mu] * P.n[mu];
+      L[mu] = (sel == MatSel::Level) ? P.E32[mu] + (size_t)idx * nn
+                                     : P.Lnode32[mu] + (size_t)(sel == MatSel::Node ? idx : 0) * nn;
+    }
+    return tucker32(P, in, in_stride, L, stride, nbatch, out, ta, tb, epi, st);
+  }
+  double* L[PHIKS_MAX_D];
+  for (int mu = 0; mu < P.d; ++mu) {
+    const int64_t nn = P.n[mu] * P.n[mu];
+    L[mu] = (sel == MatSel::Level) ? P.E[mu] + (size_t)idx * nn
+                                   : P.Lnode[mu] + (size_t)(sel == MatSel::Node ? idx : 0) * nn;
+  }
+  return tucker(P, in, in_stride, L, stride, nbatch, out, ta, tb, epi, st);
 }
 
 // the buffer (ta or tb) that the last mode does not read
@@ -639,7 +787,7 @@ int phiks_plan(int d, const int64_t* n, const double* const* A, double tau, int 
   *out = nullptr;
   int rc = validate_problem(d, n, A, tau, p, n_scales, tol, task, vnorms);
   if (rc != PHIKS_OK) return rc;
-  if (precision != PHIKS_FP64) return PHIKS_EINVAL;
+  if (precision != PHIKS_FP64 && precision != PHIKS_FP32) return PHIKS_EINVAL;
   PlanChoice pc;
   rc = host_plan(d, n, A, tau, p, n_scales, tol, task, vnorms, pc);
   if (rc != PHIKS_OK) return rc;
@@ -670,12 +818,21 @@ int phiks_plan(int d, const int64_t* n, const double* const* A, double tau, int 
 
   // plan-lifetime device memory: node matrices and exp(B/2^j), j = 0..s
   size_t total = 0;
-  size_t offL[PHIKS_MAX_D], offE[PHIKS_MAX_D];
+  size_t offL[PHIKS_MAX_D], offE[PHIKS_MAX_D], offL32[PHIKS_MAX_D], offE32[PHIKS_MAX_D];
   for (int mu = 0; mu < d; ++mu) {
     offL[mu] = total;
     total += (size_t)nodes * sq(n[mu]);
     offE[mu] = total;
     total += (size_t)(pc.s + 1) * sq(n[mu]);
+  }
+  const size_t total64 = total;  // in doubles; FP32 copies follow (counted in doubles, rounded up)
+  if (precision == PHIKS_FP32) {
+    for (int mu = 0; mu < d; ++mu) {
+      offL32[mu] = total * 2;  // float index
+      total += ((size_t)nodes * sq(n[mu]) + 3) / 2 + 1;
+      offE32[mu] = total * 2;
+      total += ((size_t)(pc.s + 1) * sq(n[mu]) + 3) / 2 + 1;
+    }
   }
   P->stream = st;
   if (hipMallocAsync(&P->dmem, std::max<size_t>(total, 1) * sizeof(double), st) != hipSuccess) {
@@ -687,7 +844,12 @@ int phiks_plan(int d, const int64_t* n, const double* const* A, double tau, int 
   for (int mu = 0; mu < d; ++mu) {
     P->Lnode[mu] = base + offL[mu];
     P->E[mu] = base + offE[mu];
+    if (precision == PHIKS_FP32) {
+      P->Lnode32[mu] = (float*)P->dmem + offL32[mu];
+      P->E32[mu] = (float*)P->dmem + offE32[mu];
+    }
   }
+  (void)total64;
   // shifted operators B_mu - sigma_mu I, sigma_mu = tr(B_mu)/n_mu (the shift remark
   // of Section 3.1), and their 1-norms for the Pade degree choice
   std::vector<std::vector<double>> Bs(d);
@@ -743,6 +905,24 @@ int phiks_plan(int d, const int64_t* n, const double* const* A, double tau, int 
       g.C = P->E[mu] + (size_t)(j - 1) * sq(m);
       rc = launch_gemm<false>(g, EpiStore{1.0, 0.0}, st);
       if (rc != PHIKS_OK) return fail(rc);
+    }
+  }
+  if (precision == PHIKS_FP32) {
+    // FP32 copies of every node matrix and of exp(B/2^j): the mixed-precision path
+    // multiplies by these; everything else stays FP64
+    for (int mu = 0; mu < d; ++mu) {
+      const int64_t ln = (int64_t)nodes * sq(n[mu]);
+      const int64_t le = (int64_t)(pc.s + 1) * sq(n[mu]);
+      (void)hipGetLastError();
+      if (ln > 0)
+        hipLaunchKernelGGL(to_f32_kernel, dim3((unsigned)std::min<int64_t>((ln + 255) / 256, 4096)),
+                           dim3(256), 0, st, (const double*)P->Lnode[mu], P->Lnode32[mu], ln);
+      hipLaunchKernelGGL(to_f32_kernel, dim3((unsigned)std::min<int64_t>((le + 255) / 256, 4096)),
+                         dim3(256), 0, st, (const double*)P->E[mu], P->E32[mu], le);
+      if (hipGetLastError() != hipSuccess) {
+        set_error("conversion kernel launch failed");
+        return fail(PHIKS_EDEVICE);
+      }
     }
   }
   *out = P;
@@ -901,16 +1081,12 @@ int phiks_apply(phiks_plan_t plan, const double* v, double* out, void* ws, size_
   double* pa = tb + tcount * N;
   double* pb = pa + (int64_t)p * N;
   auto slot = [&](int level, int ell) { return out + ((int64_t)level * (p + 1) + ell) * N; };
-  double* Lsh[PHIKS_MAX_D];
-  int64_t zero_stride[PHIKS_MAX_D] = {0};
-  int64_t node_stride[PHIKS_MAX_D];
-  for (int mu = 0; mu < d; ++mu) node_stride[mu] = sq(P.n[mu]);
 
   if (p > 0) {
     // eq. integrandsimul: one Tucker per node theta_i < 1, all nodes in one batch
     const int nodes = q - 1;
     double* wbuf = tucker_free_buffer(d, ta, tb);
-    RET_IF(tucker(P, v, 0, P.Lnode, node_stride, nodes, wbuf, ta, tb, EpiStore{1.0, 0.0}, st));
+    RET_IF(plan_tucker(P, MatSel::AllNodes, 0, v, 0, nodes, wbuf, ta, tb, EpiStore{1.0, 0.0}, st));
     double* cur = (s < ns) ? slot(s, 1) : pa;
     CombineArgs ca;
     std::memset(&ca, 0, sizeof(ca));
@@ -939,15 +1115,13 @@ int phiks_apply(phiks_plan_t plan, const double* v, double* out, void* ws, size_
         epi.a[ell - 1] = sc;
         for (int k = 1; k <= ell; ++k) epi.c[ell - 1][k - 1] = sc / factorial(ell - k);
       }
-      for (int mu = 0; mu < d; ++mu) Lsh[mu] = P.E[mu] + (size_t)j * sq(P.n[mu]);
-      RET_IF(tucker(P, cur, N, Lsh, zero_stride, p, dst, ta, tb, epi, st));
+      RET_IF(plan_tucker(P, MatSel::Level, j, cur, N, p, dst, ta, tb, epi, st));
       cur = dst;
     }
   }
   // exponential outputs exp(2^-j tau K) v (eq. tucker with exp(B/2^j))
   for (int lev = 0; lev < ns; ++lev) {
-    for (int mu = 0; mu < d; ++mu) Lsh[mu] = P.E[mu] + (size_t)lev * sq(P.n[mu]);
-    RET_IF(tucker(P, v, 0, Lsh, zero_stride, 1, slot(lev, 0), ta, tb, EpiStore{1.0, 0.0}, st));
+    RET_IF(plan_tucker(P, MatSel::Level, lev, v, 0, 1, slot(lev, 0), ta, tb, EpiStore{1.0, 0.0}, st));
   }
   return PHIKS_OK;
 }
@@ -968,8 +1142,6 @@ int phiks_combine(phiks_plan_t plan, const double* const* v, double* out, void* 
   double* tb = ta + pp * N;
   double* qa = tb + pp * N;
   double* qb = qa + pp * N;
-  double* Lsh[PHIKS_MAX_D];
-  int64_t zero_stride[PHIKS_MAX_D] = {0};
   bool any = false;
   for (int k = 1; k <= p; ++k) any = any || (v[k] != nullptr);
 
@@ -1001,7 +1173,6 @@ int phiks_combine(phiks_plan_t plan, const double* const* v, double* out, void* 
 
   auto emit = [&](int lev, const double* Q) -> int {
     double* o = out + (int64_t)lev * N;
-    for (int mu = 0; mu < d; ++mu) Lsh[mu] = P.E[mu] + (size_t)lev * sq(P.n[mu]);
     if (v[0]) {
       if (Q) {
         EpiLinComb epi;
@@ -1011,9 +1182,9 @@ int phiks_combine(phiks_plan_t plan, const double* const* v, double* out, void* 
         epi.p = 1;
         epi.a[0] = 1.0;
         epi.c[0][0] = 1.0;
-        return tucker(P, v[0], 0, Lsh, zero_stride, 1, o, ta, tb, epi, st);
+        return plan_tucker(P, MatSel::Level, lev, v[0], 0, 1, o, ta, tb, epi, st);
       }
-      return tucker(P, v[0], 0, Lsh, zero_stride, 1, o, ta, tb, EpiStore{1.0, 0.0}, st);
+      return plan_tucker(P, MatSel::Level, lev, v[0], 0, 1, o, ta, tb, EpiStore{1.0, 0.0}, st);
     }
     if (Q) {
       HIP_OK(hipMemcpyAsync(o, Q + (int64_t)(p - 1) * N, N * sizeof(double),
@@ -1031,8 +1202,7 @@ int phiks_combine(phiks_plan_t plan, const double* const* v, double* out, void* 
     RET_IF(node_inputs(1.0, P.w[q - 1], Q, 0.0));
     for (int i = 0; i < q - 1; ++i) {
       RET_IF(node_inputs(P.theta[i], 1.0, U, 0.0));
-      for (int mu = 0; mu < d; ++mu) Lsh[mu] = P.Lnode[mu] + (size_t)i * sq(P.n[mu]);
-      RET_IF(tucker(P, U, N, Lsh, zero_stride, p, Q, ta, tb, EpiStore{P.w[i], 1.0}, st));
+      RET_IF(plan_tucker(P, MatSel::Node, i, U, N, p, Q, ta, tb, EpiStore{P.w[i], 1.0}, st));
     }
     double* cur = Q;
     if (s < ns) RET_IF(emit(s, cur));
@@ -1049,8 +1219,7 @@ int phiks_combine(phiks_plan_t plan, const double* const* v, double* out, void* 
         for (int k = 1; k <= ell; ++k)
           epi.c[ell - 1][k - 1] = std::ldexp(1.0, -(ell - k) * j) / factorial(ell - k);
       }
-      for (int mu = 0; mu < d; ++mu) Lsh[mu] = P.E[mu] + (size_t)j * sq(P.n[mu]);
-      RET_IF(tucker(P, cur, N, Lsh, zero_stride, p, dst, ta, tb, epi, st));
+      RET_IF(plan_tucker(P, MatSel::Level, j, cur, N, p, dst, ta, tb, epi, st));
       cur = dst;
       if (j - 1 < ns) RET_IF(emit(j - 1, cur));
     }
