@@ -56,9 +56,16 @@ template <> struct Vec4<double> {
 // unless B_KCONTIG is false and it is the tensor (then it is an FP32 intermediate).
 // TC: element type of C.  VEC: 4 elements per load (K, lda, ldb, strides multiples of 4,
 // 16-byte aligned bases, and N a multiple of 4 for an n-contiguous B).
+#ifndef PHIKS_F32_BK
+#define PHIKS_F32_BK 32
+#endif
+#ifndef PHIKS_F32_MIN_WAVES
+#define PHIKS_F32_MIN_WAVES 3
+#endif
+
 template <int BM, int BN, int WM, int WN, bool B_KCONTIG, bool VEC, class TA, class TC, class Epi>
-__global__ void __launch_bounds__(256, 3) gemm_f32_kernel(GemmArgs g, Epi epi) {
-  constexpr int BK = 32;
+__global__ void __launch_bounds__(256, PHIKS_F32_MIN_WAVES) gemm_f32_kernel(GemmArgs g, Epi epi) {
+  constexpr int BK = PHIKS_F32_BK;
   constexpr int WGM = BM / WM;
   constexpr int WGN = BN / WN;
   static_assert(WGM * WGN == 4, "4 waves per work-group");
@@ -207,21 +214,20 @@ __global__ void __launch_bounds__(256, 3) gemm_f32_kernel(GemmArgs g, Epi epi) {
 
   if constexpr (std::is_same<Epi, EpiLinComb>::value) {
     static_assert(std::is_same<TC, double>::value, "the squaring epilogue writes FP64");
+    // one 16-row block at a time (FP64 partial results stay in few registers)
     const int l = (int)z1;
     const double al = epi.a[l];
-    double o[FM][FN][4];
 #pragma unroll
-    for (int i = 0; i < FM; ++i)
+    for (int i = 0; i < FM; ++i) {
+      double o[FN][4];
 #pragma unroll
       for (int j = 0; j < FN; ++j)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) o[i][j][r] = al * (double)acc[i][j][r];
-    for (int k = 0; k <= l; ++k) {
-      const double ck = epi.c[l][k];
-      const double* __restrict__ Yk = epi.Y + (int64_t)(k - l) * epi.N;
-      double y[FM][FN][4];
-#pragma unroll
-      for (int i = 0; i < FM; ++i)
+        for (int r = 0; r < 4; ++r) o[j][r] = al * (double)acc[i][j][r];
+      for (int k = 0; k <= l; ++k) {
+        const double ck = epi.c[l][k];
+        const double* __restrict__ Yk = epi.Y + (int64_t)(k - l) * epi.N;
+        double y[FN][4];
 #pragma unroll
         for (int j = 0; j < FN; ++j) {
           const int n = n0 + wn + j * 16 + lr;
@@ -229,27 +235,24 @@ __global__ void __launch_bounds__(256, 3) gemm_f32_kernel(GemmArgs g, Epi epi) {
           for (int r = 0; r < 4; ++r) {
             const int m = m0 + wm + i * 16 + 4 * lk + r;
             const bool ok = m < g.M && n < g.N;
-            y[i][j][r] = ok ? Yk[cbase + (int64_t)m * g.ldc + n] : 0.0;
+            y[j][r] = ok ? Yk[cbase + (int64_t)m * g.ldc + n] : 0.0;
           }
         }
 #pragma unroll
-      for (int i = 0; i < FM; ++i)
-#pragma unroll
         for (int j = 0; j < FN; ++j)
 #pragma unroll
-          for (int r = 0; r < 4; ++r) o[i][j][r] += ck * y[i][j][r];
-    }
-#pragma unroll
-    for (int i = 0; i < FM; ++i)
+          for (int r = 0; r < 4; ++r) o[j][r] += ck * y[j][r];
+      }
 #pragma unroll
       for (int j = 0; j < FN; ++j) {
         const int n = n0 + wn + j * 16 + lr;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int m = m0 + wm + i * 16 + 4 * lk + r;
-          if (m < g.M && n < g.N) Cb[cbase + (int64_t)m * g.ldc + n] = o[i][j][r];
+          if (m < g.M && n < g.N) Cb[cbase + (int64_t)m * g.ldc + n] = o[j][r];
         }
       }
+    }
   } else {
 #pragma unroll
     for (int i = 0; i < FM; ++i)

@@ -212,8 +212,15 @@ int launch_cfg32(GemmArgs g, const Epi& epi, hipStream_t st) {
   return PHIKS_OK;
 }
 
+#ifndef PHIKS_F32_BIG_TILE
+#define PHIKS_F32_BIG_TILE 0  // 1: 128 x 128 tiles (4 waves of 64 x 64) where they fill the GPU
+#endif
 template <bool KC, bool VEC, class TA, class TC, class Epi>
 int launch_tile32(const GemmArgs& g, const Epi& epi, hipStream_t st) {
+#if PHIKS_F32_BIG_TILE == 1
+  if (g.M >= 128 && g.N >= 128 && tiles_for(g, 128, 128) >= 256)
+    return launch_cfg32<128, 128, 64, 64, KC, VEC, TA, TC>(g, epi, st);
+#endif
   switch (pick_tile(g)) {
     case Tile::T128x128:
     case Tile::T128x64: return launch_cfg32<128, 64, 64, 32, KC, VEC, TA, TC>(g, epi, st);
