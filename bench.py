@@ -32,6 +32,8 @@ METRIC = ("φ-action dofs/s and μ-mode GFLOP/s (% MFMA peak), FP64 vs FP32-MFMA
           "p99 lat")
 FP64_PEAK_TFLOPS = 78.6   # MI355X dense FP64 (matrix and vector)
 FP32_PEAK_TFLOPS = 157.3  # MI355X dense FP32 (matrix)
+BF16_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 (matrix)
+HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E
 
 
 def log(msg):
@@ -49,7 +51,7 @@ def measured_traffic():
     except OSError:
         return None
     h = hashlib.sha256()
-    for f in ("gemm_f64.hpp", "phiks.hip"):
+    for f in ("gemm_f64.hpp", "tucker_f64.hpp"):
         h.update(open(os.path.join(ROOT, "paper_2210_07667_amd", "csrc", f), "rb").read())
     m1 = re.search(r"kernel_source_sha256: (\w+)", text)
     m2 = re.search(r"traffic_bytes_per_launch: ([0-9.eE+-]+)", text)
@@ -154,27 +156,40 @@ def main():
     apply_ms = (time.perf_counter() - a0) * 1e3 / reps
     pl.close()
 
-    # the same call with the mu-mode products in FP32 MFMA (everything else FP64)
+    # the same call with the mu-mode products in FP32 MFMA or BF16x3 (everything else FP64)
     ref64 = out.to_numpy()
-    pl32 = ph.phiks_plan(w.A, w.tau, w.p, w.n_scales, w.tol, w.task, stream=st,
-                         precision=ph.PHIKS_FP32)
-    ph.phiks_apply(pl32, v.ptr, out.ptr, ws.ptr, ws.nbytes, st)
-    ph.synchronize()
-    ph.phiks_kernel_timing_read()
-    ph.phiks_kernel_timing(True)
-    b0 = time.perf_counter()
-    for _ in range(reps):
-        ph.phiks_apply(pl32, v.ptr, out.ptr, ws.ptr, ws.nbytes, st)
-    ph.synchronize()
-    apply32_ms = (time.perf_counter() - b0) * 1e3 / reps
-    ph.phiks_kernel_timing(False)
-    k32_ms, k32_launch, k32_flops = ph.phiks_kernel_timing_read()
-    pl32.close()
-    got32 = out.to_numpy()
     N = w.N
-    err32 = max(float(np.abs(got32[l * N:(l + 1) * N] - ref64[l * N:(l + 1) * N]).max()
-                      / np.abs(ref64[l * N:(l + 1) * N]).max()) for l in range(w.p + 1))
-    ach32 = (k32_flops / (k32_ms * 1e-3)) / 1e12 if k32_ms > 0 else 0.0
+
+    def mixed(precision, peak):
+        plm = ph.phiks_plan(w.A, w.tau, w.p, w.n_scales, w.tol, w.task, stream=st,
+                            precision=precision)
+        ph.phiks_apply(plm, v.ptr, out.ptr, ws.ptr, ws.nbytes, st)
+        ph.synchronize()
+        ph.phiks_kernel_timing_read()
+        ph.phiks_kernel_timing(True)
+        b0 = time.perf_counter()
+        for _ in range(reps):
+            ph.phiks_apply(plm, v.ptr, out.ptr, ws.ptr, ws.nbytes, st)
+        ph.synchronize()
+        ms = (time.perf_counter() - b0) * 1e3 / reps
+        ph.phiks_kernel_timing(False)
+        km, _, kf = ph.phiks_kernel_timing_read()
+        plm.close()
+        got = out.to_numpy()
+        err = max(float(np.abs(got[l * N:(l + 1) * N] - ref64[l * N:(l + 1) * N]).max()
+                        / np.abs(ref64[l * N:(l + 1) * N]).max()) for l in range(w.p + 1))
+        ach = (kf / (km * 1e-3)) / 1e12 if km > 0 else 0.0
+        return {"apply_only_ms": ms, "apply_only_dofs_per_s": N / (ms * 1e-3),
+                "mu_mode_tflops": ach, "peak_tflops": peak, "frac": ach / peak,
+                "max_rel_err_vs_fp64": err}
+
+    fp32 = mixed(ph.PHIKS_FP32, FP32_PEAK_TFLOPS)
+    bf16x3 = mixed(ph.PHIKS_BF16X3, BF16_PEAK_TFLOPS / 3)
+    # BF16x3 keeps FP32 tensors in HBM: 2 N 4 bytes per product of 2 N n flops
+    bf16x3["hbm_gbps_algorithmic"] = bf16x3["mu_mode_tflops"] * 1e3 * 4.0 / w.n[0]
+    bf16x3["hbm_frac"] = bf16x3["hbm_gbps_algorithmic"] / HBM_PEAK_GBPS
+    bf16x3["note"] = ("peak_tflops is the dense BF16 MFMA peak / 3 (three products per "
+                      "FP32 product); mu_mode_tflops counts 2 M N K per product")
 
     achieved = (k_flops / (k_ms * 1e-3)) / 1e12 if k_ms > 0 else 0.0
     n_mu = w.n[0]
@@ -203,10 +218,8 @@ def main():
         "apply_only_ms": apply_ms,
         "apply_only_dofs_per_s": w.N / (apply_ms * 1e-3),
         "mu_mode_gflops_per_s": achieved * 1e3,
-        "fp32_mfma": {"apply_only_ms": apply32_ms, "apply_only_dofs_per_s": w.N / (apply32_ms * 1e-3),
-                      "mu_mode_tflops": ach32, "peak_tflops": FP32_PEAK_TFLOPS,
-                      "frac": ach32 / FP32_PEAK_TFLOPS,
-                      "max_rel_err_vs_fp64": err32},
+        "fp32_mfma": fp32,
+        "bf16x3_mfma": bf16x3,
     }
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle (one full call)")

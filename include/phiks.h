@@ -58,9 +58,12 @@ enum {
 enum { PHIKS_SAME_VECTOR = 0, PHIKS_LINCOMB = 1 };
 /* Arithmetic of the mu-mode products.  PHIKS_FP32: FP32 MFMA products of FP32 copies
  * of the small exponentials, FP32 intermediates between the modes of a Tucker
- * operator; the small exponentials themselves, the quadrature sums, the squaring
- * recurrence and every output stay FP64. */
-enum { PHIKS_FP64 = 0, PHIKS_FP32 = 1 };
+ * operator.  PHIKS_BF16X3: as PHIKS_FP32, but each product of two FP32 operands is
+ * formed from their bfloat16 splits x = hi + lo as hi*hi + hi*lo + lo*hi on BF16 MFMA
+ * with FP32 accumulation (each term a*b within 3 * 2^-16 |a b|).  In both, the
+ * small exponentials themselves, the quadrature sums, the squaring recurrence and
+ * every output stay FP64. */
+enum { PHIKS_FP64 = 0, PHIKS_FP32 = 1, PHIKS_BF16X3 = 2 };
 
 #define PHIKS_MAX_D 8      /* largest number of modes d */
 #define PHIKS_MAX_P 8      /* largest phi index p */
@@ -93,7 +96,7 @@ enum { PHIKS_FP64 = 0, PHIKS_FP32 = 1 };
  *   task      PHIKS_SAME_VECTOR or PHIKS_LINCOMB
  *   vnorms    host array of 2-norms (same vector: 1 value ||v||; combination: p+1
  *             values ||v_0||..||v_p||), or NULL for all norms = 1
- *   precision PHIKS_FP64 or PHIKS_FP32 (see above)
+ *   precision PHIKS_FP64, PHIKS_FP32 or PHIKS_BF16X3 (see above)
  *   hip_stream stream for the device work (hipStream_t), may be NULL
  *   out       receives the plan; owned by the caller, release with
  *             phiks_plan_destroy.  Its device buffers live on the current device.

@@ -33,6 +33,7 @@ PHIKS_SAME_VECTOR = 0
 PHIKS_LINCOMB = 1
 PHIKS_FP64 = 0
 PHIKS_FP32 = 1
+PHIKS_BF16X3 = 2
 
 # every exported entry point of include/phiks.h
 SYMBOLS = ("phiks_plan", "phiks_apply", "phiks_combine", "phiks_workspace_size",

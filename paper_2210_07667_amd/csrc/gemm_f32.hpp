@@ -52,6 +52,70 @@ template <> struct Vec4<double> {
   }
 };
 
+// Epilogue of the FP32-accumulating kernels: wave fragments acc[i][j] (16 x 16 each,
+// c[r] at row 4 (l >> 4) + r, column l & 15) of the output block whose top-left
+// corner is (mb, nb), written through Epi.  The squaring epilogue (EpiLinComb)
+// forms its FP64 combination one 16-row block at a time.
+template <int FM, int FN, class TC, class Epi>
+__device__ __forceinline__ void store_acc_tile(const flt4 (&acc)[FM][FN], const GemmArgs& g,
+                                               const Epi& epi, TC* Cb, int64_t cbase, int64_t z1,
+                                               int mb, int nb, int lr, int lk) {
+  if constexpr (std::is_same<Epi, EpiLinComb>::value) {
+    static_assert(std::is_same<TC, double>::value, "the squaring epilogue writes FP64");
+    // one 16-row block at a time (FP64 partial results stay in few registers)
+    const int l = (int)z1;
+    const double al = epi.a[l];
+#pragma unroll
+    for (int i = 0; i < FM; ++i) {
+      double o[FN][4];
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) o[j][r] = al * (double)acc[i][j][r];
+      for (int k = 0; k <= l; ++k) {
+        const double ck = epi.c[l][k];
+        const double* __restrict__ Yk = epi.Y + (int64_t)(k - l) * epi.N;
+        double y[FN][4];
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+          const int n = nb + j * 16 + lr;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int m = mb + i * 16 + 4 * lk + r;
+            const bool ok = m < g.M && n < g.N;
+            y[j][r] = ok ? Yk[cbase + (int64_t)m * g.ldc + n] : 0.0;
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) o[j][r] += ck * y[j][r];
+      }
+#pragma unroll
+      for (int j = 0; j < FN; ++j) {
+        const int n = nb + j * 16 + lr;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int m = mb + i * 16 + 4 * lk + r;
+          if (m < g.M && n < g.N) Cb[cbase + (int64_t)m * g.ldc + n] = o[j][r];
+        }
+      }
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j) {
+        const int n = nb + j * 16 + lr;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int m = mb + i * 16 + 4 * lk + r;
+          if (m < g.M && n < g.N) epi(Cb, cbase + (int64_t)m * g.ldc + n, z1, (double)acc[i][j][r]);
+        }
+      }
+  }
+}
+
 // TA: element type of A in memory; B is FP32 (a small matrix or an FP32 intermediate)
 // unless B_KCONTIG is false and it is the tensor (then it is an FP32 intermediate).
 // TC: element type of C.  VEC: 4 elements per load (K, lda, ldb, strides multiples of 4,
@@ -212,60 +276,7 @@ __global__ void __launch_bounds__(256, PHIKS_F32_MIN_WAVES) gemm_f32_kernel(Gemm
     __syncthreads();
   }
 
-  if constexpr (std::is_same<Epi, EpiLinComb>::value) {
-    static_assert(std::is_same<TC, double>::value, "the squaring epilogue writes FP64");
-    // one 16-row block at a time (FP64 partial results stay in few registers)
-    const int l = (int)z1;
-    const double al = epi.a[l];
-#pragma unroll
-    for (int i = 0; i < FM; ++i) {
-      double o[FN][4];
-#pragma unroll
-      for (int j = 0; j < FN; ++j)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) o[j][r] = al * (double)acc[i][j][r];
-      for (int k = 0; k <= l; ++k) {
-        const double ck = epi.c[l][k];
-        const double* __restrict__ Yk = epi.Y + (int64_t)(k - l) * epi.N;
-        double y[FN][4];
-#pragma unroll
-        for (int j = 0; j < FN; ++j) {
-          const int n = n0 + wn + j * 16 + lr;
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int m = m0 + wm + i * 16 + 4 * lk + r;
-            const bool ok = m < g.M && n < g.N;
-            y[j][r] = ok ? Yk[cbase + (int64_t)m * g.ldc + n] : 0.0;
-          }
-        }
-#pragma unroll
-        for (int j = 0; j < FN; ++j)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) o[j][r] += ck * y[j][r];
-      }
-#pragma unroll
-      for (int j = 0; j < FN; ++j) {
-        const int n = n0 + wn + j * 16 + lr;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int m = m0 + wm + i * 16 + 4 * lk + r;
-          if (m < g.M && n < g.N) Cb[cbase + (int64_t)m * g.ldc + n] = o[j][r];
-        }
-      }
-    }
-  } else {
-#pragma unroll
-    for (int i = 0; i < FM; ++i)
-#pragma unroll
-      for (int j = 0; j < FN; ++j) {
-        const int n = n0 + wn + j * 16 + lr;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int m = m0 + wm + i * 16 + 4 * lk + r;
-          if (m < g.M && n < g.N) epi(Cb, cbase + (int64_t)m * g.ldc + n, z1, (double)acc[i][j][r]);
-        }
-      }
-  }
+  store_acc_tile<FM, FN, TC>(acc, g, epi, Cb, cbase, z1, m0 + wm, n0 + wn, lr, lk);
 }
 
 }  // namespace phiks

@@ -24,375 +24,17 @@
 #include "gemm_f64.hpp"
 #include "kernels.hpp"
 #include "phiks.h"
+#include "plan.hpp"
 #include "planner.hpp"
+#include "runtime.hpp"
+#include "tucker_mixed.hpp"
+#include "tucker_f64.hpp"
 
 using namespace phiks;
 
 namespace {
 
-thread_local std::string g_last_error;
-
-void set_error(const std::string& s) { g_last_error = s; }
-
-#define HIP_OK(expr)                                                                  \
-  do {                                                                                \
-    hipError_t e_ = (expr);                                                           \
-    if (e_ != hipSuccess) {                                                           \
-      set_error(std::string(#expr) + ": " + hipGetErrorString(e_));                   \
-      return PHIKS_EDEVICE;                                                           \
-    }                                                                                 \
-  } while (0)
-
-#define CHECK_LAUNCH()                                                                \
-  do {                                                                                \
-    hipError_t e_ = hipGetLastError();                                                \
-    if (e_ != hipSuccess) {                                                           \
-      set_error(std::string("kernel launch: ") + hipGetErrorString(e_));              \
-      return PHIKS_EDEVICE;                                                           \
-    }                                                                                 \
-  } while (0)
-
-#define RET_IF(st)                                                                    \
-  do {                                                                                \
-    int r_ = (st);                                                                    \
-    if (r_ != PHIKS_OK) return r_;                                                    \
-  } while (0)
-
-// --------------------------------------------------- kernel timing (optional)
-// When enabled, every mu-mode GEMM launch is bracketed by two HIP events recorded
-// on its own stream, with its algorithmic flop count 2 M N K (per batch entry).
-struct TimedLaunch {
-  hipEvent_t a, b;
-  double flops;
-};
-std::mutex g_timing_mu;
-bool g_timing = false;
-std::vector<TimedLaunch> g_timed;
-std::vector<hipEvent_t> g_event_pool;
-
-hipEvent_t pooled_event() {
-  if (!g_event_pool.empty()) {
-    hipEvent_t e = g_event_pool.back();
-    g_event_pool.pop_back();
-    return e;
-  }
-  hipEvent_t e = nullptr;
-  if (hipEventCreate(&e) != hipSuccess) return nullptr;
-  return e;
-}
-
-// ------------------------------------------------------------- GEMM launching
-enum class Tile { T128x128, T128x64, T64x128, T64x64, T32x32 };
-
-int64_t tiles_for(const GemmArgs& g, int bm, int bn) {
-  return (int64_t)((g.M + bm - 1) / bm) * ((g.N + bn - 1) / bn) * g.nb0 * g.nb1;
-}
-
-// Largest tile that still gives at least one work-group per compute unit; small
-// products (the exponentials of the small matrices) get small tiles and more groups.
-#ifndef PHIKS_BIG_TILE
-#define PHIKS_BIG_TILE 0  // 0: 128 x 64, 1: 128 x 128
-#endif
-Tile pick_tile(const GemmArgs& g) {
-  constexpr int64_t kCUs = 256;
-  if (PHIKS_BIG_TILE == 1 && g.M >= 128 && g.N >= 128 && tiles_for(g, 128, 128) >= kCUs)
-    return Tile::T128x128;
-  if (g.M >= 128 && g.N >= 64 && tiles_for(g, 128, 64) >= kCUs) return Tile::T128x64;
-  if (g.M >= 64 && g.N >= 128 && tiles_for(g, 64, 128) >= kCUs) return Tile::T64x128;
-  if (g.M >= 64 && g.N >= 64 && tiles_for(g, 64, 64) >= kCUs) return Tile::T64x64;
-  if (g.M >= 96 && g.N >= 48 && tiles_for(g, 32, 32) < kCUs) return Tile::T64x64;
-  return Tile::T32x32;
-}
-
-bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
-
-// 16-byte loads need even contraction length, even leading dimensions and batch
-// strides, 16-byte aligned bases, and (for n-contiguous B) an even N.
-bool vec_ok(const GemmArgs& g, bool kcontig, const std::vector<const void*>& extra_ptrs) {
-  if (g.K % 2 || g.lda % 2 || g.ldb % 2) return false;
-  if (!kcontig && g.N % 2) return false;
-  if (g.sA0 % 2 || g.sA1 % 2 || g.sB0 % 2 || g.sB1 % 2) return false;
-  if (g.pA == nullptr && (!aligned16(g.A) || !aligned16(g.B))) return false;
-  for (const void* q : extra_ptrs)
-    if (!aligned16(q)) return false;
-  return true;
-}
-
-template <int BM, int BN, int WM, int WN, bool KC, bool VEC, class Epi>
-int launch_cfg(GemmArgs g, const Epi& epi, hipStream_t st) {
-  g.tiles_m = (g.M + BM - 1) / BM;
-  g.tiles_n = (g.N + BN - 1) / BN;
-  g.total_tiles = (int64_t)g.tiles_m * g.tiles_n * g.nb0 * g.nb1;
-  if (g.total_tiles <= 0) return PHIKS_OK;
-  if (g.total_tiles > 0x7fffffffLL) {
-    set_error("GEMM grid too large");
-    return PHIKS_EINVAL;
-  }
-  hipEvent_t ea = nullptr, eb = nullptr;
-  {
-    std::lock_guard<std::mutex> lk(g_timing_mu);
-    if (g_timing) {
-      ea = pooled_event();
-      eb = pooled_event();
-      if (ea && eb) HIP_OK(hipEventRecord(ea, st));
-    }
-  }
-  (void)hipGetLastError();  // clear a stale error left by an unrelated earlier call
-  hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, WM, WN, KC, VEC, Epi>),
-                     dim3((unsigned)g.total_tiles), dim3(256), 0, st, g, epi);
-  CHECK_LAUNCH();
-  if (ea && eb) {
-    HIP_OK(hipEventRecord(eb, st));
-    std::lock_guard<std::mutex> lk(g_timing_mu);
-    g_timed.push_back({ea, eb, 2.0 * g.M * (double)g.N * g.K * g.nb0 * (double)g.nb1});
-  }
-  return PHIKS_OK;
-}
-
-template <bool KC, bool VEC, class Epi>
-int launch_tile(const GemmArgs& g, const Epi& epi, hipStream_t st) {
-  switch (pick_tile(g)) {
-#if PHIKS_BIG_TILE == 1
-    case Tile::T128x128: return launch_cfg<128, 128, 64, 64, KC, VEC>(g, epi, st);
-#endif
-    case Tile::T128x64: return launch_cfg<128, 64, 64, 32, KC, VEC>(g, epi, st);
-    case Tile::T64x128: return launch_cfg<64, 128, 32, 64, KC, VEC>(g, epi, st);
-    case Tile::T64x64: return launch_cfg<64, 64, 32, 32, KC, VEC>(g, epi, st);
-    default: return launch_cfg<32, 32, 16, 16, KC, VEC>(g, epi, st);
-  }
-}
-
-template <bool KC, class Epi>
-int launch_gemm(const GemmArgs& g, const Epi& epi, hipStream_t st,
-                const std::vector<const void*>& extra_ptrs = {}) {
-  if (g.pA != nullptr && g.nb0 != 1) {
-    set_error("pointer-array GEMM needs nb0 == 1");
-    return PHIKS_EINVAL;
-  }
-  if (vec_ok(g, KC, extra_ptrs)) return launch_tile<KC, true>(g, epi, st);
-  return launch_tile<KC, false>(g, epi, st);
-}
-
-// ------------------------------------------------- FP32 MFMA mu-mode launches
-bool vec4_ok(const GemmArgs& g, bool kcontig) {
-  if (g.K % 4 || g.lda % 4 || g.ldb % 4) return false;
-  if (!kcontig && g.N % 4) return false;
-  if (g.sA0 % 4 || g.sA1 % 4 || g.sB0 % 4 || g.sB1 % 4) return false;
-  return aligned16(g.A) && aligned16(g.B);
-}
-
-template <int BM, int BN, int WM, int WN, bool KC, bool VEC, class TA, class TC, class Epi>
-int launch_cfg32(GemmArgs g, const Epi& epi, hipStream_t st) {
-  g.tiles_m = (g.M + BM - 1) / BM;
-  g.tiles_n = (g.N + BN - 1) / BN;
-  g.total_tiles = (int64_t)g.tiles_m * g.tiles_n * g.nb0 * g.nb1;
-  if (g.total_tiles <= 0) return PHIKS_OK;
-  if (g.total_tiles > 0x7fffffffLL) {
-    set_error("GEMM grid too large");
-    return PHIKS_EINVAL;
-  }
-  hipEvent_t ea = nullptr, eb = nullptr;
-  {
-    std::lock_guard<std::mutex> lk(g_timing_mu);
-    if (g_timing) {
-      ea = pooled_event();
-      eb = pooled_event();
-      if (ea && eb) HIP_OK(hipEventRecord(ea, st));
-    }
-  }
-  (void)hipGetLastError();
-  hipLaunchKernelGGL((gemm_f32_kernel<BM, BN, WM, WN, KC, VEC, TA, TC, Epi>),
-                     dim3((unsigned)g.total_tiles), dim3(256), 0, st, g, epi);
-  CHECK_LAUNCH();
-  if (ea && eb) {
-    HIP_OK(hipEventRecord(eb, st));
-    std::lock_guard<std::mutex> lk(g_timing_mu);
-    g_timed.push_back({ea, eb, 2.0 * g.M * (double)g.N * g.K * g.nb0 * (double)g.nb1});
-  }
-  return PHIKS_OK;
-}
-
-#ifndef PHIKS_F32_BIG_TILE
-#define PHIKS_F32_BIG_TILE 0  // 1: 128 x 128 tiles (4 waves of 64 x 64) where they fill the GPU
-#endif
-template <bool KC, bool VEC, class TA, class TC, class Epi>
-int launch_tile32(const GemmArgs& g, const Epi& epi, hipStream_t st) {
-#if PHIKS_F32_BIG_TILE == 1
-  if (g.M >= 128 && g.N >= 128 && tiles_for(g, 128, 128) >= 256)
-    return launch_cfg32<128, 128, 64, 64, KC, VEC, TA, TC>(g, epi, st);
-#endif
-  switch (pick_tile(g)) {
-    case Tile::T128x128:
-    case Tile::T128x64: return launch_cfg32<128, 64, 64, 32, KC, VEC, TA, TC>(g, epi, st);
-    case Tile::T64x128: return launch_cfg32<64, 128, 32, 64, KC, VEC, TA, TC>(g, epi, st);
-    case Tile::T64x64: return launch_cfg32<64, 64, 32, 32, KC, VEC, TA, TC>(g, epi, st);
-    default: return launch_cfg32<32, 32, 16, 16, KC, VEC, TA, TC>(g, epi, st);
-  }
-}
-
-template <bool KC, class TA, class TC, class Epi>
-int launch_gemm32(const GemmArgs& g, const Epi& epi, hipStream_t st) {
-  if (vec4_ok(g, KC)) return launch_tile32<KC, true, TA, TC>(g, epi, st);
-  return launch_tile32<KC, false, TA, TC>(g, epi, st);
-}
-
-GemmArgs empty_args() {
-  GemmArgs g;
-  std::memset(&g, 0, sizeof(g));
-  g.nb0 = g.nb1 = 1;
-  return g;
-}
-
-}  // namespace
-
-// ------------------------------------------------------------------- the plan
-struct phiks_plan_s {
-  int d = 0;
-  int64_t n[PHIKS_MAX_D] = {0};
-  int64_t N = 0;
-  double tau = 0.0;
-  int p = 0, ns = 1, task = 0, precision = 0;
-  int s = 0, q = 0, t_paper = 0, t_exec = 0;
-  double theta[kQMax] = {0}, w[kQMax] = {0};
-  int device = 0;
-  hipStream_t stream = nullptr;         // stream the plan was built on (and is released on)
-  void* dmem = nullptr;                 // all plan-lifetime device matrices
-  double* Lnode[PHIKS_MAX_D] = {nullptr};  // (q-1) node matrices per mode, stride n^2
-  double* E[PHIKS_MAX_D] = {nullptr};      // (s+1) matrices per mode: exp(B/2^j), stride n^2
-  float* Lnode32[PHIKS_MAX_D] = {nullptr};  // FP32 copies (precision PHIKS_FP32)
-  float* E32[PHIKS_MAX_D] = {nullptr};
-  std::vector<std::vector<char>> host_keep;  // host sources of async copies
-};
-
-namespace {
-
 int64_t sq(int64_t x) { return x * x; }
-
-// ---------------------------------------------------------- Tucker operator
-// Applies, to nbatch tensors in_b = in + b*in_stride, the Tucker operator with the
-// matrices L[mu] + b*l_stride[mu] (Section 2, eq. tucker), writing the last mode
-// through the epilogue into out (batch b at out + b*N).  ta/tb: nbatch*N scratch.
-// The result of mode mu (< d) goes to ta for odd mu and tb for even mu; out must be
-// the buffer not read by the last mode.
-template <class Epi>
-int tucker(const phiks_plan_s& P, const double* in, int64_t in_stride,
-           double* const* L, const int64_t* l_stride, int nbatch, double* out,
-           double* ta, double* tb, const Epi& epi, hipStream_t st) {
-  const int d = P.d;
-  const int64_t N = P.N;
-  const double* cur = in;
-  int64_t cur_stride = in_stride;
-  for (int mu = 1; mu <= d; ++mu) {
-    const int64_t nm = P.n[mu - 1];
-    int64_t nlo = 1, nhi = 1;
-    for (int k = 0; k < mu - 1; ++k) nlo *= P.n[k];
-    for (int k = mu; k < d; ++k) nhi *= P.n[k];
-    const bool last = (mu == d);
-    double* dst = last ? out : ((mu % 2 == 1) ? ta : tb);
-    GemmArgs g = empty_args();
-    g.nb1 = nbatch;
-    if (mu == 1) {
-      // W[m][i] = sum_j X[m][j] L[i][j], rows m < n_>
-      g.M = (int)nhi;
-      g.N = (int)nm;
-      g.K = (int)nm;
-      g.A = cur;
-      g.lda = nm;
-      g.B = L[0];
-      g.ldb = nm;
-      g.C = dst;
-      g.ldc = nm;
-      g.sA1 = cur_stride;
-      g.sB1 = l_stride[0];
-      g.sC1 = N;
-      if (last) RET_IF((launch_gemm<true>(g, epi, st)));
-      else RET_IF((launch_gemm<true>(g, EpiStore{1.0, 0.0}, st)));
-    } else {
-      // W_b[i][a] = sum_j L[i][j] X_b[j][a], batch b < n_>
-      g.M = (int)nm;
-      g.N = (int)nlo;
-      g.K = (int)nm;
-      g.A = L[mu - 1];
-      g.lda = nm;
-      g.B = cur;
-      g.ldb = nlo;
-      g.C = dst;
-      g.ldc = nlo;
-      g.nb0 = (int)nhi;
-      g.sA0 = 0;
-      g.sB0 = nm * nlo;
-      g.sC0 = nm * nlo;
-      g.sA1 = l_stride[mu - 1];
-      g.sB1 = cur_stride;
-      g.sC1 = N;
-      if (last) RET_IF((launch_gemm<false>(g, epi, st)));
-      else RET_IF((launch_gemm<false>(g, EpiStore{1.0, 0.0}, st)));
-    }
-    cur = dst;
-    cur_stride = N;
-  }
-  return PHIKS_OK;
-}
-
-// FP32 MFMA Tucker operator: the chain input (FP64) is converted in the first mode,
-// intermediate modes are FP32 (ta/tb hold floats), the last mode writes FP64 through
-// the same epilogue as the FP64 chain.  L[mu] are FP32 copies of the matrices.
-template <class Epi>
-int tucker32(const phiks_plan_s& P, const double* in, int64_t in_stride,
-             float* const* L, const int64_t* l_stride, int nbatch, double* out,
-             double* ta, double* tb, const Epi& epi, hipStream_t st) {
-  const int d = P.d;
-  const int64_t N = P.N;
-  const void* cur = in;
-  int64_t cur_stride = in_stride;
-  for (int mu = 1; mu <= d; ++mu) {
-    const int64_t nm = P.n[mu - 1];
-    int64_t nlo = 1, nhi = 1;
-    for (int k = 0; k < mu - 1; ++k) nlo *= P.n[k];
-    for (int k = mu; k < d; ++k) nhi *= P.n[k];
-    const bool last = (mu == d);
-    void* dst = last ? (void*)out : (void*)((mu % 2 == 1) ? ta : tb);
-    GemmArgs g = empty_args();
-    g.nb1 = nbatch;
-    if (mu == 1) {
-      g.M = (int)nhi;
-      g.N = (int)nm;
-      g.K = (int)nm;
-      g.A = reinterpret_cast<const double*>(cur);
-      g.lda = nm;
-      g.B = reinterpret_cast<const double*>(L[0]);
-      g.ldb = nm;
-      g.C = reinterpret_cast<double*>(dst);
-      g.ldc = nm;
-      g.sA1 = cur_stride;
-      g.sB1 = l_stride[0];
-      g.sC1 = N;
-      if (last) RET_IF((launch_gemm32<true, double, double>(g, epi, st)));
-      else RET_IF((launch_gemm32<true, double, float>(g, EpiStoreT<float>{1.0, 0.0}, st)));
-    } else {
-      g.M = (int)nm;
-      g.N = (int)nlo;
-      g.K = (int)nm;
-      g.A = reinterpret_cast<const double*>(L[mu - 1]);
-      g.lda = nm;
-      g.B = reinterpret_cast<const double*>(cur);
-      g.ldb = nlo;
-      g.C = reinterpret_cast<double*>(dst);
-      g.ldc = nlo;
-      g.nb0 = (int)nhi;
-      g.sB0 = nm * nlo;
-      g.sC0 = nm * nlo;
-      g.sA1 = l_stride[mu - 1];
-      g.sB1 = cur_stride;
-      g.sC1 = N;
-      if (last) RET_IF((launch_gemm32<false, float, double>(g, epi, st)));
-      else RET_IF((launch_gemm32<false, float, float>(g, EpiStoreT<float>{1.0, 0.0}, st)));
-    }
-    cur = dst;
-    cur_stride = N;
-  }
-  return PHIKS_OK;
-}
 
 // Which small matrices a Tucker operator of the phi recurrence uses.
 enum class MatSel { AllNodes, Node, Level };
@@ -405,14 +47,16 @@ int plan_tucker(const phiks_plan_s& P, MatSel sel, int idx, const double* in,
                 const Epi& epi, hipStream_t st) {
   int64_t stride[PHIKS_MAX_D];
   for (int mu = 0; mu < P.d; ++mu) stride[mu] = (sel == MatSel::AllNodes) ? P.n[mu] * P.n[mu] : 0;
-  if (P.precision == PHIKS_FP32) {
+  if (P.precision != PHIKS_FP64) {
     float* L[PHIKS_MAX_D];
     for (int mu = 0; mu < P.d; ++mu) {
       const int64_t nn = P.n[mu] * P.n[mu];
       L[mu] = (sel == MatSel::Level) ? P.E32[mu] + (size_t)idx * nn
                                      : P.Lnode32[mu] + (size_t)(sel == MatSel::Node ? idx : 0) * nn;
     }
-    return tucker32(P, in, in_stride, L, stride, nbatch, out, ta, tb, epi, st);
+    if (P.precision == PHIKS_BF16X3)
+      return tucker_mixed<PHIKS_BF16X3>(P, in, in_stride, L, stride, nbatch, out, ta, tb, epi, st);
+    return tucker_mixed<PHIKS_FP32>(P, in, in_stride, L, stride, nbatch, out, ta, tb, epi, st);
   }
   double* L[PHIKS_MAX_D];
   for (int mu = 0; mu < P.d; ++mu) {
@@ -794,7 +438,8 @@ int phiks_plan(int d, const int64_t* n, const double* const* A, double tau, int 
   *out = nullptr;
   int rc = validate_problem(d, n, A, tau, p, n_scales, tol, task, vnorms);
   if (rc != PHIKS_OK) return rc;
-  if (precision != PHIKS_FP64 && precision != PHIKS_FP32) return PHIKS_EINVAL;
+  if (precision != PHIKS_FP64 && precision != PHIKS_FP32 && precision != PHIKS_BF16X3)
+    return PHIKS_EINVAL;
   PlanChoice pc;
   rc = host_plan(d, n, A, tau, p, n_scales, tol, task, vnorms, pc);
   if (rc != PHIKS_OK) return rc;
@@ -833,7 +478,7 @@ int phiks_plan(int d, const int64_t* n, const double* const* A, double tau, int 
     total += (size_t)(pc.s + 1) * sq(n[mu]);
   }
   const size_t total64 = total;  // in doubles; FP32 copies follow (counted in doubles, rounded up)
-  if (precision == PHIKS_FP32) {
+  if (precision != PHIKS_FP64) {
     for (int mu = 0; mu < d; ++mu) {
       offL32[mu] = total * 2;  // float index
       total += ((size_t)nodes * sq(n[mu]) + 3) / 2 + 1;
@@ -851,7 +496,7 @@ int phiks_plan(int d, const int64_t* n, const double* const* A, double tau, int 
   for (int mu = 0; mu < d; ++mu) {
     P->Lnode[mu] = base + offL[mu];
     P->E[mu] = base + offE[mu];
-    if (precision == PHIKS_FP32) {
+    if (precision != PHIKS_FP64) {
       P->Lnode32[mu] = (float*)P->dmem + offL32[mu];
       P->E32[mu] = (float*)P->dmem + offE32[mu];
     }
@@ -914,7 +559,7 @@ int phiks_plan(int d, const int64_t* n, const double* const* A, double tau, int 
       if (rc != PHIKS_OK) return fail(rc);
     }
   }
-  if (precision == PHIKS_FP32) {
+  if (precision != PHIKS_FP64) {
     // FP32 copies of every node matrix and of exp(B/2^j): the mixed-precision path
     // multiplies by these; everything else stays FP64
     for (int mu = 0; mu < d; ++mu) {

@@ -1,0 +1,28 @@
+// The plan object behind phiks_plan_t: problem shape, the chosen (s, q), the GLL rule
+// and the device copies of the small exponentials.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <vector>
+
+#include "phiks.h"
+#include "planner.hpp"
+
+// ------------------------------------------------------------------- the plan
+struct phiks_plan_s {
+  int d = 0;
+  int64_t n[PHIKS_MAX_D] = {0};
+  int64_t N = 0;
+  double tau = 0.0;
+  int p = 0, ns = 1, task = 0, precision = 0;
+  int s = 0, q = 0, t_paper = 0, t_exec = 0;
+  double theta[phiks::kQMax] = {0}, w[phiks::kQMax] = {0};
+  int device = 0;
+  hipStream_t stream = nullptr;         // stream the plan was built on (and is released on)
+  void* dmem = nullptr;                 // all plan-lifetime device matrices
+  double* Lnode[PHIKS_MAX_D] = {nullptr};  // (q-1) node matrices per mode, stride n^2
+  double* E[PHIKS_MAX_D] = {nullptr};      // (s+1) matrices per mode: exp(B/2^j), stride n^2
+  float* Lnode32[PHIKS_MAX_D] = {nullptr};  // FP32 copies (precision PHIKS_FP32)
+  float* E32[PHIKS_MAX_D] = {nullptr};
+  std::vector<std::vector<char>> host_keep;  // host sources of async copies
+};

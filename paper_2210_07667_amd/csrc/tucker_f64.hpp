@@ -1,0 +1,174 @@
+// FP64 mu-mode products: tile choice and launch of gemm_f64_kernel, and the Tucker
+// operator as a chain of d such launches (Section 2, Lemma 1).  Included once, by
+// phiks.hip, after runtime.hpp and plan.hpp.
+#pragma once
+#include <algorithm>
+#include <vector>
+
+#include "gemm_f64.hpp"
+#include "plan.hpp"
+#include "runtime.hpp"
+
+namespace {
+
+using namespace phiks;
+
+// ------------------------------------------------------------- GEMM launching
+enum class Tile { T128x128, T128x64, T64x128, T64x64, T32x32 };
+
+int64_t tiles_for(const GemmArgs& g, int bm, int bn) {
+  return (int64_t)((g.M + bm - 1) / bm) * ((g.N + bn - 1) / bn) * g.nb0 * g.nb1;
+}
+
+// Largest tile that still gives at least one work-group per compute unit; small
+// products (the exponentials of the small matrices) get small tiles and more groups.
+#ifndef PHIKS_BIG_TILE
+#define PHIKS_BIG_TILE 0  // 0: 128 x 64, 1: 128 x 128
+#endif
+Tile pick_tile(const GemmArgs& g) {
+  constexpr int64_t kCUs = 256;
+  if (PHIKS_BIG_TILE == 1 && g.M >= 128 && g.N >= 128 && tiles_for(g, 128, 128) >= kCUs)
+    return Tile::T128x128;
+  if (g.M >= 128 && g.N >= 64 && tiles_for(g, 128, 64) >= kCUs) return Tile::T128x64;
+  if (g.M >= 64 && g.N >= 128 && tiles_for(g, 64, 128) >= kCUs) return Tile::T64x128;
+  if (g.M >= 64 && g.N >= 64 && tiles_for(g, 64, 64) >= kCUs) return Tile::T64x64;
+  if (g.M >= 96 && g.N >= 48 && tiles_for(g, 32, 32) < kCUs) return Tile::T64x64;
+  return Tile::T32x32;
+}
+
+bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
+
+// 16-byte loads need even contraction length, even leading dimensions and batch
+// strides, 16-byte aligned bases, and (for n-contiguous B) an even N.
+bool vec_ok(const GemmArgs& g, bool kcontig, const std::vector<const void*>& extra_ptrs) {
+  if (g.K % 2 || g.lda % 2 || g.ldb % 2) return false;
+  if (!kcontig && g.N % 2) return false;
+  if (g.sA0 % 2 || g.sA1 % 2 || g.sB0 % 2 || g.sB1 % 2) return false;
+  if (g.pA == nullptr && (!aligned16(g.A) || !aligned16(g.B))) return false;
+  for (const void* q : extra_ptrs)
+    if (!aligned16(q)) return false;
+  return true;
+}
+
+template <int BM, int BN, int WM, int WN, bool KC, bool VEC, class Epi>
+int launch_cfg(GemmArgs g, const Epi& epi, hipStream_t st) {
+  g.tiles_m = (g.M + BM - 1) / BM;
+  g.tiles_n = (g.N + BN - 1) / BN;
+  g.total_tiles = (int64_t)g.tiles_m * g.tiles_n * g.nb0 * g.nb1;
+  if (g.total_tiles <= 0) return PHIKS_OK;
+  if (g.total_tiles > 0x7fffffffLL) {
+    set_error("GEMM grid too large");
+    return PHIKS_EINVAL;
+  }
+  hipEvent_t ea = nullptr, eb = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_timing_mu);
+    if (g_timing) {
+      ea = pooled_event();
+      eb = pooled_event();
+      if (ea && eb) HIP_OK(hipEventRecord(ea, st));
+    }
+  }
+  (void)hipGetLastError();  // clear a stale error left by an unrelated earlier call
+  hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, WM, WN, KC, VEC, Epi>),
+                     dim3((unsigned)g.total_tiles), dim3(256), 0, st, g, epi);
+  CHECK_LAUNCH();
+  if (ea && eb) {
+    HIP_OK(hipEventRecord(eb, st));
+    std::lock_guard<std::mutex> lk(g_timing_mu);
+    g_timed.push_back({ea, eb, 2.0 * g.M * (double)g.N * g.K * g.nb0 * (double)g.nb1});
+  }
+  return PHIKS_OK;
+}
+
+template <bool KC, bool VEC, class Epi>
+int launch_tile(const GemmArgs& g, const Epi& epi, hipStream_t st) {
+  switch (pick_tile(g)) {
+#if PHIKS_BIG_TILE == 1
+    case Tile::T128x128: return launch_cfg<128, 128, 64, 64, KC, VEC>(g, epi, st);
+#endif
+    case Tile::T128x64: return launch_cfg<128, 64, 64, 32, KC, VEC>(g, epi, st);
+    case Tile::T64x128: return launch_cfg<64, 128, 32, 64, KC, VEC>(g, epi, st);
+    case Tile::T64x64: return launch_cfg<64, 64, 32, 32, KC, VEC>(g, epi, st);
+    default: return launch_cfg<32, 32, 16, 16, KC, VEC>(g, epi, st);
+  }
+}
+
+template <bool KC, class Epi>
+int launch_gemm(const GemmArgs& g, const Epi& epi, hipStream_t st,
+                const std::vector<const void*>& extra_ptrs = {}) {
+  if (g.pA != nullptr && g.nb0 != 1) {
+    set_error("pointer-array GEMM needs nb0 == 1");
+    return PHIKS_EINVAL;
+  }
+  if (vec_ok(g, KC, extra_ptrs)) return launch_tile<KC, true>(g, epi, st);
+  return launch_tile<KC, false>(g, epi, st);
+}
+
+// ---------------------------------------------------------- Tucker operator
+// Applies, to nbatch tensors in_b = in + b*in_stride, the Tucker operator with the
+// matrices L[mu] + b*l_stride[mu] (Section 2, eq. tucker), writing the last mode
+// through the epilogue into out (batch b at out + b*N).  ta/tb: nbatch*N scratch.
+// The result of mode mu (< d) goes to ta for odd mu and tb for even mu; out must be
+// the buffer not read by the last mode.
+template <class Epi>
+int tucker(const phiks_plan_s& P, const double* in, int64_t in_stride,
+           double* const* L, const int64_t* l_stride, int nbatch, double* out,
+           double* ta, double* tb, const Epi& epi, hipStream_t st) {
+  const int d = P.d;
+  const int64_t N = P.N;
+  const double* cur = in;
+  int64_t cur_stride = in_stride;
+  for (int mu = 1; mu <= d; ++mu) {
+    const int64_t nm = P.n[mu - 1];
+    int64_t nlo = 1, nhi = 1;
+    for (int k = 0; k < mu - 1; ++k) nlo *= P.n[k];
+    for (int k = mu; k < d; ++k) nhi *= P.n[k];
+    const bool last = (mu == d);
+    double* dst = last ? out : ((mu % 2 == 1) ? ta : tb);
+    GemmArgs g = empty_args();
+    g.nb1 = nbatch;
+    if (mu == 1) {
+      // W[m][i] = sum_j X[m][j] L[i][j], rows m < n_>
+      g.M = (int)nhi;
+      g.N = (int)nm;
+      g.K = (int)nm;
+      g.A = cur;
+      g.lda = nm;
+      g.B = L[0];
+      g.ldb = nm;
+      g.C = dst;
+      g.ldc = nm;
+      g.sA1 = cur_stride;
+      g.sB1 = l_stride[0];
+      g.sC1 = N;
+      if (last) RET_IF((launch_gemm<true>(g, epi, st)));
+      else RET_IF((launch_gemm<true>(g, EpiStore{1.0, 0.0}, st)));
+    } else {
+      // W_b[i][a] = sum_j L[i][j] X_b[j][a], batch b < n_>
+      g.M = (int)nm;
+      g.N = (int)nlo;
+      g.K = (int)nm;
+      g.A = L[mu - 1];
+      g.lda = nm;
+      g.B = cur;
+      g.ldb = nlo;
+      g.C = dst;
+      g.ldc = nlo;
+      g.nb0 = (int)nhi;
+      g.sA0 = 0;
+      g.sB0 = nm * nlo;
+      g.sC0 = nm * nlo;
+      g.sA1 = l_stride[mu - 1];
+      g.sB1 = cur_stride;
+      g.sC1 = N;
+      if (last) RET_IF((launch_gemm<false>(g, epi, st)));
+      else RET_IF((launch_gemm<false>(g, EpiStore{1.0, 0.0}, st)));
+    }
+    cur = dst;
+    cur_stride = N;
+  }
+  return PHIKS_OK;
+}
+
+}  // namespace

@@ -1,0 +1,191 @@
+// Mixed-precision mu-mode products: launches of gemm_f32_kernel (FP32 MFMA) and
+// gemm_bf16x3_kernel (three BF16 MFMA products per FP32 product), and the Tucker chain
+// over either.  Included once, by phiks.hip, after tucker_f64.hpp.
+#pragma once
+#include <vector>
+
+#include "gemm_bf16x3.hpp"
+#include "gemm_f32.hpp"
+#include "tucker_f64.hpp"
+
+namespace {
+
+using namespace phiks;
+
+// ------------------------------------------------- FP32 MFMA mu-mode launches
+bool vec4_ok(const GemmArgs& g, bool kcontig) {
+  if (g.K % 4 || g.lda % 4 || g.ldb % 4) return false;
+  if (!kcontig && g.N % 4) return false;
+  if (g.sA0 % 4 || g.sA1 % 4 || g.sB0 % 4 || g.sB1 % 4) return false;
+  return aligned16(g.A) && aligned16(g.B);
+}
+
+// One launch of a mixed-precision mu-mode kernel over the whole tile grid, with the
+// optional timing events of runtime.hpp.
+template <int BM, int BN, class Epi>
+int launch_grid(void (*kern)(GemmArgs, Epi), GemmArgs g, const Epi& epi, hipStream_t st) {
+  g.tiles_m = (g.M + BM - 1) / BM;
+  g.tiles_n = (g.N + BN - 1) / BN;
+  g.total_tiles = (int64_t)g.tiles_m * g.tiles_n * g.nb0 * g.nb1;
+  if (g.total_tiles <= 0) return PHIKS_OK;
+  if (g.total_tiles > 0x7fffffffLL) {
+    set_error("GEMM grid too large");
+    return PHIKS_EINVAL;
+  }
+  hipEvent_t ea = nullptr, eb = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_timing_mu);
+    if (g_timing) {
+      ea = pooled_event();
+      eb = pooled_event();
+      if (ea && eb) HIP_OK(hipEventRecord(ea, st));
+    }
+  }
+  (void)hipGetLastError();
+  hipLaunchKernelGGL(kern, dim3((unsigned)g.total_tiles), dim3(256), 0, st, g, epi);
+  CHECK_LAUNCH();
+  if (ea && eb) {
+    HIP_OK(hipEventRecord(eb, st));
+    std::lock_guard<std::mutex> lk(g_timing_mu);
+    g_timed.push_back({ea, eb, 2.0 * g.M * (double)g.N * g.K * g.nb0 * (double)g.nb1});
+  }
+  return PHIKS_OK;
+}
+
+template <int BM, int BN, int WM, int WN, bool KC, bool VEC, class TA, class TC, class Epi>
+int launch_cfg32(const GemmArgs& g, const Epi& epi, hipStream_t st) {
+  return launch_grid<BM, BN>(&gemm_f32_kernel<BM, BN, WM, WN, KC, VEC, TA, TC, Epi>, g, epi, st);
+}
+
+#ifndef PHIKS_F32_BIG_TILE
+#define PHIKS_F32_BIG_TILE 0  // 1: 128 x 128 tiles (4 waves of 64 x 64) where they fill the GPU
+#endif
+template <bool KC, bool VEC, class TA, class TC, class Epi>
+int launch_tile32(const GemmArgs& g, const Epi& epi, hipStream_t st) {
+#if PHIKS_F32_BIG_TILE == 1
+  if (g.M >= 128 && g.N >= 128 && tiles_for(g, 128, 128) >= 256)
+    return launch_cfg32<128, 128, 64, 64, KC, VEC, TA, TC>(g, epi, st);
+#endif
+  switch (pick_tile(g)) {
+    case Tile::T128x128:
+    case Tile::T128x64: return launch_cfg32<128, 64, 64, 32, KC, VEC, TA, TC>(g, epi, st);
+    case Tile::T64x128: return launch_cfg32<64, 128, 32, 64, KC, VEC, TA, TC>(g, epi, st);
+    case Tile::T64x64: return launch_cfg32<64, 64, 32, 32, KC, VEC, TA, TC>(g, epi, st);
+    default: return launch_cfg32<32, 32, 16, 16, KC, VEC, TA, TC>(g, epi, st);
+  }
+}
+
+template <bool KC, class TA, class TC, class Epi>
+int launch_gemm32(const GemmArgs& g, const Epi& epi, hipStream_t st) {
+  if (vec4_ok(g, KC)) return launch_tile32<KC, true, TA, TC>(g, epi, st);
+  return launch_tile32<KC, false, TA, TC>(g, epi, st);
+}
+// ---------------------------------------------- BF16x3 MFMA mu-mode launches
+template <int BM, int BN, int WM, int WN, bool KC, bool VEC, class TA, class TC, class Epi>
+int launch_cfg_bf(const GemmArgs& g, const Epi& epi, hipStream_t st) {
+  return launch_grid<BM, BN>(&gemm_bf16x3_kernel<BM, BN, WM, WN, KC, VEC, TA, TC, Epi>, g, epi,
+                             st);
+}
+
+// 16-byte loads need K, the leading dimensions of the k-contiguous operands and the
+// batch strides to be multiples of 4 floats, and 16-byte aligned bases.
+bool vec_bf_ok(const GemmArgs& g, bool kcontig) {
+  if (g.K % 4 || g.lda % 4 || (kcontig && g.ldb % 4)) return false;
+  if (g.sA0 % 4 || g.sA1 % 4 || g.sB0 % 4 || g.sB1 % 4) return false;
+  return aligned16(g.A) && aligned16(g.B);
+}
+
+#ifndef PHIKS_BF_BIG_TILE
+#define PHIKS_BF_BIG_TILE 1  // 1: 128 x 128 tiles (4 waves of 64 x 64) where they fill the GPU
+#endif
+// Products too small for a 64 x 64 tile per compute unit go to the FP32 kernel.
+template <bool KC, bool VEC, class TA, class TC, class Epi>
+int launch_tile_bf(const GemmArgs& g, const Epi& epi, hipStream_t st) {
+#if PHIKS_BF_BIG_TILE == 1
+  if (g.M >= 128 && g.N >= 128 && tiles_for(g, 128, 128) >= 256)
+    return launch_cfg_bf<128, 128, 64, 64, KC, VEC, TA, TC>(g, epi, st);
+#endif
+  switch (pick_tile(g)) {
+    case Tile::T128x128:
+    case Tile::T128x64: return launch_cfg_bf<128, 64, 64, 32, KC, VEC, TA, TC>(g, epi, st);
+    case Tile::T64x128: return launch_cfg_bf<64, 128, 32, 64, KC, VEC, TA, TC>(g, epi, st);
+    case Tile::T64x64: return launch_cfg_bf<64, 64, 32, 32, KC, VEC, TA, TC>(g, epi, st);
+    default: return launch_gemm32<KC, TA, TC>(g, epi, st);
+  }
+}
+
+template <bool KC, class TA, class TC, class Epi>
+int launch_gemm_bf(const GemmArgs& g, const Epi& epi, hipStream_t st) {
+  if (vec_bf_ok(g, KC)) return launch_tile_bf<KC, true, TA, TC>(g, epi, st);
+  return launch_tile_bf<KC, false, TA, TC>(g, epi, st);
+}
+
+// mu-mode launch in the arithmetic PREC (PHIKS_FP32 or PHIKS_BF16X3)
+template <int PREC, bool KC, class TA, class TC, class Epi>
+int launch_mixed(const GemmArgs& g, const Epi& epi, hipStream_t st) {
+  if constexpr (PREC == PHIKS_BF16X3) return launch_gemm_bf<KC, TA, TC>(g, epi, st);
+  else return launch_gemm32<KC, TA, TC>(g, epi, st);
+}
+
+// Mixed-precision Tucker operator (FP32 or BF16x3 products): the chain input (FP64)
+// is converted in the first mode, intermediate modes are FP32 (ta/tb hold floats), the
+// last mode writes FP64 through the same epilogue as the FP64 chain.  L[mu] are FP32
+// copies of the matrices.
+template <int PREC, class Epi>
+int tucker_mixed(const phiks_plan_s& P, const double* in, int64_t in_stride,
+             float* const* L, const int64_t* l_stride, int nbatch, double* out,
+             double* ta, double* tb, const Epi& epi, hipStream_t st) {
+  const int d = P.d;
+  const int64_t N = P.N;
+  const void* cur = in;
+  int64_t cur_stride = in_stride;
+  for (int mu = 1; mu <= d; ++mu) {
+    const int64_t nm = P.n[mu - 1];
+    int64_t nlo = 1, nhi = 1;
+    for (int k = 0; k < mu - 1; ++k) nlo *= P.n[k];
+    for (int k = mu; k < d; ++k) nhi *= P.n[k];
+    const bool last = (mu == d);
+    void* dst = last ? (void*)out : (void*)((mu % 2 == 1) ? ta : tb);
+    GemmArgs g = empty_args();
+    g.nb1 = nbatch;
+    if (mu == 1) {
+      g.M = (int)nhi;
+      g.N = (int)nm;
+      g.K = (int)nm;
+      g.A = reinterpret_cast<const double*>(cur);
+      g.lda = nm;
+      g.B = reinterpret_cast<const double*>(L[0]);
+      g.ldb = nm;
+      g.C = reinterpret_cast<double*>(dst);
+      g.ldc = nm;
+      g.sA1 = cur_stride;
+      g.sB1 = l_stride[0];
+      g.sC1 = N;
+      if (last) RET_IF((launch_mixed<PREC, true, double, double>(g, epi, st)));
+      else RET_IF((launch_mixed<PREC, true, double, float>(g, EpiStoreT<float>{1.0, 0.0}, st)));
+    } else {
+      g.M = (int)nm;
+      g.N = (int)nlo;
+      g.K = (int)nm;
+      g.A = reinterpret_cast<const double*>(L[mu - 1]);
+      g.lda = nm;
+      g.B = reinterpret_cast<const double*>(cur);
+      g.ldb = nlo;
+      g.C = reinterpret_cast<double*>(dst);
+      g.ldc = nlo;
+      g.nb0 = (int)nhi;
+      g.sB0 = nm * nlo;
+      g.sC0 = nm * nlo;
+      g.sA1 = l_stride[mu - 1];
+      g.sB1 = cur_stride;
+      g.sC1 = N;
+      if (last) RET_IF((launch_mixed<PREC, false, float, double>(g, epi, st)));
+      else RET_IF((launch_mixed<PREC, false, float, float>(g, EpiStoreT<float>{1.0, 0.0}, st)));
+    }
+    cur = dst;
+    cur_stride = N;
+  }
+  return PHIKS_OK;
+}
+
+}  // namespace

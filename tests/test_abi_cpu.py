@@ -130,6 +130,10 @@ def test_invalid_arguments_are_rejected():
         ph.phiks_plan_params(A, 1e-3, 2, 1, 1e-10, "lincomb", [1.0, -2.0, 1.0])
     assert e.value.status == ph.PHIKS_EINVAL
     assert ph.phiks_plan_params_raw(0, None, None, 1e-3, 1, 1, 1e-10, 0, None) == ph.PHIKS_EINVAL
+    # an unknown arithmetic is rejected before any device work
+    with pytest.raises(ph.PhiksError) as e:
+        ph.phiks_plan(A, 1e-3, 2, 1, 1e-10, precision=3)
+    assert e.value.status == ph.PHIKS_EINVAL
 
 
 def test_unreachable_tolerance_gives_enoplan():
