@@ -63,30 +63,60 @@ template <int G> __device__ __forceinline__ int swz_bf(int r) {
 }
 
 // Eight consecutive k (from gk) of row `row` of a k-contiguous operand with leading
-// dimension ld, as FP32; zero outside rows < rows, k < K.  VEC: two 16-byte loads
-// (K a multiple of 4, so that each four-k half is wholly inside or outside).
+// dimension ld.  load() only issues the loads (out-of-range parts read element 0 of
+// the operand); get() applies the zero fill and the conversion to FP32.  Keeping the
+// two apart lets the loads of the next K chunk stay in flight while the MFMAs of the
+// current one run.  VEC: 16-byte loads (K a multiple of 4, so that each four-k half
+// is wholly inside or outside).
 template <bool VEC, class T>
-__device__ __forceinline__ void load8_k(const T* __restrict__ P, int64_t ld, int row, int rows,
-                                        int gk, int K, float (&x)[8]) {
-  const bool rok = row < rows;
-  const int64_t base = rok ? (int64_t)row * ld : 0;
-  if constexpr (VEC) {
+struct Row8 {
+  static constexpr bool kF64 = std::is_same<T, double>::value;
+  typedef typename std::conditional<VEC, typename std::conditional<kF64, dbl2, flt4>::type, T>::type V;
+  static constexpr int kNV = VEC ? (kF64 ? 4 : 2) : 8;
+  V v[kNV];
+
+  __device__ __forceinline__ void load(const T* __restrict__ P, int64_t ld, int row, int rows,
+                                       int gk, int K) {
+    const bool rok = row < rows;
+    const int64_t base = rok ? (int64_t)row * ld : 0;
+    if constexpr (VEC) {
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const bool ok = rok && (gk + 4 * h < K);
-      const flt4 v = Vec4<T>::load(P + (ok ? base + gk + 4 * h : 0));
+      for (int h = 0; h < 2; ++h) {
+        const bool ok = rok && (gk + 4 * h < K);
+        const T* q = P + (ok ? base + gk + 4 * h : 0);
+        if constexpr (kF64) {
+          v[2 * h] = *reinterpret_cast<const dbl2*>(q);
+          v[2 * h + 1] = *reinterpret_cast<const dbl2*>(q + 2);
+        } else {
+          v[h] = *reinterpret_cast<const flt4*>(q);
+        }
+      }
+    } else {
 #pragma unroll
-      for (int t = 0; t < 4; ++t) x[4 * h + t] = ok ? v[t] : 0.f;
-    }
-  } else {
-#pragma unroll
-    for (int t = 0; t < 8; ++t) {
-      const bool ok = rok && (gk + t < K);
-      const float v = (float)P[ok ? base + gk + t : 0];
-      x[t] = ok ? v : 0.f;
+      for (int t = 0; t < 8; ++t) v[t] = P[(rok && gk + t < K) ? base + gk + t : 0];
     }
   }
-}
+
+  __device__ __forceinline__ void get(int row, int rows, int gk, int K, float (&x)[8]) const {
+    const bool rok = row < rows;
+    if constexpr (VEC) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const bool ok = rok && (gk + 4 * h < K);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          float e;
+          if constexpr (kF64) e = (float)v[2 * h + t / 2][t % 2];
+          else e = v[h][t];
+          x[4 * h + t] = ok ? e : 0.f;
+        }
+      }
+    } else {
+#pragma unroll
+      for (int t = 0; t < 8; ++t) x[t] = (rok && gk + t < K) ? (float)v[t] : 0.f;
+    }
+  }
+};
 
 // TA: element type of A in memory (FP64 for the first mode of a chain, else FP32); B is
 // FP32.  TC: element type of C.  VEC: 16-byte loads of the k-contiguous operands (K,
@@ -141,37 +171,38 @@ __global__ void __launch_bounds__(256, PHIKS_BF_MIN_WAVES) gemm_bf16x3_kernel(Ge
   const int wm = (wave / WGN) * WM;
   const int wn = (wave % WGN) * WN;
 
-  float ra[LA][8], rb[LB][8];
+  // raw operand registers of the next K chunk (see Row8)
+  Row8<VEC, TA> ra[LA];
+  typename std::conditional<B_KCONTIG, Row8<VEC, float>, Row8<false, float>>::type rb[LB];
   auto load_chunk = [&](int k0) {
 #pragma unroll
     for (int i = 0; i < LA; ++i) {
       const int e = tid + i * 256;
-      load8_k<VEC>(A, g.lda, m0 + e / G, g.M, k0 + 8 * (e % G), g.K, ra[i]);
+      ra[i].load(A, g.lda, m0 + e / G, g.M, k0 + 8 * (e % G), g.K);
     }
 #pragma unroll
     for (int i = 0; i < LB; ++i) {
       const int e = tid + i * 256;
       if constexpr (B_KCONTIG) {
-        load8_k<VEC>(B, g.ldb, n0 + e / G, g.N, k0 + 8 * (e % G), g.K, rb[i]);
+        rb[i].load(B, g.ldb, n0 + e / G, g.N, k0 + 8 * (e % G), g.K);
       } else {
         // column n of eight consecutive k rows; lanes take consecutive n (coalesced)
         const int gn = n0 + e % BN, gk = k0 + 8 * (e / BN);
 #pragma unroll
-        for (int t = 0; t < 8; ++t) {
-          const bool ok = (gn < g.N) && (gk + t < g.K);
-          const float v = B[ok ? (int64_t)(gk + t) * g.ldb + gn : 0];
-          rb[i][t] = ok ? v : 0.f;
-        }
+        for (int t = 0; t < 8; ++t)
+          rb[i].v[t] = B[(gn < g.N && gk + t < g.K) ? (int64_t)(gk + t) * g.ldb + gn : 0];
       }
     }
   };
-  auto store_chunk = [&](int buf) {
+  auto store_chunk = [&](int buf, int k0) {
 #pragma unroll
     for (int i = 0; i < LA; ++i) {
       const int e = tid + i * 256;
       const int r = e / G, c = (e % G) ^ swz_bf<G>(e / G);
+      float x[8];
+      ra[i].get(m0 + r, g.M, k0 + 8 * (e % G), g.K, x);
       u32x4 h, l;
-      split8(ra[i], h, l);
+      split8(x, h, l);
       Ah[buf][r][c] = h;
       Al[buf][r][c] = l;
     }
@@ -179,10 +210,20 @@ __global__ void __launch_bounds__(256, PHIKS_BF_MIN_WAVES) gemm_bf16x3_kernel(Ge
     for (int i = 0; i < LB; ++i) {
       const int e = tid + i * 256;
       int r, c;
-      if constexpr (B_KCONTIG) { r = e / G; c = (e % G) ^ swz_bf<G>(r); }
-      else { r = e % BN; c = (e / BN) ^ swz_bf<G>(r); }
+      float x[8];
+      if constexpr (B_KCONTIG) {
+        r = e / G;
+        c = (e % G) ^ swz_bf<G>(r);
+        rb[i].get(n0 + r, g.N, k0 + 8 * (e % G), g.K, x);
+      } else {
+        r = e % BN;
+        c = (e / BN) ^ swz_bf<G>(r);
+        const int gn = n0 + r, gk = k0 + 8 * (e / BN);
+#pragma unroll
+        for (int t = 0; t < 8; ++t) x[t] = (gn < g.N && gk + t < g.K) ? rb[i].v[t] : 0.f;
+      }
       u32x4 h, l;
-      split8(rb[i], h, l);
+      split8(x, h, l);
       Bh[buf][r][c] = h;
       Bl[buf][r][c] = l;
     }
@@ -196,7 +237,7 @@ __global__ void __launch_bounds__(256, PHIKS_BF_MIN_WAVES) gemm_bf16x3_kernel(Ge
 
   const int nchunks = (g.K + BK - 1) / BK;
   load_chunk(0);
-  store_chunk(0);
+  store_chunk(0, 0);
   __syncthreads();
   const int lr = lane & 15;
   const int lk = lane >> 4;
@@ -228,7 +269,7 @@ __global__ void __launch_bounds__(256, PHIKS_BF_MIN_WAVES) gemm_bf16x3_kernel(Ge
           acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
         }
     }
-    if (c + 1 < nchunks) store_chunk(buf ^ 1);
+    if (c + 1 < nchunks) store_chunk(buf ^ 1, (c + 1) * BK);
     __syncthreads();
   }
 

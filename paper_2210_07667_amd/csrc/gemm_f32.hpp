@@ -128,7 +128,7 @@ __device__ __forceinline__ void store_acc_tile(const flt4 (&acc)[FM][FN], const 
 #endif
 
 template <int BM, int BN, int WM, int WN, bool B_KCONTIG, bool VEC, class TA, class TC, class Epi>
-__global__ void __launch_bounds__(256, PHIKS_F32_MIN_WAVES) gemm_f32_kernel(GemmArgs g, Epi epi) {
+__global__ void __launch_bounds__(256, VEC ? PHIKS_F32_MIN_WAVES : 2) gemm_f32_kernel(GemmArgs g, Epi epi) {
   constexpr int BK = PHIKS_F32_BK;
   constexpr int WGM = BM / WM;
   constexpr int WGN = BN / WN;
@@ -174,22 +174,49 @@ __global__ void __launch_bounds__(256, PHIKS_F32_MIN_WAVES) gemm_f32_kernel(Gemm
   const int wm = (wave / WGN) * WM;
   const int wn = (wave % WGN) * WN;
 
-  vec_t ra[LA], rb[LB];
+  // Raw operand registers of the next K chunk: the loads only are issued here; the
+  // zero fill of out-of-range elements and the conversion of FP64 input happen when
+  // the registers are written to LDS, so the loads stay in flight while the MFMAs of
+  // the current chunk run.  Out-of-range elements read a clamped in-range address.
+  constexpr bool kA64 = std::is_same<TA, double>::value;
+  typedef typename std::conditional<VEC, typename std::conditional<kA64, dbl2, flt4>::type, TA>::type
+      rawa_t;
+  constexpr int kAV = (VEC && kA64) ? 2 : 1;  // raw registers per A load
+  rawa_t ra[LA][kAV];
+  vec_t rb[LB];
+  auto a_ok = [&](int e, int k0) {
+    const int m = e / (BK / VW), k = VW * (e % (BK / VW));
+    return (m0 + m < g.M) && (k0 + k < g.K);
+  };
+  auto b_ok = [&](int e, int k0) {
+    int n, k;
+    if constexpr (B_KCONTIG) { n = e / (BK / VW); k = VW * (e % (BK / VW)); }
+    else { k = e / (BN / VW); n = VW * (e % (BN / VW)); }
+    return (n0 + n < g.N) && (k0 + k < g.K);
+  };
+  static_assert(LA <= 32 && LB <= 32, "one mask bit per load");
+  // in-range bits of the loads in flight (the scalar-load variants keep them; the
+  // 16-byte ones recompute them, which costs fewer registers)
+  uint32_t amask = 0, bmask = 0;
+  auto a_in = [&](int i, int e, int k0) -> bool {
+    if constexpr (VEC) return a_ok(e, k0);
+    else return (amask >> i) & 1;
+  };
+  auto b_in = [&](int i, int e, int k0) -> bool {
+    if constexpr (VEC) return b_ok(e, k0);
+    else return (bmask >> i) & 1;
+  };
   auto load_chunk = [&](int k0) {
+    amask = bmask = 0;
 #pragma unroll
     for (int i = 0; i < LA; ++i) {
       const int e = tid + i * 256;
       const int m = e / (BK / VW), k = VW * (e % (BK / VW));
-      const int gm = m0 + m, gk = k0 + k;
-      const bool ok = (gm < g.M) && (gk < g.K);
-      const int64_t off = ok ? (int64_t)gm * g.lda + gk : 0;
-      if constexpr (VEC) {
-        const flt4 x = Vec4<TA>::load(A + off);
-        ra[i] = ok ? x : flt4{0.f, 0.f, 0.f, 0.f};
-      } else {
-        const float x = (float)A[off];
-        ra[i] = ok ? x : 0.f;
-      }
+      const bool ok = a_ok(e, k0);
+      if constexpr (!VEC) amask |= (uint32_t)ok << i;
+      const int64_t off = ok ? (int64_t)(m0 + m) * g.lda + k0 + k : 0;
+#pragma unroll
+      for (int h = 0; h < kAV; ++h) ra[i][h] = *reinterpret_cast<const rawa_t*>(A + off + 2 * h);
     }
 #pragma unroll
     for (int i = 0; i < LB; ++i) {
@@ -198,44 +225,54 @@ __global__ void __launch_bounds__(256, PHIKS_F32_MIN_WAVES) gemm_f32_kernel(Gemm
       if constexpr (B_KCONTIG) { n = e / (BK / VW); k = VW * (e % (BK / VW)); }
       else { k = e / (BN / VW); n = VW * (e % (BN / VW)); }
       const int gn = n0 + n, gk = k0 + k;
-      const bool ok = (gn < g.N) && (gk < g.K);
-      const int64_t off = ok ? (B_KCONTIG ? (int64_t)gn * g.ldb + gk : (int64_t)gk * g.ldb + gn) : 0;
-      if constexpr (VEC) {
-        const flt4 x = Vec4<float>::load(B + off);
-        rb[i] = ok ? x : flt4{0.f, 0.f, 0.f, 0.f};
-      } else {
-        const float x = B[off];
-        rb[i] = ok ? x : 0.f;
-      }
+      const bool ok = b_ok(e, k0);
+      if constexpr (!VEC) bmask |= (uint32_t)ok << i;
+      const int64_t off =
+          ok ? (B_KCONTIG ? (int64_t)gn * g.ldb + gk : (int64_t)gk * g.ldb + gn) : 0;
+      rb[i] = *reinterpret_cast<const vec_t*>(B + off);
     }
   };
-  auto store_chunk = [&](int buf) {
+  auto a_value = [&](int i, int e, int k0) -> vec_t {
+    const bool ok = a_in(i, e, k0);
+    if constexpr (VEC) {
+      flt4 x;
+      if constexpr (kA64) x = flt4{(float)ra[i][0][0], (float)ra[i][0][1], (float)ra[i][1][0], (float)ra[i][1][1]};
+      else x = ra[i][0];
+      return ok ? x : flt4{0.f, 0.f, 0.f, 0.f};
+    } else {
+      return ok ? (float)ra[i][0] : 0.f;
+    }
+  };
+  auto store_chunk = [&](int buf, int k0) {
 #pragma unroll
     for (int i = 0; i < LA; ++i) {
       const int e = tid + i * 256;
       const int m = e / (BK / VW), k = VW * (e % (BK / VW));
+      const vec_t x = a_value(i, e, k0);
       if constexpr (VEC) {
 #pragma unroll
-        for (int t = 0; t < 4; ++t) As[buf][k + t][m ^ swz32_t<BM>(k + t)] = ra[i][t];
+        for (int t = 0; t < 4; ++t) As[buf][k + t][m ^ swz32_t<BM>(k + t)] = x[t];
       } else {
-        As[buf][k][m ^ swz32_t<BM>(k)] = ra[i];
+        As[buf][k][m ^ swz32_t<BM>(k)] = x;
       }
     }
 #pragma unroll
     for (int i = 0; i < LB; ++i) {
       const int e = tid + i * 256;
+      vec_t x = rb[i];
+      if (!b_in(i, e, k0)) x = vec_t(0.f);
       if constexpr (B_KCONTIG) {
         const int n = e / (BK / VW), k = VW * (e % (BK / VW));
         if constexpr (VEC) {
 #pragma unroll
-          for (int t = 0; t < 4; ++t) Bs[buf][k + t][n ^ swz32_t<BN>(k + t)] = rb[i][t];
+          for (int t = 0; t < 4; ++t) Bs[buf][k + t][n ^ swz32_t<BN>(k + t)] = x[t];
         } else {
-          Bs[buf][k][n ^ swz32_t<BN>(k)] = rb[i];
+          Bs[buf][k][n ^ swz32_t<BN>(k)] = x;
         }
       } else {
         const int k = e / (BN / VW), n = VW * (e % (BN / VW));
-        if constexpr (VEC) *reinterpret_cast<flt4*>(&Bs[buf][k][n ^ swz32_n<BN>(k)]) = rb[i];
-        else Bs[buf][k][n ^ swz32_n<BN>(k)] = rb[i];
+        if constexpr (VEC) *reinterpret_cast<flt4*>(&Bs[buf][k][n ^ swz32_n<BN>(k)]) = x;
+        else Bs[buf][k][n ^ swz32_n<BN>(k)] = x;
       }
     }
   };
@@ -248,7 +285,7 @@ __global__ void __launch_bounds__(256, PHIKS_F32_MIN_WAVES) gemm_f32_kernel(Gemm
 
   const int nchunks = (g.K + BK - 1) / BK;
   load_chunk(0);
-  store_chunk(0);
+  store_chunk(0, 0);
   __syncthreads();
   const int lr = lane & 15;
   const int lk = lane >> 4;
@@ -272,7 +309,7 @@ __global__ void __launch_bounds__(256, PHIKS_F32_MIN_WAVES) gemm_f32_kernel(Gemm
         for (int j = 0; j < FN; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[i], fb[j], acc[i][j], 0, 0, 0);
     }
-    if (c + 1 < nchunks) store_chunk(buf ^ 1);
+    if (c + 1 < nchunks) store_chunk(buf ^ 1, (c + 1) * BK);
     __syncthreads();
   }
 

@@ -103,8 +103,11 @@ __device__ __forceinline__ int swz_n(int k) { return (k & 1) << 4; }
 #define PHIKS_GEMM_MIN_WAVES 3  // minimum waves per SIMD the register budget must allow
 #endif
 
-template <int BM, int BN, int WM, int WN, bool B_KCONTIG, bool VEC, class Epi>
-__global__ void __launch_bounds__(256, PHIKS_GEMM_MIN_WAVES) gemm_f64_kernel(GemmArgs g, Epi epi) {
+// PTRS: pointer-array batch (pA, pB, pC).  A separate instantiation, so that the
+// operands of the strided form stay provably global (global_load, which leaves the
+// LDS wait counter to the LDS reads) rather than generic pointers read from memory.
+template <int BM, int BN, int WM, int WN, bool B_KCONTIG, bool VEC, class Epi, bool PTRS = false>
+__global__ void __launch_bounds__(256, VEC ? PHIKS_GEMM_MIN_WAVES : 2) gemm_f64_kernel(GemmArgs g, Epi epi) {
   constexpr int BK = 16;
   constexpr int WGM = BM / WM;
   constexpr int WGN = BN / WN;
@@ -142,7 +145,7 @@ __global__ void __launch_bounds__(256, PHIKS_GEMM_MIN_WAVES) gemm_f64_kernel(Gem
   const double* __restrict__ B;
   double* Cb;
   int64_t cbase;
-  if (g.pA != nullptr) {
+  if constexpr (PTRS) {
     A = g.pA[z1];
     B = g.pB[z1];
     Cb = g.pC[z1];
@@ -164,19 +167,43 @@ __global__ void __launch_bounds__(256, PHIKS_GEMM_MIN_WAVES) gemm_f64_kernel(Gem
 
   // Loads: A and k-contiguous B read VW consecutive k of one row per load; an
   // n-contiguous B reads VW consecutive n of one k.  Out-of-range elements read a
-  // clamped in-range address and are replaced by zero (no branches).
+  // clamped in-range address; the zero fill is applied when the registers are
+  // written to LDS, so that the loads of the next K chunk stay in flight while the
+  // MFMAs of the current chunk run (no branches).
   typedef typename std::conditional<VEC, dbl2, double>::type vec_t;
   vec_t ra[LA], rb[LB];
+  auto a_ok = [&](int e, int k0) {
+    const int m = e / (BK / VW), k = VW * (e % (BK / VW));
+    return (m0 + m < g.M) && (k0 + k < g.K);
+  };
+  auto b_ok = [&](int e, int k0) {
+    int n, k;
+    if constexpr (B_KCONTIG) { n = e / (BK / VW); k = VW * (e % (BK / VW)); }
+    else { k = e / (BN / VW); n = VW * (e % (BN / VW)); }
+    return (n0 + n < g.N) && (k0 + k < g.K);
+  };
+  static_assert(LA <= 32 && LB <= 32, "one mask bit per load");
+  // in-range bits of the loads in flight (the scalar-load variants keep them; the
+  // 16-byte ones recompute them, which costs fewer registers)
+  uint32_t amask = 0, bmask = 0;
+  auto a_in = [&](int i, int e, int k0) -> bool {
+    if constexpr (VEC) return a_ok(e, k0);
+    else return (amask >> i) & 1;
+  };
+  auto b_in = [&](int i, int e, int k0) -> bool {
+    if constexpr (VEC) return b_ok(e, k0);
+    else return (bmask >> i) & 1;
+  };
   auto load_chunk = [&](int k0) {
+    amask = bmask = 0;
 #pragma unroll
     for (int i = 0; i < LA; ++i) {
       const int e = tid + i * 256;
       const int m = e / (BK / VW), k = VW * (e % (BK / VW));
-      const int gm = m0 + m, gk = k0 + k;
-      const bool ok = (gm < g.M) && (gk < g.K);
-      const int64_t off = ok ? (int64_t)gm * g.lda + gk : 0;
-      const vec_t x = *reinterpret_cast<const vec_t*>(A + off);
-      ra[i] = ok ? x : vec_t(0.0);
+      const bool ok = a_ok(e, k0);
+      if constexpr (!VEC) amask |= (uint32_t)ok << i;
+      const int64_t off = ok ? (int64_t)(m0 + m) * g.lda + k0 + k : 0;
+      ra[i] = *reinterpret_cast<const vec_t*>(A + off);
     }
 #pragma unroll
     for (int i = 0; i < LB; ++i) {
@@ -185,39 +212,42 @@ __global__ void __launch_bounds__(256, PHIKS_GEMM_MIN_WAVES) gemm_f64_kernel(Gem
       if constexpr (B_KCONTIG) { n = e / (BK / VW); k = VW * (e % (BK / VW)); }
       else { k = e / (BN / VW); n = VW * (e % (BN / VW)); }
       const int gn = n0 + n, gk = k0 + k;
-      const bool ok = (gn < g.N) && (gk < g.K);
-      const int64_t off = ok ? (B_KCONTIG ? (int64_t)gn * g.ldb + gk : (int64_t)gk * g.ldb + gn) : 0;
-      const vec_t x = *reinterpret_cast<const vec_t*>(B + off);
-      rb[i] = ok ? x : vec_t(0.0);
+      const bool ok = b_ok(e, k0);
+      if constexpr (!VEC) bmask |= (uint32_t)ok << i;
+      const int64_t off =
+          ok ? (B_KCONTIG ? (int64_t)gn * g.ldb + gk : (int64_t)gk * g.ldb + gn) : 0;
+      rb[i] = *reinterpret_cast<const vec_t*>(B + off);
     }
   };
-  auto store_chunk = [&](int buf) {
+  auto store_chunk = [&](int buf, int k0) {
 #pragma unroll
     for (int i = 0; i < LA; ++i) {
       const int e = tid + i * 256;
       const int m = e / (BK / VW), k = VW * (e % (BK / VW));
+      const vec_t x = a_in(i, e, k0) ? ra[i] : vec_t(0.0);
       if constexpr (VEC) {
-        As[buf][k][m ^ swz_t(k)] = ra[i][0];
-        As[buf][k + 1][m ^ swz_t(k + 1)] = ra[i][1];
+        As[buf][k][m ^ swz_t(k)] = x[0];
+        As[buf][k + 1][m ^ swz_t(k + 1)] = x[1];
       } else {
-        As[buf][k][m ^ swz_t(k)] = ra[i];
+        As[buf][k][m ^ swz_t(k)] = x;
       }
     }
 #pragma unroll
     for (int i = 0; i < LB; ++i) {
       const int e = tid + i * 256;
+      const vec_t x = b_in(i, e, k0) ? rb[i] : vec_t(0.0);
       if constexpr (B_KCONTIG) {
         const int n = e / (BK / VW), k = VW * (e % (BK / VW));
         if constexpr (VEC) {
-          Bs[buf][k][n ^ swz_t(k)] = rb[i][0];
-          Bs[buf][k + 1][n ^ swz_t(k + 1)] = rb[i][1];
+          Bs[buf][k][n ^ swz_t(k)] = x[0];
+          Bs[buf][k + 1][n ^ swz_t(k + 1)] = x[1];
         } else {
-          Bs[buf][k][n ^ swz_t(k)] = rb[i];
+          Bs[buf][k][n ^ swz_t(k)] = x;
         }
       } else {
         const int k = e / (BN / VW), n = VW * (e % (BN / VW));
-        if constexpr (VEC) *reinterpret_cast<dbl2*>(&Bs[buf][k][n ^ swz_n(k)]) = rb[i];
-        else Bs[buf][k][n ^ swz_n(k)] = rb[i];
+        if constexpr (VEC) *reinterpret_cast<dbl2*>(&Bs[buf][k][n ^ swz_n(k)]) = x;
+        else Bs[buf][k][n ^ swz_n(k)] = x;
       }
     }
   };
@@ -230,7 +260,7 @@ __global__ void __launch_bounds__(256, PHIKS_GEMM_MIN_WAVES) gemm_f64_kernel(Gem
 
   const int nchunks = (g.K + BK - 1) / BK;
   load_chunk(0);
-  store_chunk(0);
+  store_chunk(0, 0);
   __syncthreads();
   const int lr = lane & 15;
   const int lk = lane >> 4;
@@ -254,7 +284,7 @@ __global__ void __launch_bounds__(256, PHIKS_GEMM_MIN_WAVES) gemm_f64_kernel(Gem
         for (int j = 0; j < FN; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[i], fb[j], acc[i][j], 0, 0, 0);
     }
-    if (c + 1 < nchunks) store_chunk(buf ^ 1);
+    if (c + 1 < nchunks) store_chunk(buf ^ 1, (c + 1) * BK);
     __syncthreads();
   }
 

@@ -3,6 +3,7 @@
 // phiks.hip, after runtime.hpp and plan.hpp.
 #pragma once
 #include <algorithm>
+#include <type_traits>
 #include <vector>
 
 #include "gemm_f64.hpp"
@@ -50,7 +51,7 @@ bool vec_ok(const GemmArgs& g, bool kcontig, const std::vector<const void*>& ext
   return true;
 }
 
-template <int BM, int BN, int WM, int WN, bool KC, bool VEC, class Epi>
+template <int BM, int BN, int WM, int WN, bool KC, bool VEC, bool PTRS, class Epi>
 int launch_cfg(GemmArgs g, const Epi& epi, hipStream_t st) {
   g.tiles_m = (g.M + BM - 1) / BM;
   g.tiles_n = (g.N + BN - 1) / BN;
@@ -70,7 +71,7 @@ int launch_cfg(GemmArgs g, const Epi& epi, hipStream_t st) {
     }
   }
   (void)hipGetLastError();  // clear a stale error left by an unrelated earlier call
-  hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, WM, WN, KC, VEC, Epi>),
+  hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, WM, WN, KC, VEC, Epi, PTRS>),
                      dim3((unsigned)g.total_tiles), dim3(256), 0, st, g, epi);
   CHECK_LAUNCH();
   if (ea && eb) {
@@ -81,28 +82,38 @@ int launch_cfg(GemmArgs g, const Epi& epi, hipStream_t st) {
   return PHIKS_OK;
 }
 
-template <bool KC, bool VEC, class Epi>
+template <bool KC, bool VEC, bool PTRS, class Epi>
 int launch_tile(const GemmArgs& g, const Epi& epi, hipStream_t st) {
   switch (pick_tile(g)) {
 #if PHIKS_BIG_TILE == 1
-    case Tile::T128x128: return launch_cfg<128, 128, 64, 64, KC, VEC>(g, epi, st);
+    case Tile::T128x128: return launch_cfg<128, 128, 64, 64, KC, VEC, PTRS>(g, epi, st);
 #endif
-    case Tile::T128x64: return launch_cfg<128, 64, 64, 32, KC, VEC>(g, epi, st);
-    case Tile::T64x128: return launch_cfg<64, 128, 32, 64, KC, VEC>(g, epi, st);
-    case Tile::T64x64: return launch_cfg<64, 64, 32, 32, KC, VEC>(g, epi, st);
-    default: return launch_cfg<32, 32, 16, 16, KC, VEC>(g, epi, st);
+    case Tile::T128x64: return launch_cfg<128, 64, 64, 32, KC, VEC, PTRS>(g, epi, st);
+    case Tile::T64x128: return launch_cfg<64, 128, 32, 64, KC, VEC, PTRS>(g, epi, st);
+    case Tile::T64x64: return launch_cfg<64, 64, 32, 32, KC, VEC, PTRS>(g, epi, st);
+    default: return launch_cfg<32, 32, 16, 16, KC, VEC, PTRS>(g, epi, st);
   }
 }
 
+// Pointer-array GEMMs (pA != nullptr) exist only in the n-contiguous form with a
+// plain store (the batched products of the small exponentials).
 template <bool KC, class Epi>
 int launch_gemm(const GemmArgs& g, const Epi& epi, hipStream_t st,
                 const std::vector<const void*>& extra_ptrs = {}) {
-  if (g.pA != nullptr && g.nb0 != 1) {
-    set_error("pointer-array GEMM needs nb0 == 1");
-    return PHIKS_EINVAL;
+  const bool vec = vec_ok(g, KC, extra_ptrs);
+  if (g.pA != nullptr) {
+    if constexpr (!KC && std::is_same<Epi, EpiStore>::value) {
+      if (g.nb0 != 1) {
+        set_error("pointer-array GEMM needs nb0 == 1");
+        return PHIKS_EINVAL;
+      }
+      return vec ? launch_tile<KC, true, true>(g, epi, st) : launch_tile<KC, false, true>(g, epi, st);
+    } else {
+      set_error("pointer-array GEMM needs the n-contiguous form and a plain store");
+      return PHIKS_EINVAL;
+    }
   }
-  if (vec_ok(g, KC, extra_ptrs)) return launch_tile<KC, true>(g, epi, st);
-  return launch_tile<KC, false>(g, epi, st);
+  return vec ? launch_tile<KC, true, false>(g, epi, st) : launch_tile<KC, false, false>(g, epi, st);
 }
 
 // ---------------------------------------------------------- Tucker operator
