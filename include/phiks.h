@@ -80,7 +80,7 @@ enum { PHIKS_FP64 = 0, PHIKS_FP32 = 1, PHIKS_BF16X3 = 2 };
  *   combination:  sum_{k<=l} b_{q,l-k+1}(s) ||v_{p+1-k}||_2 / 2^((l-k+1)s) <= tol
  * and stop before the first s whose Tucker count (eq. Tpsv: q + s p + n_scales;
  * eq. Tlcp: q p + s p + n_scales) is strictly larger than the previous one.
- * Then, on the device, the Pade [m/m] scaling-and-squaring exponentials
+ * Then, on the device, the scaling-and-squaring exponentials (degree-24 Taylor)
  * exp((1 - theta_i) tau A_mu / 2^s) for every Gauss-Lobatto node theta_i < 1 and
  * exp(tau A_mu / 2^j) for j = s..0 (by squaring, Section 3.1) are computed.
  *

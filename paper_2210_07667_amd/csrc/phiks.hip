@@ -1,7 +1,7 @@
 // Runtime and C ABI of the phiks library for MI355X (gfx950).
 //
 // phiks_plan:    host planning (planner.cpp), then the small exponentials on the
-//                device: Pade [m/m] with scaling and squaring for every node matrix
+//                device: degree-24 Taylor with scaling and squaring for every node matrix
 //                exp((1-theta_i) tau A_mu / 2^s), and exp(tau A_mu / 2^j) for j = s..0
 //                by squaring (Section 3.1).
 // phiks_apply:   same vector, eqs. integrandsimul / simul.
@@ -93,27 +93,13 @@ double factorial(int k) {
   return f;
 }
 
-// ----------------------------------------------------------- Pade parameters
-// Backward-error thresholds theta_m for the [m/m] Pade approximant in double
-// precision and the degree selection of Higham, "The scaling and squaring method
-// for the matrix exponential revisited" (SIAM J. Matrix Anal. Appl. 2005), which is
-// the method the paper's expm follows.
-const int kPadeM[5] = {3, 5, 7, 9, 13};
-const double kPadeTheta[5] = {1.495585217958292e-2, 2.539398330063230e-1,
-                              9.504178996162932e-1, 2.097847961257068e0,
-                              5.371920351148152e0};
-
-// b_j = (2m - j)! m! / ((2m)! j! (m - j)!)
-void pade_coefs(int m, double* b) {
-  for (int j = 0; j <= m; ++j) {
-    long double v = 1.0L;
-    // (2m-j)!/(2m)! * m!/(m-j)! / j!
-    for (int k = 2 * m - j + 1; k <= 2 * m; ++k) v /= k;
-    for (int k = m - j + 1; k <= m; ++k) v *= k;
-    for (int k = 2; k <= j; ++k) v /= k;
-    b[j] = (double)v;
-  }
-}
+// ------------------------------------------------- small matrix exponentials
+// exp(c B) for the node matrices and exp(B / 2^s), B = tau A_mu shifted by
+// sigma_mu I (Section 3.1 notes the shift leaves the method unchanged): scaling and
+// squaring around a degree-24 Taylor polynomial.  For ||X||_1 <= 2 its truncation
+// error is below 2^25 / 25! = 2.2e-18, under 2^-53 of ||exp(X)|| >= e^-2.
+const double kTaylorTheta = 2.0;
+const int kTaylorDegree = 24;
 
 struct ExpmRequest {
   int mu;          // mode
@@ -121,53 +107,49 @@ struct ExpmRequest {
   double* dst;     // n^2 destination
 };
 
-// Computes exp(c_r B_{mu_r}) for every request on the device.
+// Computes exp(c_r B_{mu_r}) for every request on the device.  Bshift[mu] is the
+// shifted operator B_mu - sigma_mu I (row-major), norm1[mu] its 1-norm.
 int batched_expm(phiks_plan_s& P, const std::vector<std::vector<double>>& Bshift,
                  const double* sigma, const double* norm1,
                  const std::vector<ExpmRequest>& reqs, hipStream_t st) {
   const int d = P.d;
   if (reqs.empty()) return PHIKS_OK;
-  // degree and scaling per request
-  struct Sel { int m; int t; double gamma; };
-  std::vector<Sel> sel(reqs.size());
-  int max_nk[PHIKS_MAX_D] = {0};
+  // Bh = Bshift / beta with beta a power of two >= ||Bshift||_1 (an exact scaling)
+  double beta[PHIKS_MAX_D];
+  for (int mu = 0; mu < d; ++mu)
+    beta[mu] = norm1[mu] > 0.0 ? std::ldexp(1.0, (int)std::ceil(std::log2(norm1[mu]))) : 1.0;
+  // squarings t_r and polynomial argument X_r = g_r Bh with ||X_r||_1 <= theta
+  std::vector<int> tsq(reqs.size());
+  std::vector<double> gam(reqs.size());
   for (size_t r = 0; r < reqs.size(); ++r) {
-    const double x = std::fabs(reqs[r].c) * norm1[reqs[r].mu];
-    Sel s{13, 0, reqs[r].c};
-    bool done = false;
-    for (int k = 0; k < 4 && !done; ++k)
-      if (x <= kPadeTheta[k]) { s.m = kPadeM[k]; done = true; }
-    if (!done) {
-      s.m = 13;
-      s.t = (x > kPadeTheta[4]) ? (int)std::ceil(std::log2(x / kPadeTheta[4])) : 0;
-      if (s.t < 0) s.t = 0;
-      s.gamma = reqs[r].c / std::ldexp(1.0, s.t);
-    }
-    sel[r] = s;
-    max_nk[reqs[r].mu] = std::max(max_nk[reqs[r].mu], (s.m - 1) / 2);
+    const int mu = reqs[r].mu;
+    const double x = std::fabs(reqs[r].c) * norm1[mu];
+    int t = (x > kTaylorTheta) ? (int)std::ceil(std::log2(x / kTaylorTheta)) : 0;
+    tsq[r] = std::max(t, 0);
+    gam[r] = reqs[r].c * beta[mu] / std::ldexp(1.0, tsq[r]);
   }
-  // scratch: per mode Bs + 6 powers; per request SU, V, U, Q, X, T
+  // scratch: per mode Bh^1..Bh^5; per request D_0..D_4 and one squaring buffer
   size_t total = 0;
   std::vector<size_t> mode_off(d), req_off(reqs.size());
-  for (int mu = 0; mu < d; ++mu) { mode_off[mu] = total; total += 7 * sq(P.n[mu]); }
-  for (size_t r = 0; r < reqs.size(); ++r) { req_off[r] = total; total += 6 * sq(P.n[reqs[r].mu]); }
+  for (int mu = 0; mu < d; ++mu) { mode_off[mu] = total; total += kTaylorBlocks * sq(P.n[mu]); }
+  for (size_t r = 0; r < reqs.size(); ++r) {
+    req_off[r] = total;
+    total += (kTaylorBlocks + 1) * sq(P.n[reqs[r].mu]);
+  }
   double* scratch = nullptr;
   HIP_OK(hipMallocAsync((void**)&scratch, total * sizeof(double), st));
-  auto bs_ptr = [&](int mu) { return scratch + mode_off[mu]; };
-  auto pw_ptr = [&](int mu, int k) { return scratch + mode_off[mu] + (size_t)k * sq(P.n[mu]); };
+  auto pw_ptr = [&](int mu, int k) {  // Bh^k, k = 1..5
+    return scratch + mode_off[mu] + (size_t)(k - 1) * sq(P.n[mu]);
+  };
+  auto d_ptr = [&](size_t r, int i) { return scratch + req_off[r] + (size_t)i * sq(P.n[reqs[r].mu]); };
   for (int mu = 0; mu < d; ++mu) {
     P.host_keep.emplace_back(sizeof(double) * Bshift[mu].size());
-    std::memcpy(P.host_keep.back().data(), Bshift[mu].data(), P.host_keep.back().size());
-    HIP_OK(hipMemcpyAsync(bs_ptr(mu), P.host_keep.back().data(), P.host_keep.back().size(),
-                          hipMemcpyHostToDevice, st));
+    double* h = (double*)P.host_keep.back().data();
+    for (size_t e = 0; e < Bshift[mu].size(); ++e) h[e] = Bshift[mu][e] / beta[mu];
+    HIP_OK(hipMemcpyAsync(pw_ptr(mu, 1), h, P.host_keep.back().size(), hipMemcpyHostToDevice, st));
   }
-  // even powers Bs^2 .. Bs^(2 nk) per mode: P2 = Bs Bs, P(2k) = P(2k-2) P2
-  int kmax = 0;
-  for (int mu = 0; mu < d; ++mu) kmax = std::max(kmax, max_nk[mu]);
-  std::vector<const double*> hA, hB;
-  std::vector<double*> hC;
   auto run_ptr_gemm = [&](std::vector<const double*>& a, std::vector<const double*>& b,
-                          std::vector<double*>& c, int n) -> int {
+                          std::vector<double*>& c, int n, double beta_c) -> int {
     if (a.empty()) return PHIKS_OK;
     const size_t nb = a.size();
     P.host_keep.emplace_back(3 * nb * sizeof(void*));
@@ -191,94 +173,79 @@ int batched_expm(phiks_plan_s& P, const std::vector<std::vector<double>>& Bshift
     for (size_t i = 0; i < nb; ++i) {
       ptrs.push_back(a[i]);
       ptrs.push_back(b[i]);
+      ptrs.push_back(c[i]);
     }
-    int rc = launch_gemm<false>(g, EpiStore{1.0, 0.0}, st, ptrs);
+    int rc = launch_gemm<false>(g, EpiStore{1.0, beta_c}, st, ptrs);
     HIP_OK(hipFreeAsync(dp, st));
     return rc;
   };
-  // group modes by size for the pointer-array GEMMs
+  // modes grouped by size for the pointer-array GEMMs
   std::vector<int64_t> sizes;
   for (int mu = 0; mu < d; ++mu)
     if (std::find(sizes.begin(), sizes.end(), P.n[mu]) == sizes.end()) sizes.push_back(P.n[mu]);
-  for (int k = 1; k <= kmax; ++k) {
+  // shared powers Bh^k = Bh^(k-1) Bh, k = 2..5
+  for (int k = 2; k <= kTaylorBlocks; ++k) {
     for (int64_t nsz : sizes) {
       std::vector<const double*> a, b;
       std::vector<double*> c;
       for (int mu = 0; mu < d; ++mu) {
-        if (P.n[mu] != nsz || max_nk[mu] < k) continue;
-        if (k == 1) { a.push_back(bs_ptr(mu)); b.push_back(bs_ptr(mu)); }
-        else { a.push_back(pw_ptr(mu, k - 1)); b.push_back(pw_ptr(mu, 1)); }
+        if (P.n[mu] != nsz) continue;
+        a.push_back(pw_ptr(mu, k - 1));
+        b.push_back(pw_ptr(mu, 1));
         c.push_back(pw_ptr(mu, k));
       }
-      RET_IF(run_ptr_gemm(a, b, c, (int)nsz));
+      RET_IF(run_ptr_gemm(a, b, c, (int)nsz, 0.0));
     }
   }
-  // jobs
-  std::vector<ExpmJob> jobs(reqs.size());
+  // D_i of every request
+  std::vector<TaylorJob> jobs(reqs.size());
   for (size_t r = 0; r < reqs.size(); ++r) {
     const int mu = reqs[r].mu;
-    const int64_t nn = sq(P.n[mu]);
-    ExpmJob& J = jobs[r];
+    TaylorJob& J = jobs[r];
     std::memset(&J, 0, sizeof(J));
-    const Sel& s = sel[r];
-    double b[14];
-    pade_coefs(s.m, b);
-    J.nk = (s.m - 1) / 2;
     J.n = (int)P.n[mu];
-    for (int k = 1; k <= J.nk; ++k) J.pw[k] = pw_ptr(mu, k);
-    double g2k = 1.0;  // gamma^(2k)
-    for (int k = 0; k <= J.nk; ++k) {
-      J.cv[k] = b[2 * k] * g2k;
-      J.cu[k] = b[2 * k + 1] * g2k * s.gamma;
-      g2k *= s.gamma * s.gamma;
+    for (int k = 1; k < kTaylorBlocks; ++k) J.pw[k] = pw_ptr(mu, k);
+    double gk = 1.0;  // g^j / j!
+    for (int j = 0; j <= kTaylorDegree; ++j) {
+      J.coef[j / kTaylorBlocks][j % kTaylorBlocks] = gk;
+      gk *= gam[r] / (j + 1);
     }
-    double* base = scratch + req_off[r];
-    J.SU = base;
-    J.V = base + nn;
-    J.U = base + 2 * nn;
-    J.Q = base + 3 * nn;
-    J.X = base + 4 * nn;
+    for (int i = 0; i < kTaylorBlocks; ++i) J.D[i] = d_ptr(r, i);
   }
-  P.host_keep.emplace_back(jobs.size() * sizeof(ExpmJob));
+  P.host_keep.emplace_back(jobs.size() * sizeof(TaylorJob));
   std::memcpy(P.host_keep.back().data(), jobs.data(), P.host_keep.back().size());
-  ExpmJob* djobs = nullptr;
-  HIP_OK(hipMallocAsync((void**)&djobs, jobs.size() * sizeof(ExpmJob), st));
-  HIP_OK(hipMemcpyAsync(djobs, P.host_keep.back().data(), jobs.size() * sizeof(ExpmJob),
+  TaylorJob* djobs = nullptr;
+  HIP_OK(hipMallocAsync((void**)&djobs, jobs.size() * sizeof(TaylorJob), st));
+  HIP_OK(hipMemcpyAsync(djobs, P.host_keep.back().data(), jobs.size() * sizeof(TaylorJob),
                         hipMemcpyHostToDevice, st));
   int64_t nmax = 0;
   for (int mu = 0; mu < d; ++mu) nmax = std::max(nmax, P.n[mu]);
   const unsigned eblocks = (unsigned)std::min<int64_t>((sq(nmax) + 255) / 256, 1024);
   (void)hipGetLastError();
-  hipLaunchKernelGGL(expm_form_kernel, dim3(eblocks, (unsigned)jobs.size()), dim3(256), 0, st,
+  hipLaunchKernelGGL(taylor_form_kernel, dim3(eblocks, (unsigned)jobs.size()), dim3(256), 0, st,
                      djobs);
   CHECK_LAUNCH();
-  // U = Bs * SU
-  for (int64_t nsz : sizes) {
-    std::vector<const double*> a, b;
-    std::vector<double*> c;
-    for (size_t r = 0; r < reqs.size(); ++r) {
-      if (P.n[reqs[r].mu] != nsz) continue;
-      a.push_back(bs_ptr(reqs[r].mu));
-      b.push_back(jobs[r].SU);
-      c.push_back(jobs[r].U);
+  // Horner in S = Bh^5: D_i <- D_(i+1) S + D_i, i = 3..0; D_0 then holds T(X)
+  for (int i = kTaylorBlocks - 2; i >= 0; --i) {
+    for (int64_t nsz : sizes) {
+      std::vector<const double*> a, b;
+      std::vector<double*> c;
+      for (size_t r = 0; r < reqs.size(); ++r) {
+        if (P.n[reqs[r].mu] != nsz) continue;
+        a.push_back(d_ptr(r, i + 1));
+        b.push_back(pw_ptr(reqs[r].mu, kTaylorBlocks));
+        c.push_back(d_ptr(r, i));
+      }
+      RET_IF(run_ptr_gemm(a, b, c, (int)nsz, 1.0));
     }
-    RET_IF(run_ptr_gemm(a, b, c, (int)nsz));
   }
-  (void)hipGetLastError();
-  hipLaunchKernelGGL(expm_qx_kernel, dim3(eblocks, (unsigned)jobs.size()), dim3(256), 0, st,
-                     djobs);
-  CHECK_LAUNCH();
-  (void)hipGetLastError();
-  hipLaunchKernelGGL(lu_solve_kernel, dim3((unsigned)jobs.size()), dim3(kSolveThreads), 0, st,
-                     djobs);
-  CHECK_LAUNCH();
-  // squarings: X <- X^2 (ping-pong through the T buffer)
+  // squarings: X <- X^2 (ping-pong through the request's last buffer)
   std::vector<double*> curp(reqs.size()), othp(reqs.size());
   int tmax = 0;
   for (size_t r = 0; r < reqs.size(); ++r) {
-    curp[r] = jobs[r].X;
-    othp[r] = scratch + req_off[r] + 5 * sq(P.n[reqs[r].mu]);
-    tmax = std::max(tmax, sel[r].t);
+    curp[r] = d_ptr(r, 0);
+    othp[r] = d_ptr(r, kTaylorBlocks);
+    tmax = std::max(tmax, tsq[r]);
   }
   for (int t = 0; t < tmax; ++t) {
     for (int64_t nsz : sizes) {
@@ -286,13 +253,13 @@ int batched_expm(phiks_plan_s& P, const std::vector<std::vector<double>>& Bshift
       std::vector<double*> c;
       std::vector<size_t> idx;
       for (size_t r = 0; r < reqs.size(); ++r) {
-        if (P.n[reqs[r].mu] != nsz || sel[r].t <= t) continue;
+        if (P.n[reqs[r].mu] != nsz || tsq[r] <= t) continue;
         a.push_back(curp[r]);
         b.push_back(curp[r]);
         c.push_back(othp[r]);
         idx.push_back(r);
       }
-      RET_IF(run_ptr_gemm(a, b, c, (int)nsz));
+      RET_IF(run_ptr_gemm(a, b, c, (int)nsz, 0.0));
       for (size_t r : idx) std::swap(curp[r], othp[r]);
     }
   }
@@ -503,7 +470,7 @@ int phiks_plan(int d, const int64_t* n, const double* const* A, double tau, int 
   }
   (void)total64;
   // shifted operators B_mu - sigma_mu I, sigma_mu = tr(B_mu)/n_mu (the shift remark
-  // of Section 3.1), and their 1-norms for the Pade degree choice
+  // of Section 3.1), and their 1-norms for the scaling choice
   std::vector<std::vector<double>> Bs(d);
   double sigma[PHIKS_MAX_D], norm1[PHIKS_MAX_D];
   for (int mu = 0; mu < d; ++mu) {
