@@ -180,6 +180,41 @@ int phiks_kernel_timing(int enable);
 int phiks_kernel_timing_read(double* total_ms, int64_t* launches, double* flops);
 
 /*
+ * Batches of independent problems (same-vector task, eqs. integrandsimul / simul with
+ * the outputs of eq. scaldiffphi): many small problems of different shapes whose
+ * separate calls would each be too small to fill the GPU.
+ *
+ * phiks_batch_plan -- plan `count` problems at once.  Problem i has d[i] modes of
+ * sizes n[i][0..d[i]-1], host matrices A[i][mu] (row-major, copied) and step tau[i];
+ * p, n_scales, tol and precision are shared.  vnorms: host array of count values
+ * ||v_i||_2, or NULL (norms 1).  Each problem gets exactly the (s, q) phiks_plan would
+ * choose for it; the small exponentials of all problems are built in one device pass.
+ * precision must be PHIKS_FP64.  Errors as phiks_plan; a failing problem is named in
+ * phiks_last_error().
+ *
+ * phiks_batch_apply -- v: host array of count device pointers (N_i doubles each);
+ * out: host array of count device pointers, out[i] laid out as phiks_apply's out for
+ * problem i.  ws: device workspace of phiks_batch_workspace_size bytes, 16-byte
+ * aligned.  Every out[i] is bitwise what phiks_apply returns for problem i alone.
+ * Stream-ordered; calls on one batch must not overlap (they share its launch tables,
+ * and a call waits on the host until the previous call's table upload has run).
+ */
+typedef struct phiks_batch_s* phiks_batch_t;
+
+int phiks_batch_plan(int count, const int* d, const int64_t* const* n,
+                     const double* const* const* A, const double* tau, int p, int n_scales,
+                     double tol, const double* vnorms, int precision, void* hip_stream,
+                     phiks_batch_t* out);
+int phiks_batch_apply(phiks_batch_t batch, const double* const* v, double* const* out,
+                      void* ws, size_t ws_bytes, void* hip_stream);
+int phiks_batch_workspace_size(phiks_batch_t batch, size_t* bytes);
+/* (s, q, T# of eq. Tpsv, Tucker operators executed) of problem i. */
+int phiks_batch_info(phiks_batch_t batch, int i, int* s, int* q, int* tucker_paper,
+                     int* tucker_exec);
+/* Stream-ordered release, as phiks_plan_destroy. */
+void phiks_batch_destroy(phiks_batch_t batch);
+
+/*
  * Device-memory plumbing for callers without their own allocator (the Python
  * binding and the tests use these, so that one HIP runtime -- the one this library
  * was built against -- serves the whole process).  Copies are synchronous.

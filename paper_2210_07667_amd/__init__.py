@@ -42,7 +42,9 @@ SYMBOLS = ("phiks_plan", "phiks_apply", "phiks_combine", "phiks_workspace_size",
            "phiks_remainder", "phiks_tucker", "phiks_kernel_timing",
            "phiks_kernel_timing_read", "phiks_device_count", "phiks_device_alloc",
            "phiks_device_free", "phiks_memcpy_htod", "phiks_memcpy_dtoh",
-           "phiks_device_synchronize", "phiks_memcpy_dtod")
+           "phiks_device_synchronize", "phiks_memcpy_dtod", "phiks_batch_plan",
+           "phiks_batch_apply", "phiks_batch_workspace_size", "phiks_batch_info",
+           "phiks_batch_destroy")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with "
@@ -91,6 +93,20 @@ _lib.phiks_rectangle.argtypes = [ctypes.c_int64, _dp, _dp]
 _lib.phiks_remainder.restype = ctypes.c_int
 _lib.phiks_remainder.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                  _dp]
+
+_lib.phiks_batch_plan.restype = ctypes.c_int
+_lib.phiks_batch_plan.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(_i64p),
+                                  ctypes.POINTER(_dpp), _dp, ctypes.c_int, ctypes.c_int,
+                                  ctypes.c_double, _dp, ctypes.c_int, _vp, ctypes.POINTER(_vp)]
+_lib.phiks_batch_apply.restype = ctypes.c_int
+_lib.phiks_batch_apply.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _vp,
+                                   ctypes.c_size_t, _vp]
+_lib.phiks_batch_workspace_size.restype = ctypes.c_int
+_lib.phiks_batch_workspace_size.argtypes = [_vp, ctypes.POINTER(ctypes.c_size_t)]
+_lib.phiks_batch_info.restype = ctypes.c_int
+_lib.phiks_batch_info.argtypes = [_vp, ctypes.c_int] + [ctypes.POINTER(ctypes.c_int)] * 4
+_lib.phiks_batch_destroy.restype = None
+_lib.phiks_batch_destroy.argtypes = [_vp]
 
 
 class PhiksError(RuntimeError):
@@ -361,6 +377,87 @@ def combine_arrays(plan: Plan, vs, out: Optional[DeviceArray] = None,
     phiks_combine(plan, [None if x is None else x.ptr for x in vs], out.ptr, ws.ptr, ws.nbytes,
                   stream)
     return out
+
+
+class Batch:
+    """Owns a phiks_batch_t (released by close() or garbage collection)."""
+
+    def __init__(self, handle: int, ns_list, p: int, n_scales: int):
+        self._h = ctypes.c_void_p(handle)
+        self.n = [list(x) for x in ns_list]
+        self.N = [int(np.prod(x)) for x in self.n]
+        self.count, self.p, self.n_scales = len(self.n), p, n_scales
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self, i: int):
+        s, q, tp, te = (ctypes.c_int() for _ in range(4))
+        _check(_lib.phiks_batch_info(self._h, int(i), ctypes.byref(s), ctypes.byref(q),
+                                     ctypes.byref(tp), ctypes.byref(te)), "phiks_batch_info")
+        return {"s": s.value, "q": q.value, "tucker_paper": tp.value, "tucker_exec": te.value}
+
+    def workspace_size(self) -> int:
+        b = ctypes.c_size_t()
+        _check(_lib.phiks_batch_workspace_size(self._h, ctypes.byref(b)),
+               "phiks_batch_workspace_size")
+        return b.value
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            _lib.phiks_batch_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def phiks_batch_plan(As: Sequence[Sequence[np.ndarray]], taus: Sequence[float], p: int,
+                     n_scales: int, tol: float, vnorms: Optional[Sequence[float]] = None,
+                     precision: int = PHIKS_FP64, stream: int = 0) -> Batch:
+    """As[i] = [A_1, ..., A_d] of problem i (host matrices); taus[i] its step."""
+    count = len(As)
+    if len(taus) != count:
+        raise ValueError("one tau per problem")
+    keep = [_host_mats(A) for A in As]
+    d = (ctypes.c_int * count)(*[len(k[0]) for k in keep])
+    n = (_i64p * count)(*[ctypes.cast(k[1], _i64p) for k in keep])
+    A = (_dpp * count)(*[ctypes.cast(k[2], _dpp) for k in keep])
+    tau = (ctypes.c_double * count)(*[float(t) for t in taus])
+    karr, vn = _norms(vnorms)
+    out = ctypes.c_void_p()
+    _check(_lib.phiks_batch_plan(count, d, n, A, tau, int(p), int(n_scales), float(tol), vn,
+                                 int(precision), ctypes.c_void_p(stream), ctypes.byref(out)),
+           "phiks_batch_plan")
+    return Batch(out.value, [list(k[1]) for k in keep], p, n_scales)
+
+
+def phiks_batch_apply(batch: Batch, v_ptrs: Sequence[int], out_ptrs: Sequence[int], ws_ptr: int,
+                      ws_bytes: int, stream: int = 0) -> None:
+    va = (_vp * len(v_ptrs))(*[_vp(x) for x in v_ptrs])
+    oa = (_vp * len(out_ptrs))(*[_vp(x) for x in out_ptrs])
+    _check(_lib.phiks_batch_apply(batch.handle, va, oa, _vp(ws_ptr), ctypes.c_size_t(ws_bytes),
+                                  _vp(stream)), "phiks_batch_apply")
+
+
+def batch_apply_arrays(batch: Batch, vs: Sequence[DeviceArray], outs=None, ws=None,
+                       stream: int = 0):
+    """Every problem's outputs, each laid out as apply_arrays' for that problem."""
+    if len(vs) != batch.count:
+        raise ValueError("one vector per problem")
+    for v, N in zip(vs, batch.N):
+        if v.n != N:
+            raise ValueError("vector i must hold N_i values")
+    if outs is None:
+        outs = [DeviceArray(batch.n_scales * (batch.p + 1) * N) for N in batch.N]
+    if ws is None:
+        ws = DeviceArray(batch.workspace_size() // 8 + 1)
+    phiks_batch_apply(batch, [v.ptr for v in vs], [o.ptr for o in outs], ws.ptr, ws.nbytes, stream)
+    return outs
 
 
 def tucker_arrays(n: Sequence[int], Ls: Sequence[DeviceArray], v: DeviceArray,

@@ -49,7 +49,7 @@ def build(verbose: bool = False, out: str = LIB, build_dir: str = BUILD,
         [HIPCC, *HIP_FLAGS, *dflags, f"-I{INCLUDE}", "-c", os.path.join(CSRC, "phiks.hip"),
          "-o", phiks_o],
         [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", planner_o, phiks_o,
-         "-o", out + ".tmp"],
+         "-lpthread", "-o", out + ".tmp"],
     ]
     for cmd in steps:
         log = _run(cmd)

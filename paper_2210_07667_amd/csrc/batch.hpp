@@ -1,0 +1,489 @@
+// Many independent same-vector problems in one call: phiks_batch_plan / _apply.
+//
+// Every problem keeps its own plan (s, q, GLL rule, small exponentials) and its own
+// recurrence (eqs. integrandsimul and simul, outputs as eq. scaldiffphi), exactly as
+// phiks_plan / phiks_apply would run it alone.  What changes is the execution: the
+// problems advance in lockstep, one step per mu-mode product, and each step runs the
+// GEMMs of every problem that has one at that point as a few grouped launches (one
+// per operand layout, tile class, load width and epilogue).  The GEMM views come from
+// tucker_args, the node sums from the same CombineArgs as the single path, and the
+// per-element K order of the MFMA kernel does not depend on the tile shape, so every
+// result is bitwise the one phiks_apply returns for that problem alone.
+//
+// Included once, at the end of phiks.hip.
+#pragma once
+
+#include <algorithm>
+#include <cstring>
+#include <string>
+#include <thread>
+#include <vector>
+
+struct phiks_batch_s {
+  int count = 0;
+  int p = 0, ns = 1, precision = PHIKS_FP64;
+  int device = 0;
+  hipStream_t stream = nullptr;           // stream the batch was built on (and is released on)
+  std::vector<phiks_plan_s> plans;        // per problem; matrices inside dmem
+  void* dmem = nullptr;
+  std::vector<size_t> ws_off;             // per-problem workspace offsets, doubles
+  size_t ws_doubles = 0;
+  // launch tables of one call: built in pinned host memory, uploaded once per call
+  char* host_tab = nullptr;
+  void* dev_tab = nullptr;
+  size_t tab_bytes = 0;
+  hipEvent_t upload_done = nullptr;       // the previous call's table upload has run
+  bool uploaded = false;
+  std::vector<std::vector<char>> host_keep;
+};
+
+namespace {
+
+enum class StepKind { Gemm, Combine };
+
+// One GEMM of a step: its views, its layout (mode 1: B k-contiguous), and whether it
+// is the last mode of a squaring Tucker (squaring epilogue with Y = the problem's
+// pre-step tensors).
+struct StepGemm {
+  GemmArgs g;
+  bool kc;
+  bool lincomb;
+  const double* Y;
+  int64_t YN;
+};
+
+struct GroupedLaunch {
+  StepKind kind;
+  bool kc = false, vec = false, lincomb = false;
+  int tile = 0;          // 0: 64 x 64 (4 waves of 32 x 32), 1: 32 x 32 (4 waves of 16 x 16)
+  size_t items_off = 0;  // bytes into the table: GroupItem[n] or CombineArgs[n]
+  size_t first_off = 0;  // bytes into the table: int64_t first[n] (GEMM)
+  int n = 0;
+  int64_t total = 0;     // GEMM: tiles; Combine: largest N
+};
+
+// Host builder of one call's launches and their tables.
+struct BatchSchedule {
+  std::vector<GroupedLaunch> launches;
+  std::vector<char> buf;
+  EpiLinComb lin;
+
+  size_t put(const void* src, size_t bytes) {
+    const size_t off = (buf.size() + 15) & ~(size_t)15;
+    buf.resize(off + bytes);
+    if (src) std::memcpy(buf.data() + off, src, bytes);
+    return off;
+  }
+
+  static int tile_class(const GemmArgs& g) { return (g.M >= 48 && g.N >= 48) ? 0 : 1; }
+
+  void add_gemm_step(const std::vector<StepGemm>& items) {
+    // partition by (layout, tile class, 16-byte loads, epilogue)
+    for (int kc = 0; kc < 2; ++kc)
+      for (int tile = 0; tile < 2; ++tile)
+        for (int vec = 0; vec < 2; ++vec)
+          for (int lc = 0; lc < 2; ++lc) {
+            std::vector<GroupItem> part;
+            std::vector<int64_t> first;
+            int64_t total = 0;
+            for (const StepGemm& it : items) {
+              if (it.kc != (kc == 1) || it.lincomb != (lc == 1) || tile_class(it.g) != tile) continue;
+              if (vec_ok(it.g, it.kc, {}) != (vec == 1)) continue;
+              GroupItem gi;
+              gi.g = it.g;
+              const int bm = tile == 0 ? 64 : 32, bn = bm;
+              gi.g.tiles_m = (gi.g.M + bm - 1) / bm;
+              gi.g.tiles_n = (gi.g.N + bn - 1) / bn;
+              gi.g.total_tiles = (int64_t)gi.g.tiles_m * gi.g.tiles_n * gi.g.nb0 * gi.g.nb1;
+              if (gi.g.total_tiles <= 0) continue;
+              gi.Y = it.Y;
+              gi.YN = it.YN;
+              first.push_back(total);
+              total += gi.g.total_tiles;
+              part.push_back(gi);
+            }
+            if (part.empty()) continue;
+            GroupedLaunch L;
+            L.kind = StepKind::Gemm;
+            L.kc = kc == 1;
+            L.tile = tile;
+            L.vec = vec == 1;
+            L.lincomb = lc == 1;
+            L.n = (int)part.size();
+            L.total = total;
+            L.items_off = put(part.data(), part.size() * sizeof(GroupItem));
+            L.first_off = put(first.data(), first.size() * sizeof(int64_t));
+            launches.push_back(L);
+          }
+  }
+
+  void add_combine_step(const std::vector<CombineArgs>& items) {
+    if (items.empty()) return;
+    GroupedLaunch L;
+    L.kind = StepKind::Combine;
+    L.n = (int)items.size();
+    for (const CombineArgs& a : items) L.total = std::max(L.total, a.N);
+    L.items_off = put(items.data(), items.size() * sizeof(CombineArgs));
+    launches.push_back(L);
+  }
+};
+
+template <int BM, int BN, int WM, int WN, bool KC, bool VEC, class Epi>
+int launch_grouped_cfg(const GroupedLaunch& L, const char* dev, const Epi& epi, hipStream_t st) {
+  if (L.total > 0x7fffffffLL) {
+    set_error("grouped GEMM grid too large");
+    return PHIKS_EINVAL;
+  }
+  (void)hipGetLastError();
+  hipLaunchKernelGGL((gemm_f64_grouped<BM, BN, WM, WN, KC, VEC, Epi>), dim3((unsigned)L.total),
+                     dim3(256), 0, st, (const GroupItem*)(dev + L.items_off),
+                     (const int64_t*)(dev + L.first_off), L.n, L.total, epi);
+  CHECK_LAUNCH();
+  return PHIKS_OK;
+}
+
+template <bool KC, bool VEC, class Epi>
+int launch_grouped_tile(const GroupedLaunch& L, const char* dev, const Epi& epi, hipStream_t st) {
+  if (L.tile == 0) return launch_grouped_cfg<64, 64, 32, 32, KC, VEC>(L, dev, epi, st);
+  return launch_grouped_cfg<32, 32, 16, 16, KC, VEC>(L, dev, epi, st);
+}
+
+template <class Epi>
+int launch_grouped(const GroupedLaunch& L, const char* dev, const Epi& epi, hipStream_t st) {
+  if (L.kc) {
+    return L.vec ? launch_grouped_tile<true, true>(L, dev, epi, st)
+                 : launch_grouped_tile<true, false>(L, dev, epi, st);
+  }
+  return L.vec ? launch_grouped_tile<false, true>(L, dev, epi, st)
+               : launch_grouped_tile<false, false>(L, dev, epi, st);
+}
+
+// Builds the launches of one phiks_batch_apply call (the same order of operations as
+// phiks_apply for every problem).  v, out: the call's vectors; ws: its workspace.
+void build_batch_schedule(const phiks_batch_s& B, const double* const* v, double* const* out,
+                          double* ws, BatchSchedule& S) {
+  const int p = B.p, ns = B.ns;
+  const int count = B.count;
+  struct Bufs { double *ta, *tb, *pa, *pb, *cur; };
+  std::vector<Bufs> bf(count);
+  int dmax = 0, smax = 0;
+  for (int i = 0; i < count; ++i) {
+    const phiks_plan_s& P = B.plans[i];
+    const int64_t N = P.N;
+    const int64_t t = std::max<int64_t>({(int64_t)P.q - 1, (int64_t)p, 1});
+    bf[i].ta = ws + B.ws_off[i];
+    bf[i].tb = bf[i].ta + t * N;
+    bf[i].pa = bf[i].tb + t * N;
+    bf[i].pb = bf[i].pa + (int64_t)p * N;
+    dmax = std::max(dmax, P.d);
+    smax = std::max(smax, P.s);
+  }
+  auto slot = [&](int i, int level, int ell) {
+    return out[i] + ((int64_t)level * (p + 1) + ell) * B.plans[i].N;
+  };
+  // squaring-epilogue coefficients (the same for every problem: they depend on p only)
+  std::memset(&S.lin, 0, sizeof(S.lin));
+  S.lin.p = p;
+  for (int ell = 1; ell <= p; ++ell) {
+    const double sc = std::ldexp(1.0, -ell);
+    S.lin.a[ell - 1] = sc;
+    for (int k = 1; k <= ell; ++k) S.lin.c[ell - 1][k - 1] = sc / factorial(ell - k);
+  }
+  if (p > 0) {
+    // eq. integrandsimul: the node Tuckers of every problem, mode by mode
+    std::vector<std::vector<GemmArgs>> views(count, std::vector<GemmArgs>(PHIKS_MAX_D));
+    for (int i = 0; i < count; ++i) {
+      const phiks_plan_s& P = B.plans[i];
+      int64_t stride[PHIKS_MAX_D];
+      for (int mu = 0; mu < P.d; ++mu) stride[mu] = P.n[mu] * P.n[mu];
+      double* wbuf = tucker_free_buffer(P.d, bf[i].ta, bf[i].tb);
+      tucker_args(P.d, P.n, P.N, v[i], 0, P.Lnode, stride, plan_nodes(P), wbuf, bf[i].ta,
+                  bf[i].tb, views[i].data());
+    }
+    for (int mu = 1; mu <= dmax; ++mu) {
+      std::vector<StepGemm> items;
+      for (int i = 0; i < count; ++i)
+        if (B.plans[i].d >= mu) items.push_back({views[i][mu - 1], mu == 1, false, nullptr, 0});
+      S.add_gemm_step(items);
+    }
+    // node sums
+    std::vector<CombineArgs> comb;
+    for (int i = 0; i < count; ++i) {
+      const phiks_plan_s& P = B.plans[i];
+      const int nodes = plan_nodes(P);
+      double* wbuf = tucker_free_buffer(P.d, bf[i].ta, bf[i].tb);
+      bf[i].cur = (P.s < ns) ? slot(i, P.s, 1) : bf[i].pa;
+      CombineArgs ca;
+      std::memset(&ca, 0, sizeof(ca));
+      ca.nin = nodes + 1;
+      for (int k = 0; k < nodes; ++k) ca.in[k] = wbuf + (int64_t)k * P.N;
+      ca.in[nodes] = v[i];
+      ca.out = bf[i].cur;
+      ca.out_stride = P.N;
+      ca.nout = p;
+      ca.beta = 0.0;
+      ca.N = P.N;
+      for (int ell = 1; ell <= p; ++ell)
+        for (int k = 0; k < P.q; ++k)
+          ca.coef[ell - 1][k] = P.w[k] * std::pow(P.theta[k], ell - 1) / factorial(ell - 1);
+      ca.vec = combine_vec_ok(ca) ? 1 : 0;
+      comb.push_back(ca);
+    }
+    S.add_combine_step(comb);
+    // eq. simul: iteration t runs level j = s_i - t of every problem with s_i > t
+    for (int t = 0; t < smax; ++t) {
+      std::vector<std::vector<GemmArgs>> lv(count, std::vector<GemmArgs>(PHIKS_MAX_D));
+      std::vector<double*> dst(count, nullptr);
+      for (int i = 0; i < count; ++i) {
+        const phiks_plan_s& P = B.plans[i];
+        if (P.s <= t) continue;
+        const int j = P.s - t;
+        dst[i] = (j - 1 < ns) ? slot(i, j - 1, 1) : ((bf[i].cur == bf[i].pa) ? bf[i].pb : bf[i].pa);
+        double* L[PHIKS_MAX_D];
+        int64_t stride[PHIKS_MAX_D] = {0};
+        for (int mu = 0; mu < P.d; ++mu) L[mu] = P.E[mu] + (size_t)j * P.n[mu] * P.n[mu];
+        tucker_args(P.d, P.n, P.N, bf[i].cur, P.N, L, stride, p, dst[i], bf[i].ta, bf[i].tb,
+                    lv[i].data());
+      }
+      for (int mu = 1; mu <= dmax; ++mu) {
+        std::vector<StepGemm> items;
+        for (int i = 0; i < count; ++i) {
+          const phiks_plan_s& P = B.plans[i];
+          if (P.s <= t || P.d < mu) continue;
+          const bool last = (mu == P.d);
+          items.push_back({lv[i][mu - 1], mu == 1, last, last ? bf[i].cur : nullptr, P.N});
+        }
+        S.add_gemm_step(items);
+      }
+      for (int i = 0; i < count; ++i)
+        if (B.plans[i].s > t) bf[i].cur = dst[i];
+    }
+  }
+  // exponential outputs exp(2^-j tau K) v
+  for (int lev = 0; lev < ns; ++lev) {
+    std::vector<std::vector<GemmArgs>> ev(count, std::vector<GemmArgs>(PHIKS_MAX_D));
+    for (int i = 0; i < count; ++i) {
+      const phiks_plan_s& P = B.plans[i];
+      double* L[PHIKS_MAX_D];
+      int64_t stride[PHIKS_MAX_D] = {0};
+      for (int mu = 0; mu < P.d; ++mu) L[mu] = P.E[mu] + (size_t)lev * P.n[mu] * P.n[mu];
+      tucker_args(P.d, P.n, P.N, v[i], 0, L, stride, 1, slot(i, lev, 0), bf[i].ta, bf[i].tb,
+                  ev[i].data());
+    }
+    for (int mu = 1; mu <= dmax; ++mu) {
+      std::vector<StepGemm> items;
+      for (int i = 0; i < count; ++i)
+        if (B.plans[i].d >= mu) items.push_back({ev[i][mu - 1], mu == 1, false, nullptr, 0});
+      S.add_gemm_step(items);
+    }
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+void phiks_batch_destroy(phiks_batch_t batch) {
+  if (!batch) return;
+  int cur = 0;
+  const bool switched = (hipGetDevice(&cur) == hipSuccess) && cur != batch->device;
+  if (switched) (void)hipSetDevice(batch->device);
+  // Waits for the batch's stream, then frees.  (A host function queued on the stream
+  // may not call the HIP API, and the pinned tables need hipHostFree.)
+  (void)hipStreamSynchronize(batch->stream);
+  if (batch->dmem) (void)hipFree(batch->dmem);
+  if (batch->dev_tab) (void)hipFree(batch->dev_tab);
+  if (batch->host_tab) (void)hipHostFree(batch->host_tab);
+  if (batch->upload_done) (void)hipEventDestroy(batch->upload_done);
+  delete batch;
+  if (switched) (void)hipSetDevice(cur);
+}
+
+int phiks_batch_plan(int count, const int* d, const int64_t* const* n,
+                     const double* const* const* A, const double* tau, int p, int n_scales,
+                     double tol, const double* vnorms, int precision, void* hip_stream,
+                     phiks_batch_t* out) {
+  if (!out) return PHIKS_EINVAL;
+  *out = nullptr;
+  if (count < 1 || !d || !n || !A || !tau) return PHIKS_EINVAL;
+  if (precision != PHIKS_FP64) {
+    set_error("batched problems run in FP64");
+    return PHIKS_EINVAL;
+  }
+  phiks_batch_s* B = new (std::nothrow) phiks_batch_s;
+  if (!B) return PHIKS_ENOMEM;
+  B->count = count;
+  B->p = p;
+  B->ns = n_scales;
+  B->precision = precision;
+  B->plans.resize(count);
+  // host planning of the problems on a few threads (the planner keeps no shared
+  // mutable state; its kernel table is built once under call_once)
+  std::vector<int> rcs(count, PHIKS_OK);
+  std::vector<std::string> errs(count);
+  {
+    const int nt = std::max(1, std::min<int>({count, 16, (int)std::thread::hardware_concurrency()}));
+    std::vector<std::thread> pool;
+    for (int t = 0; t < nt; ++t)
+      pool.emplace_back([&, t]() {
+        for (int i = t; i < count; i += nt) {
+          rcs[i] = plan_init_host(B->plans[i], d[i], n[i], A[i], tau[i], p, n_scales, tol,
+                                  PHIKS_SAME_VECTOR, vnorms ? vnorms + i : nullptr, precision);
+          if (rcs[i] != PHIKS_OK) errs[i] = g_last_error;
+        }
+      });
+    for (std::thread& th : pool) th.join();
+  }
+  for (int i = 0; i < count; ++i) {
+    if (rcs[i] != PHIKS_OK) {
+      set_error("problem " + std::to_string(i) + ": " + phiks_status_string(rcs[i]) +
+                (errs[i].empty() ? "" : " (" + errs[i] + ")"));
+      delete B;
+      return rcs[i];
+    }
+  }
+  hipStream_t st = (hipStream_t)hip_stream;
+  B->stream = st;
+  auto fail = [&](int code) {
+    phiks_batch_destroy(B);
+    return code;
+  };
+  if (hipGetDevice(&B->device) != hipSuccess) { set_error("hipGetDevice failed"); return fail(PHIKS_EDEVICE); }
+  // one allocation for every problem's matrices (each slice 16-byte aligned)
+  std::vector<size_t> moff(count);
+  size_t total = 0;
+  for (int i = 0; i < count; ++i) {
+    moff[i] = total;
+    total += (plan_device_doubles(B->plans[i]) + 1) & ~(size_t)1;
+  }
+  if (hipMallocAsync(&B->dmem, std::max<size_t>(total, 1) * sizeof(double), st) != hipSuccess) {
+    B->dmem = nullptr;
+    set_error("hipMallocAsync of batch matrices failed");
+    return fail(PHIKS_ENOMEM);
+  }
+  std::vector<phiks_plan_s*> ptrs(count);
+  std::vector<const double* const*> mats(count);
+  for (int i = 0; i < count; ++i) {
+    plan_assign(B->plans[i], (double*)B->dmem + moff[i]);
+    B->plans[i].device = B->device;
+    B->plans[i].stream = st;
+    ptrs[i] = &B->plans[i];
+    mats[i] = A[i];
+  }
+  int rc = build_plan_matrices(ptrs, mats, B->host_keep, st);
+  if (rc != PHIKS_OK) return fail(rc);
+  // workspace: each problem's single-call workspace, 16-byte aligned slices
+  B->ws_off.resize(count);
+  for (int i = 0; i < count; ++i) {
+    B->ws_off[i] = B->ws_doubles;
+    B->ws_doubles += (workspace_doubles(B->plans[i]) + 1) & ~(size_t)1;
+  }
+  // size the launch tables with a dry run on stand-in 256-byte aligned addresses (the
+  // size depends on the shapes and, through the 16-byte load test, on alignment only;
+  // a call that needs more grows them)
+  {
+    std::vector<const double*> dv(count);
+    std::vector<double*> dout(count);
+    for (int i = 0; i < count; ++i) {
+      dv[i] = reinterpret_cast<const double*>((uintptr_t)256 * (2 * i + 1));
+      dout[i] = reinterpret_cast<double*>((uintptr_t)256 * (2 * i + 2));
+    }
+    BatchSchedule S;
+    build_batch_schedule(*B, dv.data(), dout.data(), reinterpret_cast<double*>((uintptr_t)256), S);
+    B->tab_bytes = std::max<size_t>(S.buf.size(), 16);
+  }
+  if (hipHostMalloc((void**)&B->host_tab, B->tab_bytes, hipHostMallocDefault) != hipSuccess) {
+    B->host_tab = nullptr;
+    set_error("hipHostMalloc of the batch launch tables failed");
+    return fail(PHIKS_ENOMEM);
+  }
+  if (hipMallocAsync(&B->dev_tab, B->tab_bytes, st) != hipSuccess) {
+    B->dev_tab = nullptr;
+    set_error("hipMallocAsync of the batch launch tables failed");
+    return fail(PHIKS_ENOMEM);
+  }
+  if (hipEventCreateWithFlags(&B->upload_done, hipEventDisableTiming) != hipSuccess) {
+    B->upload_done = nullptr;
+    set_error("hipEventCreate failed");
+    return fail(PHIKS_EDEVICE);
+  }
+  *out = B;
+  return PHIKS_OK;
+}
+
+int phiks_batch_workspace_size(phiks_batch_t batch, size_t* bytes) {
+  if (!batch || !bytes) return PHIKS_EINVAL;
+  *bytes = batch->ws_doubles * sizeof(double);
+  return PHIKS_OK;
+}
+
+int phiks_batch_info(phiks_batch_t batch, int i, int* s, int* q, int* tucker_paper,
+                     int* tucker_exec) {
+  if (!batch || i < 0 || i >= batch->count) return PHIKS_EINVAL;
+  const phiks_plan_s& P = batch->plans[i];
+  if (s) *s = P.s;
+  if (q) *q = P.q;
+  if (tucker_paper) *tucker_paper = P.t_paper;
+  if (tucker_exec) *tucker_exec = P.t_exec;
+  return PHIKS_OK;
+}
+
+int phiks_batch_apply(phiks_batch_t batch, const double* const* v, double* const* out, void* ws,
+                      size_t ws_bytes, void* hip_stream) {
+  if (!batch || !v || !out) return PHIKS_EINVAL;
+  phiks_batch_s& B = *batch;
+  for (int i = 0; i < B.count; ++i)
+    if (!v[i] || !out[i]) return PHIKS_EINVAL;
+  if (!ws || ws_bytes < B.ws_doubles * sizeof(double)) return PHIKS_EWORKSPACE;
+  if ((uintptr_t)ws % 16) {
+    set_error("batch workspace must be 16-byte aligned");
+    return PHIKS_EINVAL;
+  }
+  hipStream_t st = (hipStream_t)hip_stream;
+  BatchSchedule S;
+  build_batch_schedule(B, v, out, (double*)ws, S);
+  // the previous call's upload must have read the staging buffer before it is rewritten
+  if (B.uploaded) HIP_OK(hipEventSynchronize(B.upload_done));
+  if (S.buf.size() > B.tab_bytes) {
+    // grow the tables (the old device table is released in stream order)
+    const size_t bytes = S.buf.size() + S.buf.size() / 4;
+    char* h = nullptr;
+    void* dtab = nullptr;
+    if (hipHostMalloc((void**)&h, bytes, hipHostMallocDefault) != hipSuccess) {
+      set_error("hipHostMalloc of the batch launch tables failed");
+      return PHIKS_ENOMEM;
+    }
+    if (hipMallocAsync(&dtab, bytes, st) != hipSuccess) {
+      (void)hipHostFree(h);
+      set_error("hipMallocAsync of the batch launch tables failed");
+      return PHIKS_ENOMEM;
+    }
+    HIP_OK(hipFreeAsync(B.dev_tab, st));
+    (void)hipHostFree(B.host_tab);
+    B.host_tab = h;
+    B.dev_tab = dtab;
+    B.tab_bytes = bytes;
+  }
+  if (!S.buf.empty()) std::memcpy(B.host_tab, S.buf.data(), S.buf.size());
+  HIP_OK(hipMemcpyAsync(B.dev_tab, B.host_tab, std::max<size_t>(S.buf.size(), 16),
+                        hipMemcpyHostToDevice, st));
+  HIP_OK(hipEventRecord(B.upload_done, st));
+  B.uploaded = true;
+  const char* dev = (const char*)B.dev_tab;
+  for (const GroupedLaunch& L : S.launches) {
+    if (L.kind == StepKind::Combine) {
+      const int64_t blocks = std::min<int64_t>((L.total + 255) / 256, 1024);
+      (void)hipGetLastError();
+      hipLaunchKernelGGL(combine_grouped_kernel, dim3((unsigned)blocks, (unsigned)L.n), dim3(256),
+                         0, st, (const CombineArgs*)(dev + L.items_off));
+      CHECK_LAUNCH();
+    } else if (L.lincomb) {
+      RET_IF(launch_grouped(L, dev, S.lin, st));
+    } else {
+      RET_IF(launch_grouped(L, dev, EpiStore{1.0, 0.0}, st));
+    }
+  }
+  return PHIKS_OK;
+}
+
+}  // extern "C"

@@ -186,13 +186,13 @@ __global__ void __launch_bounds__(256, VEC ? PHIKS_F32_MIN_WAVES : 2) gemm_f32_k
   vec_t rb[LB];
   auto a_ok = [&](int e, int k0) {
     const int m = e / (BK / VW), k = VW * (e % (BK / VW));
-    return (m0 + m < g.M) && (k0 + k < g.K);
+    return (m0 + m < g.M) & (k0 + k < g.K);
   };
   auto b_ok = [&](int e, int k0) {
     int n, k;
     if constexpr (B_KCONTIG) { n = e / (BK / VW); k = VW * (e % (BK / VW)); }
     else { k = e / (BN / VW); n = VW * (e % (BN / VW)); }
-    return (n0 + n < g.N) && (k0 + k < g.K);
+    return (n0 + n < g.N) & (k0 + k < g.K);
   };
   static_assert(LA <= 32 && LB <= 32, "one mask bit per load");
   // in-range bits of the loads in flight (the scalar-load variants keep them; the

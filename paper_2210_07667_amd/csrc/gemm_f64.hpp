@@ -35,6 +35,8 @@
 #include <cstdint>
 #include <type_traits>
 
+#include "devptr.hpp"
+
 namespace phiks {
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
@@ -62,7 +64,8 @@ struct GemmArgs {
 // C = alpha * acc (+ beta * C).  beta == 0 never reads C.
 struct EpiStore {
   double alpha, beta;
-  __device__ __forceinline__ void operator()(double* C, int64_t e, int64_t, double acc) const {
+  template <class P>
+  __device__ __forceinline__ void operator()(P C, int64_t e, int64_t, double acc) const {
     C[e] = (beta == 0.0) ? alpha * acc : alpha * acc + beta * C[e];
   }
 };
@@ -76,10 +79,12 @@ struct EpiLinComb {
   int p;
   double a[8];
   double c[8][8];
-  __device__ __forceinline__ void operator()(double* C, int64_t e, int64_t l, double acc) const {
+  template <class P>
+  __device__ __forceinline__ void operator()(P C, int64_t e, int64_t l, double acc) const {
     const int64_t off = e - l * N;
+    const PHIKS_GLOBAL double* Yg = gptr(Y);
     double r = a[l] * acc;
-    for (int k = 0; k <= (int)l; ++k) r += c[l][k] * Y[k * N + off];
+    for (int k = 0; k <= (int)l; ++k) r += c[l][k] * Yg[k * N + off];
     C[e] = r;
   }
 };
@@ -103,11 +108,10 @@ __device__ __forceinline__ int swz_n(int k) { return (k & 1) << 4; }
 #define PHIKS_GEMM_MIN_WAVES 3  // minimum waves per SIMD the register budget must allow
 #endif
 
-// PTRS: pointer-array batch (pA, pB, pC).  A separate instantiation, so that the
-// operands of the strided form stay provably global (global_load, which leaves the
-// LDS wait counter to the LDS reads) rather than generic pointers read from memory.
-template <int BM, int BN, int WM, int WN, bool B_KCONTIG, bool VEC, class Epi, bool PTRS = false>
-__global__ void __launch_bounds__(256, VEC ? PHIKS_GEMM_MIN_WAVES : 2) gemm_f64_kernel(GemmArgs g, Epi epi) {
+// One output tile of one GEMM: `rest` is the logical tile index in the tile order
+// described above (0 .. g.total_tiles - 1).
+template <int BM, int BN, int WM, int WN, bool B_KCONTIG, bool VEC, class Epi>
+__device__ __forceinline__ void gemm_f64_tile(const GemmArgs& g, const Epi& epi, int64_t rest) {
   constexpr int BK = 16;
   constexpr int WGM = BM / WM;
   constexpr int WGN = BN / WN;
@@ -122,7 +126,6 @@ __global__ void __launch_bounds__(256, VEC ? PHIKS_GEMM_MIN_WAVES : 2) gemm_f64_
   __shared__ __align__(16) double As[2][BK][BM];
   __shared__ __align__(16) double Bs[2][BK][BN];
 
-  int64_t rest = xcd_remap(blockIdx.x, g.total_tiles);
   int tm, tn;
   int64_t z1, z0;
   if constexpr (B_KCONTIG) {
@@ -141,19 +144,19 @@ __global__ void __launch_bounds__(256, VEC ? PHIKS_GEMM_MIN_WAVES : 2) gemm_f64_
     z0 = rest / g.tiles_n;
   }
 
-  const double* __restrict__ A;
-  const double* __restrict__ B;
-  double* Cb;
+  const PHIKS_GLOBAL double* __restrict__ A;
+  const PHIKS_GLOBAL double* __restrict__ B;
+  PHIKS_GLOBAL double* Cb;
   int64_t cbase;
-  if constexpr (PTRS) {
-    A = g.pA[z1];
-    B = g.pB[z1];
-    Cb = g.pC[z1];
+  if (g.pA != nullptr) {
+    A = gptr(g.pA[z1]);
+    B = gptr(g.pB[z1]);
+    Cb = gptr(g.pC[z1]);
     cbase = 0;
   } else {
-    A = g.A + z0 * g.sA0 + z1 * g.sA1;
-    B = g.B + z0 * g.sB0 + z1 * g.sB1;
-    Cb = g.C;
+    A = gptr(g.A) + z0 * g.sA0 + z1 * g.sA1;
+    B = gptr(g.B) + z0 * g.sB0 + z1 * g.sB1;
+    Cb = gptr(g.C);
     cbase = z0 * g.sC0 + z1 * g.sC1;
   }
 
@@ -174,13 +177,13 @@ __global__ void __launch_bounds__(256, VEC ? PHIKS_GEMM_MIN_WAVES : 2) gemm_f64_
   vec_t ra[LA], rb[LB];
   auto a_ok = [&](int e, int k0) {
     const int m = e / (BK / VW), k = VW * (e % (BK / VW));
-    return (m0 + m < g.M) && (k0 + k < g.K);
+    return (m0 + m < g.M) & (k0 + k < g.K);
   };
   auto b_ok = [&](int e, int k0) {
     int n, k;
     if constexpr (B_KCONTIG) { n = e / (BK / VW); k = VW * (e % (BK / VW)); }
     else { k = e / (BN / VW); n = VW * (e % (BN / VW)); }
-    return (n0 + n < g.N) && (k0 + k < g.K);
+    return (n0 + n < g.N) & (k0 + k < g.K);
   };
   static_assert(LA <= 32 && LB <= 32, "one mask bit per load");
   // in-range bits of the loads in flight (the scalar-load variants keep them; the
@@ -203,7 +206,7 @@ __global__ void __launch_bounds__(256, VEC ? PHIKS_GEMM_MIN_WAVES : 2) gemm_f64_
       const bool ok = a_ok(e, k0);
       if constexpr (!VEC) amask |= (uint32_t)ok << i;
       const int64_t off = ok ? (int64_t)(m0 + m) * g.lda + k0 + k : 0;
-      ra[i] = *reinterpret_cast<const vec_t*>(A + off);
+      ra[i] = *reinterpret_cast<const PHIKS_GLOBAL vec_t*>(A + off);
     }
 #pragma unroll
     for (int i = 0; i < LB; ++i) {
@@ -216,7 +219,7 @@ __global__ void __launch_bounds__(256, VEC ? PHIKS_GEMM_MIN_WAVES : 2) gemm_f64_
       if constexpr (!VEC) bmask |= (uint32_t)ok << i;
       const int64_t off =
           ok ? (B_KCONTIG ? (int64_t)gn * g.ldb + gk : (int64_t)gk * g.ldb + gn) : 0;
-      rb[i] = *reinterpret_cast<const vec_t*>(B + off);
+      rb[i] = *reinterpret_cast<const PHIKS_GLOBAL vec_t*>(B + off);
     }
   };
   auto store_chunk = [&](int buf, int k0) {
@@ -299,7 +302,7 @@ __global__ void __launch_bounds__(256, VEC ? PHIKS_GEMM_MIN_WAVES : 2) gemm_f64_
       for (int j = 0; j < FN; ++j) acc[i][j] *= al;
     for (int k = 0; k <= l; ++k) {
       const double ck = epi.c[l][k];
-      const double* __restrict__ Yk = epi.Y + (int64_t)(k - l) * epi.N;
+      const PHIKS_GLOBAL double* __restrict__ Yk = gptr(epi.Y) + (int64_t)(k - l) * epi.N;
       double y[FM][FN][4];
 #pragma unroll
       for (int i = 0; i < FM; ++i)
@@ -343,6 +346,45 @@ __global__ void __launch_bounds__(256, VEC ? PHIKS_GEMM_MIN_WAVES : 2) gemm_f64_
           if (m < g.M && n < g.N) epi(Cb, cbase + (int64_t)m * g.ldc + n, z1, acc[i][j][r]);
         }
       }
+  }
+}
+
+template <int BM, int BN, int WM, int WN, bool B_KCONTIG, bool VEC, class Epi>
+__global__ void __launch_bounds__(256, VEC ? PHIKS_GEMM_MIN_WAVES : 2) gemm_f64_kernel(GemmArgs g, Epi epi) {
+  gemm_f64_tile<BM, BN, WM, WN, B_KCONTIG, VEC>(g, epi, xcd_remap(blockIdx.x, g.total_tiles));
+}
+
+// Grouped launch: many independent GEMMs of one kind (same tile shape, operand layout
+// and epilogue type) in one grid.  Item i owns the logical tiles first[i] ..
+// first[i] + items[i].g.total_tiles - 1; a work-group finds its item by binary search
+// over `first` (a few KB, served by the scalar cache).  The epilogue is shared by the
+// launch except for the per-item output-side operands carried by GroupItem::Y / YN
+// (used by EpiLinComb: the pre-step tensors of the item's problem).
+struct GroupItem {
+  GemmArgs g;
+  const double* Y;
+  int64_t YN;
+};
+
+template <int BM, int BN, int WM, int WN, bool B_KCONTIG, bool VEC, class Epi>
+__global__ void __launch_bounds__(256, VEC ? PHIKS_GEMM_MIN_WAVES : 2)
+    gemm_f64_grouped(const GroupItem* __restrict__ items, const int64_t* __restrict__ first,
+                     int nitems, int64_t total, Epi epi) {
+  const int64_t t = xcd_remap(blockIdx.x, total);
+  int lo = 0, hi = nitems - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (first[mid] <= t) lo = mid;
+    else hi = mid - 1;
+  }
+  const GroupItem& it = items[lo];
+  if constexpr (std::is_same<Epi, EpiLinComb>::value) {
+    Epi e = epi;
+    e.Y = it.Y;
+    e.N = it.YN;
+    gemm_f64_tile<BM, BN, WM, WN, B_KCONTIG, VEC>(it.g, e, t - first[lo]);
+  } else {
+    gemm_f64_tile<BM, BN, WM, WN, B_KCONTIG, VEC>(it.g, epi, t - first[lo]);
   }
 }
 

@@ -5,6 +5,8 @@
 
 #include <cstdint>
 
+#include "devptr.hpp"
+
 namespace phiks {
 
 constexpr int kMaxIn = 16;
@@ -25,42 +27,53 @@ struct CombineArgs {
   double coef[8][kMaxIn];
 };
 
-__global__ void __launch_bounds__(256) combine_kernel(CombineArgs a) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+// Elements first, first + stride, ... of one combination.
+__device__ __forceinline__ void combine_body(const CombineArgs& a, int64_t first, int64_t stride) {
+  PHIKS_GLOBAL double* out = gptr(a.out);
   if (a.vec) {
     // 16-byte accesses (conditions checked by the launcher)
     typedef double d2 __attribute__((ext_vector_type(2)));
     const int64_t N2 = a.N >> 1;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < N2; e += stride) {
+    for (int64_t e = first; e < N2; e += stride) {
       d2 x[kMaxIn];
 #pragma unroll
       for (int t = 0; t < kMaxIn; ++t)
-        if (t < a.nin) x[t] = reinterpret_cast<const d2*>(a.in[t])[e];
+        if (t < a.nin) x[t] = reinterpret_cast<const PHIKS_GLOBAL d2*>(gptr(a.in[t]))[e];
       for (int l = 0; l < a.nout; ++l) {
         d2 r = {0.0, 0.0};
 #pragma unroll
         for (int t = 0; t < kMaxIn; ++t)
           if (t < a.nin) r += a.coef[l][t] * x[t];
-        d2* o = reinterpret_cast<d2*>(a.out + l * a.out_stride) + e;
+        PHIKS_GLOBAL d2* o = reinterpret_cast<PHIKS_GLOBAL d2*>(out + l * a.out_stride) + e;
         *o = (a.beta == 0.0) ? r : a.beta * (*o) + r;
       }
     }
     return;
   }
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < a.N; e += stride) {
+  for (int64_t e = first; e < a.N; e += stride) {
     double x[kMaxIn];
 #pragma unroll
     for (int t = 0; t < kMaxIn; ++t)
-      if (t < a.nin) x[t] = a.in[t][e];
+      if (t < a.nin) x[t] = gptr(a.in[t])[e];
     for (int l = 0; l < a.nout; ++l) {
       double r = 0.0;
 #pragma unroll
       for (int t = 0; t < kMaxIn; ++t)
         if (t < a.nin) r += a.coef[l][t] * x[t];
-      double* o = a.out + l * a.out_stride + e;
+      PHIKS_GLOBAL double* o = out + l * a.out_stride + e;
       *o = (a.beta == 0.0) ? r : a.beta * (*o) + r;
     }
   }
+}
+
+__global__ void __launch_bounds__(256) combine_kernel(CombineArgs a) {
+  combine_body(a, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, (int64_t)gridDim.x * blockDim.x);
+}
+
+// One combination per blockIdx.y (many independent problems in one launch).
+__global__ void __launch_bounds__(256) combine_grouped_kernel(const CombineArgs* __restrict__ items) {
+  combine_body(items[blockIdx.y], (int64_t)blockIdx.x * blockDim.x + threadIdx.x,
+               (int64_t)gridDim.x * blockDim.x);
 }
 
 // dst = (float)src, n entries.

@@ -73,12 +73,17 @@ double* tucker_free_buffer(int d, double* ta, double* tb) {
   return ((d - 1) % 2 == 1) ? tb : ta;
 }
 
+// 16-byte accesses: even N and output stride, 16-byte aligned bases
+bool combine_vec_ok(const CombineArgs& a) {
+  bool v = (a.N % 2 == 0) && (a.out_stride % 2 == 0) && ((uintptr_t)a.out % 16 == 0);
+  for (int t = 0; t < a.nin; ++t) v = v && ((uintptr_t)a.in[t] % 16 == 0);
+  return v;
+}
+
 int launch_combine(const CombineArgs& a_in, hipStream_t st) {
   if (a_in.N <= 0 || a_in.nout <= 0) return PHIKS_OK;
   CombineArgs a = a_in;
-  bool v = (a.N % 2 == 0) && (a.out_stride % 2 == 0) && ((uintptr_t)a.out % 16 == 0);
-  for (int t = 0; t < a.nin; ++t) v = v && ((uintptr_t)a.in[t] % 16 == 0);
-  a.vec = v ? 1 : 0;
+  a.vec = combine_vec_ok(a) ? 1 : 0;
   int64_t blocks = (a.N + 255) / 256;
   blocks = std::min<int64_t>(blocks, 8192);
   (void)hipGetLastError();
@@ -101,110 +106,129 @@ double factorial(int k) {
 const double kTaylorTheta = 2.0;
 const int kTaylorDegree = 24;
 
+// One small operator: the shifted B - sigma I (host, row-major), sigma, its 1-norm.
+struct ExpmOp {
+  int64_t n;
+  std::vector<double> Bshift;
+  double sigma;
+  double norm1;
+};
+
 struct ExpmRequest {
-  int mu;          // mode
-  double c;        // exp(c B_mu) is requested
+  int op;          // index into the operator list
+  double c;        // exp(c B_op) is requested
   double* dst;     // n^2 destination
 };
 
-// Computes exp(c_r B_{mu_r}) for every request on the device.  Bshift[mu] is the
-// shifted operator B_mu - sigma_mu I (row-major), norm1[mu] its 1-norm.
-int batched_expm(phiks_plan_s& P, const std::vector<std::vector<double>>& Bshift,
-                 const double* sigma, const double* norm1,
-                 const std::vector<ExpmRequest>& reqs, hipStream_t st) {
-  const int d = P.d;
+// C_i = A_i B_i (+ beta C_i) for pointer arrays of equal-size n x n products; the
+// pointer table's host copy is kept alive in host_keep until the plan is released.
+int ptr_gemm(const std::vector<const double*>& a, const std::vector<const double*>& b,
+             const std::vector<double*>& c, int n, double beta,
+             std::vector<std::vector<char>>& host_keep, hipStream_t st) {
+  if (a.empty()) return PHIKS_OK;
+  const size_t nb = a.size();
+  host_keep.emplace_back(3 * nb * sizeof(void*));
+  void** hp = (void**)host_keep.back().data();
+  for (size_t i = 0; i < nb; ++i) {
+    hp[i] = (void*)a[i];
+    hp[nb + i] = (void*)b[i];
+    hp[2 * nb + i] = (void*)c[i];
+  }
+  void** dp = nullptr;
+  HIP_OK(hipMallocAsync((void**)&dp, 3 * nb * sizeof(void*), st));
+  HIP_OK(hipMemcpyAsync(dp, hp, 3 * nb * sizeof(void*), hipMemcpyHostToDevice, st));
+  GemmArgs g = empty_args();
+  g.M = g.N = g.K = n;
+  g.lda = g.ldb = g.ldc = n;
+  g.nb1 = (int)nb;
+  g.pA = (const double* const*)dp;
+  g.pB = (const double* const*)(dp + nb);
+  g.pC = (double* const*)(dp + 2 * nb);
+  std::vector<const void*> ptrs;
+  for (size_t i = 0; i < nb; ++i) {
+    ptrs.push_back(a[i]);
+    ptrs.push_back(b[i]);
+    ptrs.push_back(c[i]);
+  }
+  int rc = launch_gemm<false>(g, EpiStore{1.0, beta}, st, ptrs);
+  HIP_OK(hipFreeAsync(dp, st));
+  return rc;
+}
+
+// Computes exp(c_r B_{op_r}) for every request on the device.
+int batched_expm(const std::vector<ExpmOp>& ops, const std::vector<ExpmRequest>& reqs,
+                 std::vector<std::vector<char>>& host_keep, hipStream_t st) {
+  const size_t nops = ops.size();
   if (reqs.empty()) return PHIKS_OK;
   // Bh = Bshift / beta with beta a power of two >= ||Bshift||_1 (an exact scaling)
-  double beta[PHIKS_MAX_D];
-  for (int mu = 0; mu < d; ++mu)
-    beta[mu] = norm1[mu] > 0.0 ? std::ldexp(1.0, (int)std::ceil(std::log2(norm1[mu]))) : 1.0;
+  std::vector<double> beta(nops);
+  for (size_t o = 0; o < nops; ++o)
+    beta[o] = ops[o].norm1 > 0.0 ? std::ldexp(1.0, (int)std::ceil(std::log2(ops[o].norm1))) : 1.0;
   // squarings t_r and polynomial argument X_r = g_r Bh with ||X_r||_1 <= theta
   std::vector<int> tsq(reqs.size());
   std::vector<double> gam(reqs.size());
   for (size_t r = 0; r < reqs.size(); ++r) {
-    const int mu = reqs[r].mu;
-    const double x = std::fabs(reqs[r].c) * norm1[mu];
+    const int o = reqs[r].op;
+    const double x = std::fabs(reqs[r].c) * ops[o].norm1;
     int t = (x > kTaylorTheta) ? (int)std::ceil(std::log2(x / kTaylorTheta)) : 0;
     tsq[r] = std::max(t, 0);
-    gam[r] = reqs[r].c * beta[mu] / std::ldexp(1.0, tsq[r]);
+    gam[r] = reqs[r].c * beta[o] / std::ldexp(1.0, tsq[r]);
   }
-  // scratch: per mode Bh^1..Bh^5; per request D_0..D_4 and one squaring buffer
+  // scratch: per operator Bh^1..Bh^5; per request D_0..D_4 and one squaring buffer
   size_t total = 0;
-  std::vector<size_t> mode_off(d), req_off(reqs.size());
-  for (int mu = 0; mu < d; ++mu) { mode_off[mu] = total; total += kTaylorBlocks * sq(P.n[mu]); }
+  std::vector<size_t> op_off(nops), req_off(reqs.size());
+  for (size_t o = 0; o < nops; ++o) { op_off[o] = total; total += kTaylorBlocks * sq(ops[o].n); }
   for (size_t r = 0; r < reqs.size(); ++r) {
     req_off[r] = total;
-    total += (kTaylorBlocks + 1) * sq(P.n[reqs[r].mu]);
+    total += (kTaylorBlocks + 1) * sq(ops[reqs[r].op].n);
   }
   double* scratch = nullptr;
   HIP_OK(hipMallocAsync((void**)&scratch, total * sizeof(double), st));
-  auto pw_ptr = [&](int mu, int k) {  // Bh^k, k = 1..5
-    return scratch + mode_off[mu] + (size_t)(k - 1) * sq(P.n[mu]);
+  auto pw_ptr = [&](size_t o, int k) {  // Bh^k, k = 1..5
+    return scratch + op_off[o] + (size_t)(k - 1) * sq(ops[o].n);
   };
-  auto d_ptr = [&](size_t r, int i) { return scratch + req_off[r] + (size_t)i * sq(P.n[reqs[r].mu]); };
-  for (int mu = 0; mu < d; ++mu) {
-    P.host_keep.emplace_back(sizeof(double) * Bshift[mu].size());
-    double* h = (double*)P.host_keep.back().data();
-    for (size_t e = 0; e < Bshift[mu].size(); ++e) h[e] = Bshift[mu][e] / beta[mu];
-    HIP_OK(hipMemcpyAsync(pw_ptr(mu, 1), h, P.host_keep.back().size(), hipMemcpyHostToDevice, st));
+  auto d_ptr = [&](size_t r, int i) { return scratch + req_off[r] + (size_t)i * sq(ops[reqs[r].op].n); };
+  {
+    size_t hbytes = 0;
+    for (size_t o = 0; o < nops; ++o) hbytes += sizeof(double) * ops[o].Bshift.size();
+    host_keep.emplace_back(hbytes);
+    double* h = (double*)host_keep.back().data();
+    size_t pos = 0;
+    for (size_t o = 0; o < nops; ++o) {
+      for (size_t e = 0; e < ops[o].Bshift.size(); ++e) h[pos + e] = ops[o].Bshift[e] / beta[o];
+      HIP_OK(hipMemcpyAsync(pw_ptr(o, 1), h + pos, sizeof(double) * ops[o].Bshift.size(),
+                            hipMemcpyHostToDevice, st));
+      pos += ops[o].Bshift.size();
+    }
   }
-  auto run_ptr_gemm = [&](std::vector<const double*>& a, std::vector<const double*>& b,
-                          std::vector<double*>& c, int n, double beta_c) -> int {
-    if (a.empty()) return PHIKS_OK;
-    const size_t nb = a.size();
-    P.host_keep.emplace_back(3 * nb * sizeof(void*));
-    void** hp = (void**)P.host_keep.back().data();
-    for (size_t i = 0; i < nb; ++i) {
-      hp[i] = (void*)a[i];
-      hp[nb + i] = (void*)b[i];
-      hp[2 * nb + i] = (void*)c[i];
-    }
-    void** dp = nullptr;
-    HIP_OK(hipMallocAsync((void**)&dp, 3 * nb * sizeof(void*), st));
-    HIP_OK(hipMemcpyAsync(dp, hp, 3 * nb * sizeof(void*), hipMemcpyHostToDevice, st));
-    GemmArgs g = empty_args();
-    g.M = g.N = g.K = n;
-    g.lda = g.ldb = g.ldc = n;
-    g.nb1 = (int)nb;
-    g.pA = (const double* const*)dp;
-    g.pB = (const double* const*)(dp + nb);
-    g.pC = (double* const*)(dp + 2 * nb);
-    std::vector<const void*> ptrs;
-    for (size_t i = 0; i < nb; ++i) {
-      ptrs.push_back(a[i]);
-      ptrs.push_back(b[i]);
-      ptrs.push_back(c[i]);
-    }
-    int rc = launch_gemm<false>(g, EpiStore{1.0, beta_c}, st, ptrs);
-    HIP_OK(hipFreeAsync(dp, st));
-    return rc;
-  };
-  // modes grouped by size for the pointer-array GEMMs
+  // operators grouped by size for the pointer-array GEMMs
   std::vector<int64_t> sizes;
-  for (int mu = 0; mu < d; ++mu)
-    if (std::find(sizes.begin(), sizes.end(), P.n[mu]) == sizes.end()) sizes.push_back(P.n[mu]);
+  for (size_t o = 0; o < nops; ++o)
+    if (std::find(sizes.begin(), sizes.end(), ops[o].n) == sizes.end()) sizes.push_back(ops[o].n);
   // shared powers Bh^k = Bh^(k-1) Bh, k = 2..5
   for (int k = 2; k <= kTaylorBlocks; ++k) {
     for (int64_t nsz : sizes) {
       std::vector<const double*> a, b;
       std::vector<double*> c;
-      for (int mu = 0; mu < d; ++mu) {
-        if (P.n[mu] != nsz) continue;
-        a.push_back(pw_ptr(mu, k - 1));
-        b.push_back(pw_ptr(mu, 1));
-        c.push_back(pw_ptr(mu, k));
+      for (size_t o = 0; o < nops; ++o) {
+        if (ops[o].n != nsz) continue;
+        a.push_back(pw_ptr(o, k - 1));
+        b.push_back(pw_ptr(o, 1));
+        c.push_back(pw_ptr(o, k));
       }
-      RET_IF(run_ptr_gemm(a, b, c, (int)nsz, 0.0));
+      RET_IF(ptr_gemm(a, b, c, (int)nsz, 0.0, host_keep, st));
     }
   }
   // D_i of every request
   std::vector<TaylorJob> jobs(reqs.size());
+  int64_t nmax = 0;
   for (size_t r = 0; r < reqs.size(); ++r) {
-    const int mu = reqs[r].mu;
+    const int o = reqs[r].op;
     TaylorJob& J = jobs[r];
     std::memset(&J, 0, sizeof(J));
-    J.n = (int)P.n[mu];
-    for (int k = 1; k < kTaylorBlocks; ++k) J.pw[k] = pw_ptr(mu, k);
+    J.n = (int)ops[o].n;
+    nmax = std::max(nmax, ops[o].n);
+    for (int k = 1; k < kTaylorBlocks; ++k) J.pw[k] = pw_ptr(o, k);
     double gk = 1.0;  // g^j / j!
     for (int j = 0; j <= kTaylorDegree; ++j) {
       J.coef[j / kTaylorBlocks][j % kTaylorBlocks] = gk;
@@ -212,14 +236,12 @@ int batched_expm(phiks_plan_s& P, const std::vector<std::vector<double>>& Bshift
     }
     for (int i = 0; i < kTaylorBlocks; ++i) J.D[i] = d_ptr(r, i);
   }
-  P.host_keep.emplace_back(jobs.size() * sizeof(TaylorJob));
-  std::memcpy(P.host_keep.back().data(), jobs.data(), P.host_keep.back().size());
+  host_keep.emplace_back(jobs.size() * sizeof(TaylorJob));
+  std::memcpy(host_keep.back().data(), jobs.data(), host_keep.back().size());
   TaylorJob* djobs = nullptr;
   HIP_OK(hipMallocAsync((void**)&djobs, jobs.size() * sizeof(TaylorJob), st));
-  HIP_OK(hipMemcpyAsync(djobs, P.host_keep.back().data(), jobs.size() * sizeof(TaylorJob),
+  HIP_OK(hipMemcpyAsync(djobs, host_keep.back().data(), jobs.size() * sizeof(TaylorJob),
                         hipMemcpyHostToDevice, st));
-  int64_t nmax = 0;
-  for (int mu = 0; mu < d; ++mu) nmax = std::max(nmax, P.n[mu]);
   const unsigned eblocks = (unsigned)std::min<int64_t>((sq(nmax) + 255) / 256, 1024);
   (void)hipGetLastError();
   hipLaunchKernelGGL(taylor_form_kernel, dim3(eblocks, (unsigned)jobs.size()), dim3(256), 0, st,
@@ -231,12 +253,12 @@ int batched_expm(phiks_plan_s& P, const std::vector<std::vector<double>>& Bshift
       std::vector<const double*> a, b;
       std::vector<double*> c;
       for (size_t r = 0; r < reqs.size(); ++r) {
-        if (P.n[reqs[r].mu] != nsz) continue;
+        if (ops[reqs[r].op].n != nsz) continue;
         a.push_back(d_ptr(r, i + 1));
-        b.push_back(pw_ptr(reqs[r].mu, kTaylorBlocks));
+        b.push_back(pw_ptr(reqs[r].op, kTaylorBlocks));
         c.push_back(d_ptr(r, i));
       }
-      RET_IF(run_ptr_gemm(a, b, c, (int)nsz, 1.0));
+      RET_IF(ptr_gemm(a, b, c, (int)nsz, 1.0, host_keep, st));
     }
   }
   // squarings: X <- X^2 (ping-pong through the request's last buffer)
@@ -253,13 +275,13 @@ int batched_expm(phiks_plan_s& P, const std::vector<std::vector<double>>& Bshift
       std::vector<double*> c;
       std::vector<size_t> idx;
       for (size_t r = 0; r < reqs.size(); ++r) {
-        if (P.n[reqs[r].mu] != nsz || tsq[r] <= t) continue;
+        if (ops[reqs[r].op].n != nsz || tsq[r] <= t) continue;
         a.push_back(curp[r]);
         b.push_back(curp[r]);
         c.push_back(othp[r]);
         idx.push_back(r);
       }
-      RET_IF(run_ptr_gemm(a, b, c, (int)nsz, 0.0));
+      RET_IF(ptr_gemm(a, b, c, (int)nsz, 0.0, host_keep, st));
       for (size_t r : idx) std::swap(curp[r], othp[r]);
     }
   }
@@ -268,14 +290,14 @@ int batched_expm(phiks_plan_s& P, const std::vector<std::vector<double>>& Bshift
   for (size_t r = 0; r < reqs.size(); ++r) {
     sj[r].src = curp[r];
     sj[r].dst = reqs[r].dst;
-    sj[r].scale = std::exp(reqs[r].c * sigma[reqs[r].mu]);
-    sj[r].n = (int)P.n[reqs[r].mu];
+    sj[r].scale = std::exp(reqs[r].c * ops[reqs[r].op].sigma);
+    sj[r].n = (int)ops[reqs[r].op].n;
   }
-  P.host_keep.emplace_back(sj.size() * sizeof(ScaleJob));
-  std::memcpy(P.host_keep.back().data(), sj.data(), P.host_keep.back().size());
+  host_keep.emplace_back(sj.size() * sizeof(ScaleJob));
+  std::memcpy(host_keep.back().data(), sj.data(), host_keep.back().size());
   ScaleJob* dsj = nullptr;
   HIP_OK(hipMallocAsync((void**)&dsj, sj.size() * sizeof(ScaleJob), st));
-  HIP_OK(hipMemcpyAsync(dsj, P.host_keep.back().data(), sj.size() * sizeof(ScaleJob),
+  HIP_OK(hipMemcpyAsync(dsj, host_keep.back().data(), sj.size() * sizeof(ScaleJob),
                         hipMemcpyHostToDevice, st));
   (void)hipGetLastError();
   hipLaunchKernelGGL(scale_copy_kernel, dim3(eblocks, (unsigned)sj.size()), dim3(256), 0, st,
@@ -329,6 +351,9 @@ int host_plan(int d, const int64_t* n, const double* const* A, double tau, int p
   return PHIKS_OK;
 }
 
+// quadrature nodes theta_i < 1, each of which needs a Tucker operator
+int plan_nodes(const phiks_plan_s& P) { return (P.p > 0) ? P.q - 1 : 0; }
+
 size_t workspace_doubles(const phiks_plan_s& P) {
   const int64_t N = P.N;
   if (P.task == PHIKS_SAME_VECTOR) {
@@ -337,6 +362,184 @@ size_t workspace_doubles(const phiks_plan_s& P) {
   }
   const int64_t pp = std::max(P.p, 1);
   return (size_t)(5 * pp) * N;
+}
+
+
+// Fills P with the problem and its host plan (no device work).
+int plan_init_host(phiks_plan_s& P, int d, const int64_t* n, const double* const* A, double tau,
+                   int p, int n_scales, double tol, int task, const double* vnorms,
+                   int precision) {
+  int rc = validate_problem(d, n, A, tau, p, n_scales, tol, task, vnorms);
+  if (rc != PHIKS_OK) return rc;
+  if (precision != PHIKS_FP64 && precision != PHIKS_FP32 && precision != PHIKS_BF16X3)
+    return PHIKS_EINVAL;
+  PlanChoice pc;
+  rc = host_plan(d, n, A, tau, p, n_scales, tol, task, vnorms, pc);
+  if (rc != PHIKS_OK) return rc;
+  P.d = d;
+  P.N = 1;
+  for (int mu = 0; mu < d; ++mu) { P.n[mu] = n[mu]; P.N *= n[mu]; }
+  P.tau = tau;
+  P.p = p;
+  P.ns = n_scales;
+  P.task = task;
+  P.precision = precision;
+  P.s = pc.s;
+  P.q = pc.q;
+  P.t_paper = pc.tucker_paper;
+  if (p > 0) gll_rule(pc.q, P.theta, P.w);
+  const int nodes = plan_nodes(P);
+  if (task == PHIKS_SAME_VECTOR) P.t_exec = nodes + pc.s * p + n_scales;
+  else P.t_exec = nodes * p + pc.s * p + n_scales;
+  return PHIKS_OK;
+}
+
+// Plan-lifetime device memory in doubles: per mode the node matrices and exp(B/2^j),
+// j = 0..s, then (mixed precision) their FP32 copies, rounded up to whole doubles.
+size_t plan_device_doubles(const phiks_plan_s& P) {
+  const int nodes = plan_nodes(P);
+  size_t total = 0;
+  for (int mu = 0; mu < P.d; ++mu) total += (size_t)(nodes + P.s + 1) * sq(P.n[mu]);
+  if (P.precision != PHIKS_FP64)
+    for (int mu = 0; mu < P.d; ++mu)
+      total += ((size_t)nodes * sq(P.n[mu]) + 3) / 2 + 1 + ((size_t)(P.s + 1) * sq(P.n[mu]) + 3) / 2 + 1;
+  return total;
+}
+
+// Points P's matrices into base (plan_device_doubles(P) doubles, 16-byte aligned).
+void plan_assign(phiks_plan_s& P, double* base) {
+  const int nodes = plan_nodes(P);
+  size_t total = 0;
+  for (int mu = 0; mu < P.d; ++mu) {
+    P.Lnode[mu] = base + total;
+    total += (size_t)nodes * sq(P.n[mu]);
+    P.E[mu] = base + total;
+    total += (size_t)(P.s + 1) * sq(P.n[mu]);
+  }
+  if (P.precision != PHIKS_FP64) {
+    for (int mu = 0; mu < P.d; ++mu) {
+      P.Lnode32[mu] = (float*)(base + total);
+      total += ((size_t)nodes * sq(P.n[mu]) + 3) / 2 + 1;
+      P.E32[mu] = (float*)(base + total);
+      total += ((size_t)(P.s + 1) * sq(P.n[mu]) + 3) / 2 + 1;
+    }
+  }
+}
+
+// Batched dst_i = scale_i * src_i over n_i x n_i entries.
+int launch_scale_jobs(const std::vector<ScaleJob>& sj, std::vector<std::vector<char>>& host_keep,
+                      hipStream_t st) {
+  if (sj.empty()) return PHIKS_OK;
+  host_keep.emplace_back(sj.size() * sizeof(ScaleJob));
+  std::memcpy(host_keep.back().data(), sj.data(), host_keep.back().size());
+  ScaleJob* dsj = nullptr;
+  HIP_OK(hipMallocAsync((void**)&dsj, sj.size() * sizeof(ScaleJob), st));
+  HIP_OK(hipMemcpyAsync(dsj, host_keep.back().data(), sj.size() * sizeof(ScaleJob),
+                        hipMemcpyHostToDevice, st));
+  int64_t nmax = 0;
+  for (const ScaleJob& j : sj) nmax = std::max<int64_t>(nmax, j.n);
+  (void)hipGetLastError();
+  hipLaunchKernelGGL(scale_copy_kernel, dim3((unsigned)std::min<int64_t>((sq(nmax) + 255) / 256, 1024),
+                                             (unsigned)sj.size()),
+                     dim3(256), 0, st, dsj);
+  CHECK_LAUNCH();
+  HIP_OK(hipFreeAsync(dsj, st));
+  return PHIKS_OK;
+}
+
+// Builds the small exponentials of every plan in one device pass (Section 3.1): one
+// batched_expm over all their operators for the node matrices exp((1-theta_i) B/2^s)
+// (theta_1 = 0 gives exp(B/2^s) itself) or exp(B/2^s) alone when p = 0, then
+// exp(B/2^(j-1)) = exp(B/2^j)^2 for j = s..1 grouped over plans and modes of equal
+// size, then the FP32 copies of the mixed-precision plans.  A[i] are plan i's host
+// matrices; every plan's device pointers must already be assigned.
+int build_plan_matrices(const std::vector<phiks_plan_s*>& plans,
+                        const std::vector<const double* const*>& A,
+                        std::vector<std::vector<char>>& host_keep, hipStream_t st) {
+  std::vector<ExpmOp> ops;
+  std::vector<ExpmRequest> reqs;
+  for (size_t i = 0; i < plans.size(); ++i) {
+    const phiks_plan_s& P = *plans[i];
+    const int nodes = plan_nodes(P);
+    const double inv2s = std::ldexp(1.0, -P.s);
+    for (int mu = 0; mu < P.d; ++mu) {
+      // shifted operator B - sigma I, sigma = tr(B)/n (the shift remark of Section 3.1)
+      const int64_t m = P.n[mu];
+      ExpmOp op;
+      op.n = m;
+      op.Bshift.resize(m * m);
+      double tr = 0.0;
+      for (int64_t k = 0; k < m; ++k) tr += A[i][mu][k * m + k];
+      op.sigma = P.tau * tr / m;
+      for (int64_t e = 0; e < m * m; ++e) op.Bshift[e] = P.tau * A[i][mu][e];
+      for (int64_t k = 0; k < m; ++k) op.Bshift[k * m + k] -= op.sigma;
+      double nrm = 0.0;
+      for (int64_t c = 0; c < m; ++c) {
+        double col = 0.0;
+        for (int64_t r = 0; r < m; ++r) col += std::fabs(op.Bshift[r * m + c]);
+        nrm = std::max(nrm, col);
+      }
+      op.norm1 = nrm;
+      const int o = (int)ops.size();
+      ops.push_back(std::move(op));
+      if (nodes > 0) {
+        for (int k = 0; k < nodes; ++k)
+          reqs.push_back({o, (1.0 - P.theta[k]) * inv2s, P.Lnode[mu] + (size_t)k * sq(m)});
+      } else {
+        reqs.push_back({o, inv2s, P.E[mu] + (size_t)P.s * sq(m)});
+      }
+    }
+  }
+  RET_IF(batched_expm(ops, reqs, host_keep, st));
+  // exp(B/2^s) = the node matrix of theta_1 = 0
+  std::vector<ScaleJob> copies;
+  int smax = 0;
+  for (phiks_plan_s* P : plans) {
+    smax = std::max(smax, P->s);
+    if (plan_nodes(*P) == 0) continue;
+    for (int mu = 0; mu < P->d; ++mu)
+      copies.push_back({P->Lnode[mu], P->E[mu] + (size_t)P->s * sq(P->n[mu]), 1.0, (int)P->n[mu]});
+  }
+  RET_IF(launch_scale_jobs(copies, host_keep, st));
+  // exp(B/2^(j-1)) = exp(B/2^j)^2, j = s..1, grouped by size
+  for (int j = smax; j >= 1; --j) {
+    std::vector<int64_t> sizes;
+    for (phiks_plan_s* P : plans)
+      if (P->s >= j)
+        for (int mu = 0; mu < P->d; ++mu)
+          if (std::find(sizes.begin(), sizes.end(), P->n[mu]) == sizes.end()) sizes.push_back(P->n[mu]);
+    for (int64_t nsz : sizes) {
+      std::vector<const double*> a;
+      std::vector<double*> c;
+      for (phiks_plan_s* P : plans) {
+        if (P->s < j) continue;
+        for (int mu = 0; mu < P->d; ++mu) {
+          if (P->n[mu] != nsz) continue;
+          a.push_back(P->E[mu] + (size_t)j * sq(nsz));
+          c.push_back(P->E[mu] + (size_t)(j - 1) * sq(nsz));
+        }
+      }
+      RET_IF(ptr_gemm(a, a, c, (int)nsz, 0.0, host_keep, st));
+    }
+  }
+  // FP32 copies of every node matrix and of exp(B/2^j): the mixed-precision paths
+  // multiply by these; everything else stays FP64
+  for (phiks_plan_s* P : plans) {
+    if (P->precision == PHIKS_FP64) continue;
+    const int nodes = plan_nodes(*P);
+    for (int mu = 0; mu < P->d; ++mu) {
+      const int64_t ln = (int64_t)nodes * sq(P->n[mu]);
+      const int64_t le = (int64_t)(P->s + 1) * sq(P->n[mu]);
+      (void)hipGetLastError();
+      if (ln > 0)
+        hipLaunchKernelGGL(to_f32_kernel, dim3((unsigned)std::min<int64_t>((ln + 255) / 256, 4096)),
+                           dim3(256), 0, st, (const double*)P->Lnode[mu], P->Lnode32[mu], ln);
+      hipLaunchKernelGGL(to_f32_kernel, dim3((unsigned)std::min<int64_t>((le + 255) / 256, 4096)),
+                         dim3(256), 0, st, (const double*)P->E[mu], P->E32[mu], le);
+      CHECK_LAUNCH();
+    }
+  }
+  return PHIKS_OK;
 }
 
 }  // namespace
@@ -403,147 +606,29 @@ int phiks_plan(int d, const int64_t* n, const double* const* A, double tau, int 
                void* hip_stream, phiks_plan_t* out) {
   if (!out) return PHIKS_EINVAL;
   *out = nullptr;
-  int rc = validate_problem(d, n, A, tau, p, n_scales, tol, task, vnorms);
-  if (rc != PHIKS_OK) return rc;
-  if (precision != PHIKS_FP64 && precision != PHIKS_FP32 && precision != PHIKS_BF16X3)
-    return PHIKS_EINVAL;
-  PlanChoice pc;
-  rc = host_plan(d, n, A, tau, p, n_scales, tol, task, vnorms, pc);
-  if (rc != PHIKS_OK) return rc;
-
   phiks_plan_s* P = new (std::nothrow) phiks_plan_s;
   if (!P) return PHIKS_ENOMEM;
-  P->d = d;
-  P->N = 1;
-  for (int mu = 0; mu < d; ++mu) { P->n[mu] = n[mu]; P->N *= n[mu]; }
-  P->tau = tau;
-  P->p = p;
-  P->ns = n_scales;
-  P->task = task;
-  P->precision = precision;
-  P->s = pc.s;
-  P->q = pc.q;
-  P->t_paper = pc.tucker_paper;
-  if (p > 0) gll_rule(pc.q, P->theta, P->w);
-  const int nodes = (p > 0) ? pc.q - 1 : 0;  // nodes with theta < 1 need a Tucker
-  if (task == PHIKS_SAME_VECTOR) P->t_exec = nodes + pc.s * p + n_scales;
-  else P->t_exec = nodes * p + pc.s * p + n_scales;
+  int rc = plan_init_host(*P, d, n, A, tau, p, n_scales, tol, task, vnorms, precision);
+  if (rc != PHIKS_OK) {
+    delete P;
+    return rc;
+  }
   hipStream_t st = (hipStream_t)hip_stream;
   auto fail = [&](int code) {
     phiks_plan_destroy(P);
     return code;
   };
   if (hipGetDevice(&P->device) != hipSuccess) { set_error("hipGetDevice failed"); return fail(PHIKS_EDEVICE); }
-
-  // plan-lifetime device memory: node matrices and exp(B/2^j), j = 0..s
-  size_t total = 0;
-  size_t offL[PHIKS_MAX_D], offE[PHIKS_MAX_D], offL32[PHIKS_MAX_D], offE32[PHIKS_MAX_D];
-  for (int mu = 0; mu < d; ++mu) {
-    offL[mu] = total;
-    total += (size_t)nodes * sq(n[mu]);
-    offE[mu] = total;
-    total += (size_t)(pc.s + 1) * sq(n[mu]);
-  }
-  const size_t total64 = total;  // in doubles; FP32 copies follow (counted in doubles, rounded up)
-  if (precision != PHIKS_FP64) {
-    for (int mu = 0; mu < d; ++mu) {
-      offL32[mu] = total * 2;  // float index
-      total += ((size_t)nodes * sq(n[mu]) + 3) / 2 + 1;
-      offE32[mu] = total * 2;
-      total += ((size_t)(pc.s + 1) * sq(n[mu]) + 3) / 2 + 1;
-    }
-  }
   P->stream = st;
-  if (hipMallocAsync(&P->dmem, std::max<size_t>(total, 1) * sizeof(double), st) != hipSuccess) {
+  if (hipMallocAsync(&P->dmem, std::max<size_t>(plan_device_doubles(*P), 1) * sizeof(double), st) !=
+      hipSuccess) {
     P->dmem = nullptr;
     set_error("hipMallocAsync of plan matrices failed");
     return fail(PHIKS_ENOMEM);
   }
-  double* base = (double*)P->dmem;
-  for (int mu = 0; mu < d; ++mu) {
-    P->Lnode[mu] = base + offL[mu];
-    P->E[mu] = base + offE[mu];
-    if (precision != PHIKS_FP64) {
-      P->Lnode32[mu] = (float*)P->dmem + offL32[mu];
-      P->E32[mu] = (float*)P->dmem + offE32[mu];
-    }
-  }
-  (void)total64;
-  // shifted operators B_mu - sigma_mu I, sigma_mu = tr(B_mu)/n_mu (the shift remark
-  // of Section 3.1), and their 1-norms for the scaling choice
-  std::vector<std::vector<double>> Bs(d);
-  double sigma[PHIKS_MAX_D], norm1[PHIKS_MAX_D];
-  for (int mu = 0; mu < d; ++mu) {
-    const int64_t m = n[mu];
-    Bs[mu].resize(m * m);
-    double tr = 0.0;
-    for (int64_t i = 0; i < m; ++i) tr += A[mu][i * m + i];
-    sigma[mu] = tau * tr / m;
-    for (int64_t e = 0; e < m * m; ++e) Bs[mu][e] = tau * A[mu][e];
-    for (int64_t i = 0; i < m; ++i) Bs[mu][i * m + i] -= sigma[mu];
-    double nrm = 0.0;
-    for (int64_t j = 0; j < m; ++j) {
-      double col = 0.0;
-      for (int64_t i = 0; i < m; ++i) col += std::fabs(Bs[mu][i * m + j]);
-      nrm = std::max(nrm, col);
-    }
-    norm1[mu] = nrm;
-  }
-  // requests: node matrices exp((1-theta_i) B / 2^s) for theta_i < 1 (theta_0 = 0
-  // gives exp(B/2^s) itself), or exp(B/2^s) alone when there is no quadrature
-  std::vector<ExpmRequest> reqs;
-  const double inv2s = std::ldexp(1.0, -pc.s);
-  for (int mu = 0; mu < d; ++mu) {
-    if (nodes > 0) {
-      for (int i = 0; i < nodes; ++i)
-        reqs.push_back({mu, (1.0 - P->theta[i]) * inv2s, P->Lnode[mu] + (size_t)i * sq(n[mu])});
-    } else {
-      reqs.push_back({mu, inv2s, P->E[mu] + (size_t)pc.s * sq(n[mu])});
-    }
-  }
-  rc = batched_expm(*P, Bs, sigma, norm1, reqs, st);
+  plan_assign(*P, (double*)P->dmem);
+  rc = build_plan_matrices({P}, {A}, P->host_keep, st);
   if (rc != PHIKS_OK) return fail(rc);
-  if (nodes > 0) {
-    for (int mu = 0; mu < d; ++mu) {
-      if (hipMemcpyAsync(P->E[mu] + (size_t)pc.s * sq(n[mu]), P->Lnode[mu],
-                         sq(n[mu]) * sizeof(double), hipMemcpyDeviceToDevice, st) != hipSuccess) {
-        set_error("hipMemcpyAsync failed");
-        return fail(PHIKS_EDEVICE);
-      }
-    }
-  }
-  // exp(B/2^(j-1)) = exp(B/2^j)^2, j = s..1 (Section 3.1)
-  for (int j = pc.s; j >= 1; --j) {
-    for (int mu = 0; mu < d; ++mu) {
-      GemmArgs g = empty_args();
-      const int64_t m = n[mu];
-      g.M = g.N = g.K = (int)m;
-      g.lda = g.ldb = g.ldc = m;
-      g.A = P->E[mu] + (size_t)j * sq(m);
-      g.B = g.A;
-      g.C = P->E[mu] + (size_t)(j - 1) * sq(m);
-      rc = launch_gemm<false>(g, EpiStore{1.0, 0.0}, st);
-      if (rc != PHIKS_OK) return fail(rc);
-    }
-  }
-  if (precision != PHIKS_FP64) {
-    // FP32 copies of every node matrix and of exp(B/2^j): the mixed-precision path
-    // multiplies by these; everything else stays FP64
-    for (int mu = 0; mu < d; ++mu) {
-      const int64_t ln = (int64_t)nodes * sq(n[mu]);
-      const int64_t le = (int64_t)(pc.s + 1) * sq(n[mu]);
-      (void)hipGetLastError();
-      if (ln > 0)
-        hipLaunchKernelGGL(to_f32_kernel, dim3((unsigned)std::min<int64_t>((ln + 255) / 256, 4096)),
-                           dim3(256), 0, st, (const double*)P->Lnode[mu], P->Lnode32[mu], ln);
-      hipLaunchKernelGGL(to_f32_kernel, dim3((unsigned)std::min<int64_t>((le + 255) / 256, 4096)),
-                         dim3(256), 0, st, (const double*)P->E[mu], P->E32[mu], le);
-      if (hipGetLastError() != hipSuccess) {
-        set_error("conversion kernel launch failed");
-        return fail(PHIKS_EDEVICE);
-      }
-    }
-  }
   *out = P;
   return PHIKS_OK;
 }
@@ -851,3 +936,5 @@ int phiks_combine(phiks_plan_t plan, const double* const* v, double* out, void* 
 }
 
 }  // extern "C"
+
+#include "batch.hpp"

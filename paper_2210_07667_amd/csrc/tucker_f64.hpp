@@ -51,7 +51,7 @@ bool vec_ok(const GemmArgs& g, bool kcontig, const std::vector<const void*>& ext
   return true;
 }
 
-template <int BM, int BN, int WM, int WN, bool KC, bool VEC, bool PTRS, class Epi>
+template <int BM, int BN, int WM, int WN, bool KC, bool VEC, class Epi>
 int launch_cfg(GemmArgs g, const Epi& epi, hipStream_t st) {
   g.tiles_m = (g.M + BM - 1) / BM;
   g.tiles_n = (g.N + BN - 1) / BN;
@@ -71,7 +71,7 @@ int launch_cfg(GemmArgs g, const Epi& epi, hipStream_t st) {
     }
   }
   (void)hipGetLastError();  // clear a stale error left by an unrelated earlier call
-  hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, WM, WN, KC, VEC, Epi, PTRS>),
+  hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, WM, WN, KC, VEC, Epi>),
                      dim3((unsigned)g.total_tiles), dim3(256), 0, st, g, epi);
   CHECK_LAUNCH();
   if (ea && eb) {
@@ -82,62 +82,52 @@ int launch_cfg(GemmArgs g, const Epi& epi, hipStream_t st) {
   return PHIKS_OK;
 }
 
-template <bool KC, bool VEC, bool PTRS, class Epi>
+template <bool KC, bool VEC, class Epi>
 int launch_tile(const GemmArgs& g, const Epi& epi, hipStream_t st) {
   switch (pick_tile(g)) {
 #if PHIKS_BIG_TILE == 1
-    case Tile::T128x128: return launch_cfg<128, 128, 64, 64, KC, VEC, PTRS>(g, epi, st);
+    case Tile::T128x128: return launch_cfg<128, 128, 64, 64, KC, VEC>(g, epi, st);
 #endif
-    case Tile::T128x64: return launch_cfg<128, 64, 64, 32, KC, VEC, PTRS>(g, epi, st);
-    case Tile::T64x128: return launch_cfg<64, 128, 32, 64, KC, VEC, PTRS>(g, epi, st);
-    case Tile::T64x64: return launch_cfg<64, 64, 32, 32, KC, VEC, PTRS>(g, epi, st);
-    default: return launch_cfg<32, 32, 16, 16, KC, VEC, PTRS>(g, epi, st);
+    case Tile::T128x64: return launch_cfg<128, 64, 64, 32, KC, VEC>(g, epi, st);
+    case Tile::T64x128: return launch_cfg<64, 128, 32, 64, KC, VEC>(g, epi, st);
+    case Tile::T64x64: return launch_cfg<64, 64, 32, 32, KC, VEC>(g, epi, st);
+    default: return launch_cfg<32, 32, 16, 16, KC, VEC>(g, epi, st);
   }
 }
 
-// Pointer-array GEMMs (pA != nullptr) exist only in the n-contiguous form with a
-// plain store (the batched products of the small exponentials).
 template <bool KC, class Epi>
 int launch_gemm(const GemmArgs& g, const Epi& epi, hipStream_t st,
                 const std::vector<const void*>& extra_ptrs = {}) {
-  const bool vec = vec_ok(g, KC, extra_ptrs);
-  if (g.pA != nullptr) {
-    if constexpr (!KC && std::is_same<Epi, EpiStore>::value) {
-      if (g.nb0 != 1) {
-        set_error("pointer-array GEMM needs nb0 == 1");
-        return PHIKS_EINVAL;
-      }
-      return vec ? launch_tile<KC, true, true>(g, epi, st) : launch_tile<KC, false, true>(g, epi, st);
-    } else {
-      set_error("pointer-array GEMM needs the n-contiguous form and a plain store");
-      return PHIKS_EINVAL;
-    }
+  if (g.pA != nullptr && g.nb0 != 1) {
+    set_error("pointer-array GEMM needs nb0 == 1");
+    return PHIKS_EINVAL;
   }
-  return vec ? launch_tile<KC, true, false>(g, epi, st) : launch_tile<KC, false, false>(g, epi, st);
+  if (vec_ok(g, KC, extra_ptrs)) return launch_tile<KC, true>(g, epi, st);
+  return launch_tile<KC, false>(g, epi, st);
 }
 
 // ---------------------------------------------------------- Tucker operator
-// Applies, to nbatch tensors in_b = in + b*in_stride, the Tucker operator with the
-// matrices L[mu] + b*l_stride[mu] (Section 2, eq. tucker), writing the last mode
-// through the epilogue into out (batch b at out + b*N).  ta/tb: nbatch*N scratch.
-// The result of mode mu (< d) goes to ta for odd mu and tb for even mu; out must be
-// the buffer not read by the last mode.
-template <class Epi>
-int tucker(const phiks_plan_s& P, const double* in, int64_t in_stride,
-           double* const* L, const int64_t* l_stride, int nbatch, double* out,
-           double* ta, double* tb, const Epi& epi, hipStream_t st) {
-  const int d = P.d;
-  const int64_t N = P.N;
+// GEMM views of the d mu-mode products of one Tucker operator (Section 2, eq. tucker;
+// Lemma 1 for the vec order) applied to nbatch tensors in_b = in + b*in_stride with
+// the matrices L[mu] + b*l_stride[mu]; the last mode writes batch b at out + b*N.
+// ta/tb: nbatch*N scratch; mode mu (< d) writes ta for odd mu and tb for even mu,
+// so out must be the buffer the last mode does not read.  Pointers are copied, not
+// dereferenced: the mixed-precision chains reuse these views with FP32 buffers.
+// Every execution path (single, mixed, grouped over many problems) builds its
+// launches from these views, so their per-element arithmetic is the same.
+void tucker_args(int d, const int64_t* n, int64_t N, const double* in, int64_t in_stride,
+                 double* const* L, const int64_t* l_stride, int nbatch, double* out,
+                 double* ta, double* tb, GemmArgs* gs) {
   const double* cur = in;
   int64_t cur_stride = in_stride;
   for (int mu = 1; mu <= d; ++mu) {
-    const int64_t nm = P.n[mu - 1];
+    const int64_t nm = n[mu - 1];
     int64_t nlo = 1, nhi = 1;
-    for (int k = 0; k < mu - 1; ++k) nlo *= P.n[k];
-    for (int k = mu; k < d; ++k) nhi *= P.n[k];
-    const bool last = (mu == d);
-    double* dst = last ? out : ((mu % 2 == 1) ? ta : tb);
-    GemmArgs g = empty_args();
+    for (int k = 0; k < mu - 1; ++k) nlo *= n[k];
+    for (int k = mu; k < d; ++k) nhi *= n[k];
+    double* dst = (mu == d) ? out : ((mu % 2 == 1) ? ta : tb);
+    GemmArgs& g = gs[mu - 1];
+    g = empty_args();
     g.nb1 = nbatch;
     if (mu == 1) {
       // W[m][i] = sum_j X[m][j] L[i][j], rows m < n_>
@@ -153,8 +143,6 @@ int tucker(const phiks_plan_s& P, const double* in, int64_t in_stride,
       g.sA1 = cur_stride;
       g.sB1 = l_stride[0];
       g.sC1 = N;
-      if (last) RET_IF((launch_gemm<true>(g, epi, st)));
-      else RET_IF((launch_gemm<true>(g, EpiStore{1.0, 0.0}, st)));
     } else {
       // W_b[i][a] = sum_j L[i][j] X_b[j][a], batch b < n_>
       g.M = (int)nm;
@@ -173,11 +161,28 @@ int tucker(const phiks_plan_s& P, const double* in, int64_t in_stride,
       g.sA1 = l_stride[mu - 1];
       g.sB1 = cur_stride;
       g.sC1 = N;
-      if (last) RET_IF((launch_gemm<false>(g, epi, st)));
-      else RET_IF((launch_gemm<false>(g, EpiStore{1.0, 0.0}, st)));
     }
     cur = dst;
     cur_stride = N;
+  }
+}
+
+// Applies the Tucker operator of tucker_args, the last mode through `epi`.
+template <class Epi>
+int tucker(const phiks_plan_s& P, const double* in, int64_t in_stride,
+           double* const* L, const int64_t* l_stride, int nbatch, double* out,
+           double* ta, double* tb, const Epi& epi, hipStream_t st) {
+  GemmArgs gs[PHIKS_MAX_D];
+  tucker_args(P.d, P.n, P.N, in, in_stride, L, l_stride, nbatch, out, ta, tb, gs);
+  for (int mu = 1; mu <= P.d; ++mu) {
+    const bool last = (mu == P.d);
+    if (mu == 1) {
+      if (last) RET_IF((launch_gemm<true>(gs[0], epi, st)));
+      else RET_IF((launch_gemm<true>(gs[0], EpiStore{1.0, 0.0}, st)));
+    } else {
+      if (last) RET_IF((launch_gemm<false>(gs[mu - 1], epi, st)));
+      else RET_IF((launch_gemm<false>(gs[mu - 1], EpiStore{1.0, 0.0}, st)));
+    }
   }
   return PHIKS_OK;
 }

@@ -133,57 +133,24 @@ int launch_mixed(const GemmArgs& g, const Epi& epi, hipStream_t st) {
 // copies of the matrices.
 template <int PREC, class Epi>
 int tucker_mixed(const phiks_plan_s& P, const double* in, int64_t in_stride,
-             float* const* L, const int64_t* l_stride, int nbatch, double* out,
-             double* ta, double* tb, const Epi& epi, hipStream_t st) {
-  const int d = P.d;
-  const int64_t N = P.N;
-  const void* cur = in;
-  int64_t cur_stride = in_stride;
-  for (int mu = 1; mu <= d; ++mu) {
-    const int64_t nm = P.n[mu - 1];
-    int64_t nlo = 1, nhi = 1;
-    for (int k = 0; k < mu - 1; ++k) nlo *= P.n[k];
-    for (int k = mu; k < d; ++k) nhi *= P.n[k];
-    const bool last = (mu == d);
-    void* dst = last ? (void*)out : (void*)((mu % 2 == 1) ? ta : tb);
-    GemmArgs g = empty_args();
-    g.nb1 = nbatch;
+                 float* const* L, const int64_t* l_stride, int nbatch, double* out,
+                 double* ta, double* tb, const Epi& epi, hipStream_t st) {
+  GemmArgs gs[PHIKS_MAX_D];
+  double* Ld[PHIKS_MAX_D];
+  for (int mu = 0; mu < P.d; ++mu) Ld[mu] = reinterpret_cast<double*>(L[mu]);
+  tucker_args(P.d, P.n, P.N, in, in_stride, Ld, l_stride, nbatch, out, ta, tb, gs);
+  for (int mu = 1; mu <= P.d; ++mu) {
+    const bool last = (mu == P.d);
+    const GemmArgs& g = gs[mu - 1];
     if (mu == 1) {
-      g.M = (int)nhi;
-      g.N = (int)nm;
-      g.K = (int)nm;
-      g.A = reinterpret_cast<const double*>(cur);
-      g.lda = nm;
-      g.B = reinterpret_cast<const double*>(L[0]);
-      g.ldb = nm;
-      g.C = reinterpret_cast<double*>(dst);
-      g.ldc = nm;
-      g.sA1 = cur_stride;
-      g.sB1 = l_stride[0];
-      g.sC1 = N;
+      // A: the FP64 input (converted on the way into LDS), B: the FP32 matrix
       if (last) RET_IF((launch_mixed<PREC, true, double, double>(g, epi, st)));
       else RET_IF((launch_mixed<PREC, true, double, float>(g, EpiStoreT<float>{1.0, 0.0}, st)));
     } else {
-      g.M = (int)nm;
-      g.N = (int)nlo;
-      g.K = (int)nm;
-      g.A = reinterpret_cast<const double*>(L[mu - 1]);
-      g.lda = nm;
-      g.B = reinterpret_cast<const double*>(cur);
-      g.ldb = nlo;
-      g.C = reinterpret_cast<double*>(dst);
-      g.ldc = nlo;
-      g.nb0 = (int)nhi;
-      g.sB0 = nm * nlo;
-      g.sC0 = nm * nlo;
-      g.sA1 = l_stride[mu - 1];
-      g.sB1 = cur_stride;
-      g.sC1 = N;
+      // A: the FP32 matrix, B: the FP32 intermediate
       if (last) RET_IF((launch_mixed<PREC, false, float, double>(g, epi, st)));
       else RET_IF((launch_mixed<PREC, false, float, float>(g, EpiStoreT<float>{1.0, 0.0}, st)));
     }
-    cur = dst;
-    cur_stride = N;
   }
   return PHIKS_OK;
 }

@@ -154,3 +154,31 @@ def test_host_only_calls_on_null_plan():
     assert lib.phiks_apply(None, None, None, None, 0, None) == ph.PHIKS_EINVAL
     lib.phiks_plan_destroy.argtypes = [ctypes.c_void_p]
     lib.phiks_plan_destroy(None)
+
+
+def test_batch_plan_rejects_bad_problems_before_device_work():
+    problems = workloads.config_batch(count=6, seed=5)
+    taus = [b.tau for b in problems]
+    taus[4] = -1.0
+    with pytest.raises(ph.PhiksError) as e:
+        ph.phiks_batch_plan([b.A for b in problems], taus, 3, 1, 1e-10)
+    assert e.value.status == ph.PHIKS_EINVAL
+    assert "problem 4" in str(e.value)
+    with pytest.raises(ph.PhiksError) as e:
+        ph.phiks_batch_plan([b.A for b in problems], [b.tau for b in problems], 3, 1, 1e-10,
+                            precision=ph.PHIKS_FP32)
+    assert e.value.status == ph.PHIKS_EINVAL
+    with pytest.raises(ValueError):
+        ph.phiks_batch_plan([b.A for b in problems], [b.tau for b in problems[:-1]], 3, 1, 1e-10)
+
+
+def test_batched_workload_shapes():
+    """The batched workload has the advertised mix: d in {2, 3}, sizes from the set,
+    tau in [1e-4, 1e-2]."""
+    problems = workloads.config_batch()
+    assert len(problems) == 512
+    ds = [len(b.n) for b in problems]
+    assert set(ds) == {2, 3} and 200 < ds.count(3) < 312
+    assert all(m in workloads.BATCH_SIZES for b in problems for m in b.n)
+    assert all(1e-4 <= b.tau <= 1e-2 for b in problems)
+    assert all(b.A[0].shape == (b.n[0], b.n[0]) and b.v.shape == (b.N,) for b in problems)

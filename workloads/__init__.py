@@ -27,7 +27,7 @@ import numpy as np
 __all__ = [
     "fd2_dirichlet", "central_adv_dirichlet", "adr_1d", "cheb_d2_dirichlet",
     "randn_vec", "uniform_vec", "Workload", "config_fd2_2d", "config_allen_cahn_3d",
-    "config_adr_3d", "validation_table1",
+    "config_adr_3d", "validation_table1", "BatchProblem", "config_batch",
 ]
 
 
@@ -157,3 +157,42 @@ def validation_table1(d: int, n: int):
         v = np.kron(f, v)          # i_1 fastest: new (slower) index on the left
     v = 4096.0 * (1.0 + 1.0j) * v
     return [A.copy() for _ in range(d)], v
+
+
+@dataclass
+class BatchProblem:
+    """One problem of a batch: phi_0..phi_p of tau K on v, K = A_d (+) ... (+) A_1."""
+    n: List[int]
+    A: List[np.ndarray]
+    tau: float
+    v: np.ndarray
+
+    @property
+    def N(self) -> int:
+        return int(np.prod(self.n))
+
+
+BATCH_SIZES = (16, 24, 32, 48, 64, 96, 128)
+
+
+def config_batch(count: int = 512, seed: int = 3, sizes: Sequence[int] = BATCH_SIZES,
+                 tau_range=(1e-4, 1e-2)) -> List[BatchProblem]:
+    """Many uneven problems: d in {2, 3} with equal probability, each n_mu drawn
+    uniformly from `sizes`, A_mu the Dirichlet Chebyshev second-derivative matrix of
+    size n_mu, tau log-uniform in tau_range, v ~ N(0, 1).  Shared settings of such a
+    batch: p = 3, one scale, tolerance 2^-53 ||v||_2."""
+    rng = np.random.default_rng(seed)
+    cache = {}
+    out = []
+    for _ in range(count):
+        d = int(rng.integers(2, 4))
+        n = [int(x) for x in rng.choice(np.asarray(sizes), size=d)]
+        tau = float(np.exp(rng.uniform(np.log(tau_range[0]), np.log(tau_range[1]))))
+        for m in n:
+            if m not in cache:
+                cache[m] = cheb_d2_dirichlet(m)
+        vseed = int(rng.integers(0, 2 ** 31 - 1))
+        out.append(BatchProblem(n=n, A=[cache[m].copy() for m in n], tau=tau,
+                                v=randn_vec(n, vseed)))
+    return out
+
