@@ -82,6 +82,64 @@ def cpu_baseline(w, plan_info):
             "seconds": t2 - t0}
 
 
+def batched_section(ph, reps=3):
+    """The 512-problem batched workload (d in {2, 3}, n_mu in 16..128, Chebyshev D^2,
+    tau log-uniform, phi_0..phi_3): one phiks_batch_apply against the same problems
+    run one by one through phiks_apply (plans built beforehand in both cases)."""
+    import workloads
+    problems = workloads.config_batch()
+    norms = [float(np.linalg.norm(b.v)) for b in problems]
+    tp0 = time.perf_counter()
+    batch = ph.phiks_batch_plan([b.A for b in problems], [b.tau for b in problems], 3, 1,
+                                2.0 ** -53, vnorms=norms)
+    ph.synchronize()
+    plan_s = time.perf_counter() - tp0
+    dv = [ph.DeviceArray.from_numpy(b.v) for b in problems]
+    outs = [ph.DeviceArray(4 * b.N) for b in problems]
+    ws = ph.DeviceArray(batch.workspace_size() // 8 + 1)
+    vp, op = [v.ptr for v in dv], [o.ptr for o in outs]
+    ph.phiks_batch_apply(batch, vp, op, ws.ptr, ws.nbytes)
+    ph.synchronize()
+    ph.phiks_kernel_timing_read()
+    ph.phiks_kernel_timing(True)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ph.phiks_batch_apply(batch, vp, op, ws.ptr, ws.nbytes)
+    ph.synchronize()
+    batch_ms = (time.perf_counter() - t0) * 1e3 / reps
+    ph.phiks_kernel_timing(False)
+    k_ms, k_launch, k_flops = ph.phiks_kernel_timing_read()
+    smax = max(batch.info(i)["s"] for i in range(len(problems)))
+    batch.close()
+    ws.free()
+    # the same problems through the single-problem path, one call each
+    plans = [ph.phiks_plan(b.A, b.tau, 3, 1, 2.0 ** -53, "same_vector", [nv])
+             for b, nv in zip(problems, norms)]
+    wsz = max(pl.workspace_size() for pl in plans)
+    ws1 = ph.DeviceArray(wsz // 8 + 1)
+    for pl, v, o in zip(plans, vp, op):
+        ph.phiks_apply(pl, v, o, ws1.ptr, ws1.nbytes)
+    ph.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        for pl, v, o in zip(plans, vp, op):
+            ph.phiks_apply(pl, v, o, ws1.ptr, ws1.nbytes)
+    ph.synchronize()
+    seq_ms = (time.perf_counter() - t0) * 1e3 / reps
+    for pl in plans:
+        pl.close()
+    ws1.free()
+    for x in dv + outs:
+        x.free()
+    total = sum(b.N for b in problems)
+    return {"workload": "batched_512_cheb_d2_phi0-3_tau1e-4..1e-2_fp64", "problems": len(problems),
+            "total_dofs": total, "apply_ms": batch_ms, "dofs_per_s": total / (batch_ms * 1e-3),
+            "plan_s": plan_s, "max_s": smax, "mu_mode_launches": k_launch // reps,
+            "mu_mode_tflops": (k_flops / (k_ms * 1e-3)) / 1e12 if k_ms > 0 else 0.0,
+            "mu_mode_ms": k_ms / reps, "single_calls_ms": seq_ms,
+            "speedup_vs_single_calls": seq_ms / batch_ms}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -89,6 +147,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the 512-problem batched section")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy N doubles device-to-device once (a plain copy of known "
                          "size, to scale hardware byte counters)")
@@ -221,6 +281,9 @@ def main():
         "fp32_mfma": fp32,
         "bf16x3_mfma": bf16x3,
     }
+    if not args.no_batched:
+        log("[bench] batched workload (512 problems)")
+        line["batched"] = batched_section(ph)
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle (one full call)")
         line["cpu_baseline"] = cpu_baseline(w, info)

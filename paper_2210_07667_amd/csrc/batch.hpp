@@ -60,6 +60,7 @@ struct GroupedLaunch {
   size_t first_off = 0;  // bytes into the table: int64_t first[n] (GEMM)
   int n = 0;
   int64_t total = 0;     // GEMM: tiles; Combine: largest N
+  double flops = 0.0;    // GEMM: algorithmic 2 M N K over all items and batches
 };
 
 // Host builder of one call's launches and their tables.
@@ -86,6 +87,7 @@ struct BatchSchedule {
             std::vector<GroupItem> part;
             std::vector<int64_t> first;
             int64_t total = 0;
+            double flops = 0.0;
             for (const StepGemm& it : items) {
               if (it.kc != (kc == 1) || it.lincomb != (lc == 1) || tile_class(it.g) != tile) continue;
               if (vec_ok(it.g, it.kc, {}) != (vec == 1)) continue;
@@ -98,6 +100,7 @@ struct BatchSchedule {
               if (gi.g.total_tiles <= 0) continue;
               gi.Y = it.Y;
               gi.YN = it.YN;
+              flops += 2.0 * gi.g.M * (double)gi.g.N * gi.g.K * gi.g.nb0 * (double)gi.g.nb1;
               first.push_back(total);
               total += gi.g.total_tiles;
               part.push_back(gi);
@@ -111,6 +114,7 @@ struct BatchSchedule {
             L.lincomb = lc == 1;
             L.n = (int)part.size();
             L.total = total;
+            L.flops = flops;
             L.items_off = put(part.data(), part.size() * sizeof(GroupItem));
             L.first_off = put(first.data(), first.size() * sizeof(int64_t));
             launches.push_back(L);
@@ -134,11 +138,25 @@ int launch_grouped_cfg(const GroupedLaunch& L, const char* dev, const Epi& epi, 
     set_error("grouped GEMM grid too large");
     return PHIKS_EINVAL;
   }
+  hipEvent_t ea = nullptr, eb = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_timing_mu);
+    if (g_timing) {
+      ea = pooled_event();
+      eb = pooled_event();
+      if (ea && eb) HIP_OK(hipEventRecord(ea, st));
+    }
+  }
   (void)hipGetLastError();
   hipLaunchKernelGGL((gemm_f64_grouped<BM, BN, WM, WN, KC, VEC, Epi>), dim3((unsigned)L.total),
                      dim3(256), 0, st, (const GroupItem*)(dev + L.items_off),
                      (const int64_t*)(dev + L.first_off), L.n, L.total, epi);
   CHECK_LAUNCH();
+  if (ea && eb) {
+    HIP_OK(hipEventRecord(eb, st));
+    std::lock_guard<std::mutex> lk(g_timing_mu);
+    g_timed.push_back({ea, eb, L.flops});
+  }
   return PHIKS_OK;
 }
 
