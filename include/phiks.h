@@ -215,6 +215,50 @@ int phiks_batch_info(phiks_batch_t batch, int i, int* s, int* q, int* tucker_pap
 void phiks_batch_destroy(phiks_batch_t batch);
 
 /*
+ * Serving: same-vector requests submitted one at a time (each one phiks_apply on
+ * caller-owned device vectors), run by the library in groups.
+ *
+ * phiks_server_create -- hbm_budget: device bytes for cached plans plus the workspace
+ * arena; workspace_bytes: the arena (a request whose workspace, computed for the
+ * largest q, exceeds it is refused with PHIKS_EWORKSPACE); max_group: most requests
+ * per grouped execution; hip_stream: the stream all of the server's device work runs
+ * on.  Starts a worker thread (admission, plan cache, launches) and a completion thread.
+ *
+ * phiks_server_submit -- arguments as phiks_plan (real FP64, tolerance tol relative:
+ * norms taken as 1) plus v (device, N doubles) and out (device, n_scales*(p+1)*N
+ * doubles, laid out as phiks_apply's out).  A is copied; v and out must stay valid
+ * until phiks_server_wait returns for the ticket.  Validation errors are returned
+ * here, before anything is queued.  Plans are cached on the exact bytes of A and the
+ * parameters (least recently used plans that no queued request holds are evicted
+ * when the cache would exceed hbm_budget - workspace_bytes).
+ *
+ * phiks_server_wait -- blocks until the request is done, returns its status (the
+ * result is then in out, bitwise what phiks_apply returns for it) and its latency
+ * in seconds (submission to completion); the ticket is then released.
+ *
+ * phiks_server_destroy -- runs everything still queued, waits for it, frees.
+ */
+typedef struct phiks_server_s* phiks_server_t;
+typedef struct {
+  int64_t completed;     /* requests finished (any status) */
+  int64_t groups;        /* grouped executions launched */
+  int64_t cache_hits;
+  int64_t cache_misses;
+  int64_t evictions;
+  int64_t cache_bytes;   /* device bytes of the cached plans */
+  int64_t cached_plans;
+} phiks_server_stats_t;
+
+int phiks_server_create(size_t hbm_budget, size_t workspace_bytes, int max_group,
+                        void* hip_stream, phiks_server_t* out);
+int phiks_server_submit(phiks_server_t server, int d, const int64_t* n, const double* const* A,
+                        double tau, int p, int n_scales, double tol, const double* v,
+                        double* out, int64_t* ticket);
+int phiks_server_wait(phiks_server_t server, int64_t ticket, double* latency_s);
+int phiks_server_stats(phiks_server_t server, phiks_server_stats_t* out);
+void phiks_server_destroy(phiks_server_t server);
+
+/*
  * Device-memory plumbing for callers without their own allocator (the Python
  * binding and the tests use these, so that one HIP runtime -- the one this library
  * was built against -- serves the whole process).  Copies are synchronous.

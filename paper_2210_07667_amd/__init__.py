@@ -44,7 +44,8 @@ SYMBOLS = ("phiks_plan", "phiks_apply", "phiks_combine", "phiks_workspace_size",
            "phiks_device_free", "phiks_memcpy_htod", "phiks_memcpy_dtoh",
            "phiks_device_synchronize", "phiks_memcpy_dtod", "phiks_batch_plan",
            "phiks_batch_apply", "phiks_batch_workspace_size", "phiks_batch_info",
-           "phiks_batch_destroy")
+           "phiks_batch_destroy", "phiks_server_create", "phiks_server_submit",
+           "phiks_server_wait", "phiks_server_stats", "phiks_server_destroy")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with "
@@ -107,6 +108,26 @@ _lib.phiks_batch_info.restype = ctypes.c_int
 _lib.phiks_batch_info.argtypes = [_vp, ctypes.c_int] + [ctypes.POINTER(ctypes.c_int)] * 4
 _lib.phiks_batch_destroy.restype = None
 _lib.phiks_batch_destroy.argtypes = [_vp]
+
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int64) for k in ("completed", "groups", "cache_hits", "cache_misses",
+                                              "evictions", "cache_bytes", "cached_plans")]
+
+
+_lib.phiks_server_create.restype = ctypes.c_int
+_lib.phiks_server_create.argtypes = [ctypes.c_size_t, ctypes.c_size_t, ctypes.c_int, _vp,
+                                     ctypes.POINTER(_vp)]
+_lib.phiks_server_submit.restype = ctypes.c_int
+_lib.phiks_server_submit.argtypes = [_vp, ctypes.c_int, _i64p, _dpp, ctypes.c_double, ctypes.c_int,
+                                     ctypes.c_int, ctypes.c_double, _vp, _vp, _i64p]
+_lib.phiks_server_wait.restype = ctypes.c_int
+_lib.phiks_server_wait.argtypes = [_vp, ctypes.c_int64, _dp]
+_lib.phiks_server_stats.restype = ctypes.c_int
+_lib.phiks_server_stats.argtypes = [_vp, ctypes.POINTER(ServerStats)]
+_lib.phiks_server_destroy.restype = None
+_lib.phiks_server_destroy.argtypes = [_vp]
 
 
 class PhiksError(RuntimeError):
@@ -458,6 +479,49 @@ def batch_apply_arrays(batch: Batch, vs: Sequence[DeviceArray], outs=None, ws=No
         ws = DeviceArray(batch.workspace_size() // 8 + 1)
     phiks_batch_apply(batch, [v.ptr for v in vs], [o.ptr for o in outs], ws.ptr, ws.nbytes, stream)
     return outs
+
+
+class Server:
+    """Owns a phiks_server_t: submit() queues one same-vector request, wait() blocks
+    until it is done and returns its latency in seconds."""
+
+    def __init__(self, hbm_budget: int, workspace_bytes: int, max_group: int = 64,
+                 stream: int = 0):
+        h = ctypes.c_void_p()
+        _check(_lib.phiks_server_create(ctypes.c_size_t(hbm_budget), ctypes.c_size_t(workspace_bytes),
+                                        int(max_group), _vp(stream), ctypes.byref(h)),
+               "phiks_server_create")
+        self._h = h
+
+    def submit(self, A: Sequence[np.ndarray], tau: float, p: int, n_scales: int, tol: float,
+               v_ptr: int, out_ptr: int) -> int:
+        mats, n, ptrs = _host_mats(A)
+        t = ctypes.c_int64()
+        _check(_lib.phiks_server_submit(self._h, len(mats), n, ptrs, float(tau), int(p),
+                                        int(n_scales), float(tol), _vp(v_ptr), _vp(out_ptr),
+                                        ctypes.byref(t)), "phiks_server_submit")
+        return t.value
+
+    def wait(self, ticket: int) -> float:
+        lat = ctypes.c_double()
+        _check(_lib.phiks_server_wait(self._h, int(ticket), ctypes.byref(lat)), "phiks_server_wait")
+        return lat.value
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(_lib.phiks_server_stats(self._h, ctypes.byref(st)), "phiks_server_stats")
+        return {k: getattr(st, k) for k, _ in ServerStats._fields_}
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            _lib.phiks_server_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def tucker_arrays(n: Sequence[int], Ls: Sequence[DeviceArray], v: DeviceArray,

@@ -19,21 +19,31 @@
 #include <thread>
 #include <vector>
 
+namespace {
+
+// Launch tables of grouped executions: built per call in pinned host memory and
+// uploaded once; grown when a call needs more.  A call waits on the host until the
+// previous call's upload has read the staging buffer.
+struct GroupTables {
+  char* host = nullptr;
+  void* dev = nullptr;
+  size_t bytes = 0;
+  hipEvent_t upload_done = nullptr;
+  bool uploaded = false;
+};
+
+}  // namespace
+
 struct phiks_batch_s {
   int count = 0;
   int p = 0, ns = 1, precision = PHIKS_FP64;
   int device = 0;
-  hipStream_t stream = nullptr;           // stream the batch was built on (and is released on)
+  hipStream_t stream = nullptr;           // stream the batch was built on
   std::vector<phiks_plan_s> plans;        // per problem; matrices inside dmem
   void* dmem = nullptr;
   std::vector<size_t> ws_off;             // per-problem workspace offsets, doubles
   size_t ws_doubles = 0;
-  // launch tables of one call: built in pinned host memory, uploaded once per call
-  char* host_tab = nullptr;
-  void* dev_tab = nullptr;
-  size_t tab_bytes = 0;
-  hipEvent_t upload_done = nullptr;       // the previous call's table upload has run
-  bool uploaded = false;
+  GroupTables tab;
   std::vector<std::vector<char>> host_keep;
 };
 
@@ -176,20 +186,32 @@ int launch_grouped(const GroupedLaunch& L, const char* dev, const Epi& epi, hipS
                : launch_grouped_tile<false, false>(L, dev, epi, st);
 }
 
-// Builds the launches of one phiks_batch_apply call (the same order of operations as
-// phiks_apply for every problem).  v, out: the call's vectors; ws: its workspace.
-void build_batch_schedule(const phiks_batch_s& B, const double* const* v, double* const* out,
-                          double* ws, BatchSchedule& S) {
-  const int p = B.p, ns = B.ns;
-  const int count = B.count;
+// One grouped execution: problem i runs plan *plans[i] (all with the same p and
+// n_scales) on v[i] into out[i] (laid out as phiks_apply's out), with ws[i] a
+// workspace of workspace_doubles(*plans[i]) doubles, 16-byte aligned.
+struct GroupWork {
+  std::vector<const phiks_plan_s*> plans;
+  std::vector<const double*> v;
+  std::vector<double*> out;
+  std::vector<double*> ws;
+  int p = 0, ns = 1;
+};
+
+// Builds the launches of one grouped execution (the same order of operations as
+// phiks_apply for every problem).
+void build_group_schedule(const GroupWork& W, BatchSchedule& S) {
+  const int p = W.p, ns = W.ns;
+  const int count = (int)W.plans.size();
+  const double* const* v = W.v.data();
+  double* const* out = W.out.data();
   struct Bufs { double *ta, *tb, *pa, *pb, *cur; };
   std::vector<Bufs> bf(count);
   int dmax = 0, smax = 0;
   for (int i = 0; i < count; ++i) {
-    const phiks_plan_s& P = B.plans[i];
+    const phiks_plan_s& P = (*W.plans[i]);
     const int64_t N = P.N;
     const int64_t t = std::max<int64_t>({(int64_t)P.q - 1, (int64_t)p, 1});
-    bf[i].ta = ws + B.ws_off[i];
+    bf[i].ta = W.ws[i];
     bf[i].tb = bf[i].ta + t * N;
     bf[i].pa = bf[i].tb + t * N;
     bf[i].pb = bf[i].pa + (int64_t)p * N;
@@ -197,7 +219,7 @@ void build_batch_schedule(const phiks_batch_s& B, const double* const* v, double
     smax = std::max(smax, P.s);
   }
   auto slot = [&](int i, int level, int ell) {
-    return out[i] + ((int64_t)level * (p + 1) + ell) * B.plans[i].N;
+    return out[i] + ((int64_t)level * (p + 1) + ell) * (*W.plans[i]).N;
   };
   // squaring-epilogue coefficients (the same for every problem: they depend on p only)
   std::memset(&S.lin, 0, sizeof(S.lin));
@@ -211,7 +233,7 @@ void build_batch_schedule(const phiks_batch_s& B, const double* const* v, double
     // eq. integrandsimul: the node Tuckers of every problem, mode by mode
     std::vector<std::vector<GemmArgs>> views(count, std::vector<GemmArgs>(PHIKS_MAX_D));
     for (int i = 0; i < count; ++i) {
-      const phiks_plan_s& P = B.plans[i];
+      const phiks_plan_s& P = (*W.plans[i]);
       int64_t stride[PHIKS_MAX_D];
       for (int mu = 0; mu < P.d; ++mu) stride[mu] = P.n[mu] * P.n[mu];
       double* wbuf = tucker_free_buffer(P.d, bf[i].ta, bf[i].tb);
@@ -221,13 +243,13 @@ void build_batch_schedule(const phiks_batch_s& B, const double* const* v, double
     for (int mu = 1; mu <= dmax; ++mu) {
       std::vector<StepGemm> items;
       for (int i = 0; i < count; ++i)
-        if (B.plans[i].d >= mu) items.push_back({views[i][mu - 1], mu == 1, false, nullptr, 0});
+        if ((*W.plans[i]).d >= mu) items.push_back({views[i][mu - 1], mu == 1, false, nullptr, 0});
       S.add_gemm_step(items);
     }
     // node sums
     std::vector<CombineArgs> comb;
     for (int i = 0; i < count; ++i) {
-      const phiks_plan_s& P = B.plans[i];
+      const phiks_plan_s& P = (*W.plans[i]);
       const int nodes = plan_nodes(P);
       double* wbuf = tucker_free_buffer(P.d, bf[i].ta, bf[i].tb);
       bf[i].cur = (P.s < ns) ? slot(i, P.s, 1) : bf[i].pa;
@@ -253,7 +275,7 @@ void build_batch_schedule(const phiks_batch_s& B, const double* const* v, double
       std::vector<std::vector<GemmArgs>> lv(count, std::vector<GemmArgs>(PHIKS_MAX_D));
       std::vector<double*> dst(count, nullptr);
       for (int i = 0; i < count; ++i) {
-        const phiks_plan_s& P = B.plans[i];
+        const phiks_plan_s& P = (*W.plans[i]);
         if (P.s <= t) continue;
         const int j = P.s - t;
         dst[i] = (j - 1 < ns) ? slot(i, j - 1, 1) : ((bf[i].cur == bf[i].pa) ? bf[i].pb : bf[i].pa);
@@ -266,7 +288,7 @@ void build_batch_schedule(const phiks_batch_s& B, const double* const* v, double
       for (int mu = 1; mu <= dmax; ++mu) {
         std::vector<StepGemm> items;
         for (int i = 0; i < count; ++i) {
-          const phiks_plan_s& P = B.plans[i];
+          const phiks_plan_s& P = (*W.plans[i]);
           if (P.s <= t || P.d < mu) continue;
           const bool last = (mu == P.d);
           items.push_back({lv[i][mu - 1], mu == 1, last, last ? bf[i].cur : nullptr, P.N});
@@ -274,14 +296,14 @@ void build_batch_schedule(const phiks_batch_s& B, const double* const* v, double
         S.add_gemm_step(items);
       }
       for (int i = 0; i < count; ++i)
-        if (B.plans[i].s > t) bf[i].cur = dst[i];
+        if ((*W.plans[i]).s > t) bf[i].cur = dst[i];
     }
   }
   // exponential outputs exp(2^-j tau K) v
   for (int lev = 0; lev < ns; ++lev) {
     std::vector<std::vector<GemmArgs>> ev(count, std::vector<GemmArgs>(PHIKS_MAX_D));
     for (int i = 0; i < count; ++i) {
-      const phiks_plan_s& P = B.plans[i];
+      const phiks_plan_s& P = (*W.plans[i]);
       double* L[PHIKS_MAX_D];
       int64_t stride[PHIKS_MAX_D] = {0};
       for (int mu = 0; mu < P.d; ++mu) L[mu] = P.E[mu] + (size_t)lev * P.n[mu] * P.n[mu];
@@ -291,10 +313,65 @@ void build_batch_schedule(const phiks_batch_s& B, const double* const* v, double
     for (int mu = 1; mu <= dmax; ++mu) {
       std::vector<StepGemm> items;
       for (int i = 0; i < count; ++i)
-        if (B.plans[i].d >= mu) items.push_back({ev[i][mu - 1], mu == 1, false, nullptr, 0});
+        if ((*W.plans[i]).d >= mu) items.push_back({ev[i][mu - 1], mu == 1, false, nullptr, 0});
       S.add_gemm_step(items);
     }
   }
+}
+
+// Uploads S's tables (growing them if needed) and issues its launches on st.
+int run_group(GroupTables& T, const BatchSchedule& S, hipStream_t st) {
+  // the previous call's upload must have read the staging buffer before it is rewritten
+  if (T.uploaded) HIP_OK(hipEventSynchronize(T.upload_done));
+  if (!T.upload_done) HIP_OK(hipEventCreateWithFlags(&T.upload_done, hipEventDisableTiming));
+  const size_t need = std::max<size_t>(S.buf.size(), 16);
+  if (need > T.bytes) {
+    // the old device table is released in stream order
+    const size_t bytes = need + need / 4;
+    char* h = nullptr;
+    void* d = nullptr;
+    if (hipHostMalloc((void**)&h, bytes, hipHostMallocDefault) != hipSuccess) {
+      set_error("hipHostMalloc of the launch tables failed");
+      return PHIKS_ENOMEM;
+    }
+    if (hipMallocAsync(&d, bytes, st) != hipSuccess) {
+      (void)hipHostFree(h);
+      set_error("hipMallocAsync of the launch tables failed");
+      return PHIKS_ENOMEM;
+    }
+    if (T.dev) HIP_OK(hipFreeAsync(T.dev, st));
+    if (T.host) (void)hipHostFree(T.host);
+    T.host = h;
+    T.dev = d;
+    T.bytes = bytes;
+  }
+  if (!S.buf.empty()) std::memcpy(T.host, S.buf.data(), S.buf.size());
+  HIP_OK(hipMemcpyAsync(T.dev, T.host, need, hipMemcpyHostToDevice, st));
+  HIP_OK(hipEventRecord(T.upload_done, st));
+  T.uploaded = true;
+  const char* dev = (const char*)T.dev;
+  for (const GroupedLaunch& L : S.launches) {
+    if (L.kind == StepKind::Combine) {
+      const int64_t blocks = std::min<int64_t>((L.total + 255) / 256, 1024);
+      (void)hipGetLastError();
+      hipLaunchKernelGGL(combine_grouped_kernel, dim3((unsigned)blocks, (unsigned)L.n), dim3(256),
+                         0, st, (const CombineArgs*)(dev + L.items_off));
+      CHECK_LAUNCH();
+    } else if (L.lincomb) {
+      RET_IF(launch_grouped(L, dev, S.lin, st));
+    } else {
+      RET_IF(launch_grouped(L, dev, EpiStore{1.0, 0.0}, st));
+    }
+  }
+  return PHIKS_OK;
+}
+
+// Frees the tables; the caller has synchronised the stream that used them.
+void free_group_tables(GroupTables& T) {
+  if (T.dev) (void)hipFree(T.dev);
+  if (T.host) (void)hipHostFree(T.host);
+  if (T.upload_done) (void)hipEventDestroy(T.upload_done);
+  T = GroupTables();
 }
 
 }  // namespace
@@ -310,9 +387,7 @@ void phiks_batch_destroy(phiks_batch_t batch) {
   // may not call the HIP API, and the pinned tables need hipHostFree.)
   (void)hipStreamSynchronize(batch->stream);
   if (batch->dmem) (void)hipFree(batch->dmem);
-  if (batch->dev_tab) (void)hipFree(batch->dev_tab);
-  if (batch->host_tab) (void)hipHostFree(batch->host_tab);
-  if (batch->upload_done) (void)hipEventDestroy(batch->upload_done);
+  free_group_tables(batch->tab);
   delete batch;
   if (switched) (void)hipSetDevice(cur);
 }
@@ -396,35 +471,6 @@ int phiks_batch_plan(int count, const int* d, const int64_t* const* n,
     B->ws_off[i] = B->ws_doubles;
     B->ws_doubles += (workspace_doubles(B->plans[i]) + 1) & ~(size_t)1;
   }
-  // size the launch tables with a dry run on stand-in 256-byte aligned addresses (the
-  // size depends on the shapes and, through the 16-byte load test, on alignment only;
-  // a call that needs more grows them)
-  {
-    std::vector<const double*> dv(count);
-    std::vector<double*> dout(count);
-    for (int i = 0; i < count; ++i) {
-      dv[i] = reinterpret_cast<const double*>((uintptr_t)256 * (2 * i + 1));
-      dout[i] = reinterpret_cast<double*>((uintptr_t)256 * (2 * i + 2));
-    }
-    BatchSchedule S;
-    build_batch_schedule(*B, dv.data(), dout.data(), reinterpret_cast<double*>((uintptr_t)256), S);
-    B->tab_bytes = std::max<size_t>(S.buf.size(), 16);
-  }
-  if (hipHostMalloc((void**)&B->host_tab, B->tab_bytes, hipHostMallocDefault) != hipSuccess) {
-    B->host_tab = nullptr;
-    set_error("hipHostMalloc of the batch launch tables failed");
-    return fail(PHIKS_ENOMEM);
-  }
-  if (hipMallocAsync(&B->dev_tab, B->tab_bytes, st) != hipSuccess) {
-    B->dev_tab = nullptr;
-    set_error("hipMallocAsync of the batch launch tables failed");
-    return fail(PHIKS_ENOMEM);
-  }
-  if (hipEventCreateWithFlags(&B->upload_done, hipEventDisableTiming) != hipSuccess) {
-    B->upload_done = nullptr;
-    set_error("hipEventCreate failed");
-    return fail(PHIKS_EDEVICE);
-  }
   *out = B;
   return PHIKS_OK;
 }
@@ -457,50 +503,18 @@ int phiks_batch_apply(phiks_batch_t batch, const double* const* v, double* const
     set_error("batch workspace must be 16-byte aligned");
     return PHIKS_EINVAL;
   }
-  hipStream_t st = (hipStream_t)hip_stream;
+  GroupWork W;
+  W.p = B.p;
+  W.ns = B.ns;
+  for (int i = 0; i < B.count; ++i) {
+    W.plans.push_back(&B.plans[i]);
+    W.v.push_back(v[i]);
+    W.out.push_back(out[i]);
+    W.ws.push_back((double*)ws + B.ws_off[i]);
+  }
   BatchSchedule S;
-  build_batch_schedule(B, v, out, (double*)ws, S);
-  // the previous call's upload must have read the staging buffer before it is rewritten
-  if (B.uploaded) HIP_OK(hipEventSynchronize(B.upload_done));
-  if (S.buf.size() > B.tab_bytes) {
-    // grow the tables (the old device table is released in stream order)
-    const size_t bytes = S.buf.size() + S.buf.size() / 4;
-    char* h = nullptr;
-    void* dtab = nullptr;
-    if (hipHostMalloc((void**)&h, bytes, hipHostMallocDefault) != hipSuccess) {
-      set_error("hipHostMalloc of the batch launch tables failed");
-      return PHIKS_ENOMEM;
-    }
-    if (hipMallocAsync(&dtab, bytes, st) != hipSuccess) {
-      (void)hipHostFree(h);
-      set_error("hipMallocAsync of the batch launch tables failed");
-      return PHIKS_ENOMEM;
-    }
-    HIP_OK(hipFreeAsync(B.dev_tab, st));
-    (void)hipHostFree(B.host_tab);
-    B.host_tab = h;
-    B.dev_tab = dtab;
-    B.tab_bytes = bytes;
-  }
-  if (!S.buf.empty()) std::memcpy(B.host_tab, S.buf.data(), S.buf.size());
-  HIP_OK(hipMemcpyAsync(B.dev_tab, B.host_tab, std::max<size_t>(S.buf.size(), 16),
-                        hipMemcpyHostToDevice, st));
-  HIP_OK(hipEventRecord(B.upload_done, st));
-  B.uploaded = true;
-  const char* dev = (const char*)B.dev_tab;
-  for (const GroupedLaunch& L : S.launches) {
-    if (L.kind == StepKind::Combine) {
-      const int64_t blocks = std::min<int64_t>((L.total + 255) / 256, 1024);
-      (void)hipGetLastError();
-      hipLaunchKernelGGL(combine_grouped_kernel, dim3((unsigned)blocks, (unsigned)L.n), dim3(256),
-                         0, st, (const CombineArgs*)(dev + L.items_off));
-      CHECK_LAUNCH();
-    } else if (L.lincomb) {
-      RET_IF(launch_grouped(L, dev, S.lin, st));
-    } else {
-      RET_IF(launch_grouped(L, dev, EpiStore{1.0, 0.0}, st));
-    }
-  }
+  build_group_schedule(W, S);
+  RET_IF(run_group(B.tab, S, (hipStream_t)hip_stream));
   return PHIKS_OK;
 }
 

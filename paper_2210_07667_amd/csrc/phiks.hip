@@ -938,3 +938,4 @@ int phiks_combine(phiks_plan_t plan, const double* const* v, double* out, void* 
 }  // extern "C"
 
 #include "batch.hpp"
+#include "server.hpp"

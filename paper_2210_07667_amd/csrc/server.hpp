@@ -1,0 +1,393 @@
+// Serving: same-vector requests submitted one at a time, run in groups.
+//
+// A request is one phiks_apply (outputs as eq. scaldiffphi) on caller-owned device
+// vectors.  Inside the server:
+//   * plan cache: the plans (host plan + the small exponentials of Section 3.1 on the
+//     device) keyed on the exact operator bytes, tau, p, n_scales and tol; requests of
+//     one operator and step share one plan.  LRU eviction of unused plans keeps the
+//     cache within the HBM budget less the workspace arena.
+//   * admission: the worker takes pending requests in arrival order that share the
+//     first one's (p, n_scales), as long as their workspaces fit the arena and the
+//     group has at most max_group requests (continuous batching: whatever arrived
+//     while the previous group ran forms the next one).
+//   * execution: a group runs as the grouped launches of phiks_batch_apply (so every
+//     result is bitwise what phiks_apply returns for that request alone); host
+//     planning of the next group overlaps the device work of the previous ones.
+//   * completion: a second thread waits on each group's event in order, stamps the
+//     completion time and wakes the callers blocked in phiks_server_wait.
+// Requests are planned with the relative reading of the tolerance (vnorms = NULL), so
+// the plan does not depend on the vector.
+//
+// Included once, at the end of phiks.hip, after batch.hpp.
+#pragma once
+
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+namespace {
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+struct PlanKey {
+  std::vector<char> bytes;  // d, n, tau, p, n_scales, tol, then every A_mu
+  uint64_t hash = 0;
+  bool operator==(const PlanKey& o) const { return hash == o.hash && bytes == o.bytes; }
+};
+struct PlanKeyHash {
+  size_t operator()(const PlanKey& k) const { return (size_t)k.hash; }
+};
+
+struct CachedPlan {
+  phiks_plan_s* plan = nullptr;
+  size_t bytes = 0;        // device bytes of its matrices
+  int refs = 0;            // requests admitted and not yet completed
+  uint64_t last_use = 0;   // LRU tick
+};
+
+struct ServerRequest {
+  int64_t ticket = 0;
+  PlanKey key;
+  std::vector<std::vector<double>> A;  // host copies (built into a plan on a cache miss)
+  int d = 0;
+  int64_t n[PHIKS_MAX_D] = {0};
+  double tau = 0.0, tol = 0.0;
+  int p = 0, ns = 1;
+  const double* v = nullptr;
+  double* out = nullptr;
+  size_t ws_bound = 0;     // workspace doubles for the largest q (admission)
+  double t_submit = 0.0, t_done = 0.0;
+  int status = PHIKS_OK;
+  bool done = false;
+  CachedPlan* cp = nullptr;
+};
+
+struct InFlightGroup {
+  hipEvent_t ev = nullptr;
+  std::vector<ServerRequest*> reqs;
+};
+
+uint64_t fnv1a(const char* p, size_t n, uint64_t h = 1469598103934665603ull) {
+  for (size_t i = 0; i < n; ++i) {
+    h ^= (unsigned char)p[i];
+    h *= 1099511628211ull;
+  }
+  return h;
+}
+
+}  // namespace
+
+struct phiks_server_s {
+  size_t budget = 0, arena_doubles = 0;
+  int max_group = 1;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  double* arena = nullptr;
+  GroupTables tab;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done, cv_inflight;
+  std::deque<ServerRequest*> pending;
+  std::unordered_map<int64_t, ServerRequest*> tickets;
+  std::unordered_map<PlanKey, CachedPlan, PlanKeyHash> cache;
+  size_t cache_bytes = 0;
+  std::deque<InFlightGroup> inflight;
+  bool stop = false, worker_done = false;
+  int64_t next_ticket = 1;
+  uint64_t tick = 0;
+  phiks_server_stats_t st{};
+  std::thread worker, completer;
+};
+
+namespace {
+
+void server_finish(phiks_server_s& S, ServerRequest* r, int status, double t) {
+  r->status = status;
+  r->t_done = t;
+  r->done = true;
+  ++S.st.completed;
+}
+
+// Cached plan for r (built on a miss); called by the worker without the lock held.
+int server_plan(phiks_server_s& S, ServerRequest* r) {
+  {
+    std::lock_guard<std::mutex> lk(S.mu);
+    auto it = S.cache.find(r->key);
+    if (it != S.cache.end()) {
+      r->cp = &it->second;
+      ++r->cp->refs;
+      r->cp->last_use = ++S.tick;
+      ++S.st.cache_hits;
+      return PHIKS_OK;
+    }
+  }
+  std::vector<const double*> A(r->d);
+  for (int mu = 0; mu < r->d; ++mu) A[mu] = r->A[mu].data();
+  phiks_plan_t plan = nullptr;
+  int rc = phiks_plan(r->d, r->n, A.data(), r->tau, r->p, r->ns, r->tol, PHIKS_SAME_VECTOR,
+                      nullptr, PHIKS_FP64, S.stream, &plan);
+  if (rc != PHIKS_OK) return rc;
+  const size_t bytes = plan_device_doubles(*plan) * sizeof(double);
+  std::vector<phiks_plan_s*> evict;
+  {
+    std::lock_guard<std::mutex> lk(S.mu);
+    ++S.st.cache_misses;
+    // least recently used plans that no admitted request holds, until the new one fits
+    const size_t cap = S.budget > S.arena_doubles * sizeof(double)
+                           ? S.budget - S.arena_doubles * sizeof(double) : 0;
+    while (S.cache_bytes + bytes > cap) {
+      auto victim = S.cache.end();
+      for (auto it = S.cache.begin(); it != S.cache.end(); ++it)
+        if (it->second.refs == 0 && (victim == S.cache.end() || it->second.last_use < victim->second.last_use))
+          victim = it;
+      if (victim == S.cache.end()) break;  // every cached plan is in use: run over budget
+      S.cache_bytes -= victim->second.bytes;
+      evict.push_back(victim->second.plan);
+      S.cache.erase(victim);
+      ++S.st.evictions;
+    }
+    auto ins = S.cache.emplace(r->key, CachedPlan{plan, bytes, 1, ++S.tick});
+    r->cp = &ins.first->second;
+    S.cache_bytes += bytes;
+    S.st.cache_bytes = (int64_t)S.cache_bytes;
+  }
+  for (phiks_plan_s* P : evict) phiks_plan_destroy(P);  // stream-ordered release
+  return PHIKS_OK;
+}
+
+void server_worker(phiks_server_s* Sp) {
+  phiks_server_s& S = *Sp;
+  (void)hipSetDevice(S.device);
+  for (;;) {
+    std::vector<ServerRequest*> group;
+    {
+      std::unique_lock<std::mutex> lk(S.mu);
+      S.cv_work.wait(lk, [&] { return S.stop || !S.pending.empty(); });
+      if (S.pending.empty()) break;  // stop requested and drained
+      const int p0 = S.pending.front()->p, ns0 = S.pending.front()->ns;
+      size_t ws = 0;
+      for (auto it = S.pending.begin(); it != S.pending.end() && (int)group.size() < S.max_group;) {
+        ServerRequest* r = *it;
+        if (r->p != p0 || r->ns != ns0) { ++it; continue; }
+        const size_t need = (r->ws_bound + 1) & ~(size_t)1;
+        if (ws + need > S.arena_doubles) break;
+        ws += need;
+        group.push_back(r);
+        it = S.pending.erase(it);
+      }
+    }
+    // plans (cache lookups; misses are planned here, overlapping earlier groups)
+    std::vector<ServerRequest*> run;
+    for (ServerRequest* r : group) {
+      const int rc = server_plan(S, r);
+      if (rc != PHIKS_OK) {
+        std::lock_guard<std::mutex> lk(S.mu);
+        server_finish(S, r, rc, now_s());
+      } else {
+        run.push_back(r);
+      }
+    }
+    if (run.empty()) {
+      S.cv_done.notify_all();
+      continue;
+    }
+    GroupWork W;
+    W.p = run[0]->p;
+    W.ns = run[0]->ns;
+    size_t off = 0;
+    for (ServerRequest* r : run) {
+      W.plans.push_back(r->cp->plan);
+      W.v.push_back(r->v);
+      W.out.push_back(r->out);
+      W.ws.push_back(S.arena + off);
+      off += (workspace_doubles(*r->cp->plan) + 1) & ~(size_t)1;
+    }
+    BatchSchedule sched;
+    build_group_schedule(W, sched);
+    int rc = run_group(S.tab, sched, S.stream);
+    hipEvent_t ev = nullptr;
+    if (rc == PHIKS_OK && (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess ||
+                           hipEventRecord(ev, S.stream) != hipSuccess)) {
+      rc = PHIKS_EDEVICE;
+      if (ev) (void)hipEventDestroy(ev);
+      ev = nullptr;
+    }
+    std::lock_guard<std::mutex> lk(S.mu);
+    ++S.st.groups;
+    if (rc != PHIKS_OK) {
+      (void)hipStreamSynchronize(S.stream);
+      const double t = now_s();
+      for (ServerRequest* r : run) {
+        --r->cp->refs;
+        server_finish(S, r, rc, t);
+      }
+      S.cv_done.notify_all();
+      continue;
+    }
+    S.inflight.push_back({ev, run});
+    S.cv_inflight.notify_all();
+  }
+  std::lock_guard<std::mutex> lk(S.mu);
+  S.worker_done = true;
+  S.cv_inflight.notify_all();
+}
+
+void server_completer(phiks_server_s* Sp) {
+  phiks_server_s& S = *Sp;
+  (void)hipSetDevice(S.device);
+  for (;;) {
+    InFlightGroup g;
+    {
+      std::unique_lock<std::mutex> lk(S.mu);
+      S.cv_inflight.wait(lk, [&] { return !S.inflight.empty() || S.worker_done; });
+      if (S.inflight.empty()) break;
+      g = S.inflight.front();
+      S.inflight.pop_front();
+    }
+    const int status = (hipEventSynchronize(g.ev) == hipSuccess) ? PHIKS_OK : PHIKS_EDEVICE;
+    const double t = now_s();
+    (void)hipEventDestroy(g.ev);
+    {
+      std::lock_guard<std::mutex> lk(S.mu);
+      for (ServerRequest* r : g.reqs) {
+        --r->cp->refs;
+        server_finish(S, r, status, t);
+      }
+    }
+    S.cv_done.notify_all();
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+int phiks_server_create(size_t hbm_budget, size_t workspace_bytes, int max_group,
+                        void* hip_stream, phiks_server_t* out) {
+  if (!out) return PHIKS_EINVAL;
+  *out = nullptr;
+  if (max_group < 1 || workspace_bytes < 16 || hbm_budget < workspace_bytes) return PHIKS_EINVAL;
+  phiks_server_s* S = new (std::nothrow) phiks_server_s;
+  if (!S) return PHIKS_ENOMEM;
+  S->budget = hbm_budget;
+  S->arena_doubles = workspace_bytes / sizeof(double);
+  S->max_group = max_group;
+  S->stream = (hipStream_t)hip_stream;
+  if (hipGetDevice(&S->device) != hipSuccess) {
+    delete S;
+    set_error("hipGetDevice failed");
+    return PHIKS_EDEVICE;
+  }
+  if (hipMalloc((void**)&S->arena, S->arena_doubles * sizeof(double)) != hipSuccess) {
+    delete S;
+    set_error("hipMalloc of the server workspace failed");
+    return PHIKS_ENOMEM;
+  }
+  S->worker = std::thread(server_worker, S);
+  S->completer = std::thread(server_completer, S);
+  *out = S;
+  return PHIKS_OK;
+}
+
+int phiks_server_submit(phiks_server_t server, int d, const int64_t* n, const double* const* A,
+                        double tau, int p, int n_scales, double tol, const double* v,
+                        double* out, int64_t* ticket) {
+  if (!server || !v || !out || !ticket) return PHIKS_EINVAL;
+  int rc = validate_problem(d, n, A, tau, p, n_scales, tol, PHIKS_SAME_VECTOR, nullptr);
+  if (rc != PHIKS_OK) return rc;
+  ServerRequest* r = new (std::nothrow) ServerRequest;
+  if (!r) return PHIKS_ENOMEM;
+  r->d = d;
+  int64_t N = 1;
+  for (int mu = 0; mu < d; ++mu) { r->n[mu] = n[mu]; N *= n[mu]; }
+  r->tau = tau;
+  r->tol = tol;
+  r->p = p;
+  r->ns = n_scales;
+  r->v = v;
+  r->out = out;
+  const int64_t t = std::max<int64_t>({(int64_t)kQMax - 1, (int64_t)p, 1});
+  r->ws_bound = (size_t)(2 * t + 2 * p) * N;
+  if (r->ws_bound > server->arena_doubles) {
+    delete r;
+    set_error("request workspace exceeds the server's workspace arena");
+    return PHIKS_EWORKSPACE;
+  }
+  // key: the parameters, then the operator bytes (exact match on lookup)
+  auto put = [&](const void* src, size_t bytes) {
+    const char* c = (const char*)src;
+    r->key.bytes.insert(r->key.bytes.end(), c, c + bytes);
+  };
+  put(&d, sizeof(d));
+  put(n, sizeof(int64_t) * d);
+  put(&tau, sizeof(tau));
+  put(&p, sizeof(p));
+  put(&n_scales, sizeof(n_scales));
+  put(&tol, sizeof(tol));
+  r->A.resize(d);
+  for (int mu = 0; mu < d; ++mu) {
+    r->A[mu].assign(A[mu], A[mu] + n[mu] * n[mu]);
+    put(A[mu], sizeof(double) * n[mu] * n[mu]);
+  }
+  r->key.hash = fnv1a(r->key.bytes.data(), r->key.bytes.size());
+  std::lock_guard<std::mutex> lk(server->mu);
+  if (server->stop) {
+    delete r;
+    return PHIKS_EINVAL;
+  }
+  r->ticket = server->next_ticket++;
+  r->t_submit = now_s();
+  server->tickets[r->ticket] = r;
+  server->pending.push_back(r);
+  *ticket = r->ticket;
+  server->cv_work.notify_one();
+  return PHIKS_OK;
+}
+
+int phiks_server_wait(phiks_server_t server, int64_t ticket, double* latency_s) {
+  if (!server) return PHIKS_EINVAL;
+  std::unique_lock<std::mutex> lk(server->mu);
+  auto it = server->tickets.find(ticket);
+  if (it == server->tickets.end()) return PHIKS_EINVAL;
+  ServerRequest* r = it->second;
+  server->cv_done.wait(lk, [&] { return r->done; });
+  const int status = r->status;
+  if (latency_s) *latency_s = r->t_done - r->t_submit;
+  server->tickets.erase(it);
+  delete r;
+  return status;
+}
+
+int phiks_server_stats(phiks_server_t server, phiks_server_stats_t* out) {
+  if (!server || !out) return PHIKS_EINVAL;
+  std::lock_guard<std::mutex> lk(server->mu);
+  *out = server->st;
+  out->cache_bytes = (int64_t)server->cache_bytes;
+  out->cached_plans = (int64_t)server->cache.size();
+  return PHIKS_OK;
+}
+
+void phiks_server_destroy(phiks_server_t server) {
+  if (!server) return;
+  {
+    std::lock_guard<std::mutex> lk(server->mu);
+    server->stop = true;
+  }
+  server->cv_work.notify_all();
+  server->worker.join();      // runs what is pending, then stops
+  server->completer.join();   // every group has completed
+  (void)hipStreamSynchronize(server->stream);
+  for (auto& kv : server->cache) phiks_plan_destroy(kv.second.plan);
+  (void)hipStreamSynchronize(server->stream);
+  free_group_tables(server->tab);
+  if (server->arena) (void)hipFree(server->arena);
+  for (auto& kv : server->tickets) delete kv.second;
+  delete server;
+}
+
+}  // extern "C"

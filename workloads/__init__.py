@@ -28,6 +28,7 @@ __all__ = [
     "fd2_dirichlet", "central_adv_dirichlet", "adr_1d", "cheb_d2_dirichlet",
     "randn_vec", "uniform_vec", "Workload", "config_fd2_2d", "config_allen_cahn_3d",
     "config_adr_3d", "validation_table1", "BatchProblem", "config_batch",
+    "fd2_neumann", "Session", "serving_sessions", "poisson_arrivals",
 ]
 
 
@@ -195,4 +196,75 @@ def config_batch(count: int = 512, seed: int = 3, sizes: Sequence[int] = BATCH_S
         out.append(BatchProblem(n=n, A=[cache[m].copy() for m in n], tau=tau,
                                 v=randn_vec(n, vseed)))
     return out
+
+
+def fd2_neumann(n: int, length: float = 1.0) -> np.ndarray:
+    """Second difference on n grid points of [0, length] including both ends
+    (h = length/(n-1)), homogeneous Neumann conditions by ghost reflection
+    (u_{-1} = u_1, u_n = u_{n-2}): rows 0 and n-1 read (-2, 2)/h^2."""
+    h = length / (n - 1)
+    A = np.zeros((n, n))
+    idx = np.arange(n)
+    A[idx, idx] = -2.0
+    A[idx[:-1], idx[:-1] + 1] = 1.0
+    A[idx[1:], idx[1:] - 1] = 1.0
+    A[0, 1] = 2.0
+    A[n - 1, n - 2] = 2.0
+    return A / (h * h)
+
+
+@dataclass
+class Session:
+    """A stream of requests sharing one operator, step and phi order (a time stepper
+    calling the same phi-functions every step): phi_0..phi_p of tau K, one scale."""
+    name: str
+    n: List[int]
+    A: List[np.ndarray]
+    tau: float
+    p: int
+
+    @property
+    def N(self) -> int:
+        return int(np.prod(self.n))
+
+
+SERVING_SHAPES = ([256, 256], [1024, 1024], [64, 64, 64], [128, 128, 128], [192, 192, 192])
+
+
+def serving_sessions(count: int = 12, seed: int = 4, shapes=SERVING_SHAPES) -> List[Session]:
+    """Sessions of the serving workload: shape drawn from `shapes`; operator one of
+    the FD2 Laplacian (Dirichlet), advection-diffusion-reaction (eps = 0.5, beta =
+    (1, 0.5, 0.25) per direction, reaction -1 split over the directions as in the ADR
+    workload) or the diffusion part of a Brusselator-type system (d = 0.02 times the
+    Neumann Laplacian with the shift -(b+1) = -4 split evenly over the directions);
+    p in 1..4; tau log-uniform in [1e-4, 1e-2]."""
+    rng = np.random.default_rng(seed)
+    kinds = ("fd2", "adr", "bruss")
+    out = []
+    for k in range(count):
+        n = list(shapes[int(rng.integers(len(shapes)))])
+        kind = kinds[int(rng.integers(len(kinds)))]
+        d = len(n)
+        if kind == "fd2":
+            A = [fd2_dirichlet(m) for m in n]
+        elif kind == "adr":
+            betas = (1.0, 0.5, 0.25)
+            A = [adr_1d(m, 0.5, betas[j], -1.0) for j, m in enumerate(n)]
+        else:
+            A = [0.02 * fd2_neumann(m) - (4.0 / d) * np.eye(m) for m in n]
+        tau = float(np.exp(rng.uniform(np.log(1e-4), np.log(1e-2))))
+        p = int(rng.integers(1, 5))
+        out.append(Session(name=f"{kind}_{'x'.join(map(str, n))}", n=n, A=A, tau=tau, p=p))
+    return out
+
+
+def poisson_arrivals(rate: float, duration: float, seed: int) -> np.ndarray:
+    """Arrival times (seconds from 0) of a Poisson process of the given rate."""
+    rng = np.random.default_rng(seed)
+    t, out = 0.0, []
+    while True:
+        t += rng.exponential(1.0 / rate)
+        if t >= duration:
+            return np.asarray(out)
+        out.append(t)
 
