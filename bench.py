@@ -140,6 +140,79 @@ def batched_section(ph, reps=3):
             "speedup_vs_single_calls": seq_ms / batch_ms}
 
 
+def serving_section(ph, rates=(100, 300, 600), duration=1.5):
+    """Served requests of the serving workload (12 sessions: FD2 / ADR / Brusselator-type
+    diffusion on 256^2, 1024^2, 64^3, 128^3, 192^3; p in 1..4; tau log-uniform) arriving as
+    a Poisson stream at each rate; latency is submission to completion as the server
+    stamps it.  Every session's plan is built once before the timed streams."""
+    import queue
+    import threading
+    import workloads
+    sessions = workloads.serving_sessions()
+    GiB = 1 << 30
+    server = ph.Server(hbm_budget=64 * GiB, workspace_bytes=32 * GiB, max_group=32)
+    rng = np.random.default_rng(4)
+    ops = [server.register(sess.A) for sess in sessions]
+    vin = [[ph.DeviceArray.from_numpy(rng.standard_normal(sess.N)) for _ in range(2)]
+           for sess in sessions]
+    pools = []
+    for sess in sessions:
+        q = queue.Queue()
+        for _ in range(24):
+            q.put(ph.DeviceArray((sess.p + 1) * sess.N))
+        pools.append(q)
+    # plans: one request per session (cache misses), not timed
+    warm = []
+    for si, sess in enumerate(sessions):
+        buf = pools[si].get()
+        warm.append((server.submit(ops[si], sess.tau, sess.p, 1, 2.0 ** -53, vin[si][0].ptr, buf.ptr),
+                     si, buf))
+    for t, si, buf in warm:
+        server.wait(t)
+        pools[si].put(buf)
+    out = []
+    for k, rate in enumerate(rates):
+        arrivals = workloads.poisson_arrivals(rate, duration, 40 + k)
+        picks = rng.integers(len(sessions), size=len(arrivals))
+        lat = []
+        waitq = queue.Queue()
+
+        def waiter():
+            while True:
+                item = waitq.get()
+                if item is None:
+                    return
+                t, si, buf = item
+                lat.append(server.wait(t))
+                pools[si].put(buf)
+
+        th = threading.Thread(target=waiter)
+        th.start()
+        dofs = 0
+        t0 = time.perf_counter()
+        for j, (at, si) in enumerate(zip(arrivals, picks)):
+            delay = t0 + at - time.perf_counter()
+            if delay > 0:
+                time.sleep(delay)
+            sess = sessions[si]
+            buf = pools[si].get()
+            t = server.submit(ops[si], sess.tau, sess.p, 1, 2.0 ** -53, vin[si][j % 2].ptr, buf.ptr)
+            waitq.put((t, si, buf))
+            dofs += sess.N
+        waitq.put(None)
+        th.join()
+        wall = time.perf_counter() - t0
+        la = np.asarray(lat) * 1e3
+        out.append({"rate_per_s": rate, "requests": len(la), "p50_ms": float(np.percentile(la, 50)),
+                    "p99_ms": float(np.percentile(la, 99)), "mean_ms": float(la.mean()),
+                    "throughput_per_s": len(la) / wall, "dofs_per_s": dofs / wall})
+        log(f"[bench] serving rate {rate}/s: p50 {out[-1]['p50_ms']:.2f} ms p99 {out[-1]['p99_ms']:.2f} ms")
+    st = server.stats()
+    server.close()
+    return {"workload": "serving_12_sessions_poisson", "sessions": [s.name for s in sessions],
+            "duration_s_per_rate": duration, "rates": out, "server": st}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -149,6 +222,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the 512-problem batched section")
+    ap.add_argument("--no-serving", action="store_true",
+                    help="skip the served-requests section")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy N doubles device-to-device once (a plain copy of known "
                          "size, to scale hardware byte counters)")
@@ -284,6 +359,9 @@ def main():
     if not args.no_batched:
         log("[bench] batched workload (512 problems)")
         line["batched"] = batched_section(ph)
+    if not args.no_serving:
+        log("[bench] serving workload")
+        line["serving"] = serving_section(ph)
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle (one full call)")
         line["cpu_baseline"] = cpu_baseline(w, info)

@@ -224,13 +224,16 @@ void phiks_batch_destroy(phiks_batch_t batch);
  * per grouped execution; hip_stream: the stream all of the server's device work runs
  * on.  Starts a worker thread (admission, plan cache, launches) and a completion thread.
  *
- * phiks_server_submit -- arguments as phiks_plan (real FP64, tolerance tol relative:
- * norms taken as 1) plus v (device, N doubles) and out (device, n_scales*(p+1)*N
- * doubles, laid out as phiks_apply's out).  A is copied; v and out must stay valid
- * until phiks_server_wait returns for the ticket.  Validation errors are returned
- * here, before anything is queued.  Plans are cached on the exact bytes of A and the
- * parameters (least recently used plans that no queued request holds are evicted
- * when the cache would exceed hbm_budget - workspace_bytes).
+ * phiks_server_register -- copies the host matrices A_1..A_d (as phiks_plan) once and
+ * returns an operator id for submit.  Operators stay registered until destroy.
+ *
+ * phiks_server_submit -- one request on a registered operator: tau, p, n_scales, tol
+ * as phiks_plan (real FP64, tolerance tol relative: norms taken as 1), v (device, N
+ * doubles) and out (device, n_scales*(p+1)*N doubles, laid out as phiks_apply's out).
+ * v and out must stay valid until phiks_server_wait returns for the ticket.
+ * Validation errors are returned here, before anything is queued.  Plans are cached
+ * on (operator, tau, p, n_scales, tol); least recently used plans that no queued
+ * request holds are evicted when the cache would exceed hbm_budget - workspace_bytes.
  *
  * phiks_server_wait -- blocks until the request is done, returns its status (the
  * result is then in out, bitwise what phiks_apply returns for it) and its latency
@@ -251,9 +254,10 @@ typedef struct {
 
 int phiks_server_create(size_t hbm_budget, size_t workspace_bytes, int max_group,
                         void* hip_stream, phiks_server_t* out);
-int phiks_server_submit(phiks_server_t server, int d, const int64_t* n, const double* const* A,
-                        double tau, int p, int n_scales, double tol, const double* v,
-                        double* out, int64_t* ticket);
+int phiks_server_register(phiks_server_t server, int d, const int64_t* n,
+                          const double* const* A, int64_t* op_id);
+int phiks_server_submit(phiks_server_t server, int64_t op_id, double tau, int p, int n_scales,
+                        double tol, const double* v, double* out, int64_t* ticket);
 int phiks_server_wait(phiks_server_t server, int64_t ticket, double* latency_s);
 int phiks_server_stats(phiks_server_t server, phiks_server_stats_t* out);
 void phiks_server_destroy(phiks_server_t server);

@@ -44,7 +44,7 @@ SYMBOLS = ("phiks_plan", "phiks_apply", "phiks_combine", "phiks_workspace_size",
            "phiks_device_free", "phiks_memcpy_htod", "phiks_memcpy_dtoh",
            "phiks_device_synchronize", "phiks_memcpy_dtod", "phiks_batch_plan",
            "phiks_batch_apply", "phiks_batch_workspace_size", "phiks_batch_info",
-           "phiks_batch_destroy", "phiks_server_create", "phiks_server_submit",
+           "phiks_batch_destroy", "phiks_server_create", "phiks_server_register", "phiks_server_submit",
            "phiks_server_wait", "phiks_server_stats", "phiks_server_destroy")
 
 if not os.path.exists(LIB_PATH):
@@ -119,8 +119,10 @@ class ServerStats(ctypes.Structure):
 _lib.phiks_server_create.restype = ctypes.c_int
 _lib.phiks_server_create.argtypes = [ctypes.c_size_t, ctypes.c_size_t, ctypes.c_int, _vp,
                                      ctypes.POINTER(_vp)]
+_lib.phiks_server_register.restype = ctypes.c_int
+_lib.phiks_server_register.argtypes = [_vp, ctypes.c_int, _i64p, _dpp, _i64p]
 _lib.phiks_server_submit.restype = ctypes.c_int
-_lib.phiks_server_submit.argtypes = [_vp, ctypes.c_int, _i64p, _dpp, ctypes.c_double, ctypes.c_int,
+_lib.phiks_server_submit.argtypes = [_vp, ctypes.c_int64, ctypes.c_double, ctypes.c_int,
                                      ctypes.c_int, ctypes.c_double, _vp, _vp, _i64p]
 _lib.phiks_server_wait.restype = ctypes.c_int
 _lib.phiks_server_wait.argtypes = [_vp, ctypes.c_int64, _dp]
@@ -493,13 +495,20 @@ class Server:
                "phiks_server_create")
         self._h = h
 
-    def submit(self, A: Sequence[np.ndarray], tau: float, p: int, n_scales: int, tol: float,
-               v_ptr: int, out_ptr: int) -> int:
+    def register(self, A: Sequence[np.ndarray]) -> int:
+        """Registers the operator A_1..A_d; returns its id."""
         mats, n, ptrs = _host_mats(A)
+        op = ctypes.c_int64()
+        _check(_lib.phiks_server_register(self._h, len(mats), n, ptrs, ctypes.byref(op)),
+               "phiks_server_register")
+        return op.value
+
+    def submit(self, op: int, tau: float, p: int, n_scales: int, tol: float, v_ptr: int,
+               out_ptr: int) -> int:
         t = ctypes.c_int64()
-        _check(_lib.phiks_server_submit(self._h, len(mats), n, ptrs, float(tau), int(p),
-                                        int(n_scales), float(tol), _vp(v_ptr), _vp(out_ptr),
-                                        ctypes.byref(t)), "phiks_server_submit")
+        _check(_lib.phiks_server_submit(self._h, int(op), float(tau), int(p), int(n_scales),
+                                        float(tol), _vp(v_ptr), _vp(out_ptr), ctypes.byref(t)),
+               "phiks_server_submit")
         return t.value
 
     def wait(self, ticket: int) -> float:

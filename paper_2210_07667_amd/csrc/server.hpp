@@ -2,9 +2,10 @@
 //
 // A request is one phiks_apply (outputs as eq. scaldiffphi) on caller-owned device
 // vectors.  Inside the server:
+//   * operators are registered once (host copies of A_1..A_d) and named by an id;
 //   * plan cache: the plans (host plan + the small exponentials of Section 3.1 on the
-//     device) keyed on the exact operator bytes, tau, p, n_scales and tol; requests of
-//     one operator and step share one plan.  LRU eviction of unused plans keeps the
+//     device) keyed on (operator id, tau, p, n_scales, tol); requests of one operator
+//     and step share one plan.  LRU eviction of unused plans keeps the
 //     cache within the HBM budget less the workspace arena.
 //   * admission: the worker takes pending requests in arrival order that share the
 //     first one's (p, n_scales), as long as their workspaces fit the arena and the
@@ -36,7 +37,7 @@ double now_s() {
 }
 
 struct PlanKey {
-  std::vector<char> bytes;  // d, n, tau, p, n_scales, tol, then every A_mu
+  std::vector<char> bytes;  // operator id, tau, p, n_scales, tol
   uint64_t hash = 0;
   bool operator==(const PlanKey& o) const { return hash == o.hash && bytes == o.bytes; }
 };
@@ -51,12 +52,17 @@ struct CachedPlan {
   uint64_t last_use = 0;   // LRU tick
 };
 
+struct ServerOperator {
+  int d = 0;
+  int64_t n[PHIKS_MAX_D] = {0};
+  int64_t N = 1;
+  std::vector<std::vector<double>> A;  // host copies, row-major
+};
+
 struct ServerRequest {
   int64_t ticket = 0;
   PlanKey key;
-  std::vector<std::vector<double>> A;  // host copies (built into a plan on a cache miss)
-  int d = 0;
-  int64_t n[PHIKS_MAX_D] = {0};
+  const ServerOperator* op = nullptr;
   double tau = 0.0, tol = 0.0;
   int p = 0, ns = 1;
   const double* v = nullptr;
@@ -94,6 +100,8 @@ struct phiks_server_s {
   std::condition_variable cv_work, cv_done, cv_inflight;
   std::deque<ServerRequest*> pending;
   std::unordered_map<int64_t, ServerRequest*> tickets;
+  std::unordered_map<int64_t, ServerOperator> ops;
+  int64_t next_op = 1;
   std::unordered_map<PlanKey, CachedPlan, PlanKeyHash> cache;
   size_t cache_bytes = 0;
   std::deque<InFlightGroup> inflight;
@@ -126,10 +134,11 @@ int server_plan(phiks_server_s& S, ServerRequest* r) {
       return PHIKS_OK;
     }
   }
-  std::vector<const double*> A(r->d);
-  for (int mu = 0; mu < r->d; ++mu) A[mu] = r->A[mu].data();
+  const ServerOperator& op = *r->op;
+  std::vector<const double*> A(op.d);
+  for (int mu = 0; mu < op.d; ++mu) A[mu] = op.A[mu].data();
   phiks_plan_t plan = nullptr;
-  int rc = phiks_plan(r->d, r->n, A.data(), r->tau, r->p, r->ns, r->tol, PHIKS_SAME_VECTOR,
+  int rc = phiks_plan(op.d, op.n, A.data(), r->tau, r->p, r->ns, r->tol, PHIKS_SAME_VECTOR,
                       nullptr, PHIKS_FP64, S.stream, &plan);
   if (rc != PHIKS_OK) return rc;
   const size_t bytes = plan_device_doubles(*plan) * sizeof(double);
@@ -294,51 +303,63 @@ int phiks_server_create(size_t hbm_budget, size_t workspace_bytes, int max_group
   return PHIKS_OK;
 }
 
-int phiks_server_submit(phiks_server_t server, int d, const int64_t* n, const double* const* A,
-                        double tau, int p, int n_scales, double tol, const double* v,
-                        double* out, int64_t* ticket) {
-  if (!server || !v || !out || !ticket) return PHIKS_EINVAL;
-  int rc = validate_problem(d, n, A, tau, p, n_scales, tol, PHIKS_SAME_VECTOR, nullptr);
+int phiks_server_register(phiks_server_t server, int d, const int64_t* n,
+                          const double* const* A, int64_t* op_id) {
+  if (!server || !op_id) return PHIKS_EINVAL;
+  // any valid same-vector problem on these matrices (tau, p and tol are checked at submit)
+  int rc = validate_problem(d, n, A, 1.0, 0, 1, 1.0, PHIKS_SAME_VECTOR, nullptr);
   if (rc != PHIKS_OK) return rc;
+  ServerOperator op;
+  op.d = d;
+  op.A.resize(d);
+  for (int mu = 0; mu < d; ++mu) {
+    op.n[mu] = n[mu];
+    op.N *= n[mu];
+    op.A[mu].assign(A[mu], A[mu] + n[mu] * n[mu]);
+  }
+  std::lock_guard<std::mutex> lk(server->mu);
+  *op_id = server->next_op++;
+  server->ops.emplace(*op_id, std::move(op));
+  return PHIKS_OK;
+}
+
+int phiks_server_submit(phiks_server_t server, int64_t op_id, double tau, int p, int n_scales,
+                        double tol, const double* v, double* out, int64_t* ticket) {
+  if (!server || !v || !out || !ticket) return PHIKS_EINVAL;
+  if (p < 0 || p > PHIKS_MAX_P || n_scales < 1 || n_scales > 16) return PHIKS_EINVAL;
+  if (!std::isfinite(tau) || !std::isfinite(tol)) return PHIKS_ENONFINITE;
+  if (!(tau > 0.0) || !(tol > 0.0)) return PHIKS_EINVAL;
   ServerRequest* r = new (std::nothrow) ServerRequest;
   if (!r) return PHIKS_ENOMEM;
-  r->d = d;
-  int64_t N = 1;
-  for (int mu = 0; mu < d; ++mu) { r->n[mu] = n[mu]; N *= n[mu]; }
   r->tau = tau;
   r->tol = tol;
   r->p = p;
   r->ns = n_scales;
   r->v = v;
   r->out = out;
-  const int64_t t = std::max<int64_t>({(int64_t)kQMax - 1, (int64_t)p, 1});
-  r->ws_bound = (size_t)(2 * t + 2 * p) * N;
-  if (r->ws_bound > server->arena_doubles) {
-    delete r;
-    set_error("request workspace exceeds the server's workspace arena");
-    return PHIKS_EWORKSPACE;
-  }
-  // key: the parameters, then the operator bytes (exact match on lookup)
   auto put = [&](const void* src, size_t bytes) {
     const char* c = (const char*)src;
     r->key.bytes.insert(r->key.bytes.end(), c, c + bytes);
   };
-  put(&d, sizeof(d));
-  put(n, sizeof(int64_t) * d);
+  put(&op_id, sizeof(op_id));
   put(&tau, sizeof(tau));
   put(&p, sizeof(p));
   put(&n_scales, sizeof(n_scales));
   put(&tol, sizeof(tol));
-  r->A.resize(d);
-  for (int mu = 0; mu < d; ++mu) {
-    r->A[mu].assign(A[mu], A[mu] + n[mu] * n[mu]);
-    put(A[mu], sizeof(double) * n[mu] * n[mu]);
-  }
   r->key.hash = fnv1a(r->key.bytes.data(), r->key.bytes.size());
   std::lock_guard<std::mutex> lk(server->mu);
-  if (server->stop) {
+  auto it = server->ops.find(op_id);
+  if (it == server->ops.end() || server->stop) {
     delete r;
     return PHIKS_EINVAL;
+  }
+  r->op = &it->second;
+  const int64_t t = std::max<int64_t>({(int64_t)kQMax - 1, (int64_t)p, 1});
+  r->ws_bound = (size_t)(2 * t + 2 * p) * r->op->N;
+  if (r->ws_bound > server->arena_doubles) {
+    delete r;
+    set_error("request workspace exceeds the server's workspace arena");
+    return PHIKS_EWORKSPACE;
   }
   r->ticket = server->next_ticket++;
   r->t_submit = now_s();

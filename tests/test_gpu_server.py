@@ -45,6 +45,7 @@ def reference(sess, v, ns=1):
 
 def run_requests(server, sessions, picks, seed, ns_of=lambda k: 1):
     rng = np.random.default_rng(seed)
+    ops = {}
     reqs = []
     for k, si in enumerate(picks):
         sess = sessions[si]
@@ -52,7 +53,9 @@ def run_requests(server, sessions, picks, seed, ns_of=lambda k: 1):
         v = rng.standard_normal(sess.N)
         dv = ph.DeviceArray.from_numpy(v)
         out = ph.DeviceArray(ns * (sess.p + 1) * sess.N)
-        t = server.submit(sess.A, sess.tau, sess.p, ns, TOL, dv.ptr, out.ptr)
+        if si not in ops:
+            ops[si] = server.register(sess.A)
+        t = server.submit(ops[si], sess.tau, sess.p, ns, TOL, dv.ptr, out.ptr)
         reqs.append((si, ns, v, dv, out, t))
     lat = [server.wait(t) for (_, _, _, _, _, t) in reqs]
     return reqs, lat
@@ -96,14 +99,22 @@ def test_submit_errors():
     sess = small_sessions()[0]
     dv = ph.DeviceArray(sess.N)
     out = ph.DeviceArray(3 * sess.N)
+    op = server.register(sess.A)
     with pytest.raises(ph.PhiksError) as e:
-        server.submit(sess.A, -1.0, sess.p, 1, TOL, dv.ptr, out.ptr)
+        server.submit(op, -1.0, sess.p, 1, TOL, dv.ptr, out.ptr)
     assert e.value.status == ph.PHIKS_EINVAL
+    with pytest.raises(ph.PhiksError) as e:
+        server.submit(op + 100, sess.tau, sess.p, 1, TOL, dv.ptr, out.ptr)
+    assert e.value.status == ph.PHIKS_EINVAL
+    bad = [workloads.fd2_dirichlet(24), np.full((24, 24), np.nan)]
+    with pytest.raises(ph.PhiksError) as e:
+        server.register(bad)
+    assert e.value.status == ph.PHIKS_ENONFINITE
     big = workloads.Session("big", [128, 128, 64], [workloads.fd2_dirichlet(m) for m in (128, 128, 64)], 1e-3, 4)
     dvb = ph.DeviceArray(big.N)
     outb = ph.DeviceArray(5 * big.N)
     with pytest.raises(ph.PhiksError) as e:
-        server.submit(big.A, big.tau, big.p, 1, TOL, dvb.ptr, outb.ptr)
+        server.submit(server.register(big.A), big.tau, big.p, 1, TOL, dvb.ptr, outb.ptr)
     assert e.value.status == ph.PHIKS_EWORKSPACE
     server.close()
 
