@@ -28,7 +28,8 @@ __all__ = [
     "fd2_dirichlet", "central_adv_dirichlet", "adr_1d", "cheb_d2_dirichlet",
     "randn_vec", "uniform_vec", "Workload", "config_fd2_2d", "config_allen_cahn_3d",
     "config_adr_3d", "validation_table1", "BatchProblem", "config_batch",
-    "fd2_neumann", "Session", "serving_sessions", "poisson_arrivals",
+    "fd2_neumann", "Session", "serving_sessions", "poisson_arrivals", "ADRProblem",
+    "adr_integration_problem",
 ]
 
 
@@ -267,4 +268,41 @@ def poisson_arrivals(rate: float, duration: float, seed: int) -> np.ndarray:
         if t >= duration:
             return np.asarray(out)
         out.append(t)
+
+
+@dataclass
+class ADRProblem:
+    """The evolutionary advection-diffusion-reaction problem of Section 4.2:
+    u_t = eps Lap u + alpha (d_1 + d_2 + d_3) u + 1/(1 + u^2) + Psi(t, x) on [0,1]^3,
+    homogeneous Dirichlet, u_0 = 64 prod x_j (1 - x_j), Psi chosen so that the exact
+    solution is e^t u_0.  Semi-discretised with n interior points per direction
+    (second-order centred differences, exact for this u_0), K = A_3 (+) A_2 (+) A_1 with
+    A_mu = eps FD2 + alpha central_adv.  Then Psi(t) = e^t w - 1/(1 + e^(2t) u_0^2) with
+    w = u_0 - eps Lap u_0 - alpha sum_j d_j u_0 (analytic, at the grid points)."""
+    n: int
+    eps: float
+    alpha: float
+    A: List[np.ndarray]
+    u0: np.ndarray
+    w: np.ndarray
+
+    def exact(self, t: float) -> np.ndarray:
+        return math.exp(t) * self.u0
+
+
+def adr_integration_problem(n: int = 20, eps: float = 0.5, alpha: float = 10.0) -> ADRProblem:
+    x = grid_1d(n)
+    f = x * (1.0 - x)            # f_j(x) = x (1 - x)
+    df = 1.0 - 2.0 * x           # f'
+    d2f = -2.0 * np.ones_like(x)  # f''
+
+    def tens(a, b, c):           # vec order: x_1 fastest
+        return np.kron(c, np.kron(b, a))
+
+    u0 = 64.0 * tens(f, f, f)
+    lap = 64.0 * (tens(d2f, f, f) + tens(f, d2f, f) + tens(f, f, d2f))
+    grad = 64.0 * (tens(df, f, f) + tens(f, df, f) + tens(f, f, df))
+    w = u0 - eps * lap - alpha * grad
+    Amu = eps * fd2_dirichlet(n) + central_adv_dirichlet(n, alpha)
+    return ADRProblem(n=n, eps=eps, alpha=alpha, A=[Amu.copy() for _ in range(3)], u0=u0, w=w)
 
