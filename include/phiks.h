@@ -263,6 +263,19 @@ int phiks_server_stats(phiks_server_t server, phiks_server_stats_t* out);
 void phiks_server_destroy(phiks_server_t server);
 
 /*
+ * Elementwise device vector operations for time integrators built on the phi-actions
+ * (the nonlinear terms and stage combinations of the exponential integrators of
+ * Section 4): out[k] for k < n, with y[k] read as 0 when y is NULL.
+ *   PHIKS_VOP_AXPBY     a x + b y
+ *   PHIKS_VOP_RATIONAL  a / (1 + (b x)^2) + y
+ *   PHIKS_VOP_CUBIC     a (x - x^3) + b y
+ * x, y, out: device arrays of n doubles; out may alias x or y.  Stream-ordered.
+ */
+enum { PHIKS_VOP_AXPBY = 0, PHIKS_VOP_RATIONAL = 1, PHIKS_VOP_CUBIC = 2 };
+int phiks_vector_op(int op, int64_t n, double a, const double* x, double b, const double* y,
+                    double* out, void* hip_stream);
+
+/*
  * Device-memory plumbing for callers without their own allocator (the Python
  * binding and the tests use these, so that one HIP runtime -- the one this library
  * was built against -- serves the whole process).  Copies are synchronous.

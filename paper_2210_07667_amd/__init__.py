@@ -34,6 +34,9 @@ PHIKS_LINCOMB = 1
 PHIKS_FP64 = 0
 PHIKS_FP32 = 1
 PHIKS_BF16X3 = 2
+PHIKS_VOP_AXPBY = 0
+PHIKS_VOP_RATIONAL = 1
+PHIKS_VOP_CUBIC = 2
 
 # every exported entry point of include/phiks.h
 SYMBOLS = ("phiks_plan", "phiks_apply", "phiks_combine", "phiks_workspace_size",
@@ -45,7 +48,8 @@ SYMBOLS = ("phiks_plan", "phiks_apply", "phiks_combine", "phiks_workspace_size",
            "phiks_device_synchronize", "phiks_memcpy_dtod", "phiks_batch_plan",
            "phiks_batch_apply", "phiks_batch_workspace_size", "phiks_batch_info",
            "phiks_batch_destroy", "phiks_server_create", "phiks_server_register", "phiks_server_submit",
-           "phiks_server_wait", "phiks_server_stats", "phiks_server_destroy")
+           "phiks_server_wait", "phiks_server_stats", "phiks_server_destroy",
+           "phiks_vector_op")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with "
@@ -130,6 +134,9 @@ _lib.phiks_server_stats.restype = ctypes.c_int
 _lib.phiks_server_stats.argtypes = [_vp, ctypes.POINTER(ServerStats)]
 _lib.phiks_server_destroy.restype = None
 _lib.phiks_server_destroy.argtypes = [_vp]
+_lib.phiks_vector_op.restype = ctypes.c_int
+_lib.phiks_vector_op.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_double, _vp, ctypes.c_double,
+                                 _vp, _vp, _vp]
 
 
 class PhiksError(RuntimeError):
@@ -481,6 +488,14 @@ def batch_apply_arrays(batch: Batch, vs: Sequence[DeviceArray], outs=None, ws=No
         ws = DeviceArray(batch.workspace_size() // 8 + 1)
     phiks_batch_apply(batch, [v.ptr for v in vs], [o.ptr for o in outs], ws.ptr, ws.nbytes, stream)
     return outs
+
+
+def vector_op(op: int, n: int, a: float, x_ptr: int, b: float, y_ptr: Optional[int],
+              out_ptr: int, stream: int = 0) -> None:
+    """Elementwise device op (PHIKS_VOP_*): see include/phiks.h."""
+    _check(_lib.phiks_vector_op(int(op), int(n), float(a), _vp(x_ptr), float(b),
+                                None if y_ptr is None else _vp(y_ptr), _vp(out_ptr), _vp(stream)),
+           "phiks_vector_op")
 
 
 class Server:

@@ -76,6 +76,36 @@ __global__ void __launch_bounds__(256) combine_grouped_kernel(const CombineArgs*
                (int64_t)gridDim.x * blockDim.x);
 }
 
+// Elementwise vector operations for integrators built on the phi-actions (y may be
+// null: zero).  Axpby: a x + b y.  Rational: a / (1 + (b x)^2) + y.  Cubic: a (x - x^3) + b y.
+enum { kVopAxpby = 0, kVopRational = 1, kVopCubic = 2 };
+struct VecOpArgs {
+  int op;
+  int64_t N;
+  double a, b;
+  const double* x;
+  const double* y;
+  double* out;
+};
+
+__global__ void __launch_bounds__(256) vector_op_kernel(VecOpArgs v) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < v.N;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const double x = v.x[e];
+    const double y = v.y ? v.y[e] : 0.0;
+    double r;
+    if (v.op == kVopAxpby) {
+      r = v.a * x + v.b * y;
+    } else if (v.op == kVopRational) {
+      const double bx = v.b * x;
+      r = v.a / (1.0 + bx * bx) + y;
+    } else {
+      r = v.a * (x - x * x * x) + v.b * y;
+    }
+    v.out[e] = r;
+  }
+}
+
 // dst = (float)src, n entries.
 __global__ void __launch_bounds__(256) to_f32_kernel(const double* src, float* dst, int64_t n) {
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;

@@ -763,6 +763,20 @@ int phiks_tucker(int d, const int64_t* n, const double* const* L, const double* 
                 (hipStream_t)hip_stream);
 }
 
+int phiks_vector_op(int op, int64_t n, double a, const double* x, double b, const double* y,
+                    double* out, void* hip_stream) {
+  if (op < PHIKS_VOP_AXPBY || op > PHIKS_VOP_CUBIC || n < 0 || (n > 0 && (!x || !out)))
+    return PHIKS_EINVAL;
+  if (!std::isfinite(a) || !std::isfinite(b)) return PHIKS_ENONFINITE;
+  if (n == 0) return PHIKS_OK;
+  VecOpArgs v{op, n, a, b, x, y, out};
+  const int64_t blocks = std::min<int64_t>((n + 255) / 256, 4096);
+  (void)hipGetLastError();
+  hipLaunchKernelGGL(vector_op_kernel, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)hip_stream, v);
+  CHECK_LAUNCH();
+  return PHIKS_OK;
+}
+
 int phiks_workspace_size(phiks_plan_t plan, size_t* bytes) {
   if (!plan || !bytes) return PHIKS_EINVAL;
   *bytes = workspace_doubles(*plan) * sizeof(double);
