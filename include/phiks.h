@@ -109,6 +109,20 @@ int phiks_plan(int d, const int64_t* n, const double* const* A, double tau, int 
                void* hip_stream, phiks_plan_t* out);
 
 /*
+ * phiks_plan_complex -- as phiks_plan for complex A_mu and a complex step tau (the
+ * paper admits both; the validation operators of Section 4.1 are complex).  A[mu]
+ * is an n[mu] x n[mu] complex matrix, row-major, each entry two float64 (re, im);
+ * tau = tau_re + i tau_im, nonzero.  Arithmetic FP64.  With such a plan every vector
+ * of phiks_apply / phiks_combine (v, out) holds N complex values as 2N float64
+ * (re, im interleaved), in the same index order, and the workspace is doubled.
+ * Internally each complex matrix is used in its real form (2 x 2 blocks [[Re, -Im],
+ * [Im, Re]]); the quadrature and squaring coefficients are real.
+ */
+int phiks_plan_complex(int d, const int64_t* n, const double* const* A, double tau_re,
+                       double tau_im, int p, int n_scales, double tol, int task,
+                       const double* vnorms, void* hip_stream, phiks_plan_t* out);
+
+/*
  * phiks_apply -- same vector (eqs. integrandsimul and simul, multi-scale outputs
  * of eq. scaldiffphi).  Requires a plan made with PHIKS_SAME_VECTOR.
  *
@@ -303,6 +317,10 @@ const char* phiks_last_error(void);
 int phiks_plan_params(int d, const int64_t* n, const double* const* A, double tau,
                       int p, int n_scales, double tol, int task, const double* vnorms,
                       int* s, int* q, int* tucker_paper);
+/* The (s, q, T#) that phiks_plan_complex would choose. */
+int phiks_plan_params_complex(int d, const int64_t* n, const double* const* A, double tau_re,
+                              double tau_im, int p, int n_scales, double tol, int task,
+                              const double* vnorms, int* s, int* q, int* tucker_paper);
 
 /* Gauss-Lobatto-Legendre rule on [0,1] with q points, 2 <= q <= 12:
  * theta[0] = 0 < ... < theta[q-1] = 1 and weights w (host arrays of q doubles). */

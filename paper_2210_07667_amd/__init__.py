@@ -49,7 +49,7 @@ SYMBOLS = ("phiks_plan", "phiks_apply", "phiks_combine", "phiks_workspace_size",
            "phiks_batch_apply", "phiks_batch_workspace_size", "phiks_batch_info",
            "phiks_batch_destroy", "phiks_server_create", "phiks_server_register", "phiks_server_submit",
            "phiks_server_wait", "phiks_server_stats", "phiks_server_destroy",
-           "phiks_vector_op")
+           "phiks_vector_op", "phiks_plan_complex", "phiks_plan_params_complex")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with "
@@ -134,6 +134,15 @@ _lib.phiks_server_stats.restype = ctypes.c_int
 _lib.phiks_server_stats.argtypes = [_vp, ctypes.POINTER(ServerStats)]
 _lib.phiks_server_destroy.restype = None
 _lib.phiks_server_destroy.argtypes = [_vp]
+_lib.phiks_plan_complex.restype = ctypes.c_int
+_lib.phiks_plan_complex.argtypes = [ctypes.c_int, _i64p, _dpp, ctypes.c_double, ctypes.c_double,
+                                    ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int, _dp,
+                                    _vp, ctypes.POINTER(_vp)]
+_lib.phiks_plan_params_complex.restype = ctypes.c_int
+_lib.phiks_plan_params_complex.argtypes = [ctypes.c_int, _i64p, _dpp, ctypes.c_double,
+                                           ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                                           ctypes.c_double, ctypes.c_int, _dp]
+_lib.phiks_plan_params_complex.argtypes += [ctypes.POINTER(ctypes.c_int)] * 3
 _lib.phiks_vector_op.restype = ctypes.c_int
 _lib.phiks_vector_op.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_double, _vp, ctypes.c_double,
                                  _vp, _vp, _vp]
@@ -181,13 +190,28 @@ def _norms(vnorms):
     return arr, ctypes.cast(arr, _dp)
 
 
+def _host_mats_complex(A: Sequence[np.ndarray]):
+    """Complex matrices as row-major (re, im) interleaved float64."""
+    mats = [np.ascontiguousarray(np.asarray(a, dtype=np.complex128)) for a in A]
+    for m in mats:
+        if m.ndim != 2 or m.shape[0] != m.shape[1]:
+            raise ValueError("each A_mu must be a square matrix")
+    flat = [m.view(np.float64) for m in mats]
+    n = (ctypes.c_int64 * len(mats))(*[m.shape[0] for m in mats])
+    ptrs = (_dp * len(mats))(*[f.ctypes.data_as(_dp) for f in flat])
+    return (mats, flat), n, ptrs
+
+
 class Plan:
     """Owns a phiks_plan_t (released by close() or garbage collection)."""
 
-    def __init__(self, handle: int, d: int, n, p: int, n_scales: int, task: int):
+    def __init__(self, handle: int, d: int, n, p: int, n_scales: int, task: int,
+                 cplx: bool = False):
         self._h = ctypes.c_void_p(handle)
         self.d, self.n, self.p, self.n_scales, self.task = d, list(n), p, n_scales, task
         self.N = int(np.prod(self.n))
+        self.cplx = cplx
+        self.vlen = 2 * self.N if cplx else self.N   # float64 values per vector
 
     @property
     def handle(self):
@@ -227,6 +251,35 @@ def phiks_plan(A: Sequence[np.ndarray], tau: float, p: int, n_scales: int, tol: 
                            tc, vn, int(precision), ctypes.c_void_p(stream), ctypes.byref(out)),
            "phiks_plan")
     return Plan(out.value, len(mats), list(n), p, n_scales, tc)
+
+
+def phiks_plan_complex(A: Sequence[np.ndarray], tau: complex, p: int, n_scales: int, tol: float,
+                       task="same_vector", vnorms: Optional[Sequence[float]] = None,
+                       stream: int = 0) -> Plan:
+    """Complex A_mu and step tau; the plan's vectors are complex (DeviceArray.from_numpy
+    of a complex array stores it as interleaved float64)."""
+    keep, n, ptrs = _host_mats_complex(A)
+    karr, vn = _norms(vnorms)
+    out = ctypes.c_void_p()
+    tc = _task_code(task)
+    tau = complex(tau)
+    _check(_lib.phiks_plan_complex(len(A), n, ptrs, tau.real, tau.imag, int(p), int(n_scales),
+                                   float(tol), tc, vn, ctypes.c_void_p(stream), ctypes.byref(out)),
+           "phiks_plan_complex")
+    return Plan(out.value, len(A), list(n), p, n_scales, tc, cplx=True)
+
+
+def phiks_plan_params_complex(A: Sequence[np.ndarray], tau: complex, p: int, n_scales: int,
+                              tol: float, task="same_vector", vnorms=None):
+    keep, n, ptrs = _host_mats_complex(A)
+    karr, vn = _norms(vnorms)
+    s, q, tp = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    tau = complex(tau)
+    _check(_lib.phiks_plan_params_complex(len(A), n, ptrs, tau.real, tau.imag, int(p),
+                                          int(n_scales), float(tol), _task_code(task), vn,
+                                          ctypes.byref(s), ctypes.byref(q), ctypes.byref(tp)),
+           "phiks_plan_params_complex")
+    return s.value, q.value, tp.value
 
 
 def phiks_apply(plan: Plan, v_ptr: int, out_ptr: int, ws_ptr: int, ws_bytes: int,
@@ -353,6 +406,10 @@ class DeviceArray:
 
     @classmethod
     def from_numpy(cls, x) -> "DeviceArray":
+        """float64 data; complex data is stored as interleaved (re, im) float64."""
+        x = np.asarray(x)
+        if np.iscomplexobj(x):
+            x = np.ascontiguousarray(x.astype(np.complex128)).reshape(-1).view(np.float64)
         x = np.ascontiguousarray(np.asarray(x, dtype=np.float64)).reshape(-1)
         d = cls(x.size)
         _check(_lib.phiks_memcpy_htod(d._p, x.ctypes.data_as(_vp), x.nbytes), "phiks_memcpy_htod")
@@ -362,6 +419,10 @@ class DeviceArray:
         x = np.empty(self.n, dtype=np.float64)
         _check(_lib.phiks_memcpy_dtoh(x.ctypes.data_as(_vp), self._p, x.nbytes), "phiks_memcpy_dtoh")
         return x
+
+    def to_complex(self) -> np.ndarray:
+        """The contents read as interleaved (re, im) pairs."""
+        return self.to_numpy().view(np.complex128)
 
     def free(self) -> None:
         if self._p is not None and self._p.value:
@@ -380,10 +441,10 @@ def apply_arrays(plan: Plan, v: DeviceArray, out: Optional[DeviceArray] = None,
     """Same-vector task; out holds n_scales * (p+1) * N values."""
     if plan.task != PHIKS_SAME_VECTOR:
         raise ValueError("plan was made for a linear combination")
-    if v.n != plan.N:
-        raise ValueError("v must hold N values")
+    if v.n != plan.vlen:
+        raise ValueError("v must hold N values (2N float64 for a complex plan)")
     if out is None:
-        out = DeviceArray(plan.n_scales * (plan.p + 1) * plan.N)
+        out = DeviceArray(plan.n_scales * (plan.p + 1) * plan.vlen)
     if ws is None:
         ws = DeviceArray(plan.workspace_size() // 8 + 1)
     phiks_apply(plan, v.ptr, out.ptr, ws.ptr, ws.nbytes, stream)
@@ -398,10 +459,10 @@ def combine_arrays(plan: Plan, vs, out: Optional[DeviceArray] = None,
     if len(vs) != plan.p + 1:
         raise ValueError("need p+1 vectors")
     for x in vs:
-        if x is not None and x.n != plan.N:
-            raise ValueError("vectors must hold N values")
+        if x is not None and x.n != plan.vlen:
+            raise ValueError("vectors must hold N values (2N float64 for a complex plan)")
     if out is None:
-        out = DeviceArray(plan.n_scales * plan.N)
+        out = DeviceArray(plan.n_scales * plan.vlen)
     if ws is None:
         ws = DeviceArray(plan.workspace_size() // 8 + 1)
     phiks_combine(plan, [None if x is None else x.ptr for x in vs], out.ptr, ws.ptr, ws.nbytes,

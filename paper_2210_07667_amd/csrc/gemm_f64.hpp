@@ -110,8 +110,14 @@ __device__ __forceinline__ int swz_n(int k) { return (k & 1) << 4; }
 
 // One output tile of one GEMM: `rest` is the logical tile index in the tile order
 // described above (0 .. g.total_tiles - 1).
-template <int BM, int BN, int WM, int WN, bool B_KCONTIG, bool VEC, class Epi>
+//
+// CPLX (n-contiguous B with 16-byte loads only): the complex mu-mode product of modes
+// > 1 on re/im interleaved tensors.  With K = 2n, rows k < n of B are the tensor slab
+// itself and rows k >= n are the same slab with every (re, im) pair replaced by
+// (-im, re), so that C = [Re L | Im L] B is the interleaved complex product L X.
+template <int BM, int BN, int WM, int WN, bool B_KCONTIG, bool VEC, class Epi, bool CPLX = false>
 __device__ __forceinline__ void gemm_f64_tile(const GemmArgs& g, const Epi& epi, int64_t rest) {
+  static_assert(!CPLX || (!B_KCONTIG && VEC), "the complex form needs an n-contiguous B, 16-byte loads");
   constexpr int BK = 16;
   constexpr int WGM = BM / WM;
   constexpr int WGN = BN / WN;
@@ -214,9 +220,10 @@ __device__ __forceinline__ void gemm_f64_tile(const GemmArgs& g, const Epi& epi,
       int n, k;
       if constexpr (B_KCONTIG) { n = e / (BK / VW); k = VW * (e % (BK / VW)); }
       else { k = e / (BN / VW); n = VW * (e % (BN / VW)); }
-      const int gn = n0 + n, gk = k0 + k;
+      int gn = n0 + n, gk = k0 + k;
       const bool ok = b_ok(e, k0);
       if constexpr (!VEC) bmask |= (uint32_t)ok << i;
+      if constexpr (CPLX) gk -= (gk >= (g.K >> 1)) ? (g.K >> 1) : 0;
       const int64_t off =
           ok ? (B_KCONTIG ? (int64_t)gn * g.ldb + gk : (int64_t)gk * g.ldb + gn) : 0;
       rb[i] = *reinterpret_cast<const PHIKS_GLOBAL vec_t*>(B + off);
@@ -238,7 +245,10 @@ __device__ __forceinline__ void gemm_f64_tile(const GemmArgs& g, const Epi& epi,
 #pragma unroll
     for (int i = 0; i < LB; ++i) {
       const int e = tid + i * 256;
-      const vec_t x = b_in(i, e, k0) ? rb[i] : vec_t(0.0);
+      vec_t x = b_in(i, e, k0) ? rb[i] : vec_t(0.0);
+      if constexpr (CPLX) {
+        if (k0 + e / (BN / VW) >= (g.K >> 1)) x = vec_t{-x[1], x[0]};
+      }
       if constexpr (B_KCONTIG) {
         const int n = e / (BK / VW), k = VW * (e % (BK / VW));
         if constexpr (VEC) {
@@ -349,9 +359,9 @@ __device__ __forceinline__ void gemm_f64_tile(const GemmArgs& g, const Epi& epi,
   }
 }
 
-template <int BM, int BN, int WM, int WN, bool B_KCONTIG, bool VEC, class Epi>
+template <int BM, int BN, int WM, int WN, bool B_KCONTIG, bool VEC, class Epi, bool CPLX = false>
 __global__ void __launch_bounds__(256, VEC ? PHIKS_GEMM_MIN_WAVES : 2) gemm_f64_kernel(GemmArgs g, Epi epi) {
-  gemm_f64_tile<BM, BN, WM, WN, B_KCONTIG, VEC>(g, epi, xcd_remap(blockIdx.x, g.total_tiles));
+  gemm_f64_tile<BM, BN, WM, WN, B_KCONTIG, VEC, Epi, CPLX>(g, epi, xcd_remap(blockIdx.x, g.total_tiles));
 }
 
 // Grouped launch: many independent GEMMs of one kind (same tile shape, operand layout

@@ -158,4 +158,18 @@ __global__ void __launch_bounds__(256) scale_copy_kernel(const ScaleJob* jobs) {
     J.dst[e] = J.scale * J.src[e];
 }
 
+// Complex plans: [Re | Im] form (n x 2n) of a matrix held in its real form R (2n x 2n,
+// 2 x 2 blocks [[Re, -Im], [Im, Re]]): dst[i][j] = R[2i][2j], dst[i][n+j] = R[2i+1][2j].
+// Batched like the scale jobs (src, dst, n = the complex size).
+__global__ void __launch_bounds__(256) complex_split_kernel(const ScaleJob* jobs) {
+  const ScaleJob& J = jobs[blockIdx.y];
+  const int64_t n = J.n;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < 2 * n * n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e / (2 * n), c = e % (2 * n);
+    const int64_t j = c % n, im = c / n;
+    J.dst[e] = J.src[(2 * i + im) * (2 * n) + 2 * j];
+  }
+}
+
 }  // namespace phiks

@@ -47,6 +47,20 @@ int plan_tucker(const phiks_plan_s& P, MatSel sel, int idx, const double* in,
                 const Epi& epi, hipStream_t st) {
   int64_t stride[PHIKS_MAX_D];
   for (int mu = 0; mu < P.d; ++mu) stride[mu] = (sel == MatSel::AllNodes) ? P.n[mu] * P.n[mu] : 0;
+  if (P.cplx) {
+    double* Lr[PHIKS_MAX_D];
+    double* Ls[PHIKS_MAX_D];
+    int64_t sr[PHIKS_MAX_D], ss[PHIKS_MAX_D];
+    for (int mu = 0; mu < P.d; ++mu) {
+      const int64_t nn = P.n[mu] * P.n[mu];
+      const size_t k = (sel == MatSel::AllNodes) ? 0 : (size_t)idx;
+      Lr[mu] = (sel == MatSel::Level) ? P.E[mu] + k * 4 * nn : P.Lnode[mu] + k * 4 * nn;
+      Ls[mu] = (sel == MatSel::Level) ? P.Esplit[mu] + k * 2 * nn : P.Lsplit[mu] + k * 2 * nn;
+      sr[mu] = 4 * stride[mu];
+      ss[mu] = 2 * stride[mu];
+    }
+    return tucker_complex(P, in, in_stride, Lr, sr, Ls, ss, nbatch, out, ta, tb, epi, st);
+  }
   if (P.precision != PHIKS_FP64) {
     float* L[PHIKS_MAX_D];
     for (int mu = 0; mu < P.d; ++mu) {
@@ -355,7 +369,7 @@ int host_plan(int d, const int64_t* n, const double* const* A, double tau, int p
 int plan_nodes(const phiks_plan_s& P) { return (P.p > 0) ? P.q - 1 : 0; }
 
 size_t workspace_doubles(const phiks_plan_s& P) {
-  const int64_t N = P.N;
+  const int64_t N = plan_vec_doubles(P);
   if (P.task == PHIKS_SAME_VECTOR) {
     const int64_t t = std::max<int64_t>({(int64_t)P.q - 1, (int64_t)P.p, 1});
     return (size_t)(2 * t + 2 * P.p) * N;
@@ -394,11 +408,75 @@ int plan_init_host(phiks_plan_s& P, int d, const int64_t* n, const double* const
   return PHIKS_OK;
 }
 
+// Complex problems: A_mu complex (re/im interleaved, row-major), tau complex and
+// nonzero.  The rectangle is the Bendixson rectangle of each B_mu = tau A_mu, summed.
+int plan_init_host_complex(phiks_plan_s& P, int d, const int64_t* n, const double* const* A,
+                           double tau_re, double tau_im, int p, int n_scales, double tol,
+                           int task, const double* vnorms) {
+  if (d < 1 || d > PHIKS_MAX_D || !n || !A) return PHIKS_EINVAL;
+  if (p < 0 || p > PHIKS_MAX_P || n_scales < 1 || n_scales > 16) return PHIKS_EINVAL;
+  if (task != PHIKS_SAME_VECTOR && task != PHIKS_LINCOMB) return PHIKS_EINVAL;
+  if (!std::isfinite(tau_re) || !std::isfinite(tau_im) || !std::isfinite(tol)) return PHIKS_ENONFINITE;
+  if ((tau_re == 0.0 && tau_im == 0.0) || !(tol > 0.0)) return PHIKS_EINVAL;
+  int64_t N = 1;
+  Rect xi{0.0, 0.0, 0.0, 0.0};
+  for (int mu = 0; mu < d; ++mu) {
+    if (n[mu] < 1 || n[mu] > PHIKS_MAX_N || !A[mu]) return PHIKS_EINVAL;
+    N *= n[mu];
+    if (N > (int64_t)1 << 39) return PHIKS_EINVAL;
+    const int64_t m = n[mu];
+    std::vector<double> B(2 * m * m);
+    for (int64_t e = 0; e < m * m; ++e) {
+      const double ar = A[mu][2 * e], ai = A[mu][2 * e + 1];
+      if (!std::isfinite(ar) || !std::isfinite(ai)) return PHIKS_ENONFINITE;
+      B[2 * e] = tau_re * ar - tau_im * ai;
+      B[2 * e + 1] = tau_re * ai + tau_im * ar;
+    }
+    const Rect r = bendixson_rectangle_complex(m, B.data());
+    xi.re_lo += r.re_lo;
+    xi.re_hi += r.re_hi;
+    xi.im_lo += r.im_lo;
+    xi.im_hi += r.im_hi;
+  }
+  if (vnorms) {
+    const int nv = (task == PHIKS_SAME_VECTOR) ? 1 : p + 1;
+    for (int k = 0; k < nv; ++k)
+      if (!std::isfinite(vnorms[k]) || vnorms[k] < 0.0) return PHIKS_EINVAL;
+  }
+  const PlanChoice pc = choose_sq(xi, p, n_scales, tol, task, vnorms);
+  if (!pc.ok) {
+    set_error("no (s, q) with s <= 64 and q <= 12 meets the tolerance");
+    return PHIKS_ENOPLAN;
+  }
+  P.d = d;
+  P.N = N;
+  for (int mu = 0; mu < d; ++mu) P.n[mu] = n[mu];
+  P.tau = tau_re;
+  P.tau_im = tau_im;
+  P.cplx = 1;
+  P.p = p;
+  P.ns = n_scales;
+  P.task = task;
+  P.precision = PHIKS_FP64;
+  P.s = pc.s;
+  P.q = pc.q;
+  P.t_paper = pc.tucker_paper;
+  if (p > 0) gll_rule(pc.q, P.theta, P.w);
+  const int nodes = plan_nodes(P);
+  if (task == PHIKS_SAME_VECTOR) P.t_exec = nodes + pc.s * p + n_scales;
+  else P.t_exec = nodes * p + pc.s * p + n_scales;
+  return PHIKS_OK;
+}
+
 // Plan-lifetime device memory in doubles: per mode the node matrices and exp(B/2^j),
 // j = 0..s, then (mixed precision) their FP32 copies, rounded up to whole doubles.
 size_t plan_device_doubles(const phiks_plan_s& P) {
   const int nodes = plan_nodes(P);
   size_t total = 0;
+  if (P.cplx) {  // real forms (4 n^2) and [Re | Im] forms (2 n^2) of every matrix
+    for (int mu = 0; mu < P.d; ++mu) total += (size_t)(nodes + P.s + 1) * 6 * sq(P.n[mu]);
+    return total;
+  }
   for (int mu = 0; mu < P.d; ++mu) total += (size_t)(nodes + P.s + 1) * sq(P.n[mu]);
   if (P.precision != PHIKS_FP64)
     for (int mu = 0; mu < P.d; ++mu)
@@ -410,6 +488,20 @@ size_t plan_device_doubles(const phiks_plan_s& P) {
 void plan_assign(phiks_plan_s& P, double* base) {
   const int nodes = plan_nodes(P);
   size_t total = 0;
+  if (P.cplx) {
+    for (int mu = 0; mu < P.d; ++mu) {
+      const size_t nn = sq(P.n[mu]);
+      P.Lnode[mu] = base + total;
+      total += (size_t)nodes * 4 * nn;
+      P.E[mu] = base + total;
+      total += (size_t)(P.s + 1) * 4 * nn;
+      P.Lsplit[mu] = base + total;
+      total += (size_t)nodes * 2 * nn;
+      P.Esplit[mu] = base + total;
+      total += (size_t)(P.s + 1) * 2 * nn;
+    }
+    return;
+  }
   for (int mu = 0; mu < P.d; ++mu) {
     P.Lnode[mu] = base + total;
     total += (size_t)nodes * sq(P.n[mu]);
@@ -463,15 +555,31 @@ int build_plan_matrices(const std::vector<phiks_plan_s*>& plans,
     const int nodes = plan_nodes(P);
     const double inv2s = std::ldexp(1.0, -P.s);
     for (int mu = 0; mu < P.d; ++mu) {
-      // shifted operator B - sigma I, sigma = tr(B)/n (the shift remark of Section 3.1)
-      const int64_t m = P.n[mu];
+      // shifted operator B - sigma I, sigma = tr(B)/n (the shift remark of Section 3.1);
+      // a complex B = tau A is taken in its real form (2n x 2n, blocks [[Re, -Im],
+      // [Im, Re]]), whose exponential is the real form of exp(B)
+      const int64_t nc = P.n[mu];
+      const int64_t m = P.cplx ? 2 * nc : nc;
       ExpmOp op;
       op.n = m;
       op.Bshift.resize(m * m);
+      if (P.cplx) {
+        const double* Ac = A[i][mu];
+        for (int64_t r = 0; r < nc; ++r)
+          for (int64_t c = 0; c < nc; ++c) {
+            const double ar = Ac[2 * (r * nc + c)], ai = Ac[2 * (r * nc + c) + 1];
+            const double br = P.tau * ar - P.tau_im * ai, bi = P.tau * ai + P.tau_im * ar;
+            op.Bshift[(2 * r) * m + 2 * c] = br;
+            op.Bshift[(2 * r) * m + 2 * c + 1] = -bi;
+            op.Bshift[(2 * r + 1) * m + 2 * c] = bi;
+            op.Bshift[(2 * r + 1) * m + 2 * c + 1] = br;
+          }
+      } else {
+        for (int64_t e = 0; e < m * m; ++e) op.Bshift[e] = P.tau * A[i][mu][e];
+      }
       double tr = 0.0;
-      for (int64_t k = 0; k < m; ++k) tr += A[i][mu][k * m + k];
-      op.sigma = P.tau * tr / m;
-      for (int64_t e = 0; e < m * m; ++e) op.Bshift[e] = P.tau * A[i][mu][e];
+      for (int64_t k = 0; k < m; ++k) tr += op.Bshift[k * m + k];
+      op.sigma = tr / m;
       for (int64_t k = 0; k < m; ++k) op.Bshift[k * m + k] -= op.sigma;
       double nrm = 0.0;
       for (int64_t c = 0; c < m; ++c) {
@@ -488,6 +596,7 @@ int build_plan_matrices(const std::vector<phiks_plan_s*>& plans,
       } else {
         reqs.push_back({o, inv2s, P.E[mu] + (size_t)P.s * sq(m)});
       }
+      (void)nc;
     }
   }
   RET_IF(batched_expm(ops, reqs, host_keep, st));
@@ -497,30 +606,65 @@ int build_plan_matrices(const std::vector<phiks_plan_s*>& plans,
   for (phiks_plan_s* P : plans) {
     smax = std::max(smax, P->s);
     if (plan_nodes(*P) == 0) continue;
-    for (int mu = 0; mu < P->d; ++mu)
-      copies.push_back({P->Lnode[mu], P->E[mu] + (size_t)P->s * sq(P->n[mu]), 1.0, (int)P->n[mu]});
+    for (int mu = 0; mu < P->d; ++mu) {
+      const int64_t m = P->cplx ? 2 * P->n[mu] : P->n[mu];
+      copies.push_back({P->Lnode[mu], P->E[mu] + (size_t)P->s * sq(m), 1.0, (int)m});
+    }
   }
   RET_IF(launch_scale_jobs(copies, host_keep, st));
   // exp(B/2^(j-1)) = exp(B/2^j)^2, j = s..1, grouped by size
   for (int j = smax; j >= 1; --j) {
+    auto opn = [](const phiks_plan_s* P, int mu) { return P->cplx ? 2 * P->n[mu] : P->n[mu]; };
     std::vector<int64_t> sizes;
     for (phiks_plan_s* P : plans)
       if (P->s >= j)
         for (int mu = 0; mu < P->d; ++mu)
-          if (std::find(sizes.begin(), sizes.end(), P->n[mu]) == sizes.end()) sizes.push_back(P->n[mu]);
+          if (std::find(sizes.begin(), sizes.end(), opn(P, mu)) == sizes.end()) sizes.push_back(opn(P, mu));
     for (int64_t nsz : sizes) {
       std::vector<const double*> a;
       std::vector<double*> c;
       for (phiks_plan_s* P : plans) {
         if (P->s < j) continue;
         for (int mu = 0; mu < P->d; ++mu) {
-          if (P->n[mu] != nsz) continue;
+          if (opn(P, mu) != nsz) continue;
           a.push_back(P->E[mu] + (size_t)j * sq(nsz));
           c.push_back(P->E[mu] + (size_t)(j - 1) * sq(nsz));
         }
       }
       RET_IF(ptr_gemm(a, a, c, (int)nsz, 0.0, host_keep, st));
     }
+  }
+  // complex plans: the [Re | Im] forms used by the modes > 1
+  std::vector<ScaleJob> splits;
+  for (phiks_plan_s* P : plans) {
+    if (!P->cplx) continue;
+    const int nodes = plan_nodes(*P);
+    for (int mu = 0; mu < P->d; ++mu) {
+      const int64_t nn = sq(P->n[mu]);
+      for (int k = 0; k < nodes; ++k)
+        splits.push_back({P->Lnode[mu] + (size_t)k * 4 * nn, P->Lsplit[mu] + (size_t)k * 2 * nn, 1.0,
+                          (int)P->n[mu]});
+      for (int k = 0; k <= P->s; ++k)
+        splits.push_back({P->E[mu] + (size_t)k * 4 * nn, P->Esplit[mu] + (size_t)k * 2 * nn, 1.0,
+                          (int)P->n[mu]});
+    }
+  }
+  if (!splits.empty()) {
+    host_keep.emplace_back(splits.size() * sizeof(ScaleJob));
+    std::memcpy(host_keep.back().data(), splits.data(), host_keep.back().size());
+    ScaleJob* dsj = nullptr;
+    HIP_OK(hipMallocAsync((void**)&dsj, splits.size() * sizeof(ScaleJob), st));
+    HIP_OK(hipMemcpyAsync(dsj, host_keep.back().data(), splits.size() * sizeof(ScaleJob),
+                          hipMemcpyHostToDevice, st));
+    int64_t nmax = 0;
+    for (const ScaleJob& j : splits) nmax = std::max<int64_t>(nmax, j.n);
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(complex_split_kernel,
+                       dim3((unsigned)std::min<int64_t>((2 * sq(nmax) + 255) / 256, 1024),
+                            (unsigned)splits.size()),
+                       dim3(256), 0, st, dsj);
+    CHECK_LAUNCH();
+    HIP_OK(hipFreeAsync(dsj, st));
   }
   // FP32 copies of every node matrix and of exp(B/2^j): the mixed-precision paths
   // multiply by these; everything else stays FP64
@@ -601,6 +745,8 @@ int phiks_plan_params(int d, const int64_t* n, const double* const* A, double ta
   return PHIKS_OK;
 }
 
+int finish_plan(phiks_plan_s* P, const double* const* A, void* hip_stream, phiks_plan_t* out);
+
 int phiks_plan(int d, const int64_t* n, const double* const* A, double tau, int p,
                int n_scales, double tol, int task, const double* vnorms, int precision,
                void* hip_stream, phiks_plan_t* out) {
@@ -613,6 +759,39 @@ int phiks_plan(int d, const int64_t* n, const double* const* A, double tau, int 
     delete P;
     return rc;
   }
+  return finish_plan(P, A, hip_stream, out);
+}
+
+int phiks_plan_complex(int d, const int64_t* n, const double* const* A, double tau_re,
+                       double tau_im, int p, int n_scales, double tol, int task,
+                       const double* vnorms, void* hip_stream, phiks_plan_t* out) {
+  if (!out) return PHIKS_EINVAL;
+  *out = nullptr;
+  phiks_plan_s* P = new (std::nothrow) phiks_plan_s;
+  if (!P) return PHIKS_ENOMEM;
+  int rc = plan_init_host_complex(*P, d, n, A, tau_re, tau_im, p, n_scales, tol, task, vnorms);
+  if (rc != PHIKS_OK) {
+    delete P;
+    return rc;
+  }
+  return finish_plan(P, A, hip_stream, out);
+}
+
+int phiks_plan_params_complex(int d, const int64_t* n, const double* const* A, double tau_re,
+                              double tau_im, int p, int n_scales, double tol, int task,
+                              const double* vnorms, int* s, int* q, int* tucker_paper) {
+  phiks_plan_s P;
+  int rc = plan_init_host_complex(P, d, n, A, tau_re, tau_im, p, n_scales, tol, task, vnorms);
+  if (rc != PHIKS_OK) return rc;
+  if (s) *s = P.s;
+  if (q) *q = P.q;
+  if (tucker_paper) *tucker_paper = P.t_paper;
+  return PHIKS_OK;
+}
+
+// Device part of phiks_plan / phiks_plan_complex: allocation and the small exponentials.
+int finish_plan(phiks_plan_s* P, const double* const* A, void* hip_stream, phiks_plan_t* out) {
+  int rc = PHIKS_OK;
   hipStream_t st = (hipStream_t)hip_stream;
   auto fail = [&](int code) {
     phiks_plan_destroy(P);
@@ -791,7 +970,7 @@ int phiks_apply(phiks_plan_t plan, const double* v, double* out, void* ws, size_
   const size_t need = workspace_doubles(P) * sizeof(double);
   if (!ws || ws_bytes < need) return PHIKS_EWORKSPACE;
   hipStream_t st = (hipStream_t)hip_stream;
-  const int64_t N = P.N;
+  const int64_t N = plan_vec_doubles(P);  // doubles per vector
   const int p = P.p, ns = P.ns, s = P.s, q = P.q, d = P.d;
   const int64_t tcount = std::max<int64_t>({(int64_t)q - 1, (int64_t)p, 1});
   double* ta = (double*)ws;
@@ -852,7 +1031,7 @@ int phiks_combine(phiks_plan_t plan, const double* const* v, double* out, void* 
   const size_t need = workspace_doubles(P) * sizeof(double);
   if (!ws || ws_bytes < need) return PHIKS_EWORKSPACE;
   hipStream_t st = (hipStream_t)hip_stream;
-  const int64_t N = P.N;
+  const int64_t N = plan_vec_doubles(P);  // doubles per vector
   const int p = P.p, ns = P.ns, s = P.s, q = P.q, d = P.d;
   const int64_t pp = std::max(p, 1);
   double* U = (double*)ws;

@@ -13,7 +13,7 @@ struct phiks_plan_s {
   int d = 0;
   int64_t n[PHIKS_MAX_D] = {0};
   int64_t N = 0;
-  double tau = 0.0;
+  double tau = 0.0, tau_im = 0.0;    // the step (imaginary part: complex plans)
   int p = 0, ns = 1, task = 0, precision = 0;
   int s = 0, q = 0, t_paper = 0, t_exec = 0;
   double theta[phiks::kQMax] = {0}, w[phiks::kQMax] = {0};
@@ -24,5 +24,15 @@ struct phiks_plan_s {
   double* E[PHIKS_MAX_D] = {nullptr};      // (s+1) matrices per mode: exp(B/2^j), stride n^2
   float* Lnode32[PHIKS_MAX_D] = {nullptr};  // FP32 copies (precision PHIKS_FP32)
   float* E32[PHIKS_MAX_D] = {nullptr};
+  // Complex plans (A_mu or tau complex; vectors of N complex values, re/im interleaved):
+  // Lnode / E hold the real forms of the complex matrices (2n x 2n, the 2 x 2 block
+  // [[Re, -Im], [Im, Re]] at block (i, j)), stride 4n^2, and Lsplit / Esplit the
+  // n x 2n matrices [Re | Im] of the same exponentials, stride 2n^2.
+  int cplx = 0;
+  double* Lsplit[PHIKS_MAX_D] = {nullptr};
+  double* Esplit[PHIKS_MAX_D] = {nullptr};
   std::vector<std::vector<char>> host_keep;  // host sources of async copies
 };
+
+// Doubles per vector of the plan's problem (N, or 2N for complex vectors).
+inline int64_t plan_vec_doubles(const phiks_plan_s& P) { return P.cplx ? 2 * P.N : P.N; }

@@ -225,6 +225,63 @@ Rect bendixson_rectangle(int64_t n, const double* B) {
   return r;
 }
 
+// Bendixson rectangle of a complex matrix (interleaved re/im, row-major): the real
+// parts of the numerical range lie between the extreme eigenvalues of H = (B + B^*)/2,
+// the imaginary parts between those of G = (B - B^*)/(2i); both are Hermitian.  A
+// Hermitian tridiagonal matrix is unitarily similar (diagonal phase scaling) to the
+// real symmetric tridiagonal with the moduli of its off-diagonals; a dense Hermitian
+// matrix X has the real symmetric form [[Re X, -Im X], [Im X, Re X]], whose
+// eigenvalues are those of X, each twice.
+Rect bendixson_rectangle_complex(int64_t n, const double* B) {
+  auto re = [&](int64_t i, int64_t j) { return B[2 * (i * n + j)]; };
+  auto im = [&](int64_t i, int64_t j) { return B[2 * (i * n + j) + 1]; };
+  Rect r{};
+  bool tri = true;
+  for (int64_t i = 0; i < n && tri; ++i)
+    for (int64_t j = 0; j < n; ++j)
+      if ((j > i + 1 || i > j + 1) && (re(i, j) != 0.0 || im(i, j) != 0.0)) { tri = false; break; }
+  std::vector<double> a, b;
+  if (tri) {
+    a.resize(n);
+    b.resize(n > 0 ? n - 1 : 0);
+    // H: diagonal Re B_kk, off-diagonal (B_{k+1,k} + conj B_{k,k+1}) / 2
+    for (int64_t k = 0; k < n; ++k) a[k] = re(k, k);
+    for (int64_t k = 0; k + 1 < n; ++k)
+      b[k] = std::hypot(0.5 * (re(k + 1, k) + re(k, k + 1)), 0.5 * (im(k + 1, k) - im(k, k + 1)));
+    tridiag_extremes(a, b, r.re_lo, r.re_hi);
+    // G: diagonal Im B_kk, off-diagonal (B_{k+1,k} - conj B_{k,k+1}) / (2i)
+    for (int64_t k = 0; k < n; ++k) a[k] = im(k, k);
+    for (int64_t k = 0; k + 1 < n; ++k)
+      b[k] = std::hypot(0.5 * (re(k + 1, k) - re(k, k + 1)), 0.5 * (im(k + 1, k) + im(k, k + 1)));
+    tridiag_extremes(a, b, r.im_lo, r.im_hi);
+  } else {
+    const int64_t m = 2 * n;
+    for (int part = 0; part < 2; ++part) {
+      // X = H (part 0) or G (part 1) as a complex Hermitian matrix, then its real form
+      std::vector<double> R(m * m);
+      for (int64_t i = 0; i < n; ++i)
+        for (int64_t j = 0; j < n; ++j) {
+          double xr, xi;
+          if (part == 0) {  // (B_ij + conj B_ji) / 2
+            xr = 0.5 * (re(i, j) + re(j, i));
+            xi = 0.5 * (im(i, j) - im(j, i));
+          } else {          // (B_ij - conj B_ji) / (2i)
+            xr = 0.5 * (im(i, j) + im(j, i));
+            xi = -0.5 * (re(i, j) - re(j, i));
+          }
+          R[i * m + j] = xr;
+          R[(i + n) * m + (j + n)] = xr;
+          R[i * m + (j + n)] = -xi;
+          R[(i + n) * m + j] = xi;
+        }
+      householder_tridiag(R, m, false, a, b);
+      if (part == 0) tridiag_extremes(a, b, r.re_lo, r.re_hi);
+      else tridiag_extremes(a, b, r.im_lo, r.im_hi);
+    }
+  }
+  return r;
+}
+
 // ------------------------------------------------------ kernel k_q and contour
 namespace {
 

@@ -22,6 +22,8 @@ void gll_rule(int q, double* theta, double* w);
 
 // Bendixson rectangle of a real n x n row-major matrix.
 Rect bendixson_rectangle(int64_t n, const double* B);
+// Bendixson rectangle of a complex n x n row-major matrix (re/im interleaved).
+Rect bendixson_rectangle_complex(int64_t n, const double* B);
 
 // |R_q(f_l(., w))|, l = 1..p, by the contour integral of Section 3.3.
 // Returns false (and +inf entries) when the integrand overflows.

@@ -51,7 +51,7 @@ bool vec_ok(const GemmArgs& g, bool kcontig, const std::vector<const void*>& ext
   return true;
 }
 
-template <int BM, int BN, int WM, int WN, bool KC, bool VEC, class Epi>
+template <int BM, int BN, int WM, int WN, bool KC, bool VEC, bool CPLX = false, class Epi>
 int launch_cfg(GemmArgs g, const Epi& epi, hipStream_t st) {
   g.tiles_m = (g.M + BM - 1) / BM;
   g.tiles_n = (g.N + BN - 1) / BN;
@@ -71,7 +71,7 @@ int launch_cfg(GemmArgs g, const Epi& epi, hipStream_t st) {
     }
   }
   (void)hipGetLastError();  // clear a stale error left by an unrelated earlier call
-  hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, WM, WN, KC, VEC, Epi>),
+  hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, WM, WN, KC, VEC, Epi, CPLX>),
                      dim3((unsigned)g.total_tiles), dim3(256), 0, st, g, epi);
   CHECK_LAUNCH();
   if (ea && eb) {
@@ -82,16 +82,16 @@ int launch_cfg(GemmArgs g, const Epi& epi, hipStream_t st) {
   return PHIKS_OK;
 }
 
-template <bool KC, bool VEC, class Epi>
+template <bool KC, bool VEC, bool CPLX = false, class Epi>
 int launch_tile(const GemmArgs& g, const Epi& epi, hipStream_t st) {
   switch (pick_tile(g)) {
 #if PHIKS_BIG_TILE == 1
-    case Tile::T128x128: return launch_cfg<128, 128, 64, 64, KC, VEC>(g, epi, st);
+    case Tile::T128x128: return launch_cfg<128, 128, 64, 64, KC, VEC, CPLX>(g, epi, st);
 #endif
-    case Tile::T128x64: return launch_cfg<128, 64, 64, 32, KC, VEC>(g, epi, st);
-    case Tile::T64x128: return launch_cfg<64, 128, 32, 64, KC, VEC>(g, epi, st);
-    case Tile::T64x64: return launch_cfg<64, 64, 32, 32, KC, VEC>(g, epi, st);
-    default: return launch_cfg<32, 32, 16, 16, KC, VEC>(g, epi, st);
+    case Tile::T128x64: return launch_cfg<128, 64, 64, 32, KC, VEC, CPLX>(g, epi, st);
+    case Tile::T64x128: return launch_cfg<64, 128, 32, 64, KC, VEC, CPLX>(g, epi, st);
+    case Tile::T64x64: return launch_cfg<64, 64, 32, 32, KC, VEC, CPLX>(g, epi, st);
+    default: return launch_cfg<32, 32, 16, 16, KC, VEC, CPLX>(g, epi, st);
   }
 }
 
@@ -104,6 +104,17 @@ int launch_gemm(const GemmArgs& g, const Epi& epi, hipStream_t st,
   }
   if (vec_ok(g, KC, extra_ptrs)) return launch_tile<KC, true>(g, epi, st);
   return launch_tile<KC, false>(g, epi, st);
+}
+
+// Complex mu-mode product of a mode > 1 (see CPLX in gemm_f64.hpp): A = [Re L | Im L]
+// (M x K, K = 2n), B the interleaved tensor slab (n rows of N doubles); 16-byte loads.
+template <class Epi>
+int launch_gemm_cplx(const GemmArgs& g, const Epi& epi, hipStream_t st) {
+  if (!vec_ok(g, false, {}) || g.K % 2) {
+    set_error("complex mu-mode product needs even sizes and 16-byte aligned operands");
+    return PHIKS_EINVAL;
+  }
+  return launch_tile<false, true, true>(g, epi, st);
 }
 
 // ---------------------------------------------------------- Tucker operator
@@ -182,6 +193,85 @@ int tucker(const phiks_plan_s& P, const double* in, int64_t in_stride,
     } else {
       if (last) RET_IF((launch_gemm<false>(gs[mu - 1], epi, st)));
       else RET_IF((launch_gemm<false>(gs[mu - 1], EpiStore{1.0, 0.0}, st)));
+    }
+  }
+  return PHIKS_OK;
+}
+
+// Complex Tucker operator on re/im interleaved tensors of N complex values (in_b = in
+// + b*in_stride doubles, out batch b at out + 2bN).  Lr[mu]: real forms (2n x 2n,
+// batch stride lr_stride[mu]) for mode 1; Ls[mu]: [Re | Im] forms (n x 2n, batch
+// stride ls_stride[mu]) for the modes > 1.  Mode 1 is a real GEMM of the interleaved
+// rows with the real form; the modes > 1 are the CPLX GEMMs.  ta/tb as tucker_args.
+void tucker_args_complex(int d, const int64_t* n, int64_t N, const double* in,
+                         int64_t in_stride, double* const* Lr, const int64_t* lr_stride,
+                         double* const* Ls, const int64_t* ls_stride, int nbatch, double* out,
+                         double* ta, double* tb, GemmArgs* gs) {
+  const double* cur = in;
+  int64_t cur_stride = in_stride;
+  for (int mu = 1; mu <= d; ++mu) {
+    const int64_t nm = n[mu - 1];
+    int64_t nlo = 1, nhi = 1;
+    for (int k = 0; k < mu - 1; ++k) nlo *= n[k];
+    for (int k = mu; k < d; ++k) nhi *= n[k];
+    double* dst = (mu == d) ? out : ((mu % 2 == 1) ? ta : tb);
+    GemmArgs& g = gs[mu - 1];
+    g = empty_args();
+    g.nb1 = nbatch;
+    if (mu == 1) {
+      // W[m][(i,c)] = sum_(j,c') X[m][(j,c')] R[(i,c)][(j,c')]
+      g.M = (int)nhi;
+      g.N = (int)(2 * nm);
+      g.K = (int)(2 * nm);
+      g.A = cur;
+      g.lda = 2 * nm;
+      g.B = Lr[0];
+      g.ldb = 2 * nm;
+      g.C = dst;
+      g.ldc = 2 * nm;
+      g.sA1 = cur_stride;
+      g.sB1 = lr_stride[0];
+      g.sC1 = 2 * N;
+    } else {
+      // W_b = [Re L | Im L] [X_b ; X_b twisted], rows of 2 n_< doubles
+      g.M = (int)nm;
+      g.N = (int)(2 * nlo);
+      g.K = (int)(2 * nm);
+      g.A = Ls[mu - 1];
+      g.lda = 2 * nm;
+      g.B = cur;
+      g.ldb = 2 * nlo;
+      g.C = dst;
+      g.ldc = 2 * nlo;
+      g.nb0 = (int)nhi;
+      g.sA0 = 0;
+      g.sB0 = 2 * nm * nlo;
+      g.sC0 = 2 * nm * nlo;
+      g.sA1 = ls_stride[mu - 1];
+      g.sB1 = cur_stride;
+      g.sC1 = 2 * N;
+    }
+    cur = dst;
+    cur_stride = 2 * N;
+  }
+}
+
+template <class Epi>
+int tucker_complex(const phiks_plan_s& P, const double* in, int64_t in_stride,
+                   double* const* Lr, const int64_t* lr_stride, double* const* Ls,
+                   const int64_t* ls_stride, int nbatch, double* out, double* ta, double* tb,
+                   const Epi& epi, hipStream_t st) {
+  GemmArgs gs[PHIKS_MAX_D];
+  tucker_args_complex(P.d, P.n, P.N, in, in_stride, Lr, lr_stride, Ls, ls_stride, nbatch, out,
+                      ta, tb, gs);
+  for (int mu = 1; mu <= P.d; ++mu) {
+    const bool last = (mu == P.d);
+    if (mu == 1) {
+      if (last) RET_IF((launch_gemm<true>(gs[0], epi, st)));
+      else RET_IF((launch_gemm<true>(gs[0], EpiStore{1.0, 0.0}, st)));
+    } else {
+      if (last) RET_IF((launch_gemm_cplx(gs[mu - 1], epi, st)));
+      else RET_IF((launch_gemm_cplx(gs[mu - 1], EpiStore{1.0, 0.0}, st)));
     }
   }
   return PHIKS_OK;

@@ -182,3 +182,35 @@ def test_batched_workload_shapes():
     assert all(m in workloads.BATCH_SIZES for b in problems for m in b.n)
     assert all(1e-4 <= b.tau <= 1e-2 for b in problems)
     assert all(b.A[0].shape == (b.n[0], b.n[0]) and b.v.shape == (b.N,) for b in problems)
+
+
+def test_complex_planner_reproduces_table1():
+    """The library's complex planner (Bendixson rectangle of complex operators) on the
+    validation operators of Section 4.1: every (s, q, T#) of Table 1, both tasks."""
+    import json
+    import os
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "table1.json")))
+    for task in ("same_vector", "lincomb"):
+        for d, cols in gold[task].items():
+            for n, ref in cols.items():
+                A, v = workloads.validation_table1(int(d), int(n))
+                nv = float(np.linalg.norm(v))
+                vn = [nv] if task == "same_vector" else [nv] * 6
+                got = ph.phiks_plan_params_complex(A, 1.0, 5, 2, 2.0 ** -53, task, vn)
+                if task == "same_vector":
+                    assert got == tuple(ref), (task, d, n, got)
+                else:
+                    assert got[2] == ref[2], (task, d, n, got)
+
+
+def test_complex_planner_matches_oracle_on_dense_operators():
+    """Dense complex operators and a complex step: library planner == oracle planner."""
+    rng = np.random.default_rng(3)
+    for trial in range(4):
+        n = [int(x) for x in rng.integers(3, 12, size=int(rng.integers(1, 4)))]
+        A = [(rng.standard_normal((k, k)) + 1j * rng.standard_normal((k, k))) for k in n]
+        tau = complex(rng.uniform(0.05, 0.5), rng.uniform(-0.3, 0.3))
+        got = ph.phiks_plan_params_complex(A, tau, 3, 1, 2.0 ** -53, "same_vector")
+        xi = bound.kron_sum_rectangle([tau * a for a in A])
+        ref = bound.plan(xi, 3, 1, 2.0 ** -53, "same_vector")
+        assert got == tuple(ref), (trial, n, tau, got, ref)

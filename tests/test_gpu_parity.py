@@ -83,10 +83,15 @@ SV_CASES = [
     ("adr", [40, 30, 20], 1e-3, 4, 2),
     ("fd2", [65, 70], 2e-3, 4, 1),
     ("cheb", [24, 20], 1e-3, 3, 1),
+    # d = 6 as in the validation of Section 4.1 (real part of its operators)
+    ("val", [8, 8, 8, 8, 8, 8], 1.0, 4, 1),
+    ("val", [11, 10, 9, 8, 9, 10], 1.0, 3, 2),
 ]
 
 
 def ops(kind, n):
+    if kind == "val":
+        return [workloads.fd2_dirichlet(k) / 100.0 for k in n]
     if kind == "fd2":
         return [workloads.fd2_dirichlet(k) for k in n]
     if kind == "cheb":
@@ -144,6 +149,18 @@ def test_combine_vs_oracle(n, tau, p, ns):
     got, info = run_combine(A, tau, vs, p, ns)
     ref = ophiks.phi_lincomb(A, tau, vs, p, ns, info["s"], info["q"])
     for j in range(ns):
+        assert relerr(got[j], ref[j]) < TOL, (j, info)
+
+
+def test_combine_six_modes():
+    """Linear combination with d = 6 (the validation dimension of Section 4.1)."""
+    n = [9, 8, 10, 8, 9, 8]
+    A = ops("val", n)
+    vs = [workloads.randn_vec(n, 60 + k) for k in range(4)]
+    print(f"[combine] val n={n}", flush=True)
+    got, info = run_combine(A, 1.0, vs, 3, 2)
+    ref = ophiks.phi_lincomb(A, 1.0, vs, 3, 2, info["s"], info["q"])
+    for j in range(2):
         assert relerr(got[j], ref[j]) < TOL, (j, info)
 
 
