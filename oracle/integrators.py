@@ -58,3 +58,87 @@ def adr_nonlinearity(prob):
         et = math.exp(t)
         return 1.0 / (1.0 + u * u) + et * prob.w - 1.0 / (1.0 + (et * prob.u0) ** 2)
     return g
+
+
+def exprk3s3(A, u0: np.ndarray, g: Callable[[float, np.ndarray], np.ndarray], T: float,
+             steps: int, tol: float = 2.0 ** -53) -> np.ndarray:
+    """Third-order exponential Runge-Kutta scheme with the reduced tableau of eq.
+    expRK3s3: c_3 = 2 c_2 = 1/2, gamma = (3c_3 - 2) c_3 / ((2 - 3c_2) c_2) = -4/5.
+      U_2     = e^(c_2 tau K) u_n + c_2 tau phi_1(c_2 tau K) g_n
+      U_3     = e^(c_3 tau K) u_n + c_3 tau phi_1(c_3 tau K) g_n
+                + tau (gamma c_2 phi_2(c_2 tau K) + c_3^2/c_2 phi_2(c_3 tau K)) D_2
+      u_{n+1} = e^(tau K) u_n + tau phi_1(tau K) g_n
+                + tau phi_2(tau K) (gamma D_2 + D_3) / (gamma c_2 + c_3),
+    D_j = g(t_n + c_j tau, U_j) - g_n.  A call of phi_lincomb with step h returns
+    e^(hK) v_0 + sum_l phi_l(hK) v_l, so every argument v_l carries its own h^l."""
+    c2, c3 = 0.25, 0.5
+    gam = (3 * c3 - 2) * c3 / ((2 - 3 * c2) * c2)
+    tau = T / steps
+    plans = {}
+
+    def lc(h, vs, p):
+        if (h, p) not in plans:
+            plans[(h, p)] = _plan(A, h, p, tol)
+        s, q = plans[(h, p)]
+        return phi_lincomb(A, h, vs, p, 1, s, q)[0]
+
+    u = np.asarray(u0, dtype=np.float64).copy()
+    for n in range(steps):
+        t = n * tau
+        gn = g(t, u)
+        U2 = lc(c2 * tau, [u, c2 * tau * gn], 1)
+        D2 = g(t + c2 * tau, U2) - gn
+        # phi_2 at two times: the c_3 part joins stage 3's combination, the c_2 part
+        # is a second combination without exponential term
+        U3 = lc(c3 * tau, [u, c3 * tau * gn, tau * (c3 ** 2 / c2) * D2], 2)
+        U3 = U3 + lc(c2 * tau, [None, None, tau * gam * c2 * D2], 2)
+        D3 = g(t + c3 * tau, U3) - gn
+        u = lc(tau, [u, tau * gn, tau * (gam * D2 + D3) / (gam * c2 + c3)], 2)
+    return u
+
+
+def exprk4s6(A, u0: np.ndarray, g: Callable[[float, np.ndarray], np.ndarray], T: float,
+             steps: int, tol: float = 2.0 ** -53) -> np.ndarray:
+    """Fourth-order six-stage exponential Runge-Kutta scheme with the reduced tableau of
+    eq. expRK4s6, c = (c_2, c_3, c_4, c_5, c_6) = (1/3, 1/3, 2/3, 1/2, 1): stages 3
+    and 4 come from one two-scale linear combination with step c_4 tau (c_3 = c_4/2 is
+    its half-step output, eq. scallincomb), stages 5 and 6 from one with step tau.
+      U_i     = e^(c_i tau K) u_n + c_i tau phi_1(c_i tau K) g_n + tau sum_j a_ij D_j
+      u_{n+1} = e^(tau K) u_n + tau phi_1(tau K) g_n + tau (b_5 D_5 + b_6 D_6),
+    with a_32 = c_3^2/c_2 phi_{2,3}, a_42 = c_4^2/c_2 phi_{2,4} and a_{5,3}, a_{5,4},
+    a_{6,3}, a_{6,4}, b_5, b_6 as in the tableau."""
+    c2, c3, c4, c5, c6 = 1 / 3, 1 / 3, 2 / 3, 0.5, 1.0
+    tau = T / steps
+    plans = {}
+
+    def lc(h, vs, p, ns):
+        if (h, p, ns) not in plans:
+            xi = bound.kron_sum_rectangle([h * np.asarray(a) for a in A])
+            s, q, _ = bound.plan(xi, p, ns, tol, "lincomb")
+            plans[(h, p, ns)] = (s, q)
+        s, q = plans[(h, p, ns)]
+        return phi_lincomb(A, h, vs, p, ns, s, q)
+
+    u = np.asarray(u0, dtype=np.float64).copy()
+    for n in range(steps):
+        t = n * tau
+        gn = g(t, u)
+        U2 = lc(c2 * tau, [u, c2 * tau * gn], 1, 1)[0]
+        D2 = g(t + c2 * tau, U2) - gn
+        # step h = c_4 tau: output 0 is stage 4, output 1 (h/2 = c_3 tau) stage 3
+        h = c4 * tau
+        o = lc(h, [u, h * gn, tau * (c4 ** 2 / c2) * D2], 2, 2)
+        U4, U3 = o[0], o[1]
+        D3 = g(t + c3 * tau, U3) - gn
+        D4 = g(t + c4 * tau, U4) - gn
+        # step h = c_6 tau = tau: output 0 is stage 6, output 1 (c_5 = 1/2) stage 5
+        v2 = tau * (c4 * c6 ** 2 / (c3 * (c4 - c3)) * D3 + c3 * c6 ** 2 / (c4 * (c3 - c4)) * D4)
+        v3 = tau * (2 * c6 ** 3 / (c3 * (c3 - c4)) * D3 + 2 * c6 ** 3 / (c4 * (c4 - c3)) * D4)
+        o = lc(tau, [u, tau * gn, v2, v3], 3, 2)
+        U6, U5 = o[0], o[1]
+        D5 = g(t + c5 * tau, U5) - gn
+        D6 = g(t + c6 * tau, U6) - gn
+        w2 = tau * (c6 / (c5 * (c6 - c5)) * D5 + c5 / (c6 * (c5 - c6)) * D6)
+        w3 = tau * (2 / (c5 * (c5 - c6)) * D5 + 2 / (c6 * (c6 - c5)) * D6)
+        u = lc(tau, [u, tau * gn, w2, w3], 3, 1)[0]
+    return u

@@ -95,3 +95,110 @@ def etd2rk(A: Sequence[np.ndarray], u0, g: Callable[[float, int, int], None], T:
     p1.close()
     p2.close()
     return u
+
+
+def _pair(buf: DeviceArray, N: int):
+    """Pointers to the two outputs of a two-scale combination (scale 1, scale 1/2)."""
+    return buf.ptr, buf.ptr + 8 * N
+
+
+def exprk3s3(A: Sequence[np.ndarray], u0, g: Callable[[float, int, int], None], T: float,
+             steps: int, tol: float = 2.0 ** -53, stream: int = 0) -> DeviceArray:
+    """Third-order scheme of eq. expRK3s3 (c_3 = 2 c_2 = 1/2, gamma = -4/5):
+      U_2     = e^(c_2 tau K) u_n + c_2 tau phi_1(c_2 tau K) g_n
+      U_3     = e^(c_3 tau K) u_n + c_3 tau phi_1(c_3 tau K) g_n
+                + tau (gamma c_2 phi_2(c_2 tau K) + c_3^2/c_2 phi_2(c_3 tau K)) D_2
+      u_{n+1} = e^(tau K) u_n + tau phi_1(tau K) g_n + tau phi_2(tau K) (gamma D_2 + D_3) / (gamma c_2 + c_3)
+    with D_j = g(t_n + c_j tau, U_j) - g_n."""
+    c2, c3 = 0.25, 0.5
+    gam = (3 * c3 - 2) * c3 / ((2 - 3 * c2) * c2)
+    tau = T / steps
+    N = int(np.prod([a.shape[0] for a in A]))
+    P2 = phiks_plan(A, c2 * tau, 1, 1, tol, "lincomb", stream=stream)
+    P3 = phiks_plan(A, c3 * tau, 2, 1, tol, "lincomb", stream=stream)
+    P3b = phiks_plan(A, c2 * tau, 2, 1, tol, "lincomb", stream=stream)
+    Pf = phiks_plan(A, tau, 2, 1, tol, "lincomb", stream=stream)
+    plans = (P2, P3, P3b, Pf)
+    ws = DeviceArray(max(p.workspace_size() for p in plans) // 8 + 1)
+    u, un = _start(u0, N), DeviceArray(N)
+    gn, U2, U3, D2, D3, v1, v2, tmp = (DeviceArray(N) for _ in range(8))
+    AX = PHIKS_VOP_AXPBY
+    for n in range(steps):
+        t = n * tau
+        g(t, u.ptr, gn.ptr)
+        vector_op(AX, N, c2 * tau, gn.ptr, 0.0, None, v1.ptr, stream)
+        phiks_combine(P2, [u.ptr, v1.ptr], U2.ptr, ws.ptr, ws.nbytes, stream)
+        g(t + c2 * tau, U2.ptr, D2.ptr)
+        vector_op(AX, N, 1.0, D2.ptr, -1.0, gn.ptr, D2.ptr, stream)
+        vector_op(AX, N, c3 * tau, gn.ptr, 0.0, None, v1.ptr, stream)
+        vector_op(AX, N, tau * c3 * c3 / c2, D2.ptr, 0.0, None, v2.ptr, stream)
+        phiks_combine(P3, [u.ptr, v1.ptr, v2.ptr], U3.ptr, ws.ptr, ws.nbytes, stream)
+        vector_op(AX, N, tau * gam * c2, D2.ptr, 0.0, None, v2.ptr, stream)
+        phiks_combine(P3b, [None, None, v2.ptr], tmp.ptr, ws.ptr, ws.nbytes, stream)
+        vector_op(AX, N, 1.0, U3.ptr, 1.0, tmp.ptr, U3.ptr, stream)
+        g(t + c3 * tau, U3.ptr, D3.ptr)
+        vector_op(AX, N, 1.0, D3.ptr, -1.0, gn.ptr, D3.ptr, stream)
+        vector_op(AX, N, tau, gn.ptr, 0.0, None, v1.ptr, stream)
+        den = gam * c2 + c3
+        vector_op(AX, N, tau * gam / den, D2.ptr, tau / den, D3.ptr, v2.ptr, stream)
+        phiks_combine(Pf, [u.ptr, v1.ptr, v2.ptr], un.ptr, ws.ptr, ws.nbytes, stream)
+        u, un = un, u
+    for p in plans:
+        p.close()
+    return u
+
+
+def exprk4s6(A: Sequence[np.ndarray], u0, g: Callable[[float, int, int], None], T: float,
+             steps: int, tol: float = 2.0 ** -53, stream: int = 0) -> DeviceArray:
+    """Fourth-order six-stage scheme of eq. expRK4s6 with c = (1/3, 1/3, 2/3, 1/2, 1):
+    four combinations per step -- stage 2; stages 4 and 3 as the two scales of one
+    combination with step c_4 tau (c_3 = c_4/2); stages 6 and 5 likewise with step tau;
+    the update (coefficients as in the tableau)."""
+    c2, c3, c4, c5, c6 = 1 / 3, 1 / 3, 2 / 3, 0.5, 1.0
+    tau = T / steps
+    N = int(np.prod([a.shape[0] for a in A]))
+    P2 = phiks_plan(A, c2 * tau, 1, 1, tol, "lincomb", stream=stream)
+    P34 = phiks_plan(A, c4 * tau, 2, 2, tol, "lincomb", stream=stream)
+    P56 = phiks_plan(A, tau, 3, 2, tol, "lincomb", stream=stream)
+    Pf = phiks_plan(A, tau, 3, 1, tol, "lincomb", stream=stream)
+    plans = (P2, P34, P56, Pf)
+    ws = DeviceArray(max(p.workspace_size() for p in plans) // 8 + 1)
+    u, un = _start(u0, N), DeviceArray(N)
+    gn, U2, D2, D3, D4, D5, D6, v1, v2, v3 = (DeviceArray(N) for _ in range(10))
+    O34, O56 = DeviceArray(2 * N), DeviceArray(2 * N)
+    AX = PHIKS_VOP_AXPBY
+    a53 = (c4 * c6 ** 2 / (c3 * (c4 - c3)), c3 * c6 ** 2 / (c4 * (c3 - c4)))
+    a63 = (2 * c6 ** 3 / (c3 * (c3 - c4)), 2 * c6 ** 3 / (c4 * (c4 - c3)))
+    b2 = (c6 / (c5 * (c6 - c5)), c5 / (c6 * (c5 - c6)))
+    b3 = (2 / (c5 * (c5 - c6)), 2 / (c6 * (c6 - c5)))
+
+    def diff(tt, U_ptr, D):
+        g(tt, U_ptr, D.ptr)
+        vector_op(AX, N, 1.0, D.ptr, -1.0, gn.ptr, D.ptr, stream)
+
+    for n in range(steps):
+        t = n * tau
+        g(t, u.ptr, gn.ptr)
+        vector_op(AX, N, c2 * tau, gn.ptr, 0.0, None, v1.ptr, stream)
+        phiks_combine(P2, [u.ptr, v1.ptr], U2.ptr, ws.ptr, ws.nbytes, stream)
+        diff(t + c2 * tau, U2.ptr, D2)
+        vector_op(AX, N, c4 * tau, gn.ptr, 0.0, None, v1.ptr, stream)
+        vector_op(AX, N, tau * c4 * c4 / c2, D2.ptr, 0.0, None, v2.ptr, stream)
+        phiks_combine(P34, [u.ptr, v1.ptr, v2.ptr], O34.ptr, ws.ptr, ws.nbytes, stream)
+        U4, U3 = _pair(O34, N)
+        diff(t + c3 * tau, U3, D3)
+        diff(t + c4 * tau, U4, D4)
+        vector_op(AX, N, tau, gn.ptr, 0.0, None, v1.ptr, stream)
+        vector_op(AX, N, tau * a53[0], D3.ptr, tau * a53[1], D4.ptr, v2.ptr, stream)
+        vector_op(AX, N, tau * a63[0], D3.ptr, tau * a63[1], D4.ptr, v3.ptr, stream)
+        phiks_combine(P56, [u.ptr, v1.ptr, v2.ptr, v3.ptr], O56.ptr, ws.ptr, ws.nbytes, stream)
+        U6, U5 = _pair(O56, N)
+        diff(t + c5 * tau, U5, D5)
+        diff(t + c6 * tau, U6, D6)
+        vector_op(AX, N, tau * b2[0], D5.ptr, tau * b2[1], D6.ptr, v2.ptr, stream)
+        vector_op(AX, N, tau * b3[0], D5.ptr, tau * b3[1], D6.ptr, v3.ptr, stream)
+        phiks_combine(Pf, [u.ptr, v1.ptr, v2.ptr, v3.ptr], un.ptr, ws.ptr, ws.nbytes, stream)
+        u, un = un, u
+    for p in plans:
+        p.close()
+    return u

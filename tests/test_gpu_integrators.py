@@ -88,3 +88,15 @@ def test_allen_cahn_exp_euler_matches_oracle():
     d = rel_inf(u, ref)
     print(f"[gpu Allen-Cahn expEuler] vs oracle {d:.2e}")
     assert d < 1e-12
+
+
+@pytest.mark.parametrize("scheme,steps", [("exprk3s3", 10), ("exprk4s6", 5)])
+def test_higher_order_schemes_on_gpu_match_oracle(adr, scheme, steps):
+    from paper_2210_07667_amd import integrators as gi
+    g = gi.ADRNonlinearity(adr.u0, adr.w)
+    u = getattr(gi, scheme)(adr.A, adr.u0, g, 0.1, steps).to_numpy()
+    ref = getattr(oi, scheme)(adr.A, adr.u0, oi.adr_nonlinearity(adr), 0.1, steps)
+    d = rel_inf(u, ref)
+    err = rel_inf(u, adr.exact(0.1))
+    print(f"[gpu {scheme} {steps} steps] error {err:.3e}; vs oracle {d:.2e}")
+    assert d < 1e-11

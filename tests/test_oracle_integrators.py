@@ -59,3 +59,16 @@ def test_exp_euler_first_order(problem):
     g = oi.adr_nonlinearity(problem)
     err = rel_inf(oi.exp_euler(problem.A, problem.u0, g, 0.1, 600), problem.exact(0.1))
     assert abs(err / GOLD["exp_euler"]["kiops"][3] - 1) < 1e-6
+
+
+@pytest.mark.parametrize("scheme,steps,order", [("exprk3s3", (10, 20), 3), ("exprk4s6", (5, 10), 4)])
+def test_higher_order_schemes_converge_at_their_order(problem, scheme, steps, order):
+    """expRK3s3 (eq. expRK3s3) and expRK4s6 (eq. expRK4s6, stages 3/4 and 5/6 from
+    two-scale combinations) on the ADR problem, whose exact solution is known: halving
+    the step divides the error by 2^order."""
+    g = oi.adr_nonlinearity(problem)
+    f = getattr(oi, scheme)
+    e = [rel_inf(f(problem.A, problem.u0, g, 0.1, k), problem.exact(0.1)) for k in steps]
+    rate = np.log2(e[0] / e[1])
+    print(f"[{scheme}] errors {e} observed order {rate:.2f}")
+    assert abs(rate - order) < 0.3
