@@ -51,7 +51,7 @@ def measured_traffic():
     except OSError:
         return None
     h = hashlib.sha256()
-    for f in ("gemm_f64.hpp", "tucker_f64.hpp"):
+    for f in ("gemm_f64.hpp", "gemm_f64_dl.hpp", "tucker_f64.hpp"):
         h.update(open(os.path.join(ROOT, "paper_2210_07667_amd", "csrc", f), "rb").read())
     m1 = re.search(r"kernel_source_sha256: (\w+)", text)
     m2 = re.search(r"traffic_bytes_per_launch: ([0-9.eE+-]+)", text)
@@ -267,11 +267,15 @@ def main():
         log(f"[bench] warmup {i + 1}/{args.warmup}")
     ph.synchronize()
 
+    # HIP events on every mu-mode launch of a sample of the timed steps (every fifth and
+    # the last): a timestamped dispatch costs about 9 us of idle time after the kernel,
+    # so events on every step would slow the steps they measure
+    sampled = {i for i in range(args.steps) if i % 5 == 4 or i == args.steps - 1}
     ph.phiks_kernel_timing_read()          # clear
-    ph.phiks_kernel_timing(True)
     ph.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
+        ph.phiks_kernel_timing(i in sampled)
         step()
         log(f"[bench] step {i + 1}/{args.steps}")
     ph.synchronize()
@@ -347,8 +351,9 @@ def main():
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
                      "traffic": measured_traffic(), "traffic_unit": "bytes per launch",
-                     "kernel": "gemm_f64_kernel (mu-mode product)",
-                     "launches": k_launch, "avg_launch_ms": k_ms / max(k_launch, 1),
+                     "kernel": "gemm_f64_dl_kernel / gemm_f64_kernel (mu-mode product)",
+                     "launches": k_launch, "timed_steps": len(sampled),
+                     "avg_launch_ms": k_ms / max(k_launch, 1),
                      "flops_per_launch": k_flops / max(k_launch, 1)},
         "apply_only_ms": apply_ms,
         "apply_only_dofs_per_s": w.N / (apply_ms * 1e-3),

@@ -44,7 +44,6 @@ struct phiks_batch_s {
   std::vector<size_t> ws_off;             // per-problem workspace offsets, doubles
   size_t ws_doubles = 0;
   GroupTables tab;
-  std::vector<std::vector<char>> host_keep;
 };
 
 namespace {
@@ -148,26 +147,9 @@ int launch_grouped_cfg(const GroupedLaunch& L, const char* dev, const Epi& epi, 
     set_error("grouped GEMM grid too large");
     return PHIKS_EINVAL;
   }
-  hipEvent_t ea = nullptr, eb = nullptr;
-  {
-    std::lock_guard<std::mutex> lk(g_timing_mu);
-    if (g_timing) {
-      ea = pooled_event();
-      eb = pooled_event();
-      if (ea && eb) HIP_OK(hipEventRecord(ea, st));
-    }
-  }
-  (void)hipGetLastError();
-  hipLaunchKernelGGL((gemm_f64_grouped<BM, BN, WM, WN, KC, VEC, Epi>), dim3((unsigned)L.total),
-                     dim3(256), 0, st, (const GroupItem*)(dev + L.items_off),
-                     (const int64_t*)(dev + L.first_off), L.n, L.total, epi);
-  CHECK_LAUNCH();
-  if (ea && eb) {
-    HIP_OK(hipEventRecord(eb, st));
-    std::lock_guard<std::mutex> lk(g_timing_mu);
-    g_timed.push_back({ea, eb, L.flops});
-  }
-  return PHIKS_OK;
+  return timed_launch(&gemm_f64_grouped<BM, BN, WM, WN, KC, VEC, Epi>, (unsigned)L.total, st, L.flops,
+                      (const GroupItem*)(dev + L.items_off), (const int64_t*)(dev + L.first_off),
+                      L.n, L.total, epi);
 }
 
 template <bool KC, bool VEC, class Epi>
@@ -463,7 +445,7 @@ int phiks_batch_plan(int count, const int* d, const int64_t* const* n,
     ptrs[i] = &B->plans[i];
     mats[i] = A[i];
   }
-  int rc = build_plan_matrices(ptrs, mats, B->host_keep, st);
+  int rc = build_plan_matrices(ptrs, mats, st);
   if (rc != PHIKS_OK) return fail(rc);
   // workspace: each problem's single-call workspace, 16-byte aligned slices
   B->ws_off.resize(count);

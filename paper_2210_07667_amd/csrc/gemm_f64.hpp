@@ -54,6 +54,10 @@ struct GemmArgs {
   int64_t sA0, sA1, sB0, sB1, sC0, sC1;
   int tiles_m, tiles_n;
   int64_t total_tiles;
+  // tile order: 0 as described above; 1 batch index z1 slowest (tiles of one z1 back to
+  // back), for batches whose small-matrix operand differs per z1: with z1 fastest every
+  // matrix of the batch is live in L2 at once and, past its capacity, refetched per tile
+  int order;
   // pointer-array batch (used when pA != nullptr): operands of batch z1 are
   // pA[z1], pB[z1], pC[z1] (nb0 must be 1); the strides above are then ignored
   const double* const* pA;
@@ -97,16 +101,148 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t g, int64_t G) {
   return (xcd < rem) ? xcd * (per + 1) + slot : rem * (per + 1) + (xcd - rem) * per + slot;
 }
 
-// swizzle of a transposed (k-major) tile: bit 4 from k's parity, bits 2..4 from k/2
-__device__ __forceinline__ int swz_t(int k) { return ((k & 1) << 4) ^ (((k >> 1) & 7) << 2); }
-// swizzle of an n-contiguous tile: flips the 16-column half on odd k
-__device__ __forceinline__ int swz_n(int k) { return (k & 1) << 4; }
+// MFMA k order (shared by every FP64 kernel, so that a product gives the same bits
+// whichever kernel or tile computes it): K is taken in groups of 8; within group j the
+// first MFMA step takes k = 8j + 2 lk, the second k = 8j + 2 lk + 1 (lane group
+// lk = l >> 4).  A 32-lane half of a fragment read then touches rows k and k + 2.
+//
+// swizzle of a transposed (k-major) tile, p = (k/2) mod 8: bit 4 from p's parity (rows
+// k and k + 2 land on different bank halves), bits 2..3 from p/2, so the 8 even (odd)
+// rows of a 16-k chunk written by one store instruction get distinct offsets
+__device__ __forceinline__ int swz_t(int k) {
+  const int p = (k >> 1) & 7;
+  return ((p & 1) << 4) | ((p >> 1) << 2);
+}
+// swizzle of an n-contiguous tile: flips the 16-column half when bit 1 of k is set
+__device__ __forceinline__ int swz_n(int k) { return ((k >> 1) & 1) << 4; }
 
 // VEC: operands are loaded 2 doubles (16 bytes) at a time; requires even K, lda, ldb,
 // batch strides and 16-byte aligned base pointers (checked by the launcher).
 #ifndef PHIKS_GEMM_MIN_WAVES
 #define PHIKS_GEMM_MIN_WAVES 3  // minimum waves per SIMD the register budget must allow
 #endif
+
+// Tile coordinates and operand bases of logical tile `rest` (tile order above).
+struct TileOperands {
+  const PHIKS_GLOBAL double* A;
+  const PHIKS_GLOBAL double* B;
+  PHIKS_GLOBAL double* Cb;
+  int64_t cbase;   // offset of the output tensor within Cb
+  int64_t z1;
+  int tm, tn;
+};
+
+template <bool B_KCONTIG>
+__device__ __forceinline__ TileOperands tile_operands(const GemmArgs& g, int64_t rest) {
+  TileOperands t;
+  int64_t z0;
+  if (g.order == 1) {
+    // the tiles sharing an operand block run back to back: mode 1 the n tiles of one
+    // row block (one block of the tensor), modes > 1 the m tiles of one column block
+    if constexpr (B_KCONTIG) {
+      t.tn = (int)(rest % g.tiles_n);
+      rest /= g.tiles_n;
+      t.tm = (int)(rest % g.tiles_m);
+      rest /= g.tiles_m;
+    } else {
+      t.tm = (int)(rest % g.tiles_m);
+      rest /= g.tiles_m;
+      t.tn = (int)(rest % g.tiles_n);
+      rest /= g.tiles_n;
+    }
+    z0 = rest % g.nb0;
+    t.z1 = rest / g.nb0;
+  } else if constexpr (B_KCONTIG) {
+    t.tn = (int)(rest % g.tiles_n);
+    rest /= g.tiles_n;
+    t.z1 = rest % g.nb1;
+    rest /= g.nb1;
+    t.tm = (int)(rest % g.tiles_m);
+    z0 = rest / g.tiles_m;
+  } else {
+    t.z1 = rest % g.nb1;
+    rest /= g.nb1;
+    t.tm = (int)(rest % g.tiles_m);
+    rest /= g.tiles_m;
+    t.tn = (int)(rest % g.tiles_n);
+    z0 = rest / g.tiles_n;
+  }
+  if (g.pA != nullptr) {
+    t.A = gptr(g.pA[t.z1]);
+    t.B = gptr(g.pB[t.z1]);
+    t.Cb = gptr(g.pC[t.z1]);
+    t.cbase = 0;
+  } else {
+    t.A = gptr(g.A) + z0 * g.sA0 + t.z1 * g.sA1;
+    t.B = gptr(g.B) + z0 * g.sB0 + t.z1 * g.sB1;
+    t.Cb = gptr(g.C);
+    t.cbase = z0 * g.sC0 + t.z1 * g.sC1;
+  }
+  return t;
+}
+
+// Writes a wave's FM x FN register tile (16 x 16 fragments, result row (l >> 4) + 4r) at
+// rows mw.., columns nw.. of output tensor z1 through the epilogue.  Element (i, j, r)
+// of a lane sits at the lane's base offset plus (16 i + 4 r) ldc + 16 j, a wave-uniform
+// delta, so no per-element 64-bit addresses are held.
+template <int FM, int FN, class Epi, class P>
+__device__ __forceinline__ void store_tile_f64(dbl4 (&acc)[FM][FN], const GemmArgs& g, const Epi& epi,
+                                               P Cb, int64_t cbase, int64_t z1, int mw, int nw,
+                                               int lr, int lk) {
+  const int ml = mw + lk, nl = nw + lr;                 // the lane's first row and column
+  const int64_t base = cbase + (int64_t)ml * g.ldc + nl;
+  auto delta = [&](int i, int j, int r) { return (int64_t)(i * 16 + 4 * r) * g.ldc + j * 16; };
+  auto inside = [&](int i, int j, int r) { return (ml + i * 16 + 4 * r < g.M) & (nl + j * 16 < g.N); };
+  if constexpr (std::is_same<Epi, EpiLinComb>::value) {
+    // Squaring recurrence on the whole register tile: out = a_l acc + sum_k c_lk Y_k.
+    // For each k and each pair of fragment rows, all loads are issued before their fused
+    // multiply-adds (two rows at a time bounds the registers the loads hold).
+    const int l = (int)z1;
+    const double al = epi.a[l];
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j) acc[i][j] *= al;
+    constexpr int FI = FM < 2 ? FM : 2;
+    static_assert(FM % FI == 0, "row pairs");
+    for (int k = 0; k <= l; ++k) {
+      const double ck = epi.c[l][k];
+      const PHIKS_GLOBAL double* __restrict__ Yk = gptr(epi.Y) + (int64_t)(k - l) * epi.N + base;
+#pragma unroll
+      for (int i0 = 0; i0 < FM; i0 += FI) {
+        double y[FI][FN][4];
+#pragma unroll
+        for (int i = 0; i < FI; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+              y[i][j][r] = inside(i0 + i, j, r) ? Yk[delta(i0 + i, j, r)] : 0.0;
+#pragma unroll
+        for (int i = 0; i < FI; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc[i0 + i][j][r] += ck * y[i][j][r];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          if (inside(i, j, r)) Cb[base + delta(i, j, r)] = acc[i][j][r];
+  } else {
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          if (inside(i, j, r)) epi(Cb, base + delta(i, j, r), z1, acc[i][j][r]);
+  }
+}
 
 // One output tile of one GEMM: `rest` is the logical tile index in the tile order
 // described above (0 .. g.total_tiles - 1).
@@ -132,42 +268,13 @@ __device__ __forceinline__ void gemm_f64_tile(const GemmArgs& g, const Epi& epi,
   __shared__ __align__(16) double As[2][BK][BM];
   __shared__ __align__(16) double Bs[2][BK][BN];
 
-  int tm, tn;
-  int64_t z1, z0;
-  if constexpr (B_KCONTIG) {
-    tn = (int)(rest % g.tiles_n);
-    rest /= g.tiles_n;
-    z1 = rest % g.nb1;
-    rest /= g.nb1;
-    tm = (int)(rest % g.tiles_m);
-    z0 = rest / g.tiles_m;
-  } else {
-    z1 = rest % g.nb1;
-    rest /= g.nb1;
-    tm = (int)(rest % g.tiles_m);
-    rest /= g.tiles_m;
-    tn = (int)(rest % g.tiles_n);
-    z0 = rest / g.tiles_n;
-  }
-
-  const PHIKS_GLOBAL double* __restrict__ A;
-  const PHIKS_GLOBAL double* __restrict__ B;
-  PHIKS_GLOBAL double* Cb;
-  int64_t cbase;
-  if (g.pA != nullptr) {
-    A = gptr(g.pA[z1]);
-    B = gptr(g.pB[z1]);
-    Cb = gptr(g.pC[z1]);
-    cbase = 0;
-  } else {
-    A = gptr(g.A) + z0 * g.sA0 + z1 * g.sA1;
-    B = gptr(g.B) + z0 * g.sB0 + z1 * g.sB1;
-    Cb = gptr(g.C);
-    cbase = z0 * g.sC0 + z1 * g.sC1;
-  }
-
-  const int m0 = tm * BM;
-  const int n0 = tn * BN;
+  const TileOperands t = tile_operands<B_KCONTIG>(g, rest);
+  const PHIKS_GLOBAL double* __restrict__ A = t.A;
+  const PHIKS_GLOBAL double* __restrict__ B = t.B;
+  PHIKS_GLOBAL double* Cb = t.Cb;
+  const int64_t cbase = t.cbase, z1 = t.z1;
+  const int m0 = t.tm * BM;
+  const int n0 = t.tn * BN;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
@@ -282,7 +389,7 @@ __device__ __forceinline__ void gemm_f64_tile(const GemmArgs& g, const Epi& epi,
     if (c + 1 < nchunks) load_chunk((c + 1) * BK);
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
-      const int k = kk + lk;
+      const int k = (kk & ~7) + 2 * lk + ((kk >> 2) & 1);   // the k order above
       double fa[FM], fb[FN];
 #pragma unroll
       for (int i = 0; i < FM; ++i) fa[i] = As[buf][k][(wm + i * 16 + lr) ^ swz_t(k)];
@@ -301,62 +408,7 @@ __device__ __forceinline__ void gemm_f64_tile(const GemmArgs& g, const Epi& epi,
     __syncthreads();
   }
 
-  if constexpr (std::is_same<Epi, EpiLinComb>::value) {
-    // Squaring recurrence on the whole register tile: out = a_l acc + sum_k c_lk Y_k.
-    // For each k all loads of the tile are issued before their fused multiply-adds.
-    const int l = (int)z1;
-    const double al = epi.a[l];
-#pragma unroll
-    for (int i = 0; i < FM; ++i)
-#pragma unroll
-      for (int j = 0; j < FN; ++j) acc[i][j] *= al;
-    for (int k = 0; k <= l; ++k) {
-      const double ck = epi.c[l][k];
-      const PHIKS_GLOBAL double* __restrict__ Yk = gptr(epi.Y) + (int64_t)(k - l) * epi.N;
-      double y[FM][FN][4];
-#pragma unroll
-      for (int i = 0; i < FM; ++i)
-#pragma unroll
-        for (int j = 0; j < FN; ++j) {
-          const int n = n0 + wn + j * 16 + lr;
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int m = m0 + wm + i * 16 + lk + 4 * r;
-            const bool ok = m < g.M && n < g.N;
-            y[i][j][r] = ok ? Yk[cbase + (int64_t)m * g.ldc + n] : 0.0;
-          }
-        }
-#pragma unroll
-      for (int i = 0; i < FM; ++i)
-#pragma unroll
-        for (int j = 0; j < FN; ++j)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) acc[i][j][r] += ck * y[i][j][r];
-    }
-#pragma unroll
-    for (int i = 0; i < FM; ++i)
-#pragma unroll
-      for (int j = 0; j < FN; ++j) {
-        const int n = n0 + wn + j * 16 + lr;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int m = m0 + wm + i * 16 + lk + 4 * r;
-          if (m < g.M && n < g.N) Cb[cbase + (int64_t)m * g.ldc + n] = acc[i][j][r];
-        }
-      }
-  } else {
-#pragma unroll
-    for (int i = 0; i < FM; ++i)
-#pragma unroll
-      for (int j = 0; j < FN; ++j) {
-        const int n = n0 + wn + j * 16 + lr;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int m = m0 + wm + i * 16 + lk + 4 * r;
-          if (m < g.M && n < g.N) epi(Cb, cbase + (int64_t)m * g.ldc + n, z1, acc[i][j][r]);
-        }
-      }
-  }
+  store_tile_f64<FM, FN>(acc, g, epi, Cb, cbase, z1, m0 + wm, n0 + wn, lr, lk);
 }
 
 template <int BM, int BN, int WM, int WN, bool B_KCONTIG, bool VEC, class Epi, bool CPLX = false>

@@ -1,0 +1,200 @@
+// FP64 MFMA GEMM for gfx950 with direct-to-LDS operand loads: the mu-mode products of
+// Section 2 at tile sizes 64 and 128, K a multiple of the chunk length.
+//
+// Same products, tile order and epilogues as gemm_f64_kernel (gemm_f64.hpp); what
+// differs is how operands reach LDS.  Every operand load is a global_load_lds_dwordx4:
+// each lane moves 16 bytes from global memory straight into LDS, lane l of a wave
+// writing the l-th 16-byte slot after the wave's base (held in M0).  No registers hold
+// staged operands and no instructions copy them, so chunks can be fetched ST - 1 ahead
+// of the MFMAs through an ST-stage LDS ring, synchronised by the load counter (vmcnt)
+// and one barrier per chunk.
+//
+// LDS layouts (16-byte slots; the lane -> slot map is fixed, so each lane fetches the
+// global data that belongs in its slot):
+//  * k-contiguous operand (A, and B of mode 1), rows r < R, k < BK: the slot of
+//    (r, k pair kp) is r*KP + (kp ^ swz_kp(r)), KP = BK/2.  KP consecutive lanes fetch one
+//    row's BK*8 contiguous bytes.  A fragment read takes one k pair per lane
+//    (ds_read_b128) and feeds two MFMAs: lane group lk = l >> 4 of MFMA step 2j (2j+1)
+//    holds k = 8j + 2lk (8j + 2lk + 1), the same k for both operands of each MFMA.
+//  * n-contiguous operand (B of modes > 1), k < BK, columns c < BN: the slot of
+//    (k, column pair cp) is k*BN/2 + (cp ^ swz_np(k)).  Fragment reads are 8 bytes.
+// Both swizzles make every 16-lane (b128) or 32-lane (b64) group of a fragment read hit
+// distinct banks; the DMA writes are contiguous.
+//
+// Ragged M and N: rows (columns) past the end are fetched from a clamped in-range
+// address; they only reach output rows (columns) that are never stored.  K must be a
+// multiple of BK (the launcher checks), so no zero fill is needed.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <type_traits>
+
+#include "gemm_f64.hpp"
+
+namespace phiks {
+
+#ifndef PHIKS_DL_BK
+#define PHIKS_DL_BK 8   // k per chunk
+#endif
+#ifndef PHIKS_DL_ST
+#define PHIKS_DL_ST 2   // LDS stages
+#endif
+#ifndef PHIKS_DL_MIN_WAVES
+#define PHIKS_DL_MIN_WAVES 4     // waves per SIMD the register budget must allow
+#endif
+#ifndef PHIKS_DL_MIN_WAVES_LC
+#define PHIKS_DL_MIN_WAVES_LC 3  // the same for the squaring epilogue (more live registers)
+#endif
+
+template <int KP>
+__device__ __forceinline__ int swz_kp(int r) { return (r / (16 / KP)) & (KP - 1); }
+__device__ __forceinline__ int swz_np(int k) { return ((k >> 1) & 1) << 3; }
+
+// s_waitcnt with only the vector-memory counter bounded (gfx9 encoding: vmcnt in bits
+// 3:0 and 15:14, expcnt 6:4 and lgkmcnt 11:8 left at their no-wait maxima).
+template <int N>
+__device__ __forceinline__ void wait_vmcnt() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8) | ((N >> 4) << 14));
+}
+__device__ __forceinline__ void wait_lgkmcnt0() {
+  __builtin_amdgcn_s_waitcnt(15 | (7 << 4) | (0 << 8) | (3 << 14));
+}
+
+// 16 bytes per lane from src into LDS: lane l writes bytes [16 l, 16 l + 16) after the
+// wave-uniform LDS address lds_dst.  Issued from inline asm: the compiler would
+// otherwise wait for every LDS-DMA load in flight before each LDS read it cannot prove
+// disjoint from them, which serialises the stages.  The ordering is explicit instead:
+// wait_vmcnt for this wave's loads of a chunk, then a barrier for everyone's.  The
+// statement has no outputs; its inputs are read when it issues.
+__device__ __forceinline__ void dma16(const PHIKS_GLOBAL double* src, double* lds_dst) {
+  const uint32_t lds = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) double*)lds_dst;
+  asm volatile("global_load_lds_dwordx4 %0, off" : : "v"(src), "{m0}"(lds) : "memory");
+}
+
+template <int BM, int BN, int WM, int WN, bool B_KCONTIG, class Epi, int BK, int ST>
+__device__ __forceinline__ void gemm_f64_dl_tile(const GemmArgs& g, const Epi& epi, int64_t rest) {
+  static_assert(BK == 8 || BK == 16, "chunk of 8 or 16 k");
+  static_assert(ST >= 2, "at least two stages");
+  constexpr int KP = BK / 2;
+  constexpr int WGM = BM / WM, WGN = BN / WN;
+  static_assert(WGM * WGN == 4, "4 waves per work-group");
+  constexpr int FM = WM / 16, FN = WN / 16;
+  constexpr int A_SLOTS = BM * KP, B_SLOTS = BN * KP;
+  static_assert(A_SLOTS % 256 == 0 && B_SLOTS % 256 == 0, "every thread fetches the same count");
+  constexpr int LA = A_SLOTS / 256, LB = B_SLOTS / 256;
+  static_assert(B_KCONTIG || BN / 2 >= 16, "column-pair swizzle needs BN >= 32");
+
+  __shared__ __align__(16) double As[ST][2 * A_SLOTS];
+  __shared__ __align__(16) double Bs[ST][2 * B_SLOTS];
+
+  const TileOperands t = tile_operands<B_KCONTIG>(g, rest);
+  const int m0 = t.tm * BM, n0 = t.tn * BN;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wm = (wave / WGN) * WM, wn = (wave % WGN) * WN;
+  const int lr = lane & 15, lk = lane >> 4;
+
+  // global sources of this thread's slots, chunk 0
+  const PHIKS_GLOBAL double* asrc[LA];
+  const PHIKS_GLOBAL double* bsrc[LB];
+#pragma unroll
+  for (int i = 0; i < LA; ++i) {
+    const int s = i * 256 + tid;
+    const int r = s / KP, kp = (s % KP) ^ swz_kp<KP>(s / KP);
+    asrc[i] = t.A + (int64_t)min(m0 + r, g.M - 1) * g.lda + 2 * kp;
+  }
+#pragma unroll
+  for (int i = 0; i < LB; ++i) {
+    const int s = i * 256 + tid;
+    if constexpr (B_KCONTIG) {
+      const int r = s / KP, kp = (s % KP) ^ swz_kp<KP>(s / KP);
+      bsrc[i] = t.B + (int64_t)min(n0 + r, g.N - 1) * g.ldb + 2 * kp;
+    } else {
+      const int k = s / (BN / 2), cp = (s % (BN / 2)) ^ swz_np(s / (BN / 2));
+      bsrc[i] = t.B + (int64_t)k * g.ldb + min(n0 + 2 * cp, g.N - 2);
+    }
+  }
+  const int64_t bstep = B_KCONTIG ? BK : (int64_t)BK * g.ldb;   // source advance per chunk
+
+  auto issue = [&](int c) {
+    const int st = c % ST;
+#pragma unroll
+    for (int i = 0; i < LA; ++i) dma16(asrc[i] + (int64_t)c * BK, &As[st][2 * (i * 256 + wave * 64)]);
+#pragma unroll
+    for (int i = 0; i < LB; ++i) dma16(bsrc[i] + (int64_t)c * bstep, &Bs[st][2 * (i * 256 + wave * 64)]);
+  };
+
+  dbl4 acc[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
+
+  const int nchunks = g.K / BK;
+#pragma unroll
+  for (int c = 0; c < ST - 1; ++c)
+    if (c < nchunks) issue(c);
+
+  for (int c = 0; c < nchunks; ++c) {
+    // chunk c has landed once no more than the later chunks' loads are outstanding
+    if (c + ST - 2 < nchunks) wait_vmcnt<(ST - 2) * (LA + LB)>();
+    else wait_vmcnt<0>();
+    wait_lgkmcnt0();
+    // chunk c visible; every wave is done with chunk c - 1.  The empty asm statements
+    // keep the compiler from moving LDS accesses across the barrier (a fence would
+    // also wait for the loads of the later chunks).
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+    if (c + ST - 1 < nchunks) issue(c + ST - 1);   // into the stage chunk c - 1 used
+    const double* as = As[c % ST];
+    const double* bs = Bs[c % ST];
+#pragma unroll
+    for (int j = 0; j < BK / 8; ++j) {
+      const int kp = 4 * j + lk;
+      dbl2 fa[FM], fb[FN];
+#pragma unroll
+      for (int i = 0; i < FM; ++i) {
+        const int r = wm + i * 16 + lr;
+        fa[i] = *reinterpret_cast<const dbl2*>(as + 2 * (r * KP + (kp ^ swz_kp<KP>(r))));
+      }
+#pragma unroll
+      for (int jj = 0; jj < FN; ++jj) {
+        const int n = wn + jj * 16 + lr;
+        if constexpr (B_KCONTIG) {
+          fb[jj] = *reinterpret_cast<const dbl2*>(bs + 2 * (n * KP + (kp ^ swz_kp<KP>(n))));
+        } else {
+          const int k = 8 * j + 2 * lk;
+          fb[jj][0] = bs[2 * (k * (BN / 2) + ((n >> 1) ^ swz_np(k))) + (n & 1)];
+          fb[jj][1] = bs[2 * ((k + 1) * (BN / 2) + ((n >> 1) ^ swz_np(k + 1))) + (n & 1)];
+        }
+      }
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int jj = 0; jj < FN; ++jj)
+            acc[i][jj] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[i][h], fb[jj][h], acc[i][jj], 0, 0, 0);
+    }
+  }
+
+  store_tile_f64<FM, FN>(acc, g, epi, t.Cb, t.cbase, t.z1, m0 + wm, n0 + wn, lr, lk);
+}
+
+template <class Epi>
+constexpr int dl_min_waves() {
+  return std::is_same<Epi, EpiLinComb>::value ? PHIKS_DL_MIN_WAVES_LC : PHIKS_DL_MIN_WAVES;
+}
+
+template <int BM, int BN, int WM, int WN, bool B_KCONTIG, class Epi>
+__global__ void __launch_bounds__(256, dl_min_waves<Epi>()) gemm_f64_dl_kernel(GemmArgs g, Epi epi) {
+  gemm_f64_dl_tile<BM, BN, WM, WN, B_KCONTIG, Epi, PHIKS_DL_BK, PHIKS_DL_ST>(
+      g, epi, xcd_remap(blockIdx.x, g.total_tiles));
+}
+
+}  // namespace phiks

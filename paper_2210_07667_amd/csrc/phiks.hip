@@ -27,6 +27,7 @@
 #include "plan.hpp"
 #include "planner.hpp"
 #include "runtime.hpp"
+#include "stage.hpp"
 #include "tucker_mixed.hpp"
 #include "tucker_f64.hpp"
 
@@ -135,22 +136,19 @@ struct ExpmRequest {
 };
 
 // C_i = A_i B_i (+ beta C_i) for pointer arrays of equal-size n x n products; the
-// pointer table's host copy is kept alive in host_keep until the plan is released.
+// pointer table is staged through S.
 int ptr_gemm(const std::vector<const double*>& a, const std::vector<const double*>& b,
-             const std::vector<double*>& c, int n, double beta,
-             std::vector<std::vector<char>>& host_keep, hipStream_t st) {
+             const std::vector<double*>& c, int n, double beta, Stager& S, hipStream_t st) {
   if (a.empty()) return PHIKS_OK;
   const size_t nb = a.size();
-  host_keep.emplace_back(3 * nb * sizeof(void*));
-  void** hp = (void**)host_keep.back().data();
+  std::vector<void*> hp(3 * nb);
   for (size_t i = 0; i < nb; ++i) {
     hp[i] = (void*)a[i];
     hp[nb + i] = (void*)b[i];
     hp[2 * nb + i] = (void*)c[i];
   }
   void** dp = nullptr;
-  HIP_OK(hipMallocAsync((void**)&dp, 3 * nb * sizeof(void*), st));
-  HIP_OK(hipMemcpyAsync(dp, hp, 3 * nb * sizeof(void*), hipMemcpyHostToDevice, st));
+  RET_IF(S.table(hp.data(), hp.size(), &dp));
   GemmArgs g = empty_args();
   g.M = g.N = g.K = n;
   g.lda = g.ldb = g.ldc = n;
@@ -164,14 +162,12 @@ int ptr_gemm(const std::vector<const double*>& a, const std::vector<const double
     ptrs.push_back(b[i]);
     ptrs.push_back(c[i]);
   }
-  int rc = launch_gemm<false>(g, EpiStore{1.0, beta}, st, ptrs);
-  HIP_OK(hipFreeAsync(dp, st));
-  return rc;
+  return launch_gemm<false>(g, EpiStore{1.0, beta}, st, ptrs);
 }
 
 // Computes exp(c_r B_{op_r}) for every request on the device.
 int batched_expm(const std::vector<ExpmOp>& ops, const std::vector<ExpmRequest>& reqs,
-                 std::vector<std::vector<char>>& host_keep, hipStream_t st) {
+                 Stager& S, hipStream_t st) {
   const size_t nops = ops.size();
   if (reqs.empty()) return PHIKS_OK;
   // Bh = Bshift / beta with beta a power of two >= ||Bshift||_1 (an exact scaling)
@@ -203,16 +199,11 @@ int batched_expm(const std::vector<ExpmOp>& ops, const std::vector<ExpmRequest>&
   };
   auto d_ptr = [&](size_t r, int i) { return scratch + req_off[r] + (size_t)i * sq(ops[reqs[r].op].n); };
   {
-    size_t hbytes = 0;
-    for (size_t o = 0; o < nops; ++o) hbytes += sizeof(double) * ops[o].Bshift.size();
-    host_keep.emplace_back(hbytes);
-    double* h = (double*)host_keep.back().data();
-    size_t pos = 0;
+    std::vector<double> h;
     for (size_t o = 0; o < nops; ++o) {
-      for (size_t e = 0; e < ops[o].Bshift.size(); ++e) h[pos + e] = ops[o].Bshift[e] / beta[o];
-      HIP_OK(hipMemcpyAsync(pw_ptr(o, 1), h + pos, sizeof(double) * ops[o].Bshift.size(),
-                            hipMemcpyHostToDevice, st));
-      pos += ops[o].Bshift.size();
+      h.resize(ops[o].Bshift.size());
+      for (size_t e = 0; e < h.size(); ++e) h[e] = ops[o].Bshift[e] / beta[o];
+      RET_IF(S.upload(pw_ptr(o, 1), h.data(), sizeof(double) * h.size()));
     }
   }
   // operators grouped by size for the pointer-array GEMMs
@@ -230,7 +221,7 @@ int batched_expm(const std::vector<ExpmOp>& ops, const std::vector<ExpmRequest>&
         b.push_back(pw_ptr(o, 1));
         c.push_back(pw_ptr(o, k));
       }
-      RET_IF(ptr_gemm(a, b, c, (int)nsz, 0.0, host_keep, st));
+      RET_IF(ptr_gemm(a, b, c, (int)nsz, 0.0, S, st));
     }
   }
   // D_i of every request
@@ -250,12 +241,8 @@ int batched_expm(const std::vector<ExpmOp>& ops, const std::vector<ExpmRequest>&
     }
     for (int i = 0; i < kTaylorBlocks; ++i) J.D[i] = d_ptr(r, i);
   }
-  host_keep.emplace_back(jobs.size() * sizeof(TaylorJob));
-  std::memcpy(host_keep.back().data(), jobs.data(), host_keep.back().size());
   TaylorJob* djobs = nullptr;
-  HIP_OK(hipMallocAsync((void**)&djobs, jobs.size() * sizeof(TaylorJob), st));
-  HIP_OK(hipMemcpyAsync(djobs, host_keep.back().data(), jobs.size() * sizeof(TaylorJob),
-                        hipMemcpyHostToDevice, st));
+  RET_IF(S.table(jobs.data(), jobs.size(), &djobs));
   const unsigned eblocks = (unsigned)std::min<int64_t>((sq(nmax) + 255) / 256, 1024);
   (void)hipGetLastError();
   hipLaunchKernelGGL(taylor_form_kernel, dim3(eblocks, (unsigned)jobs.size()), dim3(256), 0, st,
@@ -272,7 +259,7 @@ int batched_expm(const std::vector<ExpmOp>& ops, const std::vector<ExpmRequest>&
         b.push_back(pw_ptr(reqs[r].op, kTaylorBlocks));
         c.push_back(d_ptr(r, i));
       }
-      RET_IF(ptr_gemm(a, b, c, (int)nsz, 1.0, host_keep, st));
+      RET_IF(ptr_gemm(a, b, c, (int)nsz, 1.0, S, st));
     }
   }
   // squarings: X <- X^2 (ping-pong through the request's last buffer)
@@ -295,7 +282,7 @@ int batched_expm(const std::vector<ExpmOp>& ops, const std::vector<ExpmRequest>&
         c.push_back(othp[r]);
         idx.push_back(r);
       }
-      RET_IF(ptr_gemm(a, b, c, (int)nsz, 0.0, host_keep, st));
+      RET_IF(ptr_gemm(a, b, c, (int)nsz, 0.0, S, st));
       for (size_t r : idx) std::swap(curp[r], othp[r]);
     }
   }
@@ -307,18 +294,12 @@ int batched_expm(const std::vector<ExpmOp>& ops, const std::vector<ExpmRequest>&
     sj[r].scale = std::exp(reqs[r].c * ops[reqs[r].op].sigma);
     sj[r].n = (int)ops[reqs[r].op].n;
   }
-  host_keep.emplace_back(sj.size() * sizeof(ScaleJob));
-  std::memcpy(host_keep.back().data(), sj.data(), host_keep.back().size());
   ScaleJob* dsj = nullptr;
-  HIP_OK(hipMallocAsync((void**)&dsj, sj.size() * sizeof(ScaleJob), st));
-  HIP_OK(hipMemcpyAsync(dsj, host_keep.back().data(), sj.size() * sizeof(ScaleJob),
-                        hipMemcpyHostToDevice, st));
+  RET_IF(S.table(sj.data(), sj.size(), &dsj));
   (void)hipGetLastError();
   hipLaunchKernelGGL(scale_copy_kernel, dim3(eblocks, (unsigned)sj.size()), dim3(256), 0, st,
                      dsj);
   CHECK_LAUNCH();
-  HIP_OK(hipFreeAsync(dsj, st));
-  HIP_OK(hipFreeAsync(djobs, st));
   HIP_OK(hipFreeAsync(scratch, st));
   return PHIKS_OK;
 }
@@ -519,15 +500,10 @@ void plan_assign(phiks_plan_s& P, double* base) {
 }
 
 // Batched dst_i = scale_i * src_i over n_i x n_i entries.
-int launch_scale_jobs(const std::vector<ScaleJob>& sj, std::vector<std::vector<char>>& host_keep,
-                      hipStream_t st) {
+int launch_scale_jobs(const std::vector<ScaleJob>& sj, Stager& S, hipStream_t st) {
   if (sj.empty()) return PHIKS_OK;
-  host_keep.emplace_back(sj.size() * sizeof(ScaleJob));
-  std::memcpy(host_keep.back().data(), sj.data(), host_keep.back().size());
   ScaleJob* dsj = nullptr;
-  HIP_OK(hipMallocAsync((void**)&dsj, sj.size() * sizeof(ScaleJob), st));
-  HIP_OK(hipMemcpyAsync(dsj, host_keep.back().data(), sj.size() * sizeof(ScaleJob),
-                        hipMemcpyHostToDevice, st));
+  RET_IF(S.table(sj.data(), sj.size(), &dsj));
   int64_t nmax = 0;
   for (const ScaleJob& j : sj) nmax = std::max<int64_t>(nmax, j.n);
   (void)hipGetLastError();
@@ -535,7 +511,6 @@ int launch_scale_jobs(const std::vector<ScaleJob>& sj, std::vector<std::vector<c
                                              (unsigned)sj.size()),
                      dim3(256), 0, st, dsj);
   CHECK_LAUNCH();
-  HIP_OK(hipFreeAsync(dsj, st));
   return PHIKS_OK;
 }
 
@@ -546,8 +521,8 @@ int launch_scale_jobs(const std::vector<ScaleJob>& sj, std::vector<std::vector<c
 // size, then the FP32 copies of the mixed-precision plans.  A[i] are plan i's host
 // matrices; every plan's device pointers must already be assigned.
 int build_plan_matrices(const std::vector<phiks_plan_s*>& plans,
-                        const std::vector<const double* const*>& A,
-                        std::vector<std::vector<char>>& host_keep, hipStream_t st) {
+                        const std::vector<const double* const*>& A, hipStream_t st) {
+  Stager S(st);
   std::vector<ExpmOp> ops;
   std::vector<ExpmRequest> reqs;
   for (size_t i = 0; i < plans.size(); ++i) {
@@ -599,7 +574,7 @@ int build_plan_matrices(const std::vector<phiks_plan_s*>& plans,
       (void)nc;
     }
   }
-  RET_IF(batched_expm(ops, reqs, host_keep, st));
+  RET_IF(batched_expm(ops, reqs, S, st));
   // exp(B/2^s) = the node matrix of theta_1 = 0
   std::vector<ScaleJob> copies;
   int smax = 0;
@@ -611,7 +586,7 @@ int build_plan_matrices(const std::vector<phiks_plan_s*>& plans,
       copies.push_back({P->Lnode[mu], P->E[mu] + (size_t)P->s * sq(m), 1.0, (int)m});
     }
   }
-  RET_IF(launch_scale_jobs(copies, host_keep, st));
+  RET_IF(launch_scale_jobs(copies, S, st));
   // exp(B/2^(j-1)) = exp(B/2^j)^2, j = s..1, grouped by size
   for (int j = smax; j >= 1; --j) {
     auto opn = [](const phiks_plan_s* P, int mu) { return P->cplx ? 2 * P->n[mu] : P->n[mu]; };
@@ -631,7 +606,7 @@ int build_plan_matrices(const std::vector<phiks_plan_s*>& plans,
           c.push_back(P->E[mu] + (size_t)(j - 1) * sq(nsz));
         }
       }
-      RET_IF(ptr_gemm(a, a, c, (int)nsz, 0.0, host_keep, st));
+      RET_IF(ptr_gemm(a, a, c, (int)nsz, 0.0, S, st));
     }
   }
   // complex plans: the [Re | Im] forms used by the modes > 1
@@ -650,12 +625,8 @@ int build_plan_matrices(const std::vector<phiks_plan_s*>& plans,
     }
   }
   if (!splits.empty()) {
-    host_keep.emplace_back(splits.size() * sizeof(ScaleJob));
-    std::memcpy(host_keep.back().data(), splits.data(), host_keep.back().size());
     ScaleJob* dsj = nullptr;
-    HIP_OK(hipMallocAsync((void**)&dsj, splits.size() * sizeof(ScaleJob), st));
-    HIP_OK(hipMemcpyAsync(dsj, host_keep.back().data(), splits.size() * sizeof(ScaleJob),
-                          hipMemcpyHostToDevice, st));
+    RET_IF(S.table(splits.data(), splits.size(), &dsj));
     int64_t nmax = 0;
     for (const ScaleJob& j : splits) nmax = std::max<int64_t>(nmax, j.n);
     (void)hipGetLastError();
@@ -664,7 +635,6 @@ int build_plan_matrices(const std::vector<phiks_plan_s*>& plans,
                             (unsigned)splits.size()),
                        dim3(256), 0, st, dsj);
     CHECK_LAUNCH();
-    HIP_OK(hipFreeAsync(dsj, st));
   }
   // FP32 copies of every node matrix and of exp(B/2^j): the mixed-precision paths
   // multiply by these; everything else stays FP64
@@ -806,15 +776,11 @@ int finish_plan(phiks_plan_s* P, const double* const* A, void* hip_stream, phiks
     return fail(PHIKS_ENOMEM);
   }
   plan_assign(*P, (double*)P->dmem);
-  rc = build_plan_matrices({P}, {A}, P->host_keep, st);
+  rc = build_plan_matrices({P}, {A}, st);
   if (rc != PHIKS_OK) return fail(rc);
   *out = P;
   return PHIKS_OK;
 }
-
-namespace {
-void release_host_keep(void* p) { delete static_cast<std::vector<std::vector<char>>*>(p); }
-}  // namespace
 
 void phiks_plan_destroy(phiks_plan_t plan) {
   if (!plan) return;
@@ -822,12 +788,6 @@ void phiks_plan_destroy(phiks_plan_t plan) {
   (void)hipGetDevice(&cur);
   (void)hipSetDevice(plan->device);
   if (plan->dmem) (void)hipFreeAsync(plan->dmem, plan->stream);
-  // host sources of the plan's asynchronous copies are released once the stream gets here
-  auto* keep = new std::vector<std::vector<char>>(std::move(plan->host_keep));
-  if (hipLaunchHostFunc(plan->stream, release_host_keep, keep) != hipSuccess) {
-    (void)hipStreamSynchronize(plan->stream);
-    release_host_keep(keep);
-  }
   (void)hipSetDevice(cur);
   delete plan;
 }

@@ -31,7 +31,6 @@ struct phiks_plan_s {
   int cplx = 0;
   double* Lsplit[PHIKS_MAX_D] = {nullptr};
   double* Esplit[PHIKS_MAX_D] = {nullptr};
-  std::vector<std::vector<char>> host_keep;  // host sources of async copies
 };
 
 // Doubles per vector of the plan's problem (N, or 2N for complex vectors).

@@ -1,6 +1,7 @@
 // Error state, launch checks and optional per-launch kernel timing of the phiks
 // runtime.  Included once, by phiks.hip.
 #pragma once
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstring>
@@ -44,8 +45,10 @@ void set_error(const std::string& s) { g_last_error = s; }
   } while (0)
 
 // --------------------------------------------------- kernel timing (optional)
-// When enabled, every mu-mode GEMM launch is bracketed by two HIP events recorded
-// on its own stream, with its algorithmic flop count 2 M N K (per batch entry).
+// When enabled, every mu-mode GEMM launch carries two HIP events that record its start
+// and end on its own stream, with its algorithmic flop count 2 M N K (per batch entry).
+// The events ride in the kernel's own dispatch (hipExtLaunchKernelGGL), so timing adds
+// no marker packets, and no idle time, between consecutive kernels.
 struct TimedLaunch {
   hipEvent_t a, b;
   double flops;
@@ -66,6 +69,36 @@ hipEvent_t pooled_event() {
   return e;
 }
 
+
+// kern<<<grid, 256>>>(args...) on st, timed as above while timing is enabled.
+template <typename... KArgs, typename... Args>
+int timed_launch(void (*kern)(KArgs...), unsigned grid, hipStream_t st, double flops,
+                 Args... args) {
+  hipEvent_t ea = nullptr, eb = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_timing_mu);
+    if (g_timing) {
+      ea = pooled_event();
+      eb = pooled_event();
+      if (!ea || !eb) {
+        if (ea) g_event_pool.push_back(ea);
+        if (eb) g_event_pool.push_back(eb);
+        ea = eb = nullptr;
+      }
+    }
+  }
+  (void)hipGetLastError();  // clear a stale error left by an unrelated earlier call
+  if (ea)
+    hipExtLaunchKernelGGL(kern, dim3(grid), dim3(256), 0, st, ea, eb, 0, args...);
+  else
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(256), 0, st, args...);
+  CHECK_LAUNCH();
+  if (ea) {
+    std::lock_guard<std::mutex> lk(g_timing_mu);
+    g_timed.push_back({ea, eb, flops});
+  }
+  return PHIKS_OK;
+}
 
 GemmArgs empty_args() {
   GemmArgs g;

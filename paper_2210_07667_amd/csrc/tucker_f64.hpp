@@ -7,6 +7,7 @@
 #include <vector>
 
 #include "gemm_f64.hpp"
+#include "gemm_f64_dl.hpp"
 #include "plan.hpp"
 #include "runtime.hpp"
 
@@ -16,6 +17,10 @@ using namespace phiks;
 
 // ------------------------------------------------------------- GEMM launching
 enum class Tile { T128x128, T128x64, T64x128, T64x64, T32x32 };
+
+#ifndef PHIKS_DL
+#define PHIKS_DL 1  // 1: products with 64- and 128-wide tiles load operands straight into LDS
+#endif
 
 int64_t tiles_for(const GemmArgs& g, int bm, int bn) {
   return (int64_t)((g.M + bm - 1) / bm) * ((g.N + bn - 1) / bn) * g.nb0 * g.nb1;
@@ -61,25 +66,21 @@ int launch_cfg(GemmArgs g, const Epi& epi, hipStream_t st) {
     set_error("GEMM grid too large");
     return PHIKS_EINVAL;
   }
-  hipEvent_t ea = nullptr, eb = nullptr;
-  {
-    std::lock_guard<std::mutex> lk(g_timing_mu);
-    if (g_timing) {
-      ea = pooled_event();
-      eb = pooled_event();
-      if (ea && eb) HIP_OK(hipEventRecord(ea, st));
-    }
+  const double flops = 2.0 * g.M * (double)g.N * g.K * g.nb0 * (double)g.nb1;
+  // batches whose small matrix differs per entry (node matrices, pointer arrays) run one
+  // entry's tiles back to back; the squaring epilogue keeps the entries of one tile
+  // together, since they read the same pre-step tensors
+  if (!std::is_same<Epi, EpiLinComb>::value && g.nb1 > 1 &&
+      (g.pA != nullptr || (KC ? g.sB1 != 0 : g.sA1 != 0)))
+    g.order = 1;
+  if constexpr (PHIKS_DL == 1 && VEC && !CPLX && BM >= 64 && BN >= 64) {
+    // direct-to-LDS operand loads: whole chunks of K only
+    if (g.K % PHIKS_DL_BK == 0)
+      return timed_launch(&gemm_f64_dl_kernel<BM, BN, WM, WN, KC, Epi>, (unsigned)g.total_tiles, st,
+                          flops, g, epi);
   }
-  (void)hipGetLastError();  // clear a stale error left by an unrelated earlier call
-  hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, WM, WN, KC, VEC, Epi, CPLX>),
-                     dim3((unsigned)g.total_tiles), dim3(256), 0, st, g, epi);
-  CHECK_LAUNCH();
-  if (ea && eb) {
-    HIP_OK(hipEventRecord(eb, st));
-    std::lock_guard<std::mutex> lk(g_timing_mu);
-    g_timed.push_back({ea, eb, 2.0 * g.M * (double)g.N * g.K * g.nb0 * (double)g.nb1});
-  }
-  return PHIKS_OK;
+  return timed_launch(&gemm_f64_kernel<BM, BN, WM, WN, KC, VEC, Epi, CPLX>, (unsigned)g.total_tiles,
+                      st, flops, g, epi);
 }
 
 template <bool KC, bool VEC, bool CPLX = false, class Epi>

@@ -32,24 +32,8 @@ int launch_grid(void (*kern)(GemmArgs, Epi), GemmArgs g, const Epi& epi, hipStre
     set_error("GEMM grid too large");
     return PHIKS_EINVAL;
   }
-  hipEvent_t ea = nullptr, eb = nullptr;
-  {
-    std::lock_guard<std::mutex> lk(g_timing_mu);
-    if (g_timing) {
-      ea = pooled_event();
-      eb = pooled_event();
-      if (ea && eb) HIP_OK(hipEventRecord(ea, st));
-    }
-  }
-  (void)hipGetLastError();
-  hipLaunchKernelGGL(kern, dim3((unsigned)g.total_tiles), dim3(256), 0, st, g, epi);
-  CHECK_LAUNCH();
-  if (ea && eb) {
-    HIP_OK(hipEventRecord(eb, st));
-    std::lock_guard<std::mutex> lk(g_timing_mu);
-    g_timed.push_back({ea, eb, 2.0 * g.M * (double)g.N * g.K * g.nb0 * (double)g.nb1});
-  }
-  return PHIKS_OK;
+  return timed_launch(kern, (unsigned)g.total_tiles, st,
+                      2.0 * g.M * (double)g.N * g.K * g.nb0 * (double)g.nb1, g, epi);
 }
 
 template <int BM, int BN, int WM, int WN, bool KC, bool VEC, class TA, class TC, class Epi>
