@@ -64,7 +64,8 @@ struct StepGemm {
 struct GroupedLaunch {
   StepKind kind;
   bool kc = false, vec = false, lincomb = false;
-  int tile = 0;          // 0: 64 x 64 (4 waves of 32 x 32), 1: 32 x 32 (4 waves of 16 x 16)
+  bool dl = false;       // direct-to-LDS kernel (16-byte operands, K a multiple of its chunk)
+  int tile = 0;          // class (BM x BN): 0 64x64, 1 32x32, 2 32x128, 3 128x32, 4 128x64
   size_t items_off = 0;  // bytes into the table: GroupItem[n] or CombineArgs[n]
   size_t first_off = 0;  // bytes into the table: int64_t first[n] (GEMM)
   int n = 0;
@@ -85,49 +86,73 @@ struct BatchSchedule {
     return off;
   }
 
-  static int tile_class(const GemmArgs& g) { return (g.M >= 48 && g.N >= 48) ? 0 : 1; }
+  // Tile classes (BM x BN): 64 x 64 when both sides reach 48.  The direct-to-LDS kernel
+  // also takes 128 x 64 tiles for the plain-store products of mode 1 (M >= 128), which
+  // halve the operand reads per flop, and streams skinny products (one side at
+  // most 32, the other long: the small modes of mixed-size problems, bound by HBM) through
+  // 32 x 128 or 128 x 32 tiles.  Everything else takes 32 x 32.
+  static constexpr int kClasses = 5;
+  static constexpr int kBM[kClasses] = {64, 32, 32, 128, 128};
+  static constexpr int kBN[kClasses] = {64, 32, 128, 32, 64};
+  static bool dl_ok(const GemmArgs& g, bool kc) {
+    return PHIKS_DL == 1 && g.K % PHIKS_DL_BK == 0 && vec_ok(g, kc, {});
+  }
+  static int tile_class(const GemmArgs& g, bool kc, bool dl, bool lincomb) {
+    // (measured on the batched workload: the squaring epilogue, which streams the pre-step
+    // tensors, and the products of modes > 1 run best with the larger count of 64 x 64
+    // work-groups)
+    if (dl && kc && !lincomb && g.M >= 128 && g.N >= 64) return 4;
+    if (g.M >= 48 && g.N >= 48) return 0;
+    if (dl && g.M <= 32 && g.N >= 96) return 2;
+    if (dl && g.N <= 32 && g.M >= 96) return 3;
+    return 1;
+  }
 
   void add_gemm_step(const std::vector<StepGemm>& items) {
-    // partition by (layout, tile class, 16-byte loads, epilogue)
+    // partition by (layout, tile class, 16-byte loads, direct-to-LDS, epilogue)
     for (int kc = 0; kc < 2; ++kc)
-      for (int tile = 0; tile < 2; ++tile)
+      for (int tile = 0; tile < kClasses; ++tile)
         for (int vec = 0; vec < 2; ++vec)
-          for (int lc = 0; lc < 2; ++lc) {
-            std::vector<GroupItem> part;
-            std::vector<int64_t> first;
-            int64_t total = 0;
-            double flops = 0.0;
-            for (const StepGemm& it : items) {
-              if (it.kc != (kc == 1) || it.lincomb != (lc == 1) || tile_class(it.g) != tile) continue;
-              if (vec_ok(it.g, it.kc, {}) != (vec == 1)) continue;
-              GroupItem gi;
-              gi.g = it.g;
-              const int bm = tile == 0 ? 64 : 32, bn = bm;
-              gi.g.tiles_m = (gi.g.M + bm - 1) / bm;
-              gi.g.tiles_n = (gi.g.N + bn - 1) / bn;
-              gi.g.total_tiles = (int64_t)gi.g.tiles_m * gi.g.tiles_n * gi.g.nb0 * gi.g.nb1;
-              if (gi.g.total_tiles <= 0) continue;
-              gi.Y = it.Y;
-              gi.YN = it.YN;
-              flops += 2.0 * gi.g.M * (double)gi.g.N * gi.g.K * gi.g.nb0 * (double)gi.g.nb1;
-              first.push_back(total);
-              total += gi.g.total_tiles;
-              part.push_back(gi);
+          for (int dl = 0; dl < 2; ++dl)
+            for (int lc = 0; lc < 2; ++lc) {
+              std::vector<GroupItem> part;
+              std::vector<int64_t> first;
+              int64_t total = 0;
+              double flops = 0.0;
+              for (const StepGemm& it : items) {
+                if (it.kc != (kc == 1) || it.lincomb != (lc == 1)) continue;
+                if (vec_ok(it.g, it.kc, {}) != (vec == 1)) continue;
+                const bool idl = dl_ok(it.g, it.kc);
+                if (idl != (dl == 1) || tile_class(it.g, it.kc, idl, it.lincomb) != tile) continue;
+                GroupItem gi;
+                gi.g = it.g;
+                const int bm = kBM[tile], bn = kBN[tile];
+                gi.g.tiles_m = (gi.g.M + bm - 1) / bm;
+                gi.g.tiles_n = (gi.g.N + bn - 1) / bn;
+                gi.g.total_tiles = (int64_t)gi.g.tiles_m * gi.g.tiles_n * gi.g.nb0 * gi.g.nb1;
+                if (gi.g.total_tiles <= 0) continue;
+                gi.Y = it.Y;
+                gi.YN = it.YN;
+                flops += 2.0 * gi.g.M * (double)gi.g.N * gi.g.K * gi.g.nb0 * (double)gi.g.nb1;
+                first.push_back(total);
+                total += gi.g.total_tiles;
+                part.push_back(gi);
+              }
+              if (part.empty()) continue;
+              GroupedLaunch L;
+              L.kind = StepKind::Gemm;
+              L.kc = kc == 1;
+              L.tile = tile;
+              L.vec = vec == 1;
+              L.dl = dl == 1;
+              L.lincomb = lc == 1;
+              L.n = (int)part.size();
+              L.total = total;
+              L.flops = flops;
+              L.items_off = put(part.data(), part.size() * sizeof(GroupItem));
+              L.first_off = put(first.data(), first.size() * sizeof(int64_t));
+              launches.push_back(L);
             }
-            if (part.empty()) continue;
-            GroupedLaunch L;
-            L.kind = StepKind::Gemm;
-            L.kc = kc == 1;
-            L.tile = tile;
-            L.vec = vec == 1;
-            L.lincomb = lc == 1;
-            L.n = (int)part.size();
-            L.total = total;
-            L.flops = flops;
-            L.items_off = put(part.data(), part.size() * sizeof(GroupItem));
-            L.first_off = put(first.data(), first.size() * sizeof(int64_t));
-            launches.push_back(L);
-          }
   }
 
   void add_combine_step(const std::vector<CombineArgs>& items) {
@@ -152,9 +177,35 @@ int launch_grouped_cfg(const GroupedLaunch& L, const char* dev, const Epi& epi, 
                       L.n, L.total, epi);
 }
 
+template <int BM, int BN, int WM, int WN, bool KC, class Epi>
+int launch_grouped_dl(const GroupedLaunch& L, const char* dev, const Epi& epi, hipStream_t st) {
+  if (L.total > 0x7fffffffLL) {
+    set_error("grouped GEMM grid too large");
+    return PHIKS_EINVAL;
+  }
+  return timed_launch(&gemm_f64_dl_grouped<BM, BN, WM, WN, KC, Epi>, (unsigned)L.total, st, L.flops,
+                      (const GroupItem*)(dev + L.items_off), (const int64_t*)(dev + L.first_off),
+                      L.n, L.total, epi);
+}
+
 template <bool KC, bool VEC, class Epi>
 int launch_grouped_tile(const GroupedLaunch& L, const char* dev, const Epi& epi, hipStream_t st) {
+  if constexpr (VEC && PHIKS_DL == 1) {
+    if (L.dl) {
+      switch (L.tile) {
+        case 0: return launch_grouped_dl<64, 64, 32, 32, KC>(L, dev, epi, st);
+        case 2: return launch_grouped_dl<32, 128, 32, 32, KC>(L, dev, epi, st);
+        case 3: return launch_grouped_dl<128, 32, 32, 32, KC>(L, dev, epi, st);
+        case 4: return launch_grouped_dl<128, 64, 64, 32, KC>(L, dev, epi, st);
+        default: return launch_grouped_dl<32, 32, 16, 16, KC>(L, dev, epi, st);
+      }
+    }
+  }
   if (L.tile == 0) return launch_grouped_cfg<64, 64, 32, 32, KC, VEC>(L, dev, epi, st);
+  if (L.tile != 1) {
+    set_error("grouped GEMM tile class needs the direct-to-LDS kernel");
+    return PHIKS_EINVAL;
+  }
   return launch_grouped_cfg<32, 32, 16, 16, KC, VEC>(L, dev, epi, st);
 }
 

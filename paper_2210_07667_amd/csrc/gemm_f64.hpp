@@ -428,17 +428,23 @@ struct GroupItem {
   int64_t YN;
 };
 
-template <int BM, int BN, int WM, int WN, bool B_KCONTIG, bool VEC, class Epi>
-__global__ void __launch_bounds__(256, VEC ? PHIKS_GEMM_MIN_WAVES : 2)
-    gemm_f64_grouped(const GroupItem* __restrict__ items, const int64_t* __restrict__ first,
-                     int nitems, int64_t total, Epi epi) {
-  const int64_t t = xcd_remap(blockIdx.x, total);
+// The item owning logical tile t: the last i with first[i] <= t (first[0] = 0).
+__device__ __forceinline__ int find_group_item(const int64_t* __restrict__ first, int nitems, int64_t t) {
   int lo = 0, hi = nitems - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
     if (first[mid] <= t) lo = mid;
     else hi = mid - 1;
   }
+  return lo;
+}
+
+template <int BM, int BN, int WM, int WN, bool B_KCONTIG, bool VEC, class Epi>
+__global__ void __launch_bounds__(256, VEC ? PHIKS_GEMM_MIN_WAVES : 2)
+    gemm_f64_grouped(const GroupItem* __restrict__ items, const int64_t* __restrict__ first,
+                     int nitems, int64_t total, Epi epi) {
+  const int64_t t = xcd_remap(blockIdx.x, total);
+  const int lo = find_group_item(first, nitems, t);
   const GroupItem& it = items[lo];
   if constexpr (std::is_same<Epi, EpiLinComb>::value) {
     Epi e = epi;

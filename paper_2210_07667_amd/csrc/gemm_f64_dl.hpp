@@ -83,8 +83,13 @@ __device__ __forceinline__ void gemm_f64_dl_tile(const GemmArgs& g, const Epi& e
   static_assert(WGM * WGN == 4, "4 waves per work-group");
   constexpr int FM = WM / 16, FN = WN / 16;
   constexpr int A_SLOTS = BM * KP, B_SLOTS = BN * KP;
-  static_assert(A_SLOTS % 256 == 0 && B_SLOTS % 256 == 0, "every thread fetches the same count");
-  constexpr int LA = A_SLOTS / 256, LB = B_SLOTS / 256;
+  // a tile of fewer than 256 slots is fetched by the first SLOTS/64 waves; the waves then
+  // issue different load counts, which the per-chunk wait only allows with two stages
+  // (every wait there is for all of a wave's loads)
+  static_assert(A_SLOTS % 64 == 0 && B_SLOTS % 64 == 0, "whole waves of slots");
+  static_assert(ST == 2 || (A_SLOTS % 256 == 0 && B_SLOTS % 256 == 0),
+                "every wave fetches the same count");
+  constexpr int LA = (A_SLOTS + 255) / 256, LB = (B_SLOTS + 255) / 256;
   static_assert(B_KCONTIG || BN / 2 >= 16, "column-pair swizzle needs BN >= 32");
 
   __shared__ __align__(16) double As[ST][2 * A_SLOTS];
@@ -103,13 +108,13 @@ __device__ __forceinline__ void gemm_f64_dl_tile(const GemmArgs& g, const Epi& e
   const PHIKS_GLOBAL double* bsrc[LB];
 #pragma unroll
   for (int i = 0; i < LA; ++i) {
-    const int s = i * 256 + tid;
+    const int s = min(i * 256 + tid, A_SLOTS - 1);   // (clamped slots are never issued)
     const int r = s / KP, kp = (s % KP) ^ swz_kp<KP>(s / KP);
     asrc[i] = t.A + (int64_t)min(m0 + r, g.M - 1) * g.lda + 2 * kp;
   }
 #pragma unroll
   for (int i = 0; i < LB; ++i) {
-    const int s = i * 256 + tid;
+    const int s = min(i * 256 + tid, B_SLOTS - 1);
     if constexpr (B_KCONTIG) {
       const int r = s / KP, kp = (s % KP) ^ swz_kp<KP>(s / KP);
       bsrc[i] = t.B + (int64_t)min(n0 + r, g.N - 1) * g.ldb + 2 * kp;
@@ -123,9 +128,13 @@ __device__ __forceinline__ void gemm_f64_dl_tile(const GemmArgs& g, const Epi& e
   auto issue = [&](int c) {
     const int st = c % ST;
 #pragma unroll
-    for (int i = 0; i < LA; ++i) dma16(asrc[i] + (int64_t)c * BK, &As[st][2 * (i * 256 + wave * 64)]);
+    for (int i = 0; i < LA; ++i)
+      if (A_SLOTS % 256 == 0 || i * 256 + wave * 64 < A_SLOTS)
+        dma16(asrc[i] + (int64_t)c * BK, &As[st][2 * (i * 256 + wave * 64)]);
 #pragma unroll
-    for (int i = 0; i < LB; ++i) dma16(bsrc[i] + (int64_t)c * bstep, &Bs[st][2 * (i * 256 + wave * 64)]);
+    for (int i = 0; i < LB; ++i)
+      if (B_SLOTS % 256 == 0 || i * 256 + wave * 64 < B_SLOTS)
+        dma16(bsrc[i] + (int64_t)c * bstep, &Bs[st][2 * (i * 256 + wave * 64)]);
   };
 
   dbl4 acc[FM][FN];
@@ -195,6 +204,24 @@ template <int BM, int BN, int WM, int WN, bool B_KCONTIG, class Epi>
 __global__ void __launch_bounds__(256, dl_min_waves<Epi>()) gemm_f64_dl_kernel(GemmArgs g, Epi epi) {
   gemm_f64_dl_tile<BM, BN, WM, WN, B_KCONTIG, Epi, PHIKS_DL_BK, PHIKS_DL_ST>(
       g, epi, xcd_remap(blockIdx.x, g.total_tiles));
+}
+
+// Grouped launch (many independent GEMMs of one kind in one grid; see gemm_f64_grouped).
+template <int BM, int BN, int WM, int WN, bool B_KCONTIG, class Epi>
+__global__ void __launch_bounds__(256, dl_min_waves<Epi>())
+    gemm_f64_dl_grouped(const GroupItem* __restrict__ items, const int64_t* __restrict__ first,
+                        int nitems, int64_t total, Epi epi) {
+  const int64_t t = xcd_remap(blockIdx.x, total);
+  const int i = find_group_item(first, nitems, t);
+  const GroupItem& it = items[i];
+  if constexpr (std::is_same<Epi, EpiLinComb>::value) {
+    Epi e = epi;
+    e.Y = it.Y;
+    e.N = it.YN;
+    gemm_f64_dl_tile<BM, BN, WM, WN, B_KCONTIG, Epi, PHIKS_DL_BK, PHIKS_DL_ST>(it.g, e, t - first[i]);
+  } else {
+    gemm_f64_dl_tile<BM, BN, WM, WN, B_KCONTIG, Epi, PHIKS_DL_BK, PHIKS_DL_ST>(it.g, epi, t - first[i]);
+  }
 }
 
 }  // namespace phiks
