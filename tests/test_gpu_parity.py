@@ -86,6 +86,9 @@ SV_CASES = [
     # d = 6 as in the validation of Section 4.1 (real part of its operators)
     ("val", [8, 8, 8, 8, 8, 8], 1.0, 4, 1),
     ("val", [11, 10, 9, 8, 9, 10], 1.0, 3, 2),
+    # direct-to-LDS kernel with ragged tiles: every mode has K a multiple of 8 and
+    # 128 x 64 or 64 x 128 tiles that overhang both M and N (200 = 128 + 72, 88 = 64 + 24)
+    ("adr", [200, 88, 136], 1e-3, 4, 1),
 ]
 
 
@@ -136,6 +139,8 @@ LC_CASES = [
     ([5, 4, 3], 2e-2, 4, 3),
     ([31, 18], 5e-3, 2, 2),
     ([12, 11, 10], 1e-2, 5, 2),
+    # p-batched node Tuckers on the direct-to-LDS kernel, ragged 128 x 64 tiles
+    ([96, 72, 104], 5e-3, 3, 1),
 ]
 
 
