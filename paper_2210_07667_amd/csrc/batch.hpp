@@ -122,7 +122,7 @@ struct BatchSchedule {
               for (const StepGemm& it : items) {
                 if (it.kc != (kc == 1) || it.lincomb != (lc == 1)) continue;
                 if (vec_ok(it.g, it.kc, {}) != (vec == 1)) continue;
-                const bool idl = dl_ok(it.g, it.kc);
+                const bool idl = dl_ok(it.g, it.kc) && (!it.lincomb || lincomb_dl_ok(it.g, it.Y, it.YN));
                 if (idl != (dl == 1) || tile_class(it.g, it.kc, idl, it.lincomb) != tile) continue;
                 GroupItem gi;
                 gi.g = it.g;

@@ -223,7 +223,7 @@ __device__ __forceinline__ void store_tile_f64(dbl4 (&acc)[FM][FN], const GemmAr
 #pragma unroll
           for (int j = 0; j < FN; ++j)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) acc[i0 + i][j][r] += ck * y[i][j][r];
+            for (int r = 0; r < 4; ++r) acc[i0 + i][j][r] = __builtin_fma(ck, y[i][j][r], acc[i0 + i][j][r]);
       }
     }
 #pragma unroll

@@ -74,6 +74,114 @@ __device__ __forceinline__ void dma16(const PHIKS_GLOBAL double* src, double* ld
   asm volatile("global_load_lds_dwordx4 %0, off" : : "v"(src), "{m0}"(lds) : "memory");
 }
 
+// Squaring epilogue out = a_l acc + sum_{k <= l} c_lk Y_k with the pre-step tensors Y_k
+// streamed through LDS by the same 16-byte DMA as the operands, instead of register
+// loads whose latency the work-group would wait out round after round.  Slice i of Y_k
+// (round k * FM + i) holds fragment row i of every wave: WGM * 16 rows of BN columns,
+// rows (rho / 16) * WM + i * 16 + rho % 16 of the tile, stored as column pairs with
+// slot rho * BN/2 + (cp ^ 8 (rho & 1)) (rows rho and rho + 1 of a 32-lane read land on
+// different bank halves).  YB buffers, DMA YB - 1 rounds ahead.  Per element the
+// arithmetic is the register epilogue's (acc *= a_l, then one fma per k in k order).
+// Needs 16-byte column pairs: even ldc, N, output strides and tensor stride, aligned Y
+// (lincomb_dl_ok, checked by the launchers: launches that fail it take gemm_f64_kernel).
+inline bool lincomb_dl_ok(const GemmArgs& g, const double* Y, int64_t YN) {
+  return ((g.ldc | (int64_t)g.N | g.sC0 | g.sC1 | YN) & 1) == 0 && ((uintptr_t)Y & 15) == 0 &&
+         (g.pC == nullptr);
+}
+
+template <int BM, int BN, int WM, int WN, int YB, int FM, int FN>
+__device__ __forceinline__ void lincomb_lds_epilogue(dbl4 (&acc)[FM][FN], const GemmArgs& g,
+                                                     const EpiLinComb& epi, const TileOperands& t,
+                                                     double* lds, int m0, int n0, int wave, int tid) {
+  constexpr int WGM = BM / WM, WGN = BN / WN;
+  constexpr int ROWS = WGM * 16, CP = BN / 2;
+  constexpr int YSLICE = ROWS * BN;                     // doubles
+  constexpr int SLOTS = ROWS * CP, LY = SLOTS / 256;
+  static_assert(SLOTS % 256 == 0, "every thread fetches the same count");
+  static_assert(CP >= 16, "column-pair swizzle needs BN >= 32");
+  const int lane = tid & 63, lr = lane & 15, lk = lane >> 4;
+  const int wgm = wave / WGN, wn = (wave % WGN) * WN;
+  const int l = (int)t.z1;
+  const int rounds = (l + 1) * FM;
+
+  // this thread's slots: slice-relative tile row and column (clamped in range)
+  int64_t off[LY];
+#pragma unroll
+  for (int q = 0; q < LY; ++q) {
+    const int s = q * 256 + tid;
+    const int rho = s / CP, cp = (s % CP) ^ ((rho & 1) << 3);
+    const int row = (rho / 16) * WM + rho % 16;         // + i * 16 per slice
+    off[q] = (int64_t)row * g.ldc + min(n0 + 2 * cp, g.N - 2);
+  }
+  const PHIKS_GLOBAL double* Y0 = gptr(epi.Y) + t.cbase - (int64_t)l * epi.N;   // Y_0 at this tile
+  auto issue = [&](int r) {
+    const int k = r / FM, i = r % FM;
+    const PHIKS_GLOBAL double* Yk = Y0 + (int64_t)k * epi.N;
+    double* buf = lds + (r % YB) * YSLICE;
+#pragma unroll
+    for (int q = 0; q < LY; ++q) {
+      const int s = q * 256 + tid;
+      const int rho = s / CP;
+      const int grow = min(m0 + (rho / 16) * WM + i * 16 + rho % 16, g.M - 1);
+      dma16(Yk + off[q] + (int64_t)(grow - ((rho / 16) * WM + rho % 16)) * g.ldc,
+            buf + 2 * (q * 256 + wave * 64));
+    }
+  };
+
+  // every wave is done with the operand ring before its memory is overwritten
+  wait_lgkmcnt0();
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+#pragma unroll
+  for (int r = 0; r < YB - 1; ++r)
+    if (r < rounds) issue(r);
+  const double al = epi.a[l];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) acc[i][j] *= al;
+
+  for (int k = 0; k <= l; ++k) {
+    const double ck = epi.c[l][k];
+#pragma unroll
+    for (int i = 0; i < FM; ++i) {
+      const int r = k * FM + i;
+      // round r has landed once at most the later rounds' loads are outstanding
+      if (r + YB - 2 < rounds) wait_vmcnt<(YB - 2) * LY>();
+      else wait_vmcnt<0>();
+      wait_lgkmcnt0();
+      asm volatile("" ::: "memory");
+      __builtin_amdgcn_s_barrier();
+      asm volatile("" ::: "memory");
+      if (r + YB - 1 < rounds) issue(r + YB - 1);     // into the buffer round r - 1 used
+      const double* buf = lds + (r % YB) * YSLICE;
+#pragma unroll
+      for (int j = 0; j < FN; ++j) {
+        const int c = wn + j * 16 + lr;
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+          const int rho = wgm * 16 + lk + 4 * rr;
+          const double y = buf[2 * (rho * CP + ((c >> 1) ^ ((rho & 1) << 3))) + (c & 1)];
+          acc[i][j][rr] = __builtin_fma(ck, y, acc[i][j][rr]);
+        }
+      }
+    }
+  }
+
+  const int mw = m0 + wgm * WM, nw = n0 + wn;
+  const int ml = mw + lk, nl = nw + lr;
+  const int64_t base = t.cbase + (int64_t)ml * g.ldc + nl;
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr)
+        if ((ml + i * 16 + 4 * rr < g.M) & (nl + j * 16 < g.N))
+          t.Cb[base + (int64_t)(i * 16 + 4 * rr) * g.ldc + j * 16] = acc[i][j][rr];
+}
+
 template <int BM, int BN, int WM, int WN, bool B_KCONTIG, class Epi, int BK, int ST>
 __device__ __forceinline__ void gemm_f64_dl_tile(const GemmArgs& g, const Epi& epi, int64_t rest) {
   static_assert(BK == 8 || BK == 16, "chunk of 8 or 16 k");
@@ -92,8 +200,17 @@ __device__ __forceinline__ void gemm_f64_dl_tile(const GemmArgs& g, const Epi& e
   constexpr int LA = (A_SLOTS + 255) / 256, LB = (B_SLOTS + 255) / 256;
   static_assert(B_KCONTIG || BN / 2 >= 16, "column-pair swizzle needs BN >= 32");
 
-  __shared__ __align__(16) double As[ST][2 * A_SLOTS];
-  __shared__ __align__(16) double Bs[ST][2 * B_SLOTS];
+  // LDS: the ST-stage operand ring; the squaring epilogue reuses the same memory for its
+  // YB slice buffers once the K loop is done
+  constexpr bool LC = std::is_same<Epi, EpiLinComb>::value;
+  constexpr int STAGE = 2 * (A_SLOTS + B_SLOTS);        // doubles per stage
+  // doubles per Y slice; buffers: three for 128 x 64 tiles (register-bound to 3 waves per
+  // SIMD anyway), two for smaller tiles, whose occupancy is bound by LDS
+  constexpr int YSLICE = WGM * 16 * BN, YB = BM * BN >= 8192 ? 3 : 2;
+  constexpr int LDS_DBL = (LC && YB * YSLICE > ST * STAGE) ? YB * YSLICE : ST * STAGE;
+  __shared__ __align__(16) double lds[LDS_DBL];
+  auto As = [&](int st) { return lds + st * STAGE; };
+  auto Bs = [&](int st) { return lds + st * STAGE + 2 * A_SLOTS; };
 
   const TileOperands t = tile_operands<B_KCONTIG>(g, rest);
   const int m0 = t.tm * BM, n0 = t.tn * BN;
@@ -130,11 +247,11 @@ __device__ __forceinline__ void gemm_f64_dl_tile(const GemmArgs& g, const Epi& e
 #pragma unroll
     for (int i = 0; i < LA; ++i)
       if (A_SLOTS % 256 == 0 || i * 256 + wave * 64 < A_SLOTS)
-        dma16(asrc[i] + (int64_t)c * BK, &As[st][2 * (i * 256 + wave * 64)]);
+        dma16(asrc[i] + (int64_t)c * BK, As(st) + 2 * (i * 256 + wave * 64));
 #pragma unroll
     for (int i = 0; i < LB; ++i)
       if (B_SLOTS % 256 == 0 || i * 256 + wave * 64 < B_SLOTS)
-        dma16(bsrc[i] + (int64_t)c * bstep, &Bs[st][2 * (i * 256 + wave * 64)]);
+        dma16(bsrc[i] + (int64_t)c * bstep, Bs(st) + 2 * (i * 256 + wave * 64));
   };
 
   dbl4 acc[FM][FN];
@@ -160,8 +277,8 @@ __device__ __forceinline__ void gemm_f64_dl_tile(const GemmArgs& g, const Epi& e
     __builtin_amdgcn_s_barrier();
     asm volatile("" ::: "memory");
     if (c + ST - 1 < nchunks) issue(c + ST - 1);   // into the stage chunk c - 1 used
-    const double* as = As[c % ST];
-    const double* bs = Bs[c % ST];
+    const double* as = As(c % ST);
+    const double* bs = Bs(c % ST);
 #pragma unroll
     for (int j = 0; j < BK / 8; ++j) {
       const int kp = 4 * j + lk;
@@ -192,7 +309,11 @@ __device__ __forceinline__ void gemm_f64_dl_tile(const GemmArgs& g, const Epi& e
     }
   }
 
-  store_tile_f64<FM, FN>(acc, g, epi, t.Cb, t.cbase, t.z1, m0 + wm, n0 + wn, lr, lk);
+  if constexpr (LC) {
+    lincomb_lds_epilogue<BM, BN, WM, WN, YB>(acc, g, epi, t, lds, m0, n0, wave, tid);
+  } else {
+    store_tile_f64<FM, FN>(acc, g, epi, t.Cb, t.cbase, t.z1, m0 + wm, n0 + wn, lr, lk);
+  }
 }
 
 template <class Epi>

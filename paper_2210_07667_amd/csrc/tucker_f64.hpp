@@ -74,8 +74,11 @@ int launch_cfg(GemmArgs g, const Epi& epi, hipStream_t st) {
       (g.pA != nullptr || (KC ? g.sB1 != 0 : g.sA1 != 0)))
     g.order = 1;
   if constexpr (PHIKS_DL == 1 && VEC && !CPLX && BM >= 64 && BN >= 64) {
-    // direct-to-LDS operand loads: whole chunks of K only
-    if (g.K % PHIKS_DL_BK == 0)
+    // direct-to-LDS operand loads: whole chunks of K only (and, for the squaring
+    // epilogue, pre-step tensors it can stream in 16-byte pairs)
+    bool ok = g.K % PHIKS_DL_BK == 0;
+    if constexpr (std::is_same<Epi, EpiLinComb>::value) ok = ok && lincomb_dl_ok(g, epi.Y, epi.N);
+    if (ok)
       return timed_launch(&gemm_f64_dl_kernel<BM, BN, WM, WN, KC, Epi>, (unsigned)g.total_tiles, st,
                           flops, g, epi);
   }
@@ -85,7 +88,11 @@ int launch_cfg(GemmArgs g, const Epi& epi, hipStream_t st) {
 
 template <bool KC, bool VEC, bool CPLX = false, class Epi>
 int launch_tile(const GemmArgs& g, const Epi& epi, hipStream_t st) {
-  switch (pick_tile(g)) {
+  Tile tile = pick_tile(g);
+  // the squaring epilogue stages slices of 16 rows x BN of the pre-step tensors: 128
+  // columns would take 96 KB of LDS, so it keeps 64-column tiles
+  if (std::is_same<Epi, EpiLinComb>::value && tile == Tile::T64x128) tile = Tile::T64x64;
+  switch (tile) {
 #if PHIKS_BIG_TILE == 1
     case Tile::T128x128: return launch_cfg<128, 128, 64, 64, KC, VEC, CPLX>(g, epi, st);
 #endif
