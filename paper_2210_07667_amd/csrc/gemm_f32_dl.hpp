@@ -1,0 +1,156 @@
+// FP32 MFMA mu-mode product with direct-to-LDS operand loads, for the products whose
+// operands are both FP32 in memory (modes > 1 of a mixed-precision Tucker chain; the
+// first mode reads the FP64 vectors and converts them, so it keeps gemm_f32_kernel).
+// Same products, tile order and epilogues as gemm_f32_kernel; the operand path is the
+// one of gemm_f64_dl.hpp with 16-byte slots holding four floats:
+//  * k-contiguous operand, rows r < R, k < 16 per chunk: slot of (r, k quad kq) is
+//    r*4 + (kq ^ ((r / 4) mod 4)).  Lane group lk = l >> 4 reads quad lk of its row
+//    (ds_read_b128) and feeds four MFMA steps: step h takes k = 4 lk + h, for both
+//    operands.
+//  * n-contiguous operand, k < 16, columns c < BN: slot of (k, column quad cq) is
+//    k*BN/4 + (cq ^ 4 ((k / 4) mod 4)); fragment reads are 4 bytes, the four rows of one
+//    read land on four different 64-byte bank groups.
+// MFMA v_mfma_f32_16x16x4_f32: A[m0 + (l & 15)][k(l >> 4)], B[k(l >> 4)][n0 + (l & 15)],
+// c[r] = C[m0 + 4 (l >> 4) + r][n0 + (l & 15)].  K must be a multiple of 16, the leading
+// dimensions and strides multiples of 4 floats, N too for an n-contiguous B (the
+// launcher checks); ragged M/N fetch clamped in-range rows or columns.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <type_traits>
+
+#include "gemm_f32.hpp"
+#include "gemm_f64_dl.hpp"
+
+namespace phiks {
+
+#ifndef PHIKS_F32DL_MIN_WAVES
+#define PHIKS_F32DL_MIN_WAVES 4
+#endif
+
+__device__ __forceinline__ int swz_kq(int r) { return (r >> 2) & 3; }
+__device__ __forceinline__ int swz_nq(int k) { return ((k >> 2) & 3) << 2; }
+
+template <int BM, int BN, int WM, int WN, bool B_KCONTIG, class TC, class Epi>
+__device__ __forceinline__ void gemm_f32_dl_tile(const GemmArgs& g, const Epi& epi, int64_t rest) {
+  constexpr int BK = 16;                 // floats of k per chunk
+  constexpr int KQ = BK / 4;             // 16-byte slots per k-contiguous row
+  constexpr int WGM = BM / WM, WGN = BN / WN;
+  static_assert(WGM * WGN == 4, "4 waves per work-group");
+  constexpr int FM = WM / 16, FN = WN / 16;
+  constexpr int A_SLOTS = BM * KQ, B_SLOTS = BN * KQ;
+  static_assert(A_SLOTS % 256 == 0 && B_SLOTS % 256 == 0, "every thread fetches the same count");
+  static_assert(B_KCONTIG || BN / 4 >= 16, "column-quad swizzle needs BN >= 64");
+  constexpr int LA = A_SLOTS / 256, LB = B_SLOTS / 256;
+  constexpr int STAGE = 4 * (A_SLOTS + B_SLOTS);   // floats per stage
+
+  __shared__ __align__(16) float lds[2 * STAGE];
+
+  const TileCoords tc = tile_coords<B_KCONTIG>(g, rest);
+  const PHIKS_GLOBAL float* A =
+      (const PHIKS_GLOBAL float*)gptr(g.A) + tc.z0 * g.sA0 + tc.z1 * g.sA1;
+  const PHIKS_GLOBAL float* B =
+      (const PHIKS_GLOBAL float*)gptr(g.B) + tc.z0 * g.sB0 + tc.z1 * g.sB1;
+  TC* Cb = reinterpret_cast<TC*>(g.C);
+  const int64_t cbase = tc.z0 * g.sC0 + tc.z1 * g.sC1;
+  const int m0 = tc.tm * BM, n0 = tc.tn * BN;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wm = (wave / WGN) * WM, wn = (wave % WGN) * WN;
+  const int lr = lane & 15, lk = lane >> 4;
+
+  const PHIKS_GLOBAL float* asrc[LA];
+  const PHIKS_GLOBAL float* bsrc[LB];
+#pragma unroll
+  for (int i = 0; i < LA; ++i) {
+    const int s = i * 256 + tid;
+    const int r = s / KQ, kq = (s % KQ) ^ swz_kq(s / KQ);
+    asrc[i] = A + (int64_t)min(m0 + r, g.M - 1) * g.lda + 4 * kq;
+  }
+#pragma unroll
+  for (int i = 0; i < LB; ++i) {
+    const int s = i * 256 + tid;
+    if constexpr (B_KCONTIG) {
+      const int r = s / KQ, kq = (s % KQ) ^ swz_kq(s / KQ);
+      bsrc[i] = B + (int64_t)min(n0 + r, g.N - 1) * g.ldb + 4 * kq;
+    } else {
+      const int k = s / (BN / 4), cq = (s % (BN / 4)) ^ swz_nq(s / (BN / 4));
+      bsrc[i] = B + (int64_t)k * g.ldb + min(n0 + 4 * cq, g.N - 4);
+    }
+  }
+  const int64_t bstep = B_KCONTIG ? BK : (int64_t)BK * g.ldb;
+
+  auto issue = [&](int c) {
+    float* st = lds + (c & 1) * STAGE;
+#pragma unroll
+    for (int i = 0; i < LA; ++i)
+      dma16(reinterpret_cast<const PHIKS_GLOBAL double*>(asrc[i] + (int64_t)c * BK),
+            reinterpret_cast<double*>(st + 4 * (i * 256 + wave * 64)));
+#pragma unroll
+    for (int i = 0; i < LB; ++i)
+      dma16(reinterpret_cast<const PHIKS_GLOBAL double*>(bsrc[i] + (int64_t)c * bstep),
+            reinterpret_cast<double*>(st + 4 * A_SLOTS + 4 * (i * 256 + wave * 64)));
+  };
+
+  flt4 acc[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) acc[i][j] = flt4{0.f, 0.f, 0.f, 0.f};
+
+  const int nchunks = g.K / BK;
+  issue(0);
+  for (int c = 0; c < nchunks; ++c) {
+    wait_vmcnt<0>();
+    wait_lgkmcnt0();
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();   // chunk c visible; every wave is done with chunk c - 1
+    asm volatile("" ::: "memory");
+    if (c + 1 < nchunks) issue(c + 1);
+    const float* as = lds + (c & 1) * STAGE;
+    const float* bs = as + 4 * A_SLOTS;
+    flt4 fa[FM], fb[FN];
+#pragma unroll
+    for (int i = 0; i < FM; ++i) {
+      const int r = wm + i * 16 + lr;
+      fa[i] = *reinterpret_cast<const flt4*>(as + 4 * (r * KQ + (lk ^ swz_kq(r))));
+    }
+#pragma unroll
+    for (int jj = 0; jj < FN; ++jj) {
+      const int n = wn + jj * 16 + lr;
+      if constexpr (B_KCONTIG) {
+        fb[jj] = *reinterpret_cast<const flt4*>(bs + 4 * (n * KQ + (lk ^ swz_kq(n))));
+      } else {
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+          const int k = 4 * lk + h;
+          fb[jj][h] = bs[4 * (k * (BN / 4) + ((n >> 2) ^ swz_nq(k))) + (n & 3)];
+        }
+      }
+    }
+#pragma unroll
+    for (int h = 0; h < 4; ++h)
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int jj = 0; jj < FN; ++jj)
+          acc[i][jj] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[i][h], fb[jj][h], acc[i][jj], 0, 0, 0);
+  }
+
+  store_acc_tile<FM, FN, TC>(acc, g, epi, Cb, cbase, tc.z1, m0 + wm, n0 + wn, lr, lk);
+}
+
+template <class Epi>
+constexpr int f32dl_min_waves() {
+  return std::is_same<Epi, EpiLinComb>::value ? 3 : PHIKS_F32DL_MIN_WAVES;
+}
+
+template <int BM, int BN, int WM, int WN, bool B_KCONTIG, class TC, class Epi>
+__global__ void __launch_bounds__(256, f32dl_min_waves<Epi>()) gemm_f32_dl_kernel(GemmArgs g, Epi epi) {
+  gemm_f32_dl_tile<BM, BN, WM, WN, B_KCONTIG, TC, Epi>(g, epi, xcd_remap(blockIdx.x, g.total_tiles));
+}
+
+}  // namespace phiks

@@ -132,51 +132,66 @@ struct TileOperands {
   int tm, tn;
 };
 
+// Tile and batch coordinates of logical tile `rest` (tile order above).
+struct TileCoords {
+  int tm, tn;
+  int64_t z0, z1;
+};
+
 template <bool B_KCONTIG>
-__device__ __forceinline__ TileOperands tile_operands(const GemmArgs& g, int64_t rest) {
-  TileOperands t;
-  int64_t z0;
+__device__ __forceinline__ TileCoords tile_coords(const GemmArgs& g, int64_t rest) {
+  TileCoords c;
   if (g.order == 1) {
     // the tiles sharing an operand block run back to back: mode 1 the n tiles of one
     // row block (one block of the tensor), modes > 1 the m tiles of one column block
     if constexpr (B_KCONTIG) {
-      t.tn = (int)(rest % g.tiles_n);
+      c.tn = (int)(rest % g.tiles_n);
       rest /= g.tiles_n;
-      t.tm = (int)(rest % g.tiles_m);
+      c.tm = (int)(rest % g.tiles_m);
       rest /= g.tiles_m;
     } else {
-      t.tm = (int)(rest % g.tiles_m);
+      c.tm = (int)(rest % g.tiles_m);
       rest /= g.tiles_m;
-      t.tn = (int)(rest % g.tiles_n);
+      c.tn = (int)(rest % g.tiles_n);
       rest /= g.tiles_n;
     }
-    z0 = rest % g.nb0;
-    t.z1 = rest / g.nb0;
+    c.z0 = rest % g.nb0;
+    c.z1 = rest / g.nb0;
   } else if constexpr (B_KCONTIG) {
-    t.tn = (int)(rest % g.tiles_n);
+    c.tn = (int)(rest % g.tiles_n);
     rest /= g.tiles_n;
-    t.z1 = rest % g.nb1;
+    c.z1 = rest % g.nb1;
     rest /= g.nb1;
-    t.tm = (int)(rest % g.tiles_m);
-    z0 = rest / g.tiles_m;
+    c.tm = (int)(rest % g.tiles_m);
+    c.z0 = rest / g.tiles_m;
   } else {
-    t.z1 = rest % g.nb1;
+    c.z1 = rest % g.nb1;
     rest /= g.nb1;
-    t.tm = (int)(rest % g.tiles_m);
+    c.tm = (int)(rest % g.tiles_m);
     rest /= g.tiles_m;
-    t.tn = (int)(rest % g.tiles_n);
-    z0 = rest / g.tiles_n;
+    c.tn = (int)(rest % g.tiles_n);
+    c.z0 = rest / g.tiles_n;
   }
+  return c;
+}
+
+template <bool B_KCONTIG>
+__device__ __forceinline__ TileOperands tile_operands(const GemmArgs& g, int64_t rest) {
+  const TileCoords c = tile_coords<B_KCONTIG>(g, rest);
+  TileOperands t;
+  t.tm = c.tm;
+  t.tn = c.tn;
+  t.z1 = c.z1;
   if (g.pA != nullptr) {
-    t.A = gptr(g.pA[t.z1]);
-    t.B = gptr(g.pB[t.z1]);
-    t.Cb = gptr(g.pC[t.z1]);
+    t.A = gptr(g.pA[c.z1]);
+    t.B = gptr(g.pB[c.z1]);
+    t.Cb = gptr(g.pC[c.z1]);
     t.cbase = 0;
   } else {
-    t.A = gptr(g.A) + z0 * g.sA0 + t.z1 * g.sA1;
-    t.B = gptr(g.B) + z0 * g.sB0 + t.z1 * g.sB1;
+    t.A = gptr(g.A) + c.z0 * g.sA0 + c.z1 * g.sA1;
+    t.B = gptr(g.B) + c.z0 * g.sB0 + c.z1 * g.sB1;
     t.Cb = gptr(g.C);
-    t.cbase = z0 * g.sC0 + t.z1 * g.sC1;
+    t.cbase = c.z0 * g.sC0 + c.z1 * g.sC1;
   }
   return t;
 }

@@ -6,6 +6,7 @@
 
 #include "gemm_bf16x3.hpp"
 #include "gemm_f32.hpp"
+#include "gemm_f32_dl.hpp"
 #include "tucker_f64.hpp"
 
 namespace {
@@ -38,6 +39,14 @@ int launch_grid(void (*kern)(GemmArgs, Epi), GemmArgs g, const Epi& epi, hipStre
 
 template <int BM, int BN, int WM, int WN, bool KC, bool VEC, class TA, class TC, class Epi>
 int launch_cfg32(const GemmArgs& g, const Epi& epi, hipStream_t st) {
+  if constexpr (PHIKS_DL == 1 && VEC && std::is_same<TA, float>::value && BM >= 64 && BN >= 64 &&
+                !std::is_same<Epi, EpiLinComb>::value) {
+    // FP32 operands both ways: direct-to-LDS loads (whole 16-float chunks of K).  The
+    // squaring epilogue, which reads its FP64 pre-step tensors through registers, runs
+    // faster on gemm_f32_kernel (measured 519 against 574 us per 256^3 launch).
+    if (g.K % 16 == 0 && g.pA == nullptr)
+      return launch_grid<BM, BN>(&gemm_f32_dl_kernel<BM, BN, WM, WN, KC, TC, Epi>, g, epi, st);
+  }
   return launch_grid<BM, BN>(&gemm_f32_kernel<BM, BN, WM, WN, KC, VEC, TA, TC, Epi>, g, epi, st);
 }
 
