@@ -216,8 +216,8 @@ def serving_section(ph, rates=(100, 300, 600), duration=1.5):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true",
@@ -267,10 +267,10 @@ def main():
         log(f"[bench] warmup {i + 1}/{args.warmup}")
     ph.synchronize()
 
-    # HIP events on every mu-mode launch of a sample of the timed steps (every fifth and
+    # HIP events on every mu-mode launch of a sample of the timed steps (every tenth and
     # the last): a timestamped dispatch costs about 9 us of idle time after the kernel,
     # so events on every step would slow the steps they measure
-    sampled = {i for i in range(args.steps) if i % 5 == 4 or i == args.steps - 1}
+    sampled = {i for i in range(args.steps) if i % 10 == 9 or i == args.steps - 1}
     ph.phiks_kernel_timing_read()          # clear
     ph.synchronize()
     t0 = time.perf_counter()
