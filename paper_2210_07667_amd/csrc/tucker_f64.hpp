@@ -38,7 +38,8 @@ Tile pick_tile(const GemmArgs& g) {
   if (g.M >= 128 && g.N >= 64 && tiles_for(g, 128, 64) >= kCUs) return Tile::T128x64;
   if (g.M >= 64 && g.N >= 128 && tiles_for(g, 64, 128) >= kCUs) return Tile::T64x128;
   if (g.M >= 64 && g.N >= 64 && tiles_for(g, 64, 64) >= kCUs) return Tile::T64x64;
-  if (g.M >= 96 && g.N >= 48 && tiles_for(g, 32, 32) < kCUs) return Tile::T64x64;
+  // products too small to fill the chip take the smallest tiles: more work-groups in
+  // flight (a work-group alone on its CU is bound by one wave per SIMD)
   return Tile::T32x32;
 }
 
@@ -73,7 +74,7 @@ int launch_cfg(GemmArgs g, const Epi& epi, hipStream_t st) {
   if (!std::is_same<Epi, EpiLinComb>::value && g.nb1 > 1 &&
       (g.pA != nullptr || (KC ? g.sB1 != 0 : g.sA1 != 0)))
     g.order = 1;
-  if constexpr (PHIKS_DL == 1 && VEC && !CPLX && BM >= 64 && BN >= 64) {
+  if constexpr (PHIKS_DL == 1 && VEC && !CPLX) {
     // direct-to-LDS operand loads: whole chunks of K only (and, for the squaring
     // epilogue, pre-step tensors it can stream in 16-byte pairs)
     bool ok = g.K % PHIKS_DL_BK == 0;
