@@ -77,12 +77,14 @@ struct Row8 {
 
   __device__ __forceinline__ void load(const T* __restrict__ P, int64_t ld, int row, int rows,
                                        int gk, int K) {
+    // (bitwise predicates and selected offsets: short-circuit conditions make the
+    // compiler branch around each load)
     const bool rok = row < rows;
     const int64_t base = rok ? (int64_t)row * ld : 0;
     if constexpr (VEC) {
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
-        const bool ok = rok && (gk + 4 * h < K);
+        const bool ok = rok & (gk + 4 * h < K);
         const T* q = P + (ok ? base + gk + 4 * h : 0);
         if constexpr (kF64) {
           v[2 * h] = *reinterpret_cast<const dbl2*>(q);
@@ -93,7 +95,10 @@ struct Row8 {
       }
     } else {
 #pragma unroll
-      for (int t = 0; t < 8; ++t) v[t] = P[(rok && gk + t < K) ? base + gk + t : 0];
+      for (int t = 0; t < 8; ++t) {
+        const bool ok = rok & (gk + t < K);
+        v[t] = P[ok ? base + gk + t : 0];
+      }
     }
   }
 
@@ -102,7 +107,7 @@ struct Row8 {
     if constexpr (VEC) {
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
-        const bool ok = rok && (gk + 4 * h < K);
+        const bool ok = rok & (gk + 4 * h < K);
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
           float e;
@@ -113,7 +118,7 @@ struct Row8 {
       }
     } else {
 #pragma unroll
-      for (int t = 0; t < 8; ++t) x[t] = (rok && gk + t < K) ? (float)v[t] : 0.f;
+      for (int t = 0; t < 8; ++t) x[t] = (rok & (gk + t < K)) ? (float)v[t] : 0.f;
     }
   }
 };
@@ -188,9 +193,14 @@ __global__ void __launch_bounds__(256, PHIKS_BF_MIN_WAVES) gemm_bf16x3_kernel(Ge
       } else {
         // column n of eight consecutive k rows; lanes take consecutive n (coalesced)
         const int gn = n0 + e % BN, gk = k0 + 8 * (e / BN);
+        const bool nok = gn < g.N;
+        const int64_t off0 = (int64_t)gk * g.ldb + gn;
 #pragma unroll
-        for (int t = 0; t < 8; ++t)
-          rb[i].v[t] = B[(gn < g.N && gk + t < g.K) ? (int64_t)(gk + t) * g.ldb + gn : 0];
+        for (int t = 0; t < 8; ++t) {
+          const bool ok = nok & (gk + t < g.K);
+          const int64_t off = off0 + (int64_t)t * g.ldb;
+          rb[i].v[t] = B[ok ? off : 0];
+        }
       }
     }
   };
@@ -220,7 +230,7 @@ __global__ void __launch_bounds__(256, PHIKS_BF_MIN_WAVES) gemm_bf16x3_kernel(Ge
         c = (e / BN) ^ swz_bf<G>(r);
         const int gn = n0 + r, gk = k0 + 8 * (e / BN);
 #pragma unroll
-        for (int t = 0; t < 8; ++t) x[t] = (gn < g.N && gk + t < g.K) ? rb[i].v[t] : 0.f;
+        for (int t = 0; t < 8; ++t) x[t] = ((gn < g.N) & (gk + t < g.K)) ? rb[i].v[t] : 0.f;
       }
       u32x4 h, l;
       split8(x, h, l);
