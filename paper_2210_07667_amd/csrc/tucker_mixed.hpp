@@ -5,9 +5,14 @@
 #include <vector>
 
 #include "gemm_bf16x3.hpp"
+#include "gemm_bf16x3_dl.hpp"
 #include "gemm_f32.hpp"
 #include "gemm_f32_dl.hpp"
 #include "tucker_f64.hpp"
+
+#ifndef PHIKS_BF_DL
+#define PHIKS_BF_DL 1  // 1: BF16x3 products of modes > 1 on the direct-to-LDS kernel
+#endif
 
 namespace {
 
@@ -76,6 +81,12 @@ int launch_gemm32(const GemmArgs& g, const Epi& epi, hipStream_t st) {
 // ---------------------------------------------- BF16x3 MFMA mu-mode launches
 template <int BM, int BN, int WM, int WN, bool KC, bool VEC, class TA, class TC, class Epi>
 int launch_cfg_bf(const GemmArgs& g, const Epi& epi, hipStream_t st) {
+  if constexpr (PHIKS_DL == 1 && PHIKS_BF_DL == 1 && VEC && !KC && std::is_same<TA, float>::value &&
+                BN >= 64) {
+    // modes > 1 (FP32 operands, n-contiguous tensor): direct-to-LDS operand path
+    if (g.K % 32 == 0 && g.N % 4 == 0 && g.ldb % 4 == 0 && g.pA == nullptr)
+      return launch_grid<BM, BN>(&gemm_bf16x3_dl_kernel<BM, BN, WM, WN, TC, Epi>, g, epi, st);
+  }
   return launch_grid<BM, BN>(&gemm_bf16x3_kernel<BM, BN, WM, WN, KC, VEC, TA, TC, Epi>, g, epi,
                              st);
 }
