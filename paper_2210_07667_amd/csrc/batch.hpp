@@ -5,10 +5,10 @@
 // phiks_plan / phiks_apply would run it alone.  What changes is the execution: the
 // problems advance in lockstep, one step per mu-mode product, and each step runs the
 // GEMMs of every problem that has one at that point as a few grouped launches (one
-// per operand layout, tile class, load width and epilogue).  The GEMM views come from
-// tucker_args, the node sums from the same CombineArgs as the single path, and the
-// per-element K order of the MFMA kernel does not depend on the tile shape, so every
-// result is bitwise the one phiks_apply returns for that problem alone.
+// per operand layout, tile class, load width, kernel and epilogue).  The GEMM views
+// come from tucker_args, the node sums from the same CombineArgs as the single path,
+// and every FP64 kernel takes K in the same order whatever its tile (gemm_f64.hpp), so
+// every result is bitwise the one phiks_apply returns for that problem alone.
 //
 // Included once, at the end of phiks.hip.
 #pragma once
