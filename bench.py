@@ -293,7 +293,25 @@ def main():
         ph.phiks_apply(pl, v.ptr, out.ptr, ws.ptr, ws.nbytes, st)
     ph.synchronize()
     apply_ms = (time.perf_counter() - a0) * 1e3 / reps
+    # per-call distribution: 20 calls, each waited for (adds the synchronisation, tens of us)
+    calls = []
+    for _ in range(20):
+        c0 = time.perf_counter()
+        ph.phiks_apply(pl, v.ptr, out.ptr, ws.ptr, ws.nbytes, st)
+        ph.synchronize()
+        calls.append((time.perf_counter() - c0) * 1e3)
     pl.close()
+    # plan build alone (host planner + device exponentials), each waited for
+    plans = []
+    for _ in range(10):
+        c0 = time.perf_counter()
+        plx = ph.phiks_plan(w.A, w.tau, w.p, w.n_scales, w.tol, w.task, stream=st)
+        ph.synchronize()
+        plans.append((time.perf_counter() - c0) * 1e3)
+        plx.close()
+    ph.synchronize()
+    # mu-mode flops of one call: T_exec Tucker operators of sum_mu 2 N n_mu each
+    call_flops = info["tucker_exec"] * sum(2.0 * w.N * a.shape[0] for a in w.A)
 
     # the same call with the mu-mode products in FP32 MFMA or BF16x3 (everything else FP64)
     ref64 = out.to_numpy()
@@ -357,7 +375,13 @@ def main():
                      "flops_per_launch": k_flops / max(k_launch, 1)},
         "apply_only_ms": apply_ms,
         "apply_only_dofs_per_s": w.N / (apply_ms * 1e-3),
+        "apply_call_ms": {"p10": float(np.percentile(calls, 10)), "p50": float(np.median(calls)),
+                          "p90": float(np.percentile(calls, 90)), "calls": len(calls),
+                          "note": "each call waited for on the host"},
+        "plan_ms": {"p50": float(np.median(plans)), "min": float(min(plans)), "calls": len(plans),
+                    "note": "host planner + device small exponentials, waited for"},
         "mu_mode_gflops_per_s": achieved * 1e3,
+        "mu_mode_gflops_per_s_of_call": call_flops / (apply_ms * 1e-3) / 1e9,
         "fp32_mfma": fp32,
         "bf16x3_mfma": bf16x3,
     }
