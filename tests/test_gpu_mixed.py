@@ -43,7 +43,10 @@ def ops(n, betas=(1.0, 0.5, 0.25, 0.125)):
 # ragged M, N and K tails, and (K = 97) the path without 16-byte loads; the small
 # ones fall back to the FP32 kernel for products too small to fill the GPU
 APPLY_CASES = [([40, 33, 20], 1e-3, 4, 2), ([64, 64, 64], 1e-3, 4, 1), ([33, 17], 5e-3, 3, 2),
-               ([7], 0.3, 2, 1), ([160, 144, 100], 1e-3, 4, 1), ([150, 97, 130], 2e-3, 3, 2)]
+               ([7], 0.3, 2, 1), ([160, 144, 100], 1e-3, 4, 1), ([150, 97, 130], 2e-3, 3, 2),
+               # modes > 1 on the direct-to-LDS FP32 / BF16x3 kernels with tiles overhanging
+               # M and N (160 = 128 + 32, 96 = 64 + 32; 224 = 128 + 96, 72 = 64 + 8)
+               ([96, 160, 128], 1e-3, 3, 1), ([72, 224, 160], 1e-3, 2, 1)]
 
 
 @functools.lru_cache(maxsize=None)
