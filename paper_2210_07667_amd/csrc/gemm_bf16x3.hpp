@@ -5,8 +5,10 @@
 // of two split operands is taken as hi*hi + hi*lo + lo*hi (the lo*lo term, at most
 // 2^-16 |a b|, is dropped), each term a v_mfma_f32_16x16x32_bf16 accumulating in FP32:
 // every term a b of a contraction is formed to within 3 * 2^-16 |a b|.
-// Intermediate tensors are stored in FP32 and the last mode writes FP64 through the
-// epilogues of the FP32 kernel, so the squaring recurrence stays in FP64.
+// Intermediate tensors are stored in FP32 (or, in a pair chain, as the hi/lo halves of
+// each FP32 value packed in one 32-bit word, so that the next product reads its
+// operands already split) and the last mode writes FP64 through the epilogues of the
+// FP32 kernel, so the squaring recurrence stays in FP64.
 //
 // MFMA v_mfma_f32_16x16x32_bf16, per lane l (eight consecutive k per lane):
 //   A operand  A[m0 + (l & 15)][k0 + 8 (l >> 4) + t],   t = 0..7
@@ -55,6 +57,41 @@ __device__ __forceinline__ void split8(const float (&x)[8], u32x4& hi, u32x4& lo
     hi[t] = h;
     lo[t] = __builtin_bit_cast(unsigned, __builtin_convertvector(r, bf16x2));
   }
+}
+
+// The split of one value as a pair word: hi in the low 16 bits, lo in the high 16 bits.
+// The same two roundings as split8, so a pair word holds exactly the halves split8
+// would form from x.
+__device__ __forceinline__ unsigned split_pair(float x) {
+  const flt2 v = {x, 0.f};
+  const unsigned h = __builtin_bit_cast(unsigned, __builtin_convertvector(v, bf16x2)) & 0xffffu;
+  const flt2 r = {x - __builtin_bit_cast(float, h << 16), 0.f};
+  const unsigned l = __builtin_bit_cast(unsigned, __builtin_convertvector(r, bf16x2)) & 0xffffu;
+  return h | (l << 16);
+}
+
+// Eight pair words (consecutive k) regrouped into the MFMA operands: the hi halves of
+// words 2t and 2t + 1 into word t of hi, the lo halves into word t of lo.
+__device__ __forceinline__ void unpair8(const unsigned (&w)[8], u32x4& hi, u32x4& lo) {
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    hi[t] = __builtin_amdgcn_perm(w[2 * t + 1], w[2 * t], 0x05040100u);
+    lo[t] = __builtin_amdgcn_perm(w[2 * t + 1], w[2 * t], 0x07060302u);
+  }
+}
+
+// Intermediate tensors of a pair chain: C holds split_pair of the FP32 product.
+struct EpiStorePair {
+  __device__ __forceinline__ void operator()(unsigned* C, int64_t e, int64_t, double acc) const {
+    C[e] = split_pair((float)acc);
+  }
+};
+
+// Pair words of FP64 matrices rounded to FP32 (the plan's copies for pair chains).
+__global__ void __launch_bounds__(256) to_pair_kernel(const double* src, unsigned* dst, int64_t n) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x)
+    dst[e] = split_pair((float)src[e]);
 }
 
 // Group position of row r for G groups of 16 bytes per row.

@@ -11,6 +11,10 @@
 //  * tensor operand B (n-contiguous), rows k < 32, BN/4 column quads per row:
 //    slot k*BN/4 + (cq ^ 4 ((k / 8) mod 4)); a lane reads its column at rows 8 lk + t,
 //    t = 0..7 (ds_read_b32 each; the four lane groups land on four 64-byte bank groups).
+// PAIR: both operands hold pair words (split_pair: hi | lo << 16) instead of FP32 values,
+// same layout; a fragment read then only regroups the halves (unpair8), the split having
+// been done once by whichever kernel wrote the operand.  The MFMA operands, and so the
+// results, are bitwise those of the FP32 form on the values the pairs were split from.
 // Requirements (checked by the launcher): K a multiple of 32, N of 4, the leading
 // dimensions and strides multiples of 4 floats, 16-byte aligned bases; ragged M/N fetch
 // clamped in-range rows or columns.
@@ -26,7 +30,7 @@
 
 namespace phiks {
 
-template <int BM, int BN, int WM, int WN, class TC, class Epi>
+template <int BM, int BN, int WM, int WN, class TC, class Epi, bool PAIR>
 __device__ __forceinline__ void gemm_bf16x3_dl_tile(const GemmArgs& g, const Epi& epi, int64_t rest) {
   constexpr int BK = 32;                  // floats of k per chunk (one BF16 MFMA step)
   constexpr int KQ = BK / 4;              // 16-byte quads per row of A
@@ -111,7 +115,14 @@ __device__ __forceinline__ void gemm_bf16x3_dl_tile(const GemmArgs& g, const Epi
         x[t] = bs[4 * (k * (BN / 4) + ((n >> 2) ^ (((k >> 3) & 3) << 2))) + (n & 3)];
       }
       u32x4 h, l;
-      split8(x, h, l);
+      if constexpr (PAIR) {
+        unsigned w[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) w[t] = __builtin_bit_cast(unsigned, x[t]);
+        unpair8(w, h, l);
+      } else {
+        split8(x, h, l);
+      }
       bh[jj] = __builtin_bit_cast(bf16x8, h);
       bl[jj] = __builtin_bit_cast(bf16x8, l);
     }
@@ -122,7 +133,14 @@ __device__ __forceinline__ void gemm_bf16x3_dl_tile(const GemmArgs& g, const Epi
       const flt4 q1 = *reinterpret_cast<const flt4*>(as + 4 * (r * KQ + ((2 * lk + 1) ^ ((r >> 1) & 7))));
       const float x[8] = {q0[0], q0[1], q0[2], q0[3], q1[0], q1[1], q1[2], q1[3]};
       u32x4 h, l;
-      split8(x, h, l);
+      if constexpr (PAIR) {
+        unsigned w[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) w[t] = __builtin_bit_cast(unsigned, x[t]);
+        unpair8(w, h, l);
+      } else {
+        split8(x, h, l);
+      }
       const bf16x8 ah = __builtin_bit_cast(bf16x8, h), al = __builtin_bit_cast(bf16x8, l);
 #pragma unroll
       for (int jj = 0; jj < FN; ++jj) {
@@ -140,9 +158,9 @@ __device__ __forceinline__ void gemm_bf16x3_dl_tile(const GemmArgs& g, const Epi
 #define PHIKS_BFDL_MIN_WAVES 2
 #endif
 
-template <int BM, int BN, int WM, int WN, class TC, class Epi>
+template <int BM, int BN, int WM, int WN, class TC, class Epi, bool PAIR>
 __global__ void __launch_bounds__(256, PHIKS_BFDL_MIN_WAVES) gemm_bf16x3_dl_kernel(GemmArgs g, Epi epi) {
-  gemm_bf16x3_dl_tile<BM, BN, WM, WN, TC, Epi>(g, epi, xcd_remap(blockIdx.x, g.total_tiles));
+  gemm_bf16x3_dl_tile<BM, BN, WM, WN, TC, Epi, PAIR>(g, epi, xcd_remap(blockIdx.x, g.total_tiles));
 }
 
 }  // namespace phiks

@@ -449,8 +449,19 @@ int plan_init_host_complex(phiks_plan_s& P, int d, const int64_t* n, const doubl
   return PHIKS_OK;
 }
 
+// Doubles per mode of the mixed-precision copies: the FP32 node matrices and exp(B/2^j)
+// (each block rounded up to whole doubles), then for PHIKS_BF16X3 the same blocks again
+// as pair words, the whole rounded up to an even count so the pair copy keeps the FP32
+// copy's 16-byte alignment.
+size_t mixed_doubles(const phiks_plan_s& P, int mu) {
+  if (P.precision == PHIKS_FP64) return 0;
+  const size_t nn = sq(P.n[mu]);
+  const size_t f32 = ((size_t)plan_nodes(P) * nn + 3) / 2 + 1 + ((size_t)(P.s + 1) * nn + 3) / 2 + 1;
+  return P.precision == PHIKS_BF16X3 ? 2 * ((f32 + 1) / 2 * 2) : f32;
+}
+
 // Plan-lifetime device memory in doubles: per mode the node matrices and exp(B/2^j),
-// j = 0..s, then (mixed precision) their FP32 copies, rounded up to whole doubles.
+// j = 0..s, then (mixed precision) their copies of mixed_doubles.
 size_t plan_device_doubles(const phiks_plan_s& P) {
   const int nodes = plan_nodes(P);
   size_t total = 0;
@@ -459,9 +470,7 @@ size_t plan_device_doubles(const phiks_plan_s& P) {
     return total;
   }
   for (int mu = 0; mu < P.d; ++mu) total += (size_t)(nodes + P.s + 1) * sq(P.n[mu]);
-  if (P.precision != PHIKS_FP64)
-    for (int mu = 0; mu < P.d; ++mu)
-      total += ((size_t)nodes * sq(P.n[mu]) + 3) / 2 + 1 + ((size_t)(P.s + 1) * sq(P.n[mu]) + 3) / 2 + 1;
+  for (int mu = 0; mu < P.d; ++mu) total += mixed_doubles(P, mu);
   return total;
 }
 
@@ -491,10 +500,15 @@ void plan_assign(phiks_plan_s& P, double* base) {
   }
   if (P.precision != PHIKS_FP64) {
     for (int mu = 0; mu < P.d; ++mu) {
+      const size_t start = total;
       P.Lnode32[mu] = (float*)(base + total);
       total += ((size_t)nodes * sq(P.n[mu]) + 3) / 2 + 1;
       P.E32[mu] = (float*)(base + total);
       total += ((size_t)(P.s + 1) * sq(P.n[mu]) + 3) / 2 + 1;
+      // the pair copy starts half-way into the mode's block: mixed_doubles / 2 doubles,
+      // i.e. mixed_doubles floats, after Lnode32
+      if (P.precision == PHIKS_BF16X3) P.pair_off[mu] = (int64_t)mixed_doubles(P, mu);
+      total = start + mixed_doubles(P, mu);
     }
   }
 }
@@ -650,6 +664,15 @@ int build_plan_matrices(const std::vector<phiks_plan_s*>& plans,
                            dim3(256), 0, st, (const double*)P->Lnode[mu], P->Lnode32[mu], ln);
       hipLaunchKernelGGL(to_f32_kernel, dim3((unsigned)std::min<int64_t>((le + 255) / 256, 4096)),
                          dim3(256), 0, st, (const double*)P->E[mu], P->E32[mu], le);
+      if (P->precision == PHIKS_BF16X3) {
+        if (ln > 0)
+          hipLaunchKernelGGL(to_pair_kernel, dim3((unsigned)std::min<int64_t>((ln + 255) / 256, 4096)),
+                             dim3(256), 0, st, (const double*)P->Lnode[mu],
+                             reinterpret_cast<unsigned*>(P->Lnode32[mu] + P->pair_off[mu]), ln);
+        hipLaunchKernelGGL(to_pair_kernel, dim3((unsigned)std::min<int64_t>((le + 255) / 256, 4096)),
+                           dim3(256), 0, st, (const double*)P->E[mu],
+                           reinterpret_cast<unsigned*>(P->E32[mu] + P->pair_off[mu]), le);
+      }
       CHECK_LAUNCH();
     }
   }

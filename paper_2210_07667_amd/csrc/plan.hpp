@@ -22,8 +22,11 @@ struct phiks_plan_s {
   void* dmem = nullptr;                 // all plan-lifetime device matrices
   double* Lnode[PHIKS_MAX_D] = {nullptr};  // (q-1) node matrices per mode, stride n^2
   double* E[PHIKS_MAX_D] = {nullptr};      // (s+1) matrices per mode: exp(B/2^j), stride n^2
-  float* Lnode32[PHIKS_MAX_D] = {nullptr};  // FP32 copies (precision PHIKS_FP32)
+  float* Lnode32[PHIKS_MAX_D] = {nullptr};  // FP32 copies (mixed precisions)
   float* E32[PHIKS_MAX_D] = {nullptr};
+  // PHIKS_BF16X3: the same matrices as pair words (hi | lo << 16 of each FP32 value),
+  // at Lnode32[mu] + pair_off[mu] and E32[mu] + pair_off[mu] (a multiple of 4 floats).
+  int64_t pair_off[PHIKS_MAX_D] = {0};
   // Complex plans (A_mu or tau complex; vectors of N complex values, re/im interleaved):
   // Lnode / E hold the real forms of the complex matrices (2n x 2n, the 2 x 2 block
   // [[Re, -Im], [Im, Re]] at block (i, j)), stride 4n^2, and Lsplit / Esplit the

@@ -13,6 +13,9 @@
 #ifndef PHIKS_BF_DL
 #define PHIKS_BF_DL 1  // 1: BF16x3 products of modes > 1 on the direct-to-LDS kernel
 #endif
+#ifndef PHIKS_BF_PAIR
+#define PHIKS_BF_PAIR 1  // 1: BF16x3 chains keep split pairs between modes where they can
+#endif
 
 namespace {
 
@@ -85,7 +88,7 @@ int launch_cfg_bf(const GemmArgs& g, const Epi& epi, hipStream_t st) {
                 BN >= 64) {
     // modes > 1 (FP32 operands, n-contiguous tensor): direct-to-LDS operand path
     if (g.K % 32 == 0 && g.N % 4 == 0 && g.ldb % 4 == 0 && g.pA == nullptr)
-      return launch_grid<BM, BN>(&gemm_bf16x3_dl_kernel<BM, BN, WM, WN, TC, Epi>, g, epi, st);
+      return launch_grid<BM, BN>(&gemm_bf16x3_dl_kernel<BM, BN, WM, WN, TC, Epi, false>, g, epi, st);
   }
   return launch_grid<BM, BN>(&gemm_bf16x3_kernel<BM, BN, WM, WN, KC, VEC, TA, TC, Epi>, g, epi,
                              st);
@@ -124,6 +127,44 @@ int launch_gemm_bf(const GemmArgs& g, const Epi& epi, hipStream_t st) {
   return launch_tile_bf<KC, false, TA, TC>(g, epi, st);
 }
 
+// ------------------------------------------------------- BF16x3 pair chains
+// A product of modes > 1 whose operands are pair words (matrix and intermediate):
+// only the direct-to-LDS kernel reads pairs, so a chain uses them only if every such
+// product passes this test (the tile choice and the conditions of launch_tile_bf /
+// launch_cfg_bf that lead there).
+bool pair_dl_ok(const GemmArgs& g) {
+  if (!vec_bf_ok(g, false)) return false;
+  if (g.K % 32 || g.N % 4 || g.ldb % 4 || g.pA != nullptr) return false;
+#if PHIKS_BF_BIG_TILE == 1
+  if (g.M >= 128 && g.N >= 128 && tiles_for(g, 128, 128) >= 256) return true;
+#endif
+  return pick_tile(g) != Tile::T32x32;
+}
+
+template <int BM, int BN, int WM, int WN, class TC, class Epi>
+int launch_pair_cfg(const GemmArgs& g, const Epi& epi, hipStream_t st) {
+  return launch_grid<BM, BN>(&gemm_bf16x3_dl_kernel<BM, BN, WM, WN, TC, Epi, true>, g, epi, st);
+}
+
+// Same tiles as launch_tile_bf, pair operands.
+template <class TC, class Epi>
+int launch_pair(const GemmArgs& g, const Epi& epi, hipStream_t st) {
+  if (!pair_dl_ok(g)) {
+    set_error("BF16x3 pair product outside the direct-to-LDS kernel's conditions");
+    return PHIKS_EINVAL;
+  }
+#if PHIKS_BF_BIG_TILE == 1
+  if (g.M >= 128 && g.N >= 128 && tiles_for(g, 128, 128) >= 256)
+    return launch_pair_cfg<128, 128, 64, 64, TC>(g, epi, st);
+#endif
+  switch (pick_tile(g)) {
+    case Tile::T128x128:
+    case Tile::T128x64: return launch_pair_cfg<128, 64, 64, 32, TC>(g, epi, st);
+    case Tile::T64x128: return launch_pair_cfg<64, 128, 32, 64, TC>(g, epi, st);
+    default: return launch_pair_cfg<64, 64, 32, 32, TC>(g, epi, st);
+  }
+}
+
 // mu-mode launch in the arithmetic PREC (PHIKS_FP32 or PHIKS_BF16X3)
 template <int PREC, bool KC, class TA, class TC, class Epi>
 int launch_mixed(const GemmArgs& g, const Epi& epi, hipStream_t st) {
@@ -135,6 +176,11 @@ int launch_mixed(const GemmArgs& g, const Epi& epi, hipStream_t st) {
 // is converted in the first mode, intermediate modes are FP32 (ta/tb hold floats), the
 // last mode writes FP64 through the same epilogue as the FP64 chain.  L[mu] are FP32
 // copies of the matrices.
+// BF16x3 chains of d >= 2 whose products of modes > 1 all fit the direct-to-LDS kernel
+// (pair_dl_ok) keep their intermediates as pair words and multiply the plan's pair
+// copies of the matrices (pair_off): each value is split once, by the kernel that
+// writes it, instead of by every work-group that reads it.  The MFMA operands are the
+// same bfloat16 numbers either way, so the result is bitwise that of the FP32 form.
 template <int PREC, class Epi>
 int tucker_mixed(const phiks_plan_s& P, const double* in, int64_t in_stride,
                  float* const* L, const int64_t* l_stride, int nbatch, double* out,
@@ -143,6 +189,21 @@ int tucker_mixed(const phiks_plan_s& P, const double* in, int64_t in_stride,
   double* Ld[PHIKS_MAX_D];
   for (int mu = 0; mu < P.d; ++mu) Ld[mu] = reinterpret_cast<double*>(L[mu]);
   tucker_args(P.d, P.n, P.N, in, in_stride, Ld, l_stride, nbatch, out, ta, tb, gs);
+  if constexpr (PREC == PHIKS_BF16X3) {
+    GemmArgs gp[PHIKS_MAX_D];
+    bool pairs = PHIKS_BF_PAIR == 1 && PHIKS_BF_DL == 1 && PHIKS_DL == 1 && P.d >= 2;
+    for (int mu = 2; mu <= P.d && pairs; ++mu) {
+      gp[mu - 1] = gs[mu - 1];
+      gp[mu - 1].A = reinterpret_cast<const double*>(L[mu - 1] + P.pair_off[mu - 1]);
+      pairs = pair_dl_ok(gp[mu - 1]);
+    }
+    if (pairs) {
+      // first mode: FP64 input by the FP32 matrix as before, pair words out
+      RET_IF((launch_mixed<PREC, true, double, unsigned>(gs[0], EpiStorePair{}, st)));
+      for (int mu = 2; mu < P.d; ++mu) RET_IF((launch_pair<unsigned>(gp[mu - 1], EpiStorePair{}, st)));
+      return launch_pair<double>(gp[P.d - 1], epi, st);
+    }
+  }
   for (int mu = 1; mu <= P.d; ++mu) {
     const bool last = (mu == P.d);
     const GemmArgs& g = gs[mu - 1];
