@@ -1,12 +1,15 @@
-// FP32 MFMA mu-mode product with direct-to-LDS operand loads, for the products whose
-// operands are both FP32 in memory (modes > 1 of a mixed-precision Tucker chain; the
-// first mode reads the FP64 vectors and converts them, so it keeps gemm_f32_kernel).
-// Same products, tile order and epilogues as gemm_f32_kernel; the operand path is the
-// one of gemm_f64_dl.hpp with 16-byte slots holding four floats:
+// FP32 MFMA mu-mode product with direct-to-LDS operand loads.  Same products, tile
+// order and epilogues as gemm_f32_kernel; the operand path is the one of
+// gemm_f64_dl.hpp with 16-byte slots holding four floats:
 //  * k-contiguous operand, rows r < R, k < 16 per chunk: slot of (r, k quad kq) is
 //    r*4 + (kq ^ ((r / 4) mod 4)).  Lane group lk = l >> 4 reads quad lk of its row
 //    (ds_read_b128) and feeds four MFMA steps: step h takes k = 4 lk + h, for both
 //    operands.
+//  * A in FP64 (TA = double: the first mode of a chain, which reads the FP64 vectors):
+//    its rows reach LDS unconverted, eight 16-byte slots of two doubles per row and
+//    chunk, slot r*8 + (kp ^ ((r / 2) mod 8)); lane group lk reads slots 2 lk and 2 lk + 1
+//    (k = 4 lk .. 4 lk + 3) and rounds them to FP32 there, as gemm_f32_kernel does on
+//    its way into LDS.
 //  * n-contiguous operand, k < 16, columns c < BN: slot of (k, column quad cq) is
 //    k*BN/4 + (cq ^ 4 ((k / 4) mod 4)); fragment reads are 4 bytes, the four rows of one
 //    read land on four different 64-byte bank groups.
@@ -33,14 +36,16 @@ namespace phiks {
 __device__ __forceinline__ int swz_kq(int r) { return (r >> 2) & 3; }
 __device__ __forceinline__ int swz_nq(int k) { return ((k >> 2) & 3) << 2; }
 
-template <int BM, int BN, int WM, int WN, bool B_KCONTIG, class TC, class Epi>
+template <int BM, int BN, int WM, int WN, bool B_KCONTIG, class TA, class TC, class Epi>
 __device__ __forceinline__ void gemm_f32_dl_tile(const GemmArgs& g, const Epi& epi, int64_t rest) {
   constexpr int BK = 16;                 // floats of k per chunk
-  constexpr int KQ = BK / 4;             // 16-byte slots per k-contiguous row
+  constexpr int KQ = BK / 4;             // 16-byte slots per k-contiguous FP32 row
+  constexpr bool AD = std::is_same<TA, double>::value;
+  constexpr int AQ = AD ? 2 * KQ : KQ;   // 16-byte slots per row of A
   constexpr int WGM = BM / WM, WGN = BN / WN;
   static_assert(WGM * WGN == 4, "4 waves per work-group");
   constexpr int FM = WM / 16, FN = WN / 16;
-  constexpr int A_SLOTS = BM * KQ, B_SLOTS = BN * KQ;
+  constexpr int A_SLOTS = BM * AQ, B_SLOTS = BN * KQ;
   static_assert(A_SLOTS % 256 == 0 && B_SLOTS % 256 == 0, "every thread fetches the same count");
   static_assert(B_KCONTIG || BN / 4 >= 16, "column-quad swizzle needs BN >= 64");
   constexpr int LA = A_SLOTS / 256, LB = B_SLOTS / 256;
@@ -49,8 +54,7 @@ __device__ __forceinline__ void gemm_f32_dl_tile(const GemmArgs& g, const Epi& e
   __shared__ __align__(16) float lds[2 * STAGE];
 
   const TileCoords tc = tile_coords<B_KCONTIG>(g, rest);
-  const PHIKS_GLOBAL float* A =
-      (const PHIKS_GLOBAL float*)gptr(g.A) + tc.z0 * g.sA0 + tc.z1 * g.sA1;
+  const PHIKS_GLOBAL TA* A = (const PHIKS_GLOBAL TA*)gptr(g.A) + tc.z0 * g.sA0 + tc.z1 * g.sA1;
   const PHIKS_GLOBAL float* B =
       (const PHIKS_GLOBAL float*)gptr(g.B) + tc.z0 * g.sB0 + tc.z1 * g.sB1;
   TC* Cb = reinterpret_cast<TC*>(g.C);
@@ -62,13 +66,13 @@ __device__ __forceinline__ void gemm_f32_dl_tile(const GemmArgs& g, const Epi& e
   const int wm = (wave / WGN) * WM, wn = (wave % WGN) * WN;
   const int lr = lane & 15, lk = lane >> 4;
 
-  const PHIKS_GLOBAL float* asrc[LA];
+  const PHIKS_GLOBAL TA* asrc[LA];
   const PHIKS_GLOBAL float* bsrc[LB];
 #pragma unroll
   for (int i = 0; i < LA; ++i) {
     const int s = i * 256 + tid;
-    const int r = s / KQ, kq = (s % KQ) ^ swz_kq(s / KQ);
-    asrc[i] = A + (int64_t)min(m0 + r, g.M - 1) * g.lda + 4 * kq;
+    const int r = s / AQ, q = (s % AQ) ^ (AD ? (r >> 1) & 7 : swz_kq(r));
+    asrc[i] = A + (int64_t)min(m0 + r, g.M - 1) * g.lda + (16 / (int)sizeof(TA)) * q;
   }
 #pragma unroll
   for (int i = 0; i < LB; ++i) {
@@ -116,7 +120,13 @@ __device__ __forceinline__ void gemm_f32_dl_tile(const GemmArgs& g, const Epi& e
 #pragma unroll
     for (int i = 0; i < FM; ++i) {
       const int r = wm + i * 16 + lr;
-      fa[i] = *reinterpret_cast<const flt4*>(as + 4 * (r * KQ + (lk ^ swz_kq(r))));
+      if constexpr (AD) {
+        const dbl2 p0 = *reinterpret_cast<const dbl2*>(as + 4 * (r * AQ + ((2 * lk) ^ ((r >> 1) & 7))));
+        const dbl2 p1 = *reinterpret_cast<const dbl2*>(as + 4 * (r * AQ + ((2 * lk + 1) ^ ((r >> 1) & 7))));
+        fa[i] = flt4{(float)p0[0], (float)p0[1], (float)p1[0], (float)p1[1]};
+      } else {
+        fa[i] = *reinterpret_cast<const flt4*>(as + 4 * (r * KQ + (lk ^ swz_kq(r))));
+      }
     }
 #pragma unroll
     for (int jj = 0; jj < FN; ++jj) {
@@ -148,9 +158,9 @@ constexpr int f32dl_min_waves() {
   return std::is_same<Epi, EpiLinComb>::value ? 3 : PHIKS_F32DL_MIN_WAVES;
 }
 
-template <int BM, int BN, int WM, int WN, bool B_KCONTIG, class TC, class Epi>
+template <int BM, int BN, int WM, int WN, bool B_KCONTIG, class TA, class TC, class Epi>
 __global__ void __launch_bounds__(256, f32dl_min_waves<Epi>()) gemm_f32_dl_kernel(GemmArgs g, Epi epi) {
-  gemm_f32_dl_tile<BM, BN, WM, WN, B_KCONTIG, TC, Epi>(g, epi, xcd_remap(blockIdx.x, g.total_tiles));
+  gemm_f32_dl_tile<BM, BN, WM, WN, B_KCONTIG, TA, TC, Epi>(g, epi, xcd_remap(blockIdx.x, g.total_tiles));
 }
 
 }  // namespace phiks

@@ -13,6 +13,9 @@
 #ifndef PHIKS_BF_DL
 #define PHIKS_BF_DL 1  // 1: BF16x3 products of modes > 1 on the direct-to-LDS kernel
 #endif
+#ifndef PHIKS_F32_DL_A64
+#define PHIKS_F32_DL_A64 1  // 1: FP32 products with an FP64 A (first modes) on the direct-to-LDS kernel
+#endif
 #ifndef PHIKS_BF_PAIR
 #define PHIKS_BF_PAIR 1  // 1: BF16x3 chains keep split pairs between modes where they can
 #endif
@@ -47,13 +50,14 @@ int launch_grid(void (*kern)(GemmArgs, Epi), GemmArgs g, const Epi& epi, hipStre
 
 template <int BM, int BN, int WM, int WN, bool KC, bool VEC, class TA, class TC, class Epi>
 int launch_cfg32(const GemmArgs& g, const Epi& epi, hipStream_t st) {
-  if constexpr (PHIKS_DL == 1 && VEC && std::is_same<TA, float>::value && BM >= 64 && BN >= 64 &&
-                !std::is_same<Epi, EpiLinComb>::value) {
-    // FP32 operands both ways: direct-to-LDS loads (whole 16-float chunks of K).  The
-    // squaring epilogue, which reads its FP64 pre-step tensors through registers, runs
-    // faster on gemm_f32_kernel (measured 519 against 574 us per 256^3 launch).
+  if constexpr (PHIKS_DL == 1 && VEC && (PHIKS_F32_DL_A64 == 1 || std::is_same<TA, float>::value) &&
+                BM >= 64 && BN >= 64 && !std::is_same<Epi, EpiLinComb>::value) {
+    // direct-to-LDS loads (whole 16-k chunks; an FP64 A is converted at the fragment
+    // read).  The squaring epilogue, which reads its FP64 pre-step tensors through
+    // registers, runs faster on gemm_f32_kernel (measured 519 against 574 us per 256^3
+    // launch).
     if (g.K % 16 == 0 && g.pA == nullptr)
-      return launch_grid<BM, BN>(&gemm_f32_dl_kernel<BM, BN, WM, WN, KC, TC, Epi>, g, epi, st);
+      return launch_grid<BM, BN>(&gemm_f32_dl_kernel<BM, BN, WM, WN, KC, TA, TC, Epi>, g, epi, st);
   }
   return launch_grid<BM, BN>(&gemm_f32_kernel<BM, BN, WM, WN, KC, VEC, TA, TC, Epi>, g, epi, st);
 }
