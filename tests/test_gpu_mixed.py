@@ -46,7 +46,11 @@ APPLY_CASES = [([40, 33, 20], 1e-3, 4, 2), ([64, 64, 64], 1e-3, 4, 1), ([33, 17]
                ([7], 0.3, 2, 1), ([160, 144, 100], 1e-3, 4, 1), ([150, 97, 130], 2e-3, 3, 2),
                # modes > 1 on the direct-to-LDS FP32 / BF16x3 kernels with tiles overhanging
                # M and N (160 = 128 + 32, 96 = 64 + 32; 224 = 128 + 96, 72 = 64 + 8)
-               ([96, 160, 128], 1e-3, 3, 1), ([72, 224, 160], 1e-3, 2, 1)]
+               ([96, 160, 128], 1e-3, 3, 1), ([72, 224, 160], 1e-3, 2, 1),
+               # d = 2 BF16x3 pair chain (node phase: the last mode reads pair words on
+               # 128 x 64 tiles, M = 352 = 2*128 + 96, N = 520 = 8*64 + 8); FP32 first mode
+               # with an FP64 A on the direct-to-LDS kernel, M = 7200 = 56*128 + 32
+               ([520, 352], 1e-3, 4, 1), ([96, 72, 100], 1e-3, 3, 1)]
 
 
 @functools.lru_cache(maxsize=None)
