@@ -224,9 +224,11 @@ def main():
                     help="skip the 512-problem batched section")
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the served-requests section")
-    ap.add_argument("--copy-calibration", action="store_true",
-                    help="first copy N doubles device-to-device once (a plain copy of known "
-                         "size, to scale hardware byte counters)")
+    ap.add_argument("--counters", action="store_true",
+                    help="hardware-counter run: copy N doubles device-to-device once (a plain "
+                         "copy of known size, to scale byte counters), then run exactly one "
+                         "step (one plan, one call) and exit, so the counted launches are "
+                         "the mix of a timed step")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the phi-action path here is single-GPU "
@@ -244,12 +246,21 @@ def main():
     v = ph.DeviceArray.from_numpy(w.v)
     st = 0  # null stream
 
-    if args.copy_calibration:
+    if args.counters:
         tmp = ph.DeviceArray(w.N)
         ph.copy_device(tmp, v, st)
         ph.synchronize()
         tmp.free()
         log(f"[bench] calibration copy of {w.N * 8} bytes done")
+        pl = ph.phiks_plan(w.A, w.tau, w.p, w.n_scales, w.tol, w.task, stream=st)
+        ws = ph.DeviceArray(pl.workspace_size() // 8 + 1)
+        out = ph.DeviceArray(w.n_scales * (w.p + 1) * w.N)
+        ph.phiks_apply(pl, v.ptr, out.ptr, ws.ptr, ws.nbytes, st)
+        ph.synchronize()
+        print(json.dumps({"counters": "one step: calibration copy, one plan, one call",
+                          "copy_bytes": w.N * 8, "plan": pl.info()}), flush=True)
+        pl.close()
+        return
     plan = ph.phiks_plan(w.A, w.tau, w.p, w.n_scales, w.tol, w.task, stream=st)
     info = plan.info()
     ws = ph.DeviceArray(plan.workspace_size() // 8 + 1)

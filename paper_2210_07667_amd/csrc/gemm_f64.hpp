@@ -11,9 +11,10 @@
 // tensor is ever made; the tiles are staged through LDS in the layout the MFMA
 // fragments read.
 //
-// MFMA: v_mfma_f64_16x16x4_f64.  Per lane l (64-wide wave):
-//   A operand  A[m0 + (l & 15)][k0 + (l >> 4)]
-//   B operand  B[k0 + (l >> 4)][n0 + (l & 15)]
+// MFMA: v_mfma_f64_16x16x4_f64.  Per lane l (64-wide wave), for the four k of one step
+// (k_0..k_3; which k a step takes is the k order below):
+//   A operand  A[m0 + (l & 15)][k_(l >> 4)]
+//   B operand  B[k_(l >> 4)][n0 + (l & 15)]
 //   C result   c[r] = C[m0 + (l >> 4) + 4 r][n0 + (l & 15)],  r = 0..3
 //
 // LDS: tiles are stored k-major (row k holds the BM (or BN) entries of that k) with
@@ -21,9 +22,10 @@
 // spread over k) and the fragment reads (16 columns x 2 rows per half-wave) hit
 // distinct banks: column c of row k is stored at c ^ swz(k).
 //
-// Launch: 1-D grid.  Mode 1 (k-contiguous B): the n tile (along L) varies fastest,
-// then the batch index z1, the m tile and z0, so that every work-group reading one
-// row block of the tensor (shared by the nodes of a batch too) runs back to back.
+// Launch: 1-D grid, tile order 0 (order 1: GemmArgs::order).  Mode 1 (k-contiguous B):
+// the n tile (along L) varies fastest, then the batch index z1, the m tile and z0, so
+// that every work-group reading one row block of the tensor (shared by the nodes of a
+// batch too) runs back to back.
 // Modes > 1: z1 varies fastest (the p tensors of a squaring step share the epilogue
 // operands), then the m tile (along L), the n tile and z0.  Ids are remapped so that
 // consecutive logical tiles land on one XCD (work-groups are dealt round-robin over
