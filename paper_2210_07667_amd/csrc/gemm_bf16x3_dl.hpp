@@ -26,6 +26,7 @@
 #include <type_traits>
 
 #include "gemm_bf16x3.hpp"
+#include "gemm_f32_dl.hpp"
 #include "gemm_f64_dl.hpp"
 
 namespace phiks {
@@ -42,8 +43,11 @@ __device__ __forceinline__ void gemm_bf16x3_dl_tile(const GemmArgs& g, const Epi
   static_assert(BN / 4 >= 16, "column-quad swizzle needs BN >= 64");
   constexpr int LA = A_SLOTS / 256, LB = B_SLOTS / 256;
   constexpr int STAGE = 4 * (A_SLOTS + B_SLOTS);   // floats per stage
+  constexpr bool LC = std::is_same<Epi, EpiLinComb>::value;
+  constexpr int LDS_FLOATS =
+      (LC && 2 * lc_f32_lds_doubles<BM, BN, WM>() > 2 * STAGE) ? 2 * lc_f32_lds_doubles<BM, BN, WM>() : 2 * STAGE;
 
-  __shared__ __align__(16) float lds[2 * STAGE];
+  __shared__ __align__(16) float lds[LDS_FLOATS];
 
   const TileCoords tc = tile_coords<false>(g, rest);
   const PHIKS_GLOBAL float* A =
@@ -151,7 +155,11 @@ __device__ __forceinline__ void gemm_bf16x3_dl_tile(const GemmArgs& g, const Epi
     }
   }
 
-  store_acc_tile<FM, FN, TC>(acc, g, epi, Cb, cbase, tc.z1, m0 + wm, n0 + wn, lr, lk);
+  if constexpr (LC)
+    lincomb_lds_epilogue_f32<BM, BN, WM, WN>(acc, g, epi, Cb, cbase, tc.z1,
+                                             reinterpret_cast<double*>(lds), m0, n0, wave, tid);
+  else
+    store_acc_tile<FM, FN, TC>(acc, g, epi, Cb, cbase, tc.z1, m0 + wm, n0 + wn, lr, lk);
 }
 
 #ifndef PHIKS_BFDL_MIN_WAVES

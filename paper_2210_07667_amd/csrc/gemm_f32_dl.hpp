@@ -36,6 +36,115 @@ namespace phiks {
 __device__ __forceinline__ int swz_kq(int r) { return (r >> 2) & 3; }
 __device__ __forceinline__ int swz_nq(int k) { return ((k >> 2) & 3) << 2; }
 
+// Y slice buffers of the squaring epilogue below: three while a slice is at most 16 KB,
+// else two (the buffers overlay the operand ring once the K loop is done).
+template <int BM, int BN, int WM>
+constexpr int lc_f32_bufs() { return (BM / WM) * 16 * BN * 8 <= 16384 ? 3 : 2; }
+template <int BM, int BN, int WM>
+constexpr int lc_f32_lds_doubles() { return lc_f32_bufs<BM, BN, WM>() * (BM / WM) * 16 * BN; }
+
+// Squaring epilogue of the FP32-accumulating direct-to-LDS kernels: out = a_l acc +
+// sum_{k <= l} c_lk Y_k in FP64, with the pre-step tensors Y_k streamed through LDS by
+// 16-byte DMA (the scheme of lincomb_lds_epilogue in gemm_f64_dl.hpp, for the FP32
+// accumulator layout c[r] at row 4 (l >> 4) + r).  Rounds run fragment row by fragment
+// row (round i (l + 1) + k: slice of fragment row i of every wave, of Y_k), so only one
+// row block of FP64 partial sums is live; per element the arithmetic is the register
+// epilogue's (a_l acc, then one fma per k in k order).  Slice layout: WGM * 16 rows of
+// BN columns as column pairs, slot rho * BN/2 + (cp ^ 8 ((rho / 4) mod 2)): the two row
+// groups 4 apart that one 32-lane read touches land on different bank halves.  YB
+// buffers, DMA YB - 1 rounds ahead.  Needs lincomb_dl_ok (checked by the launchers).
+template <int BM, int BN, int WM, int WN, int FM, int FN>
+__device__ __forceinline__ void lincomb_lds_epilogue_f32(const flt4 (&acc)[FM][FN], const GemmArgs& g,
+                                                         const EpiLinComb& epi, double* Cb,
+                                                         int64_t cbase, int64_t z1, double* lds,
+                                                         int m0, int n0, int wave, int tid) {
+  constexpr int WGM = BM / WM, WGN = BN / WN;
+  constexpr int ROWS = WGM * 16, CP = BN / 2;
+  constexpr int YSLICE = ROWS * BN;                     // doubles
+  constexpr int YB = lc_f32_bufs<BM, BN, WM>();
+  constexpr int SLOTS = ROWS * CP, LY = SLOTS / 256;
+  static_assert(SLOTS % 256 == 0, "every thread fetches the same count");
+  static_assert(CP >= 16, "column-pair swizzle needs BN >= 32");
+  const int lane = tid & 63, lr = lane & 15, lk = lane >> 4;
+  const int wgm = wave / WGN, wn = (wave % WGN) * WN;
+  const int l = (int)z1, nk = l + 1;
+  const int rounds = FM * nk;
+
+  // this thread's slots: source offset of slice row rho (fragment row 0), clamped column
+  int64_t off[LY];
+#pragma unroll
+  for (int q = 0; q < LY; ++q) {
+    const int s = q * 256 + tid;
+    const int rho = s / CP, cp = (s % CP) ^ (((rho >> 2) & 1) << 3);
+    const int row = (rho / 16) * WM + rho % 16;
+    off[q] = (int64_t)row * g.ldc + min(n0 + 2 * cp, g.N - 2);
+  }
+  const PHIKS_GLOBAL double* Y0 = gptr(epi.Y) + cbase - (int64_t)l * epi.N;   // Y_0 at this tile
+  auto issue = [&](int r) {
+    const int i = r / nk, k = r - i * nk;
+    const PHIKS_GLOBAL double* Yk = Y0 + (int64_t)k * epi.N;
+    double* buf = lds + (r % YB) * YSLICE;
+#pragma unroll
+    for (int q = 0; q < LY; ++q) {
+      const int s = q * 256 + tid;
+      const int rho = s / CP;
+      const int row = (rho / 16) * WM + rho % 16;
+      const int grow = min(m0 + row + i * 16, g.M - 1);
+      dma16(Yk + off[q] + (int64_t)(grow - row) * g.ldc, buf + 2 * (q * 256 + wave * 64));
+    }
+  };
+
+  // every wave is done with the operand ring before its memory is overwritten
+  wait_lgkmcnt0();
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+#pragma unroll
+  for (int r = 0; r < YB - 1; ++r)
+    if (r < rounds) issue(r);
+  const double al = epi.a[l];
+  const int ml = m0 + wgm * WM + 4 * lk, nl = n0 + wn + lr;
+#pragma unroll
+  for (int i = 0; i < FM; ++i) {
+    double o[FN][4];
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) o[j][rr] = al * (double)acc[i][j][rr];
+    for (int k = 0; k < nk; ++k) {
+      const int r = i * nk + k;
+      // round r has landed once at most the later rounds' loads are outstanding (stores
+      // of earlier row blocks issued after them only make this wait longer)
+      if (r + YB - 2 < rounds) wait_vmcnt<(YB - 2) * LY>();
+      else wait_vmcnt<0>();
+      wait_lgkmcnt0();
+      asm volatile("" ::: "memory");
+      __builtin_amdgcn_s_barrier();
+      asm volatile("" ::: "memory");
+      if (r + YB - 1 < rounds) issue(r + YB - 1);     // into the buffer round r - 1 used
+      const double* buf = lds + (r % YB) * YSLICE;
+      const double ck = epi.c[l][k];
+#pragma unroll
+      for (int j = 0; j < FN; ++j) {
+        const int c = wn + j * 16 + lr;
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+          const int rho = wgm * 16 + 4 * lk + rr;
+          const double y = buf[2 * (rho * CP + ((c >> 1) ^ (((rho >> 2) & 1) << 3))) + (c & 1)];
+          o[j][rr] = __builtin_fma(ck, y, o[j][rr]);
+        }
+      }
+    }
+    const int64_t base = cbase + (int64_t)(ml + i * 16) * g.ldc + nl;
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr)
+        if ((ml + i * 16 + rr < g.M) & (nl + j * 16 < g.N))
+          Cb[base + (int64_t)rr * g.ldc + j * 16] = o[j][rr];
+  }
+}
+
 template <int BM, int BN, int WM, int WN, bool B_KCONTIG, class TA, class TC, class Epi>
 __device__ __forceinline__ void gemm_f32_dl_tile(const GemmArgs& g, const Epi& epi, int64_t rest) {
   constexpr int BK = 16;                 // floats of k per chunk
@@ -50,8 +159,11 @@ __device__ __forceinline__ void gemm_f32_dl_tile(const GemmArgs& g, const Epi& e
   static_assert(B_KCONTIG || BN / 4 >= 16, "column-quad swizzle needs BN >= 64");
   constexpr int LA = A_SLOTS / 256, LB = B_SLOTS / 256;
   constexpr int STAGE = 4 * (A_SLOTS + B_SLOTS);   // floats per stage
+  constexpr bool LC = std::is_same<Epi, EpiLinComb>::value;
+  constexpr int LDS_FLOATS =
+      (LC && 2 * lc_f32_lds_doubles<BM, BN, WM>() > 2 * STAGE) ? 2 * lc_f32_lds_doubles<BM, BN, WM>() : 2 * STAGE;
 
-  __shared__ __align__(16) float lds[2 * STAGE];
+  __shared__ __align__(16) float lds[LDS_FLOATS];
 
   const TileCoords tc = tile_coords<B_KCONTIG>(g, rest);
   const PHIKS_GLOBAL TA* A = (const PHIKS_GLOBAL TA*)gptr(g.A) + tc.z0 * g.sA0 + tc.z1 * g.sA1;
@@ -150,7 +262,11 @@ __device__ __forceinline__ void gemm_f32_dl_tile(const GemmArgs& g, const Epi& e
           acc[i][jj] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[i][h], fb[jj][h], acc[i][jj], 0, 0, 0);
   }
 
-  store_acc_tile<FM, FN, TC>(acc, g, epi, Cb, cbase, tc.z1, m0 + wm, n0 + wn, lr, lk);
+  if constexpr (LC)
+    lincomb_lds_epilogue_f32<BM, BN, WM, WN>(acc, g, epi, Cb, cbase, tc.z1,
+                                             reinterpret_cast<double*>(lds), m0, n0, wave, tid);
+  else
+    store_acc_tile<FM, FN, TC>(acc, g, epi, Cb, cbase, tc.z1, m0 + wm, n0 + wn, lr, lk);
 }
 
 template <class Epi>

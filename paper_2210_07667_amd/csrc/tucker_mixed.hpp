@@ -48,15 +48,24 @@ int launch_grid(void (*kern)(GemmArgs, Epi), GemmArgs g, const Epi& epi, hipStre
                       2.0 * g.M * (double)g.N * g.K * g.nb0 * (double)g.nb1, g, epi);
 }
 
+// The direct-to-LDS kernels' squaring epilogue needs lincomb_dl_ok; other epilogues pass.
+#ifndef PHIKS_MIXED_LC_DL
+#define PHIKS_MIXED_LC_DL 1  // 1: mixed-precision squaring launches on the direct-to-LDS kernels
+#endif
+template <class Epi>
+bool lincomb_ok(const GemmArgs& g, const Epi& epi) {
+  if constexpr (std::is_same<Epi, EpiLinComb>::value)
+    return PHIKS_MIXED_LC_DL == 1 && lincomb_dl_ok(g, epi.Y, epi.N);
+  else return true;
+}
+
 template <int BM, int BN, int WM, int WN, bool KC, bool VEC, class TA, class TC, class Epi>
 int launch_cfg32(const GemmArgs& g, const Epi& epi, hipStream_t st) {
   if constexpr (PHIKS_DL == 1 && VEC && (PHIKS_F32_DL_A64 == 1 || std::is_same<TA, float>::value) &&
-                BM >= 64 && BN >= 64 && !std::is_same<Epi, EpiLinComb>::value) {
+                BM >= 64 && BN >= 64) {
     // direct-to-LDS loads (whole 16-k chunks; an FP64 A is converted at the fragment
-    // read).  The squaring epilogue, which reads its FP64 pre-step tensors through
-    // registers, runs faster on gemm_f32_kernel (measured 519 against 574 us per 256^3
-    // launch).
-    if (g.K % 16 == 0 && g.pA == nullptr)
+    // read); the squaring epilogue streams its pre-step tensors through LDS too
+    if (g.K % 16 == 0 && g.pA == nullptr && lincomb_ok(g, epi))
       return launch_grid<BM, BN>(&gemm_f32_dl_kernel<BM, BN, WM, WN, KC, TA, TC, Epi>, g, epi, st);
   }
   return launch_grid<BM, BN>(&gemm_f32_kernel<BM, BN, WM, WN, KC, VEC, TA, TC, Epi>, g, epi, st);
@@ -91,7 +100,7 @@ int launch_cfg_bf(const GemmArgs& g, const Epi& epi, hipStream_t st) {
   if constexpr (PHIKS_DL == 1 && PHIKS_BF_DL == 1 && VEC && !KC && std::is_same<TA, float>::value &&
                 BN >= 64) {
     // modes > 1 (FP32 operands, n-contiguous tensor): direct-to-LDS operand path
-    if (g.K % 32 == 0 && g.N % 4 == 0 && g.ldb % 4 == 0 && g.pA == nullptr)
+    if (g.K % 32 == 0 && g.N % 4 == 0 && g.ldb % 4 == 0 && g.pA == nullptr && lincomb_ok(g, epi))
       return launch_grid<BM, BN>(&gemm_bf16x3_dl_kernel<BM, BN, WM, WN, TC, Epi, false>, g, epi, st);
   }
   return launch_grid<BM, BN>(&gemm_bf16x3_kernel<BM, BN, WM, WN, KC, VEC, TA, TC, Epi>, g, epi,
@@ -153,7 +162,7 @@ int launch_pair_cfg(const GemmArgs& g, const Epi& epi, hipStream_t st) {
 // Same tiles as launch_tile_bf, pair operands.
 template <class TC, class Epi>
 int launch_pair(const GemmArgs& g, const Epi& epi, hipStream_t st) {
-  if (!pair_dl_ok(g)) {
+  if (!pair_dl_ok(g) || !lincomb_ok(g, epi)) {
     set_error("BF16x3 pair product outside the direct-to-LDS kernel's conditions");
     return PHIKS_EINVAL;
   }
@@ -201,6 +210,7 @@ int tucker_mixed(const phiks_plan_s& P, const double* in, int64_t in_stride,
       gp[mu - 1].A = reinterpret_cast<const double*>(L[mu - 1] + P.pair_off[mu - 1]);
       pairs = pair_dl_ok(gp[mu - 1]);
     }
+    pairs = pairs && lincomb_ok(gp[P.d - 1], epi);
     if (pairs) {
       // first mode: FP64 input by the FP32 matrix as before, pair words out
       RET_IF((launch_mixed<PREC, true, double, unsigned>(gs[0], EpiStorePair{}, st)));
