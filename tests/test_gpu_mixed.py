@@ -50,7 +50,10 @@ APPLY_CASES = [([40, 33, 20], 1e-3, 4, 2), ([64, 64, 64], 1e-3, 4, 1), ([33, 17]
                # d = 2 BF16x3 pair chain (node phase: the last mode reads pair words on
                # 128 x 64 tiles, M = 352 = 2*128 + 96, N = 520 = 8*64 + 8); FP32 first mode
                # with an FP64 A on the direct-to-LDS kernel, M = 7200 = 56*128 + 32
-               ([520, 352], 1e-3, 4, 1), ([96, 72, 100], 1e-3, 3, 1)]
+               ([520, 352], 1e-3, 4, 1), ([96, 72, 100], 1e-3, 3, 1),
+               # squaring launches on the direct-to-LDS kernels with a ragged N (third mode:
+               # N = 7200 = 112*64 + 32; the pre-step slices clamp their last columns)
+               ([100, 72, 128], 1e-3, 3, 1)]
 
 
 @functools.lru_cache(maxsize=None)
