@@ -72,7 +72,7 @@ int launch_cfg32(const GemmArgs& g, const Epi& epi, hipStream_t st) {
 }
 
 #ifndef PHIKS_F32_BIG_TILE
-#define PHIKS_F32_BIG_TILE 0  // 1: 128 x 128 tiles (4 waves of 64 x 64) where they fill the GPU
+#define PHIKS_F32_BIG_TILE 1  // 1: 128 x 128 tiles (4 waves of 64 x 64) where they fill the GPU
 #endif
 template <bool KC, bool VEC, class TA, class TC, class Epi>
 int launch_tile32(const GemmArgs& g, const Epi& epi, hipStream_t st) {
