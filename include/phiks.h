@@ -188,7 +188,9 @@ void phiks_plan_destroy(phiks_plan_t plan);
  * is bracketed by HIP events recorded on the launch stream.  phiks_kernel_timing_read
  * waits for the recorded launches, returns the summed kernel time (ms), the number
  * of launches and their algorithmic flops (2 * rows * cols * contraction length per
- * product), and clears the record.
+ * product), and clears the record.  Kernels of one stream never overlap, so a launch
+ * whose start stamp precedes the end of the previous timed launch on its stream is
+ * counted from that end (an upper bound on its duration).
  */
 int phiks_kernel_timing(int enable);
 int phiks_kernel_timing_read(double* total_ms, int64_t* launches, double* flops);

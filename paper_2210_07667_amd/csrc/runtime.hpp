@@ -52,6 +52,7 @@ void set_error(const std::string& s) { g_last_error = s; }
 struct TimedLaunch {
   hipEvent_t a, b;
   double flops;
+  hipStream_t st;
 };
 std::mutex g_timing_mu;
 bool g_timing = false;
@@ -95,7 +96,7 @@ int timed_launch(void (*kern)(KArgs...), unsigned grid, hipStream_t st, double f
   CHECK_LAUNCH();
   if (ea) {
     std::lock_guard<std::mutex> lk(g_timing_mu);
-    g_timed.push_back({ea, eb, flops});
+    g_timed.push_back({ea, eb, flops, st});
   }
   return PHIKS_OK;
 }

@@ -4,8 +4,9 @@
 
 Plans the batch once (d in {2, 3}, n_mu in 16..128, Chebyshev second-derivative
 operators, tau log-uniform in [1e-4, 1e-2], phi_0..phi_3 of one vector, tolerance
-2^-53 ||v||), then runs `reps` calls of phiks_batch_apply on the null stream and prints
-one JSON line with the call time and the mu-mode kernel time.  Meant for profilers
+2^-53 ||v||), then runs one warm-up call, `reps` timed calls of phiks_batch_apply on the
+null stream and one more call with kernel events, and prints one JSON line with the call
+time and the mu-mode kernel time of the last call.  Meant for profilers
 (rocprofv3 --kernel-trace / --pmc): the process launches nothing but the plan's
 kernels and the timed calls."""
 import argparse
@@ -40,18 +41,22 @@ def main():
     ph.phiks_batch_apply(batch, vp, op, ws.ptr, ws.nbytes)
     ph.synchronize()
     print(f"[run_batch] {len(problems)} problems warm", flush=True)
-    ph.phiks_kernel_timing_read()
-    ph.phiks_kernel_timing(True)
+    # call time without kernel events (a timestamped dispatch idles the GPU after each
+    # launch), then one call with them for the mu-mode kernel time
     t0 = time.perf_counter()
     for _ in range(args.reps):
         ph.phiks_batch_apply(batch, vp, op, ws.ptr, ws.nbytes)
     ph.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / args.reps
+    ph.phiks_kernel_timing_read()
+    ph.phiks_kernel_timing(True)
+    ph.phiks_batch_apply(batch, vp, op, ws.ptr, ws.nbytes)
+    ph.synchronize()
     ph.phiks_kernel_timing(False)
     k_ms, k_launch, k_flops = ph.phiks_kernel_timing_read()
     print(json.dumps({"problems": len(problems), "total_dofs": sum(b.N for b in problems),
-                      "apply_ms": ms, "mu_mode_ms_per_call": k_ms / args.reps,
-                      "mu_mode_launches_per_call": k_launch / args.reps,
+                      "apply_ms": ms, "mu_mode_ms_per_call": k_ms,
+                      "mu_mode_launches_per_call": k_launch,
                       "mu_mode_tflops": k_flops / (k_ms * 1e-3) / 1e12 if k_ms > 0 else 0.0}),
           flush=True)
     batch.close()
