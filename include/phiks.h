@@ -214,6 +214,10 @@ int phiks_kernel_timing_read(double* total_ms, int64_t* launches, double* flops)
  * aligned.  Every out[i] is bitwise what phiks_apply returns for problem i alone.
  * Stream-ordered; calls on one batch must not overlap (they share its launch tables,
  * and a call waits on the host until the previous call's table upload has run).
+ * The launches depend only on the batch and the pointers (v, out, ws): the second
+ * call with one pointer set captures them into a HIP graph, and later calls with the
+ * same set replay it (one graph launch, no host scheduling).  A call with other
+ * pointers, or with kernel timing on, runs eagerly and drops the graph.
  */
 typedef struct phiks_batch_s* phiks_batch_t;
 

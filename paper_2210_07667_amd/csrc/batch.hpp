@@ -44,6 +44,12 @@ struct phiks_batch_s {
   std::vector<size_t> ws_off;             // per-problem workspace offsets, doubles
   size_t ws_doubles = 0;
   GroupTables tab;
+  // The launches of the last pointer set (v, out, ws), captured into a graph the second
+  // time that set is applied and replayed while it stays the same (phiks_batch_apply).
+  std::vector<const void*> graph_key;
+  hipGraphExec_t graph = nullptr;
+  hipStream_t capture_stream = nullptr;   // capture only: nothing executes on it
+  hipStream_t graph_stream = nullptr;     // stream of the graph's last launch
 };
 
 namespace {
@@ -352,8 +358,8 @@ void build_group_schedule(const GroupWork& W, BatchSchedule& S) {
   }
 }
 
-// Uploads S's tables (growing them if needed) and issues its launches on st.
-int run_group(GroupTables& T, const BatchSchedule& S, hipStream_t st) {
+// Uploads S's tables (growing them if needed) on st.
+int upload_group(GroupTables& T, const BatchSchedule& S, hipStream_t st) {
   // the previous call's upload must have read the staging buffer before it is rewritten
   if (T.uploaded) HIP_OK(hipEventSynchronize(T.upload_done));
   if (!T.upload_done) HIP_OK(hipEventCreateWithFlags(&T.upload_done, hipEventDisableTiming));
@@ -382,6 +388,12 @@ int run_group(GroupTables& T, const BatchSchedule& S, hipStream_t st) {
   HIP_OK(hipMemcpyAsync(T.dev, T.host, need, hipMemcpyHostToDevice, st));
   HIP_OK(hipEventRecord(T.upload_done, st));
   T.uploaded = true;
+  return PHIKS_OK;
+}
+
+// Issues S's launches on st (their tables uploaded by upload_group).  Kernel launches
+// only, so the sequence can be captured into a graph.
+int issue_group(const GroupTables& T, const BatchSchedule& S, hipStream_t st) {
   const char* dev = (const char*)T.dev;
   for (const GroupedLaunch& L : S.launches) {
     if (L.kind == StepKind::Combine) {
@@ -395,6 +407,43 @@ int run_group(GroupTables& T, const BatchSchedule& S, hipStream_t st) {
     } else {
       RET_IF(launch_grouped(L, dev, EpiStore{1.0, 0.0}, st));
     }
+  }
+  return PHIKS_OK;
+}
+
+int run_group(GroupTables& T, const BatchSchedule& S, hipStream_t st) {
+  RET_IF(upload_group(T, S, st));
+  return issue_group(T, S, st);
+}
+
+// Releases a batch's captured graph once its last launch has finished.
+void drop_graph(phiks_batch_s& B) {
+  if (!B.graph) return;
+  (void)hipStreamSynchronize(B.graph_stream);
+  (void)hipGraphExecDestroy(B.graph);
+  B.graph = nullptr;
+}
+
+// Captures S's launches (tables already uploaded) into B.graph on B's capture stream.
+int capture_group(phiks_batch_s& B, const BatchSchedule& S) {
+  if (!B.capture_stream) HIP_OK(hipStreamCreateWithFlags(&B.capture_stream, hipStreamNonBlocking));
+  HIP_OK(hipStreamBeginCapture(B.capture_stream, hipStreamCaptureModeThreadLocal));
+  const int rc = issue_group(B.tab, S, B.capture_stream);
+  hipGraph_t g = nullptr;
+  const hipError_t ec = hipStreamEndCapture(B.capture_stream, &g);
+  if (rc != PHIKS_OK || ec != hipSuccess || !g) {
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipGetLastError();
+    set_error("capture of the batched launches failed");
+    return PHIKS_EDEVICE;
+  }
+  const hipError_t ei = hipGraphInstantiate(&B.graph, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (ei != hipSuccess) {
+    B.graph = nullptr;
+    (void)hipGetLastError();
+    set_error("instantiation of the batched launch graph failed");
+    return PHIKS_EDEVICE;
   }
   return PHIKS_OK;
 }
@@ -419,6 +468,8 @@ void phiks_batch_destroy(phiks_batch_t batch) {
   // Waits for the batch's stream, then frees.  (A host function queued on the stream
   // may not call the HIP API, and the pinned tables need hipHostFree.)
   (void)hipStreamSynchronize(batch->stream);
+  drop_graph(*batch);
+  if (batch->capture_stream) (void)hipStreamDestroy(batch->capture_stream);
   if (batch->dmem) (void)hipFree(batch->dmem);
   free_group_tables(batch->tab);
   delete batch;
@@ -536,6 +587,19 @@ int phiks_batch_apply(phiks_batch_t batch, const double* const* v, double* const
     set_error("batch workspace must be 16-byte aligned");
     return PHIKS_EINVAL;
   }
+  hipStream_t st = (hipStream_t)hip_stream;
+  // The launches depend only on the batch and the pointers: the second call with one
+  // pointer set captures them into a graph, later calls with that set replay it (no
+  // schedule, no upload, one launch).  Calls with kernel timing on stay eager.
+  std::vector<const void*> key(v, v + B.count);
+  key.insert(key.end(), out, out + B.count);
+  key.push_back(ws);
+  const bool timing = kernel_timing_on();
+  if (!timing && B.graph && key == B.graph_key) {
+    HIP_OK(hipGraphLaunch(B.graph, st));
+    B.graph_stream = st;
+    return PHIKS_OK;
+  }
   GroupWork W;
   W.p = B.p;
   W.ns = B.ns;
@@ -547,7 +611,13 @@ int phiks_batch_apply(phiks_batch_t batch, const double* const* v, double* const
   }
   BatchSchedule S;
   build_group_schedule(W, S);
-  RET_IF(run_group(B.tab, S, (hipStream_t)hip_stream));
+  drop_graph(B);   // the upload below rewrites the tables a graph reads
+  const bool repeat = (key == B.graph_key);
+  B.graph_key.swap(key);
+  RET_IF(upload_group(B.tab, S, st));
+  if (timing || !repeat || capture_group(B, S) != PHIKS_OK) return issue_group(B.tab, S, st);
+  HIP_OK(hipGraphLaunch(B.graph, st));
+  B.graph_stream = st;
   return PHIKS_OK;
 }
 

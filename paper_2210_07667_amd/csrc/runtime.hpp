@@ -59,6 +59,11 @@ bool g_timing = false;
 std::vector<TimedLaunch> g_timed;
 std::vector<hipEvent_t> g_event_pool;
 
+bool kernel_timing_on() {
+  std::lock_guard<std::mutex> lk(g_timing_mu);
+  return g_timing;
+}
+
 hipEvent_t pooled_event() {
   if (!g_event_pool.empty()) {
     hipEvent_t e = g_event_pool.back();

@@ -4,8 +4,9 @@
 
 Plans the batch once (d in {2, 3}, n_mu in 16..128, Chebyshev second-derivative
 operators, tau log-uniform in [1e-4, 1e-2], phi_0..phi_3 of one vector, tolerance
-2^-53 ||v||), then runs one warm-up call, `reps` timed calls of phiks_batch_apply on the
-null stream and one more call with kernel events, and prints one JSON line with the call
+2^-53 ||v||), then runs two warm-up calls (eager, then captured into a graph), `reps` timed
+calls of phiks_batch_apply on the null stream (graph replays) and one more call with kernel
+events (eager), and prints one JSON line with the call
 time and the mu-mode kernel time of the last call.  Meant for profilers
 (rocprofv3 --kernel-trace / --pmc): the process launches nothing but the plan's
 kernels and the timed calls."""
@@ -38,7 +39,8 @@ def main():
     outs = [ph.DeviceArray(4 * b.N) for b in problems]
     ws = ph.DeviceArray(batch.workspace_size() // 8 + 1)
     vp, op = [v.ptr for v in dv], [o.ptr for o in outs]
-    ph.phiks_batch_apply(batch, vp, op, ws.ptr, ws.nbytes)
+    for _ in range(2):   # eager, then captured into the graph the timed calls replay
+        ph.phiks_batch_apply(batch, vp, op, ws.ptr, ws.nbytes)
     ph.synchronize()
     print(f"[run_batch] {len(problems)} problems warm", flush=True)
     # call time without kernel events (a timestamped dispatch idles the GPU after each

@@ -137,3 +137,46 @@ def test_full_batched_workload_sampled():
         assert batch.info(i) == info
         assert np.array_equal(outs[i], ref), (i, problems[i].n)
     print(f"[batch 512] sampled {sample}: bitwise equal")
+
+
+def test_batch_graph_replays_match_eager():
+    """phiks_batch_apply captures its launches into a HIP graph on the second call with
+    one pointer set and replays it on later calls.  Every call's outputs (cleared to NaN
+    before it, with an unrelated single-problem call and a synchronisation between the
+    calls) must be bitwise the first, eager call's; switching to other output pointers
+    runs eagerly, and the next call with the first set runs eagerly and the one after it
+    captures again."""
+    problems = workloads.config_batch(count=24, seed=7)
+    p, ns = 3, 1
+    norms = [np.linalg.norm(b.v) for b in problems]
+    batch = ph.phiks_batch_plan([b.A for b in problems], [b.tau for b in problems], p, ns, TOL,
+                                vnorms=norms)
+    dv = [ph.DeviceArray.from_numpy(b.v) for b in problems]
+    outs = [ph.DeviceArray(ns * (p + 1) * b.N) for b in problems]
+    outs2 = [ph.DeviceArray(ns * (p + 1) * b.N) for b in problems]
+    ws = ph.DeviceArray(batch.workspace_size() // 8 + 1)
+    nans = [ph.DeviceArray.from_numpy(np.full(o.n, np.nan)) for o in outs]
+    ph.batch_apply_arrays(batch, dv, outs, ws)          # first sight of these pointers: eager
+    ph.synchronize()
+    ref = [o.to_numpy() for o in outs]
+    assert all(np.isfinite(r).all() for r in ref)
+    b0 = problems[0]
+    plan = ph.phiks_plan(b0.A, b0.tau, p, ns, TOL, "same_vector", [norms[0]])
+    # calls: 0 capture + launch, 1-2 replays, 3 eager (after the switch), 4 capture, 5 replay
+    for call in range(6):
+        for o, z in zip(outs, nans):
+            ph.copy_device(o, z)
+        print(f"[batch graph] call {call}", flush=True)
+        ph.batch_apply_arrays(batch, dv, outs, ws)
+        ph.synchronize()
+        for i, o in enumerate(outs):
+            assert np.array_equal(o.to_numpy(), ref[i]), (call, i, problems[i].n)
+        ph.apply_arrays(plan, dv[0])                     # eager work between the calls
+        ph.synchronize()
+        if call == 2:
+            ph.batch_apply_arrays(batch, dv, outs2, ws)  # other pointers: eager
+            ph.synchronize()
+            for i, o in enumerate(outs2):
+                assert np.array_equal(o.to_numpy(), ref[i]), ("switch", i)
+    plan.close()
+    batch.close()
