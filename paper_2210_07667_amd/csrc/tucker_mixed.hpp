@@ -1,6 +1,7 @@
-// Mixed-precision mu-mode products: launches of gemm_f32_kernel (FP32 MFMA) and
-// gemm_bf16x3_kernel (three BF16 MFMA products per FP32 product), and the Tucker chain
-// over either.  Included once, by phiks.hip, after tucker_f64.hpp.
+// Mixed-precision mu-mode products: launches of the FP32-MFMA kernels (gemm_f32_kernel,
+// gemm_f32_dl_kernel) and of the BF16x3 kernels (three BF16 MFMA products per FP32
+// product: gemm_bf16x3_kernel, gemm_bf16x3_dl_kernel), and the Tucker chain over either,
+// including the BF16x3 pair chains.  Included once, by phiks.hip, after tucker_f64.hpp.
 #pragma once
 #include <vector>
 
@@ -18,6 +19,9 @@
 #endif
 #ifndef PHIKS_BF_PAIR
 #define PHIKS_BF_PAIR 1  // 1: BF16x3 chains keep split pairs between modes where they can
+#endif
+#ifndef PHIKS_MIXED_LC_DL
+#define PHIKS_MIXED_LC_DL 1  // 1: mixed-precision squaring launches on the direct-to-LDS kernels
 #endif
 
 namespace {
@@ -49,9 +53,6 @@ int launch_grid(void (*kern)(GemmArgs, Epi), GemmArgs g, const Epi& epi, hipStre
 }
 
 // The direct-to-LDS kernels' squaring epilogue needs lincomb_dl_ok; other epilogues pass.
-#ifndef PHIKS_MIXED_LC_DL
-#define PHIKS_MIXED_LC_DL 1  // 1: mixed-precision squaring launches on the direct-to-LDS kernels
-#endif
 template <class Epi>
 bool lincomb_ok(const GemmArgs& g, const Epi& epi) {
   if constexpr (std::is_same<Epi, EpiLinComb>::value)
