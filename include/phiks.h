@@ -283,6 +283,35 @@ int phiks_server_stats(phiks_server_t server, phiks_server_stats_t* out);
 void phiks_server_destroy(phiks_server_t server);
 
 /*
+ * The server's scheduling policy, host only (no device work; for tests of the policy
+ * without a GPU).  The worker and the plan cache decide through exactly these rules.
+ *
+ * phiks_server_select_group -- the next group from `count` pending requests in arrival
+ * order, request i of class (p[i], n_scales[i]) needing ws_doubles[i] workspace
+ * doubles: the requests of the first one's class, in order, while their workspaces
+ * (each rounded up to an even count of doubles) fit arena_doubles together, at most
+ * max_group of them; the first request of that class that does not fit ends the group.
+ * Writes the chosen indices to picked (room for count) and their number to npicked.
+ *
+ * phiks_server_select_evictions -- plans to evict before a new plan of new_bytes
+ * joins a cache holding cache_bytes with room for capacity bytes; entry i holds
+ * bytes[i], is held by refs[i] admitted requests and was last used at tick
+ * last_use[i].  Unreferenced entries, least recently used first, until the new plan
+ * fits; none beyond the unreferenced ones (the cache then runs over its budget).
+ * Writes the chosen indices, in eviction order, to victims (room for count) and their
+ * number to nvictims.
+ *
+ * Both return PHIKS_EINVAL for a negative count, max_group < 1 or a NULL array that
+ * count requires, else PHIKS_OK.
+ */
+int phiks_server_select_group(int count, const int* p, const int* n_scales,
+                              const size_t* ws_doubles, size_t arena_doubles, int max_group,
+                              int* picked, int* npicked);
+int phiks_server_select_evictions(int count, const size_t* bytes, const int* refs,
+                                  const uint64_t* last_use, size_t cache_bytes, size_t new_bytes,
+                                  size_t capacity, int* victims, int* nvictims);
+
+/*
  * Elementwise device vector operations for time integrators built on the phi-actions
  * (the nonlinear terms and stage combinations of the exponential integrators of
  * Section 4): out[k] for k < n, with y[k] read as 0 when y is NULL.

@@ -49,7 +49,8 @@ SYMBOLS = ("phiks_plan", "phiks_apply", "phiks_combine", "phiks_workspace_size",
            "phiks_batch_apply", "phiks_batch_workspace_size", "phiks_batch_info",
            "phiks_batch_destroy", "phiks_server_create", "phiks_server_register", "phiks_server_submit",
            "phiks_server_wait", "phiks_server_stats", "phiks_server_destroy",
-           "phiks_vector_op", "phiks_plan_complex", "phiks_plan_params_complex")
+           "phiks_vector_op", "phiks_plan_complex", "phiks_plan_params_complex",
+           "phiks_server_select_group", "phiks_server_select_evictions")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with "
@@ -134,6 +135,15 @@ _lib.phiks_server_stats.restype = ctypes.c_int
 _lib.phiks_server_stats.argtypes = [_vp, ctypes.POINTER(ServerStats)]
 _lib.phiks_server_destroy.restype = None
 _lib.phiks_server_destroy.argtypes = [_vp]
+_ip = ctypes.POINTER(ctypes.c_int)
+_szp = ctypes.POINTER(ctypes.c_size_t)
+_lib.phiks_server_select_group.restype = ctypes.c_int
+_lib.phiks_server_select_group.argtypes = [ctypes.c_int, _ip, _ip, _szp, ctypes.c_size_t,
+                                           ctypes.c_int, _ip, _ip]
+_lib.phiks_server_select_evictions.restype = ctypes.c_int
+_lib.phiks_server_select_evictions.argtypes = [ctypes.c_int, _szp, _ip,
+                                               ctypes.POINTER(ctypes.c_uint64), ctypes.c_size_t,
+                                               ctypes.c_size_t, ctypes.c_size_t, _ip, _ip]
 _lib.phiks_plan_complex.restype = ctypes.c_int
 _lib.phiks_plan_complex.argtypes = [ctypes.c_int, _i64p, _dpp, ctypes.c_double, ctypes.c_double,
                                     ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int, _dp,
@@ -549,6 +559,37 @@ def batch_apply_arrays(batch: Batch, vs: Sequence[DeviceArray], outs=None, ws=No
         ws = DeviceArray(batch.workspace_size() // 8 + 1)
     phiks_batch_apply(batch, [v.ptr for v in vs], [o.ptr for o in outs], ws.ptr, ws.nbytes, stream)
     return outs
+
+
+def server_select_group(p: Sequence[int], n_scales: Sequence[int], ws_doubles: Sequence[int],
+                        arena_doubles: int, max_group: int):
+    """The server's next group from pending requests in arrival order (host only): the
+    indices phiks_server_select_group picks."""
+    n = len(p)
+    pa = (ctypes.c_int * max(n, 1))(*p)
+    na = (ctypes.c_int * max(n, 1))(*n_scales)
+    wa = (ctypes.c_size_t * max(n, 1))(*ws_doubles)
+    picked = (ctypes.c_int * max(n, 1))()
+    cnt = ctypes.c_int()
+    _check(_lib.phiks_server_select_group(n, pa, na, wa, int(arena_doubles), int(max_group), picked,
+                                          ctypes.byref(cnt)), "phiks_server_select_group")
+    return [picked[i] for i in range(cnt.value)]
+
+
+def server_select_evictions(nbytes: Sequence[int], refs: Sequence[int], last_use: Sequence[int],
+                            cache_bytes: int, new_bytes: int, capacity: int):
+    """The plan-cache entries the server would evict for a new plan (host only): the
+    indices phiks_server_select_evictions picks, in eviction order."""
+    n = len(nbytes)
+    ba = (ctypes.c_size_t * max(n, 1))(*nbytes)
+    ra = (ctypes.c_int * max(n, 1))(*refs)
+    la = (ctypes.c_uint64 * max(n, 1))(*last_use)
+    victims = (ctypes.c_int * max(n, 1))()
+    cnt = ctypes.c_int()
+    _check(_lib.phiks_server_select_evictions(n, ba, ra, la, int(cache_bytes), int(new_bytes),
+                                              int(capacity), victims, ctypes.byref(cnt)),
+           "phiks_server_select_evictions")
+    return [victims[i] for i in range(cnt.value)]
 
 
 def vector_op(op: int, n: int, a: float, x_ptr: int, b: float, y_ptr: Optional[int],

@@ -79,6 +79,63 @@ struct InFlightGroup {
   std::vector<ServerRequest*> reqs;
 };
 
+// ------------------------------------------------ scheduling policy (host only)
+// The worker and the plan cache decide through these two functions alone, so the policy
+// can be exercised without a device (phiks_server_select_group / _select_evictions).
+
+struct GroupCandidate {
+  int p, ns;
+  size_t ws;   // workspace doubles the request may need
+};
+
+// The next group from the pending requests c (arrival order): the requests with the
+// first one's (p, n_scales), in order, while their workspaces (each rounded up to an
+// even count of doubles) fit the arena together, at most max_group of them.  The first
+// request of that class that does not fit ends the group, so none overtakes another of
+// its class; requests of other classes wait for a later group.  Indices into c.
+std::vector<int> select_group(const std::vector<GroupCandidate>& c, size_t arena_doubles,
+                              int max_group) {
+  std::vector<int> g;
+  if (c.empty()) return g;
+  const int p0 = c[0].p, ns0 = c[0].ns;
+  size_t ws = 0;
+  for (int i = 0; i < (int)c.size() && (int)g.size() < max_group; ++i) {
+    if (c[i].p != p0 || c[i].ns != ns0) continue;
+    const size_t need = (c[i].ws + 1) & ~(size_t)1;
+    if (ws + need > arena_doubles) break;
+    ws += need;
+    g.push_back(i);
+  }
+  return g;
+}
+
+struct CacheEntryDesc {
+  size_t bytes;
+  int refs;            // requests admitted and not yet completed
+  uint64_t last_use;   // LRU tick
+};
+
+// Plans to evict before a new plan of new_bytes joins a cache of cache_bytes with
+// capacity cap: unreferenced entries, least recently used first, until the new plan
+// fits; when every remaining entry is referenced the cache runs over its budget.
+// Indices into e, in eviction order.
+std::vector<int> select_evictions(const std::vector<CacheEntryDesc>& e, size_t cache_bytes,
+                                  size_t new_bytes, size_t cap) {
+  std::vector<int> v;
+  std::vector<char> gone(e.size(), 0);
+  while (cache_bytes + new_bytes > cap) {
+    int victim = -1;
+    for (int i = 0; i < (int)e.size(); ++i)
+      if (!gone[i] && e[i].refs == 0 && (victim < 0 || e[i].last_use < e[victim].last_use))
+        victim = i;
+    if (victim < 0) break;
+    gone[victim] = 1;
+    cache_bytes -= e[victim].bytes;
+    v.push_back(victim);
+  }
+  return v;
+}
+
 uint64_t fnv1a(const char* p, size_t n, uint64_t h = 1469598103934665603ull) {
   for (size_t i = 0; i < n; ++i) {
     h ^= (unsigned char)p[i];
@@ -149,15 +206,16 @@ int server_plan(phiks_server_s& S, ServerRequest* r) {
     // least recently used plans that no admitted request holds, until the new one fits
     const size_t cap = S.budget > S.arena_doubles * sizeof(double)
                            ? S.budget - S.arena_doubles * sizeof(double) : 0;
-    while (S.cache_bytes + bytes > cap) {
-      auto victim = S.cache.end();
-      for (auto it = S.cache.begin(); it != S.cache.end(); ++it)
-        if (it->second.refs == 0 && (victim == S.cache.end() || it->second.last_use < victim->second.last_use))
-          victim = it;
-      if (victim == S.cache.end()) break;  // every cached plan is in use: run over budget
-      S.cache_bytes -= victim->second.bytes;
-      evict.push_back(victim->second.plan);
-      S.cache.erase(victim);
+    std::vector<decltype(S.cache)::iterator> its;
+    std::vector<CacheEntryDesc> desc;
+    for (auto it = S.cache.begin(); it != S.cache.end(); ++it) {
+      its.push_back(it);
+      desc.push_back({it->second.bytes, it->second.refs, it->second.last_use});
+    }
+    for (int i : select_evictions(desc, S.cache_bytes, bytes, cap)) {
+      S.cache_bytes -= its[i]->second.bytes;
+      evict.push_back(its[i]->second.plan);
+      S.cache.erase(its[i]);
       ++S.st.evictions;
     }
     auto ins = S.cache.emplace(r->key, CachedPlan{plan, bytes, 1, ++S.tick});
@@ -178,17 +236,18 @@ void server_worker(phiks_server_s* Sp) {
       std::unique_lock<std::mutex> lk(S.mu);
       S.cv_work.wait(lk, [&] { return S.stop || !S.pending.empty(); });
       if (S.pending.empty()) break;  // stop requested and drained
-      const int p0 = S.pending.front()->p, ns0 = S.pending.front()->ns;
-      size_t ws = 0;
-      for (auto it = S.pending.begin(); it != S.pending.end() && (int)group.size() < S.max_group;) {
-        ServerRequest* r = *it;
-        if (r->p != p0 || r->ns != ns0) { ++it; continue; }
-        const size_t need = (r->ws_bound + 1) & ~(size_t)1;
-        if (ws + need > S.arena_doubles) break;
-        ws += need;
-        group.push_back(r);
-        it = S.pending.erase(it);
+      std::vector<GroupCandidate> cand;
+      for (const ServerRequest* r : S.pending) cand.push_back({r->p, r->ns, r->ws_bound});
+      const std::vector<int> pick = select_group(cand, S.arena_doubles, S.max_group);
+      std::vector<char> taken(S.pending.size(), 0);
+      for (int i : pick) {
+        group.push_back(S.pending[i]);
+        taken[i] = 1;
       }
+      std::deque<ServerRequest*> rest;
+      for (size_t i = 0; i < S.pending.size(); ++i)
+        if (!taken[i]) rest.push_back(S.pending[i]);
+      S.pending.swap(rest);
     }
     // plans (cache lookups; misses are planned here, overlapping earlier groups)
     std::vector<ServerRequest*> run;
@@ -276,6 +335,32 @@ void server_completer(phiks_server_s* Sp) {
 
 extern "C" {
 
+int phiks_server_select_group(int count, const int* p, const int* n_scales,
+                              const size_t* ws_doubles, size_t arena_doubles, int max_group,
+                              int* picked, int* npicked) {
+  if (count < 0 || max_group < 1 || !npicked || (count > 0 && (!p || !n_scales || !ws_doubles || !picked)))
+    return PHIKS_EINVAL;
+  std::vector<GroupCandidate> c(count);
+  for (int i = 0; i < count; ++i) c[i] = {p[i], n_scales[i], ws_doubles[i]};
+  const std::vector<int> g = select_group(c, arena_doubles, max_group);
+  for (size_t i = 0; i < g.size(); ++i) picked[i] = g[i];
+  *npicked = (int)g.size();
+  return PHIKS_OK;
+}
+
+int phiks_server_select_evictions(int count, const size_t* bytes, const int* refs,
+                                  const uint64_t* last_use, size_t cache_bytes, size_t new_bytes,
+                                  size_t capacity, int* victims, int* nvictims) {
+  if (count < 0 || !nvictims || (count > 0 && (!bytes || !refs || !last_use || !victims)))
+    return PHIKS_EINVAL;
+  std::vector<CacheEntryDesc> e(count);
+  for (int i = 0; i < count; ++i) e[i] = {bytes[i], refs[i], last_use[i]};
+  const std::vector<int> v = select_evictions(e, cache_bytes, new_bytes, capacity);
+  for (size_t i = 0; i < v.size(); ++i) victims[i] = v[i];
+  *nvictims = (int)v.size();
+  return PHIKS_OK;
+}
+
 int phiks_server_create(size_t hbm_budget, size_t workspace_bytes, int max_group,
                         void* hip_stream, phiks_server_t* out) {
   if (!out) return PHIKS_EINVAL;
@@ -356,7 +441,8 @@ int phiks_server_submit(phiks_server_t server, int64_t op_id, double tau, int p,
   r->op = &it->second;
   const int64_t t = std::max<int64_t>({(int64_t)kQMax - 1, (int64_t)p, 1});
   r->ws_bound = (size_t)(2 * t + 2 * p) * r->op->N;
-  if (r->ws_bound > server->arena_doubles) {
+  // refused unless select_group could admit it alone (same rounding to even doubles)
+  if (((r->ws_bound + 1) & ~(size_t)1) > server->arena_doubles) {
     delete r;
     set_error("request workspace exceeds the server's workspace arena");
     return PHIKS_EWORKSPACE;
