@@ -10,7 +10,9 @@
 //   * admission: the worker takes pending requests in arrival order that share the
 //     first one's (p, n_scales), as long as their workspaces fit the arena and the
 //     group has at most max_group requests (continuous batching: whatever arrived
-//     while the previous group ran forms the next one).
+//     while the previous group ran forms the next one).  Both this choice and the
+//     eviction choice are pure host functions (select_group, select_evictions), also
+//     exported for tests of the policy without a device.
 //   * execution: a group runs as the grouped launches of phiks_batch_apply (so every
 //     result is bitwise what phiks_apply returns for that request alone); host
 //     planning of the next group overlaps the device work of the previous ones.
