@@ -49,6 +49,7 @@ struct phiks_batch_s {
   std::vector<const void*> graph_key;
   hipGraphExec_t graph = nullptr;
   hipStream_t capture_stream = nullptr;   // capture only: nothing executes on it
+  std::vector<hipStream_t> fork_streams;  // capture only: a step's partitions fork onto these
   hipStream_t graph_stream = nullptr;     // stream of the graph's last launch
 };
 
@@ -67,6 +68,10 @@ struct StepGemm {
   int64_t YN;
 };
 
+#ifndef PHIKS_BATCH_FORK
+#define PHIKS_BATCH_FORK 4  // streams a captured step's partitions fork onto (0: one chain)
+#endif
+
 struct GroupedLaunch {
   StepKind kind;
   bool kc = false, vec = false, lincomb = false;
@@ -77,6 +82,7 @@ struct GroupedLaunch {
   int n = 0;
   int64_t total = 0;     // GEMM: tiles; Combine: largest N
   double flops = 0.0;    // GEMM: algorithmic 2 M N K over all items and batches
+  int step = 0;          // launches of one step touch disjoint problems
 };
 
 // Host builder of one call's launches and their tables.
@@ -84,6 +90,7 @@ struct BatchSchedule {
   std::vector<GroupedLaunch> launches;
   std::vector<char> buf;
   EpiLinComb lin;
+  int steps = 0;
 
   size_t put(const void* src, size_t bytes) {
     const size_t off = (buf.size() + 15) & ~(size_t)15;
@@ -115,6 +122,7 @@ struct BatchSchedule {
   }
 
   void add_gemm_step(const std::vector<StepGemm>& items) {
+    const int step = steps++;
     // partition by (layout, tile class, 16-byte loads, direct-to-LDS, epilogue)
     for (int kc = 0; kc < 2; ++kc)
       for (int tile = 0; tile < kClasses; ++tile)
@@ -157,6 +165,7 @@ struct BatchSchedule {
               L.flops = flops;
               L.items_off = put(part.data(), part.size() * sizeof(GroupItem));
               L.first_off = put(first.data(), first.size() * sizeof(int64_t));
+              L.step = step;
               launches.push_back(L);
             }
   }
@@ -168,6 +177,7 @@ struct BatchSchedule {
     L.n = (int)items.size();
     for (const CombineArgs& a : items) L.total = std::max(L.total, a.N);
     L.items_off = put(items.data(), items.size() * sizeof(CombineArgs));
+    L.step = steps++;
     launches.push_back(L);
   }
 };
@@ -391,22 +401,54 @@ int upload_group(GroupTables& T, const BatchSchedule& S, hipStream_t st) {
   return PHIKS_OK;
 }
 
+int issue_one(const GroupedLaunch& L, const char* dev, const BatchSchedule& S, hipStream_t st) {
+  if (L.kind == StepKind::Combine) {
+    const int64_t blocks = std::min<int64_t>((L.total + 255) / 256, 1024);
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(combine_grouped_kernel, dim3((unsigned)blocks, (unsigned)L.n), dim3(256),
+                       0, st, (const CombineArgs*)(dev + L.items_off));
+    CHECK_LAUNCH();
+    return PHIKS_OK;
+  }
+  if (L.lincomb) return launch_grouped(L, dev, S.lin, st);
+  return launch_grouped(L, dev, EpiStore{1.0, 0.0}, st);
+}
+
 // Issues S's launches on st (their tables uploaded by upload_group).  Kernel launches
 // only, so the sequence can be captured into a graph.
 int issue_group(const GroupTables& T, const BatchSchedule& S, hipStream_t st) {
   const char* dev = (const char*)T.dev;
-  for (const GroupedLaunch& L : S.launches) {
-    if (L.kind == StepKind::Combine) {
-      const int64_t blocks = std::min<int64_t>((L.total + 255) / 256, 1024);
-      (void)hipGetLastError();
-      hipLaunchKernelGGL(combine_grouped_kernel, dim3((unsigned)blocks, (unsigned)L.n), dim3(256),
-                         0, st, (const CombineArgs*)(dev + L.items_off));
-      CHECK_LAUNCH();
-    } else if (L.lincomb) {
-      RET_IF(launch_grouped(L, dev, S.lin, st));
-    } else {
-      RET_IF(launch_grouped(L, dev, EpiStore{1.0, 0.0}, st));
+  for (const GroupedLaunch& L : S.launches) RET_IF(issue_one(L, dev, S, st));
+  return PHIKS_OK;
+}
+
+// As issue_group, for capture on st: the launches of one step (disjoint problems) are
+// forked over the aux streams and joined back before the next step, so the graph may
+// run a step's small partitions beside its large one.  ev: events for the fork and
+// join points (hipEventDisableTiming), at least launches + steps of them.
+int issue_group_forked(const GroupTables& T, const BatchSchedule& S, hipStream_t st,
+                       const std::vector<hipStream_t>& aux, const std::vector<hipEvent_t>& ev) {
+  const char* dev = (const char*)T.dev;
+  const std::vector<GroupedLaunch>& Ls = S.launches;
+  size_t e = 0;
+  for (size_t i = 0; i < Ls.size();) {
+    size_t j = i;
+    while (j < Ls.size() && Ls[j].step == Ls[i].step) ++j;
+    if (j - i == 1 || aux.empty()) {
+      for (size_t k = i; k < j; ++k) RET_IF(issue_one(Ls[k], dev, S, st));
+      i = j;
+      continue;
     }
+    HIP_OK(hipEventRecord(ev[e], st));
+    const hipEvent_t fork = ev[e++];
+    const size_t used = std::min(aux.size(), j - i);
+    for (size_t a = 0; a < used; ++a) HIP_OK(hipStreamWaitEvent(aux[a], fork, 0));
+    for (size_t k = i; k < j; ++k) RET_IF(issue_one(Ls[k], dev, S, aux[(k - i) % used]));
+    for (size_t a = 0; a < used; ++a) {
+      HIP_OK(hipEventRecord(ev[e], aux[a]));
+      HIP_OK(hipStreamWaitEvent(st, ev[e++], 0));
+    }
+    i = j;
   }
   return PHIKS_OK;
 }
@@ -427,10 +469,26 @@ void drop_graph(phiks_batch_s& B) {
 // Captures S's launches (tables already uploaded) into B.graph on B's capture stream.
 int capture_group(phiks_batch_s& B, const BatchSchedule& S) {
   if (!B.capture_stream) HIP_OK(hipStreamCreateWithFlags(&B.capture_stream, hipStreamNonBlocking));
+  while ((int)B.fork_streams.size() < PHIKS_BATCH_FORK) {
+    hipStream_t a = nullptr;
+    HIP_OK(hipStreamCreateWithFlags(&a, hipStreamNonBlocking));
+    B.fork_streams.push_back(a);
+  }
+  // fork and join points: one per step with several launches, plus one per joined stream
+  std::vector<hipEvent_t> ev(S.launches.size() + (size_t)S.steps);
+  for (hipEvent_t& e : ev) {
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+      for (hipEvent_t& x : ev)
+        if (x) (void)hipEventDestroy(x);
+      set_error("hipEventCreate failed");
+      return PHIKS_EDEVICE;
+    }
+  }
   HIP_OK(hipStreamBeginCapture(B.capture_stream, hipStreamCaptureModeThreadLocal));
-  const int rc = issue_group(B.tab, S, B.capture_stream);
+  const int rc = issue_group_forked(B.tab, S, B.capture_stream, B.fork_streams, ev);
   hipGraph_t g = nullptr;
   const hipError_t ec = hipStreamEndCapture(B.capture_stream, &g);
+  for (hipEvent_t e : ev) (void)hipEventDestroy(e);
   if (rc != PHIKS_OK || ec != hipSuccess || !g) {
     if (g) (void)hipGraphDestroy(g);
     (void)hipGetLastError();
@@ -470,6 +528,7 @@ void phiks_batch_destroy(phiks_batch_t batch) {
   (void)hipStreamSynchronize(batch->stream);
   drop_graph(*batch);
   if (batch->capture_stream) (void)hipStreamDestroy(batch->capture_stream);
+  for (hipStream_t a : batch->fork_streams) (void)hipStreamDestroy(a);
   if (batch->dmem) (void)hipFree(batch->dmem);
   free_group_tables(batch->tab);
   delete batch;
