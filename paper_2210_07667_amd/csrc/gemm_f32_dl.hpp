@@ -1,6 +1,8 @@
 // FP32 MFMA mu-mode product with direct-to-LDS operand loads.  Same products, tile
-// order and epilogues as gemm_f32_kernel; the operand path is the one of
-// gemm_f64_dl.hpp with 16-byte slots holding four floats:
+// order and per-element arithmetic as gemm_f32_kernel; the squaring epilogue streams its
+// FP64 pre-step tensors through LDS (lincomb_lds_epilogue_f32, also used by the BF16x3
+// direct-to-LDS kernel).  The operand path is the one of gemm_f64_dl.hpp with 16-byte
+// slots holding four floats:
 //  * k-contiguous operand, rows r < R, k < 16 per chunk: slot of (r, k quad kq) is
 //    r*4 + (kq ^ ((r / 4) mod 4)).  Lane group lk = l >> 4 reads quad lk of its row
 //    (ds_read_b128) and feeds four MFMA steps: step h takes k = 4 lk + h, for both
