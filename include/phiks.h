@@ -217,7 +217,8 @@ int phiks_kernel_timing_read(double* total_ms, int64_t* launches, double* flops)
  * The launches depend only on the batch and the pointers (v, out, ws): the second
  * call with one pointer set captures them into a HIP graph, and later calls with the
  * same set replay it (one graph launch, no host scheduling).  A call with other
- * pointers, or with kernel timing on, runs eagerly and drops the graph.
+ * pointers, or with kernel timing on, runs eagerly and drops the graph; dropping it
+ * waits on the host until the graph's last launch has finished.
  */
 typedef struct phiks_batch_s* phiks_batch_t;
 
