@@ -304,6 +304,18 @@ int batched_expm(const std::vector<ExpmOp>& ops, const std::vector<ExpmRequest>&
   return PHIKS_OK;
 }
 
+// The GEMM views of a mu-mode product hold prod(n_<mu) and prod(n_>mu) (times `mult`
+// doubles per value: 2 for complex data) in 32-bit fields; shapes beyond that are refused.
+bool views_fit_int32(int d, const int64_t* n, int64_t mult) {
+  for (int mu = 0; mu < d; ++mu) {
+    int64_t lo = mult, hi = 1;
+    for (int k = 0; k < mu; ++k) lo *= n[k];
+    for (int k = mu + 1; k < d; ++k) hi *= n[k];
+    if (lo > 0x7fffffffLL || hi > 0x7fffffffLL) return false;
+  }
+  return true;
+}
+
 int validate_problem(int d, const int64_t* n, const double* const* A, double tau, int p,
                      int n_scales, double tol, int task, const double* vnorms) {
   if (d < 1 || d > PHIKS_MAX_D || !n || !A) return PHIKS_EINVAL;
@@ -318,6 +330,10 @@ int validate_problem(int d, const int64_t* n, const double* const* A, double tau
     if (N > (int64_t)1 << 40) return PHIKS_EINVAL;
     for (int64_t e = 0; e < n[mu] * n[mu]; ++e)
       if (!std::isfinite(A[mu][e])) return PHIKS_ENONFINITE;
+  }
+  if (!views_fit_int32(d, n, 1)) {
+    set_error("a mode's leading or trailing extent exceeds 2^31 - 1");
+    return PHIKS_EINVAL;
   }
   if (vnorms) {
     const int nv = (task == PHIKS_SAME_VECTOR) ? 1 : p + 1;
@@ -418,6 +434,10 @@ int plan_init_host_complex(phiks_plan_s& P, int d, const int64_t* n, const doubl
     xi.re_hi += r.re_hi;
     xi.im_lo += r.im_lo;
     xi.im_hi += r.im_hi;
+  }
+  if (!views_fit_int32(d, n, 2)) {
+    set_error("a mode's leading or trailing extent exceeds 2^31 - 1");
+    return PHIKS_EINVAL;
   }
   if (vnorms) {
     const int nv = (task == PHIKS_SAME_VECTOR) ? 1 : p + 1;
@@ -923,7 +943,9 @@ int phiks_tucker(int d, const int64_t* n, const double* const* L, const double* 
     if (n[mu] < 1 || n[mu] > PHIKS_MAX_N || !L[mu]) return PHIKS_EINVAL;
     P.n[mu] = n[mu];
     P.N *= n[mu];
+    if (P.N > (int64_t)1 << 40) return PHIKS_EINVAL;
   }
+  if (!views_fit_int32(d, n, 1)) return PHIKS_EINVAL;
   const size_t need = (d >= 2) ? 2 * (size_t)P.N * sizeof(double) : 0;
   if (need > 0 && (!ws || ws_bytes < need)) return PHIKS_EWORKSPACE;
   double* ta = (double*)ws;

@@ -136,6 +136,32 @@ def test_invalid_arguments_are_rejected():
     assert e.value.status == ph.PHIKS_EINVAL
 
 
+def test_shapes_beyond_32_bit_views_are_rejected():
+    """Within the documented limits (n_mu <= 1024, N <= 2^40) but with a mode whose
+    leading extent prod(n_<mu) or trailing extent prod(n_>mu) exceeds 2^31 - 1:
+    refused with EINVAL before any planning, for real and complex operators and for
+    phiks_tucker."""
+    n = [2, 1024, 1024, 1024, 2]                  # N / n_1 = 2^31
+    A = [np.diag(-np.ones(k)) for k in n]          # finite, cheap rectangles
+    with pytest.raises(ph.PhiksError) as e:
+        ph.phiks_plan_params(A, 1e-3, 0, 1, 1e-10)
+    assert e.value.status == ph.PHIKS_EINVAL
+    Ac = [a.astype(complex) for a in A]
+    with pytest.raises(ph.PhiksError) as e:
+        ph.phiks_plan_params_complex(Ac, 1e-3, 0, 1, 1e-10, "same_vector")
+    assert e.value.status == ph.PHIKS_EINVAL
+    # one size smaller fits: every extent is then 2 * 1024 * 1024 * 1023 < 2^31
+    ok = [2, 1024, 1024, 1023, 2]
+    s, q, t = ph.phiks_plan_params([np.diag(-np.ones(k)) for k in ok], 1e-3, 0, 1, 1e-10)
+    assert t >= 1
+    lib = ctypes.CDLL(ph.LIB_PATH)
+    lib.phiks_tucker.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                 ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
+    nn = (ctypes.c_int64 * 5)(*n)
+    Lp = (ctypes.c_void_p * 5)(*([8] * 5))          # never dereferenced: refused first
+    assert lib.phiks_tucker(5, nn, Lp, 8, 8, 8, 1 << 40, None) == ph.PHIKS_EINVAL
+
+
 def test_unreachable_tolerance_gives_enoplan():
     """A tolerance far below what q <= 12 can reach at any s <= 64."""
     A = [workloads.fd2_dirichlet(8)]
