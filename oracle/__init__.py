@@ -11,7 +11,8 @@ helpers, tables or constant generators with it).  Inputs come from the neutral
 Contents (each function cites the passage it follows):
 
 * ``gll``     -- Gauss-Lobatto-Legendre nodes/weights on [0, 1] (Section 3.3).
-* ``tensor``  -- mu-mode product, Tucker operator, vec layout (Section 2, Lemma 1).
+* ``tensor``  -- mu-mode product by explicit loops (``loops.c``, plain C compiled
+                 with gcc), Tucker operator, vec layout (Section 2, Lemma 1).
 * ``expm``    -- small-matrix exponential by scaled Taylor series + squaring
                  (plain definition of exp; the paper uses a Pade variant).
 * ``bound``   -- numerical-range rectangle, quadrature remainder and the (s, q)

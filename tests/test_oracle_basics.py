@@ -66,6 +66,44 @@ def test_mode_product_loops_vs_contraction():
         assert np.allclose(a, b, rtol=1e-14, atol=1e-14)
 
 
+@pytest.mark.parametrize("n", [[1], [17], [5, 1, 3], [33, 7], [6, 5, 4, 3], [64, 3, 40]])
+def test_mode_product_loops_vs_library_contraction(n):
+    """The C loops against numpy.tensordot on every mode, real and complex."""
+    rng = np.random.default_rng(sum(n))
+    v = rng.standard_normal(int(np.prod(n)))
+    vc = v + 1j * rng.standard_normal(v.size)
+    for mu in range(1, len(n) + 1):
+        L = rng.standard_normal((n[mu - 1], n[mu - 1]))
+        Lc = L + 1j * rng.standard_normal(L.shape)
+        for vv, LL in ((v, L), (vc, L), (v, Lc), (vc, Lc)):
+            V = tensor.as_tensor(vv, n)
+            a = tensor.mode_product(V, LL, mu)
+            b = tensor.mode_product_tensordot(V, LL, mu)
+            assert a.shape == V.shape
+            assert np.abs(a - b).max() <= 1e-14 * max(np.abs(b).max(), 1.0), (n, mu)
+
+
+def test_mode_product_loops_exact_on_integers():
+    """Small integer entries make every product and partial sum exact in FP64, so the
+    loops must equal integer arithmetic bit for bit (index or transpose mistakes show
+    as wrong integers)."""
+    rng = np.random.default_rng(11)
+    n = [5, 3, 4, 2]
+    v = rng.integers(-9, 10, int(np.prod(n)))
+    for mu in range(1, len(n) + 1):
+        L = rng.integers(-9, 10, (n[mu - 1], n[mu - 1]))
+        got = tensor.mode_product(tensor.as_tensor(v.astype(float), n), L.astype(float), mu)
+        ref = np.zeros(v.size, dtype=np.int64)
+        nlo = int(np.prod(n[: mu - 1])) if mu > 1 else 1
+        nmu, nhi = n[mu - 1], int(np.prod(n[mu:])) if mu < len(n) else 1
+        for b in range(nhi):
+            for i in range(nmu):
+                for a in range(nlo):
+                    ref[a + nlo * (i + nmu * b)] = sum(
+                        int(L[i, j]) * int(v[a + nlo * (j + nmu * b)]) for j in range(nmu))
+        assert np.array_equal(got.reshape(-1), ref.astype(float)), mu
+
+
 def test_d2_matrix_form():
     """exp(K) v = vec(exp(A_1) V exp(A_2)^T) for d = 2 (Section 1)."""
     rng = np.random.default_rng(3)
@@ -140,6 +178,29 @@ def test_quad_error_vanishes_for_polynomials_up_to_degree():
     e2 = bound.quad_errors(q, 5e-3 + 0j, ell)[ell - 1]
     order = math.log(e1 / e2) / math.log(2)
     assert abs(order - (2 * q - 2 - (ell - 1))) < 0.05
+
+
+def test_rectangle_is_tight():
+    """Each side of the rectangle is attained by a Rayleigh quotient: the extreme
+    eigenvectors of the Hermitian part H = (B + B*)/2 give Re = its edges, those of
+    (B - B*)/(2i) give Im = its edges.  For a normal matrix the rectangle is the
+    bounding box of the eigenvalues."""
+    rng = np.random.default_rng(8)
+    B = rng.standard_normal((9, 9)) + 0.4j * rng.standard_normal((9, 9))
+    a, b, c, d = bound.rectangle(B)
+    H = (B + B.conj().T) / 2
+    S = (B - B.conj().T) / 2j
+    for M, lo, hi, part in ((H, a, b, np.real), (S, c, d, np.imag)):
+        ev, U = np.linalg.eigh(M)
+        for x, edge in ((U[:, 0], lo), (U[:, -1], hi)):
+            r = (x.conj() @ B @ x) / (x.conj() @ x)
+            assert abs(part(r) - edge) <= 1e-12 * max(1.0, abs(edge))
+    Q, _ = np.linalg.qr(rng.standard_normal((6, 6)) + 1j * rng.standard_normal((6, 6)))
+    lam = rng.standard_normal(6) + 1j * rng.standard_normal(6)
+    Nrm = Q @ np.diag(lam) @ Q.conj().T
+    box = bound.rectangle(Nrm)
+    ref = (lam.real.min(), lam.real.max(), lam.imag.min(), lam.imag.max())
+    assert np.allclose(box, ref, atol=1e-12)
 
 
 def test_rectangle_contains_numerical_range():
