@@ -175,6 +175,22 @@ int phiks_plan_info(phiks_plan_t plan, int* s, int* q, int* tucker_paper,
                     int* tucker_exec);
 
 /*
+ * phiks_plan_matrix -- copy one of the plan's small exponentials (Section 3.1) into a
+ * caller buffer, for inspection:
+ *   kind PHIKS_MATRIX_NODE,  0 <= index < q-1 (p > 0):
+ *        exp((1 - theta_{index+1}) tau A_mu / 2^s), theta_1 = 0 < ... < theta_q = 1
+ *        the Gauss-Lobatto nodes on [0, 1];
+ *   kind PHIKS_MATRIX_LEVEL, 0 <= index <= s:  exp(tau A_mu / 2^index).
+ *   mu    0-based mode (the matrix of A_{mu+1})
+ *   dst   device, n[mu]^2 float64, row-major (complex plans: the real form, 2n x 2n,
+ *         2 x 2 blocks [[Re, -Im], [Im, Re]], 4 n[mu]^2 float64)
+ * Stream-ordered device-to-device copy.  Errors: EINVAL, EDEVICE.
+ */
+enum { PHIKS_MATRIX_NODE = 0, PHIKS_MATRIX_LEVEL = 1 };
+int phiks_plan_matrix(phiks_plan_t plan, int mu, int kind, int index, double* dst,
+                      void* hip_stream);
+
+/*
  * Release a plan.  Stream-ordered: its device memory is freed (hipFreeAsync) and its
  * host staging buffers are released after all work already enqueued on the stream the
  * plan was made with; the call itself does not wait.  Work using the plan that was

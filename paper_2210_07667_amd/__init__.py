@@ -37,6 +37,8 @@ PHIKS_BF16X3 = 2
 PHIKS_VOP_AXPBY = 0
 PHIKS_VOP_RATIONAL = 1
 PHIKS_VOP_CUBIC = 2
+PHIKS_MATRIX_NODE = 0
+PHIKS_MATRIX_LEVEL = 1
 
 # every exported entry point of include/phiks.h
 SYMBOLS = ("phiks_plan", "phiks_apply", "phiks_combine", "phiks_workspace_size",
@@ -50,7 +52,8 @@ SYMBOLS = ("phiks_plan", "phiks_apply", "phiks_combine", "phiks_workspace_size",
            "phiks_batch_destroy", "phiks_server_create", "phiks_server_register", "phiks_server_submit",
            "phiks_server_wait", "phiks_server_stats", "phiks_server_destroy",
            "phiks_vector_op", "phiks_plan_complex", "phiks_plan_params_complex",
-           "phiks_server_select_group", "phiks_server_select_evictions")
+           "phiks_server_select_group", "phiks_server_select_evictions",
+           "phiks_plan_matrix")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with "
@@ -69,6 +72,8 @@ _lib.phiks_plan.argtypes = [ctypes.c_int, _i64p, _dpp, ctypes.c_double, ctypes.c
                             _vp, ctypes.POINTER(_vp)]
 _lib.phiks_apply.restype = ctypes.c_int
 _lib.phiks_apply.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]
+_lib.phiks_plan_matrix.restype = ctypes.c_int
+_lib.phiks_plan_matrix.argtypes = [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp, _vp]
 _lib.phiks_combine.restype = ctypes.c_int
 _lib.phiks_combine.argtypes = [_vp, ctypes.POINTER(_vp), _vp, _vp, ctypes.c_size_t, _vp]
 _lib.phiks_workspace_size.restype = ctypes.c_int
@@ -232,6 +237,15 @@ class Plan:
         _check(_lib.phiks_plan_info(self._h, ctypes.byref(s), ctypes.byref(q),
                                     ctypes.byref(tp), ctypes.byref(te)), "phiks_plan_info")
         return {"s": s.value, "q": q.value, "tucker_paper": tp.value, "tucker_exec": te.value}
+
+    def matrix(self, mu: int, kind: int, index: int) -> np.ndarray:
+        """One of the plan's small exponentials (phiks_plan_matrix) as a host array:
+        kind PHIKS_MATRIX_NODE (node index < q-1) or PHIKS_MATRIX_LEVEL (exp(tau A/2^index))."""
+        m = self.n[mu] * (2 if self.cplx else 1)
+        buf = DeviceArray(m * m)
+        _check(_lib.phiks_plan_matrix(self._h, int(mu), int(kind), int(index), _vp(buf.ptr), None),
+               "phiks_plan_matrix")
+        return buf.to_numpy().reshape(m, m)
 
     def workspace_size(self) -> int:
         b = ctypes.c_size_t()

@@ -367,12 +367,11 @@ int plan_nodes(const phiks_plan_s& P) { return (P.p > 0) ? P.q - 1 : 0; }
 
 size_t workspace_doubles(const phiks_plan_s& P) {
   const int64_t N = plan_vec_doubles(P);
-  if (P.task == PHIKS_SAME_VECTOR) {
-    const int64_t t = std::max<int64_t>({(int64_t)P.q - 1, (int64_t)P.p, 1});
-    return (size_t)(2 * t + 2 * P.p) * N;
-  }
-  const int64_t pp = std::max(P.p, 1);
-  return (size_t)(5 * pp) * N;
+  // same vector and combination alike: two Tucker buffers of max(q - 1, p) tensors (the
+  // node Tuckers of one input, batched over the nodes, or the p tensors of a squaring
+  // step) and the double-buffered p running sums
+  const int64_t t = std::max<int64_t>({(int64_t)P.q - 1, (int64_t)P.p, 1});
+  return (size_t)(2 * t + 2 * std::max(P.p, 1)) * N;
 }
 
 
@@ -844,6 +843,25 @@ int phiks_plan_info(phiks_plan_t plan, int* s, int* q, int* tucker_paper, int* t
   return PHIKS_OK;
 }
 
+int phiks_plan_matrix(phiks_plan_t plan, int mu, int kind, int index, double* dst,
+                      void* hip_stream) {
+  if (!plan || !dst || mu < 0 || mu >= plan->d) return PHIKS_EINVAL;
+  const int64_t m = plan->cplx ? 2 * plan->n[mu] : plan->n[mu];
+  const double* src = nullptr;
+  if (kind == PHIKS_MATRIX_NODE) {
+    if (index < 0 || index >= plan_nodes(*plan)) return PHIKS_EINVAL;
+    src = plan->Lnode[mu] + (size_t)index * sq(m);
+  } else if (kind == PHIKS_MATRIX_LEVEL) {
+    if (index < 0 || index > plan->s) return PHIKS_EINVAL;
+    src = plan->E[mu] + (size_t)index * sq(m);
+  } else {
+    return PHIKS_EINVAL;
+  }
+  HIP_OK(hipMemcpyAsync(dst, src, sq(m) * sizeof(double), hipMemcpyDeviceToDevice,
+                        (hipStream_t)hip_stream));
+  return PHIKS_OK;
+}
+
 int phiks_device_count(int* count) {
   if (!count) return PHIKS_EINVAL;
   *count = 0;
@@ -977,14 +995,21 @@ int phiks_workspace_size(phiks_plan_t plan, size_t* bytes) {
   return PHIKS_OK;
 }
 
+static int apply_body(const phiks_plan_s& P, const double* v, double* out, void* ws,
+                      hipStream_t st);
+
 int phiks_apply(phiks_plan_t plan, const double* v, double* out, void* ws, size_t ws_bytes,
                 void* hip_stream) {
   if (!plan || !v || !out) return PHIKS_EINVAL;
   if (plan->task != PHIKS_SAME_VECTOR) return PHIKS_EINVAL;
-  const phiks_plan_s& P = *plan;
-  const size_t need = workspace_doubles(P) * sizeof(double);
+  const size_t need = workspace_doubles(*plan) * sizeof(double);
   if (!ws || ws_bytes < need) return PHIKS_EWORKSPACE;
-  hipStream_t st = (hipStream_t)hip_stream;
+  return apply_body(*plan, v, out, ws, (hipStream_t)hip_stream);
+}
+
+// Body of phiks_apply once the arguments are checked; ws holds workspace_doubles(P).
+static int apply_body(const phiks_plan_s& P, const double* v, double* out, void* ws,
+                      hipStream_t st) {
   const int64_t N = plan_vec_doubles(P);  // doubles per vector
   const int p = P.p, ns = P.ns, s = P.s, q = P.q, d = P.d;
   const int64_t tcount = std::max<int64_t>({(int64_t)q - 1, (int64_t)p, 1});
@@ -1048,41 +1073,24 @@ int phiks_combine(phiks_plan_t plan, const double* const* v, double* out, void* 
   hipStream_t st = (hipStream_t)hip_stream;
   const int64_t N = plan_vec_doubles(P);  // doubles per vector
   const int p = P.p, ns = P.ns, s = P.s, q = P.q, d = P.d;
-  const int64_t pp = std::max(p, 1);
-  double* U = (double*)ws;
-  double* ta = U + pp * N;
-  double* tb = ta + pp * N;
-  double* qa = tb + pp * N;
-  double* qb = qa + pp * N;
+  const int64_t tcount = std::max<int64_t>({(int64_t)q - 1, (int64_t)p, 1});
+  double* ta = (double*)ws;
+  double* tb = ta + tcount * N;
+  double* qa = tb + tcount * N;
+  double* qb = qa + (int64_t)std::max(p, 1) * N;
   bool any = false;
   for (int k = 1; k <= p; ++k) any = any || (v[k] != nullptr);
 
-  // node inputs U_il = sum_{k<=l} theta^(l-k)/(l-k)! v_{p+1-k} / 2^((l-k+1)s)
-  auto node_inputs = [&](double th, double scale, double* dst, double beta) -> int {
-    CombineArgs ca;
-    std::memset(&ca, 0, sizeof(ca));
-    ca.out = dst;
-    ca.out_stride = N;
-    ca.nout = p;
-    ca.beta = beta;
-    ca.N = N;
-    int t = 0;
-    for (int vi = 1; vi <= p; ++vi) {  // vi = p + 1 - k
-      if (!v[vi]) continue;
-      ca.in[t] = v[vi];
-      const int k = p + 1 - vi;
-      for (int ell = 1; ell <= p; ++ell) {
-        double c = 0.0;
-        if (k <= ell)
-          c = scale * std::pow(th, ell - k) / factorial(ell - k) * std::ldexp(1.0, -(ell - k + 1) * s);
-        ca.coef[ell - 1][t] = c;
-      }
-      ++t;
-    }
-    ca.nin = t;
-    return launch_combine(ca, st);
+  // Node sums of eq. integrandcomb, Q_l = sum_i w_i Tucker_i(U_il) with node inputs
+  // U_il = sum_{k<=l} theta_i^(l-k)/(l-k)! v_{p+1-k} / 2^((l-k+1)s).  The Tucker operator
+  // is linear, so Q_l = sum_{k<=l} sum_i c_ilk Tucker_i(v_{p+1-k}) with
+  // c_ilk = w_i theta_i^(l-k)/(l-k)! / 2^((l-k+1)s): one Tucker of each input vector per
+  // node, all nodes of one vector in one batched launch per mode (as the same-vector
+  // path), their weighted sums accumulated into Q_k..Q_p.  The U_il are never formed.
+  auto coef = [&](int i, int ell, int k) {
+    return P.w[i] * std::pow(P.theta[i], ell - k) / factorial(ell - k) *
+           std::ldexp(1.0, -(ell - k + 1) * s);
   };
-
   auto emit = [&](int lev, const double* Q) -> int {
     double* o = out + (int64_t)lev * N;
     if (v[0]) {
@@ -1110,11 +1118,46 @@ int phiks_combine(phiks_plan_t plan, const double* const* v, double* out, void* 
   const double* Qcur = nullptr;
   if (p > 0 && any) {
     double* Q = qa;
-    // node theta_q = 1: no Tucker, Q_l = w_q U_ql
-    RET_IF(node_inputs(1.0, P.w[q - 1], Q, 0.0));
-    for (int i = 0; i < q - 1; ++i) {
-      RET_IF(node_inputs(P.theta[i], 1.0, U, 0.0));
-      RET_IF(plan_tucker(P, MatSel::Node, i, U, N, p, Q, ta, tb, EpiStore{P.w[i], 1.0}, st));
+    // node theta_q = 1 (exp(0) = I, no Tucker): Q_l = sum_{k<=l} c_qlk v_{p+1-k}
+    {
+      CombineArgs ca;
+      std::memset(&ca, 0, sizeof(ca));
+      ca.out = Q;
+      ca.out_stride = N;
+      ca.nout = p;
+      ca.beta = 0.0;
+      ca.N = N;
+      int t = 0;
+      for (int vi = 1; vi <= p; ++vi) {
+        if (!v[vi]) continue;
+        const int k = p + 1 - vi;
+        ca.in[t] = v[vi];
+        for (int ell = k; ell <= p; ++ell) ca.coef[ell - 1][t] = coef(q - 1, ell, k);
+        ++t;
+      }
+      ca.nin = t;
+      RET_IF(launch_combine(ca, st));
+    }
+    // nodes theta_i < 1, one input vector at a time
+    const int nodes = q - 1;
+    double* wbuf = tucker_free_buffer(d, ta, tb);
+    for (int vi = 1; vi <= p; ++vi) {
+      if (!v[vi]) continue;
+      const int k = p + 1 - vi;
+      RET_IF(plan_tucker(P, MatSel::AllNodes, 0, v[vi], 0, nodes, wbuf, ta, tb,
+                         EpiStore{1.0, 0.0}, st));
+      CombineArgs ca;
+      std::memset(&ca, 0, sizeof(ca));
+      ca.nin = nodes;
+      for (int i = 0; i < nodes; ++i) ca.in[i] = wbuf + (int64_t)i * N;
+      ca.out = Q + (int64_t)(k - 1) * N;
+      ca.out_stride = N;
+      ca.nout = p - k + 1;
+      ca.beta = 1.0;
+      ca.N = N;
+      for (int ell = k; ell <= p; ++ell)
+        for (int i = 0; i < nodes; ++i) ca.coef[ell - k][i] = coef(i, ell, k);
+      RET_IF(launch_combine(ca, st));
     }
     double* cur = Q;
     if (s < ns) RET_IF(emit(s, cur));
