@@ -28,6 +28,7 @@ Follows Section 3.3 of the paper:
 """
 from __future__ import annotations
 
+import functools
 import math
 from typing import List, Optional, Sequence, Tuple
 
@@ -122,14 +123,21 @@ def quad_errors(q: int, w: complex, p: int) -> List[float]:
 
 
 def bounds_at(xi, s: int, q: int, p: int) -> List[float]:
-    """b_{q,l}(s) = (1 + sqrt 2) max_{w on boundary of Xi/2^s} |R_q(f_l(., w))|, l = 1..p."""
+    """b_{q,l}(s) = (1 + sqrt 2) max_{w on boundary of Xi/2^s} |R_q(f_l(., w))|, l = 1..p.
+    A pure function of its arguments, so its values are kept (a plan made again for the
+    same rectangle, as time integrators do every step size, does not recompute them)."""
+    return list(_bounds_at(tuple(float(x) for x in xi), int(s), int(q), int(p)))
+
+
+@functools.lru_cache(maxsize=4096)
+def _bounds_at(xi, s: int, q: int, p: int):
     sc = 2.0 ** (-s)
     best = [0.0] * p
     for w in boundary_points(xi):
         e = quad_errors(q, w * sc, p)
         for k in range(p):
             best[k] = max(best[k], e[k])
-    return [CP_CONST * b for b in best]
+    return tuple(CP_CONST * b for b in best)
 
 
 def tucker_count(task: str, s: int, q: int, p: int, n_scales: int) -> int:

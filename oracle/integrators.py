@@ -18,7 +18,7 @@ from typing import Callable, Sequence
 import numpy as np
 
 from . import bound
-from .phiks import phi_lincomb
+from .phiks import phi_lincomb, phi_same_vector
 
 
 def _plan(A: Sequence[np.ndarray], tau: float, p: int, tol: float):
@@ -99,6 +99,11 @@ def exprk3s3(A, u0: np.ndarray, g: Callable[[float, np.ndarray], np.ndarray], T:
 
 def exprk4s6(A, u0: np.ndarray, g: Callable[[float, np.ndarray], np.ndarray], T: float,
              steps: int, tol: float = 2.0 ** -53) -> np.ndarray:
+    return exprk4s6_blocks([A], u0, g, T, steps, tol)
+
+
+def exprk4s6_blocks(blocks, u0: np.ndarray, g: Callable[[float, np.ndarray], np.ndarray],
+                    T: float, steps: int, tol: float = 2.0 ** -53) -> np.ndarray:
     """Fourth-order six-stage exponential Runge-Kutta scheme with the reduced tableau of
     eq. expRK4s6, c = (c_2, c_3, c_4, c_5, c_6) = (1/3, 1/3, 2/3, 1/2, 1): stages 3
     and 4 come from one two-scale linear combination with step c_4 tau (c_3 = c_4/2 is
@@ -106,18 +111,14 @@ def exprk4s6(A, u0: np.ndarray, g: Callable[[float, np.ndarray], np.ndarray], T:
       U_i     = e^(c_i tau K) u_n + c_i tau phi_1(c_i tau K) g_n + tau sum_j a_ij D_j
       u_{n+1} = e^(tau K) u_n + tau phi_1(tau K) g_n + tau (b_5 D_5 + b_6 D_6),
     with a_32 = c_3^2/c_2 phi_{2,3}, a_42 = c_4^2/c_2 phi_{2,4} and a_{5,3}, a_{5,4},
-    a_{6,3}, a_{6,4}, b_5, b_6 as in the tableau."""
+    a_{6,3}, a_{6,4}, b_5, b_6 as in the tableau.  K may be block diagonal (blocks[b]:
+    the A_mu of block b, u the concatenated state; exprk4s6 is the one-block case)."""
     c2, c3, c4, c5, c6 = 1 / 3, 1 / 3, 2 / 3, 0.5, 1.0
     tau = T / steps
     plans = {}
 
     def lc(h, vs, p, ns):
-        if (h, p, ns) not in plans:
-            xi = bound.kron_sum_rectangle([h * np.asarray(a) for a in A])
-            s, q, _ = bound.plan(xi, p, ns, tol, "lincomb")
-            plans[(h, p, ns)] = (s, q)
-        s, q = plans[(h, p, ns)]
-        return phi_lincomb(A, h, vs, p, ns, s, q)
+        return _lc_blocks(blocks, plans, h, vs, p, ns, tol)
 
     u = np.asarray(u0, dtype=np.float64).copy()
     for n in range(steps):
@@ -142,3 +143,114 @@ def exprk4s6(A, u0: np.ndarray, g: Callable[[float, np.ndarray], np.ndarray], T:
         w3 = tau * (2 / (c5 * (c5 - c6)) * D5 + 2 / (c6 * (c6 - c5)) * D6)
         u = lc(tau, [u, tau * gn, w2, w3], 3, 1)[0]
     return u
+
+
+# ----------------------------------------------- block-diagonal operators (two species)
+def _blocks_split(blocks, w):
+    """Views of the concatenated state w per block (block b: prod of its n_mu values)."""
+    out, off = [], 0
+    for A in blocks:
+        N = int(np.prod([a.shape[0] for a in A]))
+        out.append(w[off:off + N])
+        off += N
+    return out
+
+
+def _lc_blocks(blocks, plans, h, vs, p, ns, tol):
+    """phi_lincomb on every diagonal block of K = diag(K_1, K_2, ...) (Section 4.4: the
+    actions of a block-diagonal operator are those of its blocks); vs are concatenated
+    vectors or None.  Returns an (ns, N) array."""
+    parts = [_blocks_split(blocks, v) if v is not None else [None] * len(blocks) for v in vs]
+    res = []
+    for b, A in enumerate(blocks):
+        key = ("lc", b, h, p, ns)
+        if key not in plans:
+            xi = bound.kron_sum_rectangle([h * np.asarray(a) for a in A])
+            s, q, _ = bound.plan(xi, p, ns, tol, "lincomb")
+            plans[key] = (s, q)
+        s, q = plans[key]
+        res.append(phi_lincomb(A, h, [parts[k][b] for k in range(p + 1)], p, ns, s, q))
+    return np.concatenate(res, axis=1)
+
+
+def _sv_blocks(blocks, plans, h, v, p, ns, tol):
+    """phi_same_vector on every diagonal block; returns an (ns, p + 1, N) array."""
+    res = []
+    for b, (A, x) in enumerate(zip(blocks, _blocks_split(blocks, v))):
+        key = ("sv", b, h, p, ns)
+        if key not in plans:
+            xi = bound.kron_sum_rectangle([h * np.asarray(a) for a in A])
+            s, q, _ = bound.plan(xi, p, ns, tol, "same_vector")
+            plans[key] = (s, q)
+        s, q = plans[key]
+        res.append(phi_same_vector(A, h, x, p, ns, s, q))
+    return np.concatenate(res, axis=2)
+
+
+def exprk4s5(blocks, w0: np.ndarray, g: Callable[[float, np.ndarray], np.ndarray], T: float,
+             steps: int, tol: float = 2.0 ** -53, smart: bool = False) -> np.ndarray:
+    """Fourth-order five-stage exponential Runge-Kutta scheme of the reduced tableau of
+    eq. expRK4s5 (c = (1/2, 1/2, 1, 1/2)), for w' = K w + g(t, w) with K block diagonal:
+    blocks[b] is the list of A_mu of block b's Kronecker sum, w the concatenated state.
+    With D_j = g(t_n + c_j tau, U_j) - g_n and phi_{k,j} = phi_k(c_j tau K):
+      U_2 = e^(tau K/2) u_n + tau/2 phi_1(tau K/2) g_n
+      U_3 = U_2 + tau phi_{2,3} D_2
+      U_4 = e^(tau K) u_n + tau phi_1(tau K) g_n + tau phi_{2,4} (D_2 + D_3)
+      U_5 = U_2 + tau (a_52 (D_2 + D_3) + a_54 D_4),  a_54 = phi_{2,5}/4 - a_52,
+            a_52 = phi_{2,5}/2 - phi_{3,4} + phi_{2,4}/4 - phi_{3,5}/2
+      u_{n+1} = e^(tau K) u_n + tau phi_1(tau K) g_n
+                + tau ((-phi_2 + 4 phi_3) D_4 + (4 phi_2 - 8 phi_3) D_5).
+    smart=False takes the stages one by one as linear combinations (stage 5 mixes the
+    scales tau/2 and tau, so it is two combinations); smart=True assembles them from the
+    five lines of eq. expRK4s5_smart: two-scale outputs (j = 0, 1) of phi_1 on the
+    first line (taken here as the combination e^(c tau K) u_n + c tau phi_1(c tau K) g_n,
+    which equals u_n + c tau phi_1(c tau K) f_n), of phi_2 on D_2 and on D_3 (same
+    vector), the two-scale combination phi_2/4^j D_4 + phi_3/8^j 4 (D_2 + D_3 - D_4),
+    and phi_2 (4 D_5 - D_4) + phi_3 (4 D_4 - 8 D_5)."""
+    tau = T / steps
+    plans = {}
+    w = np.asarray(w0, dtype=np.float64).copy()
+    h2 = 0.5 * tau
+    for n in range(steps):
+        t = n * tau
+        gn = g(t, w)
+        if not smart:
+            U2 = _lc_blocks(blocks, plans, h2, [w, h2 * gn], 1, 1, tol)[0]
+            D2 = g(t + h2, U2) - gn
+            U3 = _lc_blocks(blocks, plans, h2, [w, h2 * gn, tau * D2], 2, 1, tol)[0]
+            D3 = g(t + h2, U3) - gn
+            U4 = _lc_blocks(blocks, plans, tau, [w, tau * gn, tau * (D2 + D3)], 2, 1, tol)[0]
+            D4 = g(t + tau, U4) - gn
+            D = D2 + D3 - D4
+            U5 = _lc_blocks(blocks, plans, h2, [w, h2 * gn, tau * (0.5 * D + 0.25 * D4),
+                                                -0.5 * tau * D], 3, 1, tol)[0]
+            U5 = U5 + _lc_blocks(blocks, plans, tau, [None, None, 0.25 * tau * D, -tau * D],
+                                 3, 1, tol)[0]
+            D5 = g(t + h2, U5) - gn
+            w = _lc_blocks(blocks, plans, tau, [w, tau * gn, tau * (4 * D5 - D4),
+                                                tau * (4 * D4 - 8 * D5)], 3, 1, tol)[0]
+            continue
+        E = _lc_blocks(blocks, plans, tau, [w, tau * gn], 1, 2, tol)      # scales 1, 1/2
+        D2 = g(t + h2, E[1]) - gn
+        P2 = _sv_blocks(blocks, plans, tau, D2, 2, 2, tol)                  # phi_l(tau K/2^j) D_2
+        D3 = g(t + h2, E[1] + tau * P2[1, 2]) - gn
+        P3 = _sv_blocks(blocks, plans, tau, D3, 2, 2, tol)
+        D4 = g(t + tau, E[0] + tau * (P2[0, 2] + P3[0, 2])) - gn
+        L4 = _lc_blocks(blocks, plans, tau, [None, None, D4, 4.0 * (D2 + D3 - D4)], 3, 2, tol)
+        U5 = E[1] + tau * (0.5 * (P2[1, 2] + P3[1, 2]) + 0.25 * (P2[0, 2] + P3[0, 2])
+                           - L4[1] - 0.25 * L4[0])
+        D5 = g(t + h2, U5) - gn
+        L5 = _lc_blocks(blocks, plans, tau, [None, None, 4.0 * D5 - D4, 4.0 * D4 - 8.0 * D5],
+                        3, 1, tol)
+        w = E[0] + tau * L5[0]
+    return w
+
+
+def brusselator_nonlinearity(a: float, b: float, N: int):
+    """g(w) = (a + u^2 v, b u - u^2 v) for w = (u, v), each of N values (the reaction
+    terms of the Brusselator system of Section 4.4)."""
+    def g(t, w):
+        u, v = w[:N], w[N:]
+        uuv = u * u * v
+        return np.concatenate([a + uuv, b * u - uuv])
+    return g

@@ -55,6 +55,8 @@ def _lib():
                                             dp, dp, dp, dp]
         lib.oracle_mode_product.restype = None
         lib.oracle_threads.restype = ctypes.c_int
+        lib.oracle_set_threads.argtypes = [ctypes.c_int]
+        lib.oracle_set_threads.restype = None
         _loops = lib
     return _loops
 
@@ -62,6 +64,11 @@ def _lib():
 def threads() -> int:
     """OpenMP threads the loop products run on."""
     return int(_lib().oracle_threads())
+
+
+def set_threads(n: int) -> None:
+    """Run the loop products on n OpenMP threads from now on."""
+    _lib().oracle_set_threads(int(n))
 
 
 def _real_loops(v: np.ndarray, nlo: int, nmu: int, nhi: int, L: np.ndarray) -> np.ndarray:

@@ -72,3 +72,42 @@ def test_higher_order_schemes_converge_at_their_order(problem, scheme, steps, or
     rate = np.log2(e[0] / e[1])
     print(f"[{scheme}] errors {e} observed order {rate:.2f}")
     assert abs(rate - order) < 0.3
+
+
+@pytest.fixture(scope="module")
+def bruss():
+    return workloads.brusselator_problem(n=6, d=3)
+
+
+def test_exprk4s5_plain_and_smart_agree(bruss):
+    """The stage-by-stage combinations and the assembly of eq. expRK4s5_smart compute the
+    same stages from different phi-action calls (same-vector outputs at two scales in
+    place of combinations): they agree to rounding."""
+    g = oi.brusselator_nonlinearity(bruss.a, bruss.b, bruss.N)
+    a = oi.exprk4s5(bruss.blocks, bruss.w0, g, 1.0, 4, smart=False)
+    b = oi.exprk4s5(bruss.blocks, bruss.w0, g, 1.0, 4, smart=True)
+    d = rel_inf(a, b)
+    print(f"[expRK4s5 plain vs smart] {d:.2e}")
+    assert d < 1e-12
+
+
+def test_exprk4s5_fourth_order_on_brusselator(bruss):
+    """Order 4 on the two-species Brusselator system (block-diagonal K, Neumann FD2),
+    T = 1, against the six-stage fourth-order scheme with 32 steps (an independent
+    tableau): halving the step from 4 to 8 divides the error by ~16."""
+    g = oi.brusselator_nonlinearity(bruss.a, bruss.b, bruss.N)
+    ref = oi.exprk4s6_blocks(bruss.blocks, bruss.w0, g, 1.0, 32)
+    e = [rel_inf(oi.exprk4s5(bruss.blocks, bruss.w0, g, 1.0, k, smart=True), ref) for k in (4, 8)]
+    rate = np.log2(e[0] / e[1])
+    print(f"[expRK4s5 brusselator] errors {e} observed order {rate:.2f}")
+    assert abs(rate - 4) < 0.3
+
+
+def test_exprk4s5_fourth_order_on_adr(problem):
+    """Order 4 on the ADR problem of Section 4.2 against its exact solution."""
+    g = oi.adr_nonlinearity(problem)
+    e = [rel_inf(oi.exprk4s5([problem.A], problem.u0, g, 0.1, k), problem.exact(0.1))
+         for k in (5, 10)]
+    rate = np.log2(e[0] / e[1])
+    print(f"[expRK4s5 adr] errors {e} observed order {rate:.2f}")
+    assert abs(rate - 4) < 0.3

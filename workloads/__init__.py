@@ -29,7 +29,7 @@ __all__ = [
     "randn_vec", "uniform_vec", "Workload", "config_fd2_2d", "config_allen_cahn_3d",
     "config_adr_3d", "validation_table1", "BatchProblem", "config_batch",
     "fd2_neumann", "Session", "serving_sessions", "poisson_arrivals", "ADRProblem",
-    "adr_integration_problem",
+    "adr_integration_problem", "BrusselatorProblem", "brusselator_problem",
 ]
 
 
@@ -306,3 +306,39 @@ def adr_integration_problem(n: int = 20, eps: float = 0.5, alpha: float = 10.0) 
     Amu = eps * fd2_dirichlet(n) + central_adv_dirichlet(n, alpha)
     return ADRProblem(n=n, eps=eps, alpha=alpha, A=[Amu.copy() for _ in range(3)], u0=u0, w=w)
 
+
+
+@dataclass
+class BrusselatorProblem:
+    """The two-species Brusselator system of Section 4.4 on [0, 1]^d with homogeneous
+    Neumann conditions: u' = d_1 Lap u - (b + 1) u + a + u^2 v, v' = d_2 Lap v + b u - u^2 v,
+    u_0 = 64^2 prod x_j^2 (1 - x_j)^2 (the paper's d = 3 form, 4^(2d) in general),
+    v_0 = c.  Semi-discretised on n grid points per direction including both ends with
+    the Neumann second difference of fd2_neumann (reading: the paper's fourth-order
+    closure is not stated).  K is block diagonal: blocks[0] the A_mu of K_1 = d_1 Lap -
+    (b + 1) (the shift split evenly over the directions), blocks[1] those of
+    K_2 = d_2 Lap.  The state w = (u, v) is concatenated in vec order."""
+    n: int
+    d: int
+    a: float
+    b: float
+    blocks: List[List[np.ndarray]]
+    w0: np.ndarray
+
+    @property
+    def N(self) -> int:
+        return self.n ** self.d
+
+
+def brusselator_problem(n: int = 10, d: int = 3, a: float = 1.0, b: float = 3.0,
+                        c: float = 1.0, d1: float = 0.02, d2: float = 0.02) -> BrusselatorProblem:
+    x = np.arange(n) / (n - 1)
+    f = (4.0 * x * (1.0 - x)) ** 2      # per direction: 4^2 x^2 (1 - x)^2
+    u0 = np.array([1.0])
+    for _ in range(d):
+        u0 = np.kron(f, u0)              # i_1 fastest
+    L = fd2_neumann(n)
+    K1 = [d1 * L - ((b + 1.0) / d) * np.eye(n) for _ in range(d)]
+    K2 = [d2 * L for _ in range(d)]
+    w0 = np.concatenate([u0, c * np.ones(n ** d)])
+    return BrusselatorProblem(n=n, d=d, a=a, b=b, blocks=[K1, K2], w0=w0)
