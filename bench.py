@@ -60,26 +60,170 @@ def measured_traffic():
     return float(m2.group(1))
 
 
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(w, plan_info):
-    """Time the oracle (as it stands) for one full call of the same workload:
-    its own planner plus the phi-actions with the resulting (s, q)."""
-    from oracle import bound, phiks as ophiks
+    """Time the oracle (as it stands) on this host.  All-core leg: its own planner plus one
+    full phi_0..phi_4 call of the same workload.  One-core leg, a bounded sample: one
+    Tucker operator (the three loop mode products) and the small exponentials of one
+    mode on one thread, scaled to a full call (T_exec Tucker operators, d modes of
+    exponentials) plus the planner's time (single-threaded Python either way)."""
+    from oracle import bound, expm as oexpm, gll as ogll, phiks as ophiks, tensor
+    all_threads = tensor.threads()
     t0 = time.perf_counter()
     xi = bound.kron_sum_rectangle([w.tau * a for a in w.A])
     s, q, _ = bound.plan(xi, w.p, w.n_scales, w.tol, w.task)
     t1 = time.perf_counter()
     ophiks.phi_same_vector(w.A, w.tau, w.v, w.p, w.n_scales, s, q)
     t2 = time.perf_counter()
+    plan_s = t1 - t0
+    # one-core sample
+    t_exec = (q - 1) + s * w.p + w.n_scales
     try:
         import threadpoolctl
-        threads = max([x.get("num_threads", 1) for x in threadpoolctl.threadpool_info()] or [1])
+        limiter = threadpoolctl.threadpool_limits(1)
     except Exception:
-        threads = os.cpu_count() or 1
-    return {"value": w.N / (t2 - t0), "unit": "dofs/s", "cores": int(threads),
+        limiter = None
+    tensor.set_threads(1)
+    try:
+        theta, _ = ogll.gll(q)
+        B = w.tau * np.asarray(w.A[0])
+        e0 = time.perf_counter()
+        mats = [oexpm.expm_taylor((1.0 - th) * B / 2.0 ** s) for th in theta[:-1]]
+        E = oexpm.expm_taylor(B / 2.0 ** s)
+        for _ in range(s):
+            E = E @ E
+        e1 = time.perf_counter()
+        tensor.tucker(w.v, w.n, [mats[0]] * len(w.n))
+        e2 = time.perf_counter()
+    finally:
+        tensor.set_threads(all_threads)
+        if limiter is not None:
+            limiter.unregister()
+    expm_1 = (e1 - e0) * len(w.n)
+    tucker_1 = e2 - e1
+    one_core_s = plan_s + expm_1 + t_exec * tucker_1
+    try:
+        nproc = len(os.sched_getaffinity(0))
+    except Exception:
+        nproc = os.cpu_count() or 1
+    return {"value": w.N / (t2 - t0), "unit": "dofs/s", "cores": int(all_threads),
             "kind": "oracle",
-            "sample": (f"one full call at 256^3 (planner {t1 - t0:.1f} s + phi-actions "
-                       f"{t2 - t1:.1f} s, plan s={s} q={q})"),
-            "seconds": t2 - t0}
+            "sample": (f"one full call at 256^3 on {all_threads} threads (planner {plan_s:.1f} s + "
+                       f"phi-actions {t2 - t1:.1f} s, plan s={s} q={q}); mu-mode products by "
+                       "plain C loops (OpenMP over output fibres), small exponentials by a "
+                       "Taylor series on NumPy matmuls"),
+            "seconds": t2 - t0, "nproc": nproc, "cpu_model": _cpu_model(),
+            "one_core": {"value": w.N / one_core_s, "unit": "dofs/s", "cores": 1,
+                         "seconds_extrapolated": one_core_s,
+                         "sample": (f"one Tucker operator {tucker_1:.1f} s and one mode's "
+                                    f"{q} small exponentials {e1 - e0:.1f} s on one thread, "
+                                    f"scaled by T_exec = {t_exec} and d = {len(w.n)}, plus the "
+                                    f"planner {plan_s:.1f} s")}}
+
+
+def combine_section(ph, reps=5):
+    """Linear combinations (phiks_combine, eqs. integrandcomb / comb): the 256^3 ADR
+    operator with p = 4 and five N(0, 1) vectors, and the 3D Allen-Cahn 64^3 workload
+    (p = 4, two scales, tau = 1e-3 and 1e-2) with one step of the scheme of eq.
+    expRK4s6 on it.  Plans built once; wall time without kernel events, then one call
+    with events for the mu-mode kernel rate."""
+    import workloads
+    from paper_2210_07667_amd import integrators as gi
+
+    def timed(A, tau, vs, p, ns):
+        N = int(vs[0].size)
+        plan = ph.phiks_plan(A, tau, p, ns, 2.0 ** -53, "lincomb")
+        dv = [ph.DeviceArray.from_numpy(x) for x in vs]
+        out = ph.DeviceArray(ns * N)
+        ws = ph.DeviceArray(plan.workspace_size() // 8 + 1)
+        ptrs = [x.ptr for x in dv]
+        ph.phiks_combine(plan, ptrs, out.ptr, ws.ptr, ws.nbytes)
+        ph.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            ph.phiks_combine(plan, ptrs, out.ptr, ws.ptr, ws.nbytes)
+        ph.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / reps
+        ph.phiks_kernel_timing_read()
+        ph.phiks_kernel_timing(True)
+        ph.phiks_combine(plan, ptrs, out.ptr, ws.ptr, ws.nbytes)
+        ph.synchronize()
+        ph.phiks_kernel_timing(False)
+        km, kl, kf = ph.phiks_kernel_timing_read()
+        info = plan.info()
+        plan.close()
+        for x in dv + [out, ws]:
+            x.free()
+        return {"call_ms": ms, "dofs_per_s": N / (ms * 1e-3), "plan": info,
+                "mu_mode_launches": kl, "mu_mode_ms": km,
+                "mu_mode_tflops": (kf / (km * 1e-3)) / 1e12 if km > 0 else 0.0,
+                "mu_mode_frac_fp64_peak": ((kf / (km * 1e-3)) / 1e12 / FP64_PEAK_TFLOPS) if km > 0 else 0.0}
+
+    out = {}
+    wa = workloads.config_adr_3d()
+    vs = [workloads.randn_vec(wa.n, 90 + k) for k in range(5)]
+    log("[bench] combination 256^3 p=4")
+    out["adr3d_256^3_p4"] = timed(wa.A, wa.tau, vs, 4, 1)
+    del vs
+    for tau in (1e-3, 1e-2):
+        w = workloads.config_allen_cahn_3d(tau=tau)
+        log(f"[bench] combination allen-cahn 64^3 tau={tau}")
+        r = timed(w.A, w.tau, w.vs, w.p, w.n_scales)
+        # one step of the fourth-order six-stage scheme (four combinations + stage vectors)
+        u0 = w.vs[0]
+        g = gi.AllenCahnNonlinearity(u0.size)
+        gi.exprk4s6(w.A, u0, g, tau, 1)
+        ph.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            gi.exprk4s6(w.A, u0, g, tau, 1)
+        ph.synchronize()
+        r["exprk4s6_step_ms"] = (time.perf_counter() - t0) * 1e3 / reps
+        r["exprk4s6_note"] = "one step incl. its plan builds and host-to-device copy of u_0"
+        out[f"allen_cahn_64^3_p4_2scales_tau{tau:g}"] = r
+    return out
+
+
+def small_2d_section(ph, reps=50):
+    """The 2D FD Laplacian 32x32 workload (tau = 1e-3, phi_0..phi_3, one scale): plan
+    build, small exponentials and phi-action call latency, each waited for."""
+    import workloads
+    w = workloads.config_fd2_2d()
+    v = ph.DeviceArray.from_numpy(w.v)
+    out = ph.DeviceArray((w.p + 1) * w.N)
+    plan_ms, call_ms = [], []
+    for it in range(reps + 3):
+        c0 = time.perf_counter()
+        pl = ph.phiks_plan(w.A, w.tau, w.p, 1, w.tol, "same_vector", [float(np.linalg.norm(w.v))])
+        ph.synchronize()
+        c1 = time.perf_counter()
+        ws = ph.DeviceArray(pl.workspace_size() // 8 + 1)
+        ph.synchronize()
+        c2 = time.perf_counter()
+        ph.phiks_apply(pl, v.ptr, out.ptr, ws.ptr, ws.nbytes)
+        ph.synchronize()
+        c3 = time.perf_counter()
+        info = pl.info()
+        pl.close()
+        ws.free()
+        if it >= 3:
+            plan_ms.append((c1 - c0) * 1e3)
+            call_ms.append((c3 - c2) * 1e3)
+    return {"workload": "fd2_2d_32x32_phi0-3_tau1e-3", "N": w.N, "plan": info,
+            "plan_ms_p50": float(np.median(plan_ms)), "call_ms_p50": float(np.median(call_ms)),
+            "call_ms_p90": float(np.percentile(call_ms, 90)),
+            "dofs_per_s_call": w.N / (np.median(call_ms) * 1e-3),
+            "note": "plan = host planner + device small exponentials; call = phiks_apply, "
+                    "each waited for on the host"}
 
 
 def batched_section(ph, reps=3):
@@ -231,6 +375,10 @@ def main():
                     help="skip the 512-problem batched section")
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the served-requests section")
+    ap.add_argument("--no-combine", action="store_true",
+                    help="skip the linear-combination section")
+    ap.add_argument("--no-small", action="store_true",
+                    help="skip the 2D 32x32 latency section")
     ap.add_argument("--counters", action="store_true",
                     help="hardware-counter run: copy N doubles device-to-device once (a plain "
                          "copy of known size, to scale byte counters), then run exactly one "
@@ -406,6 +554,11 @@ def main():
         "fp32_mfma": fp32,
         "bf16x3_mfma": bf16x3,
     }
+    if not args.no_combine:
+        line["combine"] = combine_section(ph)
+    if not args.no_small:
+        log("[bench] 2D 32x32 latency")
+        line["small_2d"] = small_2d_section(ph)
     if not args.no_batched:
         log("[bench] batched workload (512 problems)")
         line["batched"] = batched_section(ph)
