@@ -136,6 +136,26 @@ int phiks_apply(phiks_plan_t plan, const double* v, double* out, void* ws,
                 size_t ws_bytes, void* hip_stream);
 
 /*
+ * phiks_apply_noalloc -- phiks_apply for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  No workspace argument: the workspace is a fixed device array of
+ * PHIKS_NOALLOC_SCRATCH_BYTES bytes inside the library, one per device, placed there
+ * when the library is loaded and held until the process ends.  The call allocates
+ * nothing (no hipMalloc / hipFree, no allocating library routine).
+ *
+ *   plan, v, out, hip_stream  as phiks_apply; results are those of phiks_apply
+ * The scratch of the plan's device is used.  Every call on one device shares it and
+ * it keeps the last call's contents (nothing in it needs to start at zero): calls
+ * that overlap on one device (other streams, other threads) race, and the caller
+ * must order them.
+ * Errors: EINVAL (wrong task, NULL pointers), EWORKSPACE (phiks_workspace_size of
+ * the plan exceeds PHIKS_NOALLOC_SCRATCH_BYTES; checked before any device work),
+ * EDEVICE.
+ */
+#define PHIKS_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int phiks_apply_noalloc(phiks_plan_t plan, const double* v, double* out, void* hip_stream);
+
+/*
  * phiks_combine -- linear combination (eqs. integrandcomb and comb, eq. scallincomb).
  * Requires a plan made with PHIKS_LINCOMB.
  *

@@ -39,6 +39,7 @@ PHIKS_VOP_RATIONAL = 1
 PHIKS_VOP_CUBIC = 2
 PHIKS_MATRIX_NODE = 0
 PHIKS_MATRIX_LEVEL = 1
+NOALLOC_SCRATCH_BYTES = 64 << 20     # PHIKS_NOALLOC_SCRATCH_BYTES
 
 # every exported entry point of include/phiks.h
 SYMBOLS = ("phiks_plan", "phiks_apply", "phiks_combine", "phiks_workspace_size",
@@ -53,7 +54,7 @@ SYMBOLS = ("phiks_plan", "phiks_apply", "phiks_combine", "phiks_workspace_size",
            "phiks_server_wait", "phiks_server_stats", "phiks_server_destroy",
            "phiks_vector_op", "phiks_plan_complex", "phiks_plan_params_complex",
            "phiks_server_select_group", "phiks_server_select_evictions",
-           "phiks_plan_matrix")
+           "phiks_apply_noalloc", "phiks_plan_matrix")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with "
@@ -72,6 +73,8 @@ _lib.phiks_plan.argtypes = [ctypes.c_int, _i64p, _dpp, ctypes.c_double, ctypes.c
                             _vp, ctypes.POINTER(_vp)]
 _lib.phiks_apply.restype = ctypes.c_int
 _lib.phiks_apply.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]
+_lib.phiks_apply_noalloc.restype = ctypes.c_int
+_lib.phiks_apply_noalloc.argtypes = [_vp, _vp, _vp, _vp]
 _lib.phiks_plan_matrix.restype = ctypes.c_int
 _lib.phiks_plan_matrix.argtypes = [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp, _vp]
 _lib.phiks_combine.restype = ctypes.c_int
@@ -310,6 +313,13 @@ def phiks_apply(plan: Plan, v_ptr: int, out_ptr: int, ws_ptr: int, ws_bytes: int
                 stream: int = 0) -> None:
     _check(_lib.phiks_apply(plan.handle, _vp(v_ptr), _vp(out_ptr), _vp(ws_ptr),
                             ctypes.c_size_t(ws_bytes), _vp(stream)), "phiks_apply")
+
+
+def phiks_apply_noalloc(plan: Plan, v_ptr: int, out_ptr: int, stream: int = 0) -> None:
+    """phiks_apply on the library's fixed per-device scratch (no workspace argument,
+    no device allocation); plans needing more than NOALLOC_SCRATCH_BYTES are refused."""
+    _check(_lib.phiks_apply_noalloc(plan.handle, _vp(v_ptr), _vp(out_ptr), _vp(stream)),
+           "phiks_apply_noalloc")
 
 
 def phiks_combine(plan: Plan, v_ptrs: Sequence[Optional[int]], out_ptr: int, ws_ptr: int,

@@ -184,7 +184,7 @@ int batched_expm(const std::vector<ExpmOp>& ops, const std::vector<ExpmRequest>&
     tsq[r] = std::max(t, 0);
     gam[r] = reqs[r].c * beta[o] / std::ldexp(1.0, tsq[r]);
   }
-  // scratch: per operator Bh^1..Bh^5; per request D_0..D_4 and one squaring buffer
+  // work buffer: per operator Bh^1..Bh^5; per request D_0..D_4 and one squaring buffer
   size_t total = 0;
   std::vector<size_t> op_off(nops), req_off(reqs.size());
   for (size_t o = 0; o < nops; ++o) { op_off[o] = total; total += kTaylorBlocks * sq(ops[o].n); }
@@ -192,12 +192,12 @@ int batched_expm(const std::vector<ExpmOp>& ops, const std::vector<ExpmRequest>&
     req_off[r] = total;
     total += (kTaylorBlocks + 1) * sq(ops[reqs[r].op].n);
   }
-  double* scratch = nullptr;
-  HIP_OK(hipMallocAsync((void**)&scratch, total * sizeof(double), st));
+  double* work = nullptr;
+  HIP_OK(hipMallocAsync((void**)&work, total * sizeof(double), st));
   auto pw_ptr = [&](size_t o, int k) {  // Bh^k, k = 1..5
-    return scratch + op_off[o] + (size_t)(k - 1) * sq(ops[o].n);
+    return work + op_off[o] + (size_t)(k - 1) * sq(ops[o].n);
   };
-  auto d_ptr = [&](size_t r, int i) { return scratch + req_off[r] + (size_t)i * sq(ops[reqs[r].op].n); };
+  auto d_ptr = [&](size_t r, int i) { return work + req_off[r] + (size_t)i * sq(ops[reqs[r].op].n); };
   {
     std::vector<double> h;
     for (size_t o = 0; o < nops; ++o) {
@@ -300,7 +300,7 @@ int batched_expm(const std::vector<ExpmOp>& ops, const std::vector<ExpmRequest>&
   hipLaunchKernelGGL(scale_copy_kernel, dim3(eblocks, (unsigned)sj.size()), dim3(256), 0, st,
                      dsj);
   CHECK_LAUNCH();
-  HIP_OK(hipFreeAsync(scratch, st));
+  HIP_OK(hipFreeAsync(work, st));
   return PHIKS_OK;
 }
 
@@ -700,6 +700,46 @@ int build_plan_matrices(const std::vector<phiks_plan_s*>& plans,
 
 }  // namespace
 
+namespace {
+
+// ------------------------------------------------ fixed scratch (no allocation)
+// Workspace of phiks_apply_noalloc: a file-scope device array, one copy per device
+// (the code object places it on every device the library runs on, where it stays
+// until the process ends).  Host code never uses the name `scratch` as an address:
+// the array's device address on a device comes from hipGetSymbolAddress, taken once
+// per device with that device current, and only that address reaches kernels.
+__device__ __align__(256) double scratch[PHIKS_NOALLOC_SCRATCH_BYTES / sizeof(double)];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {nullptr};
+
+// Device address of `scratch` on `device` (looked up on the first call for it).
+int noalloc_scratch(int device, void** ptr) {
+  if (device < 0 || device >= kMaxDevices) {
+    set_error("phiks_apply_noalloc: device index out of range");
+    return PHIKS_EINVAL;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    int cur = 0;
+    HIP_OK(hipGetDevice(&cur));
+    if (cur != device) HIP_OK(hipSetDevice(device));
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != device) HIP_OK(hipSetDevice(cur));
+    if (e != hipSuccess || p == nullptr) {
+      set_error(std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+      return PHIKS_EDEVICE;
+    }
+    g_scratch_ptr[device] = p;
+  }
+  *ptr = g_scratch_ptr[device];
+  return PHIKS_OK;
+}
+
+}  // namespace
+
 // =================================================================== C ABI
 extern "C" {
 
@@ -1004,6 +1044,21 @@ int phiks_apply(phiks_plan_t plan, const double* v, double* out, void* ws, size_
   if (plan->task != PHIKS_SAME_VECTOR) return PHIKS_EINVAL;
   const size_t need = workspace_doubles(*plan) * sizeof(double);
   if (!ws || ws_bytes < need) return PHIKS_EWORKSPACE;
+  return apply_body(*plan, v, out, ws, (hipStream_t)hip_stream);
+}
+
+int phiks_apply_noalloc(phiks_plan_t plan, const double* v, double* out, void* hip_stream) {
+  if (!plan || !v || !out) return PHIKS_EINVAL;
+  if (plan->task != PHIKS_SAME_VECTOR) return PHIKS_EINVAL;
+  const size_t need = workspace_doubles(*plan) * sizeof(double);
+  if (need > (size_t)PHIKS_NOALLOC_SCRATCH_BYTES) {
+    set_error("phiks_apply_noalloc: the plan needs " + std::to_string(need) +
+              " workspace bytes, more than the fixed scratch of " +
+              std::to_string((size_t)PHIKS_NOALLOC_SCRATCH_BYTES));
+    return PHIKS_EWORKSPACE;
+  }
+  void* ws = nullptr;
+  RET_IF(noalloc_scratch(plan->device, &ws));
   return apply_body(*plan, v, out, ws, (hipStream_t)hip_stream);
 }
 
