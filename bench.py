@@ -291,17 +291,20 @@ def batched_section(ph, reps=3):
             "speedup_vs_single_calls": seq_ms / batch_ms}
 
 
-def serving_section(ph, rates=(100, 300, 600), duration=1.5):
+def serving_section(ph, rates=(100, 300, 600), duration=1.5, mixed=False):
     """Served requests of the serving workload (12 sessions: FD2 / ADR / Brusselator-type
     diffusion on 256^2, 1024^2, 64^3, 128^3, 192^3; p in 1..4; tau log-uniform) arriving as
     a Poisson stream at each rate; latency is submission to completion as the server
-    stamps it.  Every session's plan is built once before the timed streams."""
+    stamps it.  mixed=True: the odd-numbered sessions' requests take FP32 mu-mode
+    products (the rest FP64).  Every session's plan is built once before the timed
+    streams."""
     import queue
     import threading
     import workloads
     sessions = workloads.serving_sessions()
+    prec = [ph.PHIKS_FP32 if (mixed and k % 2 == 1) else ph.PHIKS_FP64 for k in range(len(sessions))]
     GiB = 1 << 30
-    server = ph.Server(hbm_budget=64 * GiB, workspace_bytes=32 * GiB, max_group=32)
+    server = ph.Server(hbm_budget=64 * GiB, workspace_bytes=32 * GiB, max_active=32, lanes=3)
     rng = np.random.default_rng(4)
     ops = [server.register(sess.A) for sess in sessions]
     vin = [[ph.DeviceArray.from_numpy(rng.standard_normal(sess.N)) for _ in range(2)]
@@ -316,8 +319,8 @@ def serving_section(ph, rates=(100, 300, 600), duration=1.5):
     warm = []
     for si, sess in enumerate(sessions):
         buf = pools[si].get()
-        warm.append((server.submit(ops[si], sess.tau, sess.p, 1, 2.0 ** -53, vin[si][0].ptr, buf.ptr),
-                     si, buf))
+        warm.append((server.submit(ops[si], sess.tau, sess.p, 1, 2.0 ** -53, vin[si][0].ptr, buf.ptr,
+                                   precision=prec[si]), si, buf))
     for t, si, buf in warm:
         server.wait(t)
         pools[si].put(buf)
@@ -347,7 +350,8 @@ def serving_section(ph, rates=(100, 300, 600), duration=1.5):
                 time.sleep(delay)
             sess = sessions[si]
             buf = pools[si].get()
-            t = server.submit(ops[si], sess.tau, sess.p, 1, 2.0 ** -53, vin[si][j % 2].ptr, buf.ptr)
+            t = server.submit(ops[si], sess.tau, sess.p, 1, 2.0 ** -53, vin[si][j % 2].ptr, buf.ptr,
+                              precision=prec[si])
             waitq.put((t, si, buf))
             dofs += sess.N
         waitq.put(None)
@@ -357,11 +361,14 @@ def serving_section(ph, rates=(100, 300, 600), duration=1.5):
         out.append({"rate_per_s": rate, "requests": len(la), "p50_ms": float(np.percentile(la, 50)),
                     "p99_ms": float(np.percentile(la, 99)), "mean_ms": float(la.mean()),
                     "throughput_per_s": len(la) / wall, "dofs_per_s": dofs / wall})
-        log(f"[bench] serving rate {rate}/s: p50 {out[-1]['p50_ms']:.2f} ms p99 {out[-1]['p99_ms']:.2f} ms")
+        log(f"[bench] serving{' mixed' if mixed else ''} rate {rate}/s: p50 {out[-1]['p50_ms']:.2f} ms "
+            f"p99 {out[-1]['p99_ms']:.2f} ms")
     st = server.stats()
     server.close()
-    return {"workload": "serving_12_sessions_poisson", "sessions": [s.name for s in sessions],
-            "duration_s_per_rate": duration, "rates": out, "server": st}
+    return {"workload": "serving_12_sessions_poisson" + ("_fp64_fp32_mix" if mixed else "_fp64"),
+            "sessions": [s.name + ("_fp32" if p == ph.PHIKS_FP32 else "") for s, p in zip(sessions, prec)],
+            "duration_s_per_rate": duration, "rates": out, "server": st,
+            "engine": "3 size lanes (own streams), step-level continuous batching, slot per request"}
 
 
 def main():
@@ -565,6 +572,7 @@ def main():
     if not args.no_serving:
         log("[bench] serving workload")
         line["serving"] = serving_section(ph)
+        line["serving_mixed"] = serving_section(ph, mixed=True)
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle (one full call)")
         line["cpu_baseline"] = cpu_baseline(w, info)

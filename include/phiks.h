@@ -272,36 +272,50 @@ int phiks_batch_info(phiks_batch_t batch, int i, int* s, int* q, int* tucker_pap
 void phiks_batch_destroy(phiks_batch_t batch);
 
 /*
- * Serving: same-vector requests submitted one at a time (each one phiks_apply on
- * caller-owned device vectors), run by the library in groups.
+ * Serving: phi-action requests (same vector, eq. scaldiffphi) submitted one at a time
+ * and run by step-level continuous batching.
+ *
+ * Requests are routed by size to `lanes` lanes (phiks_server_lane), each with its own
+ * stream.  In a lane, requests are admitted in arrival order as soon as a workspace
+ * slot of the arena is free for them (a slot per request, allocated on admission,
+ * released on completion) and fewer than max_active of the lane's requests run; the
+ * lane then issues ticks, each one step of every running request (an FP64 mu-mode
+ * product or node-sum pass, grouped across the requests into shared launches; for
+ * FP32 / BF16x3 requests one Tucker operator).  A request submitted while others run
+ * joins its lane at the next tick, and the lanes' work overlaps on the device.  Every
+ * result is bitwise what phiks_plan (tolerance relative, vnorms = NULL) + phiks_apply
+ * return for that request alone.
  *
  * phiks_server_create -- hbm_budget: device bytes for cached plans plus the workspace
  * arena; workspace_bytes: the arena (a request whose workspace, computed for the
- * largest q, exceeds it is refused with PHIKS_EWORKSPACE); max_group: most requests
- * per grouped execution; hip_stream: the stream all of the server's device work runs
- * on.  Starts a worker thread (admission, plan cache, launches) and a completion thread.
+ * largest q, exceeds it is refused with PHIKS_EWORKSPACE); max_active: most requests
+ * running per lane; lanes: 1..PHIKS_SERVER_MAX_LANES.  Creates the lanes' streams and
+ * a worker and a completion thread per lane.
  *
  * phiks_server_register -- copies the host matrices A_1..A_d (as phiks_plan) once and
  * returns an operator id for submit.  Operators stay registered until destroy.
  *
  * phiks_server_submit -- one request on a registered operator: tau, p, n_scales, tol
- * as phiks_plan (real FP64, tolerance tol relative: norms taken as 1), v (device, N
- * doubles) and out (device, n_scales*(p+1)*N doubles, laid out as phiks_apply's out).
- * v and out must stay valid until phiks_server_wait returns for the ticket.
- * Validation errors are returned here, before anything is queued.  Plans are cached
- * on (operator, tau, p, n_scales, tol); least recently used plans that no queued
- * request holds are evicted when the cache would exceed hbm_budget - workspace_bytes.
+ * as phiks_plan (tolerance relative: norms taken as 1), precision PHIKS_FP64 /
+ * PHIKS_FP32 / PHIKS_BF16X3, v (device, N doubles) and out (device,
+ * n_scales*(p+1)*N doubles, laid out as phiks_apply's out).  v and out must stay valid
+ * until phiks_server_wait returns for the ticket.  Validation errors are returned here,
+ * before anything is queued.  Plans are cached on (operator, tau, p, n_scales, tol,
+ * precision); least recently used plans that no running request holds are evicted when
+ * the cache would exceed hbm_budget - workspace_bytes.
  *
  * phiks_server_wait -- blocks until the request is done, returns its status (the
- * result is then in out, bitwise what phiks_apply returns for it) and its latency
- * in seconds (submission to completion); the ticket is then released.
+ * result is then in out), its latency in seconds (submission to completion) and its
+ * completion time on the phiks_server_clock() clock (either pointer may be NULL); the
+ * ticket is then released.
  *
  * phiks_server_destroy -- runs everything still queued, waits for it, frees.
  */
+#define PHIKS_SERVER_MAX_LANES 4
 typedef struct phiks_server_s* phiks_server_t;
 typedef struct {
   int64_t completed;     /* requests finished (any status) */
-  int64_t groups;        /* grouped executions launched */
+  int64_t ticks;         /* ticks issued (all lanes) */
   int64_t cache_hits;
   int64_t cache_misses;
   int64_t evictions;
@@ -309,26 +323,25 @@ typedef struct {
   int64_t cached_plans;
 } phiks_server_stats_t;
 
-int phiks_server_create(size_t hbm_budget, size_t workspace_bytes, int max_group,
-                        void* hip_stream, phiks_server_t* out);
+int phiks_server_create(size_t hbm_budget, size_t workspace_bytes, int max_active, int lanes,
+                        phiks_server_t* out);
 int phiks_server_register(phiks_server_t server, int d, const int64_t* n,
                           const double* const* A, int64_t* op_id);
 int phiks_server_submit(phiks_server_t server, int64_t op_id, double tau, int p, int n_scales,
-                        double tol, const double* v, double* out, int64_t* ticket);
-int phiks_server_wait(phiks_server_t server, int64_t ticket, double* latency_s);
+                        double tol, int precision, const double* v, double* out,
+                        int64_t* ticket);
+int phiks_server_wait(phiks_server_t server, int64_t ticket, double* latency_s, double* done_s);
 int phiks_server_stats(phiks_server_t server, phiks_server_stats_t* out);
 void phiks_server_destroy(phiks_server_t server);
+/* Seconds on the monotonic clock of the server's time stamps. */
+double phiks_server_clock(void);
 
 /*
- * The server's scheduling policy, host only (no device work; for tests of the policy
- * without a GPU).  The worker and the plan cache decide through exactly these rules.
+ * The server's policy, host only (no device work; for tests without a GPU).
  *
- * phiks_server_select_group -- the next group from `count` pending requests in arrival
- * order, request i of class (p[i], n_scales[i]) needing ws_doubles[i] workspace
- * doubles: the requests of the first one's class, in order, while their workspaces
- * (each rounded up to an even count of doubles) fit arena_doubles together, at most
- * max_group of them; the first request of that class that does not fit ends the group.
- * Writes the chosen indices to picked (room for count) and their number to npicked.
+ * phiks_server_lane -- the lane of a request of n_values values among `lanes`: lane 0
+ * up to 2^18 values, then one lane per factor 8 (capped at lanes - 1).  Returns the
+ * lane, or PHIKS_EINVAL for n_values < 1 or lanes < 1.
  *
  * phiks_server_select_evictions -- plans to evict before a new plan of new_bytes
  * joins a cache holding cache_bytes with room for capacity bytes; entry i holds
@@ -336,14 +349,10 @@ void phiks_server_destroy(phiks_server_t server);
  * last_use[i].  Unreferenced entries, least recently used first, until the new plan
  * fits; none beyond the unreferenced ones (the cache then runs over its budget).
  * Writes the chosen indices, in eviction order, to victims (room for count) and their
- * number to nvictims.
- *
- * Both return PHIKS_EINVAL for a negative count, max_group < 1 or a NULL array that
- * count requires, else PHIKS_OK.
+ * number to nvictims.  PHIKS_EINVAL for a negative count or a NULL array that count
+ * requires, else PHIKS_OK.
  */
-int phiks_server_select_group(int count, const int* p, const int* n_scales,
-                              const size_t* ws_doubles, size_t arena_doubles, int max_group,
-                              int* picked, int* npicked);
+int phiks_server_lane(int64_t n_values, int lanes);
 int phiks_server_select_evictions(int count, const size_t* bytes, const int* refs,
                                   const uint64_t* last_use, size_t cache_bytes, size_t new_bytes,
                                   size_t capacity, int* victims, int* nvictims);

@@ -53,7 +53,7 @@ SYMBOLS = ("phiks_plan", "phiks_apply", "phiks_combine", "phiks_workspace_size",
            "phiks_batch_destroy", "phiks_server_create", "phiks_server_register", "phiks_server_submit",
            "phiks_server_wait", "phiks_server_stats", "phiks_server_destroy",
            "phiks_vector_op", "phiks_plan_complex", "phiks_plan_params_complex",
-           "phiks_server_select_group", "phiks_server_select_evictions",
+           "phiks_server_lane", "phiks_server_select_evictions", "phiks_server_clock",
            "phiks_apply_noalloc", "phiks_plan_matrix")
 
 if not os.path.exists(LIB_PATH):
@@ -125,29 +125,30 @@ _lib.phiks_batch_destroy.argtypes = [_vp]
 
 
 class ServerStats(ctypes.Structure):
-    _fields_ = [(k, ctypes.c_int64) for k in ("completed", "groups", "cache_hits", "cache_misses",
+    _fields_ = [(k, ctypes.c_int64) for k in ("completed", "ticks", "cache_hits", "cache_misses",
                                               "evictions", "cache_bytes", "cached_plans")]
 
 
 _lib.phiks_server_create.restype = ctypes.c_int
-_lib.phiks_server_create.argtypes = [ctypes.c_size_t, ctypes.c_size_t, ctypes.c_int, _vp,
+_lib.phiks_server_create.argtypes = [ctypes.c_size_t, ctypes.c_size_t, ctypes.c_int, ctypes.c_int,
                                      ctypes.POINTER(_vp)]
 _lib.phiks_server_register.restype = ctypes.c_int
 _lib.phiks_server_register.argtypes = [_vp, ctypes.c_int, _i64p, _dpp, _i64p]
 _lib.phiks_server_submit.restype = ctypes.c_int
 _lib.phiks_server_submit.argtypes = [_vp, ctypes.c_int64, ctypes.c_double, ctypes.c_int,
-                                     ctypes.c_int, ctypes.c_double, _vp, _vp, _i64p]
+                                     ctypes.c_int, ctypes.c_double, ctypes.c_int, _vp, _vp, _i64p]
 _lib.phiks_server_wait.restype = ctypes.c_int
-_lib.phiks_server_wait.argtypes = [_vp, ctypes.c_int64, _dp]
+_lib.phiks_server_wait.argtypes = [_vp, ctypes.c_int64, _dp, _dp]
+_lib.phiks_server_clock.restype = ctypes.c_double
+_lib.phiks_server_clock.argtypes = []
+_lib.phiks_server_lane.restype = ctypes.c_int
+_lib.phiks_server_lane.argtypes = [ctypes.c_int64, ctypes.c_int]
 _lib.phiks_server_stats.restype = ctypes.c_int
 _lib.phiks_server_stats.argtypes = [_vp, ctypes.POINTER(ServerStats)]
 _lib.phiks_server_destroy.restype = None
 _lib.phiks_server_destroy.argtypes = [_vp]
 _ip = ctypes.POINTER(ctypes.c_int)
 _szp = ctypes.POINTER(ctypes.c_size_t)
-_lib.phiks_server_select_group.restype = ctypes.c_int
-_lib.phiks_server_select_group.argtypes = [ctypes.c_int, _ip, _ip, _szp, ctypes.c_size_t,
-                                           ctypes.c_int, _ip, _ip]
 _lib.phiks_server_select_evictions.restype = ctypes.c_int
 _lib.phiks_server_select_evictions.argtypes = [ctypes.c_int, _szp, _ip,
                                                ctypes.POINTER(ctypes.c_uint64), ctypes.c_size_t,
@@ -585,19 +586,17 @@ def batch_apply_arrays(batch: Batch, vs: Sequence[DeviceArray], outs=None, ws=No
     return outs
 
 
-def server_select_group(p: Sequence[int], n_scales: Sequence[int], ws_doubles: Sequence[int],
-                        arena_doubles: int, max_group: int):
-    """The server's next group from pending requests in arrival order (host only): the
-    indices phiks_server_select_group picks."""
-    n = len(p)
-    pa = (ctypes.c_int * max(n, 1))(*p)
-    na = (ctypes.c_int * max(n, 1))(*n_scales)
-    wa = (ctypes.c_size_t * max(n, 1))(*ws_doubles)
-    picked = (ctypes.c_int * max(n, 1))()
-    cnt = ctypes.c_int()
-    _check(_lib.phiks_server_select_group(n, pa, na, wa, int(arena_doubles), int(max_group), picked,
-                                          ctypes.byref(cnt)), "phiks_server_select_group")
-    return [picked[i] for i in range(cnt.value)]
+def server_lane(n_values: int, lanes: int) -> int:
+    """The server's lane for a request of n_values values among `lanes` (host only)."""
+    r = _lib.phiks_server_lane(int(n_values), int(lanes))
+    if r < 0:
+        raise PhiksError(r, "phiks_server_lane")
+    return r
+
+
+def server_clock() -> float:
+    """Seconds on the clock of the server's time stamps."""
+    return float(_lib.phiks_server_clock())
 
 
 def server_select_evictions(nbytes: Sequence[int], refs: Sequence[int], last_use: Sequence[int],
@@ -626,13 +625,14 @@ def vector_op(op: int, n: int, a: float, x_ptr: int, b: float, y_ptr: Optional[i
 
 class Server:
     """Owns a phiks_server_t: submit() queues one same-vector request, wait() blocks
-    until it is done and returns its latency in seconds."""
+    until it is done and returns its latency in seconds (wait_times() also its
+    completion time on server_clock())."""
 
-    def __init__(self, hbm_budget: int, workspace_bytes: int, max_group: int = 64,
-                 stream: int = 0):
+    def __init__(self, hbm_budget: int, workspace_bytes: int, max_active: int = 32,
+                 lanes: int = 3):
         h = ctypes.c_void_p()
         _check(_lib.phiks_server_create(ctypes.c_size_t(hbm_budget), ctypes.c_size_t(workspace_bytes),
-                                        int(max_group), _vp(stream), ctypes.byref(h)),
+                                        int(max_active), int(lanes), ctypes.byref(h)),
                "phiks_server_create")
         self._h = h
 
@@ -645,17 +645,23 @@ class Server:
         return op.value
 
     def submit(self, op: int, tau: float, p: int, n_scales: int, tol: float, v_ptr: int,
-               out_ptr: int) -> int:
+               out_ptr: int, precision: int = PHIKS_FP64) -> int:
         t = ctypes.c_int64()
         _check(_lib.phiks_server_submit(self._h, int(op), float(tau), int(p), int(n_scales),
-                                        float(tol), _vp(v_ptr), _vp(out_ptr), ctypes.byref(t)),
+                                        float(tol), int(precision), _vp(v_ptr), _vp(out_ptr),
+                                        ctypes.byref(t)),
                "phiks_server_submit")
         return t.value
 
+    def wait_times(self, ticket: int):
+        """(latency, completion time) in seconds."""
+        lat, done = ctypes.c_double(), ctypes.c_double()
+        _check(_lib.phiks_server_wait(self._h, int(ticket), ctypes.byref(lat), ctypes.byref(done)),
+               "phiks_server_wait")
+        return lat.value, done.value
+
     def wait(self, ticket: int) -> float:
-        lat = ctypes.c_double()
-        _check(_lib.phiks_server_wait(self._h, int(ticket), ctypes.byref(lat)), "phiks_server_wait")
-        return lat.value
+        return self.wait_times(ticket)[0]
 
     def stats(self) -> dict:
         st = ServerStats()

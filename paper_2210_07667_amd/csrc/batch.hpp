@@ -66,6 +66,7 @@ struct StepGemm {
   bool lincomb;
   const double* Y;
   int64_t YN;
+  int p = 0;   // squaring epilogue: the problem's highest phi index (its coefficients)
 };
 
 #ifndef PHIKS_BATCH_FORK
@@ -83,14 +84,28 @@ struct GroupedLaunch {
   int64_t total = 0;     // GEMM: tiles; Combine: largest N
   double flops = 0.0;    // GEMM: algorithmic 2 M N K over all items and batches
   int step = 0;          // launches of one step touch disjoint problems
+  int lin_p = 0;         // squaring epilogue: coefficients of BatchSchedule::lin[lin_p]
 };
 
 // Host builder of one call's launches and their tables.
 struct BatchSchedule {
   std::vector<GroupedLaunch> launches;
   std::vector<char> buf;
-  EpiLinComb lin;
+  EpiLinComb lin[PHIKS_MAX_P + 1];   // squaring-epilogue coefficients by p (eq. simul)
   int steps = 0;
+
+  // The coefficients of phiks_apply's squaring step for problems of highest index p:
+  // out_l = 2^-l (acc + sum_{k<=l} Y_k / (l-k)!).
+  void set_lin(int p) {
+    EpiLinComb& e = lin[p];
+    std::memset(&e, 0, sizeof(e));
+    e.p = p;
+    for (int ell = 1; ell <= p; ++ell) {
+      const double sc = std::ldexp(1.0, -ell);
+      e.a[ell - 1] = sc;
+      for (int k = 1; k <= ell; ++k) e.c[ell - 1][k - 1] = sc / factorial(ell - k);
+    }
+  }
 
   size_t put(const void* src, size_t bytes) {
     const size_t off = (buf.size() + 15) & ~(size_t)15;
@@ -123,18 +138,26 @@ struct BatchSchedule {
 
   void add_gemm_step(const std::vector<StepGemm>& items) {
     const int step = steps++;
-    // partition by (layout, tile class, 16-byte loads, direct-to-LDS, epilogue)
+    // the p values of the squaring-epilogue items (one launch per p: their coefficients)
+    std::vector<int> lps;
+    for (const StepGemm& it : items)
+      if (it.lincomb && std::find(lps.begin(), lps.end(), it.p) == lps.end()) lps.push_back(it.p);
+    if (lps.empty()) lps.push_back(0);
+    // partition by (layout, tile class, 16-byte loads, direct-to-LDS, epilogue, its p)
     for (int kc = 0; kc < 2; ++kc)
       for (int tile = 0; tile < kClasses; ++tile)
         for (int vec = 0; vec < 2; ++vec)
           for (int dl = 0; dl < 2; ++dl)
-            for (int lc = 0; lc < 2; ++lc) {
+            for (int lc = 0; lc < 2; ++lc)
+            for (size_t pi = 0; pi < (lc == 1 ? lps.size() : 1); ++pi) {
+              const int lp = (lc == 1) ? lps[pi] : 0;
               std::vector<GroupItem> part;
               std::vector<int64_t> first;
               int64_t total = 0;
               double flops = 0.0;
               for (const StepGemm& it : items) {
                 if (it.kc != (kc == 1) || it.lincomb != (lc == 1)) continue;
+                if (it.lincomb && it.p != lp) continue;
                 if (vec_ok(it.g, it.kc, {}) != (vec == 1)) continue;
                 const bool idl = dl_ok(it.g, it.kc) && (!it.lincomb || lincomb_dl_ok(it.g, it.Y, it.YN));
                 if (idl != (dl == 1) || tile_class(it.g, it.kc, idl, it.lincomb) != tile) continue;
@@ -166,6 +189,7 @@ struct BatchSchedule {
               L.items_off = put(part.data(), part.size() * sizeof(GroupItem));
               L.first_off = put(first.data(), first.size() * sizeof(int64_t));
               L.step = step;
+              L.lin_p = lp;
               launches.push_back(L);
             }
   }
@@ -271,13 +295,7 @@ void build_group_schedule(const GroupWork& W, BatchSchedule& S) {
     return out[i] + ((int64_t)level * (p + 1) + ell) * (*W.plans[i]).N;
   };
   // squaring-epilogue coefficients (the same for every problem: they depend on p only)
-  std::memset(&S.lin, 0, sizeof(S.lin));
-  S.lin.p = p;
-  for (int ell = 1; ell <= p; ++ell) {
-    const double sc = std::ldexp(1.0, -ell);
-    S.lin.a[ell - 1] = sc;
-    for (int k = 1; k <= ell; ++k) S.lin.c[ell - 1][k - 1] = sc / factorial(ell - k);
-  }
+  S.set_lin(p);
   if (p > 0) {
     // eq. integrandsimul: the node Tuckers of every problem, mode by mode
     std::vector<std::vector<GemmArgs>> views(count, std::vector<GemmArgs>(PHIKS_MAX_D));
@@ -340,7 +358,7 @@ void build_group_schedule(const GroupWork& W, BatchSchedule& S) {
           const phiks_plan_s& P = (*W.plans[i]);
           if (P.s <= t || P.d < mu) continue;
           const bool last = (mu == P.d);
-          items.push_back({lv[i][mu - 1], mu == 1, last, last ? bf[i].cur : nullptr, P.N});
+          items.push_back({lv[i][mu - 1], mu == 1, last, last ? bf[i].cur : nullptr, P.N, p});
         }
         S.add_gemm_step(items);
       }
@@ -410,7 +428,7 @@ int issue_one(const GroupedLaunch& L, const char* dev, const BatchSchedule& S, h
     CHECK_LAUNCH();
     return PHIKS_OK;
   }
-  if (L.lincomb) return launch_grouped(L, dev, S.lin, st);
+  if (L.lincomb) return launch_grouped(L, dev, S.lin[L.lin_p], st);
   return launch_grouped(L, dev, EpiStore{1.0, 0.0}, st);
 }
 

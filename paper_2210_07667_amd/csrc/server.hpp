@@ -1,45 +1,43 @@
-// Serving: same-vector requests submitted one at a time, run in groups.
+// Serving: phi-action requests submitted one at a time, run by step-level continuous
+// batching on the GPU.
 //
 // A request is one phiks_apply (outputs as eq. scaldiffphi) on caller-owned device
-// vectors.  Inside the server:
+// vectors, in FP64, FP32 or BF16x3 mu-mode arithmetic.  Inside the server:
 //   * operators are registered once (host copies of A_1..A_d) and named by an id;
 //   * plan cache: the plans (host plan + the small exponentials of Section 3.1 on the
-//     device) keyed on (operator id, tau, p, n_scales, tol); requests of one operator
-//     and step share one plan.  LRU eviction of unused plans keeps the
-//     cache within the HBM budget less the workspace arena.
-//   * admission: the worker takes pending requests in arrival order that share the
-//     first one's (p, n_scales), as long as their workspaces fit the arena and the
-//     group has at most max_group requests (continuous batching: whatever arrived
-//     while the previous group ran forms the next one).  Both this choice and the
-//     eviction choice are pure host functions (select_group, select_evictions), also
-//     exported for tests of the policy without a device.
-//   * execution: a group runs as the grouped launches of phiks_batch_apply (so every
-//     result is bitwise what phiks_apply returns for that request alone); host
-//     planning of the next group overlaps the device work of the previous ones.
-//   * completion: a second thread waits on each group's event in order, stamps the
-//     completion time and wakes the callers blocked in phiks_server_wait.
+//     device) keyed on (operator, tau, p, n_scales, tol, precision); least recently
+//     used plans that no running request holds are evicted when the cache would exceed
+//     the HBM budget less the workspace arena (select_evictions);
+//   * lanes: requests are routed by size (phiks_serve::lane_of) to lanes, each with its
+//     own stream, so small requests never wait behind the steps of large ones; the
+//     lanes' kernels overlap on the device;
+//   * within a lane, the engine of server_core.hpp admits requests in arrival order as
+//     workspace slots free up (one slot per request, allocated on admission, released
+//     on completion) and runs ticks: one step of every running request of the lane.
+//     A request's steps are the launches of phiks_apply -- for FP64 one mu-mode product
+//     or node-sum pass each, grouped across the lane's requests into the launches of
+//     the batched path (BatchSchedule); for FP32 / BF16x3 one Tucker operator each,
+//     issued as phiks_apply issues it -- so every result is bitwise what phiks_apply
+//     returns for that request alone, whatever else is running.  A request submitted
+//     while others run joins its lane's schedule at the next tick.
 // Requests are planned with the relative reading of the tolerance (vnorms = NULL), so
 // the plan does not depend on the vector.
 //
 // Included once, at the end of phiks.hip, after batch.hpp.
 #pragma once
 
-#include <chrono>
-#include <condition_variable>
-#include <deque>
+#include <atomic>
+#include <memory>
 #include <mutex>
-#include <thread>
 #include <unordered_map>
 #include <vector>
 
+#include "server_core.hpp"
+
 namespace {
 
-double now_s() {
-  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
-}
-
 struct PlanKey {
-  std::vector<char> bytes;  // operator id, tau, p, n_scales, tol
+  std::vector<char> bytes;  // operator id, tau, p, n_scales, tol, precision
   uint64_t hash = 0;
   bool operator==(const PlanKey& o) const { return hash == o.hash && bytes == o.bytes; }
 };
@@ -50,7 +48,7 @@ struct PlanKeyHash {
 struct CachedPlan {
   phiks_plan_s* plan = nullptr;
   size_t bytes = 0;        // device bytes of its matrices
-  int refs = 0;            // requests admitted and not yet completed
+  int refs = 0;            // admitted requests not yet completed
   uint64_t last_use = 0;   // LRU tick
 };
 
@@ -61,56 +59,7 @@ struct ServerOperator {
   std::vector<std::vector<double>> A;  // host copies, row-major
 };
 
-struct ServerRequest {
-  int64_t ticket = 0;
-  PlanKey key;
-  const ServerOperator* op = nullptr;
-  double tau = 0.0, tol = 0.0;
-  int p = 0, ns = 1;
-  const double* v = nullptr;
-  double* out = nullptr;
-  size_t ws_bound = 0;     // workspace doubles for the largest q (admission)
-  double t_submit = 0.0, t_done = 0.0;
-  int status = PHIKS_OK;
-  bool done = false;
-  CachedPlan* cp = nullptr;
-};
-
-struct InFlightGroup {
-  hipEvent_t ev = nullptr;
-  std::vector<ServerRequest*> reqs;
-};
-
 // ------------------------------------------------ scheduling policy (host only)
-// The worker and the plan cache decide through these two functions alone, so the policy
-// can be exercised without a device (phiks_server_select_group / _select_evictions).
-
-struct GroupCandidate {
-  int p, ns;
-  size_t ws;   // workspace doubles the request may need
-};
-
-// The next group from the pending requests c (arrival order): the requests with the
-// first one's (p, n_scales), in order, while their workspaces (each rounded up to an
-// even count of doubles) fit the arena together, at most max_group of them.  The first
-// request of that class that does not fit ends the group, so none overtakes another of
-// its class; requests of other classes wait for a later group.  Indices into c.
-std::vector<int> select_group(const std::vector<GroupCandidate>& c, size_t arena_doubles,
-                              int max_group) {
-  std::vector<int> g;
-  if (c.empty()) return g;
-  const int p0 = c[0].p, ns0 = c[0].ns;
-  size_t ws = 0;
-  for (int i = 0; i < (int)c.size() && (int)g.size() < max_group; ++i) {
-    if (c[i].p != p0 || c[i].ns != ns0) continue;
-    const size_t need = (c[i].ws + 1) & ~(size_t)1;
-    if (ws + need > arena_doubles) break;
-    ws += need;
-    g.push_back(i);
-  }
-  return g;
-}
-
 struct CacheEntryDesc {
   size_t bytes;
   int refs;            // requests admitted and not yet completed
@@ -146,208 +95,349 @@ uint64_t fnv1a(const char* p, size_t n, uint64_t h = 1469598103934665603ull) {
   return h;
 }
 
+// Workspace doubles a request may need: phiks_apply's workspace for the largest q.
+size_t request_ws_bound(int p, int64_t N) {
+  const int64_t t = std::max<int64_t>({(int64_t)kQMax - 1, (int64_t)p, 1});
+  return (size_t)(2 * t + 2 * std::max(p, 1)) * N;
+}
+
+// One step of a served request.
+struct ReqStep {
+  enum Kind { Gemm = 0, Combine = 1, Tucker = 2 } kind = Gemm;
+  StepGemm sg{};            // Gemm: one FP64 mu-mode product (grouped across requests)
+  CombineArgs ca{};         // Combine: the node sums (grouped)
+  // Tucker: one mixed-precision Tucker operator, issued as phiks_apply issues it
+  MatSel sel = MatSel::Level;
+  int idx = 0, nbatch = 1;
+  const double* in = nullptr;
+  int64_t in_stride = 0;
+  double* out = nullptr;
+  bool lincomb = false;
+  EpiLinComb lin{};
+};
+
+// Executor state of one request (phiks_serve::Request::ctx).
+struct ServedRequest {
+  PlanKey key;
+  const ServerOperator* op = nullptr;
+  double tau = 0.0, tol = 0.0;
+  int p = 0, ns = 1, precision = PHIKS_FP64;
+  const double* v = nullptr;
+  double* out = nullptr;
+  CachedPlan* cp = nullptr;
+  double *ta = nullptr, *tb = nullptr;
+  std::vector<ReqStep> steps;
+};
+
+// The steps of phiks_apply for plan P on v into out with workspace ws, in its order
+// (eqs. integrandsimul and simul, then the exponential outputs): FP64 plans one step
+// per mu-mode product (the views of tucker_args) or node-sum pass, mixed-precision plans
+// one step per Tucker operator.
+void request_steps(const phiks_plan_s& P, const double* v, double* out, double* ws,
+                   ServedRequest& R) {
+  std::vector<ReqStep>& steps = R.steps;
+  steps.clear();
+  const int64_t N = P.N;
+  const int p = P.p, ns = P.ns, s = P.s, q = P.q, d = P.d;
+  const int64_t tcount = std::max<int64_t>({(int64_t)q - 1, (int64_t)p, 1});
+  double* ta = ws;
+  double* tb = ta + tcount * N;
+  double* pa = tb + tcount * N;
+  double* pb = pa + (int64_t)p * N;
+  R.ta = ta;
+  R.tb = tb;
+  auto slot = [&](int level, int ell) { return out + ((int64_t)level * (p + 1) + ell) * N; };
+  const bool f64 = (P.precision == PHIKS_FP64);
+  EpiLinComb lin;
+  std::memset(&lin, 0, sizeof(lin));
+  lin.N = N;
+  lin.p = p;
+  for (int ell = 1; ell <= p; ++ell) {
+    const double sc = std::ldexp(1.0, -ell);
+    lin.a[ell - 1] = sc;
+    for (int k = 1; k <= ell; ++k) lin.c[ell - 1][k - 1] = sc / factorial(ell - k);
+  }
+  auto tucker_steps = [&](MatSel sel, int idx, const double* in, int64_t in_stride, int nbatch,
+                          double* dst, const double* Y) {
+    if (f64) {
+      double* L[PHIKS_MAX_D];
+      int64_t stride[PHIKS_MAX_D];
+      for (int mu = 0; mu < d; ++mu) {
+        const int64_t nn = P.n[mu] * P.n[mu];
+        stride[mu] = (sel == MatSel::AllNodes) ? nn : 0;
+        L[mu] = (sel == MatSel::Level) ? P.E[mu] + (size_t)idx * nn
+                                       : P.Lnode[mu] + (size_t)(sel == MatSel::Node ? idx : 0) * nn;
+      }
+      GemmArgs gs[PHIKS_MAX_D];
+      tucker_args(d, P.n, N, in, in_stride, L, stride, nbatch, dst, ta, tb, gs);
+      for (int mu = 1; mu <= d; ++mu) {
+        ReqStep st;
+        st.kind = ReqStep::Gemm;
+        const bool lc = (mu == d) && Y != nullptr;
+        st.sg = StepGemm{gs[mu - 1], mu == 1, lc, lc ? Y : nullptr, N, p};
+        steps.push_back(st);
+      }
+      return;
+    }
+    ReqStep st;
+    st.kind = ReqStep::Tucker;
+    st.sel = sel;
+    st.idx = idx;
+    st.in = in;
+    st.in_stride = in_stride;
+    st.nbatch = nbatch;
+    st.out = dst;
+    st.lincomb = Y != nullptr;
+    st.lin = lin;
+    st.lin.Y = Y;
+    steps.push_back(st);
+  };
+  if (p > 0) {
+    const int nodes = q - 1;
+    double* wbuf = tucker_free_buffer(d, ta, tb);
+    tucker_steps(MatSel::AllNodes, 0, v, 0, nodes, wbuf, nullptr);
+    double* cur = (s < ns) ? slot(s, 1) : pa;
+    ReqStep cs;
+    cs.kind = ReqStep::Combine;
+    CombineArgs& ca = cs.ca;
+    std::memset(&ca, 0, sizeof(ca));
+    ca.nin = nodes + 1;
+    for (int i = 0; i < nodes; ++i) ca.in[i] = wbuf + (int64_t)i * N;
+    ca.in[nodes] = v;
+    ca.out = cur;
+    ca.out_stride = N;
+    ca.nout = p;
+    ca.beta = 0.0;
+    ca.N = N;
+    for (int ell = 1; ell <= p; ++ell)
+      for (int i = 0; i < q; ++i)
+        ca.coef[ell - 1][i] = P.w[i] * std::pow(P.theta[i], ell - 1) / factorial(ell - 1);
+    ca.vec = combine_vec_ok(ca) ? 1 : 0;
+    steps.push_back(cs);
+    for (int j = s; j >= 1; --j) {
+      double* dst = (j - 1 < ns) ? slot(j - 1, 1) : ((cur == pa) ? pb : pa);
+      tucker_steps(MatSel::Level, j, cur, N, p, dst, cur);
+      cur = dst;
+    }
+  }
+  for (int lev = 0; lev < ns; ++lev) tucker_steps(MatSel::Level, lev, v, 0, 1, slot(lev, 0), nullptr);
+}
+
+struct ServerExec;
+
 }  // namespace
 
 struct phiks_server_s {
   size_t budget = 0, arena_doubles = 0;
-  int max_group = 1;
-  hipStream_t stream = nullptr;
+  int lanes = 1, max_active = 1;
   int device = 0;
   double* arena = nullptr;
-  GroupTables tab;
-  std::mutex mu;
-  std::condition_variable cv_work, cv_done, cv_inflight;
-  std::deque<ServerRequest*> pending;
-  std::unordered_map<int64_t, ServerRequest*> tickets;
+  std::vector<hipStream_t> streams;                 // one per lane
+  std::vector<std::vector<GroupTables>> rings;      // launch tables per lane, one per tick in flight + 1
+  std::vector<int> ring_next;
+  std::mutex ev_mu;
+  std::vector<hipEvent_t> event_pool;
+  std::mutex mu;                                    // operators, cache, stats
   std::unordered_map<int64_t, ServerOperator> ops;
   int64_t next_op = 1;
   std::unordered_map<PlanKey, CachedPlan, PlanKeyHash> cache;
   size_t cache_bytes = 0;
-  std::deque<InFlightGroup> inflight;
-  bool stop = false, worker_done = false;
-  int64_t next_ticket = 1;
   uint64_t tick = 0;
   phiks_server_stats_t st{};
-  std::thread worker, completer;
+  std::atomic<int64_t> next_ticket{1};
+  std::unique_ptr<ServerExec> exec;
+  std::unique_ptr<phiks_serve::Engine<ServerExec>> engine;
 };
 
 namespace {
 
-void server_finish(phiks_server_s& S, ServerRequest* r, int status, double t) {
-  r->status = status;
-  r->t_done = t;
-  r->done = true;
-  ++S.st.completed;
-}
+constexpr int kTicksInFlight = 2;
 
-// Cached plan for r (built on a miss); called by the worker without the lock held.
-int server_plan(phiks_server_s& S, ServerRequest* r) {
+// Cached plan for R on the lane's stream (built on a miss).  Plans of one operator
+// all have its size and so serve one lane only.
+int server_plan(phiks_server_s& S, ServedRequest& R, hipStream_t st) {
   {
     std::lock_guard<std::mutex> lk(S.mu);
-    auto it = S.cache.find(r->key);
+    auto it = S.cache.find(R.key);
     if (it != S.cache.end()) {
-      r->cp = &it->second;
-      ++r->cp->refs;
-      r->cp->last_use = ++S.tick;
+      R.cp = &it->second;
+      ++R.cp->refs;
+      R.cp->last_use = ++S.tick;
       ++S.st.cache_hits;
       return PHIKS_OK;
     }
   }
-  const ServerOperator& op = *r->op;
+  const ServerOperator& op = *R.op;
   std::vector<const double*> A(op.d);
   for (int mu = 0; mu < op.d; ++mu) A[mu] = op.A[mu].data();
   phiks_plan_t plan = nullptr;
-  int rc = phiks_plan(op.d, op.n, A.data(), r->tau, r->p, r->ns, r->tol, PHIKS_SAME_VECTOR,
-                      nullptr, PHIKS_FP64, S.stream, &plan);
+  int rc = phiks_plan(op.d, op.n, A.data(), R.tau, R.p, R.ns, R.tol, PHIKS_SAME_VECTOR, nullptr,
+                      R.precision, st, &plan);
   if (rc != PHIKS_OK) return rc;
   const size_t bytes = plan_device_doubles(*plan) * sizeof(double);
   std::vector<phiks_plan_s*> evict;
   {
     std::lock_guard<std::mutex> lk(S.mu);
     ++S.st.cache_misses;
-    // least recently used plans that no admitted request holds, until the new one fits
-    const size_t cap = S.budget > S.arena_doubles * sizeof(double)
-                           ? S.budget - S.arena_doubles * sizeof(double) : 0;
-    std::vector<decltype(S.cache)::iterator> its;
-    std::vector<CacheEntryDesc> desc;
-    for (auto it = S.cache.begin(); it != S.cache.end(); ++it) {
-      its.push_back(it);
-      desc.push_back({it->second.bytes, it->second.refs, it->second.last_use});
+    auto it = S.cache.find(R.key);
+    if (it != S.cache.end()) {
+      // (not reached: a key's requests all run on one lane, whose worker plans them one
+      // at a time) the cached plan wins and the new one is released
+      R.cp = &it->second;
+      ++R.cp->refs;
+      R.cp->last_use = ++S.tick;
+      evict.push_back(plan);
+    } else {
+      const size_t cap = S.budget > S.arena_doubles * sizeof(double)
+                             ? S.budget - S.arena_doubles * sizeof(double) : 0;
+      std::vector<decltype(S.cache)::iterator> its;
+      std::vector<CacheEntryDesc> desc;
+      for (auto e = S.cache.begin(); e != S.cache.end(); ++e) {
+        its.push_back(e);
+        desc.push_back({e->second.bytes, e->second.refs, e->second.last_use});
+      }
+      for (int i : select_evictions(desc, S.cache_bytes, bytes, cap)) {
+        S.cache_bytes -= its[i]->second.bytes;
+        evict.push_back(its[i]->second.plan);
+        S.cache.erase(its[i]);
+        ++S.st.evictions;
+      }
+      auto ins = S.cache.emplace(R.key, CachedPlan{plan, bytes, 1, ++S.tick});
+      R.cp = &ins.first->second;
+      S.cache_bytes += bytes;
     }
-    for (int i : select_evictions(desc, S.cache_bytes, bytes, cap)) {
-      S.cache_bytes -= its[i]->second.bytes;
-      evict.push_back(its[i]->second.plan);
-      S.cache.erase(its[i]);
-      ++S.st.evictions;
-    }
-    auto ins = S.cache.emplace(r->key, CachedPlan{plan, bytes, 1, ++S.tick});
-    r->cp = &ins.first->second;
-    S.cache_bytes += bytes;
-    S.st.cache_bytes = (int64_t)S.cache_bytes;
   }
-  for (phiks_plan_s* P : evict) phiks_plan_destroy(P);  // stream-ordered release
+  for (phiks_plan_s* P : evict) phiks_plan_destroy(P);  // stream-ordered on its lane
   return PHIKS_OK;
 }
 
-void server_worker(phiks_server_s* Sp) {
-  phiks_server_s& S = *Sp;
-  (void)hipSetDevice(S.device);
-  for (;;) {
-    std::vector<ServerRequest*> group;
-    {
-      std::unique_lock<std::mutex> lk(S.mu);
-      S.cv_work.wait(lk, [&] { return S.stop || !S.pending.empty(); });
-      if (S.pending.empty()) break;  // stop requested and drained
-      std::vector<GroupCandidate> cand;
-      for (const ServerRequest* r : S.pending) cand.push_back({r->p, r->ns, r->ws_bound});
-      const std::vector<int> pick = select_group(cand, S.arena_doubles, S.max_group);
-      std::vector<char> taken(S.pending.size(), 0);
-      for (int i : pick) {
-        group.push_back(S.pending[i]);
-        taken[i] = 1;
-      }
-      std::deque<ServerRequest*> rest;
-      for (size_t i = 0; i < S.pending.size(); ++i)
-        if (!taken[i]) rest.push_back(S.pending[i]);
-      S.pending.swap(rest);
-    }
-    // plans (cache lookups; misses are planned here, overlapping earlier groups)
-    std::vector<ServerRequest*> run;
-    for (ServerRequest* r : group) {
-      const int rc = server_plan(S, r);
-      if (rc != PHIKS_OK) {
-        std::lock_guard<std::mutex> lk(S.mu);
-        server_finish(S, r, rc, now_s());
-      } else {
-        run.push_back(r);
-      }
-    }
-    if (run.empty()) {
-      S.cv_done.notify_all();
-      continue;
-    }
-    GroupWork W;
-    W.p = run[0]->p;
-    W.ns = run[0]->ns;
-    size_t off = 0;
-    for (ServerRequest* r : run) {
-      W.plans.push_back(r->cp->plan);
-      W.v.push_back(r->v);
-      W.out.push_back(r->out);
-      W.ws.push_back(S.arena + off);
-      off += (workspace_doubles(*r->cp->plan) + 1) & ~(size_t)1;
-    }
-    BatchSchedule sched;
-    build_group_schedule(W, sched);
-    int rc = run_group(S.tab, sched, S.stream);
-    hipEvent_t ev = nullptr;
-    if (rc == PHIKS_OK && (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess ||
-                           hipEventRecord(ev, S.stream) != hipSuccess)) {
-      rc = PHIKS_EDEVICE;
-      if (ev) (void)hipEventDestroy(ev);
-      ev = nullptr;
-    }
-    std::lock_guard<std::mutex> lk(S.mu);
-    ++S.st.groups;
-    if (rc != PHIKS_OK) {
-      (void)hipStreamSynchronize(S.stream);
-      const double t = now_s();
-      for (ServerRequest* r : run) {
-        --r->cp->refs;
-        server_finish(S, r, rc, t);
-      }
-      S.cv_done.notify_all();
-      continue;
-    }
-    S.inflight.push_back({ev, run});
-    S.cv_inflight.notify_all();
-  }
-  std::lock_guard<std::mutex> lk(S.mu);
-  S.worker_done = true;
-  S.cv_inflight.notify_all();
-}
+struct ServerExec {
+  phiks_server_s* S;
 
-void server_completer(phiks_server_s* Sp) {
-  phiks_server_s& S = *Sp;
-  (void)hipSetDevice(S.device);
-  for (;;) {
-    InFlightGroup g;
+  int prepare(phiks_serve::Request& r) {
+    (void)hipSetDevice(S->device);
+    ServedRequest& R = *(ServedRequest*)r.ctx;
+    RET_IF(server_plan(*S, R, S->streams[r.lane]));
+    request_steps(*R.cp->plan, R.v, R.out, S->arena + r.ws_off, R);
+    r.nsteps = (int)R.steps.size();
+    return PHIKS_OK;
+  }
+
+  hipEvent_t get_event() {
     {
-      std::unique_lock<std::mutex> lk(S.mu);
-      S.cv_inflight.wait(lk, [&] { return !S.inflight.empty() || S.worker_done; });
-      if (S.inflight.empty()) break;
-      g = S.inflight.front();
-      S.inflight.pop_front();
-    }
-    const int status = (hipEventSynchronize(g.ev) == hipSuccess) ? PHIKS_OK : PHIKS_EDEVICE;
-    const double t = now_s();
-    (void)hipEventDestroy(g.ev);
-    {
-      std::lock_guard<std::mutex> lk(S.mu);
-      for (ServerRequest* r : g.reqs) {
-        --r->cp->refs;
-        server_finish(S, r, status, t);
+      std::lock_guard<std::mutex> lk(S->ev_mu);
+      if (!S->event_pool.empty()) {
+        hipEvent_t e = S->event_pool.back();
+        S->event_pool.pop_back();
+        return e;
       }
     }
-    S.cv_done.notify_all();
+    hipEvent_t e = nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
+    return e;
   }
+
+  int issue_steps(int lane, const std::vector<phiks_serve::Request*>& reqs,
+                  const std::vector<int>& step) {
+    hipStream_t st = S->streams[lane];
+    BatchSchedule sch;
+    std::vector<StepGemm> gemms;
+    std::vector<CombineArgs> combs;
+    std::vector<std::pair<ServedRequest*, const ReqStep*>> tuckers;
+    for (size_t i = 0; i < reqs.size(); ++i) {
+      ServedRequest& R = *(ServedRequest*)reqs[i]->ctx;
+      const ReqStep& x = R.steps[step[i]];
+      if (x.kind == ReqStep::Gemm) {
+        gemms.push_back(x.sg);
+        if (x.sg.lincomb) sch.set_lin(x.sg.p);
+      } else if (x.kind == ReqStep::Combine) {
+        combs.push_back(x.ca);
+      } else {
+        tuckers.push_back({&R, &x});
+      }
+    }
+    if (!gemms.empty()) sch.add_gemm_step(gemms);
+    if (!combs.empty()) sch.add_combine_step(combs);
+    if (!sch.launches.empty()) {
+      GroupTables& T = S->rings[lane][S->ring_next[lane]];
+      S->ring_next[lane] = (S->ring_next[lane] + 1) % (int)S->rings[lane].size();
+      RET_IF(upload_group(T, sch, st));
+      RET_IF(issue_group(T, sch, st));
+    }
+    for (auto& t : tuckers) {
+      const phiks_plan_s& P = *t.first->cp->plan;
+      const ReqStep& x = *t.second;
+      if (x.lincomb)
+        RET_IF(plan_tucker(P, x.sel, x.idx, x.in, x.in_stride, x.nbatch, x.out, t.first->ta,
+                           t.first->tb, x.lin, st));
+      else
+        RET_IF(plan_tucker(P, x.sel, x.idx, x.in, x.in_stride, x.nbatch, x.out, t.first->ta,
+                           t.first->tb, EpiStore{1.0, 0.0}, st));
+    }
+    return PHIKS_OK;
+  }
+
+  int issue(int lane, const std::vector<phiks_serve::Request*>& reqs, const std::vector<int>& step,
+            void** token) {
+    (void)hipSetDevice(S->device);
+    *token = nullptr;
+    int rc = issue_steps(lane, reqs, step);
+    hipEvent_t ev = nullptr;
+    if (rc == PHIKS_OK) {
+      ev = get_event();
+      if (!ev || hipEventRecord(ev, S->streams[lane]) != hipSuccess) rc = PHIKS_EDEVICE;
+    }
+    if (rc != PHIKS_OK) {
+      // nothing of the failed tick may remain queued once its requests are completed
+      (void)hipStreamSynchronize(S->streams[lane]);
+      (void)hipGetLastError();
+      if (ev) {
+        std::lock_guard<std::mutex> lk(S->ev_mu);
+        S->event_pool.push_back(ev);
+      }
+      return rc;
+    }
+    *token = ev;
+    return PHIKS_OK;
+  }
+
+  int wait(int, void* token) {
+    (void)hipSetDevice(S->device);
+    hipEvent_t ev = (hipEvent_t)token;
+    const int rc = hipEventSynchronize(ev) == hipSuccess ? PHIKS_OK : PHIKS_EDEVICE;
+    std::lock_guard<std::mutex> lk(S->ev_mu);
+    S->event_pool.push_back(ev);
+    return rc;
+  }
+
+  void finish(phiks_serve::Request& r) {
+    ServedRequest& R = *(ServedRequest*)r.ctx;
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (R.cp) --R.cp->refs;
+    R.cp = nullptr;
+    ++S->st.completed;
+  }
+};
+
+void server_release(phiks_server_s* S) {
+  if (S->engine) S->engine->shutdown();
+  for (hipStream_t s : S->streams) (void)hipStreamSynchronize(s);
+  for (auto& kv : S->cache) phiks_plan_destroy(kv.second.plan);
+  for (hipStream_t s : S->streams) (void)hipStreamSynchronize(s);
+  for (auto& ring : S->rings)
+    for (GroupTables& T : ring) free_group_tables(T);
+  for (hipEvent_t e : S->event_pool) (void)hipEventDestroy(e);
+  for (hipStream_t s : S->streams) (void)hipStreamDestroy(s);
+  if (S->arena) (void)hipFree(S->arena);
 }
 
 }  // namespace
 
 extern "C" {
 
-int phiks_server_select_group(int count, const int* p, const int* n_scales,
-                              const size_t* ws_doubles, size_t arena_doubles, int max_group,
-                              int* picked, int* npicked) {
-  if (count < 0 || max_group < 1 || !npicked || (count > 0 && (!p || !n_scales || !ws_doubles || !picked)))
-    return PHIKS_EINVAL;
-  std::vector<GroupCandidate> c(count);
-  for (int i = 0; i < count; ++i) c[i] = {p[i], n_scales[i], ws_doubles[i]};
-  const std::vector<int> g = select_group(c, arena_doubles, max_group);
-  for (size_t i = 0; i < g.size(); ++i) picked[i] = g[i];
-  *npicked = (int)g.size();
-  return PHIKS_OK;
+int phiks_server_lane(int64_t n_values, int lanes) {
+  if (n_values < 1 || lanes < 1) return PHIKS_EINVAL;
+  return phiks_serve::lane_of(n_values, lanes);
 }
 
 int phiks_server_select_evictions(int count, const size_t* bytes, const int* refs,
@@ -363,29 +453,43 @@ int phiks_server_select_evictions(int count, const size_t* bytes, const int* ref
   return PHIKS_OK;
 }
 
-int phiks_server_create(size_t hbm_budget, size_t workspace_bytes, int max_group,
-                        void* hip_stream, phiks_server_t* out) {
+int phiks_server_create(size_t hbm_budget, size_t workspace_bytes, int max_active, int lanes,
+                        phiks_server_t* out) {
   if (!out) return PHIKS_EINVAL;
   *out = nullptr;
-  if (max_group < 1 || workspace_bytes < 16 || hbm_budget < workspace_bytes) return PHIKS_EINVAL;
+  if (max_active < 1 || lanes < 1 || lanes > PHIKS_SERVER_MAX_LANES || workspace_bytes < 16 ||
+      hbm_budget < workspace_bytes)
+    return PHIKS_EINVAL;
   phiks_server_s* S = new (std::nothrow) phiks_server_s;
   if (!S) return PHIKS_ENOMEM;
   S->budget = hbm_budget;
-  S->arena_doubles = workspace_bytes / sizeof(double);
-  S->max_group = max_group;
-  S->stream = (hipStream_t)hip_stream;
-  if (hipGetDevice(&S->device) != hipSuccess) {
+  S->arena_doubles = (workspace_bytes / sizeof(double)) & ~(size_t)1;
+  S->max_active = max_active;
+  S->lanes = lanes;
+  auto fail = [&](int code, const char* msg) {
+    set_error(msg);
+    server_release(S);
     delete S;
-    set_error("hipGetDevice failed");
-    return PHIKS_EDEVICE;
-  }
+    return code;
+  };
+  if (hipGetDevice(&S->device) != hipSuccess) return fail(PHIKS_EDEVICE, "hipGetDevice failed");
   if (hipMalloc((void**)&S->arena, S->arena_doubles * sizeof(double)) != hipSuccess) {
-    delete S;
-    set_error("hipMalloc of the server workspace failed");
-    return PHIKS_ENOMEM;
+    S->arena = nullptr;
+    return fail(PHIKS_ENOMEM, "hipMalloc of the server workspace failed");
   }
-  S->worker = std::thread(server_worker, S);
-  S->completer = std::thread(server_completer, S);
+  for (int l = 0; l < lanes; ++l) {
+    hipStream_t s = nullptr;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess)
+      return fail(PHIKS_EDEVICE, "hipStreamCreate failed");
+    S->streams.push_back(s);
+  }
+  S->rings.assign(lanes, std::vector<GroupTables>(kTicksInFlight + 1));
+  S->ring_next.assign(lanes, 0);
+  S->exec.reset(new (std::nothrow) ServerExec{S});
+  if (!S->exec) return fail(PHIKS_ENOMEM, "out of host memory");
+  S->engine.reset(new (std::nothrow) phiks_serve::Engine<ServerExec>(
+      S->exec.get(), S->arena_doubles, lanes, max_active, kTicksInFlight));
+  if (!S->engine) return fail(PHIKS_ENOMEM, "out of host memory");
   *out = S;
   return PHIKS_OK;
 }
@@ -411,91 +515,90 @@ int phiks_server_register(phiks_server_t server, int d, const int64_t* n,
 }
 
 int phiks_server_submit(phiks_server_t server, int64_t op_id, double tau, int p, int n_scales,
-                        double tol, const double* v, double* out, int64_t* ticket) {
+                        double tol, int precision, const double* v, double* out,
+                        int64_t* ticket) {
   if (!server || !v || !out || !ticket) return PHIKS_EINVAL;
   if (p < 0 || p > PHIKS_MAX_P || n_scales < 1 || n_scales > 16) return PHIKS_EINVAL;
+  if (precision != PHIKS_FP64 && precision != PHIKS_FP32 && precision != PHIKS_BF16X3)
+    return PHIKS_EINVAL;
   if (!std::isfinite(tau) || !std::isfinite(tol)) return PHIKS_ENONFINITE;
   if (!(tau > 0.0) || !(tol > 0.0)) return PHIKS_EINVAL;
-  ServerRequest* r = new (std::nothrow) ServerRequest;
-  if (!r) return PHIKS_ENOMEM;
-  r->tau = tau;
-  r->tol = tol;
-  r->p = p;
-  r->ns = n_scales;
-  r->v = v;
-  r->out = out;
+  std::unique_ptr<ServedRequest> R(new (std::nothrow) ServedRequest);
+  std::unique_ptr<phiks_serve::Request> r(new (std::nothrow) phiks_serve::Request);
+  if (!R || !r) return PHIKS_ENOMEM;
+  R->tau = tau;
+  R->tol = tol;
+  R->p = p;
+  R->ns = n_scales;
+  R->precision = precision;
+  R->v = v;
+  R->out = out;
   auto put = [&](const void* src, size_t bytes) {
     const char* c = (const char*)src;
-    r->key.bytes.insert(r->key.bytes.end(), c, c + bytes);
+    R->key.bytes.insert(R->key.bytes.end(), c, c + bytes);
   };
   put(&op_id, sizeof(op_id));
   put(&tau, sizeof(tau));
   put(&p, sizeof(p));
   put(&n_scales, sizeof(n_scales));
   put(&tol, sizeof(tol));
-  r->key.hash = fnv1a(r->key.bytes.data(), r->key.bytes.size());
-  std::lock_guard<std::mutex> lk(server->mu);
-  auto it = server->ops.find(op_id);
-  if (it == server->ops.end() || server->stop) {
-    delete r;
-    return PHIKS_EINVAL;
+  put(&precision, sizeof(precision));
+  R->key.hash = fnv1a(R->key.bytes.data(), R->key.bytes.size());
+  {
+    std::lock_guard<std::mutex> lk(server->mu);
+    auto it = server->ops.find(op_id);
+    if (it == server->ops.end()) return PHIKS_EINVAL;
+    R->op = &it->second;   // operators stay registered until destroy
   }
-  r->op = &it->second;
-  const int64_t t = std::max<int64_t>({(int64_t)kQMax - 1, (int64_t)p, 1});
-  r->ws_bound = (size_t)(2 * t + 2 * p) * r->op->N;
-  // refused unless select_group could admit it alone (same rounding to even doubles)
-  if (((r->ws_bound + 1) & ~(size_t)1) > server->arena_doubles) {
-    delete r;
+  r->lane = phiks_serve::lane_of(R->op->N, server->lanes);
+  r->ws_doubles = phiks_serve::Arena::round(request_ws_bound(p, R->op->N));
+  if (r->ws_doubles > server->arena_doubles) {
     set_error("request workspace exceeds the server's workspace arena");
     return PHIKS_EWORKSPACE;
   }
-  r->ticket = server->next_ticket++;
-  r->t_submit = now_s();
-  server->tickets[r->ticket] = r;
-  server->pending.push_back(r);
+  r->ticket = server->next_ticket.fetch_add(1);
+  r->ctx = R.get();
+  if (!server->engine->submit(r.get())) return PHIKS_EINVAL;
   *ticket = r->ticket;
-  server->cv_work.notify_one();
+  R.release();
+  r.release();
   return PHIKS_OK;
 }
 
-int phiks_server_wait(phiks_server_t server, int64_t ticket, double* latency_s) {
+int phiks_server_wait(phiks_server_t server, int64_t ticket, double* latency_s, double* done_s) {
   if (!server) return PHIKS_EINVAL;
-  std::unique_lock<std::mutex> lk(server->mu);
-  auto it = server->tickets.find(ticket);
-  if (it == server->tickets.end()) return PHIKS_EINVAL;
-  ServerRequest* r = it->second;
-  server->cv_done.wait(lk, [&] { return r->done; });
+  phiks_serve::Request* r = server->engine->wait(ticket);
+  if (!r) return PHIKS_EINVAL;
   const int status = r->status;
   if (latency_s) *latency_s = r->t_done - r->t_submit;
-  server->tickets.erase(it);
+  if (done_s) *done_s = r->t_done;
+  delete (ServedRequest*)r->ctx;
   delete r;
   return status;
 }
 
 int phiks_server_stats(phiks_server_t server, phiks_server_stats_t* out) {
   if (!server || !out) return PHIKS_EINVAL;
+  const phiks_serve::EngineStats es = server->engine->stats();
   std::lock_guard<std::mutex> lk(server->mu);
   *out = server->st;
+  out->ticks = es.ticks;
   out->cache_bytes = (int64_t)server->cache_bytes;
   out->cached_plans = (int64_t)server->cache.size();
   return PHIKS_OK;
 }
 
+double phiks_server_clock(void) { return phiks_serve::now_s(); }
+
 void phiks_server_destroy(phiks_server_t server) {
   if (!server) return;
-  {
-    std::lock_guard<std::mutex> lk(server->mu);
-    server->stop = true;
+  server_release(server);
+  // requests never waited for
+  for (phiks_serve::Request* r : server->engine->take_all()) {
+    delete (ServedRequest*)r->ctx;
+    delete r;
   }
-  server->cv_work.notify_all();
-  server->worker.join();      // runs what is pending, then stops
-  server->completer.join();   // every group has completed
-  (void)hipStreamSynchronize(server->stream);
-  for (auto& kv : server->cache) phiks_plan_destroy(kv.second.plan);
-  (void)hipStreamSynchronize(server->stream);
-  free_group_tables(server->tab);
-  if (server->arena) (void)hipFree(server->arena);
-  for (auto& kv : server->tickets) delete kv.second;
+  server->engine.reset();
   delete server;
 }
 

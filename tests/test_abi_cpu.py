@@ -18,7 +18,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def test_exports_every_declared_symbol():
     hdr = open(os.path.join(ROOT, "include", "phiks.h")).read()
-    declared = set(re.findall(r"^\s*(?:int|void|const char\*)\s+(phiks_\w+)\s*\(", hdr, re.M))
+    declared = set(re.findall(r"^\s*(?:int|void|double|const char\*)\s+(phiks_\w+)\s*\(", hdr, re.M))
     assert declared, "no declarations parsed"
     lib = ctypes.CDLL(ph.LIB_PATH)
     for name in declared:
