@@ -272,6 +272,23 @@ int phiks_batch_info(phiks_batch_t batch, int i, int* s, int* q, int* tucker_pap
 void phiks_batch_destroy(phiks_batch_t batch);
 
 /*
+ * phiks_batch_dryrun -- host only (no device, nothing launched): builds the launch
+ * schedule phiks_batch_apply would issue for `count` problems of shapes d[i], n[i][..]
+ * with plans (s[i], q[i]) and the given p, n_scales (FP64), and its fork plan over
+ * fork_streams capture streams, on synthetic device addresses (each buffer a region
+ * followed by a gap), and checks them: every operand range of every launch-table item
+ * inside one buffer of its own problem, tile counts and first-tile offsets consistent,
+ * every mu-mode product of every problem scheduled once (d (1 + s + n_scales) of them
+ * for p > 0, d n_scales for p = 0), and the fork plan's events recorded before they are
+ * waited for, indices in range, each launch issued once in step order.  Writes the
+ * launch count, the table bytes and the number of failed checks (the first described
+ * by phiks_last_error()).  PHIKS_EINVAL for invalid shapes or plans.
+ */
+int phiks_batch_dryrun(int count, const int* d, const int64_t* const* n, const int* s,
+                       const int* q, int p, int n_scales, int fork_streams, int64_t* launches,
+                       int64_t* table_bytes, int64_t* violations);
+
+/*
  * Serving: phi-action requests (same vector, eq. scaldiffphi) submitted one at a time
  * and run by step-level continuous batching.
  *
@@ -364,9 +381,12 @@ int phiks_server_select_evictions(int count, const size_t* bytes, const int* ref
  *   PHIKS_VOP_AXPBY     a x + b y
  *   PHIKS_VOP_RATIONAL  a / (1 + (b x)^2) + y
  *   PHIKS_VOP_CUBIC     a (x - x^3) + b y
+ *   PHIKS_VOP_BRUSS_U   a + x^2 y       (Brusselator reaction of u, x = u, y = v; b unused)
+ *   PHIKS_VOP_BRUSS_V   a x - x^2 y     (Brusselator reaction of v, x = u, y = v; b unused)
  * x, y, out: device arrays of n doubles; out may alias x or y.  Stream-ordered.
  */
-enum { PHIKS_VOP_AXPBY = 0, PHIKS_VOP_RATIONAL = 1, PHIKS_VOP_CUBIC = 2 };
+enum { PHIKS_VOP_AXPBY = 0, PHIKS_VOP_RATIONAL = 1, PHIKS_VOP_CUBIC = 2, PHIKS_VOP_BRUSS_U = 3,
+       PHIKS_VOP_BRUSS_V = 4 };
 int phiks_vector_op(int op, int64_t n, double a, const double* x, double b, const double* y,
                     double* out, void* hip_stream);
 

@@ -37,6 +37,8 @@ PHIKS_BF16X3 = 2
 PHIKS_VOP_AXPBY = 0
 PHIKS_VOP_RATIONAL = 1
 PHIKS_VOP_CUBIC = 2
+PHIKS_VOP_BRUSS_U = 3
+PHIKS_VOP_BRUSS_V = 4
 PHIKS_MATRIX_NODE = 0
 PHIKS_MATRIX_LEVEL = 1
 NOALLOC_SCRATCH_BYTES = 64 << 20     # PHIKS_NOALLOC_SCRATCH_BYTES
@@ -54,7 +56,7 @@ SYMBOLS = ("phiks_plan", "phiks_apply", "phiks_combine", "phiks_workspace_size",
            "phiks_server_wait", "phiks_server_stats", "phiks_server_destroy",
            "phiks_vector_op", "phiks_plan_complex", "phiks_plan_params_complex",
            "phiks_server_lane", "phiks_server_select_evictions", "phiks_server_clock",
-           "phiks_apply_noalloc", "phiks_plan_matrix")
+           "phiks_apply_noalloc", "phiks_plan_matrix", "phiks_batch_dryrun")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with "
@@ -121,6 +123,10 @@ _lib.phiks_batch_info.restype = ctypes.c_int
 _lib.phiks_batch_info.argtypes = [_vp, ctypes.c_int] + [ctypes.POINTER(ctypes.c_int)] * 4
 _lib.phiks_batch_destroy.restype = None
 _lib.phiks_batch_destroy.argtypes = [_vp]
+_lib.phiks_batch_dryrun.restype = ctypes.c_int
+_lib.phiks_batch_dryrun.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(_i64p),
+                                    ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                    ctypes.c_int, ctypes.c_int, ctypes.c_int, _i64p, _i64p, _i64p]
 
 
 
@@ -418,6 +424,12 @@ def copy_device(dst: "DeviceArray", src: "DeviceArray", stream: int = 0) -> None
     _check(_lib.phiks_memcpy_dtod(_vp(dst.ptr), _vp(src.ptr), n, _vp(stream)), "phiks_memcpy_dtod")
 
 
+def memcpy_dtod(dst_ptr: int, src_ptr: int, nbytes: int, stream: int = 0) -> None:
+    """Stream-ordered device-to-device copy of nbytes."""
+    _check(_lib.phiks_memcpy_dtod(_vp(dst_ptr), _vp(src_ptr), int(nbytes), _vp(stream)),
+           "phiks_memcpy_dtod")
+
+
 def synchronize() -> None:
     _check(_lib.phiks_device_synchronize(), "phiks_device_synchronize")
 
@@ -584,6 +596,23 @@ def batch_apply_arrays(batch: Batch, vs: Sequence[DeviceArray], outs=None, ws=No
         ws = DeviceArray(batch.workspace_size() // 8 + 1)
     phiks_batch_apply(batch, [v.ptr for v in vs], [o.ptr for o in outs], ws.ptr, ws.nbytes, stream)
     return outs
+
+
+def batch_dryrun(shapes, plans, p: int, n_scales: int, fork_streams: int = 4):
+    """Host-only check of the batched launch schedule (phiks_batch_dryrun): shapes[i] the
+    n of problem i, plans[i] its (s, q).  Returns (launches, table bytes, failed checks,
+    first failure text)."""
+    count = len(shapes)
+    d = (ctypes.c_int * count)(*[len(x) for x in shapes])
+    ns_arr = [(ctypes.c_int64 * len(x))(*[int(v) for v in x]) for x in shapes]
+    n = (_i64p * count)(*[ctypes.cast(a, _i64p) for a in ns_arr])
+    s = (ctypes.c_int * count)(*[int(x[0]) for x in plans])
+    q = (ctypes.c_int * count)(*[int(x[1]) for x in plans])
+    L, T, V = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    _check(_lib.phiks_batch_dryrun(count, d, n, s, q, int(p), int(n_scales), int(fork_streams),
+                                   ctypes.byref(L), ctypes.byref(T), ctypes.byref(V)),
+           "phiks_batch_dryrun")
+    return L.value, T.value, V.value, _lib.phiks_last_error().decode() if V.value else ""
 
 
 def server_lane(n_values: int, lanes: int) -> int:

@@ -440,33 +440,58 @@ int issue_group(const GroupTables& T, const BatchSchedule& S, hipStream_t st) {
   return PHIKS_OK;
 }
 
-// As issue_group, for capture on st: the launches of one step (disjoint problems) are
+// Fork and join of a captured call: the launches of one step (disjoint problems) are
 // forked over the aux streams and joined back before the next step, so the graph may
-// run a step's small partitions beside its large one.  ev: events for the fork and
-// join points (hipEventDisableTiming), at least launches + steps of them.
-int issue_group_forked(const GroupTables& T, const BatchSchedule& S, hipStream_t st,
-                       const std::vector<hipStream_t>& aux, const std::vector<hipEvent_t>& ev) {
-  const char* dev = (const char*)T.dev;
+// run a step's small partitions beside its large one.  The plan is host data only (so
+// it can be checked without a device): a step with one launch, or no aux stream, runs on
+// the main stream; otherwise the main stream records a fork event that `used` aux
+// streams wait for, the step's launches go round-robin over them, and each aux stream
+// records a join event the main stream waits for.  Events are numbered in order of use;
+// a call needs at most launches + steps of them.
+struct ForkOp {
+  enum Kind { Record = 0, Wait = 1, Launch = 2 } kind;
+  int stream;   // -1: the main stream, else an aux stream
+  int event;    // Record / Wait
+  int launch;   // Launch: index into BatchSchedule::launches
+};
+
+std::vector<ForkOp> fork_plan(const BatchSchedule& S, int naux) {
+  std::vector<ForkOp> ops;
   const std::vector<GroupedLaunch>& Ls = S.launches;
-  size_t e = 0;
+  int e = 0;
   for (size_t i = 0; i < Ls.size();) {
     size_t j = i;
     while (j < Ls.size() && Ls[j].step == Ls[i].step) ++j;
-    if (j - i == 1 || aux.empty()) {
-      for (size_t k = i; k < j; ++k) RET_IF(issue_one(Ls[k], dev, S, st));
+    if (j - i == 1 || naux <= 0) {
+      for (size_t k = i; k < j; ++k) ops.push_back({ForkOp::Launch, -1, -1, (int)k});
       i = j;
       continue;
     }
-    HIP_OK(hipEventRecord(ev[e], st));
-    const hipEvent_t fork = ev[e++];
-    const size_t used = std::min(aux.size(), j - i);
-    for (size_t a = 0; a < used; ++a) HIP_OK(hipStreamWaitEvent(aux[a], fork, 0));
-    for (size_t k = i; k < j; ++k) RET_IF(issue_one(Ls[k], dev, S, aux[(k - i) % used]));
-    for (size_t a = 0; a < used; ++a) {
-      HIP_OK(hipEventRecord(ev[e], aux[a]));
-      HIP_OK(hipStreamWaitEvent(st, ev[e++], 0));
+    const int fork = e++;
+    ops.push_back({ForkOp::Record, -1, fork, -1});
+    const int used = (int)std::min<size_t>((size_t)naux, j - i);
+    for (int a = 0; a < used; ++a) ops.push_back({ForkOp::Wait, a, fork, -1});
+    for (size_t k = i; k < j; ++k) ops.push_back({ForkOp::Launch, (int)((k - i) % used), -1, (int)k});
+    for (int a = 0; a < used; ++a) {
+      const int join = e++;
+      ops.push_back({ForkOp::Record, a, join, -1});
+      ops.push_back({ForkOp::Wait, -1, join, -1});
     }
     i = j;
+  }
+  return ops;
+}
+
+// As issue_group, for capture on st, following fork_plan over the aux streams.  ev:
+// events for the fork and join points (hipEventDisableTiming), launches + steps of them.
+int issue_group_forked(const GroupTables& T, const BatchSchedule& S, hipStream_t st,
+                       const std::vector<hipStream_t>& aux, const std::vector<hipEvent_t>& ev) {
+  const char* dev = (const char*)T.dev;
+  for (const ForkOp& op : fork_plan(S, (int)aux.size())) {
+    hipStream_t s = op.stream < 0 ? st : aux[op.stream];
+    if (op.kind == ForkOp::Record) HIP_OK(hipEventRecord(ev[op.event], s));
+    else if (op.kind == ForkOp::Wait) HIP_OK(hipStreamWaitEvent(s, ev[op.event], 0));
+    else RET_IF(issue_one(S.launches[op.launch], dev, S, s));
   }
   return PHIKS_OK;
 }
@@ -532,9 +557,190 @@ void free_group_tables(GroupTables& T) {
   T = GroupTables();
 }
 
+// ---------------------------------------------------------------- host dry run
+// phiks_batch_dryrun: builds a call's schedule and fork plan for given shapes and plans
+// with synthetic device addresses (nothing is dereferenced or launched) and checks them.
+// Each buffer of a problem (plan matrices, v, out, workspace) is a region of a synthetic
+// address space with a gap after it; every operand range a launch table names must lie
+// inside one region, all ranges of one item inside the same problem's regions.
+struct DryRunSpace {
+  uintptr_t next = (uintptr_t)1 << 44;
+  struct Region { uintptr_t lo, hi; int owner; };
+  std::vector<Region> regions;
+  double* take(size_t doubles, int owner) {
+    const uintptr_t lo = next, hi = lo + std::max<size_t>(doubles, 1) * sizeof(double);
+    regions.push_back({lo, hi, owner});
+    next = (hi + ((uintptr_t)1 << 20) + 255) & ~(uintptr_t)255;
+    return reinterpret_cast<double*>(lo);
+  }
+  int owner(uintptr_t lo, uintptr_t hi) const {
+    for (const Region& r : regions)
+      if (lo >= r.lo && hi <= r.hi) return r.owner;
+    return -1;
+  }
+};
+
+struct DryRunCheck {
+  int64_t violations = 0;
+  std::string first;
+  void fail(const std::string& what) {
+    if (violations++ == 0) first = what;
+  }
+};
+
+// Owner of the byte range [base + lo_el, base + hi_el) in doubles, or -1.
+int dry_owner(const DryRunSpace& sp, const double* base, int64_t lo_el, int64_t hi_el) {
+  const uintptr_t b = reinterpret_cast<uintptr_t>(base);
+  return sp.owner(b + (uintptr_t)(lo_el * 8), b + (uintptr_t)(hi_el * 8));
+}
+
+void dry_check_schedule(const BatchSchedule& S, const DryRunSpace& sp, int count,
+                        const std::vector<int64_t>& want_gemms, int naux, DryRunCheck& ck) {
+  std::vector<int64_t> gemms(count, 0), combs(count, 0);
+  for (size_t li = 0; li < S.launches.size(); ++li) {
+    const GroupedLaunch& L = S.launches[li];
+    const std::string at = "launch " + std::to_string(li) + ": ";
+    if (L.n < 1) ck.fail(at + "empty launch");
+    if (L.kind == StepKind::Combine) {
+      const CombineArgs* items = (const CombineArgs*)(S.buf.data() + L.items_off);
+      for (int k = 0; k < L.n; ++k) {
+        const CombineArgs& a = items[k];
+        if (a.nin < 1 || a.nin > kMaxIn || a.nout < 1 || a.nout > 8 || a.N < 1 ||
+            a.N > L.total) {
+          ck.fail(at + "combine item sizes");
+          continue;
+        }
+        const int own = dry_owner(sp, a.out, 0, (int64_t)(a.nout - 1) * a.out_stride + a.N);
+        if (own < 0) ck.fail(at + "combine output outside its buffer");
+        for (int t = 0; t < a.nin; ++t)
+          if (dry_owner(sp, a.in[t], 0, a.N) != own) ck.fail(at + "combine input outside the problem");
+        if (own >= 0) ++combs[own];
+      }
+      continue;
+    }
+    const GroupItem* items = (const GroupItem*)(S.buf.data() + L.items_off);
+    const int64_t* first = (const int64_t*)(S.buf.data() + L.first_off);
+    const int bm = BatchSchedule::kBM[L.tile], bn = BatchSchedule::kBN[L.tile];
+    int64_t tiles = 0;
+    for (int k = 0; k < L.n; ++k) {
+      const GemmArgs& g = items[k].g;
+      if (first[k] != tiles) ck.fail(at + "first[] is not the prefix sum of the item tiles");
+      if (g.M < 1 || g.N < 1 || g.K < 1 || g.nb0 < 1 || g.nb1 < 1 || g.pA != nullptr) {
+        ck.fail(at + "item view sizes");
+        continue;
+      }
+      if (g.tiles_m != (g.M + bm - 1) / bm || g.tiles_n != (g.N + bn - 1) / bn ||
+          g.total_tiles != (int64_t)g.tiles_m * g.tiles_n * g.nb0 * g.nb1)
+        ck.fail(at + "tile counts do not match the tile class");
+      if (L.dl && g.K % PHIKS_DL_BK != 0) ck.fail(at + "direct-to-LDS item with a partial K chunk");
+      tiles += g.total_tiles;
+      const int64_t bz = (int64_t)(g.nb0 - 1), b1 = (int64_t)(g.nb1 - 1);
+      const int64_t a_hi = bz * g.sA0 + b1 * g.sA1 + (int64_t)(g.M - 1) * g.lda + g.K;
+      const int64_t b_hi = bz * g.sB0 + b1 * g.sB1 +
+                           (L.kc ? (int64_t)(g.N - 1) * g.ldb + g.K : (int64_t)(g.K - 1) * g.ldb + g.N);
+      const int64_t c_hi = bz * g.sC0 + b1 * g.sC1 + (int64_t)(g.M - 1) * g.ldc + g.N;
+      const int oa = dry_owner(sp, g.A, 0, a_hi), ob = dry_owner(sp, g.B, 0, b_hi),
+                oc = dry_owner(sp, g.C, 0, c_hi);
+      if (oa < 0 || ob < 0 || oc < 0) ck.fail(at + "operand range outside its buffer");
+      else if (oa != ob || ob != oc) ck.fail(at + "operands of one item in different problems");
+      if (L.lincomb) {
+        const int64_t y_hi = b1 * items[k].YN + bz * g.sC0 + (int64_t)(g.M - 1) * g.ldc + g.N;
+        if (dry_owner(sp, items[k].Y, 0, y_hi) != oc) ck.fail(at + "squaring-epilogue tensors outside the problem");
+        if (b1 + 1 != S.lin[L.lin_p].p) ck.fail(at + "squaring epilogue batch is not p");
+      }
+      if (oc >= 0) ++gemms[oc];
+    }
+    if (tiles != L.total) ck.fail(at + "launch total is not the sum of its item tiles");
+  }
+  for (int i = 0; i < count; ++i)
+    if (gemms[i] != want_gemms[i])
+      ck.fail("problem " + std::to_string(i) + ": " + std::to_string(gemms[i]) +
+              " mu-mode products scheduled, " + std::to_string(want_gemms[i]) + " expected");
+  // fork and join of the captured form
+  const std::vector<ForkOp> ops = fork_plan(S, naux);
+  const int nev = (int)(S.launches.size() + S.steps);
+  std::vector<char> recorded(nev, 0);
+  std::vector<int> launched(S.launches.size(), 0);
+  int last_step = -1;
+  for (const ForkOp& op : ops) {
+    if (op.stream < -1 || op.stream >= std::max(naux, 0)) ck.fail("fork plan: stream index out of range");
+    if (op.kind == ForkOp::Launch) {
+      if (op.launch < 0 || op.launch >= (int)S.launches.size()) {
+        ck.fail("fork plan: launch index out of range");
+        continue;
+      }
+      ++launched[op.launch];
+      if (S.launches[op.launch].step < last_step) ck.fail("fork plan: steps out of order");
+      last_step = S.launches[op.launch].step;
+      continue;
+    }
+    if (op.event < 0 || op.event >= nev) {
+      ck.fail("fork plan: event index out of range");
+      continue;
+    }
+    if (op.kind == ForkOp::Record) recorded[op.event] = 1;
+    else if (!recorded[op.event]) ck.fail("fork plan: wait on an event not yet recorded");
+  }
+  for (int c : launched)
+    if (c != 1) ck.fail("fork plan: a launch issued other than once");
+}
+
 }  // namespace
 
 extern "C" {
+
+int phiks_batch_dryrun(int count, const int* d, const int64_t* const* n, const int* s,
+                       const int* q, int p, int n_scales, int fork_streams, int64_t* launches,
+                       int64_t* table_bytes, int64_t* violations) {
+  if (count < 1 || !d || !n || !s || !q || !launches || !table_bytes || !violations)
+    return PHIKS_EINVAL;
+  if (p < 0 || p > PHIKS_MAX_P || n_scales < 1 || n_scales > 16 || fork_streams < 0)
+    return PHIKS_EINVAL;
+  std::vector<phiks_plan_s> plans(count);
+  DryRunSpace sp;
+  GroupWork W;
+  W.p = p;
+  W.ns = n_scales;
+  std::vector<int64_t> want(count, 0);
+  for (int i = 0; i < count; ++i) {
+    if (d[i] < 1 || d[i] > PHIKS_MAX_D || !n[i] || s[i] < std::max(0, n_scales - 1) || s[i] > kSMax)
+      return PHIKS_EINVAL;
+    if (p > 0 && (q[i] < kQMin || q[i] > kQMax)) return PHIKS_EINVAL;
+    phiks_plan_s& P = plans[i];
+    P.d = d[i];
+    P.N = 1;
+    for (int mu = 0; mu < d[i]; ++mu) {
+      if (n[i][mu] < 1 || n[i][mu] > PHIKS_MAX_N) return PHIKS_EINVAL;
+      P.n[mu] = n[i][mu];
+      P.N *= n[i][mu];
+    }
+    if (!views_fit_int32(P.d, P.n, 1)) return PHIKS_EINVAL;
+    P.p = p;
+    P.ns = n_scales;
+    P.task = PHIKS_SAME_VECTOR;
+    P.precision = PHIKS_FP64;
+    P.s = s[i];
+    P.q = p > 0 ? q[i] : 0;
+    if (p > 0) gll_rule(P.q, P.theta, P.w);
+    plan_assign(P, sp.take(plan_device_doubles(P), i));
+    W.plans.push_back(&P);
+    W.v.push_back(sp.take(P.N, i));
+    W.out.push_back(sp.take((size_t)n_scales * (p + 1) * P.N, i));
+    W.ws.push_back(sp.take(workspace_doubles(P), i));
+    want[i] = (int64_t)P.d * ((p > 0 ? 1 + P.s : 0) + n_scales);
+  }
+  BatchSchedule S;
+  build_group_schedule(W, S);
+  DryRunCheck ck;
+  dry_check_schedule(S, sp, count, want, fork_streams, ck);
+  *launches = (int64_t)S.launches.size();
+  *table_bytes = (int64_t)S.buf.size();
+  *violations = ck.violations;
+  if (ck.violations) set_error(ck.first);
+  return PHIKS_OK;
+}
+
+
 
 void phiks_batch_destroy(phiks_batch_t batch) {
   if (!batch) return;

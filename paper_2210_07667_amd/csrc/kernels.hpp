@@ -78,7 +78,8 @@ __global__ void __launch_bounds__(256) combine_grouped_kernel(const CombineArgs*
 
 // Elementwise vector operations for integrators built on the phi-actions (y may be
 // null: zero).  Axpby: a x + b y.  Rational: a / (1 + (b x)^2) + y.  Cubic: a (x - x^3) + b y.
-enum { kVopAxpby = 0, kVopRational = 1, kVopCubic = 2 };
+// Brusselator reaction terms with x = u, y = v: BrussU a + x^2 y, BrussV a x - x^2 y.
+enum { kVopAxpby = 0, kVopRational = 1, kVopCubic = 2, kVopBrussU = 3, kVopBrussV = 4 };
 struct VecOpArgs {
   int op;
   int64_t N;
@@ -99,8 +100,12 @@ __global__ void __launch_bounds__(256) vector_op_kernel(VecOpArgs v) {
     } else if (v.op == kVopRational) {
       const double bx = v.b * x;
       r = v.a / (1.0 + bx * bx) + y;
-    } else {
+    } else if (v.op == kVopCubic) {
       r = v.a * (x - x * x * x) + v.b * y;
+    } else if (v.op == kVopBrussU) {
+      r = v.a + x * x * y;
+    } else {
+      r = v.a * x - x * x * y;
     }
     v.out[e] = r;
   }

@@ -1017,7 +1017,7 @@ int phiks_tucker(int d, const int64_t* n, const double* const* L, const double* 
 
 int phiks_vector_op(int op, int64_t n, double a, const double* x, double b, const double* y,
                     double* out, void* hip_stream) {
-  if (op < PHIKS_VOP_AXPBY || op > PHIKS_VOP_CUBIC || n < 0 || (n > 0 && (!x || !out)))
+  if (op < PHIKS_VOP_AXPBY || op > PHIKS_VOP_BRUSS_V || n < 0 || (n > 0 && (!x || !out)))
     return PHIKS_EINVAL;
   if (!std::isfinite(a) || !std::isfinite(b)) return PHIKS_ENONFINITE;
   if (n == 0) return PHIKS_OK;

@@ -240,3 +240,28 @@ def test_complex_planner_matches_oracle_on_dense_operators():
         xi = bound.kron_sum_rectangle([tau * a for a in A])
         ref = bound.plan(xi, 3, 1, 2.0 ** -53, "same_vector")
         assert got == tuple(ref), (trial, n, tau, got, ref)
+
+
+def test_batch_dryrun_checks_the_512_problem_schedule():
+    """The batched launch schedule of the 512-problem workload, built on synthetic device
+    addresses by the library itself (phiks_batch_dryrun: every table entry inside its
+    problem's buffers, tile bookkeeping, every mu-mode product once, fork plan), with the
+    plans the host planner gives; also odd shapes, p = 0 and two scales."""
+    probs = workloads.config_batch()
+    plans = [ph.phiks_plan_params(b.A, b.tau, 3, 1, 2.0 ** -53, "same_vector",
+                                  [float(np.linalg.norm(b.v))])[:2] for b in probs]
+    launches, nbytes, bad, why = ph.batch_dryrun([b.n for b in probs], plans, 3, 1, 4)
+    print(f"[dryrun] 512 problems: {launches} launches, {nbytes} table bytes")
+    assert bad == 0, why
+    assert launches > 0 and nbytes > 0
+    shapes = [[7], [5, 3], [9, 10, 11], [1, 1], [130, 3, 2], [2, 3, 2, 3, 2]]
+    pl = [(2, 5), (1, 3), (4, 12), (1, 4), (3, 7), (2, 9)]
+    for p in (0, 1, 4):
+        for ns in (1, 2):
+            for fk in (0, 1, 4):
+                _, _, bad, why = ph.batch_dryrun(shapes, pl, p, ns, fk)
+                assert bad == 0, (p, ns, fk, why)
+    with pytest.raises(ph.PhiksError):
+        ph.batch_dryrun([[7]], [(0, 5)], 2, 2)       # s < n_scales - 1
+    with pytest.raises(ph.PhiksError):
+        ph.batch_dryrun([[7]], [(1, 2)], 2, 1)       # q below 3

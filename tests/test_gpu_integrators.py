@@ -100,3 +100,47 @@ def test_higher_order_schemes_on_gpu_match_oracle(adr, scheme, steps):
     err = rel_inf(u, adr.exact(0.1))
     print(f"[gpu {scheme} {steps} steps] error {err:.3e}; vs oracle {d:.2e}")
     assert d < 1e-11
+
+
+@pytest.mark.parametrize("smart", [True, False])
+def test_exprk4s5_brusselator_matches_oracle(smart):
+    """The five-stage fourth-order scheme (eq. expRK4s5; smart: the five lines of eq.
+    expRK4s5_smart) on the two-species Brusselator system (block-diagonal K, 12^3 grid per
+    species, Neumann FD2), GPU driver against the oracle driver of the same form."""
+    from paper_2210_07667_amd import integrators as gi
+    pr = workloads.brusselator_problem(n=12, d=3)
+    g_gpu = gi.BrusselatorNonlinearity(pr.a, pr.b, pr.N)
+    g_cpu = oi.brusselator_nonlinearity(pr.a, pr.b, pr.N)
+    u = gi.exprk4s5(pr.blocks, pr.w0, g_gpu, 0.5, 3, smart=smart).to_numpy()
+    ref = oi.exprk4s5(pr.blocks, pr.w0, g_cpu, 0.5, 3, smart=smart)
+    d = rel_inf(u, ref)
+    print(f"[gpu expRK4s5 brusselator smart={smart}] vs oracle {d:.2e}")
+    assert d < 1e-11
+
+
+def test_exprk4s5_adr_matches_oracle_and_converges(adr):
+    """One block (the ADR problem of Section 4.2): GPU against the oracle, and the GPU
+    errors against the exact solution fall at fourth order."""
+    from paper_2210_07667_amd import integrators as gi
+    g = gi.ADRNonlinearity(adr.u0, adr.w)
+    e = []
+    for steps in (5, 10):
+        u = gi.exprk4s5([adr.A], adr.u0, g, 0.1, steps).to_numpy()
+        e.append(rel_inf(u, adr.exact(0.1)))
+        if steps == 5:
+            ref = oi.exprk4s5([adr.A], adr.u0, oi.adr_nonlinearity(adr), 0.1, 5, smart=True)
+            assert rel_inf(u, ref) < 1e-11
+    rate = np.log2(e[0] / e[1])
+    print(f"[gpu expRK4s5 adr] errors {e} observed order {rate:.2f}")
+    assert abs(rate - 4) < 0.3
+
+
+def test_brusselator_vector_ops_match_numpy():
+    rng = np.random.default_rng(3)
+    n = 777
+    x, y = rng.standard_normal(n), rng.standard_normal(n)
+    dx, dy, do = ph.DeviceArray.from_numpy(x), ph.DeviceArray.from_numpy(y), ph.DeviceArray(n)
+    ph.vector_op(ph.PHIKS_VOP_BRUSS_U, n, 1.5, dx.ptr, 0.0, dy.ptr, do.ptr)
+    np.testing.assert_allclose(do.to_numpy(), 1.5 + x * x * y, rtol=1e-14, atol=1e-14)
+    ph.vector_op(ph.PHIKS_VOP_BRUSS_V, n, 3.0, dx.ptr, 0.0, dy.ptr, do.ptr)
+    np.testing.assert_allclose(do.to_numpy(), 3.0 * x - x * x * y, rtol=1e-14, atol=1e-14)
