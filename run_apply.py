@@ -1,6 +1,6 @@
 """Time phiks_apply on the 3D advection-diffusion-reaction workload in one arithmetic.
 
-    python paper_2210_07667_amd/run_apply.py --precision bf16x3 --n 256 --reps 5
+    python run_apply.py --precision bf16x3 --n 256 --reps 5
 
 Builds the plan once (tau = 1e-3, phi_0..phi_4 of one vector, tolerance 2^-53 ||v||),
 then runs one warm-up call, `reps` timed calls of phiks_apply on the null stream and one
@@ -14,7 +14,7 @@ import os
 import sys
 import time
 
-ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 

@@ -1,6 +1,6 @@
 """Time phiks_batch_apply on the batched workload (512 uneven problems).
 
-    python paper_2210_07667_amd/run_batch.py --count 512 --reps 3
+    python run_batch.py --count 512 --reps 3
 
 Plans the batch once (d in {2, 3}, n_mu in 16..128, Chebyshev second-derivative
 operators, tau log-uniform in [1e-4, 1e-2], phi_0..phi_3 of one vector, tolerance
@@ -18,7 +18,7 @@ import time
 
 import numpy as np
 
-ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 
