@@ -226,16 +226,17 @@ def small_2d_section(ph, reps=50):
                     "each waited for on the host"}
 
 
-def batched_section(ph, reps=3):
+def batched_section(ph, reps=3, precision=0):
     """The 512-problem batched workload (d in {2, 3}, n_mu in 16..128, Chebyshev D^2,
     tau log-uniform, phi_0..phi_3): one phiks_batch_apply against the same problems
-    run one by one through phiks_apply (plans built beforehand in both cases)."""
+    run one by one through phiks_apply (plans built beforehand in both cases), in the
+    mu-mode arithmetic `precision` (FP64 or FP32 MFMA)."""
     import workloads
     problems = workloads.config_batch()
     norms = [float(np.linalg.norm(b.v)) for b in problems]
     tp0 = time.perf_counter()
     batch = ph.phiks_batch_plan([b.A for b in problems], [b.tau for b in problems], 3, 1,
-                                2.0 ** -53, vnorms=norms)
+                                2.0 ** -53, vnorms=norms, precision=precision)
     ph.synchronize()
     plan_s = time.perf_counter() - tp0
     dv = [ph.DeviceArray.from_numpy(b.v) for b in problems]
@@ -264,7 +265,7 @@ def batched_section(ph, reps=3):
     batch.close()
     ws.free()
     # the same problems through the single-problem path, one call each
-    plans = [ph.phiks_plan(b.A, b.tau, 3, 1, 2.0 ** -53, "same_vector", [nv])
+    plans = [ph.phiks_plan(b.A, b.tau, 3, 1, 2.0 ** -53, "same_vector", [nv], precision=precision)
              for b, nv in zip(problems, norms)]
     wsz = max(pl.workspace_size() for pl in plans)
     ws1 = ph.DeviceArray(wsz // 8 + 1)
@@ -283,7 +284,8 @@ def batched_section(ph, reps=3):
     for x in dv + outs:
         x.free()
     total = sum(b.N for b in problems)
-    return {"workload": "batched_512_cheb_d2_phi0-3_tau1e-4..1e-2_fp64", "problems": len(problems),
+    return {"workload": "batched_512_cheb_d2_phi0-3_tau1e-4..1e-2_" +
+                        ("fp32" if precision == ph.PHIKS_FP32 else "fp64"), "problems": len(problems),
             "total_dofs": total, "apply_ms": batch_ms, "dofs_per_s": total / (batch_ms * 1e-3),
             "plan_s": plan_s, "max_s": smax, "mu_mode_launches": k_launch,
             "mu_mode_tflops": (k_flops / (k_ms * 1e-3)) / 1e12 if k_ms > 0 else 0.0,
@@ -569,6 +571,7 @@ def main():
     if not args.no_batched:
         log("[bench] batched workload (512 problems)")
         line["batched"] = batched_section(ph)
+        line["batched_fp32"] = batched_section(ph, precision=ph.PHIKS_FP32)
     if not args.no_serving:
         log("[bench] serving workload")
         line["serving"] = serving_section(ph)

@@ -241,7 +241,9 @@ int phiks_kernel_timing_read(double* total_ms, int64_t* launches, double* flops)
  * p, n_scales, tol and precision are shared.  vnorms: host array of count values
  * ||v_i||_2, or NULL (norms 1).  Each problem gets exactly the (s, q) phiks_plan would
  * choose for it; the small exponentials of all problems are built in one device pass.
- * precision must be PHIKS_FP64.  Errors as phiks_plan; a failing problem is named in
+ * precision: PHIKS_FP64, or PHIKS_FP32 (FP32-MFMA mu-mode products; every product of a
+ * problem then runs in the tile and kernel its single FP32 call gives it, so the
+ * outputs are bitwise that call's).  Errors as phiks_plan; a failing problem is named in
  * phiks_last_error().
  *
  * phiks_batch_apply -- v: host array of count device pointers (N_i doubles each);
@@ -270,6 +272,19 @@ int phiks_batch_info(phiks_batch_t batch, int i, int* s, int* q, int* tucker_pap
                      int* tucker_exec);
 /* Stream-ordered release, as phiks_plan_destroy. */
 void phiks_batch_destroy(phiks_batch_t batch);
+
+/*
+ * phiks_batch_tuning -- the rules that pick the tile class of the batched path's grouped
+ * FP64 products (host only).  params[0..4]: the side from which 64 x 64 tiles are used
+ * (1..128), and 0/1 switches for the skinny 32 x 128 / 128 x 32 classes, 128 x 64 tiles for
+ * mode-1 plain stores, for plain stores of modes > 1, and for the squaring epilogue (each
+ * with M >= 128, N >= 64).  set = 0 reads them into params; set = 1 replaces them (a
+ * batch's captured graph is then rebuilt on its next calls) and reads them back.  The
+ * built-in values are those tune_batch.py recorded for the batched workload.  Every
+ * choice gives bitwise the same results (one k order in every FP64 kernel and tile).
+ * PHIKS_EINVAL for out-of-range values.
+ */
+int phiks_batch_tuning(int set, int* params);
 
 /*
  * phiks_batch_dryrun -- host only (no device, nothing launched): builds the launch

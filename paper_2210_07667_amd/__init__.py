@@ -56,7 +56,7 @@ SYMBOLS = ("phiks_plan", "phiks_apply", "phiks_combine", "phiks_workspace_size",
            "phiks_server_wait", "phiks_server_stats", "phiks_server_destroy",
            "phiks_vector_op", "phiks_plan_complex", "phiks_plan_params_complex",
            "phiks_server_lane", "phiks_server_select_evictions", "phiks_server_clock",
-           "phiks_apply_noalloc", "phiks_plan_matrix", "phiks_batch_dryrun")
+           "phiks_apply_noalloc", "phiks_plan_matrix", "phiks_batch_dryrun", "phiks_batch_tuning")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with "
@@ -123,6 +123,8 @@ _lib.phiks_batch_info.restype = ctypes.c_int
 _lib.phiks_batch_info.argtypes = [_vp, ctypes.c_int] + [ctypes.POINTER(ctypes.c_int)] * 4
 _lib.phiks_batch_destroy.restype = None
 _lib.phiks_batch_destroy.argtypes = [_vp]
+_lib.phiks_batch_tuning.restype = ctypes.c_int
+_lib.phiks_batch_tuning.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
 _lib.phiks_batch_dryrun.restype = ctypes.c_int
 _lib.phiks_batch_dryrun.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(_i64p),
                                     ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
@@ -596,6 +598,22 @@ def batch_apply_arrays(batch: Batch, vs: Sequence[DeviceArray], outs=None, ws=No
         ws = DeviceArray(batch.workspace_size() // 8 + 1)
     phiks_batch_apply(batch, [v.ptr for v in vs], [o.ptr for o in outs], ws.ptr, ws.nbytes, stream)
     return outs
+
+
+BATCH_TUNING_FIELDS = ("sq_min", "skinny", "wide_m1", "wide_mk", "wide_lc")
+
+
+def batch_tuning(values: Optional[dict] = None) -> dict:
+    """The batched path's tile-class rules (phiks_batch_tuning); with values, replace them
+    first (missing keys keep their current value)."""
+    arr = (ctypes.c_int * 5)()
+    _check(_lib.phiks_batch_tuning(0, arr), "phiks_batch_tuning")
+    if values:
+        for k, name in enumerate(BATCH_TUNING_FIELDS):
+            if name in values:
+                arr[k] = int(values[name])
+        _check(_lib.phiks_batch_tuning(1, arr), "phiks_batch_tuning")
+    return {name: arr[k] for k, name in enumerate(BATCH_TUNING_FIELDS)}
 
 
 def batch_dryrun(shapes, plans, p: int, n_scales: int, fork_streams: int = 4):

@@ -15,7 +15,9 @@
 
 #include <algorithm>
 #include <cstring>
+#include <map>
 #include <string>
+#include <tuple>
 #include <thread>
 #include <vector>
 
@@ -55,6 +57,28 @@ struct phiks_batch_s {
 
 namespace {
 
+// Rules that pick the tile class of an FP64 grouped product (BatchSchedule::tile_class).
+// The values in use come from batch_tuning.inc, written by tune_batch.py, which times the
+// batched workload under every combination and keeps the fastest; phiks_batch_tuning
+// reads or replaces them at run time (the tuner's own knob).
+struct BatchTuning {
+  int sq_min;    // 64 x 64 tiles when both sides reach this (else 32 x 32 or a skinny class)
+  int skinny;    // 1: 32 x 128 / 128 x 32 tiles for one side <= 32 against the other >= 96
+  int wide_m1;   // 1: 128 x 64 tiles for plain-store products of mode 1 with M >= 128
+  int wide_mk;   // 1: 128 x 64 tiles for plain-store products of modes > 1 with M >= 128
+  int wide_lc;   // 1: 128 x 64 tiles for the squaring epilogue's products with M >= 128
+};
+#include "batch_tuning.inc"
+std::mutex g_tuning_mu;
+BatchTuning g_batch_tuning = kBatchTuningTuned;
+int64_t g_tuning_gen = 0;   // bumped on every change (captured graphs depend on the rules)
+
+BatchTuning batch_tuning(int64_t* gen = nullptr) {
+  std::lock_guard<std::mutex> lk(g_tuning_mu);
+  if (gen) *gen = g_tuning_gen;
+  return g_batch_tuning;
+}
+
 enum class StepKind { Gemm, Combine };
 
 // One GEMM of a step: its views, its layout (mode 1: B k-contiguous), and whether it
@@ -67,6 +91,10 @@ struct StepGemm {
   const double* Y;
   int64_t YN;
   int p = 0;   // squaring epilogue: the problem's highest phi index (its coefficients)
+  // arithmetic: PHIKS_FP64, or PHIKS_FP32 with f32_kind 0 (mode 1: FP64 input, FP32 out),
+  // 1 (FP32 -> FP32), 2 (FP32 -> FP64 store), 3 (FP32 -> FP64 squaring epilogue)
+  int prec = PHIKS_FP64;
+  int f32_kind = 0;
 };
 
 #ifndef PHIKS_BATCH_FORK
@@ -85,6 +113,11 @@ struct GroupedLaunch {
   double flops = 0.0;    // GEMM: algorithmic 2 M N K over all items and batches
   int step = 0;          // launches of one step touch disjoint problems
   int lin_p = 0;         // squaring epilogue: coefficients of BatchSchedule::lin[lin_p]
+  // FP32 products: the single path's configuration (tile bm x bn, kernel), the kind of
+  // product (StepGemm::f32_kind); single: one item, launched as the single path launches it
+  int prec = PHIKS_FP64;
+  int bm = 0, bn = 0, f32_kind = 0;
+  bool single = false;
 };
 
 // Host builder of one call's launches and their tables.
@@ -125,19 +158,104 @@ struct BatchSchedule {
   static bool dl_ok(const GemmArgs& g, bool kc) {
     return PHIKS_DL == 1 && g.K % PHIKS_DL_BK == 0 && vec_ok(g, kc, {});
   }
-  static int tile_class(const GemmArgs& g, bool kc, bool dl, bool lincomb) {
-    // (measured on the batched workload: the squaring epilogue, which streams the pre-step
-    // tensors, and the products of modes > 1 run best with the larger count of 64 x 64
-    // work-groups)
-    if (dl && kc && !lincomb && g.M >= 128 && g.N >= 64) return 4;
-    if (g.M >= 48 && g.N >= 48) return 0;
-    if (dl && g.M <= 32 && g.N >= 96) return 2;
-    if (dl && g.N <= 32 && g.M >= 96) return 3;
+  BatchTuning tune = batch_tuning();
+  int tile_class(const GemmArgs& g, bool kc, bool dl, bool lincomb) const {
+    const bool wide = g.M >= 128 && g.N >= 64;
+    if (dl && wide && !lincomb && (kc ? tune.wide_m1 : tune.wide_mk)) return 4;
+    if (dl && wide && lincomb && tune.wide_lc) return 4;
+    if (g.M >= tune.sq_min && g.N >= tune.sq_min) return 0;
+    if (tune.skinny && dl && g.M <= 32 && g.N >= 96) return 2;
+    if (tune.skinny && dl && g.N <= 32 && g.M >= 96) return 3;
     return 1;
   }
 
-  void add_gemm_step(const std::vector<StepGemm>& items) {
+  // FP32 products of one step: partitioned by the configuration the single path gives
+  // each item (cfg32), so every item runs the tiles and kernel of its single call.
+  void add_gemm32(const std::vector<StepGemm>& items, int step) {
+    struct Key {
+      int kc, bm, bn, dl, kind, lp;
+      bool operator<(const Key& o) const {
+        return std::tie(kc, bm, bn, dl, kind, lp) < std::tie(o.kc, o.bm, o.bn, o.dl, o.kind, o.lp);
+      }
+    };
+    std::map<Key, std::vector<const StepGemm*>> parts;
+    for (const StepGemm& it : items) {
+      const bool lc = it.f32_kind == 3;
+      const bool dl_epi = !lc || (PHIKS_MIXED_LC_DL == 1 && lincomb_dl_ok(it.g, it.Y, it.YN));
+      const Cfg32 c = cfg32(it.g, it.kc, it.f32_kind == 0, dl_epi);
+      // grouped kernels exist for 16-byte loads, tiles up to 128 x 64 and mode 1 feeding
+      // FP32 intermediates; anything else is launched alone, as its single call does
+      const bool grouped = c.vec && !(c.bm == 128 && c.bn == 128) && (it.kc == (it.f32_kind == 0));
+      if (!grouped) {
+        GroupedLaunch L;
+        L.kind = StepKind::Gemm;
+        L.prec = PHIKS_FP32;
+        L.single = true;
+        L.kc = it.kc;
+        L.f32_kind = it.f32_kind;
+        L.lin_p = lc ? it.p : 0;
+        L.lincomb = lc;
+        GroupItem gi;
+        gi.g = it.g;
+        gi.Y = it.Y;
+        gi.YN = it.YN;
+        L.n = 1;
+        L.total = 1;
+        L.flops = 2.0 * it.g.M * (double)it.g.N * it.g.K * it.g.nb0 * (double)it.g.nb1;
+        L.items_off = put(&gi, sizeof(gi));
+        L.step = step;
+        launches.push_back(L);
+        continue;
+      }
+      parts[{it.kc ? 1 : 0, c.bm, c.bn, c.dl ? 1 : 0, it.f32_kind, lc ? it.p : 0}].push_back(&it);
+    }
+    for (auto& kv : parts) {
+      const Key& k = kv.first;
+      std::vector<GroupItem> part;
+      std::vector<int64_t> first;
+      int64_t total = 0;
+      double flops = 0.0;
+      for (const StepGemm* it : kv.second) {
+        GroupItem gi;
+        gi.g = it->g;
+        gi.g.tiles_m = (gi.g.M + k.bm - 1) / k.bm;
+        gi.g.tiles_n = (gi.g.N + k.bn - 1) / k.bn;
+        gi.g.total_tiles = (int64_t)gi.g.tiles_m * gi.g.tiles_n * gi.g.nb0 * gi.g.nb1;
+        if (gi.g.total_tiles <= 0) continue;
+        gi.Y = it->Y;
+        gi.YN = it->YN;
+        flops += 2.0 * gi.g.M * (double)gi.g.N * gi.g.K * gi.g.nb0 * (double)gi.g.nb1;
+        first.push_back(total);
+        total += gi.g.total_tiles;
+        part.push_back(gi);
+      }
+      if (part.empty()) continue;
+      GroupedLaunch L;
+      L.kind = StepKind::Gemm;
+      L.prec = PHIKS_FP32;
+      L.kc = k.kc == 1;
+      L.bm = k.bm;
+      L.bn = k.bn;
+      L.dl = k.dl == 1;
+      L.vec = true;
+      L.f32_kind = k.kind;
+      L.lincomb = k.kind == 3;
+      L.lin_p = k.lp;
+      L.n = (int)part.size();
+      L.total = total;
+      L.flops = flops;
+      L.items_off = put(part.data(), part.size() * sizeof(GroupItem));
+      L.first_off = put(first.data(), first.size() * sizeof(int64_t));
+      L.step = step;
+      launches.push_back(L);
+    }
+  }
+
+  void add_gemm_step(const std::vector<StepGemm>& all) {
     const int step = steps++;
+    std::vector<StepGemm> items, items32;
+    for (const StepGemm& it : all) (it.prec == PHIKS_FP32 ? items32 : items).push_back(it);
+    if (!items32.empty()) add_gemm32(items32, step);
     // the p values of the squaring-epilogue items (one launch per p: their coefficients)
     std::vector<int> lps;
     for (const StepGemm& it : items)
@@ -270,6 +388,31 @@ struct GroupWork {
   int p = 0, ns = 1;
 };
 
+// Matrices of a plan's Tucker operator in its arithmetic: the node matrices (level false,
+// from node idx) or exp(B/2^idx) (level true); FP32 plans use their FP32 copies (views
+// hold them as double pointers, as the single path's mixed chains do).
+void plan_mats(const phiks_plan_s& P, bool level, int idx, double** L) {
+  for (int mu = 0; mu < P.d; ++mu) {
+    const size_t off = (size_t)idx * P.n[mu] * P.n[mu];
+    if (P.precision == PHIKS_FP32)
+      L[mu] = reinterpret_cast<double*>((level ? P.E32[mu] : P.Lnode32[mu]) + off);
+    else
+      L[mu] = (level ? P.E[mu] : P.Lnode[mu]) + off;
+  }
+}
+
+// A step item of mode mu (1-based) of a plan's Tucker operator, tagged with its arithmetic.
+StepGemm step_item(const phiks_plan_s& P, const GemmArgs& g, int mu, bool lincomb,
+                   const double* Y, int p) {
+  const bool last = (mu == P.d);
+  StepGemm it{g, mu == 1, last && lincomb, (last && lincomb) ? Y : nullptr, P.N, p};
+  if (P.precision == PHIKS_FP32) {
+    it.prec = PHIKS_FP32;
+    it.f32_kind = !last ? (mu == 1 ? 0 : 1) : (lincomb ? 3 : 2);
+  }
+  return it;
+}
+
 // Builds the launches of one grouped execution (the same order of operations as
 // phiks_apply for every problem).
 void build_group_schedule(const GroupWork& W, BatchSchedule& S) {
@@ -304,13 +447,16 @@ void build_group_schedule(const GroupWork& W, BatchSchedule& S) {
       int64_t stride[PHIKS_MAX_D];
       for (int mu = 0; mu < P.d; ++mu) stride[mu] = P.n[mu] * P.n[mu];
       double* wbuf = tucker_free_buffer(P.d, bf[i].ta, bf[i].tb);
-      tucker_args(P.d, P.n, P.N, v[i], 0, P.Lnode, stride, plan_nodes(P), wbuf, bf[i].ta,
+      double* Ln[PHIKS_MAX_D];
+      plan_mats(P, false, 0, Ln);
+      tucker_args(P.d, P.n, P.N, v[i], 0, Ln, stride, plan_nodes(P), wbuf, bf[i].ta,
                   bf[i].tb, views[i].data());
     }
     for (int mu = 1; mu <= dmax; ++mu) {
       std::vector<StepGemm> items;
       for (int i = 0; i < count; ++i)
-        if ((*W.plans[i]).d >= mu) items.push_back({views[i][mu - 1], mu == 1, false, nullptr, 0});
+        if ((*W.plans[i]).d >= mu)
+          items.push_back(step_item(*W.plans[i], views[i][mu - 1], mu, false, nullptr, p));
       S.add_gemm_step(items);
     }
     // node sums
@@ -348,7 +494,7 @@ void build_group_schedule(const GroupWork& W, BatchSchedule& S) {
         dst[i] = (j - 1 < ns) ? slot(i, j - 1, 1) : ((bf[i].cur == bf[i].pa) ? bf[i].pb : bf[i].pa);
         double* L[PHIKS_MAX_D];
         int64_t stride[PHIKS_MAX_D] = {0};
-        for (int mu = 0; mu < P.d; ++mu) L[mu] = P.E[mu] + (size_t)j * P.n[mu] * P.n[mu];
+        plan_mats(P, true, j, L);
         tucker_args(P.d, P.n, P.N, bf[i].cur, P.N, L, stride, p, dst[i], bf[i].ta, bf[i].tb,
                     lv[i].data());
       }
@@ -358,7 +504,7 @@ void build_group_schedule(const GroupWork& W, BatchSchedule& S) {
           const phiks_plan_s& P = (*W.plans[i]);
           if (P.s <= t || P.d < mu) continue;
           const bool last = (mu == P.d);
-          items.push_back({lv[i][mu - 1], mu == 1, last, last ? bf[i].cur : nullptr, P.N, p});
+          items.push_back(step_item(P, lv[i][mu - 1], mu, last, bf[i].cur, p));
         }
         S.add_gemm_step(items);
       }
@@ -373,14 +519,15 @@ void build_group_schedule(const GroupWork& W, BatchSchedule& S) {
       const phiks_plan_s& P = (*W.plans[i]);
       double* L[PHIKS_MAX_D];
       int64_t stride[PHIKS_MAX_D] = {0};
-      for (int mu = 0; mu < P.d; ++mu) L[mu] = P.E[mu] + (size_t)lev * P.n[mu] * P.n[mu];
+      plan_mats(P, true, lev, L);
       tucker_args(P.d, P.n, P.N, v[i], 0, L, stride, 1, slot(i, lev, 0), bf[i].ta, bf[i].tb,
                   ev[i].data());
     }
     for (int mu = 1; mu <= dmax; ++mu) {
       std::vector<StepGemm> items;
       for (int i = 0; i < count; ++i)
-        if ((*W.plans[i]).d >= mu) items.push_back({ev[i][mu - 1], mu == 1, false, nullptr, 0});
+        if ((*W.plans[i]).d >= mu)
+          items.push_back(step_item(*W.plans[i], ev[i][mu - 1], mu, false, nullptr, p));
       S.add_gemm_step(items);
     }
   }
@@ -419,7 +566,64 @@ int upload_group(GroupTables& T, const BatchSchedule& S, hipStream_t st) {
   return PHIKS_OK;
 }
 
+// ------------------------------------------------ FP32 grouped launches
+template <int BM, int BN, int WM, int WN, bool KC, class TA, class TC, class Epi>
+int launch_grouped32_cfg(const GroupedLaunch& L, const char* dev, const Epi& epi, hipStream_t st) {
+  if (L.total > 0x7fffffffLL) {
+    set_error("grouped GEMM grid too large");
+    return PHIKS_EINVAL;
+  }
+  const GroupItem* items = (const GroupItem*)(dev + L.items_off);
+  const int64_t* first = (const int64_t*)(dev + L.first_off);
+  if constexpr (BM >= 64 && BN >= 64) {
+    if (L.dl)
+      return timed_launch(&gemm_f32_dl_grouped<BM, BN, WM, WN, KC, TA, TC, Epi>, (unsigned)L.total, st,
+                          L.flops, items, first, L.n, L.total, epi);
+  }
+  return timed_launch(&gemm_f32_grouped<BM, BN, WM, WN, KC, true, TA, TC, Epi>, (unsigned)L.total, st,
+                      L.flops, items, first, L.n, L.total, epi);
+}
+
+template <bool KC, class TA, class TC, class Epi>
+int launch_grouped32(const GroupedLaunch& L, const char* dev, const Epi& epi, hipStream_t st) {
+  if (L.bm == 128 && L.bn == 64) return launch_grouped32_cfg<128, 64, 64, 32, KC, TA, TC>(L, dev, epi, st);
+  if (L.bm == 64 && L.bn == 128) return launch_grouped32_cfg<64, 128, 32, 64, KC, TA, TC>(L, dev, epi, st);
+  if (L.bm == 64 && L.bn == 64) return launch_grouped32_cfg<64, 64, 32, 32, KC, TA, TC>(L, dev, epi, st);
+  return launch_grouped32_cfg<32, 32, 16, 16, KC, TA, TC>(L, dev, epi, st);
+}
+
+// An FP32 product of a batch: grouped, or (L.single) launched as its single call does.
+int issue_one32(const GroupedLaunch& L, const char* dev, const BatchSchedule& S, hipStream_t st) {
+  const EpiStoreT<float> to32{1.0, 0.0};
+  const EpiStore to64{1.0, 0.0};
+  if (L.single) {
+    const GroupItem& it = *(const GroupItem*)(S.buf.data() + L.items_off);   // host copy
+    switch (L.f32_kind) {
+      case 0:
+        return L.kc ? launch_gemm32<true, double, float>(it.g, to32, st)
+                    : launch_gemm32<false, double, float>(it.g, to32, st);
+      case 1: return launch_gemm32<false, float, float>(it.g, to32, st);
+      case 2: return L.kc ? launch_gemm32<true, double, double>(it.g, to64, st)
+                          : launch_gemm32<false, float, double>(it.g, to64, st);
+      default: {
+        EpiLinComb e = S.lin[L.lin_p];
+        e.Y = it.Y;
+        e.N = it.YN;
+        return L.kc ? launch_gemm32<true, double, double>(it.g, e, st)
+                    : launch_gemm32<false, float, double>(it.g, e, st);
+      }
+    }
+  }
+  switch (L.f32_kind) {
+    case 0: return launch_grouped32<true, double, float>(L, dev, to32, st);
+    case 1: return launch_grouped32<false, float, float>(L, dev, to32, st);
+    case 2: return launch_grouped32<false, float, double>(L, dev, to64, st);
+    default: return launch_grouped32<false, float, double>(L, dev, S.lin[L.lin_p], st);
+  }
+}
+
 int issue_one(const GroupedLaunch& L, const char* dev, const BatchSchedule& S, hipStream_t st) {
+  if (L.kind == StepKind::Gemm && L.prec == PHIKS_FP32) return issue_one32(L, dev, S, st);
   if (L.kind == StepKind::Combine) {
     const int64_t blocks = std::min<int64_t>((L.total + 255) / 256, 1024);
     (void)hipGetLastError();
@@ -689,6 +893,24 @@ void dry_check_schedule(const BatchSchedule& S, const DryRunSpace& sp, int count
 
 extern "C" {
 
+int phiks_batch_tuning(int set, int* params) {
+  if (!params) return PHIKS_EINVAL;
+  std::lock_guard<std::mutex> lk(g_tuning_mu);
+  if (set) {
+    if (params[0] < 1 || params[0] > 128) return PHIKS_EINVAL;
+    for (int k = 1; k < 5; ++k)
+      if (params[k] != 0 && params[k] != 1) return PHIKS_EINVAL;
+    g_batch_tuning = BatchTuning{params[0], params[1], params[2], params[3], params[4]};
+    ++g_tuning_gen;
+  }
+  params[0] = g_batch_tuning.sq_min;
+  params[1] = g_batch_tuning.skinny;
+  params[2] = g_batch_tuning.wide_m1;
+  params[3] = g_batch_tuning.wide_mk;
+  params[4] = g_batch_tuning.wide_lc;
+  return PHIKS_OK;
+}
+
 int phiks_batch_dryrun(int count, const int* d, const int64_t* const* n, const int* s,
                        const int* q, int p, int n_scales, int fork_streams, int64_t* launches,
                        int64_t* table_bytes, int64_t* violations) {
@@ -766,8 +988,8 @@ int phiks_batch_plan(int count, const int* d, const int64_t* const* n,
   if (!out) return PHIKS_EINVAL;
   *out = nullptr;
   if (count < 1 || !d || !n || !A || !tau) return PHIKS_EINVAL;
-  if (precision != PHIKS_FP64) {
-    set_error("batched problems run in FP64");
+  if (precision != PHIKS_FP64 && precision != PHIKS_FP32) {
+    set_error("batched problems run in FP64 or FP32");
     return PHIKS_EINVAL;
   }
   phiks_batch_s* B = new (std::nothrow) phiks_batch_s;
@@ -877,6 +1099,9 @@ int phiks_batch_apply(phiks_batch_t batch, const double* const* v, double* const
   std::vector<const void*> key(v, v + B.count);
   key.insert(key.end(), out, out + B.count);
   key.push_back(ws);
+  int64_t gen = 0;
+  (void)batch_tuning(&gen);
+  key.push_back((const void*)(uintptr_t)gen);   // the rules the captured launches used
   const bool timing = kernel_timing_on();
   if (!timing && B.graph && key == B.graph_key) {
     HIP_OK(hipGraphLaunch(B.graph, st));

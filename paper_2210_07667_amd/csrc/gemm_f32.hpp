@@ -128,7 +128,7 @@ __device__ __forceinline__ void store_acc_tile(const flt4 (&acc)[FM][FN], const 
 #endif
 
 template <int BM, int BN, int WM, int WN, bool B_KCONTIG, bool VEC, class TA, class TC, class Epi>
-__global__ void __launch_bounds__(256, VEC ? PHIKS_F32_MIN_WAVES : 2) gemm_f32_kernel(GemmArgs g, Epi epi) {
+__device__ __forceinline__ void gemm_f32_tile(const GemmArgs& g, const Epi& epi, int64_t rest) {
   constexpr int BK = PHIKS_F32_BK;
   constexpr int WGM = BM / WM;
   constexpr int WGN = BN / WN;
@@ -143,7 +143,6 @@ __global__ void __launch_bounds__(256, VEC ? PHIKS_F32_MIN_WAVES : 2) gemm_f32_k
   __shared__ __align__(16) float As[2][BK][BM];
   __shared__ __align__(16) float Bs[2][BK][BN];
 
-  int64_t rest = xcd_remap(blockIdx.x, g.total_tiles);
   int tm, tn;
   int64_t z1, z0;
   if constexpr (B_KCONTIG) {
@@ -314,6 +313,30 @@ __global__ void __launch_bounds__(256, VEC ? PHIKS_F32_MIN_WAVES : 2) gemm_f32_k
   }
 
   store_acc_tile<FM, FN, TC>(acc, g, epi, Cb, cbase, z1, m0 + wm, n0 + wn, lr, lk);
+}
+
+template <int BM, int BN, int WM, int WN, bool B_KCONTIG, bool VEC, class TA, class TC, class Epi>
+__global__ void __launch_bounds__(256, VEC ? PHIKS_F32_MIN_WAVES : 2) gemm_f32_kernel(GemmArgs g, Epi epi) {
+  gemm_f32_tile<BM, BN, WM, WN, B_KCONTIG, VEC, TA, TC, Epi>(g, epi, xcd_remap(blockIdx.x, g.total_tiles));
+}
+
+// Grouped launch (many independent FP32 products of one configuration in one grid, as
+// gemm_f64_grouped): each item runs exactly the tiles gemm_f32_kernel would run for it.
+template <int BM, int BN, int WM, int WN, bool B_KCONTIG, bool VEC, class TA, class TC, class Epi>
+__global__ void __launch_bounds__(256, VEC ? PHIKS_F32_MIN_WAVES : 2)
+    gemm_f32_grouped(const GroupItem* __restrict__ items, const int64_t* __restrict__ first,
+                     int nitems, int64_t total, Epi epi) {
+  const int64_t t = xcd_remap(blockIdx.x, total);
+  const int i = find_group_item(first, nitems, t);
+  const GroupItem& it = items[i];
+  if constexpr (std::is_same<Epi, EpiLinComb>::value) {
+    Epi e = epi;
+    e.Y = it.Y;
+    e.N = it.YN;
+    gemm_f32_tile<BM, BN, WM, WN, B_KCONTIG, VEC, TA, TC, Epi>(it.g, e, t - first[i]);
+  } else {
+    gemm_f32_tile<BM, BN, WM, WN, B_KCONTIG, VEC, TA, TC, Epi>(it.g, epi, t - first[i]);
+  }
 }
 
 }  // namespace phiks

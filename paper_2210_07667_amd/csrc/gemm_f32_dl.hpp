@@ -281,4 +281,22 @@ __global__ void __launch_bounds__(256, f32dl_min_waves<Epi>()) gemm_f32_dl_kerne
   gemm_f32_dl_tile<BM, BN, WM, WN, B_KCONTIG, TA, TC, Epi>(g, epi, xcd_remap(blockIdx.x, g.total_tiles));
 }
 
+// Grouped launch of the direct-to-LDS FP32 kernel (see gemm_f32_grouped).
+template <int BM, int BN, int WM, int WN, bool B_KCONTIG, class TA, class TC, class Epi>
+__global__ void __launch_bounds__(256, f32dl_min_waves<Epi>())
+    gemm_f32_dl_grouped(const GroupItem* __restrict__ items, const int64_t* __restrict__ first,
+                        int nitems, int64_t total, Epi epi) {
+  const int64_t t = xcd_remap(blockIdx.x, total);
+  const int i = find_group_item(first, nitems, t);
+  const GroupItem& it = items[i];
+  if constexpr (std::is_same<Epi, EpiLinComb>::value) {
+    Epi e = epi;
+    e.Y = it.Y;
+    e.N = it.YN;
+    gemm_f32_dl_tile<BM, BN, WM, WN, B_KCONTIG, TA, TC, Epi>(it.g, e, t - first[i]);
+  } else {
+    gemm_f32_dl_tile<BM, BN, WM, WN, B_KCONTIG, TA, TC, Epi>(it.g, epi, t - first[i]);
+  }
+}
+
 }  // namespace phiks

@@ -75,19 +75,46 @@ int launch_cfg32(const GemmArgs& g, const Epi& epi, hipStream_t st) {
 #ifndef PHIKS_F32_BIG_TILE
 #define PHIKS_F32_BIG_TILE 1  // 1: 128 x 128 tiles (4 waves of 64 x 64) where they fill the GPU
 #endif
+// The configuration an FP32 product runs in (tile, load width, kernel): 128 x 128 tiles
+// (4 waves of 64 x 64) where 256 of them fill the GPU, else 128 x 64 or 64 x 128 where those
+// do, else 64 x 64 when both sides reach 48 (the direct-to-LDS kernel needs 64-wide tiles;
+// a product too small to fill the GPU keeps that tile rather than splitting into 32 x 32
+// ones, so grouped launches of many small products -- batches -- run it too), else 32 x 32.
+// launch_gemm32 runs exactly this; grouped launches of FP32 batches take it per item, so
+// each item runs the tiles of its single call.  a_double: A is the FP64 input (mode 1);
+// dl_epi_ok: the epilogue passes lincomb_ok.
+struct Cfg32 {
+  int bm, bn;
+  bool vec, dl;
+};
+Cfg32 cfg32(const GemmArgs& g, bool kc, bool a_double, bool dl_epi_ok) {
+  Cfg32 c{32, 32, vec4_ok(g, kc), false};
+  if (PHIKS_F32_BIG_TILE == 1 && g.M >= 128 && g.N >= 128 && tiles_for(g, 128, 128) >= 256) {
+    c.bm = c.bn = 128;
+  } else {
+    switch (pick_tile(g)) {
+      case Tile::T128x128:
+      case Tile::T128x64: c.bm = 128; c.bn = 64; break;
+      case Tile::T64x128: c.bm = 64; c.bn = 128; break;
+      case Tile::T64x64: c.bm = 64; c.bn = 64; break;
+      default:
+        if (g.M >= 48 && g.N >= 48) c.bm = c.bn = 64;
+        break;
+    }
+  }
+  c.dl = PHIKS_DL == 1 && c.vec && (PHIKS_F32_DL_A64 == 1 || !a_double) && c.bm >= 64 &&
+         c.bn >= 64 && g.K % 16 == 0 && g.pA == nullptr && dl_epi_ok;
+  return c;
+}
+
 template <bool KC, bool VEC, class TA, class TC, class Epi>
 int launch_tile32(const GemmArgs& g, const Epi& epi, hipStream_t st) {
-#if PHIKS_F32_BIG_TILE == 1
-  if (g.M >= 128 && g.N >= 128 && tiles_for(g, 128, 128) >= 256)
-    return launch_cfg32<128, 128, 64, 64, KC, VEC, TA, TC>(g, epi, st);
-#endif
-  switch (pick_tile(g)) {
-    case Tile::T128x128:
-    case Tile::T128x64: return launch_cfg32<128, 64, 64, 32, KC, VEC, TA, TC>(g, epi, st);
-    case Tile::T64x128: return launch_cfg32<64, 128, 32, 64, KC, VEC, TA, TC>(g, epi, st);
-    case Tile::T64x64: return launch_cfg32<64, 64, 32, 32, KC, VEC, TA, TC>(g, epi, st);
-    default: return launch_cfg32<32, 32, 16, 16, KC, VEC, TA, TC>(g, epi, st);
-  }
+  const Cfg32 c = cfg32(g, KC, std::is_same<TA, double>::value, lincomb_ok(g, epi));
+  if (c.bm == 128 && c.bn == 128) return launch_cfg32<128, 128, 64, 64, KC, VEC, TA, TC>(g, epi, st);
+  if (c.bm == 128) return launch_cfg32<128, 64, 64, 32, KC, VEC, TA, TC>(g, epi, st);
+  if (c.bn == 128) return launch_cfg32<64, 128, 32, 64, KC, VEC, TA, TC>(g, epi, st);
+  if (c.bm == 64) return launch_cfg32<64, 64, 32, 32, KC, VEC, TA, TC>(g, epi, st);
+  return launch_cfg32<32, 32, 16, 16, KC, VEC, TA, TC>(g, epi, st);
 }
 
 template <bool KC, class TA, class TC, class Epi>

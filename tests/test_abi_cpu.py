@@ -192,7 +192,7 @@ def test_batch_plan_rejects_bad_problems_before_device_work():
     assert "problem 4" in str(e.value)
     with pytest.raises(ph.PhiksError) as e:
         ph.phiks_batch_plan([b.A for b in problems], [b.tau for b in problems], 3, 1, 1e-10,
-                            precision=ph.PHIKS_FP32)
+                            precision=ph.PHIKS_BF16X3)     # batches run in FP64 or FP32
     assert e.value.status == ph.PHIKS_EINVAL
     with pytest.raises(ValueError):
         ph.phiks_batch_plan([b.A for b in problems], [b.tau for b in problems[:-1]], 3, 1, 1e-10)
@@ -265,3 +265,26 @@ def test_batch_dryrun_checks_the_512_problem_schedule():
         ph.batch_dryrun([[7]], [(0, 5)], 2, 2)       # s < n_scales - 1
     with pytest.raises(ph.PhiksError):
         ph.batch_dryrun([[7]], [(1, 2)], 2, 1)       # q below 3
+
+
+def test_batch_tuning_rules_roundtrip_and_schedules_stay_consistent():
+    """The batched path's tile rules (phiks_batch_tuning) can be read and replaced, bad
+    values are refused, and the 512-problem schedule passes the dry-run checks under
+    other rules too."""
+    start = ph.batch_tuning()
+    try:
+        probs = workloads.config_batch(count=64, seed=9)
+        plans = [ph.phiks_plan_params(b.A, b.tau, 3, 1, 2.0 ** -53)[:2] for b in probs]
+        for rules in ({"sq_min": 32, "skinny": 0}, {"sq_min": 64, "wide_mk": 1, "wide_lc": 1},
+                      {"sq_min": 1, "wide_m1": 0}):
+            got = ph.batch_tuning(rules)
+            assert all(got[k] == v for k, v in rules.items())
+            _, _, bad, why = ph.batch_dryrun([b.n for b in probs], plans, 3, 1, 4)
+            assert bad == 0, (rules, why)
+        with pytest.raises(ph.PhiksError):
+            ph.batch_tuning({"skinny": 2})
+        with pytest.raises(ph.PhiksError):
+            ph.batch_tuning({"sq_min": 0})
+    finally:
+        ph.batch_tuning(start)
+    assert ph.batch_tuning() == start

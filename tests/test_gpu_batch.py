@@ -28,8 +28,9 @@ def _need_gpu():
         pytest.skip("no GPU")
 
 
-def single(b, p, ns):
-    plan = ph.phiks_plan(b.A, b.tau, p, ns, TOL, "same_vector", [np.linalg.norm(b.v)])
+def single(b, p, ns, precision=0):
+    plan = ph.phiks_plan(b.A, b.tau, p, ns, TOL, "same_vector", [np.linalg.norm(b.v)],
+                         precision=precision)
     out = ph.apply_arrays(plan, ph.DeviceArray.from_numpy(b.v))
     ph.synchronize()
     info = plan.info()
@@ -37,10 +38,10 @@ def single(b, p, ns):
     return out.to_numpy(), info
 
 
-def run_batch(problems, p, ns, vs=None):
+def run_batch(problems, p, ns, vs=None, precision=0):
     vs = vs if vs is not None else [b.v for b in problems]
     batch = ph.phiks_batch_plan([b.A for b in problems], [b.tau for b in problems], p, ns, TOL,
-                                vnorms=[np.linalg.norm(v) for v in vs])
+                                vnorms=[np.linalg.norm(v) for v in vs], precision=precision)
     dv = [ph.DeviceArray.from_numpy(v) for v in vs]
     outs = ph.batch_apply_arrays(batch, dv)
     ph.synchronize()
@@ -179,4 +180,55 @@ def test_batch_graph_replays_match_eager():
             for i, o in enumerate(outs2):
                 assert np.array_equal(o.to_numpy(), ref[i]), ("switch", i)
     plan.close()
+    batch.close()
+
+
+FP32_CASES = {
+    "batched_workload_24": (lambda: workloads.config_batch(count=24, seed=5), 3, 1),
+    # odd sizes (products launched alone, as their single calls are) and d = 1
+    "ragged_p2_two_scales": (ragged_problems, 2, 2),
+}
+
+
+@pytest.mark.parametrize("name", list(FP32_CASES))
+def test_fp32_batch_bitwise_equals_single_fp32_calls(name):
+    """FP32-MFMA batches: every product of a problem runs, grouped with the other
+    problems', in the configuration (tile, load width, kernel) its single FP32 call gives it
+    (or alone when no grouped kernel has that configuration), so each problem's outputs are
+    bitwise those of phiks_apply with a PHIKS_FP32 plan."""
+    make, p, ns = FP32_CASES[name]
+    problems = make()
+    print(f"[batch fp32] {name}: {len(problems)} problems", flush=True)
+    batch, outs = run_batch(problems, p, ns, precision=ph.PHIKS_FP32)
+    for i, b in enumerate(problems):
+        ref, info = single(b, p, ns, precision=ph.PHIKS_FP32)
+        assert batch.info(i) == info
+        assert np.array_equal(outs[i], ref), (name, i, b.n)
+    batch.close()
+
+
+def test_fp32_full_batched_workload_sampled_and_against_oracle():
+    """The 512-problem workload in FP32: a sample bitwise against single FP32 calls, and
+    the smallest sampled problems against the FP64 oracle within the FP32 bar of
+    test_gpu_mixed.py (2e-6: the rounding of each level's FP32 products is not amplified
+    by the contractive recurrence; measured <= 4.1e-7 up to s = 10)."""
+    problems = workloads.config_batch()
+    batch, outs = run_batch(problems, 3, 1, precision=ph.PHIKS_FP32)
+    rng = np.random.default_rng(1)
+    sample = sorted(set(rng.choice(len(problems), size=8, replace=False).tolist()) |
+                    {int(np.argmax([b.N for b in problems]))})
+    for i in sample:
+        ref, info = single(problems[i], 3, 1, precision=ph.PHIKS_FP32)
+        assert batch.info(i) == info
+        assert np.array_equal(outs[i], ref), (i, problems[i].n)
+    small = sorted(sample, key=lambda i: problems[i].N)[:3]
+    for i in small:
+        b = problems[i]
+        info = batch.info(i)
+        o = ophiks.phi_same_vector(b.A, b.tau, b.v, 3, 1, info["s"], info["q"])
+        got = outs[i].reshape(1, 4, -1)
+        err = max(float(np.abs(got[0, l] - o[0, l]).max() / np.abs(o[0, l]).max()) for l in range(4))
+        bar = 2e-6
+        print(f"[batch fp32] problem {i} n={b.n} s={info['s']}: rel err vs oracle {err:.2e} (bar {bar:.1e})")
+        assert err < bar
     batch.close()
