@@ -52,7 +52,8 @@ enum {
   PHIKS_ENOMEM = -3,      /* device or host allocation failed */
   PHIKS_EDEVICE = -4,     /* a HIP call failed; phiks_last_error() has the text */
   PHIKS_EWORKSPACE = -5,  /* workspace pointer NULL or ws_bytes too small */
-  PHIKS_ENONFINITE = -6   /* non-finite matrix entry, tau or tolerance */
+  PHIKS_ENONFINITE = -6,  /* non-finite matrix entry, tau or tolerance */
+  PHIKS_ETIMEDOUT = -7    /* a served request's deadline passed before it finished */
 };
 
 enum { PHIKS_SAME_VECTOR = 0, PHIKS_LINCOMB = 1 };
@@ -72,14 +73,16 @@ enum { PHIKS_FP64 = 0, PHIKS_FP32 = 1, PHIKS_BF16X3 = 2 };
 /*
  * phiks_plan -- choose (s, q) and build the small exponentials.
  *
- * Section 3.3: for s = max(0, n_scales-1), max(0, n_scales-1)+1, ... take the
- * smallest q in [3, 12] whose quadrature remainder bound (estimate CPestimate over
- * the rectangle Xi = Xi_1 + ... + Xi_d containing the numerical range of tau K,
- * Xi_mu the Bendixson rectangle of tau A_mu) satisfies
+ * Section 3.3: for s = max(0, n_scales-1), max(0, n_scales-1)+1, ... (up to s_max) take
+ * the smallest q in [q_min, q_max] whose quadrature remainder bound (estimate
+ * CPestimate over the rectangle Xi = Xi_1 + ... + Xi_d containing the numerical range
+ * of tau K, Xi_mu the rectangle of tau A_mu) satisfies
  *   same vector:  b_{q,l}(s) ||v||_2 <= tol 2^(l s),                       l = 1..p
  *   combination:  sum_{k<=l} b_{q,l-k+1}(s) ||v_{p+1-k}||_2 / 2^((l-k+1)s) <= tol
  * and stop before the first s whose Tucker count (eq. Tpsv: q + s p + n_scales;
  * eq. Tlcp: q p + s p + n_scales) is strictly larger than the previous one.
+ * q_min, q_max, s_max and the rectangle's kind are the planner options
+ * (phiks_planner_options; defaults 3, 12, 64 and the Bendixson rectangle).
  * Then, on the device, the scaling-and-squaring exponentials (degree-24 Taylor)
  * exp((1 - theta_i) tau A_mu / 2^s) for every Gauss-Lobatto node theta_i < 1 and
  * exp(tau A_mu / 2^j) for j = s..0 (by squaring, Section 3.1) are computed.
@@ -329,10 +332,14 @@ int phiks_batch_dryrun(int count, const int* d, const int64_t* const* n, const i
  *
  * phiks_server_submit -- one request on a registered operator: tau, p, n_scales, tol
  * as phiks_plan (tolerance relative: norms taken as 1), precision PHIKS_FP64 /
- * PHIKS_FP32 / PHIKS_BF16X3, v (device, N doubles) and out (device,
- * n_scales*(p+1)*N doubles, laid out as phiks_apply's out).  v and out must stay valid
- * until phiks_server_wait returns for the ticket.  Validation errors are returned here,
- * before anything is queued.  Plans are cached on (operator, tau, p, n_scales, tol,
+ * PHIKS_FP32 / PHIKS_BF16X3, timeout_s (seconds from submission, >= 0; 0 = no
+ * deadline), v (device, N doubles) and out (device, n_scales*(p+1)*N doubles, laid out
+ * as phiks_apply's out).  v and out must stay valid until phiks_server_wait returns for
+ * the ticket.  Validation errors are returned here, before anything is queued.  A
+ * request still queued at its deadline completes with PHIKS_ETIMEDOUT without running
+ * (out untouched); one running at its deadline is issued no further step and completes
+ * with PHIKS_ETIMEDOUT once its steps already issued are done (out then holds partial
+ * results).  Plans are cached on (operator, tau, p, n_scales, tol,
  * precision); least recently used plans that no running request holds are evicted when
  * the cache would exceed hbm_budget - workspace_bytes.
  *
@@ -353,6 +360,7 @@ typedef struct {
   int64_t evictions;
   int64_t cache_bytes;   /* device bytes of the cached plans */
   int64_t cached_plans;
+  int64_t timed_out;     /* requests completed with PHIKS_ETIMEDOUT */
 } phiks_server_stats_t;
 
 int phiks_server_create(size_t hbm_budget, size_t workspace_bytes, int max_active, int lanes,
@@ -360,8 +368,8 @@ int phiks_server_create(size_t hbm_budget, size_t workspace_bytes, int max_activ
 int phiks_server_register(phiks_server_t server, int d, const int64_t* n,
                           const double* const* A, int64_t* op_id);
 int phiks_server_submit(phiks_server_t server, int64_t op_id, double tau, int p, int n_scales,
-                        double tol, int precision, const double* v, double* out,
-                        int64_t* ticket);
+                        double tol, int precision, double timeout_s, const double* v,
+                        double* out, int64_t* ticket);
 int phiks_server_wait(phiks_server_t server, int64_t ticket, double* latency_s, double* done_s);
 int phiks_server_stats(phiks_server_t server, phiks_server_stats_t* out);
 void phiks_server_destroy(phiks_server_t server);
@@ -445,6 +453,44 @@ int phiks_gll(int q, double* theta, double* w);
 /* Bendixson rectangle of the n x n row-major host matrix B: re_lo, re_hi, im_lo,
  * im_hi (xi[0..3]) of [lambda(H)] x i[lambda(S)], H = (B+B^T)/2, S = (B-B^T)/(2i). */
 int phiks_rectangle(int64_t n, const double* B, double* xi);
+
+/* Planner options (Section 3.3: q is searched over 3..12 and s upward from n_scales - 1
+ * until the Tucker count grows; the rectangle covering the numerical range of each A_mu
+ * is to be built from its Hermitian and skew-Hermitian parts, with no construction
+ * fixed).  Two readings of that rectangle:
+ *   PHIKS_RECT_BENDIXSON      [lambda_min(H), lambda_max(H)] x i[lambda_min(G),
+ *                             lambda_max(G)], H = (B+B^*)/2, G = (B-B^*)/(2i): the
+ *                             tightest axis-aligned box around W(B) (default);
+ *   PHIKS_RECT_NORM_CENTERED  the box centred at sigma = tr(B)/n (the shift of the
+ *                             remark in Section 3.1) with half-widths
+ *                             ||H - Re(sigma) I||_2 and ||G - Im(sigma) I||_2; it
+ *                             contains the Bendixson box. */
+enum { PHIKS_RECT_BENDIXSON = 0, PHIKS_RECT_NORM_CENTERED = 1 };
+
+typedef struct phiks_planner_options_s {
+  int q_min;  /* smallest q tried, >= 3 */
+  int q_max;  /* largest q tried, q_min <= q_max <= 12 */
+  int s_max;  /* largest s tried, 0..64; no feasible s <= s_max gives PHIKS_ENOPLAN */
+  int rect;   /* PHIKS_RECT_BENDIXSON or PHIKS_RECT_NORM_CENTERED */
+} phiks_planner_options_t;
+
+/* phiks_planner_options -- reads and/or replaces the process-wide planner options that
+ * every later plan uses (phiks_plan, phiks_plan_complex, phiks_plan_params*,
+ * phiks_batch_plan, the server's plans; existing plans keep their (s, q)).
+ *   set  host struct, or NULL to leave the options unchanged.
+ *   get  host struct receiving the options in force before this call, or NULL.
+ * Defaults: q 3..12, s_max 64, Bendixson.  At the first plan or options call the
+ * environment variables PHIKS_QMIN, PHIKS_QMAX, PHIKS_SMAX (integers) and
+ * PHIKS_PLAN_RECT (bendixson | normcentered) override them; a malformed or out-of-range
+ * setting keeps the defaults and makes every plan, and this call with set == NULL,
+ * return PHIKS_EINVAL until a valid `set` replaces it.  Returns PHIKS_EINVAL (nothing
+ * changed) for an invalid `set`.  Thread-safe; the server's plan cache does not reuse
+ * plans made under earlier options. */
+int phiks_planner_options(const phiks_planner_options_t* set, phiks_planner_options_t* get);
+
+/* The rectangle of kind `rect` (PHIKS_RECT_*) of the n x n row-major host matrix B:
+ * re_lo, re_hi, im_lo, im_hi in xi[0..3]. */
+int phiks_range_rectangle(int64_t n, const double* B, int rect, double* xi);
 
 /* Remainder bound of estimate (CPestimate) at one point w = w_re + i w_im of the
  * numerical range: |R_q(f_l(., w))| for l = 1..p written to err[0..p-1], computed

@@ -13,9 +13,11 @@ Follows Section 3.3 of the paper:
   which is what the oracle computes, directly from that definition, in mpmath with
   as many digits as the cancellation needs.
 * Omega is the rectangle Xi = Xi_1 + ... + Xi_d, Xi_mu covering W(B_mu) (B_mu = tau
-  A_mu); W(K) is the Minkowski sum of the W(A_mu).  Reading used here: Xi_mu is the
-  Bendixson rectangle [lambda_min(H), lambda_max(H)] x i[lambda_min(S), lambda_max(S)]
-  with H = (B + B^H)/2 and S = (B - B^H)/(2i).
+  A_mu); W(K) is the Minkowski sum of the W(A_mu).  Reading used by default: Xi_mu is
+  the Bendixson rectangle [lambda_min(H), lambda_max(H)] x i[lambda_min(S),
+  lambda_max(S)] with H = (B + B^H)/2 and S = (B - B^H)/(2i); the alternative reading
+  (``rectangle(..., "norm_centered")``) centres the box at tr(B)/n with the 2-norms of
+  the shifted H and S as half-widths.
 * By the maximum modulus principle the supremum is taken on the boundary of Xi,
   discretised by ``M_SIDE`` equispaced points per side (corners included).
 * Same vector (formula (Tpsv)): starting from s = 0 (here from s = n_scales - 1 so
@@ -43,22 +45,43 @@ M_SIDE = 16                       # boundary points per side of the rectangle
 CP_CONST = 1.0 + math.sqrt(2.0)   # Crouzeix-Palencia constant
 
 
-def rectangle(B: np.ndarray) -> Tuple[float, float, float, float]:
-    """Bendixson rectangle (re_lo, re_hi, im_lo, im_hi) containing W(B)."""
+RECT_KINDS = ("bendixson", "norm_centered")
+
+
+def rectangle(B: np.ndarray, kind: str = "bendixson") -> Tuple[float, float, float, float]:
+    """A rectangle (re_lo, re_hi, im_lo, im_hi) containing W(B).
+
+    Section 3.3 builds it from the Hermitian part H = (B + B^H)/2 and the skew-Hermitian
+    part, written here as the Hermitian S = (B - B^H)/(2i), without fixing how; two
+    readings:
+    * ``bendixson``: [lambda_min(H), lambda_max(H)] x i[lambda_min(S), lambda_max(S)];
+    * ``norm_centered``: centred at sigma = tr(B)/n (the shift of the remark in Section
+      3.1), half-widths ||H - Re(sigma) I||_2 and ||S - Im(sigma) I||_2.
+    """
     B = np.asarray(B)
     Bh = B.conj().T
     H = (B + Bh) / 2.0
     S = (B - Bh) / 2.0j
-    eh = np.linalg.eigvalsh(H)
-    es = np.linalg.eigvalsh(S)
-    return float(eh[0]), float(eh[-1]), float(es[0]), float(es[-1])
+    if kind == "bendixson":
+        eh = np.linalg.eigvalsh(H)
+        es = np.linalg.eigvalsh(S)
+        return float(eh[0]), float(eh[-1]), float(es[0]), float(es[-1])
+    if kind == "norm_centered":
+        n = B.shape[0]
+        sigma = complex(np.trace(B)) / n
+        eye = np.eye(n)
+        hr = float(np.linalg.norm(H - sigma.real * eye, 2))
+        hi = float(np.linalg.norm(S - sigma.imag * eye, 2))
+        return sigma.real - hr, sigma.real + hr, sigma.imag - hi, sigma.imag + hi
+    raise ValueError(f"unknown rectangle kind {kind!r}")
 
 
-def kron_sum_rectangle(Bs: Sequence[np.ndarray]) -> Tuple[float, float, float, float]:
+def kron_sum_rectangle(Bs: Sequence[np.ndarray],
+                       kind: str = "bendixson") -> Tuple[float, float, float, float]:
     """Xi = Xi_1 + ... + Xi_d (sum of the rectangles of the B_mu)."""
     r = [0.0, 0.0, 0.0, 0.0]
     for B in Bs:
-        x = rectangle(B)
+        x = rectangle(B, kind)
         for k in range(4):
             r[k] += x[k]
     return tuple(r)

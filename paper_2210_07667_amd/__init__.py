@@ -29,6 +29,7 @@ PHIKS_ENOMEM = -3
 PHIKS_EDEVICE = -4
 PHIKS_EWORKSPACE = -5
 PHIKS_ENONFINITE = -6
+PHIKS_ETIMEDOUT = -7
 PHIKS_SAME_VECTOR = 0
 PHIKS_LINCOMB = 1
 PHIKS_FP64 = 0
@@ -42,6 +43,8 @@ PHIKS_VOP_BRUSS_V = 4
 PHIKS_MATRIX_NODE = 0
 PHIKS_MATRIX_LEVEL = 1
 NOALLOC_SCRATCH_BYTES = 64 << 20     # PHIKS_NOALLOC_SCRATCH_BYTES
+PHIKS_RECT_BENDIXSON = 0
+PHIKS_RECT_NORM_CENTERED = 1
 
 # every exported entry point of include/phiks.h
 SYMBOLS = ("phiks_plan", "phiks_apply", "phiks_combine", "phiks_workspace_size",
@@ -56,7 +59,8 @@ SYMBOLS = ("phiks_plan", "phiks_apply", "phiks_combine", "phiks_workspace_size",
            "phiks_server_wait", "phiks_server_stats", "phiks_server_destroy",
            "phiks_vector_op", "phiks_plan_complex", "phiks_plan_params_complex",
            "phiks_server_lane", "phiks_server_select_evictions", "phiks_server_clock",
-           "phiks_apply_noalloc", "phiks_plan_matrix", "phiks_batch_dryrun", "phiks_batch_tuning")
+           "phiks_apply_noalloc", "phiks_plan_matrix", "phiks_batch_dryrun", "phiks_batch_tuning",
+           "phiks_planner_options", "phiks_range_rectangle")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with "
@@ -106,6 +110,21 @@ _lib.phiks_gll.restype = ctypes.c_int
 _lib.phiks_gll.argtypes = [ctypes.c_int, _dp, _dp]
 _lib.phiks_rectangle.restype = ctypes.c_int
 _lib.phiks_rectangle.argtypes = [ctypes.c_int64, _dp, _dp]
+_lib.phiks_range_rectangle.restype = ctypes.c_int
+_lib.phiks_range_rectangle.argtypes = [ctypes.c_int64, _dp, ctypes.c_int, _dp]
+
+
+class PlannerOptions(ctypes.Structure):
+    """phiks_planner_options_t: the planner's q range, s limit and rectangle kind."""
+    _fields_ = [("q_min", ctypes.c_int), ("q_max", ctypes.c_int), ("s_max", ctypes.c_int),
+                ("rect", ctypes.c_int)]
+
+    def as_tuple(self):
+        return (self.q_min, self.q_max, self.s_max, self.rect)
+
+
+_lib.phiks_planner_options.restype = ctypes.c_int
+_lib.phiks_planner_options.argtypes = [ctypes.POINTER(PlannerOptions), ctypes.POINTER(PlannerOptions)]
 _lib.phiks_remainder.restype = ctypes.c_int
 _lib.phiks_remainder.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                  _dp]
@@ -134,7 +153,8 @@ _lib.phiks_batch_dryrun.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_int), 
 
 class ServerStats(ctypes.Structure):
     _fields_ = [(k, ctypes.c_int64) for k in ("completed", "ticks", "cache_hits", "cache_misses",
-                                              "evictions", "cache_bytes", "cached_plans")]
+                                              "evictions", "cache_bytes", "cached_plans",
+                                              "timed_out")]
 
 
 _lib.phiks_server_create.restype = ctypes.c_int
@@ -144,7 +164,8 @@ _lib.phiks_server_register.restype = ctypes.c_int
 _lib.phiks_server_register.argtypes = [_vp, ctypes.c_int, _i64p, _dpp, _i64p]
 _lib.phiks_server_submit.restype = ctypes.c_int
 _lib.phiks_server_submit.argtypes = [_vp, ctypes.c_int64, ctypes.c_double, ctypes.c_int,
-                                     ctypes.c_int, ctypes.c_double, ctypes.c_int, _vp, _vp, _i64p]
+                                     ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_double,
+                                     _vp, _vp, _i64p]
 _lib.phiks_server_wait.restype = ctypes.c_int
 _lib.phiks_server_wait.argtypes = [_vp, ctypes.c_int64, _dp, _dp]
 _lib.phiks_server_clock.restype = ctypes.c_double
@@ -390,6 +411,33 @@ def phiks_rectangle(B: np.ndarray):
     xi = (ctypes.c_double * 4)()
     _check(_lib.phiks_rectangle(B.shape[0], B.ctypes.data_as(_dp), xi), "phiks_rectangle")
     return tuple(xi)
+
+
+def phiks_range_rectangle(B: np.ndarray, rect: int = PHIKS_RECT_BENDIXSON):
+    B = np.ascontiguousarray(np.asarray(B, dtype=np.float64))
+    xi = (ctypes.c_double * 4)()
+    _check(_lib.phiks_range_rectangle(B.shape[0], B.ctypes.data_as(_dp), int(rect), xi),
+           "phiks_range_rectangle")
+    return tuple(xi)
+
+
+def planner_options(q_min=None, q_max=None, s_max=None, rect=None):
+    """Returns the planner options in force, as (q_min, q_max, s_max, rect); with any
+    argument given, replaces those fields (the others kept) and returns the previous
+    options."""
+    cur = PlannerOptions()
+    if q_min is None and q_max is None and s_max is None and rect is None:
+        _check(_lib.phiks_planner_options(None, ctypes.byref(cur)), "phiks_planner_options")
+        return cur.as_tuple()
+    rc = _lib.phiks_planner_options(None, ctypes.byref(cur))
+    if rc not in (PHIKS_OK, PHIKS_EINVAL):   # EINVAL: an invalid environment setting
+        _check(rc, "phiks_planner_options")
+    new = PlannerOptions(cur.q_min if q_min is None else int(q_min),
+                         cur.q_max if q_max is None else int(q_max),
+                         cur.s_max if s_max is None else int(s_max),
+                         cur.rect if rect is None else int(rect))
+    _check(_lib.phiks_planner_options(ctypes.byref(new), None), "phiks_planner_options")
+    return cur.as_tuple()
 
 
 def phiks_remainder(q: int, p: int, w: complex):
@@ -692,11 +740,12 @@ class Server:
         return op.value
 
     def submit(self, op: int, tau: float, p: int, n_scales: int, tol: float, v_ptr: int,
-               out_ptr: int, precision: int = PHIKS_FP64) -> int:
+               out_ptr: int, precision: int = PHIKS_FP64, timeout: float = 0.0) -> int:
+        """Queues one request; `timeout` seconds from now is its deadline (0: none)."""
         t = ctypes.c_int64()
         _check(_lib.phiks_server_submit(self._h, int(op), float(tau), int(p), int(n_scales),
-                                        float(tol), int(precision), _vp(v_ptr), _vp(out_ptr),
-                                        ctypes.byref(t)),
+                                        float(tol), int(precision), float(timeout), _vp(v_ptr),
+                                        _vp(out_ptr), ctypes.byref(t)),
                "phiks_server_submit")
         return t.value
 

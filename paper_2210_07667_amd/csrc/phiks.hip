@@ -344,19 +344,39 @@ int validate_problem(int d, const int64_t* n, const double* const* A, double tau
 }
 
 // host planning shared by phiks_plan and phiks_plan_params
+// The process-wide planner options, or EINVAL (with the reason) while the environment
+// holds an invalid setting.
+int current_planner_options(PlannerOptions& opt) {
+  if (planner_options(opt)) return PHIKS_OK;
+  set_error("invalid planner setting in PHIKS_QMIN, PHIKS_QMAX, PHIKS_SMAX or PHIKS_PLAN_RECT");
+  return PHIKS_EINVAL;
+}
+
+void set_noplan_error(const PlannerOptions& opt) {
+  char msg[128];
+  std::snprintf(msg, sizeof msg, "no (s, q) with s <= %d and %d <= q <= %d meets the tolerance",
+                opt.s_max, opt.q_min, opt.q_max);
+  set_error(msg);
+}
+
+// host planning shared by phiks_plan and phiks_plan_params (tau > 0, so tau scales the
+// rectangle without reordering its sides)
 int host_plan(int d, const int64_t* n, const double* const* A, double tau, int p,
               int n_scales, double tol, int task, const double* vnorms, PlanChoice& pc) {
+  PlannerOptions opt;
+  int rc = current_planner_options(opt);
+  if (rc != PHIKS_OK) return rc;
   Rect xi{0.0, 0.0, 0.0, 0.0};
   for (int mu = 0; mu < d; ++mu) {
-    Rect r = bendixson_rectangle(n[mu], A[mu]);
+    Rect r = range_rectangle(n[mu], A[mu], opt.rect);
     xi.re_lo += tau * r.re_lo;
     xi.re_hi += tau * r.re_hi;
     xi.im_lo += tau * r.im_lo;
     xi.im_hi += tau * r.im_hi;
   }
-  pc = choose_sq(xi, p, n_scales, tol, task, vnorms);
+  pc = choose_sq(xi, p, n_scales, tol, task, vnorms, opt);
   if (!pc.ok) {
-    set_error("no (s, q) with s <= 64 and q <= 12 meets the tolerance");
+    set_noplan_error(opt);
     return PHIKS_ENOPLAN;
   }
   return PHIKS_OK;
@@ -405,7 +425,8 @@ int plan_init_host(phiks_plan_s& P, int d, const int64_t* n, const double* const
 }
 
 // Complex problems: A_mu complex (re/im interleaved, row-major), tau complex and
-// nonzero.  The rectangle is the Bendixson rectangle of each B_mu = tau A_mu, summed.
+// nonzero.  The rectangle (of the kind the planner options select) is that of each
+// B_mu = tau A_mu, summed.
 int plan_init_host_complex(phiks_plan_s& P, int d, const int64_t* n, const double* const* A,
                            double tau_re, double tau_im, int p, int n_scales, double tol,
                            int task, const double* vnorms) {
@@ -414,6 +435,9 @@ int plan_init_host_complex(phiks_plan_s& P, int d, const int64_t* n, const doubl
   if (task != PHIKS_SAME_VECTOR && task != PHIKS_LINCOMB) return PHIKS_EINVAL;
   if (!std::isfinite(tau_re) || !std::isfinite(tau_im) || !std::isfinite(tol)) return PHIKS_ENONFINITE;
   if ((tau_re == 0.0 && tau_im == 0.0) || !(tol > 0.0)) return PHIKS_EINVAL;
+  PlannerOptions opt;
+  int orc = current_planner_options(opt);
+  if (orc != PHIKS_OK) return orc;
   int64_t N = 1;
   Rect xi{0.0, 0.0, 0.0, 0.0};
   for (int mu = 0; mu < d; ++mu) {
@@ -428,7 +452,7 @@ int plan_init_host_complex(phiks_plan_s& P, int d, const int64_t* n, const doubl
       B[2 * e] = tau_re * ar - tau_im * ai;
       B[2 * e + 1] = tau_re * ai + tau_im * ar;
     }
-    const Rect r = bendixson_rectangle_complex(m, B.data());
+    const Rect r = range_rectangle_complex(m, B.data(), opt.rect);
     xi.re_lo += r.re_lo;
     xi.re_hi += r.re_hi;
     xi.im_lo += r.im_lo;
@@ -443,9 +467,9 @@ int plan_init_host_complex(phiks_plan_s& P, int d, const int64_t* n, const doubl
     for (int k = 0; k < nv; ++k)
       if (!std::isfinite(vnorms[k]) || vnorms[k] < 0.0) return PHIKS_EINVAL;
   }
-  const PlanChoice pc = choose_sq(xi, p, n_scales, tol, task, vnorms);
+  const PlanChoice pc = choose_sq(xi, p, n_scales, tol, task, vnorms, opt);
   if (!pc.ok) {
-    set_error("no (s, q) with s <= 64 and q <= 12 meets the tolerance");
+    set_noplan_error(opt);
     return PHIKS_ENOPLAN;
   }
   P.d = d;
@@ -752,6 +776,7 @@ const char* phiks_status_string(int status) {
     case PHIKS_EDEVICE: return "device error";
     case PHIKS_EWORKSPACE: return "workspace missing or too small";
     case PHIKS_ENONFINITE: return "non-finite input";
+    case PHIKS_ETIMEDOUT: return "deadline passed before the request finished";
     default: return "unknown status";
   }
 }
@@ -773,6 +798,51 @@ int phiks_rectangle(int64_t n, const double* B, double* xi) {
   xi[1] = r.re_hi;
   xi[2] = r.im_lo;
   xi[3] = r.im_hi;
+  return PHIKS_OK;
+}
+
+int phiks_range_rectangle(int64_t n, const double* B, int rect, double* xi) {
+  if (n < 1 || n > PHIKS_MAX_N || !B || !xi) return PHIKS_EINVAL;
+  if (rect != PHIKS_RECT_BENDIXSON && rect != PHIKS_RECT_NORM_CENTERED) return PHIKS_EINVAL;
+  for (int64_t e = 0; e < n * n; ++e)
+    if (!std::isfinite(B[e])) return PHIKS_ENONFINITE;
+  const Rect r = range_rectangle(n, B, (RectKind)rect);
+  xi[0] = r.re_lo;
+  xi[1] = r.re_hi;
+  xi[2] = r.im_lo;
+  xi[3] = r.im_hi;
+  return PHIKS_OK;
+}
+
+int phiks_planner_options(const phiks_planner_options_t* set, phiks_planner_options_t* get) {
+  PlannerOptions cur;
+  const bool env_ok = planner_options(cur);
+  if (get) {
+    get->q_min = cur.q_min;
+    get->q_max = cur.q_max;
+    get->s_max = cur.s_max;
+    get->rect = (int)cur.rect;
+  }
+  if (set) {
+    PlannerOptions o;
+    o.q_min = set->q_min;
+    o.q_max = set->q_max;
+    o.s_max = set->s_max;
+    if (set->rect != PHIKS_RECT_BENDIXSON && set->rect != PHIKS_RECT_NORM_CENTERED) {
+      set_error("planner options: unknown rectangle kind");
+      return PHIKS_EINVAL;
+    }
+    o.rect = (RectKind)set->rect;
+    if (!set_planner_options(o)) {
+      set_error("planner options: need 3 <= q_min <= q_max <= 12 and 0 <= s_max <= 64");
+      return PHIKS_EINVAL;
+    }
+    return PHIKS_OK;
+  }
+  if (!env_ok) {
+    set_error("invalid planner setting in PHIKS_QMIN, PHIKS_QMAX, PHIKS_SMAX or PHIKS_PLAN_RECT");
+    return PHIKS_EINVAL;
+  }
   return PHIKS_OK;
 }
 

@@ -23,14 +23,76 @@
 #include "planner.hpp"
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <complex>
+#include <cstdlib>
+#include <cstring>
 #include <limits>
 #include <mutex>
 
 namespace phiks {
 
 using cd = std::complex<double>;
+
+// ------------------------------------------------------------ planner options
+namespace {
+std::mutex g_opt_mu;
+bool g_opt_init = false;
+bool g_opt_env_bad = false;
+uint64_t g_opt_gen = 0;
+PlannerOptions g_opt;
+
+// First use: PHIKS_QMIN, PHIKS_QMAX, PHIKS_SMAX (integers) and PHIKS_PLAN_RECT
+// (bendixson | normcentered) override the defaults.  A malformed or out-of-range
+// setting leaves the defaults in place and marks the options invalid until replaced.
+void init_options_locked() {
+  if (g_opt_init) return;
+  g_opt_init = true;
+  PlannerOptions o;
+  bool bad = false;
+  auto read_int = [&](const char* name, int& dst) {
+    const char* v = std::getenv(name);
+    if (!v || !*v) return;
+    char* end = nullptr;
+    const long x = std::strtol(v, &end, 10);
+    if (*end != '\0' || x < INT_MIN || x > INT_MAX) {
+      bad = true;
+      return;
+    }
+    dst = (int)x;
+  };
+  read_int("PHIKS_QMIN", o.q_min);
+  read_int("PHIKS_QMAX", o.q_max);
+  read_int("PHIKS_SMAX", o.s_max);
+  const char* r = std::getenv("PHIKS_PLAN_RECT");
+  if (r && *r) {
+    if (!std::strcmp(r, "bendixson")) o.rect = RectKind::Bendixson;
+    else if (!std::strcmp(r, "normcentered")) o.rect = RectKind::NormCentered;
+    else bad = true;
+  }
+  if (bad || !planner_options_valid(o)) g_opt_env_bad = true;
+  else g_opt = o;
+}
+}  // namespace
+
+bool planner_options(PlannerOptions& out, uint64_t* generation) {
+  std::lock_guard<std::mutex> lk(g_opt_mu);
+  init_options_locked();
+  out = g_opt;
+  if (generation) *generation = g_opt_gen;
+  return !g_opt_env_bad;
+}
+
+bool set_planner_options(const PlannerOptions& o) {
+  if (!planner_options_valid(o)) return false;
+  std::lock_guard<std::mutex> lk(g_opt_mu);
+  init_options_locked();
+  g_opt = o;
+  g_opt_env_bad = false;
+  ++g_opt_gen;
+  return true;
+}
 
 // ------------------------------------------------------------------ GLL rule
 void gll_rule(int q, double* theta, double* w) {
@@ -449,10 +511,45 @@ bool check(int task, const double* b, int s, int p, double tol, const double* vn
 
 }  // namespace
 
+bool planner_options_valid(const PlannerOptions& o) {
+  return o.q_min >= kQMin && o.q_min <= o.q_max && o.q_max <= kQMax && o.s_max >= 0 &&
+         o.s_max <= kSMax && (o.rect == RectKind::Bendixson || o.rect == RectKind::NormCentered);
+}
+
+Rect norm_centered_rectangle(const Rect& b, double mean_re, double mean_im) {
+  const double hr = std::max(mean_re - b.re_lo, b.re_hi - mean_re);
+  const double hi = std::max(mean_im - b.im_lo, b.im_hi - mean_im);
+  return Rect{mean_re - hr, mean_re + hr, mean_im - hi, mean_im + hi};
+}
+
+Rect range_rectangle(int64_t n, const double* B, RectKind kind) {
+  Rect r = bendixson_rectangle(n, B);
+  if (kind == RectKind::NormCentered) {
+    double tr = 0.0;
+    for (int64_t k = 0; k < n; ++k) tr += B[k * n + k];
+    r = norm_centered_rectangle(r, tr / (double)n, 0.0);
+  }
+  return r;
+}
+
+Rect range_rectangle_complex(int64_t n, const double* B, RectKind kind) {
+  Rect r = bendixson_rectangle_complex(n, B);
+  if (kind == RectKind::NormCentered) {
+    double tr_re = 0.0, tr_im = 0.0;
+    for (int64_t k = 0; k < n; ++k) {
+      tr_re += B[2 * (k * n + k)];
+      tr_im += B[2 * (k * n + k) + 1];
+    }
+    r = norm_centered_rectangle(r, tr_re / (double)n, tr_im / (double)n);
+  }
+  return r;
+}
+
 PlanChoice choose_sq(const Rect& xi, int p, int n_scales, double tol, int task,
-                     const double* vnorms) {
+                     const double* vnorms, const PlannerOptions& opt) {
   PlanChoice out;
   const int s0 = std::max(0, n_scales - 1);
+  if (s0 > opt.s_max) return out;  // the requested scales need s >= n_scales - 1
   if (p == 0) {
     out.s = s0;
     out.q = 0;
@@ -484,11 +581,11 @@ PlanChoice choose_sq(const Rect& xi, int p, int n_scales, double tol, int task,
   bool have_prev = false;
   PlanChoice prev;
   double prevT = 0.0;
-  for (int s = s0; s <= kSMax; ++s) {
+  for (int s = s0; s <= opt.s_max; ++s) {
     int qf = -1;
-    if (feasible(s, kQMax)) {
-      for (int q = kQMin; q <= kQMax; ++q) {
-        if (q == kQMax || feasible(s, q)) { qf = q; break; }
+    if (feasible(s, opt.q_max)) {
+      for (int q = opt.q_min; q <= opt.q_max; ++q) {
+        if (q == opt.q_max || feasible(s, q)) { qf = q; break; }
       }
     }
     double T = (qf < 0) ? std::numeric_limits<double>::infinity()
@@ -501,7 +598,7 @@ PlanChoice choose_sq(const Rect& xi, int p, int n_scales, double tol, int task,
     prevT = T;
     have_prev = true;
   }
-  return prev;  // ok == false when no s <= kSMax was feasible
+  return prev;  // ok == false when no s <= opt.s_max was feasible
 }
 
 }  // namespace phiks

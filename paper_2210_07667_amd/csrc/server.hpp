@@ -37,7 +37,7 @@
 namespace {
 
 struct PlanKey {
-  std::vector<char> bytes;  // operator id, tau, p, n_scales, tol, precision
+  std::vector<char> bytes;  // operator id, tau, p, n_scales, tol, precision, options generation
   uint64_t hash = 0;
   bool operator==(const PlanKey& o) const { return hash == o.hash && bytes == o.bytes; }
 };
@@ -514,15 +514,18 @@ int phiks_server_register(phiks_server_t server, int d, const int64_t* n,
   return PHIKS_OK;
 }
 
+static_assert(phiks_serve::kTimedOut == PHIKS_ETIMEDOUT, "one status for expired requests");
+
 int phiks_server_submit(phiks_server_t server, int64_t op_id, double tau, int p, int n_scales,
-                        double tol, int precision, const double* v, double* out,
-                        int64_t* ticket) {
+                        double tol, int precision, double timeout_s, const double* v,
+                        double* out, int64_t* ticket) {
   if (!server || !v || !out || !ticket) return PHIKS_EINVAL;
   if (p < 0 || p > PHIKS_MAX_P || n_scales < 1 || n_scales > 16) return PHIKS_EINVAL;
   if (precision != PHIKS_FP64 && precision != PHIKS_FP32 && precision != PHIKS_BF16X3)
     return PHIKS_EINVAL;
   if (!std::isfinite(tau) || !std::isfinite(tol)) return PHIKS_ENONFINITE;
   if (!(tau > 0.0) || !(tol > 0.0)) return PHIKS_EINVAL;
+  if (!std::isfinite(timeout_s) || timeout_s < 0.0) return PHIKS_EINVAL;
   std::unique_ptr<ServedRequest> R(new (std::nothrow) ServedRequest);
   std::unique_ptr<phiks_serve::Request> r(new (std::nothrow) phiks_serve::Request);
   if (!R || !r) return PHIKS_ENOMEM;
@@ -543,6 +546,11 @@ int phiks_server_submit(phiks_server_t server, int64_t op_id, double tau, int p,
   put(&n_scales, sizeof(n_scales));
   put(&tol, sizeof(tol));
   put(&precision, sizeof(precision));
+  // plans made under other planner options are not reused
+  PlannerOptions popt;
+  uint64_t pgen = 0;
+  planner_options(popt, &pgen);
+  put(&pgen, sizeof(pgen));
   R->key.hash = fnv1a(R->key.bytes.data(), R->key.bytes.size());
   {
     std::lock_guard<std::mutex> lk(server->mu);
@@ -557,6 +565,7 @@ int phiks_server_submit(phiks_server_t server, int64_t op_id, double tau, int p,
     return PHIKS_EWORKSPACE;
   }
   r->ticket = server->next_ticket.fetch_add(1);
+  r->timeout = timeout_s;
   r->ctx = R.get();
   if (!server->engine->submit(r.get())) return PHIKS_EINVAL;
   *ticket = r->ticket;
@@ -583,6 +592,7 @@ int phiks_server_stats(phiks_server_t server, phiks_server_stats_t* out) {
   std::lock_guard<std::mutex> lk(server->mu);
   *out = server->st;
   out->ticks = es.ticks;
+  out->timed_out = es.timed_out;
   out->cache_bytes = (int64_t)server->cache_bytes;
   out->cached_plans = (int64_t)server->cache.size();
   return PHIKS_OK;

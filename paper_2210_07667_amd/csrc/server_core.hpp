@@ -20,6 +20,13 @@
 // independent (their own streams in the library), so the steps of small requests do not
 // wait behind the steps of large ones.
 //
+// Deadlines.  A request may carry a timeout (Request::timeout, seconds from submission;
+// 0 = none).  Still queued when it passes, the request completes with kTimedOut
+// without being prepared or run (the worker wakes for the earliest queued deadline).
+// Running when it passes, it is issued no further step: it leaves the running set at the
+// next tick boundary and completes with kTimedOut once every tick holding one of its
+// steps has completed (its slot is in use until then).  Its output is then partial.
+//
 // Executor interface (called without the engine's lock held):
 //   int  prepare(Request& r);            plan + steps; sets r.nsteps >= 1; status
 //   int  issue(int lane, const std::vector<Request*>& reqs, const std::vector<int>& step,
@@ -43,6 +50,9 @@
 #include <vector>
 
 namespace phiks_serve {
+
+// Status of a request whose deadline passed (the library's PHIKS_ETIMEDOUT).
+constexpr int kTimedOut = -7;
 
 inline double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
@@ -130,12 +140,15 @@ struct Request {
   int nsteps = 0, next = 0;
   int status = 0;
   bool done = false;
+  double timeout = 0.0;    // seconds from submission to the deadline; 0: none
+  double deadline = 0.0;   // set by submit: t_submit + timeout (0: none)
   double t_submit = 0.0, t_admit = 0.0, t_done = 0.0;
   void* ctx = nullptr;     // the executor's state of this request
 };
 
 struct EngineStats {
   int64_t submitted = 0, admitted = 0, completed = 0, ticks = 0;
+  int64_t timed_out = 0;   // completed with kTimedOut (queued or running)
 };
 
 template <class Exec>
@@ -162,6 +175,7 @@ class Engine {
     std::lock_guard<std::mutex> lk(mu_);
     if (stopping_ || r->lane < 0 || r->lane >= L_) return false;
     r->t_submit = now_s();
+    r->deadline = r->timeout > 0.0 ? r->t_submit + r->timeout : 0.0;
     reqs_[r->ticket] = r;
     lanes_[r->lane].pending.push_back(r);
     ++stats_.submitted;
@@ -222,6 +236,7 @@ class Engine {
     void* token = nullptr;
     int status = 0;                    // nonzero: the tick failed when issued
     std::vector<Request*> finishing;   // requests whose last step is in this tick
+    std::vector<Request*> expired;     // running requests stopped by their deadline
   };
   struct Lane {
     std::deque<Request*> pending;
@@ -233,23 +248,38 @@ class Engine {
     std::thread worker, completer;
   };
 
-  // Completes r under the lock: releases its slot, records the time and status.
-  void complete_locked(Request* r, int status, double t) {
-    arena_.release(r->ws_off, r->ws_doubles);
+  // Completes r under the lock: releases its slot (if admitted), records the time and
+  // status.
+  void complete_locked(Request* r, int status, double t, bool admitted = true) {
+    if (admitted) arena_.release(r->ws_off, r->ws_doubles);
     r->status = status;
     r->t_done = t;
     r->done = true;
     ++stats_.completed;
+    if (status == kTimedOut) ++stats_.timed_out;
   }
+
+  static bool expired_at(const Request* r, double now) { return r->deadline > 0.0 && now >= r->deadline; }
 
   void worker(int l) {
     Lane& ln = lanes_[l];
     std::vector<Request*> active;   // this worker's running requests, in admission order
     for (;;) {
-      std::vector<Request*> fresh;
+      std::vector<Request*> fresh, stale;   // admitted now; queued past their deadline
       {
         std::unique_lock<std::mutex> lk(mu_);
         for (;;) {
+          const double now = now_s();
+          double wake = 0.0;   // earliest deadline still queued
+          for (auto it = ln.pending.begin(); it != ln.pending.end();) {
+            if (expired_at(*it, now)) {
+              stale.push_back(*it);
+              it = ln.pending.erase(it);
+            } else {
+              if ((*it)->deadline > 0.0 && (wake == 0.0 || (*it)->deadline < wake)) wake = (*it)->deadline;
+              ++it;
+            }
+          }
           while (!ln.pending.empty() && (int)(active.size() + fresh.size()) < max_active_) {
             Request* r = ln.pending.front();
             size_t off = 0;
@@ -260,14 +290,33 @@ class Engine {
             fresh.push_back(r);
             ++stats_.admitted;
           }
+          if (!stale.empty()) break;
           if ((!active.empty() || !fresh.empty()) && ln.queued_ticks < kif_) break;
           if (stopping_ && ln.pending.empty() && active.empty() && fresh.empty()) {
             ln.worker_done = true;
             ln.cv_comp.notify_all();
             return;
           }
-          ln.cv.wait(lk);
+          if (wake > 0.0) {
+            // Sleep until the earliest queued deadline, at most 10 ms at a time.  The wait
+            // is on the system clock (pthread_cond_timedwait, which the thread sanitizer
+            // follows; a steady-clock wait_for maps to pthread_cond_clockwait, which it does
+            // not); the deadlines themselves are compared on the steady clock above, so a
+            // step of the system clock delays an expiry by at most the 10 ms cap.
+            const double dt = std::min(0.01, std::max(0.0, wake - now_s())) + 1e-6;
+            ln.cv.wait_until(lk, std::chrono::system_clock::now() +
+                                     std::chrono::duration_cast<std::chrono::system_clock::duration>(
+                                         std::chrono::duration<double>(dt)));
+          } else {
+            ln.cv.wait(lk);
+          }
         }
+      }
+      for (Request* r : stale) {   // never admitted: no slot, nothing issued
+        ex_->finish(*r);
+        std::lock_guard<std::mutex> lk(mu_);
+        complete_locked(r, kTimedOut, now_s(), false);
+        cv_done_.notify_all();
       }
       for (Request* r : fresh) {
         const int rc = ex_->prepare(*r);
@@ -282,10 +331,19 @@ class Engine {
         }
       }
       if (active.empty()) continue;
-      std::vector<int> step(active.size());
-      for (size_t i = 0; i < active.size(); ++i) step[i] = active[i]->next++;
       Tick t;
-      t.status = ex_->issue(l, active, step, &t.token);
+      {
+        // running requests past their deadline get no further step
+        const double now = now_s();
+        std::vector<Request*> live;
+        for (Request* r : active) (expired_at(r, now) ? t.expired : live).push_back(r);
+        active.swap(live);
+      }
+      if (!active.empty()) {
+        std::vector<int> step(active.size());
+        for (size_t i = 0; i < active.size(); ++i) step[i] = active[i]->next++;
+        t.status = ex_->issue(l, active, step, &t.token);
+      }
       std::vector<Request*> still;
       for (Request* r : active) {
         if (t.status != 0 || r->next >= r->nsteps) t.finishing.push_back(r);
@@ -293,7 +351,7 @@ class Engine {
       }
       active.swap(still);
       std::lock_guard<std::mutex> lk(mu_);
-      ++stats_.ticks;
+      if (t.token || t.status != 0) ++stats_.ticks;   // a tick of expiries only issues nothing
       ++ln.queued_ticks;
       ln.inflight.push_back(std::move(t));
       ln.cv_comp.notify_all();
@@ -316,10 +374,13 @@ class Engine {
         const int ws = ex_->wait(l, t.token);
         if (status == 0) status = ws;
       }
+      // ticks complete in order, so every earlier step of an expired request is done
       const double now = now_s();
       for (Request* r : t.finishing) ex_->finish(*r);
+      for (Request* r : t.expired) ex_->finish(*r);
       std::lock_guard<std::mutex> lk(mu_);
       for (Request* r : t.finishing) complete_locked(r, status, now);
+      for (Request* r : t.expired) complete_locked(r, kTimedOut, now);
       --ln.queued_ticks;
       cv_done_.notify_all();
       for (Lane& o : lanes_) o.cv.notify_all();   // slots released, a tick fewer queued

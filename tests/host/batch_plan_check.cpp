@@ -82,6 +82,27 @@ int main(int argc, char** argv) {
     CHECK(phiks_plan_params_complex(2, nn, A, 1e-3, 1e-3, 4, 2, 1e-12, PHIKS_SAME_VECTOR, nullptr,
                                     &a, &b, &c) == PHIKS_OK);
   }
+  // planner options: norm-centred rectangles and a narrower q range on the first problems,
+  // then the defaults back (the rest of the run plans with them)
+  {
+    phiks_planner_options_t prev{}, opt{5, 9, 40, PHIKS_RECT_NORM_CENTERED}, bad{2, 12, 64, 0};
+    CHECK(phiks_planner_options(&opt, &prev) == PHIKS_OK);
+    CHECK(prev.q_min == 3 && prev.q_max == 12 && prev.s_max == 64 && prev.rect == PHIKS_RECT_BENDIXSON);
+    CHECK(phiks_planner_options(&bad, nullptr) == PHIKS_EINVAL);
+    for (int i = 0; i < (count < 64 ? count : 64); ++i) {
+      std::vector<const double*> A(d[i]);
+      for (int mu = 0; mu < d[i]; ++mu) A[mu] = mats[(int)n[i][mu]].data();
+      int a = 0, b = 0, c = 0;
+      const int rc = phiks_plan_params(d[i], n[i].data(), A.data(), tau[i], 3, 1,
+                                       std::ldexp(1.0, -53), PHIKS_SAME_VECTOR, nullptr, &a, &b, &c);
+      CHECK(rc == PHIKS_OK || rc == PHIKS_ENOPLAN);
+      if (rc == PHIKS_OK) CHECK(b >= 5 && b <= 9 && a <= 40);
+      double xi[4];
+      CHECK(phiks_range_rectangle(n[i][0], A[0], PHIKS_RECT_NORM_CENTERED, xi) == PHIKS_OK);
+      CHECK(xi[0] <= xi[1] && xi[2] <= xi[3]);
+    }
+    CHECK(phiks_planner_options(&prev, nullptr) == PHIKS_OK);
+  }
   // the batched schedule of every problem, and of a few subsets and settings
   std::vector<const int64_t*> np(count);
   for (int i = 0; i < count; ++i) np[i] = n[i].data();

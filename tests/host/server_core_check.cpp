@@ -9,7 +9,11 @@
 //   * a request is completed only after every tick holding one of its steps completed;
 //   * admission within a lane follows submission order;
 //   * every request completes once, with the executor's status (injected failures of
-//     prepare and of issue included); the arena is whole again at the end.
+//     prepare and of issue included); the arena is whole again at the end;
+//   * deadlines: a request queued past its deadline completes with kTimedOut without
+//     being prepared; one running past it is issued no further step and completes with
+//     kTimedOut only after its issued steps completed; requests without a deadline are
+//     unaffected.
 // Exit status 0 when every check holds.
 #include <atomic>
 #include <condition_variable>
@@ -26,6 +30,7 @@
 #include "server_core.hpp"
 
 using phiks_serve::Engine;
+using phiks_serve::kTimedOut;
 using phiks_serve::Request;
 
 static std::atomic<int> g_fail{0};
@@ -103,7 +108,7 @@ struct FakeExec {
       CHECK(r.ws_off + r.ws_doubles <= a0 || a1 <= r.ws_off);
     }
     running[r.ticket] = {r.ws_off, r.ws_doubles};
-    if (s.fail_prepare) return -7;
+    if (s.fail_prepare) return -8;
     r.nsteps = s.nsteps;
     return 0;
   }
@@ -154,7 +159,7 @@ struct FakeExec {
 };
 
 static int run(int lanes, int max_active, size_t arena, int fail_every, int nreq, int threads,
-               unsigned seed) {
+               unsigned seed, bool deadlines = false) {
   FakeExec ex(lanes, fail_every);
   std::vector<Request*> all(nreq);
   std::vector<Spec*> spec(nreq);
@@ -167,6 +172,7 @@ static int run(int lanes, int max_active, size_t arena, int fail_every, int nreq
     all[i]->ws_doubles = phiks_serve::Arena::round(1 + rng() % (arena / 3));
     spec[i]->nsteps = 1 + (int)(rng() % 12);
     spec[i]->fail_prepare = (rng() % 29) == 0;
+    if (deadlines && rng() % 4 == 0) all[i]->timeout = 1e-6 * (50 + rng() % 3000);
     all[i]->ctx = spec[i];
   }
   {
@@ -197,9 +203,16 @@ static int run(int lanes, int max_active, size_t arena, int fail_every, int nreq
           CHECK(r && r->done);
           if (r) {
             const Spec& s = *spec[i];
-            if (s.fail_prepare) CHECK(r->status == -7 && s.issued.empty());
-            else if (r->status == 0) CHECK((int)s.issued.size() == s.nsteps);
-            else CHECK(r->status == -9);
+            if (r->status == kTimedOut) {
+              CHECK(r->timeout > 0.0 && r->t_done >= r->deadline);
+              CHECK((int)s.issued.size() < s.nsteps);
+            } else if (s.fail_prepare) {
+              CHECK(r->status == -8 && s.issued.empty());
+            } else if (r->status == 0) {
+              CHECK((int)s.issued.size() == s.nsteps);
+            } else {
+              CHECK(r->status == -9);
+            }
             CHECK(r->t_done >= r->t_submit);
           }
         }
@@ -208,13 +221,28 @@ static int run(int lanes, int max_active, size_t arena, int fail_every, int nreq
     for (auto& t : subs) t.join();
     CHECK(eng.wait(1) == nullptr);   // every ticket already claimed
     const auto st = eng.stats();
-    CHECK(st.submitted == nreq && st.completed == nreq && st.admitted == nreq);
+    int64_t n_admitted = 0, n_timed_out = 0;
+    for (int l = 0; l < lanes; ++l) n_admitted += (int64_t)ex.admitted[l].size();
+    for (int i = 0; i < nreq; ++i) n_timed_out += all[i]->status == kTimedOut;
+    CHECK(st.submitted == nreq && st.completed == nreq && st.admitted == n_admitted);
+    CHECK(st.timed_out == n_timed_out);
+    if (!deadlines) CHECK(n_admitted == nreq && n_timed_out == 0);
     eng.shutdown();
     CHECK(eng.arena_consistent());
     CHECK(eng.take_all().empty());
-    for (int l = 0; l < lanes; ++l) CHECK(ex.admitted[l] == submit_order[l]);
-    std::printf("lanes %d max_active %d arena %zu fail_every %d: %d requests, %lld ticks\n", lanes,
-                max_active, arena, fail_every, nreq, (long long)st.ticks);
+    // admission follows submission order (requests expired in the queue are skipped)
+    for (int l = 0; l < lanes; ++l) {
+      std::vector<int64_t> expect;
+      std::set<int64_t> adm(ex.admitted[l].begin(), ex.admitted[l].end());
+      for (int64_t t : submit_order[l])
+        if (adm.count(t)) expect.push_back(t);
+      CHECK(ex.admitted[l] == expect);
+      for (int64_t t : submit_order[l])
+        if (!adm.count(t)) CHECK(all[t - 1]->status == kTimedOut && spec[t - 1]->issued.empty());
+    }
+    std::printf("lanes %d max_active %d arena %zu fail_every %d%s: %d requests, %lld ticks, "
+                "%lld timed out\n", lanes, max_active, arena, fail_every,
+                deadlines ? " deadlines" : "", nreq, (long long)st.ticks, (long long)n_timed_out);
   }
   for (int i = 0; i < nreq; ++i) {
     CHECK(spec[i]->finished);
@@ -222,6 +250,48 @@ static int run(int lanes, int max_active, size_t arena, int fail_every, int nreq
     delete all[i];
   }
   return g_fail.load();
+}
+
+// Deterministic deadlines: one slot, so B waits behind A and expires in the queue; C
+// runs far longer than its timeout and is stopped at a step boundary; D (no deadline)
+// and A complete normally.
+static void deadline_scenarios() {
+  FakeExec ex(1, 0);
+  Request r[4];
+  Spec sp[4];
+  const int steps[4] = {40, 3, 1000, 5};
+  for (int i = 0; i < 4; ++i) {
+    r[i].ticket = 100 + i;
+    r[i].lane = 0;
+    r[i].ws_doubles = 64;
+    sp[i].nsteps = steps[i];
+    r[i].ctx = &sp[i];
+  }
+  r[1].timeout = 1e-3;
+  r[2].timeout = 2e-3;
+  {
+    Engine<FakeExec> eng(&ex, 64, 1, 4, 2);
+    CHECK(eng.submit(&r[0]));
+    CHECK(eng.submit(&r[1]));
+    Request* b = eng.wait(101);
+    CHECK(b == &r[1] && b->status == kTimedOut && sp[1].issued.empty());
+    CHECK(b->t_done >= b->deadline);
+    Request* a = eng.wait(100);
+    CHECK(a == &r[0] && a->status == 0 && (int)sp[0].issued.size() == 40);
+    CHECK(eng.submit(&r[2]));
+    CHECK(eng.submit(&r[3]));
+    Request* c = eng.wait(102);
+    CHECK(c == &r[2] && c->status == kTimedOut);
+    CHECK(!sp[2].issued.empty() && (int)sp[2].issued.size() < 1000 && sp[2].finished);
+    Request* d = eng.wait(103);
+    CHECK(d == &r[3] && d->status == 0 && (int)sp[3].issued.size() == 5);
+    const auto st = eng.stats();
+    CHECK(st.timed_out == 2 && st.completed == 4 && st.admitted == 3);
+    eng.shutdown();
+    CHECK(eng.arena_consistent());
+    std::printf("deadlines: B expired in the queue, C stopped after %zu of 1000 steps\n",
+                sp[2].issued.size());
+  }
 }
 
 int main() {
@@ -260,6 +330,9 @@ int main() {
   run(3, 3, 400, 0, 300, 4, 2);
   run(2, 8, 1000, 37, 300, 3, 3);
   run(4, 2, 150, 11, 200, 4, 4);
+  run(2, 3, 300, 0, 300, 4, 5, true);
+  run(3, 8, 1000, 23, 300, 3, 6, true);
+  deadline_scenarios();
   if (g_fail.load()) {
     std::fprintf(stderr, "server core check FAILED\n");
     return 1;

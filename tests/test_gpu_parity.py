@@ -124,6 +124,28 @@ def test_apply_fd2_32x32_workload():
         assert relerr(got[0, ell], ref[0, ell]) < TOL
 
 
+def test_apply_under_other_planner_options():
+    """Planner options (norm-centred rectangle, q in 5..8): the library plans as the
+    oracle planner does under the same options, and the action matches the oracle at
+    that plan."""
+    n, tau, p = [24, 20, 16], 1e-3, 3
+    A = ops("cheb", n)
+    v = workloads.randn_vec(n, 23)
+    tol = 2.0 ** -53 * float(np.linalg.norm(v))
+    old = ph.planner_options(5, 8, 64, ph.PHIKS_RECT_NORM_CENTERED)
+    try:
+        print(f"[apply options] n={n} tau={tau} p={p}", flush=True)
+        got, info = run_apply(A, tau, v, p, 1, tol)
+    finally:
+        ph.planner_options(*old)
+    xi = bound.kron_sum_rectangle([tau * a for a in A], "norm_centered")
+    s, q, _ = bound.plan(xi, p, 1, tol, "same_vector", q_min=5, q_max=8)
+    assert (info["s"], info["q"]) == (s, q)
+    ref = ophiks.phi_same_vector(A, tau, v, p, 1, s, q)
+    for ell in range(p + 1):
+        assert relerr(got[0, ell], ref[0, ell]) < TOL, (ell, info)
+
+
 def test_apply_exponential_only():
     A = ops("adr", [20, 9, 7])
     v = workloads.randn_vec([20, 9, 7], 22)

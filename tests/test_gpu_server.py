@@ -224,3 +224,46 @@ def test_lanes_overlap_small_requests_pass_large_ones():
         assert np.array_equal(o.to_numpy(), reference(small, v))
     assert np.array_equal(obuf.to_numpy(), reference(big, vb))
     server.close()
+
+
+def test_request_deadlines():
+    """Deadlines (one running request at a time): B, queued behind a long request A
+    with a 0.1 ms timeout, completes with PHIKS_ETIMEDOUT without running (its output
+    untouched); C, whose timeout (1 ms) is far below its run time, is stopped at a step
+    boundary with PHIKS_ETIMEDOUT; A and a later request D without a deadline complete
+    bitwise equal to their single calls."""
+    lng = workloads.Session("adr_1024", [1024, 1024],
+                            [workloads.adr_1d(1024, 0.5, b, -1.0) for b in (1.0, 0.5)], 4e-3, 4)
+    server = ph.Server(hbm_budget=8 * GiB, workspace_bytes=2 * GiB, max_active=1, lanes=1)
+    rng = np.random.default_rng(9)
+    op = server.register(lng.A)
+    v0 = ph.DeviceArray.from_numpy(rng.standard_normal(lng.N))
+    o0 = ph.DeviceArray((lng.p + 1) * lng.N)
+    server.wait(server.submit(op, lng.tau, lng.p, 1, TOL, v0.ptr, o0.ptr))   # plan cached
+    vals = [rng.standard_normal(lng.N) for _ in range(4)]
+    dv = [ph.DeviceArray.from_numpy(x) for x in vals]
+    outs = [ph.DeviceArray.from_numpy(np.full((lng.p + 1) * lng.N, np.nan)) for _ in range(4)]
+    ph.synchronize()
+    print("[server deadlines] A + B queued behind it", flush=True)
+    ta = server.submit(op, lng.tau, lng.p, 1, TOL, dv[0].ptr, outs[0].ptr)
+    tb = server.submit(op, lng.tau, lng.p, 1, TOL, dv[1].ptr, outs[1].ptr, timeout=1e-4)
+    with pytest.raises(ph.PhiksError) as e:
+        server.wait(tb)
+    assert e.value.status == ph.PHIKS_ETIMEDOUT
+    server.wait(ta)
+    assert np.isnan(outs[1].to_numpy()).all()          # B never ran
+    print("[server deadlines] C stopped while running", flush=True)
+    tc = server.submit(op, lng.tau, lng.p, 1, TOL, dv[2].ptr, outs[2].ptr, timeout=1e-3)
+    with pytest.raises(ph.PhiksError) as e:
+        server.wait(tc)
+    assert e.value.status == ph.PHIKS_ETIMEDOUT
+    print("[server deadlines] D", flush=True)
+    td = server.submit(op, lng.tau, lng.p, 1, TOL, dv[3].ptr, outs[3].ptr, timeout=60.0)
+    server.wait(td)
+    for k in (0, 3):
+        assert np.array_equal(outs[k].to_numpy(), reference(lng, vals[k]))
+    assert server.stats()["timed_out"] == 2
+    with pytest.raises(ph.PhiksError) as e:
+        server.submit(op, lng.tau, lng.p, 1, TOL, dv[3].ptr, outs[3].ptr, timeout=-1.0)
+    assert e.value.status == ph.PHIKS_EINVAL
+    server.close()

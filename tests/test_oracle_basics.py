@@ -213,3 +213,50 @@ def test_rectangle_contains_numerical_range():
         assert a - 1e-12 <= r.real <= b + 1e-12 and c - 1e-12 <= r.imag <= d + 1e-12
     ev = np.linalg.eigvals(B)
     assert np.all(ev.real >= a - 1e-12) and np.all(ev.real <= b + 1e-12)
+
+
+def test_norm_centered_rectangle_closed_forms():
+    """Centre tr(B)/n, half-widths ||H - Re(sigma) I||_2 and ||S - Im(sigma) I||_2
+    (S = (B - B^H)/(2i)), worked by hand:
+    * diag(1, 2, 6): sigma = 3, H - 3I = diag(-2, -1, 3) -> [0, 6] x i[0, 0];
+    * diag(0, 0, 3i): sigma = i, H = 0, S = diag(0, 0, 3), S - I = diag(-1, -1, 2)
+      -> [0, 0] x i[-1, 3] (the Bendixson box is [0, 0] x i[0, 3]);
+    * [[0, 1], [-1, 0]]: sigma = 0, H = 0, S = [[0, -i], [i, 0]] with eigenvalues +-1
+      -> [0, 0] x i[-1, 1]."""
+    cases = [
+        (np.diag([1.0, 2.0, 6.0]), (0.0, 6.0, 0.0, 0.0)),
+        (np.diag([0.0, 0.0, 3.0j]), (0.0, 0.0, -1.0, 3.0)),
+        (np.array([[0.0, 1.0], [-1.0, 0.0]]), (0.0, 0.0, -1.0, 1.0)),
+    ]
+    for B, ref in cases:
+        assert np.allclose(bound.rectangle(B, "norm_centered"), ref, atol=1e-14), B
+    assert np.allclose(bound.rectangle(np.diag([0.0, 0.0, 3.0j])), (0.0, 0.0, 0.0, 3.0),
+                       atol=1e-14)
+
+
+def test_norm_centered_rectangle_contains_bendixson_and_shifts():
+    """The norm-centred box contains the Bendixson box (so W(B)), is centred at the mean
+    eigenvalue tr(B)/n, and moves with B + c I by c."""
+    rng = np.random.default_rng(11)
+    for trial in range(6):
+        n = 3 + trial
+        B = rng.standard_normal((n, n)) + (0.5j * rng.standard_normal((n, n)) if trial % 2 else 0)
+        a, b, c, d = bound.rectangle(B)
+        A_, B_, C_, D_ = bound.rectangle(B, "norm_centered")
+        assert A_ <= a + 1e-12 and B_ >= b - 1e-12 and C_ <= c + 1e-12 and D_ >= d - 1e-12
+        mean = np.linalg.eigvals(B).mean()
+        assert abs((A_ + B_) / 2 - mean.real) < 1e-12 and abs((C_ + D_) / 2 - mean.imag) < 1e-12
+        for _ in range(50):
+            x = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+            r = (x.conj() @ B @ x) / (x.conj() @ x)
+            assert A_ - 1e-12 <= r.real <= B_ + 1e-12 and C_ - 1e-12 <= r.imag <= D_ + 1e-12
+        shift = 0.7 - 1.3j
+        moved = bound.rectangle(B + shift * np.eye(n), "norm_centered")
+        expect = (A_ + shift.real, B_ + shift.real, C_ + shift.imag, D_ + shift.imag)
+        assert np.allclose(moved, expect, atol=1e-12)
+    try:
+        bound.rectangle(np.eye(2), "ellipse")
+    except ValueError:
+        pass
+    else:
+        raise AssertionError("unknown kinds are refused")
