@@ -72,6 +72,9 @@ int launch_cfg32(const GemmArgs& g, const Epi& epi, hipStream_t st) {
   return launch_grid<BM, BN>(&gemm_f32_kernel<BM, BN, WM, WN, KC, VEC, TA, TC, Epi>, g, epi, st);
 }
 
+#ifndef PHIKS_F32_SKINNY64
+#define PHIKS_F32_SKINNY64 1  // 1: skinny FP32 products on 64 x 64 direct-to-LDS tiles
+#endif
 #ifndef PHIKS_F32_BIG_TILE
 #define PHIKS_F32_BIG_TILE 1  // 1: 128 x 128 tiles (4 waves of 64 x 64) where they fill the GPU
 #endif
@@ -80,6 +83,10 @@ int launch_cfg32(const GemmArgs& g, const Epi& epi, hipStream_t st) {
 // do, else 64 x 64 when both sides reach 48 (the direct-to-LDS kernel needs 64-wide tiles;
 // a product too small to fill the GPU keeps that tile rather than splitting into 32 x 32
 // ones, so grouped launches of many small products -- batches -- run it too), else 32 x 32.
+// Skinny products (one side 16..47, the other >= 256: the small modes of mixed-size
+// problems) take 64 x 64 tiles too when the direct-to-LDS kernel can run them: they move
+// 2-3 flop per byte, so the tile's idle rows or columns cost no time, and their squaring
+// steps get the LDS-streamed epilogue.
 // launch_gemm32 runs exactly this; grouped launches of FP32 batches take it per item, so
 // each item runs the tiles of its single call.  a_double: A is the FP64 input (mode 1);
 // dl_epi_ok: the epilogue passes lincomb_ok.
@@ -102,8 +109,14 @@ Cfg32 cfg32(const GemmArgs& g, bool kc, bool a_double, bool dl_epi_ok) {
         break;
     }
   }
-  c.dl = PHIKS_DL == 1 && c.vec && (PHIKS_F32_DL_A64 == 1 || !a_double) && c.bm >= 64 &&
-         c.bn >= 64 && g.K % 16 == 0 && g.pA == nullptr && dl_epi_ok;
+  auto dl_ok32 = [&](int bm, int bn) {
+    return PHIKS_DL == 1 && c.vec && (PHIKS_F32_DL_A64 == 1 || !a_double) && bm >= 64 &&
+           bn >= 64 && g.K % 16 == 0 && g.pA == nullptr && dl_epi_ok;
+  };
+  if (PHIKS_F32_SKINNY64 == 1 && c.bm == 32 && std::min(g.M, g.N) >= 16 &&
+      std::max(g.M, g.N) >= 256 && dl_ok32(64, 64))
+    c.bm = c.bn = 64;
+  c.dl = dl_ok32(c.bm, c.bn);
   return c;
 }
 

@@ -1,6 +1,6 @@
 """Time phiks_batch_apply on the batched workload (512 uneven problems).
 
-    python run_batch.py --count 512 --reps 3
+    python run_batch.py --count 512 --reps 3 [--precision fp32]
 
 Plans the batch once (d in {2, 3}, n_mu in 16..128, Chebyshev second-derivative
 operators, tau log-uniform in [1e-4, 1e-2], phi_0..phi_3 of one vector, tolerance
@@ -26,6 +26,7 @@ def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--count", type=int, default=512)
     ap.add_argument("--reps", type=int, default=3)
+    ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
     args = ap.parse_args()
 
     import paper_2210_07667_amd as ph
@@ -33,8 +34,9 @@ def main():
 
     problems = workloads.config_batch(count=args.count)
     norms = [float(np.linalg.norm(b.v)) for b in problems]
+    prec = ph.PHIKS_FP32 if args.precision == "fp32" else ph.PHIKS_FP64
     batch = ph.phiks_batch_plan([b.A for b in problems], [b.tau for b in problems], 3, 1,
-                                2.0 ** -53, vnorms=norms)
+                                2.0 ** -53, vnorms=norms, precision=prec)
     dv = [ph.DeviceArray.from_numpy(b.v) for b in problems]
     outs = [ph.DeviceArray(4 * b.N) for b in problems]
     ws = ph.DeviceArray(batch.workspace_size() // 8 + 1)
@@ -56,7 +58,8 @@ def main():
     ph.synchronize()
     ph.phiks_kernel_timing(False)
     k_ms, k_launch, k_flops = ph.phiks_kernel_timing_read()
-    print(json.dumps({"problems": len(problems), "total_dofs": sum(b.N for b in problems),
+    print(json.dumps({"problems": len(problems), "precision": args.precision,
+                      "total_dofs": sum(b.N for b in problems),
                       "apply_ms": ms, "mu_mode_ms_per_call": k_ms,
                       "mu_mode_launches_per_call": k_launch,
                       "mu_mode_tflops": k_flops / (k_ms * 1e-3) / 1e12 if k_ms > 0 else 0.0}),
