@@ -16,9 +16,12 @@
 //    k*BN/4 + (cq ^ 4 ((k / 4) mod 4)); fragment reads are 4 bytes, the four rows of one
 //    read land on four different 64-byte bank groups.
 // MFMA v_mfma_f32_16x16x4_f32: A[m0 + (l & 15)][k(l >> 4)], B[k(l >> 4)][n0 + (l & 15)],
-// c[r] = C[m0 + 4 (l >> 4) + r][n0 + (l & 15)].  K must be a multiple of 16, the leading
+// c[r] = C[m0 + 4 (l >> 4) + r][n0 + (l & 15)].  K must be a multiple of 4, the leading
 // dimensions and strides multiples of 4 floats, N too for an n-contiguous B (the
-// launcher checks); ragged M/N fetch clamped in-range rows or columns.
+// launcher checks); ragged M/N fetch clamped in-range rows or columns.  A K that is not a
+// multiple of 16 ends in a partial chunk: its slots past K fetch an in-range address of the
+// same operand, and the lane groups whose four k lie past K zero both fragments, so those
+// k add exact zeros (the chunks before it run as for any K).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -201,16 +204,39 @@ __device__ __forceinline__ void gemm_f32_dl_tile(const GemmArgs& g, const Epi& e
   }
   const int64_t bstep = B_KCONTIG ? BK : (int64_t)BK * g.ldb;
 
+  const int nchunks = (g.K + BK - 1) / BK;
+  const int ktail = g.K % BK;   // k in the last chunk when K is not a multiple of 16 (4-aligned)
   auto issue = [&](int c) {
     float* st = lds + (c & 1) * STAGE;
+    const bool tail = ktail != 0 && c == nchunks - 1;   // wave-uniform
 #pragma unroll
-    for (int i = 0; i < LA; ++i)
-      dma16(reinterpret_cast<const PHIKS_GLOBAL double*>(asrc[i] + (int64_t)c * BK),
+    for (int i = 0; i < LA; ++i) {
+      const PHIKS_GLOBAL TA* src = asrc[i] + (int64_t)c * BK;
+      if (tail) {
+        // k of the slot within the chunk; past K: the row's first slot (k = 0, in range)
+        const int s = i * 256 + tid;
+        const int r = s / AQ, q = (s % AQ) ^ (AD ? (r >> 1) & 7 : swz_kq(r));
+        if ((16 / (int)sizeof(TA)) * q >= ktail) src = asrc[i] - (16 / (int)sizeof(TA)) * q;
+      }
+      dma16(reinterpret_cast<const PHIKS_GLOBAL double*>(src),
             reinterpret_cast<double*>(st + 4 * (i * 256 + wave * 64)));
+    }
 #pragma unroll
-    for (int i = 0; i < LB; ++i)
-      dma16(reinterpret_cast<const PHIKS_GLOBAL double*>(bsrc[i] + (int64_t)c * bstep),
+    for (int i = 0; i < LB; ++i) {
+      const PHIKS_GLOBAL float* src = bsrc[i] + (int64_t)c * bstep;
+      if (tail) {
+        const int s = i * 256 + tid;
+        if constexpr (B_KCONTIG) {
+          const int kq = (s % KQ) ^ swz_kq(s / KQ);
+          if (4 * kq >= ktail) src = bsrc[i] - 4 * kq;
+        } else {
+          const int k = s / (BN / 4);   // row of the chunk; past K: the last row of K
+          if (k >= ktail) src += (int64_t)(ktail - 1 - k) * g.ldb;
+        }
+      }
+      dma16(reinterpret_cast<const PHIKS_GLOBAL double*>(src),
             reinterpret_cast<double*>(st + 4 * A_SLOTS + 4 * (i * 256 + wave * 64)));
+    }
   };
 
   flt4 acc[FM][FN];
@@ -219,7 +245,6 @@ __device__ __forceinline__ void gemm_f32_dl_tile(const GemmArgs& g, const Epi& e
 #pragma unroll
     for (int j = 0; j < FN; ++j) acc[i][j] = flt4{0.f, 0.f, 0.f, 0.f};
 
-  const int nchunks = g.K / BK;
   issue(0);
   for (int c = 0; c < nchunks; ++c) {
     wait_vmcnt<0>();
@@ -254,6 +279,13 @@ __device__ __forceinline__ void gemm_f32_dl_tile(const GemmArgs& g, const Epi& e
           fb[jj][h] = bs[4 * (k * (BN / 4) + ((n >> 2) ^ swz_nq(k))) + (n & 3)];
         }
       }
+    }
+    if (ktail != 0 && c == nchunks - 1 && 4 * lk >= ktail) {
+      // this lane group's k (4 lk .. 4 lk + 3) lie past K
+#pragma unroll
+      for (int i = 0; i < FM; ++i) fa[i] = flt4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int jj = 0; jj < FN; ++jj) fb[jj] = flt4{0.f, 0.f, 0.f, 0.f};
     }
 #pragma unroll
     for (int h = 0; h < 4; ++h)

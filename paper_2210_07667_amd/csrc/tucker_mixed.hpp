@@ -64,9 +64,10 @@ template <int BM, int BN, int WM, int WN, bool KC, bool VEC, class TA, class TC,
 int launch_cfg32(const GemmArgs& g, const Epi& epi, hipStream_t st) {
   if constexpr (PHIKS_DL == 1 && VEC && (PHIKS_F32_DL_A64 == 1 || std::is_same<TA, float>::value) &&
                 BM >= 64 && BN >= 64) {
-    // direct-to-LDS loads (whole 16-k chunks; an FP64 A is converted at the fragment
-    // read); the squaring epilogue streams its pre-step tensors through LDS too
-    if (g.K % 16 == 0 && g.pA == nullptr && lincomb_ok(g, epi))
+    // direct-to-LDS loads (16-k chunks, the last one partial when K is not a multiple
+    // of 16; an FP64 A is converted at the fragment read); the squaring epilogue streams
+    // its pre-step tensors through LDS too
+    if (g.K % 4 == 0 && g.pA == nullptr && lincomb_ok(g, epi))
       return launch_grid<BM, BN>(&gemm_f32_dl_kernel<BM, BN, WM, WN, KC, TA, TC, Epi>, g, epi, st);
   }
   return launch_grid<BM, BN>(&gemm_f32_kernel<BM, BN, WM, WN, KC, VEC, TA, TC, Epi>, g, epi, st);
@@ -74,6 +75,9 @@ int launch_cfg32(const GemmArgs& g, const Epi& epi, hipStream_t st) {
 
 #ifndef PHIKS_F32_SKINNY64
 #define PHIKS_F32_SKINNY64 1  // 1: skinny FP32 products on 64 x 64 direct-to-LDS tiles
+#endif
+#ifndef PHIKS_F32_SKINNY_LONG
+#define PHIKS_F32_SKINNY_LONG 256  // the longer side from which a skinny product takes them
 #endif
 #ifndef PHIKS_F32_BIG_TILE
 #define PHIKS_F32_BIG_TILE 1  // 1: 128 x 128 tiles (4 waves of 64 x 64) where they fill the GPU
@@ -84,7 +88,8 @@ int launch_cfg32(const GemmArgs& g, const Epi& epi, hipStream_t st) {
 // a product too small to fill the GPU keeps that tile rather than splitting into 32 x 32
 // ones, so grouped launches of many small products -- batches -- run it too), else 32 x 32.
 // Skinny products (one side 16..47, the other >= 256: the small modes of mixed-size
-// problems) take 64 x 64 tiles too when the direct-to-LDS kernel can run them: they move
+// problems) take 64 x 64 tiles too when the direct-to-LDS kernel can run them (K a multiple
+// of 4, its last chunk partial when K is not a multiple of 16): they move
 // 2-3 flop per byte, so the tile's idle rows or columns cost no time, and their squaring
 // steps get the LDS-streamed epilogue.
 // launch_gemm32 runs exactly this; grouped launches of FP32 batches take it per item, so
@@ -111,10 +116,10 @@ Cfg32 cfg32(const GemmArgs& g, bool kc, bool a_double, bool dl_epi_ok) {
   }
   auto dl_ok32 = [&](int bm, int bn) {
     return PHIKS_DL == 1 && c.vec && (PHIKS_F32_DL_A64 == 1 || !a_double) && bm >= 64 &&
-           bn >= 64 && g.K % 16 == 0 && g.pA == nullptr && dl_epi_ok;
+           bn >= 64 && g.K % 4 == 0 && g.pA == nullptr && dl_epi_ok;
   };
   if (PHIKS_F32_SKINNY64 == 1 && c.bm == 32 && std::min(g.M, g.N) >= 16 &&
-      std::max(g.M, g.N) >= 256 && dl_ok32(64, 64))
+      std::max(g.M, g.N) >= PHIKS_F32_SKINNY_LONG && dl_ok32(64, 64))
     c.bm = c.bn = 64;
   c.dl = dl_ok32(c.bm, c.bn);
   return c;

@@ -57,7 +57,11 @@ APPLY_CASES = [([40, 33, 20], 1e-3, 4, 2), ([64, 64, 64], 1e-3, 4, 1), ([33, 17]
                ([520, 352], 1e-3, 4, 1), ([96, 72, 100], 1e-3, 3, 1),
                # squaring launches on the direct-to-LDS kernels with a ragged N (third mode:
                # N = 7200 = 112*64 + 32; the pre-step slices clamp their last columns)
-               ([100, 72, 128], 1e-3, 3, 1)]
+               ([100, 72, 128], 1e-3, 3, 1),
+               # K tails of 12 on the FP32 direct-to-LDS kernel (K = 60 with an FP64 A,
+               # K = 300 with an n-contiguous B) and a skinny squaring product on 64 x 64
+               # tiles (third mode: M = K = 28, N = 18000)
+               ([60, 300, 28], 1e-3, 3, 1)]
 
 
 @functools.lru_cache(maxsize=None)
