@@ -255,3 +255,26 @@ def test_adr_256_full_size_against_oracle():
         lhs = got[0, ell]
         rhs = tensor.kron_sum_apply(B, got[0, ell + 1]) + w.v / math.factorial(ell)
         assert relerr(lhs, rhs) < 1e-9, ell
+
+
+@pytest.mark.parametrize("n", [[2, 3, 2, 2, 2, 3, 2, 2], [6, 5, 4, 3, 4, 5, 3, 4]],
+                         ids=["d8_tiny", "d8_small"])
+def test_largest_d_and_p(n):
+    """d = PHIKS_MAX_D = 8 modes and p = PHIKS_MAX_P = 8, three scales, both tasks,
+    against the oracle at the library's plan."""
+    print(f"[max d,p] n={n}", flush=True)
+    betas = [1.0, -0.5, 0.25, 0.75, -1.0, 0.5, -0.25, 0.125]
+    A = [workloads.adr_1d(k, 0.5, betas[i], -1.0) for i, k in enumerate(n)]
+    tau, p, ns = 0.05, 8, 3
+    v = workloads.randn_vec(n, 13)
+    got, info = run_apply(A, tau, v, p, ns)
+    ref = ophiks.phi_same_vector(A, tau, v, p, ns, info["s"], info["q"])
+    for j in range(ns):
+        for ell in range(p + 1):
+            assert relerr(got[j, ell], ref[j, ell]) < TOL, (j, ell, info)
+    rng = np.random.default_rng(14)
+    vs = [rng.standard_normal(int(np.prod(n))) for _ in range(p + 1)]
+    got, info = run_combine(A, tau, vs, p, ns)
+    ref = ophiks.phi_lincomb(A, tau, vs, p, ns, info["s"], info["q"])
+    for j in range(ns):
+        assert relerr(got[j], ref[j]) < TOL, (j, info)

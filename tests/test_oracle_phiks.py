@@ -196,3 +196,25 @@ def test_planner_reproduces_table1():
             assert (s, q, T) == tuple(ref), (task, d, n)
         else:
             assert T == ref[2], (task, d, n)
+
+
+def test_largest_d_and_p_vs_augmented():
+    """The largest shapes the interface admits in d and p (d = 8 modes, p = 8, three
+    scales), both tasks, against the augmented-matrix exponential (N + p = 584)."""
+    n = [2, 3, 2, 2, 2, 3, 2, 2]
+    betas = [1.0, -0.5, 0.25, 0.75, -1.0, 0.5, -0.25, 0.125]
+    A = [workloads.adr_1d(k, 0.5, betas[i], -1.0) for i, k in enumerate(n)]
+    tau, p, shat = 0.05, 8, 3
+    v = workloads.randn_vec(n, 13)
+    s, q = _plan(A, tau, p, shat, "same_vector")
+    out = phiks.phi_same_vector(A, tau, v, p, shat, s, q)
+    for j in range(shat):
+        ref = brute.phi_actions_dense(A, tau, v, p, c=2.0 ** -j)
+        for ell in range(p + 1):
+            assert relerr(out[j, ell], ref[ell]) < 1e-12, (j, ell)
+    rng = np.random.default_rng(14)
+    vs = [rng.standard_normal(int(np.prod(n))) for _ in range(p + 1)]
+    s, q = _plan(A, tau, p, shat, "lincomb")
+    out = phiks.phi_lincomb(A, tau, vs, p, shat, s, q)
+    for j in range(shat):
+        assert relerr(out[j], brute.augmented(A, tau, vs, c=2.0 ** -j)) < 1e-12, j
