@@ -45,7 +45,7 @@ namespace phiks {
 #define PHIKS_DL_MIN_WAVES 4     // waves per SIMD the register budget must allow
 #endif
 #ifndef PHIKS_DL_MIN_WAVES_LC
-#define PHIKS_DL_MIN_WAVES_LC 3  // the same for the squaring epilogue (more live registers)
+#define PHIKS_DL_MIN_WAVES_LC 4  // the same for the squaring epilogue
 #endif
 
 template <int KP>
@@ -74,57 +74,53 @@ __device__ __forceinline__ void dma16(const PHIKS_GLOBAL double* src, double* ld
   asm volatile("global_load_lds_dwordx4 %0, off" : : "v"(src), "{m0}"(lds) : "memory");
 }
 
-// Squaring epilogue out = a_l acc + sum_{k <= l} c_lk Y_k with the pre-step tensors Y_k
-// streamed through LDS by the same 16-byte DMA as the operands, instead of register
-// loads whose latency the work-group would wait out round after round.  Slice i of Y_k
-// (round k * FM + i) holds fragment row i of every wave: WGM * 16 rows of BN columns,
-// rows (rho / 16) * WM + i * 16 + rho % 16 of the tile, stored as column pairs with
-// slot rho * BN/2 + (cp ^ 8 (rho & 1)) (rows rho and rho + 1 of a 32-lane read land on
-// different bank halves).  YB buffers, DMA YB - 1 rounds ahead.  Per element the
-// arithmetic is the register epilogue's (acc *= a_l, then one fma per k in k order).
-// Needs 16-byte column pairs: even ldc, N, output strides and tensor stride, aligned Y
+// The squaring epilogue (lincomb_wave_epilogue below) streams the pre-step tensors in
+// 16-byte column pairs: even ldc, N, output strides and tensor stride, aligned Y
 // (lincomb_dl_ok, checked by the launchers: launches that fail it take gemm_f64_kernel).
 inline bool lincomb_dl_ok(const GemmArgs& g, const double* Y, int64_t YN) {
   return ((g.ldc | (int64_t)g.N | g.sC0 | g.sC1 | YN) & 1) == 0 && ((uintptr_t)Y & 15) == 0 &&
          (g.pC == nullptr);
 }
 
-template <int BM, int BN, int WM, int WN, int YB, int FM, int FN>
-__device__ __forceinline__ void lincomb_lds_epilogue(dbl4 (&acc)[FM][FN], const GemmArgs& g,
-                                                     const EpiLinComb& epi, const TileOperands& t,
-                                                     double* lds, int m0, int n0, int wave, int tid) {
-  constexpr int WGM = BM / WM, WGN = BN / WN;
-  constexpr int ROWS = WGM * 16, CP = BN / 2;
-  constexpr int YSLICE = ROWS * BN;                     // doubles
-  constexpr int SLOTS = ROWS * CP, LY = SLOTS / 256;
-  static_assert(SLOTS % 256 == 0, "every thread fetches the same count");
-  static_assert(CP >= 16, "column-pair swizzle needs BN >= 32");
-  const int lane = tid & 63, lr = lane & 15, lk = lane >> 4;
-  const int wgm = wave / WGN, wn = (wave % WGN) * WN;
+// Squaring epilogue out = a_l acc + sum_{k <= l} c_lk Y_k with the pre-step tensors Y_k
+// streamed through LDS by the same 16-byte DMA as the operands, instead of register loads
+// whose latency each wave would wait out round after round.  Round r = k * FM + i brings
+// fragment row i of Y_k for this wave only (16 rows of WN columns, stored as column pairs,
+// slot row * WN/2 + (cp ^ (WN/4) (row & 1)) so the two row parities of a 32-lane read land
+// on different bank halves) into one of the wave's YB buffers, YB - 1 rounds ahead.  A wave
+// reads only what it fetched, so a round waits on the wave's own loads (vmcnt) and no
+// work-group barrier follows the first: the waves do not wait for each other round after
+// round, and the epilogue needs fewer registers than one with shared slices, so the
+// squaring kernels run at 4 waves per SIMD.  Per element the arithmetic is acc *= a_l, then
+// one fma per k in k order (every FP64 squaring kernel does exactly this).
+template <int WM, int WN, int YB, int FM, int FN>
+__device__ __forceinline__ void lincomb_wave_epilogue(dbl4 (&acc)[FM][FN], const GemmArgs& g,
+                                                      const EpiLinComb& epi, const TileOperands& t,
+                                                      double* lds, int mw, int nw, int wave, int lane) {
+  constexpr int CPW = WN / 2;                 // column pairs per row
+  constexpr int SLICE = 16 * WN;              // doubles per wave slice
+  constexpr int LW = 16 * CPW / 64;           // 16-byte loads per lane per round
+  static_assert(CPW >= 2 && (16 * CPW) % 64 == 0, "whole waves of slots");
+  const int lr = lane & 15, lk = lane >> 4;
   const int l = (int)t.z1;
   const int rounds = (l + 1) * FM;
-
-  // this thread's slots: slice-relative tile row and column (clamped in range)
-  int64_t off[LY];
-#pragma unroll
-  for (int q = 0; q < LY; ++q) {
-    const int s = q * 256 + tid;
-    const int rho = s / CP, cp = (s % CP) ^ ((rho & 1) << 3);
-    const int row = (rho / 16) * WM + rho % 16;         // + i * 16 per slice
-    off[q] = (int64_t)row * g.ldc + min(n0 + 2 * cp, g.N - 2);
-  }
+  double* wbuf = lds + wave * YB * SLICE;
   const PHIKS_GLOBAL double* Y0 = gptr(epi.Y) + t.cbase - (int64_t)l * epi.N;   // Y_0 at this tile
   auto issue = [&](int r) {
     const int k = r / FM, i = r % FM;
     const PHIKS_GLOBAL double* Yk = Y0 + (int64_t)k * epi.N;
-    double* buf = lds + (r % YB) * YSLICE;
+    double* buf = wbuf + (r % YB) * SLICE;
+    // computed per round (not hoisted out of the k loop: held across it they would not fit)
+    int64_t ldc = g.ldc;
+    int M = g.M, N = g.N;
+    int mr = __builtin_amdgcn_readfirstlane(mw), nc = __builtin_amdgcn_readfirstlane(nw);   // wave-uniform
+    asm volatile("" : "+s"(ldc), "+s"(M), "+s"(N), "+s"(mr), "+s"(nc));
 #pragma unroll
-    for (int q = 0; q < LY; ++q) {
-      const int s = q * 256 + tid;
-      const int rho = s / CP;
-      const int grow = min(m0 + (rho / 16) * WM + i * 16 + rho % 16, g.M - 1);
-      dma16(Yk + off[q] + (int64_t)(grow - ((rho / 16) * WM + rho % 16)) * g.ldc,
-            buf + 2 * (q * 256 + wave * 64));
+    for (int q = 0; q < LW; ++q) {
+      const int s = q * 64 + lane;
+      const int row = s / CPW, cp = (s % CPW) ^ ((row & 1) * (CPW / 2));
+      const int grow = min(mr + i * 16 + row, M - 1), gcol = min(nc + 2 * cp, N - 2);
+      dma16(Yk + (int64_t)grow * ldc + gcol, buf + 2 * (q * 64));
     }
   };
 
@@ -148,28 +144,25 @@ __device__ __forceinline__ void lincomb_lds_epilogue(dbl4 (&acc)[FM][FN], const 
     for (int i = 0; i < FM; ++i) {
       const int r = k * FM + i;
       // round r has landed once at most the later rounds' loads are outstanding
-      if (r + YB - 2 < rounds) wait_vmcnt<(YB - 2) * LY>();
+      if (r + YB - 2 < rounds) wait_vmcnt<(YB - 2) * LW>();
       else wait_vmcnt<0>();
-      wait_lgkmcnt0();
       asm volatile("" ::: "memory");
-      __builtin_amdgcn_s_barrier();
-      asm volatile("" ::: "memory");
-      if (r + YB - 1 < rounds) issue(r + YB - 1);     // into the buffer round r - 1 used
-      const double* buf = lds + (r % YB) * YSLICE;
+      // the buffer round r - 1 used is free: its reads fed the fmas above
+      if (r + YB - 1 < rounds) issue(r + YB - 1);
+      const double* buf = wbuf + (r % YB) * SLICE;
 #pragma unroll
       for (int j = 0; j < FN; ++j) {
-        const int c = wn + j * 16 + lr;
+        const int c = j * 16 + lr;
 #pragma unroll
         for (int rr = 0; rr < 4; ++rr) {
-          const int rho = wgm * 16 + lk + 4 * rr;
-          const double y = buf[2 * (rho * CP + ((c >> 1) ^ ((rho & 1) << 3))) + (c & 1)];
+          const int row = lk + 4 * rr;
+          const double y = buf[2 * (row * CPW + ((c >> 1) ^ ((row & 1) * (CPW / 2)))) + (c & 1)];
           acc[i][j][rr] = __builtin_fma(ck, y, acc[i][j][rr]);
         }
       }
     }
   }
 
-  const int mw = m0 + wgm * WM, nw = n0 + wn;
   const int ml = mw + lk, nl = nw + lr;
   const int64_t base = t.cbase + (int64_t)ml * g.ldc + nl;
 #pragma unroll
@@ -201,12 +194,11 @@ __device__ __forceinline__ void gemm_f64_dl_tile(const GemmArgs& g, const Epi& e
   static_assert(B_KCONTIG || BN / 2 >= 16, "column-pair swizzle needs BN >= 32");
 
   // LDS: the ST-stage operand ring; the squaring epilogue reuses the same memory for its
-  // YB slice buffers once the K loop is done
+  // YB slice buffers per wave once the K loop is done (two: with three, a 128 x 64 tile
+  // needs 48 KB and LDS holds only 3 work-groups per CU)
   constexpr bool LC = std::is_same<Epi, EpiLinComb>::value;
   constexpr int STAGE = 2 * (A_SLOTS + B_SLOTS);        // doubles per stage
-  // doubles per Y slice; buffers: three for 128 x 64 tiles (register-bound to 3 waves per
-  // SIMD anyway), two for smaller tiles, whose occupancy is bound by LDS
-  constexpr int YSLICE = WGM * 16 * BN, YB = BM * BN >= 8192 ? 3 : 2;
+  constexpr int YSLICE = WGM * 16 * BN, YB = 2;         // doubles per work-group slice round
   constexpr int LDS_DBL = (LC && YB * YSLICE > ST * STAGE) ? YB * YSLICE : ST * STAGE;
   __shared__ __align__(16) double lds[LDS_DBL];
   auto As = [&](int st) { return lds + st * STAGE; };
@@ -310,7 +302,7 @@ __device__ __forceinline__ void gemm_f64_dl_tile(const GemmArgs& g, const Epi& e
   }
 
   if constexpr (LC) {
-    lincomb_lds_epilogue<BM, BN, WM, WN, YB>(acc, g, epi, t, lds, m0, n0, wave, tid);
+    lincomb_wave_epilogue<WM, WN, YB>(acc, g, epi, t, lds, m0 + wm, n0 + wn, wave, lane);
   } else {
     store_tile_f64<FM, FN>(acc, g, epi, t.Cb, t.cbase, t.z1, m0 + wm, n0 + wn, lr, lk);
   }
