@@ -44,8 +44,9 @@ __device__ __forceinline__ void gemm_bf16x3_dl_tile(const GemmArgs& g, const Epi
   constexpr int LA = A_SLOTS / 256, LB = B_SLOTS / 256;
   constexpr int STAGE = 4 * (A_SLOTS + B_SLOTS);   // floats per stage
   constexpr bool LC = std::is_same<Epi, EpiLinComb>::value;
-  constexpr int LDS_FLOATS =
-      (LC && 2 * lc_f32_lds_doubles<BM, BN, WM>() > 2 * STAGE) ? 2 * lc_f32_lds_doubles<BM, BN, WM>() : 2 * STAGE;
+  constexpr int LDS_FLOATS = (LC && 2 * lc_f32_epilogue_doubles<BM, BN, WM, WN>() > 2 * STAGE)
+                                 ? 2 * lc_f32_epilogue_doubles<BM, BN, WM, WN>()
+                                 : 2 * STAGE;
 
   __shared__ __align__(16) float lds[LDS_FLOATS];
 
@@ -156,8 +157,8 @@ __device__ __forceinline__ void gemm_bf16x3_dl_tile(const GemmArgs& g, const Epi
   }
 
   if constexpr (LC)
-    lincomb_lds_epilogue_f32<BM, BN, WM, WN>(acc, g, epi, Cb, cbase, tc.z1,
-                                             reinterpret_cast<double*>(lds), m0, n0, wave, tid);
+    lincomb_epilogue_f32<BM, BN, WM, WN>(acc, g, epi, Cb, cbase, tc.z1,
+                                         reinterpret_cast<double*>(lds), m0, n0, wave, tid);
   else
     store_acc_tile<FM, FN, TC>(acc, g, epi, Cb, cbase, tc.z1, m0 + wm, n0 + wn, lr, lk);
 }

@@ -150,6 +150,146 @@ __device__ __forceinline__ void lincomb_lds_epilogue_f32(const flt4 (&acc)[FM][F
   }
 }
 
+#ifndef PHIKS_F32_LC_WAVE
+#define PHIKS_F32_LC_WAVE 1  // 1: wave-private pre-step slices (lincomb_wave_epilogue_f32)
+#endif
+#ifndef PHIKS_F32_LC_FNP
+#define PHIKS_F32_LC_FNP 2   // 16-column fragments per round of the wave-private epilogue
+#endif
+
+// Wave-private form of the squaring epilogue above (the scheme of lincomb_wave_epilogue in
+// gemm_f64_dl.hpp): round r = ((i * JP) + jp) * (l + 1) + k brings, for this wave only, 16
+// rows (fragment row i) by FNP * 16 columns (column part jp) of Y_k into one of its YB
+// buffers, YB - 1 rounds ahead, and waits only on the wave's own loads.  A wave's slice is
+// FNP * 2 KB, so the epilogue needs 4 * YB * FNP * 2 KB of LDS (32 KB with FNP = 2, where
+// the shared slices of a 64 x 64 or 128 x 64 tile needed 48 KB and of a 64 x 128 tile
+// 64 KB: 5 work-groups per CU instead of 3 or 2; FP32 batch of 512 problems 27.0 -> 26.4
+// ms).  Slice layout: slice row
+// t = 4 (r mod 4) + r / 4 for tile row r (the four rows 4 lk + rr one read touches are
+// consecutive), column pairs swizzled by ((r / 4) mod 2) (CPS / 2).  Per element the
+// arithmetic and its order are the shared form's: a_l acc, then one fma per k in k order.
+template <int FN>
+constexpr int lc_f32w_fnp() { return FN < PHIKS_F32_LC_FNP ? FN : PHIKS_F32_LC_FNP; }
+template <int WN, int YB>
+constexpr int lc_f32w_lds_doubles() { return 4 * YB * 16 * lc_f32w_fnp<WN / 16>() * 16; }
+
+template <int WM, int WN, int YB, int FM, int FN>
+__device__ __forceinline__ void lincomb_wave_epilogue_f32(const flt4 (&acc)[FM][FN], const GemmArgs& g,
+                                                          const EpiLinComb& epi, double* Cb,
+                                                          int64_t cbase, int64_t z1, double* lds,
+                                                          int mw, int nw, int wave, int lane) {
+  constexpr int FNP = lc_f32w_fnp<FN>(), JP = FN / FNP;
+  static_assert(FN % FNP == 0, "whole column parts");
+  constexpr int CPS = FNP * 8;                 // column pairs per slice row
+  constexpr int SLICE = 16 * FNP * 16;         // doubles per wave slice
+  constexpr int LW = 16 * CPS / 64;            // 16-byte loads per lane per round
+  const int lr = lane & 15, lk = lane >> 4;
+  const int l = (int)z1, nk = l + 1;
+  const int rounds = FM * JP * nk;
+  double* wbuf = lds + wave * YB * SLICE;
+  const PHIKS_GLOBAL double* Y0 = gptr(epi.Y) + cbase - (int64_t)l * epi.N;   // Y_0 at this tile
+  auto issue = [&](int r) {
+    const int ij = r / nk, k = r - ij * nk;
+    const int i = ij / JP, jp = ij - i * JP;
+    const PHIKS_GLOBAL double* Yk = Y0 + (int64_t)k * epi.N;
+    double* buf = wbuf + (r % YB) * SLICE;
+    // computed per round (not hoisted out of the loops: held across them they would not fit)
+    int64_t ldc = g.ldc;
+    int M = g.M, N = g.N;
+    int mr = __builtin_amdgcn_readfirstlane(mw), nc = __builtin_amdgcn_readfirstlane(nw);   // wave-uniform
+    asm volatile("" : "+s"(ldc), "+s"(M), "+s"(N), "+s"(mr), "+s"(nc));
+#pragma unroll
+    for (int q = 0; q < LW; ++q) {
+      const int s = q * 64 + lane;
+      const int t = s / CPS, row = (t & 3) * 4 + (t >> 2);
+      const int cp = (s % CPS) ^ (((row >> 2) & 1) * (CPS / 2));
+      const int grow = min(mr + i * 16 + row, M - 1), gcol = min(nc + jp * FNP * 16 + 2 * cp, N - 2);
+      dma16(Yk + (int64_t)grow * ldc + gcol, buf + 2 * (q * 64));
+    }
+  };
+
+  // every wave is done with the operand ring before its memory is overwritten
+  wait_lgkmcnt0();
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+#pragma unroll
+  for (int r = 0; r < YB - 1; ++r)
+    if (r < rounds) issue(r);
+  const double al = epi.a[l];
+  const int ml = mw + 4 * lk, nl = nw + lr;
+#pragma unroll
+  for (int i = 0; i < FM; ++i) {
+#pragma unroll
+    for (int jp = 0; jp < JP; ++jp) {
+      double o[FNP][4];
+#pragma unroll
+      for (int j = 0; j < FNP; ++j)
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) o[j][rr] = al * (double)acc[i][jp * FNP + j][rr];
+      for (int k = 0; k < nk; ++k) {
+        const int r = (i * JP + jp) * nk + k;
+        // round r has landed once at most the later rounds' loads are outstanding (stores
+        // of earlier parts issued after them only make this wait longer)
+        if (r + YB - 2 < rounds) wait_vmcnt<(YB - 2) * LW>();
+        else wait_vmcnt<0>();
+        asm volatile("" ::: "memory");
+        // the buffer round r - 1 used is free: its reads fed the fmas above
+        if (r + YB - 1 < rounds) issue(r + YB - 1);
+        const double* buf = wbuf + (r % YB) * SLICE;
+        const double ck = epi.c[l][k];
+#pragma unroll
+        for (int j = 0; j < FNP; ++j) {
+          const int c = j * 16 + lr;
+#pragma unroll
+          for (int rr = 0; rr < 4; ++rr) {
+            const int row = 4 * lk + rr, t = rr * 4 + lk;   // t = slice row of tile row `row`
+            const double y = buf[2 * (t * CPS + ((c >> 1) ^ (((row >> 2) & 1) * (CPS / 2)))) + (c & 1)];
+            o[j][rr] = __builtin_fma(ck, y, o[j][rr]);
+          }
+        }
+      }
+      const int64_t base = cbase + (int64_t)(ml + i * 16) * g.ldc + nl + jp * FNP * 16;
+#pragma unroll
+      for (int j = 0; j < FNP; ++j)
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr)
+          if ((ml + i * 16 + rr < g.M) & (nl + (jp * FNP + j) * 16 < g.N))
+            Cb[base + (int64_t)rr * g.ldc + j * 16] = o[j][rr];
+    }
+  }
+}
+
+// Which form a tile takes: the wave-private one below 128 x 128 (the tiles of small and
+// mid-sized products, whose shared slices needed 48 or 64 KB of LDS), the shared one for
+// 128 x 128 tiles (large products: register-bound anyway, they keep more bytes in flight
+// per work-group with shared slices: 256^3 FP32 call 9.50 against 9.66 ms, BF16x3 6.11
+// against 6.41 ms with the wave form).
+template <int BM, int BN>
+constexpr bool lc_f32_wave_form() { return PHIKS_F32_LC_WAVE == 1 && BM * BN < 128 * 128; }
+
+// LDS doubles the squaring epilogue of a tile needs
+template <int BM, int BN, int WM, int WN>
+constexpr int lc_f32_epilogue_doubles() {
+  return lc_f32_wave_form<BM, BN>() ? lc_f32w_lds_doubles<WN, 2>() : lc_f32_lds_doubles<BM, BN, WM>();
+}
+
+// The squaring epilogue of the FP32-accumulating direct-to-LDS kernels (either form; the
+// same operations in the same order per element).
+template <int BM, int BN, int WM, int WN, int FM, int FN>
+__device__ __forceinline__ void lincomb_epilogue_f32(const flt4 (&acc)[FM][FN], const GemmArgs& g,
+                                                     const EpiLinComb& epi, double* Cb, int64_t cbase,
+                                                     int64_t z1, double* lds, int m0, int n0,
+                                                     int wave, int tid) {
+  if constexpr (lc_f32_wave_form<BM, BN>()) {
+    constexpr int WGN = BN / WN;
+    lincomb_wave_epilogue_f32<WM, WN, 2>(acc, g, epi, Cb, cbase, z1, lds, m0 + (wave / WGN) * WM,
+                                         n0 + (wave % WGN) * WN, wave, tid & 63);
+  } else {
+    lincomb_lds_epilogue_f32<BM, BN, WM, WN>(acc, g, epi, Cb, cbase, z1, lds, m0, n0, wave, tid);
+  }
+}
+
 template <int BM, int BN, int WM, int WN, bool B_KCONTIG, class TA, class TC, class Epi>
 __device__ __forceinline__ void gemm_f32_dl_tile(const GemmArgs& g, const Epi& epi, int64_t rest) {
   constexpr int BK = 16;                 // floats of k per chunk
@@ -165,8 +305,9 @@ __device__ __forceinline__ void gemm_f32_dl_tile(const GemmArgs& g, const Epi& e
   constexpr int LA = A_SLOTS / 256, LB = B_SLOTS / 256;
   constexpr int STAGE = 4 * (A_SLOTS + B_SLOTS);   // floats per stage
   constexpr bool LC = std::is_same<Epi, EpiLinComb>::value;
-  constexpr int LDS_FLOATS =
-      (LC && 2 * lc_f32_lds_doubles<BM, BN, WM>() > 2 * STAGE) ? 2 * lc_f32_lds_doubles<BM, BN, WM>() : 2 * STAGE;
+  constexpr int LDS_FLOATS = (LC && 2 * lc_f32_epilogue_doubles<BM, BN, WM, WN>() > 2 * STAGE)
+                                 ? 2 * lc_f32_epilogue_doubles<BM, BN, WM, WN>()
+                                 : 2 * STAGE;
 
   __shared__ __align__(16) float lds[LDS_FLOATS];
 
@@ -297,15 +438,18 @@ __device__ __forceinline__ void gemm_f32_dl_tile(const GemmArgs& g, const Epi& e
   }
 
   if constexpr (LC)
-    lincomb_lds_epilogue_f32<BM, BN, WM, WN>(acc, g, epi, Cb, cbase, tc.z1,
-                                             reinterpret_cast<double*>(lds), m0, n0, wave, tid);
+    lincomb_epilogue_f32<BM, BN, WM, WN>(acc, g, epi, Cb, cbase, tc.z1,
+                                         reinterpret_cast<double*>(lds), m0, n0, wave, tid);
   else
     store_acc_tile<FM, FN, TC>(acc, g, epi, Cb, cbase, tc.z1, m0 + wm, n0 + wn, lr, lk);
 }
 
+#ifndef PHIKS_F32DL_MIN_WAVES_LC
+#define PHIKS_F32DL_MIN_WAVES_LC 3
+#endif
 template <class Epi>
 constexpr int f32dl_min_waves() {
-  return std::is_same<Epi, EpiLinComb>::value ? 3 : PHIKS_F32DL_MIN_WAVES;
+  return std::is_same<Epi, EpiLinComb>::value ? PHIKS_F32DL_MIN_WAVES_LC : PHIKS_F32DL_MIN_WAVES;
 }
 
 template <int BM, int BN, int WM, int WN, bool B_KCONTIG, class TA, class TC, class Epi>
