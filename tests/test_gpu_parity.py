@@ -278,3 +278,65 @@ def test_largest_d_and_p(n):
     ref = ophiks.phi_lincomb(A, tau, vs, p, ns, info["s"], info["q"])
     for j in range(ns):
         assert relerr(got[j], ref[j]) < TOL, (j, info)
+
+
+# ------------------------------------------------------ degenerate problems
+from oracle import brute  # noqa: E402  (closed forms of the scalar phi-functions)
+
+
+def test_zero_operator_and_zero_vector():
+    """K = 0: phi_l(0) v = v / l! (the quadrature is exact for these polynomial integrands
+    and every exponential is the identity); v = 0: every output exactly zero."""
+    n, p, ns = [5, 4, 3], 4, 2
+    A = [np.zeros((k, k)) for k in n]
+    v = workloads.randn_vec(n, 31)
+    got, info = run_apply(A, 1e-2, v, p, ns)
+    print(f"[zero K] plan {info}", flush=True)
+    for j in range(ns):
+        for ell in range(p + 1):
+            assert relerr(got[j, ell], v / math.factorial(ell)) < 1e-14, (j, ell)
+    B = ops("adr", n)
+    got, info = run_apply(B, 2e-2, np.zeros(int(np.prod(n))), p, ns)
+    assert not np.any(got), info
+
+
+def test_scalar_problem_closed_form():
+    """d = 1, n = 1: phi_l(tau a) v by its closed form (60-digit evaluation)."""
+    for a, tau in [(-3.7, 0.5), (2.0, 0.25), (-150.0, 1e-2)]:
+        v = np.array([1.3])
+        got, info = run_apply([np.array([[a]])], tau, v, 4, 2)
+        for j in range(2):
+            z = tau * a * 2.0 ** -j
+            for ell in range(5):
+                ref = brute.phi_scalar(ell, z).real * 1.3
+                assert abs(got[j, ell, 0] - ref) <= 1e-12 * abs(ref), (a, tau, j, ell, info)
+
+
+def test_diagonal_operators_closed_form():
+    """Diagonal A_mu: K is diagonal, so phi_l(tau K) v acts elementwise with the scalar
+    closed form at tau (lambda_1 + lambda_2 + lambda_3), including sizes 1 and 128."""
+    rng = np.random.default_rng(32)
+    n = [7, 1, 128]
+    lams = [-rng.uniform(0.0, 300.0, k) for k in n]
+    A = [np.diag(l) for l in lams]
+    tau, p = 1e-2, 3
+    v = workloads.randn_vec(n, 33)
+    got, info = run_apply(A, tau, v, p, 1)
+    # vec order: index i_1 fastest
+    K = (lams[2][:, None, None] + lams[1][None, :, None] + lams[0][None, None, :]).ravel()
+    for ell in range(p + 1):
+        ref = np.array([brute.phi_scalar(ell, tau * k).real for k in K]) * v
+        assert relerr(got[0, ell], ref) < 1e-12, (ell, info)
+
+
+def test_size_one_modes_vs_oracle():
+    """Modes of size 1 between larger ones (a 1 x 1 A_mu shifts K by its entry)."""
+    n = [1, 9, 1, 6]
+    A = [np.array([[-0.8]]), workloads.adr_1d(9, 0.5, 1.0, -1.0), np.array([[0.3]]),
+         workloads.adr_1d(6, 0.5, -0.5, -1.0)]
+    v = workloads.randn_vec(n, 34)
+    got, info = run_apply(A, 5e-2, v, 3, 2)
+    ref = ophiks.phi_same_vector(A, 5e-2, v, 3, 2, info["s"], info["q"])
+    for j in range(2):
+        for ell in range(4):
+            assert relerr(got[j, ell], ref[j, ell]) < TOL, (j, ell, info)
