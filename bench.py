@@ -5,15 +5,16 @@ advection (beta_mu = 1, 0.5, 0.25) - I, Dirichlet, h = 1/257, tau = 1e-3,
 v ~ N(0, 1) (seed 2), phi-functions on the same vector, p = 4, one scale,
 tolerance 2^-53 ||v||_2, FP64 throughout.
 
-One step is one pass of the whole path: host planning of (s, q), the device Pade
+One step is one pass of the whole path: host planning of (s, q), the device Taylor
 exponentials of the small matrices and their squarings, and the phi-action call
-(phiks_plan + phiks_apply + phiks_plan_destroy).  Inputs are resident in HBM before
-the timed region.  The value is dofs/s = N * steps / time.
+(phiks_plan + phiks_apply + phiks_plan_destroy), all on one stream.  Inputs are
+resident in HBM before the timed region.  The value is dofs/s = N * steps / time.
 
 Also reported (same JSON line): the roofline of the dominant kernel (the FP64 MFMA
-mu-mode product), measured live with HIP events recorded by the library around every
-mu-mode launch of the timed region, and the CPU oracle timed on this host for one full
-call.  Device memory comes from the library itself (no other GPU framework is loaded).
+mu-mode product of the call), measured live with HIP events recorded by the library
+around every mu-mode launch of the calls of sampled timed steps, and the CPU oracle
+timed on this host for one full call.  Device memory comes from the library itself (no
+other GPU framework is loaded).
 """
 from __future__ import annotations
 
@@ -432,9 +433,11 @@ def main():
     plan.close()
     log(f"[bench] plan {info}, workspace {ws.nbytes / 2**30:.2f} GiB")
 
-    def step():
+    def step(timed=False):
         pl = ph.phiks_plan(w.A, w.tau, w.p, w.n_scales, w.tol, w.task, stream=st)
+        ph.phiks_kernel_timing(timed)      # events on the call's launches only
         ph.phiks_apply(pl, v.ptr, out.ptr, ws.ptr, ws.nbytes, st)
+        ph.phiks_kernel_timing(False)
         pl.close()
 
     for i in range(args.warmup):
@@ -442,20 +445,18 @@ def main():
         log(f"[bench] warmup {i + 1}/{args.warmup}")
     ph.synchronize()
 
-    # HIP events on every mu-mode launch of a sample of the timed steps (every tenth and
-    # the last): a timestamped dispatch costs about 9 us of idle time after the kernel,
-    # so events on every step would slow the steps they measure
+    # HIP events on every mu-mode launch of the calls of a sample of the timed steps
+    # (every tenth and the last): a timestamped dispatch costs about 9 us of idle time
+    # after the kernel, so events on every step would slow the steps they measure
     sampled = {i for i in range(args.steps) if i % 10 == 9 or i == args.steps - 1}
     ph.phiks_kernel_timing_read()          # clear
     ph.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
-        ph.phiks_kernel_timing(i in sampled)
-        step()
+        step(i in sampled)
         log(f"[bench] step {i + 1}/{args.steps}")
     ph.synchronize()
     wall = time.perf_counter() - t0
-    ph.phiks_kernel_timing(False)
     k_ms, k_launch, k_flops = ph.phiks_kernel_timing_read()
     ms_step = wall * 1e3 / args.steps
 
@@ -547,7 +548,8 @@ def main():
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
                      "traffic": measured_traffic(), "traffic_unit": "bytes per launch",
-                     "kernel": "gemm_f64_dl_kernel / gemm_f64_kernel (mu-mode product)",
+                     "kernel": "gemm_f64_dl_kernel (mu-mode products of the phi-action "
+                               "call; the plan's small n x n GEMMs are not timed)",
                      "launches": k_launch, "timed_steps": len(sampled),
                      "avg_launch_ms": k_ms / max(k_launch, 1),
                      "flops_per_launch": k_flops / max(k_launch, 1)},

@@ -426,6 +426,18 @@ int phiks_memcpy_dtoh(void* dst, const void* src, size_t bytes);
 int phiks_memcpy_dtod(void* dst, const void* src, size_t bytes, void* hip_stream); /* async */
 int phiks_device_synchronize(void);
 
+/*
+ * Stream plumbing for the same callers (one HIP runtime for the process).  Streams
+ * are created non-blocking at the default priority on the current device.
+ * phiks_stream_order: work enqueued on `then` after this call waits for all work
+ * enqueued on `first` before it (an event recorded on `first`, waited on by `then`;
+ * neither stream is synchronised with the host).  NULL is the null stream.
+ */
+int phiks_stream_create(void** stream);
+int phiks_stream_destroy(void* stream);        /* NULL: no-op */
+int phiks_stream_order(void* first, void* then);
+int phiks_stream_synchronize(void* stream);
+
 /* Static text for a status code. */
 const char* phiks_status_string(int status);
 

@@ -60,7 +60,8 @@ SYMBOLS = ("phiks_plan", "phiks_apply", "phiks_combine", "phiks_workspace_size",
            "phiks_vector_op", "phiks_plan_complex", "phiks_plan_params_complex",
            "phiks_server_lane", "phiks_server_select_evictions", "phiks_server_clock",
            "phiks_apply_noalloc", "phiks_plan_matrix", "phiks_batch_dryrun", "phiks_batch_tuning",
-           "phiks_planner_options", "phiks_range_rectangle")
+           "phiks_planner_options", "phiks_range_rectangle", "phiks_stream_create",
+           "phiks_stream_destroy", "phiks_stream_order", "phiks_stream_synchronize")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with "
@@ -482,6 +483,32 @@ def memcpy_dtod(dst_ptr: int, src_ptr: int, nbytes: int, stream: int = 0) -> Non
 
 def synchronize() -> None:
     _check(_lib.phiks_device_synchronize(), "phiks_device_synchronize")
+
+
+for _f, _a in (("phiks_stream_create", [ctypes.POINTER(_vp)]), ("phiks_stream_destroy", [_vp]),
+               ("phiks_stream_order", [_vp, _vp]), ("phiks_stream_synchronize", [_vp])):
+    getattr(_lib, _f).restype = ctypes.c_int
+    getattr(_lib, _f).argtypes = _a
+
+
+def stream_create() -> int:
+    """A new non-blocking stream at the default priority (raw hipStream_t handle)."""
+    h = _vp()
+    _check(_lib.phiks_stream_create(ctypes.byref(h)), "phiks_stream_create")
+    return int(h.value or 0)
+
+
+def stream_destroy(stream: int) -> None:
+    _check(_lib.phiks_stream_destroy(_vp(stream)), "phiks_stream_destroy")
+
+
+def stream_order(first: int, then: int) -> None:
+    """Work enqueued on `then` from now on waits for the work enqueued on `first` so far."""
+    _check(_lib.phiks_stream_order(_vp(first), _vp(then)), "phiks_stream_order")
+
+
+def stream_synchronize(stream: int) -> None:
+    _check(_lib.phiks_stream_synchronize(_vp(stream)), "phiks_stream_synchronize")
 
 
 class DeviceArray:

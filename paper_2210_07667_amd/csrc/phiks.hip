@@ -130,13 +130,14 @@ struct ExpmOp {
 };
 
 struct ExpmRequest {
-  int op;          // index into the operator list
-  double c;        // exp(c B_op) is requested
-  double* dst;     // n^2 destination
+  int op;                  // index into the operator list
+  double c;                // exp(c B_op) is requested
+  double* dst;             // n^2 destination
+  double* dst2 = nullptr;  // optional second destination of the same values
 };
 
 // C_i = A_i B_i (+ beta C_i) for pointer arrays of equal-size n x n products; the
-// pointer table is staged through S.
+// pointer table is staged through S and the launch goes through S.later.
 int ptr_gemm(const std::vector<const double*>& a, const std::vector<const double*>& b,
              const std::vector<double*>& c, int n, double beta, Stager& S, hipStream_t st) {
   if (a.empty()) return PHIKS_OK;
@@ -162,7 +163,7 @@ int ptr_gemm(const std::vector<const double*>& a, const std::vector<const double
     ptrs.push_back(b[i]);
     ptrs.push_back(c[i]);
   }
-  return launch_gemm<false>(g, EpiStore{1.0, beta}, st, ptrs);
+  return S.later([g, beta, st, ptrs]() { return launch_gemm<false>(g, EpiStore{1.0, beta}, st, ptrs); });
 }
 
 // Computes exp(c_r B_{op_r}) for every request on the device.
@@ -184,42 +185,50 @@ int batched_expm(const std::vector<ExpmOp>& ops, const std::vector<ExpmRequest>&
     tsq[r] = std::max(t, 0);
     gam[r] = reqs[r].c * beta[o] / std::ldexp(1.0, tsq[r]);
   }
-  // work buffer: per operator Bh^1..Bh^5; per request D_0..D_4 and one squaring buffer
+  // work buffer (freed with S): Bh of every operator, one after the other (one upload);
+  // per operator Bh^2..Bh^5; per request D_0..D_4 and one squaring buffer
   size_t total = 0;
-  std::vector<size_t> op_off(nops), req_off(reqs.size());
-  for (size_t o = 0; o < nops; ++o) { op_off[o] = total; total += kTaylorBlocks * sq(ops[o].n); }
+  std::vector<size_t> b1_off(nops), op_off(nops), req_off(reqs.size());
+  for (size_t o = 0; o < nops; ++o) { b1_off[o] = total; total += sq(ops[o].n); }
+  const size_t b1_total = total;
+  for (size_t o = 0; o < nops; ++o) { op_off[o] = total; total += (kTaylorBlocks - 1) * sq(ops[o].n); }
   for (size_t r = 0; r < reqs.size(); ++r) {
     req_off[r] = total;
     total += (kTaylorBlocks + 1) * sq(ops[reqs[r].op].n);
   }
   double* work = nullptr;
-  HIP_OK(hipMallocAsync((void**)&work, total * sizeof(double), st));
+  RET_IF(S.scratch(total * sizeof(double), (void**)&work));
   auto pw_ptr = [&](size_t o, int k) {  // Bh^k, k = 1..5
-    return work + op_off[o] + (size_t)(k - 1) * sq(ops[o].n);
+    return k == 1 ? work + b1_off[o] : work + op_off[o] + (size_t)(k - 2) * sq(ops[o].n);
   };
   auto d_ptr = [&](size_t r, int i) { return work + req_off[r] + (size_t)i * sq(ops[reqs[r].op].n); };
   {
-    std::vector<double> h;
+    std::vector<double> h(b1_total);
     for (size_t o = 0; o < nops; ++o) {
-      h.resize(ops[o].Bshift.size());
-      for (size_t e = 0; e < h.size(); ++e) h[e] = ops[o].Bshift[e] / beta[o];
-      RET_IF(S.upload(pw_ptr(o, 1), h.data(), sizeof(double) * h.size()));
+      double* dst = h.data() + b1_off[o];
+      for (size_t e = 0; e < ops[o].Bshift.size(); ++e) dst[e] = ops[o].Bshift[e] / beta[o];
     }
+    RET_IF(S.upload(work, h.data(), sizeof(double) * h.size()));
   }
   // operators grouped by size for the pointer-array GEMMs
   std::vector<int64_t> sizes;
   for (size_t o = 0; o < nops; ++o)
     if (std::find(sizes.begin(), sizes.end(), ops[o].n) == sizes.end()) sizes.push_back(ops[o].n);
-  // shared powers Bh^k = Bh^(k-1) Bh, k = 2..5
-  for (int k = 2; k <= kTaylorBlocks; ++k) {
+  // shared powers in three dependent levels: Bh^2 = Bh Bh; Bh^3 = Bh^2 Bh and
+  // Bh^4 = Bh^2 Bh^2; Bh^5 = Bh^4 Bh
+  const int levels[3][2][3] = {{{2, 1, 1}, {0, 0, 0}}, {{3, 2, 1}, {4, 2, 2}}, {{5, 4, 1}, {0, 0, 0}}};
+  for (const auto& lev : levels) {
     for (int64_t nsz : sizes) {
       std::vector<const double*> a, b;
       std::vector<double*> c;
-      for (size_t o = 0; o < nops; ++o) {
-        if (ops[o].n != nsz) continue;
-        a.push_back(pw_ptr(o, k - 1));
-        b.push_back(pw_ptr(o, 1));
-        c.push_back(pw_ptr(o, k));
+      for (const auto& prod : lev) {
+        if (prod[0] == 0) continue;
+        for (size_t o = 0; o < nops; ++o) {
+          if (ops[o].n != nsz) continue;
+          a.push_back(pw_ptr(o, prod[1]));
+          b.push_back(pw_ptr(o, prod[2]));
+          c.push_back(pw_ptr(o, prod[0]));
+        }
       }
       RET_IF(ptr_gemm(a, b, c, (int)nsz, 0.0, S, st));
     }
@@ -244,10 +253,13 @@ int batched_expm(const std::vector<ExpmOp>& ops, const std::vector<ExpmRequest>&
   TaylorJob* djobs = nullptr;
   RET_IF(S.table(jobs.data(), jobs.size(), &djobs));
   const unsigned eblocks = (unsigned)std::min<int64_t>((sq(nmax) + 255) / 256, 1024);
-  (void)hipGetLastError();
-  hipLaunchKernelGGL(taylor_form_kernel, dim3(eblocks, (unsigned)jobs.size()), dim3(256), 0, st,
-                     djobs);
-  CHECK_LAUNCH();
+  const unsigned njobs = (unsigned)jobs.size();
+  RET_IF(S.later([=]() {
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(taylor_form_kernel, dim3(eblocks, njobs), dim3(256), 0, st, djobs);
+    CHECK_LAUNCH();
+    return PHIKS_OK;
+  }));
   // Horner in S = Bh^5: D_i <- D_(i+1) S + D_i, i = 3..0; D_0 then holds T(X)
   for (int i = kTaylorBlocks - 2; i >= 0; --i) {
     for (int64_t nsz : sizes) {
@@ -286,22 +298,23 @@ int batched_expm(const std::vector<ExpmOp>& ops, const std::vector<ExpmRequest>&
       for (size_t r : idx) std::swap(curp[r], othp[r]);
     }
   }
-  // dst = e^{c sigma} X
-  std::vector<ScaleJob> sj(reqs.size());
+  // dst (and dst2) = e^{c sigma} X
+  std::vector<ScaleJob> sj;
   for (size_t r = 0; r < reqs.size(); ++r) {
-    sj[r].src = curp[r];
-    sj[r].dst = reqs[r].dst;
-    sj[r].scale = std::exp(reqs[r].c * ops[reqs[r].op].sigma);
-    sj[r].n = (int)ops[reqs[r].op].n;
+    const double scale = std::exp(reqs[r].c * ops[reqs[r].op].sigma);
+    const int n = (int)ops[reqs[r].op].n;
+    sj.push_back({curp[r], reqs[r].dst, scale, n});
+    if (reqs[r].dst2) sj.push_back({curp[r], reqs[r].dst2, scale, n});
   }
   ScaleJob* dsj = nullptr;
   RET_IF(S.table(sj.data(), sj.size(), &dsj));
-  (void)hipGetLastError();
-  hipLaunchKernelGGL(scale_copy_kernel, dim3(eblocks, (unsigned)sj.size()), dim3(256), 0, st,
-                     dsj);
-  CHECK_LAUNCH();
-  HIP_OK(hipFreeAsync(work, st));
-  return PHIKS_OK;
+  const unsigned nsj = (unsigned)sj.size();
+  return S.later([=]() {
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(scale_copy_kernel, dim3(eblocks, nsj), dim3(256), 0, st, dsj);
+    CHECK_LAUNCH();
+    return PHIKS_OK;
+  });
 }
 
 // The GEMM views of a mu-mode product hold prod(n_<mu) and prod(n_>mu) (times `mult`
@@ -557,19 +570,6 @@ void plan_assign(phiks_plan_s& P, double* base) {
 }
 
 // Batched dst_i = scale_i * src_i over n_i x n_i entries.
-int launch_scale_jobs(const std::vector<ScaleJob>& sj, Stager& S, hipStream_t st) {
-  if (sj.empty()) return PHIKS_OK;
-  ScaleJob* dsj = nullptr;
-  RET_IF(S.table(sj.data(), sj.size(), &dsj));
-  int64_t nmax = 0;
-  for (const ScaleJob& j : sj) nmax = std::max<int64_t>(nmax, j.n);
-  (void)hipGetLastError();
-  hipLaunchKernelGGL(scale_copy_kernel, dim3((unsigned)std::min<int64_t>((sq(nmax) + 255) / 256, 1024),
-                                             (unsigned)sj.size()),
-                     dim3(256), 0, st, dsj);
-  CHECK_LAUNCH();
-  return PHIKS_OK;
-}
 
 // Builds the small exponentials of every plan in one device pass (Section 3.1): one
 // batched_expm over all their operators for the node matrices exp((1-theta_i) B/2^s)
@@ -580,6 +580,7 @@ int launch_scale_jobs(const std::vector<ScaleJob>& sj, Stager& S, hipStream_t st
 int build_plan_matrices(const std::vector<phiks_plan_s*>& plans,
                         const std::vector<const double* const*>& A, hipStream_t st) {
   Stager S(st);
+  S.defer();   // every table of the exponentials in one upload, then their launches
   std::vector<ExpmOp> ops;
   std::vector<ExpmRequest> reqs;
   for (size_t i = 0; i < plans.size(); ++i) {
@@ -623,8 +624,10 @@ int build_plan_matrices(const std::vector<phiks_plan_s*>& plans,
       const int o = (int)ops.size();
       ops.push_back(std::move(op));
       if (nodes > 0) {
+        // theta_1 = 0: that node matrix is exp(B/2^s) itself, written to both places
         for (int k = 0; k < nodes; ++k)
-          reqs.push_back({o, (1.0 - P.theta[k]) * inv2s, P.Lnode[mu] + (size_t)k * sq(m)});
+          reqs.push_back({o, (1.0 - P.theta[k]) * inv2s, P.Lnode[mu] + (size_t)k * sq(m),
+                          k == 0 ? P.E[mu] + (size_t)P.s * sq(m) : nullptr});
       } else {
         reqs.push_back({o, inv2s, P.E[mu] + (size_t)P.s * sq(m)});
       }
@@ -632,18 +635,8 @@ int build_plan_matrices(const std::vector<phiks_plan_s*>& plans,
     }
   }
   RET_IF(batched_expm(ops, reqs, S, st));
-  // exp(B/2^s) = the node matrix of theta_1 = 0
-  std::vector<ScaleJob> copies;
   int smax = 0;
-  for (phiks_plan_s* P : plans) {
-    smax = std::max(smax, P->s);
-    if (plan_nodes(*P) == 0) continue;
-    for (int mu = 0; mu < P->d; ++mu) {
-      const int64_t m = P->cplx ? 2 * P->n[mu] : P->n[mu];
-      copies.push_back({P->Lnode[mu], P->E[mu] + (size_t)P->s * sq(m), 1.0, (int)m});
-    }
-  }
-  RET_IF(launch_scale_jobs(copies, S, st));
+  for (phiks_plan_s* P : plans) smax = std::max(smax, P->s);
   // exp(B/2^(j-1)) = exp(B/2^j)^2, j = s..1, grouped by size
   for (int j = smax; j >= 1; --j) {
     auto opn = [](const phiks_plan_s* P, int mu) { return P->cplx ? 2 * P->n[mu] : P->n[mu]; };
@@ -666,6 +659,7 @@ int build_plan_matrices(const std::vector<phiks_plan_s*>& plans,
       RET_IF(ptr_gemm(a, a, c, (int)nsz, 0.0, S, st));
     }
   }
+  RET_IF(S.submit());
   // complex plans: the [Re | Im] forms used by the modes > 1
   std::vector<ScaleJob> splits;
   for (phiks_plan_s* P : plans) {
@@ -1022,6 +1016,41 @@ int phiks_memcpy_dtod(void* dst, const void* src, size_t bytes, void* hip_stream
 
 int phiks_device_synchronize(void) {
   HIP_OK(hipDeviceSynchronize());
+  return PHIKS_OK;
+}
+
+int phiks_stream_create(void** stream) {
+  if (!stream) return PHIKS_EINVAL;
+  *stream = nullptr;
+  hipStream_t s = nullptr;
+  HIP_OK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+  *stream = s;
+  return PHIKS_OK;
+}
+
+int phiks_stream_destroy(void* stream) {
+  if (!stream) return PHIKS_OK;
+  HIP_OK(hipStreamDestroy((hipStream_t)stream));
+  return PHIKS_OK;
+}
+
+int phiks_stream_order(void* first, void* then) {
+  if (first == then) return PHIKS_OK;
+  hipEvent_t e = nullptr;
+  HIP_OK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  int rc = PHIKS_OK;
+  if (hipEventRecord(e, (hipStream_t)first) != hipSuccess ||
+      hipStreamWaitEvent((hipStream_t)then, e, 0) != hipSuccess) {
+    set_error("event record or stream wait failed");
+    rc = PHIKS_EDEVICE;
+  }
+  // released by the runtime once the recorded work has completed
+  (void)hipEventDestroy(e);
+  return rc;
+}
+
+int phiks_stream_synchronize(void* stream) {
+  HIP_OK(hipStreamSynchronize((hipStream_t)stream));
   return PHIKS_OK;
 }
 

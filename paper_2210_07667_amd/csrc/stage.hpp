@@ -11,6 +11,9 @@
 // blocks stay pinned per device; past that the host waits for the oldest one.
 // Device side: tables are carved from chunks allocated in stream order and freed in
 // stream order when the build ends, after every kernel that reads them was enqueued.
+// Deferred mode: each separate upload costs a copy launch of its own on the stream, so
+// a build may hold its uploads and record its launches, then submit them: the uploads
+// go out as one copy per contiguous run, followed by the launches in recorded order.
 // Included once, by phiks.hip.
 #pragma once
 #include <hip/hip_runtime.h>
@@ -18,6 +21,7 @@
 #include <algorithm>
 #include <cstring>
 #include <deque>
+#include <functional>
 #include <mutex>
 #include <vector>
 
@@ -136,7 +140,38 @@ class Stager {
     char* h = nullptr;
     RET_IF(host_space(bytes, h));
     std::memcpy(h, src, bytes);
+    if (deferred_) {
+      pending_.push_back({static_cast<char*>(dst), h, bytes});
+      return PHIKS_OK;
+    }
     HIP_OK(hipMemcpyAsync(dst, h, bytes, hipMemcpyHostToDevice, st_));
+    return PHIKS_OK;
+  }
+
+  // Device memory of `bytes` for the kernels enqueued before finish(), which frees it
+  // (stream-ordered).
+  int scratch(size_t bytes, void** d) {
+    *d = nullptr;
+    return device_space(bytes, reinterpret_cast<char**>(d));
+  }
+
+  // Holds uploads and records launches from here on, until submit().
+  void defer() { deferred_ = true; }
+
+  // Runs `f` (a launch or another stream-ordered call) now, or at submit() when deferred.
+  int later(std::function<int()> f) {
+    if (!deferred_) return f();
+    launches_.push_back(std::move(f));
+    return PHIKS_OK;
+  }
+
+  // Issues the held uploads, then the recorded launches in order; leaves deferred mode.
+  int submit() {
+    RET_IF(issue_copies());
+    deferred_ = false;
+    std::vector<std::function<int()>> fs;
+    fs.swap(launches_);
+    for (auto& f : fs) RET_IF(f());
     return PHIKS_OK;
   }
 
@@ -152,6 +187,10 @@ class Stager {
 
   int finish() {
     int rc = PHIKS_OK;
+    // a build that failed before submit(): nothing recorded reaches the stream
+    launches_.clear();
+    pending_.clear();
+    deferred_ = false;
     if (have_) {
       g_stage_pool.retire(device_, blk_, st_);
       g_stage_pool.checked_out(device_, -1);
@@ -167,9 +206,30 @@ class Stager {
  private:
   static size_t align(size_t x) { return (x + 255) & ~size_t(255); }
 
+  // One copy per run of held uploads that follow each other in the pinned block and on
+  // the device alike (consecutive tables of one chunk: each starts at the previous
+  // one's start plus its size rounded up to 256 bytes, on both sides; the padding in
+  // between belongs to the same block and chunk).
+  int issue_copies() {
+    size_t i = 0;
+    while (i < pending_.size()) {
+      size_t j = i + 1;
+      while (j < pending_.size() &&
+             pending_[j].dst == pending_[j - 1].dst + align(pending_[j - 1].bytes) &&
+             pending_[j].host == pending_[j - 1].host + align(pending_[j - 1].bytes))
+        ++j;
+      const size_t bytes = (size_t)(pending_[j - 1].dst - pending_[i].dst) + pending_[j - 1].bytes;
+      HIP_OK(hipMemcpyAsync(pending_[i].dst, pending_[i].host, bytes, hipMemcpyHostToDevice, st_));
+      i = j;
+    }
+    pending_.clear();
+    return PHIKS_OK;
+  }
+
   int host_space(size_t bytes, char*& h) {
     if (!have_ || used_ + bytes > blk_.cap) {
       if (have_) {
+        RET_IF(issue_copies());   // the block's held uploads go out before it is retired
         g_stage_pool.retire(device_, blk_, st_);
         g_stage_pool.checked_out(device_, -1);
         have_ = false;
@@ -206,6 +266,14 @@ class Stager {
   size_t used_ = 0;
   std::vector<char*> chunks_;
   size_t chunk_used_ = 0, chunk_cap_ = 0;
+  struct Held {
+    char* dst;
+    const char* host;
+    size_t bytes;
+  };
+  bool deferred_ = false;
+  std::vector<Held> pending_;
+  std::vector<std::function<int()>> launches_;
 };
 
 }  // namespace

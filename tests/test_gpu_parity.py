@@ -340,3 +340,42 @@ def test_size_one_modes_vs_oracle():
     for j in range(2):
         for ell in range(4):
             assert relerr(got[j, ell], ref[j, ell]) < TOL, (j, ell, info)
+
+
+# ------------------------------------------------------------ two streams
+def test_plans_and_calls_pipelined_over_two_streams():
+    """Step i's plan built on one stream while step i - 1's call runs on another (the call
+    ordered after its plan, the release after the call): every output bitwise equal to the
+    same plan and call on the null stream."""
+    n = [40, 33, 20]
+    A = ops("adr", n)
+    v = workloads.randn_vec(n, 35)
+    taus = [2e-3, 5e-3, 1e-2, 3e-3]
+    p, ns = 3, 2
+    ref = [run_apply(A, t, v, p, ns)[0] for t in taus]
+    N = int(np.prod(n))
+    dv = to_dev(v)
+    outs = [ph.DeviceArray(ns * (p + 1) * N) for _ in taus]
+    s_plan, s_call = ph.stream_create(), ph.stream_create()
+    try:
+        mk = lambda t: ph.phiks_plan(A, t, p, ns, 2.0 ** -53, "same_vector", stream=s_plan)
+        nxt = mk(taus[0])
+        for i in range(len(taus)):
+            pl = nxt
+            ws = ph.DeviceArray(pl.workspace_size() // 8 + 1)
+            ph.stream_order(s_plan, s_call)
+            ph.phiks_apply(pl, dv.ptr, outs[i].ptr, ws.ptr, ws.nbytes, s_call)
+            if i + 1 < len(taus):
+                nxt = mk(taus[i + 1])
+            ph.stream_order(s_call, s_plan)
+            pl.close()
+            ph.stream_synchronize(s_call)
+            ws.free()
+        ph.stream_synchronize(s_plan)
+        for i in range(len(taus)):
+            got = outs[i].to_numpy().reshape(ns, p + 1, N)
+            assert np.array_equal(got, ref[i]), i
+    finally:
+        ph.synchronize()
+        ph.stream_destroy(s_plan)
+        ph.stream_destroy(s_call)
