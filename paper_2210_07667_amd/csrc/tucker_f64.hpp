@@ -26,13 +26,20 @@ int64_t tiles_for(const GemmArgs& g, int bm, int bn) {
   return (int64_t)((g.M + bm - 1) / bm) * ((g.N + bn - 1) / bn) * g.nb0 * g.nb1;
 }
 
-// Largest tile that still gives at least one work-group per compute unit; small
-// products (the exponentials of the small matrices) get small tiles and more groups.
+// Largest tile that still gives at least PHIKS_TILE_MIN_WG work-groups per compute unit;
+// small products (the exponentials of the small matrices, 64^3 tensors) get small tiles and
+// more groups.  One work-group per CU is one wave per SIMD, which leaves the MFMA pipes
+// waiting on its loads: with two required, a 64^3 call (4-tensor products on 32 x 32
+// instead of 64 x 64 tiles) took 0.116 instead of 0.127 ms, and 96^3-256^3 calls were
+// unchanged; four gave no further gain.  The tile never changes results (one k order).
 #ifndef PHIKS_BIG_TILE
 #define PHIKS_BIG_TILE 0  // 0: 128 x 64, 1: 128 x 128
 #endif
+#ifndef PHIKS_TILE_MIN_WG
+#define PHIKS_TILE_MIN_WG 2
+#endif
 Tile pick_tile(const GemmArgs& g) {
-  constexpr int64_t kCUs = 256;
+  constexpr int64_t kCUs = 256 * PHIKS_TILE_MIN_WG;
   if (PHIKS_BIG_TILE == 1 && g.M >= 128 && g.N >= 128 && tiles_for(g, 128, 128) >= kCUs)
     return Tile::T128x128;
   if (g.M >= 128 && g.N >= 64 && tiles_for(g, 128, 64) >= kCUs) return Tile::T128x64;
