@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -398,13 +399,29 @@ int host_plan(int d, const int64_t* n, const double* const* A, double tau, int p
 // quadrature nodes theta_i < 1, each of which needs a Tucker operator
 int plan_nodes(const phiks_plan_s& P) { return (P.p > 0) ? P.q - 1 : 0; }
 
+// A combination whose node Tuckers of all p input vectors fit (q - 1) p tensors of at
+// most 2^24 doubles in all (the small problems, whose launches do not fill the GPU) runs
+// them as one batched launch per mode and sums the nodes in one pass; larger ones take
+// one input vector at a time.  FP64 real plans only.
+constexpr int64_t kCombineBatchDoubles = int64_t(1) << 24;
+bool combine_batches_vectors(const phiks_plan_s& P) {
+  return P.task == PHIKS_LINCOMB && !P.cplx && P.precision == PHIKS_FP64 && P.p > 0 &&
+         (int64_t)(P.q - 1) * P.p * plan_vec_doubles(P) <= kCombineBatchDoubles;
+}
+
+// Tensors per Tucker buffer: max(q - 1, p) (the node Tuckers of one input, batched over
+// the nodes, or the p tensors of a squaring step), or (q - 1) p for a combination whose
+// node Tuckers of all inputs run together.
+int64_t tucker_buffer_tensors(const phiks_plan_s& P) {
+  const int64_t t = std::max<int64_t>({(int64_t)P.q - 1, (int64_t)P.p, 1});
+  return combine_batches_vectors(P) ? std::max<int64_t>(t, (int64_t)(P.q - 1) * P.p) : t;
+}
+
 size_t workspace_doubles(const phiks_plan_s& P) {
   const int64_t N = plan_vec_doubles(P);
-  // same vector and combination alike: two Tucker buffers of max(q - 1, p) tensors (the
-  // node Tuckers of one input, batched over the nodes, or the p tensors of a squaring
-  // step) and the double-buffered p running sums
-  const int64_t t = std::max<int64_t>({(int64_t)P.q - 1, (int64_t)P.p, 1});
-  return (size_t)(2 * t + 2 * std::max(P.p, 1)) * N;
+  // same vector and combination alike: two Tucker buffers and the double-buffered p
+  // running sums
+  return (size_t)(2 * tucker_buffer_tensors(P) + 2 * std::max(P.p, 1)) * N;
 }
 
 
@@ -1217,6 +1234,64 @@ static int apply_body(const phiks_plan_s& P, const double* v, double* out, void*
   return PHIKS_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Node Tuckers (every node theta_i < 1) of the inputs v[act[0]], ..., v[act[na-1]] of a
+// combination with an FP64 real plan, entry (node i, input j) written at out + (i na + j) N.
+// The views are tucker_args' for one input, widened to all of them: mode 1 by its free
+// batch index z0 (one launch when the inputs lie equally far apart in memory, else one
+// launch per input), modes > 1 by folding the input index into their trailing batch z0
+// (input j's tensor of a node lies j N after input 0's, since N = n_<mu n_mu n_>mu).
+int node_tuckers_of_inputs(const phiks_plan_s& P, const double* const* v, const std::vector<int>& act,
+                           double* out, double* ta, double* tb, hipStream_t st) {
+  const int na = (int)act.size();
+  const int64_t N = P.N;
+  double* L[PHIKS_MAX_D];
+  int64_t ls[PHIKS_MAX_D];
+  for (int mu = 0; mu < P.d; ++mu) {
+    L[mu] = P.Lnode[mu];
+    ls[mu] = P.n[mu] * P.n[mu];
+  }
+  GemmArgs gs[PHIKS_MAX_D];
+  tucker_args(P.d, P.n, N, v[act[0]], 0, L, ls, plan_nodes(P), out, ta, tb, gs);
+  // mode 1: A = the input (rows of N / n_1), B = the node matrices
+  GemmArgs g1 = gs[0];
+  g1.sC1 = (int64_t)na * N;
+  const auto addr = [&](int j) { return (int64_t)(uintptr_t)v[act[j]]; };
+  bool even = na > 1 && (addr(1) - addr(0)) % (int64_t)sizeof(double) == 0;
+  const int64_t gap = na > 1 ? addr(1) - addr(0) : 0;
+  for (int j = 2; j < na && even; ++j) even = addr(j) - addr(j - 1) == gap;
+  if (even || na == 1) {
+    g1.nb0 = na;
+    g1.sA0 = gap / (int64_t)sizeof(double);
+    g1.sB0 = 0;
+    g1.sC0 = N;
+    RET_IF((launch_gemm<true>(g1, EpiStore{1.0, 0.0}, st)));
+  } else {
+    for (int j = 0; j < na; ++j) {
+      GemmArgs g = g1;
+      g.A = v[act[j]];
+      g.C = g1.C + (int64_t)j * N;
+      RET_IF((launch_gemm<true>(g, EpiStore{1.0, 0.0}, st)));
+    }
+  }
+  // modes > 1: B = the previous mode's entries, z0 = j n_>mu + (trailing index)
+  for (int mu = 2; mu <= P.d; ++mu) {
+    GemmArgs g = gs[mu - 1];
+    g.nb0 *= na;
+    g.sB1 = (int64_t)na * N;
+    g.sC1 = (int64_t)na * N;
+    RET_IF((launch_gemm<false>(g, EpiStore{1.0, 0.0}, st)));
+  }
+  return PHIKS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 int phiks_combine(phiks_plan_t plan, const double* const* v, double* out, void* ws,
                   size_t ws_bytes, void* hip_stream) {
   if (!plan || !v || !out) return PHIKS_EINVAL;
@@ -1227,7 +1302,7 @@ int phiks_combine(phiks_plan_t plan, const double* const* v, double* out, void* 
   hipStream_t st = (hipStream_t)hip_stream;
   const int64_t N = plan_vec_doubles(P);  // doubles per vector
   const int p = P.p, ns = P.ns, s = P.s, q = P.q, d = P.d;
-  const int64_t tcount = std::max<int64_t>({(int64_t)q - 1, (int64_t)p, 1});
+  const int64_t tcount = tucker_buffer_tensors(P);
   double* ta = (double*)ws;
   double* tb = ta + tcount * N;
   double* qa = tb + tcount * N;
@@ -1240,7 +1315,9 @@ int phiks_combine(phiks_plan_t plan, const double* const* v, double* out, void* 
   // is linear, so Q_l = sum_{k<=l} sum_i c_ilk Tucker_i(v_{p+1-k}) with
   // c_ilk = w_i theta_i^(l-k)/(l-k)! / 2^((l-k+1)s): one Tucker of each input vector per
   // node, all nodes of one vector in one batched launch per mode (as the same-vector
-  // path), their weighted sums accumulated into Q_k..Q_p.  The U_il are never formed.
+  // path), their weighted sums accumulated into Q_k..Q_p; for small problems the nodes of
+  // all input vectors in one batched launch per mode and one node sum into Q_1..Q_p.  The
+  // U_il are never formed.
   auto coef = [&](int i, int ell, int k) {
     return P.w[i] * std::pow(P.theta[i], ell - k) / factorial(ell - k) *
            std::ldexp(1.0, -(ell - k + 1) * s);
@@ -1271,49 +1348,88 @@ int phiks_combine(phiks_plan_t plan, const double* const* v, double* out, void* 
 
   const double* Qcur = nullptr;
   if (p > 0 && any) {
-    double* Q = qa;
-    // node theta_q = 1 (exp(0) = I, no Tucker): Q_l = sum_{k<=l} c_qlk v_{p+1-k}
-    {
-      CombineArgs ca;
-      std::memset(&ca, 0, sizeof(ca));
-      ca.out = Q;
-      ca.out_stride = N;
-      ca.nout = p;
-      ca.beta = 0.0;
-      ca.N = N;
-      int t = 0;
+    if (combine_batches_vectors(P)) {
+      // the node Tuckers of every input at once, then one node sum (possibly in several
+      // passes of at most kMaxIn inputs) over them and the theta_q = 1 terms
+      std::vector<int> act;   // input vectors present, v_act[j]
+      for (int vi = 1; vi <= p; ++vi)
+        if (v[vi]) act.push_back(vi);
+      const int na = (int)act.size();
+      const int nodes = q - 1;
+      double* wbuf = tucker_free_buffer(d, ta, tb);
+      RET_IF(node_tuckers_of_inputs(P, v, act, wbuf, ta, tb, st));
+      std::vector<const double*> in;
+      std::vector<std::array<double, 8>> cf;   // coefficient of input t for Q_1..Q_p
+      for (int j = 0; j < na; ++j) {
+        const int k = p + 1 - act[j];
+        for (int i = 0; i <= nodes; ++i) {
+          // i < nodes: entry (i, j) of the node results; i = nodes: theta_q = 1, v itself
+          in.push_back(i < nodes ? wbuf + ((int64_t)i * na + j) * N : v[act[j]]);
+          std::array<double, 8> c{};
+          for (int ell = k; ell <= p; ++ell) c[ell - 1] = coef(i, ell, k);
+          cf.push_back(c);
+        }
+      }
+      for (size_t t0 = 0; t0 < in.size(); t0 += kMaxIn) {
+        CombineArgs ca;
+        std::memset(&ca, 0, sizeof(ca));
+        ca.out = qa;
+        ca.out_stride = N;
+        ca.nout = p;
+        ca.beta = (t0 == 0) ? 0.0 : 1.0;
+        ca.N = N;
+        ca.nin = (int)std::min<size_t>(kMaxIn, in.size() - t0);
+        for (int t = 0; t < ca.nin; ++t) {
+          ca.in[t] = in[t0 + t];
+          for (int ell = 1; ell <= p; ++ell) ca.coef[ell - 1][t] = cf[t0 + t][ell - 1];
+        }
+        RET_IF(launch_combine(ca, st));
+      }
+    } else {
+      double* Q = qa;
+      // node theta_q = 1 (exp(0) = I, no Tucker): Q_l = sum_{k<=l} c_qlk v_{p+1-k}
+      {
+        CombineArgs ca;
+        std::memset(&ca, 0, sizeof(ca));
+        ca.out = Q;
+        ca.out_stride = N;
+        ca.nout = p;
+        ca.beta = 0.0;
+        ca.N = N;
+        int t = 0;
+        for (int vi = 1; vi <= p; ++vi) {
+          if (!v[vi]) continue;
+          const int k = p + 1 - vi;
+          ca.in[t] = v[vi];
+          for (int ell = k; ell <= p; ++ell) ca.coef[ell - 1][t] = coef(q - 1, ell, k);
+          ++t;
+        }
+        ca.nin = t;
+        RET_IF(launch_combine(ca, st));
+      }
+      // nodes theta_i < 1, one input vector at a time
+      const int nodes = q - 1;
+      double* wbuf = tucker_free_buffer(d, ta, tb);
       for (int vi = 1; vi <= p; ++vi) {
         if (!v[vi]) continue;
         const int k = p + 1 - vi;
-        ca.in[t] = v[vi];
-        for (int ell = k; ell <= p; ++ell) ca.coef[ell - 1][t] = coef(q - 1, ell, k);
-        ++t;
+        RET_IF(plan_tucker(P, MatSel::AllNodes, 0, v[vi], 0, nodes, wbuf, ta, tb,
+                           EpiStore{1.0, 0.0}, st));
+        CombineArgs ca;
+        std::memset(&ca, 0, sizeof(ca));
+        ca.nin = nodes;
+        for (int i = 0; i < nodes; ++i) ca.in[i] = wbuf + (int64_t)i * N;
+        ca.out = Q + (int64_t)(k - 1) * N;
+        ca.out_stride = N;
+        ca.nout = p - k + 1;
+        ca.beta = 1.0;
+        ca.N = N;
+        for (int ell = k; ell <= p; ++ell)
+          for (int i = 0; i < nodes; ++i) ca.coef[ell - k][i] = coef(i, ell, k);
+        RET_IF(launch_combine(ca, st));
       }
-      ca.nin = t;
-      RET_IF(launch_combine(ca, st));
     }
-    // nodes theta_i < 1, one input vector at a time
-    const int nodes = q - 1;
-    double* wbuf = tucker_free_buffer(d, ta, tb);
-    for (int vi = 1; vi <= p; ++vi) {
-      if (!v[vi]) continue;
-      const int k = p + 1 - vi;
-      RET_IF(plan_tucker(P, MatSel::AllNodes, 0, v[vi], 0, nodes, wbuf, ta, tb,
-                         EpiStore{1.0, 0.0}, st));
-      CombineArgs ca;
-      std::memset(&ca, 0, sizeof(ca));
-      ca.nin = nodes;
-      for (int i = 0; i < nodes; ++i) ca.in[i] = wbuf + (int64_t)i * N;
-      ca.out = Q + (int64_t)(k - 1) * N;
-      ca.out_stride = N;
-      ca.nout = p - k + 1;
-      ca.beta = 1.0;
-      ca.N = N;
-      for (int ell = k; ell <= p; ++ell)
-        for (int i = 0; i < nodes; ++i) ca.coef[ell - k][i] = coef(i, ell, k);
-      RET_IF(launch_combine(ca, st));
-    }
-    double* cur = Q;
+    double* cur = qa;
     if (s < ns) RET_IF(emit(s, cur));
     // eq. comb: Q_l <- Tucker(Q_l; E_j) + sum_{k<=l} Q_k / ((l-k)! 2^((l-k) j))
     for (int j = s; j >= 1; --j) {

@@ -179,6 +179,40 @@ def test_combine_vs_oracle(n, tau, p, ns):
         assert relerr(got[j], ref[j]) < TOL, (j, info)
 
 
+def test_combine_inputs_at_uneven_addresses():
+    """Small combinations run the node Tuckers of all inputs in one launch per mode; mode 1
+    reads the inputs through one stride when they lie equally far apart, else one launch
+    per input.  Both layouts (the inputs placed in one buffer at offsets 0, N, 2N, or 0,
+    N + 2, 2N + 10 doubles) must give the same bits, and the oracle's values."""
+    n, tau, p, ns = [24, 20, 16], 2e-2, 3, 2
+    A = ops("adr", n)
+    N = int(np.prod(n))
+    rng = np.random.default_rng(36)
+    vs = [rng.standard_normal(N) for _ in range(p + 1)]
+    plan = ph.phiks_plan(A, tau, p, ns, 2.0 ** -53, "lincomb")
+    ws = ph.DeviceArray(plan.workspace_size() // 8 + 1)
+    dv = [to_dev(x) for x in vs]
+    big = ph.DeviceArray(p * N + 16)
+    out = ph.DeviceArray(ns * N)
+    results = []
+    for offs in ([0, N, 2 * N], [0, N + 2, 2 * N + 10]):
+        assert offs[-1] + N <= p * N + 16
+        for k, o in enumerate(offs):
+            ph.memcpy_dtod(big.ptr + 8 * o, dv[k + 1].ptr, 8 * N)
+        ptrs = [dv[0].ptr] + [big.ptr + 8 * o for o in offs]
+        ph.phiks_combine(plan, ptrs, out.ptr, ws.ptr, ws.nbytes)
+        ph.synchronize()
+        results.append(out.to_numpy().reshape(ns, N))
+    info = plan.info()
+    plan.close()
+    for x in dv + [big, out, ws]:
+        x.free()
+    assert np.array_equal(results[0], results[1])
+    ref = ophiks.phi_lincomb(A, tau, vs, p, ns, info["s"], info["q"])
+    for j in range(ns):
+        assert relerr(results[1][j], ref[j]) < TOL, (j, info)
+
+
 def test_combine_six_modes():
     """Linear combination with d = 6 (the validation dimension of Section 4.1)."""
     n = [9, 8, 10, 8, 9, 8]
