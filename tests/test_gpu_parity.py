@@ -291,6 +291,29 @@ def test_adr_256_full_size_against_oracle():
         assert relerr(lhs, rhs) < 1e-9, ell
 
 
+def test_adr_256_combination_full_size_against_oracle():
+    """phiks_combine on the 3D ADR 256^3 operator, p = 4, five N(0, 1) inputs (the timed
+    combination workload): the whole output against the oracle at the same (s, q), and the
+    linearity property sum_l phi_l(tau K) v_l = sum of the l-th outputs of same-vector calls
+    (a different path through the library: node sums per vector, not per node input)."""
+    w = workloads.config_adr_3d()
+    p = w.p
+    vs = [workloads.randn_vec(w.n, 90 + k) for k in range(p + 1)]
+    print("[combine] adr 256^3 full size", flush=True)
+    got, info = run_combine(w.A, w.tau, vs, p, 1)
+    print(f"[combine] plan {info}; same-vector calls", flush=True)
+    lin = np.zeros(w.N)
+    for ell in range(p + 1):
+        out, _ = run_apply(w.A, w.tau, vs[ell], p, 1)
+        lin += out[0, ell]
+    print(f"[combine] against the same-vector calls: {relerr(got[0], lin):.2e}", flush=True)
+    assert relerr(got[0], lin) < 1e-11
+    print("[combine] running oracle", flush=True)
+    ref = ophiks.phi_lincomb(w.A, w.tau, vs, p, 1, info["s"], info["q"])
+    print(f"[combine] against the oracle: {relerr(got[0], ref[0]):.2e}", flush=True)
+    assert relerr(got[0], ref[0]) < TOL, info
+
+
 @pytest.mark.parametrize("n", [[2, 3, 2, 2, 2, 3, 2, 2], [6, 5, 4, 3, 4, 5, 3, 4]],
                          ids=["d8_tiny", "d8_small"])
 def test_largest_d_and_p(n):
