@@ -217,6 +217,7 @@ int batched_expm(const std::vector<ExpmOp>& ops, const std::vector<ExpmRequest>&
     if (std::find(sizes.begin(), sizes.end(), ops[o].n) == sizes.end()) sizes.push_back(ops[o].n);
   // shared powers in three dependent levels: Bh^2 = Bh Bh; Bh^3 = Bh^2 Bh and
   // Bh^4 = Bh^2 Bh^2; Bh^5 = Bh^4 Bh
+  static_assert(kTaylorBlocks == 5, "the power levels below form Bh^2 .. Bh^5");
   const int levels[3][2][3] = {{{2, 1, 1}, {0, 0, 0}}, {{3, 2, 1}, {4, 2, 2}}, {{5, 4, 1}, {0, 0, 0}}};
   for (const auto& lev : levels) {
     for (int64_t nsz : sizes) {
@@ -1183,7 +1184,7 @@ static int apply_body(const phiks_plan_s& P, const double* v, double* out, void*
                       hipStream_t st) {
   const int64_t N = plan_vec_doubles(P);  // doubles per vector
   const int p = P.p, ns = P.ns, s = P.s, q = P.q, d = P.d;
-  const int64_t tcount = std::max<int64_t>({(int64_t)q - 1, (int64_t)p, 1});
+  const int64_t tcount = tucker_buffer_tensors(P);
   double* ta = (double*)ws;
   double* tb = ta + tcount * N;
   double* pa = tb + tcount * N;
