@@ -559,6 +559,14 @@ PlanChoice choose_sq(const Rect& xi, int p, int n_scales, double tol, int task,
   }
   std::vector<cd> pts;
   boundary_points(xi, pts);
+  // a check passes iff the maximum over the points does, so points that repeat exactly
+  // (a side of zero length: the real rectangle of a symmetric operator) are evaluated once
+  {
+    std::vector<cd> uniq;
+    for (const cd& z : pts)
+      if (std::find(uniq.begin(), uniq.end(), z) == uniq.end()) uniq.push_back(z);
+    pts.swap(uniq);
+  }
   const double cp = 1.0 + std::sqrt(2.0);
   size_t hot = 0;  // index of the last violating point: tried first
   auto feasible = [&](int s, int q) {
