@@ -167,7 +167,9 @@ int ptr_gemm(const std::vector<const double*>& a, const std::vector<const double
   return S.later([g, beta, st, ptrs]() { return launch_gemm<false>(g, EpiStore{1.0, beta}, st, ptrs); });
 }
 
-// Computes exp(c_r B_{op_r}) for every request on the device.
+// Computes exp(c_r B_{op_r}) for every request on the device, into dst (and dst2).
+// Tables and the work buffer come from S, launches go through S.later (held until
+// S.submit when S is deferred).
 int batched_expm(const std::vector<ExpmOp>& ops, const std::vector<ExpmRequest>& reqs,
                  Stager& S, hipStream_t st) {
   const size_t nops = ops.size();
@@ -586,8 +588,6 @@ void plan_assign(phiks_plan_s& P, double* base) {
     }
   }
 }
-
-// Batched dst_i = scale_i * src_i over n_i x n_i entries.
 
 // Builds the small exponentials of every plan in one device pass (Section 3.1): one
 // batched_expm over all their operators for the node matrices exp((1-theta_i) B/2^s)
