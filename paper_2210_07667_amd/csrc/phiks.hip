@@ -188,12 +188,11 @@ int batched_expm(const std::vector<ExpmOp>& ops, const std::vector<ExpmRequest>&
     tsq[r] = std::max(t, 0);
     gam[r] = reqs[r].c * beta[o] / std::ldexp(1.0, tsq[r]);
   }
-  // work buffer (freed with S): Bh of every operator, one after the other (one upload);
-  // per operator Bh^2..Bh^5; per request D_0..D_4 and one squaring buffer
+  // work buffer (freed with S): Bh of every operator, one after the other; per operator
+  // Bh^2..Bh^5; per request D_0..D_4 and one squaring buffer
   size_t total = 0;
   std::vector<size_t> b1_off(nops), op_off(nops), req_off(reqs.size());
   for (size_t o = 0; o < nops; ++o) { b1_off[o] = total; total += sq(ops[o].n); }
-  const size_t b1_total = total;
   for (size_t o = 0; o < nops; ++o) { op_off[o] = total; total += (kTaylorBlocks - 1) * sq(ops[o].n); }
   for (size_t r = 0; r < reqs.size(); ++r) {
     req_off[r] = total;
@@ -206,12 +205,15 @@ int batched_expm(const std::vector<ExpmOp>& ops, const std::vector<ExpmRequest>&
   };
   auto d_ptr = [&](size_t r, int i) { return work + req_off[r] + (size_t)i * sq(ops[reqs[r].op].n); };
   {
-    std::vector<double> h(b1_total);
+    // one upload per operator into the side-by-side region: a deferred S joins those that
+    // follow each other in its staging block as on the device into one copy, and no
+    // staging block has to hold every operator of a large batch at once
+    std::vector<double> h;
     for (size_t o = 0; o < nops; ++o) {
-      double* dst = h.data() + b1_off[o];
-      for (size_t e = 0; e < ops[o].Bshift.size(); ++e) dst[e] = ops[o].Bshift[e] / beta[o];
+      h.resize(ops[o].Bshift.size());
+      for (size_t e = 0; e < h.size(); ++e) h[e] = ops[o].Bshift[e] / beta[o];
+      RET_IF(S.upload(pw_ptr(o, 1), h.data(), sizeof(double) * h.size()));
     }
-    RET_IF(S.upload(work, h.data(), sizeof(double) * h.size()));
   }
   // operators grouped by size for the pointer-array GEMMs
   std::vector<int64_t> sizes;
