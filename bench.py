@@ -52,7 +52,7 @@ def measured_traffic():
     except OSError:
         return None
     h = hashlib.sha256()
-    for f in ("gemm_f64.hpp", "gemm_f64_dl.hpp", "tucker_f64.hpp"):
+    for f in ("gemm_f64.hpp", "gemm_f64_dl.hpp", "tucker_f64.hpp", "kernel_tuning.inc"):
         h.update(open(os.path.join(ROOT, "paper_2210_07667_amd", "csrc", f), "rb").read())
     m1 = re.search(r"kernel_source_sha256: (\w+)", text)
     m2 = re.search(r"traffic_bytes_per_launch: ([0-9.eE+-]+)", text)

@@ -32,20 +32,14 @@
 #include <type_traits>
 
 #include "gemm_f64.hpp"
+// PHIKS_DL_BK: k per chunk; PHIKS_DL_MIN_WAVES: waves per SIMD the register budget must
+// allow; PHIKS_DL_MIN_WAVES_LC: the same for the squaring epilogue (tuned values)
+#include "kernel_tuning.inc"
 
 namespace phiks {
 
-#ifndef PHIKS_DL_BK
-#define PHIKS_DL_BK 8   // k per chunk
-#endif
 #ifndef PHIKS_DL_ST
 #define PHIKS_DL_ST 2   // LDS stages
-#endif
-#ifndef PHIKS_DL_MIN_WAVES
-#define PHIKS_DL_MIN_WAVES 4     // waves per SIMD the register budget must allow
-#endif
-#ifndef PHIKS_DL_MIN_WAVES_LC
-#define PHIKS_DL_MIN_WAVES_LC 4  // the same for the squaring epilogue
 #endif
 
 template <int KP>
