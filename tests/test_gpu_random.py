@@ -1,0 +1,95 @@
+"""GPU parity on seeded random problems: libphiks (HIP, gfx950) against the FP64 CPU oracle.
+
+Each case draws d in 1..4, every n_mu in 1..40 (sizes 1 and ragged tiles included), an
+operator family per mode (FD2 Laplacian, advection-diffusion-reaction with a random speed
+and reaction, Chebyshev second derivative, or a dense random matrix), p in 0..5, 1..3
+scales, a task (same vector, or a combination with some inputs missing) and tau; tau is
+halved until the library's plan has s <= 6, where the bar below holds (the error of one
+mu-mode product is ~ n eps, n <= 40, and the squaring recurrence multiplies it by at most
+~2^s).
+The oracle runs at the library's (s, q); bar: relative infinity-norm difference <= 1e-12.
+"""
+import numpy as np
+import pytest
+
+import workloads
+from oracle import phiks as ophiks
+
+pytestmark = pytest.mark.gpu
+
+ph = pytest.importorskip("paper_2210_07667_amd")
+TOL = 1e-12
+CASES = 32
+
+
+@pytest.fixture(autouse=True)
+def _need_gpu():
+    if ph.device_count() < 1:
+        pytest.skip("no GPU")
+
+
+def relerr(got, ref):
+    got, ref = np.asarray(got), np.asarray(ref)
+    return float(np.abs(got - ref).max() / max(np.abs(ref).max(), 1e-300))
+
+
+def draw(seed):
+    rng = np.random.default_rng(1000 + seed)
+    d = int(rng.integers(1, 5))
+    n = [int(rng.integers(1, 41)) for _ in range(d)]
+    if int(np.prod(n)) > 60000:                 # keep the oracle quick
+        n = [min(k, 24) for k in n]
+    A = []
+    for k in n:
+        kind = int(rng.integers(0, 4))
+        if kind == 0:
+            A.append(workloads.fd2_dirichlet(k) / 50.0)
+        elif kind == 1:
+            A.append(workloads.adr_1d(k, 0.5, float(rng.uniform(-2, 2)), float(rng.uniform(-2, 0))))
+        elif kind == 2:
+            A.append(workloads.cheb_d2_dirichlet(k) / 100.0)
+        else:
+            A.append(rng.standard_normal((k, k)) * float(rng.uniform(0.5, 20.0)))
+    p = int(rng.integers(0, 6))
+    ns = int(rng.integers(1, 4))
+    task = "lincomb" if rng.random() < 0.5 else "same_vector"
+    tau = float(np.exp(rng.uniform(np.log(1e-3), np.log(1.0))))
+    return rng, d, n, A, p, ns, task, tau
+
+
+@pytest.mark.parametrize("seed", range(CASES))
+def test_random_problem_vs_oracle(seed):
+    rng, d, n, A, p, ns, task, tau = draw(seed)
+    while True:
+        s, q, _ = ph.phiks_plan_params(A, tau, p, ns, 2.0 ** -53, task)
+        if s <= 6:
+            break
+        tau /= 2.0
+    N = int(np.prod(n))
+    print(f"[random {seed}] d={d} n={n} p={p} ns={ns} task={task} tau={tau:.3g} plan=({s},{q})",
+          flush=True)
+    if task == "same_vector":
+        v = rng.standard_normal(N)
+        plan = ph.phiks_plan(A, tau, p, ns, 2.0 ** -53, task)
+        out = ph.apply_arrays(plan, ph.DeviceArray.from_numpy(v))
+        ph.synchronize()
+        info = plan.info()
+        plan.close()
+        got = out.to_numpy().reshape(ns, p + 1, N)
+        ref = ophiks.phi_same_vector(A, tau, v, p, ns, info["s"], info["q"])
+        for j in range(ns):
+            for ell in range(p + 1):
+                assert relerr(got[j, ell], ref[j, ell]) < TOL, (j, ell, info)
+    else:
+        vs = [rng.standard_normal(N) if (k == 0 or rng.random() < 0.8) else None
+              for k in range(p + 1)]
+        plan = ph.phiks_plan(A, tau, p, ns, 2.0 ** -53, task)
+        out = ph.combine_arrays(plan, [None if x is None else ph.DeviceArray.from_numpy(x)
+                                       for x in vs])
+        ph.synchronize()
+        info = plan.info()
+        plan.close()
+        got = out.to_numpy().reshape(ns, N)
+        ref = ophiks.phi_lincomb(A, tau, vs, p, ns, info["s"], info["q"])
+        for j in range(ns):
+            assert relerr(got[j], ref[j]) < TOL, (j, info)
