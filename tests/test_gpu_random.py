@@ -93,3 +93,64 @@ def test_random_problem_vs_oracle(seed):
         ref = ophiks.phi_lincomb(A, tau, vs, p, ns, info["s"], info["q"])
         for j in range(ns):
             assert relerr(got[j], ref[j]) < TOL, (j, info)
+
+
+COMPLEX_CASES = 12
+
+
+def draw_complex(seed):
+    """Complex operators: a real family times a random unit phase, or dense complex Gaussian;
+    complex tau; sizes up to 24 (the complex plan holds 2n x 2n real forms)."""
+    rng = np.random.default_rng(2000 + seed)
+    d = int(rng.integers(1, 4))
+    n = [int(rng.integers(1, 25)) for _ in range(d)]
+    A = []
+    for k in n:
+        if rng.random() < 0.5:
+            A.append((rng.standard_normal((k, k)) + 1j * rng.standard_normal((k, k)))
+                     * float(rng.uniform(0.5, 10.0)) / np.sqrt(k))
+        else:
+            ph_ = np.exp(1j * rng.uniform(0, 2 * np.pi))
+            A.append(workloads.adr_1d(k, 0.5, float(rng.uniform(-2, 2)), -1.0) / 20.0 * ph_)
+    p = int(rng.integers(0, 5))
+    ns = int(rng.integers(1, 3))
+    task = "lincomb" if rng.random() < 0.5 else "same_vector"
+    tau = complex(np.exp(rng.uniform(np.log(1e-2), np.log(1.0))) * np.exp(1j * rng.uniform(-0.6, 0.6)))
+    return rng, d, n, A, p, ns, task, tau
+
+
+@pytest.mark.parametrize("seed", range(COMPLEX_CASES))
+def test_random_complex_problem_vs_oracle(seed):
+    rng, d, n, A, p, ns, task, tau = draw_complex(seed)
+    while True:
+        s, q, _ = ph.phiks_plan_params_complex(A, tau, p, ns, 2.0 ** -53, task)
+        if s <= 6:
+            break
+        tau /= 2.0
+    N = int(np.prod(n))
+    print(f"[random complex {seed}] d={d} n={n} p={p} ns={ns} task={task} tau={tau:.3g} "
+          f"plan=({s},{q})", flush=True)
+    cvec = lambda: rng.standard_normal(N) + 1j * rng.standard_normal(N)
+    plan = ph.phiks_plan_complex(A, tau, p, ns, 2.0 ** -53, task)
+    if task == "same_vector":
+        v = cvec()
+        out = ph.apply_arrays(plan, ph.DeviceArray.from_numpy(v))
+        ph.synchronize()
+        info = plan.info()
+        plan.close()
+        got = out.to_complex().reshape(ns, p + 1, N)
+        ref = ophiks.phi_same_vector(A, tau, v, p, ns, info["s"], info["q"])
+        for j in range(ns):
+            for ell in range(p + 1):
+                assert relerr(got[j, ell], ref[j, ell]) < TOL, (j, ell, info)
+    else:
+        vs = [cvec() if (k == 0 or rng.random() < 0.8) else None for k in range(p + 1)]
+        out = ph.combine_arrays(plan, [None if x is None else ph.DeviceArray.from_numpy(x)
+                                       for x in vs])
+        ph.synchronize()
+        info = plan.info()
+        plan.close()
+        got = out.to_complex().reshape(ns, N)
+        ref = ophiks.phi_lincomb(A, tau, vs, p, ns, info["s"], info["q"])
+        for j in range(ns):
+            assert relerr(got[j], ref[j]) < TOL, (j, info)
