@@ -121,6 +121,9 @@ double factorial(int k) {
 // error is below 2^25 / 25! = 2.2e-18, under 2^-53 of ||exp(X)|| >= e^-2.
 const double kTaylorTheta = 2.0;
 const int kTaylorDegree = 24;
+// bound on c (re_hi - sigma) for the shifted exponentials: e^512 < 2^739 leaves room below
+// the largest double for the Taylor factor e^2, the squarings' sums and the dimension
+const double kShiftHeadroom = 512.0;
 
 // One small operator: the shifted B - sigma I (host, row-major), sigma, its 1-norm.
 struct ExpmOp {
@@ -379,15 +382,18 @@ void set_noplan_error(const PlannerOptions& opt) {
 }
 
 // host planning shared by phiks_plan and phiks_plan_params (tau > 0, so tau scales the
-// rectangle without reordering its sides)
+// rectangle, of the kind the planner options select, without reordering its sides);
+// re_hi (if not null) receives each mode's tau * right edge
 int host_plan(int d, const int64_t* n, const double* const* A, double tau, int p,
-              int n_scales, double tol, int task, const double* vnorms, PlanChoice& pc) {
+              int n_scales, double tol, int task, const double* vnorms, PlanChoice& pc,
+              double* re_hi = nullptr) {
   PlannerOptions opt;
   int rc = current_planner_options(opt);
   if (rc != PHIKS_OK) return rc;
   Rect xi{0.0, 0.0, 0.0, 0.0};
   for (int mu = 0; mu < d; ++mu) {
     Rect r = range_rectangle(n[mu], A[mu], opt.rect);
+    if (re_hi) re_hi[mu] = tau * r.re_hi;
     xi.re_lo += tau * r.re_lo;
     xi.re_hi += tau * r.re_hi;
     xi.im_lo += tau * r.im_lo;
@@ -439,7 +445,7 @@ int plan_init_host(phiks_plan_s& P, int d, const int64_t* n, const double* const
   if (precision != PHIKS_FP64 && precision != PHIKS_FP32 && precision != PHIKS_BF16X3)
     return PHIKS_EINVAL;
   PlanChoice pc;
-  rc = host_plan(d, n, A, tau, p, n_scales, tol, task, vnorms, pc);
+  rc = host_plan(d, n, A, tau, p, n_scales, tol, task, vnorms, pc, P.re_hi);
   if (rc != PHIKS_OK) return rc;
   P.d = d;
   P.N = 1;
@@ -488,6 +494,7 @@ int plan_init_host_complex(phiks_plan_s& P, int d, const int64_t* n, const doubl
       B[2 * e + 1] = tau_re * ai + tau_im * ar;
     }
     const Rect r = range_rectangle_complex(m, B.data(), opt.rect);
+    P.re_hi[mu] = r.re_hi;   // also that of the real form's symmetric part
     xi.re_lo += r.re_lo;
     xi.re_hi += r.re_hi;
     xi.im_lo += r.im_lo;
@@ -630,9 +637,13 @@ int build_plan_matrices(const std::vector<phiks_plan_s*>& plans,
       } else {
         for (int64_t e = 0; e < m * m; ++e) op.Bshift[e] = P.tau * A[i][mu][e];
       }
+      // shift sigma = tr(B)/m, raised where exp(c (B - sigma I)) could overflow: the
+      // largest c taken is 2^-s, and ||exp(c (B - sigma I))|| <= exp(c (re_hi - sigma)),
+      // so sigma >= re_hi - kShiftHeadroom 2^s keeps it below e^kShiftHeadroom (the
+      // factor e^{c sigma} applied afterwards restores exp(c B) exactly in exact arithmetic)
       double tr = 0.0;
       for (int64_t k = 0; k < m; ++k) tr += op.Bshift[k * m + k];
-      op.sigma = tr / m;
+      op.sigma = std::max(tr / m, P.re_hi[mu] - std::ldexp(kShiftHeadroom, P.s));
       for (int64_t k = 0; k < m; ++k) op.Bshift[k * m + k] -= op.sigma;
       double nrm = 0.0;
       for (int64_t c = 0; c < m; ++c) {

@@ -17,6 +17,9 @@ struct phiks_plan_s {
   int p = 0, ns = 1, task = 0, precision = 0;
   int s = 0, q = 0, t_paper = 0, t_exec = 0;
   double theta[phiks::kQMax] = {0}, w[phiks::kQMax] = {0};
+  // right edge of the numerical-range rectangle of each B_mu = tau A_mu: at least the
+  // largest eigenvalue of its Hermitian part, so ||exp(c B_mu)|| <= exp(c re_hi[mu])
+  double re_hi[PHIKS_MAX_D] = {0};
   int device = 0;
   hipStream_t stream = nullptr;         // stream the plan was built on (and is released on)
   void* dmem = nullptr;                 // all plan-lifetime device matrices

@@ -386,6 +386,38 @@ def test_diagonal_operators_closed_form():
         assert relerr(got[0, ell], ref) < 1e-12, (ell, info)
 
 
+def test_exponential_of_a_wide_spectrum_operator():
+    """exp(tau A) v with p = 0 (so s = 0: the exponential at c = 1) for Chebyshev D^2 (n = 48,
+    tau = 0.046): the mean eigenvalue of tau A lies ~740 below the top of its Hermitian part,
+    so exp(tau A - (tr/n) I) would exceed the double range although exp(tau A) v is of
+    order 1; the shift is capped to keep every intermediate finite.  Bar: the exponential
+    takes t ~ log2(||tau A||_1 / 2) = 13 squarings here, each doubling a relative rounding
+    error, so two correct FP64 evaluations differ by about 2^t u; 256 2^t u as for the
+    batched Chebyshev problems (with t for s)."""
+    A = [workloads.cheb_d2_dirichlet(48)]
+    tau = 0.046445297112915125
+    B = tau * A[0]
+    spread = np.linalg.eigvalsh((B + B.T) / 2).max() - np.trace(B) / 48
+    assert spread > 709.0                  # the case the cap is for
+    t = int(np.ceil(np.log2(np.abs(B).sum(axis=0).max() / 2.0)))
+    bar = 256.0 * 2.0 ** t * 2.0 ** -53
+    v = workloads.randn_vec([48], 37)
+    got, info = run_apply(A, tau, v, 0, 1)
+    assert info["s"] == 0, info
+    assert np.all(np.isfinite(got))
+    ref = ophiks.phi_same_vector(A, tau, v, 0, 1, info["s"], info["q"])
+    assert relerr(got[0, 0], ref[0, 0]) < bar
+    # and as one mode of a three-mode problem next to advection-diffusion and a dense mode
+    rng = np.random.default_rng(38)
+    A3 = [workloads.adr_1d(16, 0.5, 1.0, -1.0), workloads.cheb_d2_dirichlet(48),
+          rng.standard_normal((12, 12))]
+    v3 = workloads.randn_vec([16, 48, 12], 39)
+    got, info = run_apply(A3, tau, v3, 0, 1)
+    assert np.all(np.isfinite(got))
+    ref = ophiks.phi_same_vector(A3, tau, v3, 0, 1, info["s"], info["q"])
+    assert relerr(got[0, 0], ref[0, 0]) < bar
+
+
 def test_size_one_modes_vs_oracle():
     """Modes of size 1 between larger ones (a 1 x 1 A_mu shifts K by its entry)."""
     n = [1, 9, 1, 6]

@@ -154,3 +154,59 @@ def test_random_complex_problem_vs_oracle(seed):
         ref = ophiks.phi_lincomb(A, tau, vs, p, ns, info["s"], info["q"])
         for j in range(ns):
             assert relerr(got[j], ref[j]) < TOL, (j, info)
+
+
+# ------------------------------------------------------------------ random batches
+def random_batch(seed, count):
+    """count problems of random d (1..3), sizes 1..96, operator families and tau (halved
+    while the rightmost eigenvalue of tau K exceeds 100, so that every output is finite)."""
+    rng = np.random.default_rng(3000 + seed)
+    out = []
+    for k in range(count):
+        d = int(rng.integers(1, 4))
+        n = [int(rng.integers(1, 97)) for _ in range(d)]
+        if int(np.prod(n)) > 200000:
+            n = [min(m, 48) for m in n]
+        A = []
+        for m in n:
+            kind = int(rng.integers(0, 3))
+            if kind == 0:
+                A.append(workloads.cheb_d2_dirichlet(m))
+            elif kind == 1:
+                A.append(workloads.adr_1d(m, 0.5, float(rng.uniform(-2, 2)), -1.0))
+            else:
+                A.append(rng.standard_normal((m, m)) * float(rng.uniform(0.5, 50.0)))
+        tau = float(np.exp(rng.uniform(np.log(1e-4), np.log(1e-1))))
+        # keep exp(tau K) finite: the rightmost eigenvalue of tau K is the sum over the modes
+        alpha = sum(float(np.linalg.eigvals(a).real.max()) for a in A)
+        while tau * alpha > 100.0:
+            tau /= 2.0
+        out.append(workloads.BatchProblem(n=n, A=A, tau=tau, v=rng.standard_normal(int(np.prod(n)))))
+    p, ns = ((0, 1), (3, 2), (4, 1))[seed % 3]
+    return out, p, ns
+
+
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "fp32"])
+@pytest.mark.parametrize("seed", range(3))
+def test_random_batch_bitwise_equal_to_single_calls(seed, precision):
+    """Every problem of a random batch (irregular shapes, mixed operator families, one p
+    and one scale count) gives bitwise the outputs of its own phiks_plan + phiks_apply."""
+    problems, p, ns = random_batch(seed, 24)
+    tol = 2.0 ** -53
+    print(f"[random batch {seed}] precision={precision} p={p} ns={ns} "
+          f"shapes={[b.n for b in problems]}", flush=True)
+    norms = [float(np.linalg.norm(b.v)) for b in problems]
+    batch = ph.phiks_batch_plan([b.A for b in problems], [b.tau for b in problems], p, ns, tol,
+                                vnorms=norms, precision=precision)
+    outs = ph.batch_apply_arrays(batch, [ph.DeviceArray.from_numpy(b.v) for b in problems])
+    ph.synchronize()
+    got = [o.to_numpy() for o in outs]
+    batch.close()
+    for i, b in enumerate(problems):
+        plan = ph.phiks_plan(b.A, b.tau, p, ns, tol, "same_vector", [norms[i]], precision=precision)
+        ref = ph.apply_arrays(plan, ph.DeviceArray.from_numpy(b.v))
+        ph.synchronize()
+        plan.close()
+        r = ref.to_numpy()
+        assert np.all(np.isfinite(r)), (i, b.n)
+        assert np.array_equal(got[i], r), (i, b.n)
