@@ -210,3 +210,28 @@ def test_random_batch_bitwise_equal_to_single_calls(seed, precision):
         r = ref.to_numpy()
         assert np.all(np.isfinite(r)), (i, b.n)
         assert np.array_equal(got[i], r), (i, b.n)
+
+
+# ------------------------------------------------------- no-allocation entry point
+@pytest.mark.parametrize("seed", range(8))
+def test_random_noalloc_bitwise_equal_to_apply(seed):
+    """phiks_apply_noalloc (fixed device scratch) on the random same-vector problems of
+    test_random_problem_vs_oracle's draw: bitwise the outputs of phiks_apply."""
+    rng, d, n, A, p, ns, task, tau = draw(100 + seed)
+    while True:
+        s, q, _ = ph.phiks_plan_params(A, tau, p, ns, 2.0 ** -53, "same_vector")
+        if s <= 6:
+            break
+        tau /= 2.0
+    N = int(np.prod(n))
+    print(f"[random noalloc {seed}] n={n} p={p} ns={ns} plan=({s},{q})", flush=True)
+    v = rng.standard_normal(N)
+    plan = ph.phiks_plan(A, tau, p, ns, 2.0 ** -53, "same_vector")
+    assert plan.workspace_size() <= ph.NOALLOC_SCRATCH_BYTES
+    dv = ph.DeviceArray.from_numpy(v)
+    ref = ph.apply_arrays(plan, dv)
+    out = ph.DeviceArray.from_numpy(np.full(ns * (p + 1) * N, np.nan))
+    ph.phiks_apply_noalloc(plan, dv.ptr, out.ptr)
+    ph.synchronize()
+    plan.close()
+    assert np.array_equal(out.to_numpy(), ref.to_numpy())
