@@ -235,3 +235,46 @@ def test_random_noalloc_bitwise_equal_to_apply(seed):
     ph.synchronize()
     plan.close()
     assert np.array_equal(out.to_numpy(), ref.to_numpy())
+
+
+# ------------------------------------------------------------ mixed precision (layout)
+@pytest.mark.parametrize("precision", [1, 2], ids=["fp32", "bf16x3"])
+@pytest.mark.parametrize("seed", range(12))
+def test_random_mixed_precision_layout(seed, precision):
+    """FP32 and BF16x3 mu-mode products on the random problems of the real draw, both
+    tasks: every output finite and within 1e-2 of the FP64 path's.  This is a layout check
+    over irregular shapes (skinny tiles, K tails, size-1 modes, pair chains): a wrong index
+    or stride gives O(1) differences.  The precisions' accuracy bars are tested on fixed
+    shapes in test_gpu_mixed.py.  (At these sizes BF16x3 products are too small for its
+    64 x 64 tiles at two work-groups per CU and run on the FP32 kernel, so both precisions
+    give the same numbers here.)"""
+    rng, d, n, A, p, ns, task, tau = draw(200 + seed)
+    while True:
+        s, q, _ = ph.phiks_plan_params(A, tau, p, ns, 2.0 ** -53, task)
+        if s <= 6:
+            break
+        tau /= 2.0
+    N = int(np.prod(n))
+    print(f"[random mixed {seed}] precision={precision} n={n} p={p} ns={ns} task={task} "
+          f"plan=({s},{q})", flush=True)
+    outs = []
+    if task == "same_vector":
+        dv = ph.DeviceArray.from_numpy(rng.standard_normal(N))
+        for prec in (0, precision):
+            plan = ph.phiks_plan(A, tau, p, ns, 2.0 ** -53, task, precision=prec)
+            outs.append(ph.apply_arrays(plan, dv).to_numpy().reshape(ns * (p + 1), N))
+            plan.close()
+    else:
+        dvs = [ph.DeviceArray.from_numpy(rng.standard_normal(N)) if (k == 0 or rng.random() < 0.8)
+               else None for k in range(p + 1)]
+        for prec in (0, precision):
+            plan = ph.phiks_plan(A, tau, p, ns, 2.0 ** -53, task, precision=prec)
+            outs.append(ph.combine_arrays(plan, dvs).to_numpy().reshape(ns, N))
+            plan.close()
+    ph.synchronize()
+    ref, got = outs
+    assert np.all(np.isfinite(got))
+    errs = [relerr(got[k], ref[k]) for k in range(ref.shape[0])]
+    print(f"[random mixed {seed}] precision={precision} max rel diff to FP64 {max(errs):.2e}",
+          flush=True)
+    assert max(errs) < 1e-2
