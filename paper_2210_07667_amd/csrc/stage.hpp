@@ -26,6 +26,7 @@
 #include <vector>
 
 #include "runtime.hpp"
+#include "stage_runs.hpp"
 
 namespace {
 
@@ -141,7 +142,7 @@ class Stager {
     RET_IF(host_space(bytes, h));
     std::memcpy(h, src, bytes);
     if (deferred_) {
-      pending_.push_back({static_cast<char*>(dst), h, bytes});
+      pending_.push_back({static_cast<char*>(dst), h, bytes, chunk_of(dst, bytes)});
       return PHIKS_OK;
     }
     HIP_OK(hipMemcpyAsync(dst, h, bytes, hipMemcpyHostToDevice, st_));
@@ -199,25 +200,29 @@ class Stager {
     for (char* c : chunks_)
       if (hipFreeAsync(c, st_) != hipSuccess) rc = PHIKS_EDEVICE;
     chunks_.clear();
+    chunk_caps_.clear();
     chunk_used_ = chunk_cap_ = 0;
     return rc;
   }
 
  private:
-  static size_t align(size_t x) { return (x + 255) & ~size_t(255); }
+  static size_t align(size_t x) { return phiks::staged_align(x); }
 
-  // One copy per run of held uploads that follow each other in the pinned block and on
-  // the device alike (consecutive tables of one chunk: each starts at the previous
-  // one's start plus its size rounded up to 256 bytes, on both sides; the padding in
-  // between belongs to the same block and chunk).
+  // Index of the device chunk that holds [dst, dst + bytes), or -1.
+  int chunk_of(const void* dst, size_t bytes) const {
+    const char* d = static_cast<const char*>(dst);
+    for (size_t c = 0; c < chunks_.size(); ++c)
+      if (d >= chunks_[c] && d + bytes <= chunks_[c] + chunk_caps_[c]) return (int)c;
+    return -1;
+  }
+
+  // One copy per run of held uploads that follow each other in the pinned block and in
+  // one device chunk alike (phiks::staged_run_end; the padding in between belongs to the
+  // same block and chunk).
   int issue_copies() {
     size_t i = 0;
     while (i < pending_.size()) {
-      size_t j = i + 1;
-      while (j < pending_.size() &&
-             pending_[j].dst == pending_[j - 1].dst + align(pending_[j - 1].bytes) &&
-             pending_[j].host == pending_[j - 1].host + align(pending_[j - 1].bytes))
-        ++j;
+      const size_t j = phiks::staged_run_end(pending_.data(), pending_.size(), i);
       const size_t bytes = (size_t)(pending_[j - 1].dst - pending_[i].dst) + pending_[j - 1].bytes;
       HIP_OK(hipMemcpyAsync(pending_[i].dst, pending_[i].host, bytes, hipMemcpyHostToDevice, st_));
       i = j;
@@ -250,6 +255,7 @@ class Stager {
       char* c = nullptr;
       HIP_OK(hipMallocAsync((void**)&c, cap, st_));
       chunks_.push_back(c);
+      chunk_caps_.push_back(cap);
       chunk_used_ = 0;
       chunk_cap_ = cap;
     }
@@ -265,14 +271,10 @@ class Stager {
   bool have_ = false;
   size_t used_ = 0;
   std::vector<char*> chunks_;
+  std::vector<size_t> chunk_caps_;
   size_t chunk_used_ = 0, chunk_cap_ = 0;
-  struct Held {
-    char* dst;
-    const char* host;
-    size_t bytes;
-  };
   bool deferred_ = false;
-  std::vector<Held> pending_;
+  std::vector<phiks::StagedCopy> pending_;
   std::vector<std::function<int()>> launches_;
 };
 

@@ -8,6 +8,8 @@
   plan, server policy -- built host-only (hipcc, no device code objects) with the address
   and undefined-behaviour sanitizers on the host side, driven by
   tests/host/batch_plan_check.cpp over the 512 problems of the batched workload.
+* The run rule of the deferred plan-build uploads (csrc/stage_runs.hpp), driven by
+  tests/host/stage_runs_check.cpp: joined copies stay inside one device allocation.
 Each run must report no sanitizer error and pass its own checks."""
 import os
 import shutil
@@ -48,6 +50,14 @@ def test_server_core_under_sanitizer(tmp_path, kind):
     assert r.returncode == 0, r.stdout[-4000:]
     assert "server core check passed" in r.stdout
     assert "WARNING: ThreadSanitizer" not in r.stdout and "ERROR: AddressSanitizer" not in r.stdout
+
+
+def test_staged_upload_runs_stay_in_one_allocation(tmp_path):
+    r = build_and_run(tmp_path, os.path.join(HOST, "stage_runs_check.cpp"),
+                      ["-fsanitize=address,undefined", "-fno-sanitize-recover=all"],
+                      {"ASAN_OPTIONS": "halt_on_error=1 exitcode=66"})
+    assert r.returncode == 0, r.stdout[-4000:]
+    assert "stage runs check passed" in r.stdout
 
 
 HIPCC = "/opt/rocm/bin/hipcc"
