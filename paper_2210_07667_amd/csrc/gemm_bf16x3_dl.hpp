@@ -157,7 +157,7 @@ __device__ __forceinline__ void gemm_bf16x3_dl_tile(const GemmArgs& g, const Epi
   }
 
   if constexpr (LC)
-    lincomb_epilogue_f32<BM, BN, WM, WN>(acc, g, epi, Cb, cbase, tc.z1,
+    lincomb_epilogue_f32<BM, BN, WM, WN>(acc, g, epi, epi.Y, epi.N, Cb, cbase, tc.z1,
                                          reinterpret_cast<double*>(lds), m0, n0, wave, tid);
   else
     store_acc_tile<FM, FN, TC>(acc, g, epi, Cb, cbase, tc.z1, m0 + wm, n0 + wn, lr, lk);

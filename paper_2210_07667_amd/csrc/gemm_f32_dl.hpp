@@ -60,7 +60,8 @@ constexpr int lc_f32_lds_doubles() { return lc_f32_bufs<BM, BN, WM>() * (BM / WM
 // buffers, DMA YB - 1 rounds ahead.  Needs lincomb_dl_ok (checked by the launchers).
 template <int BM, int BN, int WM, int WN, int FM, int FN>
 __device__ __forceinline__ void lincomb_lds_epilogue_f32(const flt4 (&acc)[FM][FN], const GemmArgs& g,
-                                                         const EpiLinComb& epi, double* Cb,
+                                                         const EpiLinComb& epi, const double* Yb,
+                                                         int64_t YN, double* Cb,
                                                          int64_t cbase, int64_t z1, double* lds,
                                                          int m0, int n0, int wave, int tid) {
   constexpr int WGM = BM / WM, WGN = BN / WN;
@@ -84,10 +85,10 @@ __device__ __forceinline__ void lincomb_lds_epilogue_f32(const flt4 (&acc)[FM][F
     const int row = (rho / 16) * WM + rho % 16;
     off[q] = (int64_t)row * g.ldc + min(n0 + 2 * cp, g.N - 2);
   }
-  const PHIKS_GLOBAL double* Y0 = gptr(epi.Y) + cbase - (int64_t)l * epi.N;   // Y_0 at this tile
+  const PHIKS_GLOBAL double* Y0 = gptr(Yb) + cbase - (int64_t)l * YN;   // Y_0 at this tile
   auto issue = [&](int r) {
     const int i = r / nk, k = r - i * nk;
-    const PHIKS_GLOBAL double* Yk = Y0 + (int64_t)k * epi.N;
+    const PHIKS_GLOBAL double* Yk = Y0 + (int64_t)k * YN;
     double* buf = lds + (r % YB) * YSLICE;
 #pragma unroll
     for (int q = 0; q < LY; ++q) {
@@ -175,7 +176,8 @@ constexpr int lc_f32w_lds_doubles() { return 4 * YB * 16 * lc_f32w_fnp<WN / 16>(
 
 template <int WM, int WN, int YB, int FM, int FN>
 __device__ __forceinline__ void lincomb_wave_epilogue_f32(const flt4 (&acc)[FM][FN], const GemmArgs& g,
-                                                          const EpiLinComb& epi, double* Cb,
+                                                          const EpiLinComb& epi, const double* Yb,
+                                                          int64_t YN, double* Cb,
                                                           int64_t cbase, int64_t z1, double* lds,
                                                           int mw, int nw, int wave, int lane) {
   constexpr int FNP = lc_f32w_fnp<FN>(), JP = FN / FNP;
@@ -187,11 +189,11 @@ __device__ __forceinline__ void lincomb_wave_epilogue_f32(const flt4 (&acc)[FM][
   const int l = (int)z1, nk = l + 1;
   const int rounds = FM * JP * nk;
   double* wbuf = lds + wave * YB * SLICE;
-  const PHIKS_GLOBAL double* Y0 = gptr(epi.Y) + cbase - (int64_t)l * epi.N;   // Y_0 at this tile
+  const PHIKS_GLOBAL double* Y0 = gptr(Yb) + cbase - (int64_t)l * YN;   // Y_0 at this tile
   auto issue = [&](int r) {
     const int ij = r / nk, k = r - ij * nk;
     const int i = ij / JP, jp = ij - i * JP;
-    const PHIKS_GLOBAL double* Yk = Y0 + (int64_t)k * epi.N;
+    const PHIKS_GLOBAL double* Yk = Y0 + (int64_t)k * YN;
     double* buf = wbuf + (r % YB) * SLICE;
     // computed per round (not hoisted out of the loops: held across them they would not fit)
     int64_t ldc = g.ldc;
@@ -278,20 +280,22 @@ constexpr int lc_f32_epilogue_doubles() {
 // same operations in the same order per element).
 template <int BM, int BN, int WM, int WN, int FM, int FN>
 __device__ __forceinline__ void lincomb_epilogue_f32(const flt4 (&acc)[FM][FN], const GemmArgs& g,
-                                                     const EpiLinComb& epi, double* Cb, int64_t cbase,
+                                                     const EpiLinComb& epi, const double* Yb,
+                                                     int64_t YN, double* Cb, int64_t cbase,
                                                      int64_t z1, double* lds, int m0, int n0,
                                                      int wave, int tid) {
   if constexpr (lc_f32_wave_form<BM, BN>()) {
     constexpr int WGN = BN / WN;
-    lincomb_wave_epilogue_f32<WM, WN, 2>(acc, g, epi, Cb, cbase, z1, lds, m0 + (wave / WGN) * WM,
+    lincomb_wave_epilogue_f32<WM, WN, 2>(acc, g, epi, Yb, YN, Cb, cbase, z1, lds, m0 + (wave / WGN) * WM,
                                          n0 + (wave % WGN) * WN, wave, tid & 63);
   } else {
-    lincomb_lds_epilogue_f32<BM, BN, WM, WN>(acc, g, epi, Cb, cbase, z1, lds, m0, n0, wave, tid);
+    lincomb_lds_epilogue_f32<BM, BN, WM, WN>(acc, g, epi, Yb, YN, Cb, cbase, z1, lds, m0, n0, wave, tid);
   }
 }
 
 template <int BM, int BN, int WM, int WN, bool B_KCONTIG, class TA, class TC, class Epi>
-__device__ __forceinline__ void gemm_f32_dl_tile(const GemmArgs& g, const Epi& epi, int64_t rest) {
+__device__ __forceinline__ void gemm_f32_dl_tile(const GemmArgs& g, const Epi& epi, int64_t rest,
+                                                 const double* Yb, int64_t YN) {
   constexpr int BK = 16;                 // floats of k per chunk
   constexpr int KQ = BK / 4;             // 16-byte slots per k-contiguous FP32 row
   constexpr bool AD = std::is_same<TA, double>::value;
@@ -438,7 +442,7 @@ __device__ __forceinline__ void gemm_f32_dl_tile(const GemmArgs& g, const Epi& e
   }
 
   if constexpr (LC)
-    lincomb_epilogue_f32<BM, BN, WM, WN>(acc, g, epi, Cb, cbase, tc.z1,
+    lincomb_epilogue_f32<BM, BN, WM, WN>(acc, g, epi, Yb, YN, Cb, cbase, tc.z1,
                                          reinterpret_cast<double*>(lds), m0, n0, wave, tid);
   else
     store_acc_tile<FM, FN, TC>(acc, g, epi, Cb, cbase, tc.z1, m0 + wm, n0 + wn, lr, lk);
@@ -454,7 +458,11 @@ constexpr int f32dl_min_waves() {
 
 template <int BM, int BN, int WM, int WN, bool B_KCONTIG, class TA, class TC, class Epi>
 __global__ void __launch_bounds__(256, f32dl_min_waves<Epi>()) gemm_f32_dl_kernel(GemmArgs g, Epi epi) {
-  gemm_f32_dl_tile<BM, BN, WM, WN, B_KCONTIG, TA, TC, Epi>(g, epi, xcd_remap(blockIdx.x, g.total_tiles));
+  const int64_t rest = xcd_remap(blockIdx.x, g.total_tiles);
+  if constexpr (std::is_same<Epi, EpiLinComb>::value)
+    gemm_f32_dl_tile<BM, BN, WM, WN, B_KCONTIG, TA, TC, Epi>(g, epi, rest, epi.Y, epi.N);
+  else
+    gemm_f32_dl_tile<BM, BN, WM, WN, B_KCONTIG, TA, TC, Epi>(g, epi, rest, nullptr, 0);
 }
 
 // Grouped launch of the direct-to-LDS FP32 kernel (see gemm_f32_grouped).
@@ -465,13 +473,12 @@ __global__ void __launch_bounds__(256, f32dl_min_waves<Epi>())
   const int64_t t = xcd_remap(blockIdx.x, total);
   const int i = find_group_item(first, nitems, t);
   const GroupItem& it = items[i];
+  // the item's pre-step tensors go beside epi, not into a modified copy of it (a local
+  // copy indexed by the tensor index lives in scratch memory)
   if constexpr (std::is_same<Epi, EpiLinComb>::value) {
-    Epi e = epi;
-    e.Y = it.Y;
-    e.N = it.YN;
-    gemm_f32_dl_tile<BM, BN, WM, WN, B_KCONTIG, TA, TC, Epi>(it.g, e, t - first[i]);
+    gemm_f32_dl_tile<BM, BN, WM, WN, B_KCONTIG, TA, TC, Epi>(it.g, epi, t - first[i], it.Y, it.YN);
   } else {
-    gemm_f32_dl_tile<BM, BN, WM, WN, B_KCONTIG, TA, TC, Epi>(it.g, epi, t - first[i]);
+    gemm_f32_dl_tile<BM, BN, WM, WN, B_KCONTIG, TA, TC, Epi>(it.g, epi, t - first[i], nullptr, 0);
   }
 }
 

@@ -89,7 +89,8 @@ inline bool lincomb_dl_ok(const GemmArgs& g, const double* Y, int64_t YN) {
 // one fma per k in k order (every FP64 squaring kernel does exactly this).
 template <int WM, int WN, int YB, int FM, int FN>
 __device__ __forceinline__ void lincomb_wave_epilogue(dbl4 (&acc)[FM][FN], const GemmArgs& g,
-                                                      const EpiLinComb& epi, const TileOperands& t,
+                                                      const EpiLinComb& epi, const double* Yb,
+                                                      int64_t YN, const TileOperands& t,
                                                       double* lds, int mw, int nw, int wave, int lane) {
   constexpr int CPW = WN / 2;                 // column pairs per row
   constexpr int SLICE = 16 * WN;              // doubles per wave slice
@@ -99,10 +100,10 @@ __device__ __forceinline__ void lincomb_wave_epilogue(dbl4 (&acc)[FM][FN], const
   const int l = (int)t.z1;
   const int rounds = (l + 1) * FM;
   double* wbuf = lds + wave * YB * SLICE;
-  const PHIKS_GLOBAL double* Y0 = gptr(epi.Y) + t.cbase - (int64_t)l * epi.N;   // Y_0 at this tile
+  const PHIKS_GLOBAL double* Y0 = gptr(Yb) + t.cbase - (int64_t)l * YN;   // Y_0 at this tile
   auto issue = [&](int r) {
     const int k = r / FM, i = r % FM;
-    const PHIKS_GLOBAL double* Yk = Y0 + (int64_t)k * epi.N;
+    const PHIKS_GLOBAL double* Yk = Y0 + (int64_t)k * YN;
     double* buf = wbuf + (r % YB) * SLICE;
     // computed per round (not hoisted out of the k loop: held across it they would not fit)
     int64_t ldc = g.ldc;
@@ -170,7 +171,8 @@ __device__ __forceinline__ void lincomb_wave_epilogue(dbl4 (&acc)[FM][FN], const
 }
 
 template <int BM, int BN, int WM, int WN, bool B_KCONTIG, class Epi, int BK, int ST>
-__device__ __forceinline__ void gemm_f64_dl_tile(const GemmArgs& g, const Epi& epi, int64_t rest) {
+__device__ __forceinline__ void gemm_f64_dl_tile(const GemmArgs& g, const Epi& epi, int64_t rest,
+                                                 const double* Yb, int64_t YN) {
   static_assert(BK == 8 || BK == 16, "chunk of 8 or 16 k");
   static_assert(ST >= 2, "at least two stages");
   constexpr int KP = BK / 2;
@@ -296,7 +298,7 @@ __device__ __forceinline__ void gemm_f64_dl_tile(const GemmArgs& g, const Epi& e
   }
 
   if constexpr (LC) {
-    lincomb_wave_epilogue<WM, WN, YB>(acc, g, epi, t, lds, m0 + wm, n0 + wn, wave, lane);
+    lincomb_wave_epilogue<WM, WN, YB>(acc, g, epi, Yb, YN, t, lds, m0 + wm, n0 + wn, wave, lane);
   } else {
     store_tile_f64<FM, FN>(acc, g, epi, t.Cb, t.cbase, t.z1, m0 + wm, n0 + wn, lr, lk);
   }
@@ -309,8 +311,11 @@ constexpr int dl_min_waves() {
 
 template <int BM, int BN, int WM, int WN, bool B_KCONTIG, class Epi>
 __global__ void __launch_bounds__(256, dl_min_waves<Epi>()) gemm_f64_dl_kernel(GemmArgs g, Epi epi) {
-  gemm_f64_dl_tile<BM, BN, WM, WN, B_KCONTIG, Epi, PHIKS_DL_BK, PHIKS_DL_ST>(
-      g, epi, xcd_remap(blockIdx.x, g.total_tiles));
+  const int64_t rest = xcd_remap(blockIdx.x, g.total_tiles);
+  if constexpr (std::is_same<Epi, EpiLinComb>::value)
+    gemm_f64_dl_tile<BM, BN, WM, WN, B_KCONTIG, Epi, PHIKS_DL_BK, PHIKS_DL_ST>(g, epi, rest, epi.Y, epi.N);
+  else
+    gemm_f64_dl_tile<BM, BN, WM, WN, B_KCONTIG, Epi, PHIKS_DL_BK, PHIKS_DL_ST>(g, epi, rest, nullptr, 0);
 }
 
 // Grouped launch (many independent GEMMs of one kind in one grid; see gemm_f64_grouped).
@@ -321,13 +326,14 @@ __global__ void __launch_bounds__(256, dl_min_waves<Epi>())
   const int64_t t = xcd_remap(blockIdx.x, total);
   const int i = find_group_item(first, nitems, t);
   const GroupItem& it = items[i];
+  // the item's pre-step tensors are passed beside epi rather than through a modified
+  // copy of it: a local copy indexed by the tensor index l lives in scratch memory
   if constexpr (std::is_same<Epi, EpiLinComb>::value) {
-    Epi e = epi;
-    e.Y = it.Y;
-    e.N = it.YN;
-    gemm_f64_dl_tile<BM, BN, WM, WN, B_KCONTIG, Epi, PHIKS_DL_BK, PHIKS_DL_ST>(it.g, e, t - first[i]);
+    gemm_f64_dl_tile<BM, BN, WM, WN, B_KCONTIG, Epi, PHIKS_DL_BK, PHIKS_DL_ST>(it.g, epi, t - first[i],
+                                                                             it.Y, it.YN);
   } else {
-    gemm_f64_dl_tile<BM, BN, WM, WN, B_KCONTIG, Epi, PHIKS_DL_BK, PHIKS_DL_ST>(it.g, epi, t - first[i]);
+    gemm_f64_dl_tile<BM, BN, WM, WN, B_KCONTIG, Epi, PHIKS_DL_BK, PHIKS_DL_ST>(it.g, epi, t - first[i],
+                                                                             nullptr, 0);
   }
 }
 

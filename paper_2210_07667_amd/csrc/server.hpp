@@ -341,6 +341,12 @@ struct ServerExec {
                   const std::vector<int>& step) {
     hipStream_t st = S->streams[lane];
     BatchSchedule sch;
+    // A tick groups the next steps of a lane's few running requests: 128 x 64 tiles for the
+    // squaring epilogue (the batched workload's tuned rule) halve its work-groups there,
+    // which costs more than their operand reuse gains (600 requests/s: p50 17 ms and p99
+    // 156-163 ms with them, 10-12 ms and 117-127 ms without).  The tile class does not
+    // change any result bit.
+    sch.tune.wide_lc = 0;
     std::vector<StepGemm> gemms;
     std::vector<CombineArgs> combs;
     std::vector<std::pair<ServedRequest*, const ReqStep*>> tuckers;
