@@ -59,7 +59,8 @@ template <> struct Vec4<double> {
 template <int FM, int FN, class TC, class Epi>
 __device__ __forceinline__ void store_acc_tile(const flt4 (&acc)[FM][FN], const GemmArgs& g,
                                                const Epi& epi, TC* Cb, int64_t cbase, int64_t z1,
-                                               int mb, int nb, int lr, int lk) {
+                                               int mb, int nb, int lr, int lk,
+                                               const double* Yb = nullptr, int64_t YN = 0) {
   if constexpr (std::is_same<Epi, EpiLinComb>::value) {
     static_assert(std::is_same<TC, double>::value, "the squaring epilogue writes FP64");
     // one 16-row block at a time (FP64 partial results stay in few registers)
@@ -74,7 +75,7 @@ __device__ __forceinline__ void store_acc_tile(const flt4 (&acc)[FM][FN], const 
         for (int r = 0; r < 4; ++r) o[j][r] = al * (double)acc[i][j][r];
       for (int k = 0; k <= l; ++k) {
         const double ck = epi.c[l][k];
-        const double* __restrict__ Yk = epi.Y + (int64_t)(k - l) * epi.N;
+        const double* __restrict__ Yk = (Yb ? Yb : epi.Y) + (int64_t)(k - l) * (Yb ? YN : epi.N);
         double y[FN][4];
 #pragma unroll
         for (int j = 0; j < FN; ++j) {
@@ -128,7 +129,8 @@ __device__ __forceinline__ void store_acc_tile(const flt4 (&acc)[FM][FN], const 
 #endif
 
 template <int BM, int BN, int WM, int WN, bool B_KCONTIG, bool VEC, class TA, class TC, class Epi>
-__device__ __forceinline__ void gemm_f32_tile(const GemmArgs& g, const Epi& epi, int64_t rest) {
+__device__ __forceinline__ void gemm_f32_tile(const GemmArgs& g, const Epi& epi, int64_t rest,
+                                              const double* Yb = nullptr, int64_t YN = 0) {
   constexpr int BK = PHIKS_F32_BK;
   constexpr int WGM = BM / WM;
   constexpr int WGN = BN / WN;
@@ -312,7 +314,7 @@ __device__ __forceinline__ void gemm_f32_tile(const GemmArgs& g, const Epi& epi,
     __syncthreads();
   }
 
-  store_acc_tile<FM, FN, TC>(acc, g, epi, Cb, cbase, z1, m0 + wm, n0 + wn, lr, lk);
+  store_acc_tile<FM, FN, TC>(acc, g, epi, Cb, cbase, z1, m0 + wm, n0 + wn, lr, lk, Yb, YN);
 }
 
 template <int BM, int BN, int WM, int WN, bool B_KCONTIG, bool VEC, class TA, class TC, class Epi>
@@ -329,11 +331,10 @@ __global__ void __launch_bounds__(256, VEC ? PHIKS_F32_MIN_WAVES : 2)
   const int64_t t = xcd_remap(blockIdx.x, total);
   const int i = find_group_item(first, nitems, t);
   const GroupItem& it = items[i];
+  // the item's pre-step tensors go beside epi, not into a modified copy of it (a local
+  // copy indexed by the tensor index lives in scratch memory)
   if constexpr (std::is_same<Epi, EpiLinComb>::value) {
-    Epi e = epi;
-    e.Y = it.Y;
-    e.N = it.YN;
-    gemm_f32_tile<BM, BN, WM, WN, B_KCONTIG, VEC, TA, TC, Epi>(it.g, e, t - first[i]);
+    gemm_f32_tile<BM, BN, WM, WN, B_KCONTIG, VEC, TA, TC, Epi>(it.g, epi, t - first[i], it.Y, it.YN);
   } else {
     gemm_f32_tile<BM, BN, WM, WN, B_KCONTIG, VEC, TA, TC, Epi>(it.g, epi, t - first[i]);
   }

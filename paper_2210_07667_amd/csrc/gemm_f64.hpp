@@ -205,7 +205,8 @@ __device__ __forceinline__ TileOperands tile_operands(const GemmArgs& g, int64_t
 template <int FM, int FN, class Epi, class P>
 __device__ __forceinline__ void store_tile_f64(dbl4 (&acc)[FM][FN], const GemmArgs& g, const Epi& epi,
                                                P Cb, int64_t cbase, int64_t z1, int mw, int nw,
-                                               int lr, int lk) {
+                                               int lr, int lk, const double* Yb = nullptr,
+                                               int64_t YN = 0) {
   const int ml = mw + lk, nl = nw + lr;                 // the lane's first row and column
   const int64_t base = cbase + (int64_t)ml * g.ldc + nl;
   auto delta = [&](int i, int j, int r) { return (int64_t)(i * 16 + 4 * r) * g.ldc + j * 16; };
@@ -224,7 +225,7 @@ __device__ __forceinline__ void store_tile_f64(dbl4 (&acc)[FM][FN], const GemmAr
     static_assert(FM % FI == 0, "row pairs");
     for (int k = 0; k <= l; ++k) {
       const double ck = epi.c[l][k];
-      const PHIKS_GLOBAL double* __restrict__ Yk = gptr(epi.Y) + (int64_t)(k - l) * epi.N + base;
+      const PHIKS_GLOBAL double* __restrict__ Yk = gptr(Yb ? Yb : epi.Y) + (int64_t)(k - l) * (Yb ? YN : epi.N) + base;
 #pragma unroll
       for (int i0 = 0; i0 < FM; i0 += FI) {
         double y[FI][FN][4];
@@ -269,7 +270,8 @@ __device__ __forceinline__ void store_tile_f64(dbl4 (&acc)[FM][FN], const GemmAr
 // itself and rows k >= n are the same slab with every (re, im) pair replaced by
 // (-im, re), so that C = [Re L | Im L] B is the interleaved complex product L X.
 template <int BM, int BN, int WM, int WN, bool B_KCONTIG, bool VEC, class Epi, bool CPLX = false>
-__device__ __forceinline__ void gemm_f64_tile(const GemmArgs& g, const Epi& epi, int64_t rest) {
+__device__ __forceinline__ void gemm_f64_tile(const GemmArgs& g, const Epi& epi, int64_t rest,
+                                              const double* Yb = nullptr, int64_t YN = 0) {
   static_assert(!CPLX || (!B_KCONTIG && VEC), "the complex form needs an n-contiguous B, 16-byte loads");
   constexpr int BK = 16;
   constexpr int WGM = BM / WM;
@@ -425,7 +427,7 @@ __device__ __forceinline__ void gemm_f64_tile(const GemmArgs& g, const Epi& epi,
     __syncthreads();
   }
 
-  store_tile_f64<FM, FN>(acc, g, epi, Cb, cbase, z1, m0 + wm, n0 + wn, lr, lk);
+  store_tile_f64<FM, FN>(acc, g, epi, Cb, cbase, z1, m0 + wm, n0 + wn, lr, lk, Yb, YN);
 }
 
 template <int BM, int BN, int WM, int WN, bool B_KCONTIG, bool VEC, class Epi, bool CPLX = false>
@@ -463,11 +465,10 @@ __global__ void __launch_bounds__(256, VEC ? PHIKS_GEMM_MIN_WAVES : 2)
   const int64_t t = xcd_remap(blockIdx.x, total);
   const int lo = find_group_item(first, nitems, t);
   const GroupItem& it = items[lo];
+  // the item's pre-step tensors go beside epi, not into a modified copy of it (a local
+  // copy indexed by the tensor index lives in scratch memory)
   if constexpr (std::is_same<Epi, EpiLinComb>::value) {
-    Epi e = epi;
-    e.Y = it.Y;
-    e.N = it.YN;
-    gemm_f64_tile<BM, BN, WM, WN, B_KCONTIG, VEC>(it.g, e, t - first[lo]);
+    gemm_f64_tile<BM, BN, WM, WN, B_KCONTIG, VEC>(it.g, epi, t - first[lo], it.Y, it.YN);
   } else {
     gemm_f64_tile<BM, BN, WM, WN, B_KCONTIG, VEC>(it.g, epi, t - first[lo]);
   }
